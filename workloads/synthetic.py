@@ -1,0 +1,237 @@
+"""Seeded synthetic MPS workloads on a Hofstadter cylinder (sizes and random numbers only).
+
+Recipe (each step is a workload choice, not part of the method):
+
+* chain of n = Lx * Ly orbitals, orbital i = x * Ly + m, local states |0>, |1> with
+  charges (0, 0) and (1, m) (mixed basis) or (1, 0) with modulus 1 (real-space basis);
+* bond b (left of orbital b) carries the total charge of the orbitals left of it; the
+  left end is (0, 0), the right end (N_tot, K_tot);
+* sector dimensions on bond b: weight exp(-(N - Nbar_b)^2 / (2 sigma_N^2)) for
+  |N - Nbar_b| <= ceil(3 sigma_N), uniform over k, Nbar_b = round(b * N_tot / n), chi
+  apportioned by largest remainder, then clipped forward and backward until every
+  left site tensor can be an isometry from (a, s) to b and every right site tensor an
+  isometry from (s, c) to b;
+* isometries: complex Gaussian entries (real and imaginary parts N(0, 1/2)), QR per
+  charge block, columns rephased so that diag(R) > 0; one numpy generator per site from
+  ``SeedSequence(seed).spawn(n + 1)``, the last one for the two-site wavefunction.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from math import ceil, sqrt
+
+import numpy as np
+
+
+def site_charges(Lx: int, Ly: int, basis: str = "mixed"):
+    """[(0,0), (1,m)] per orbital (mixed) or [(0,0), (1,0)] (real space, modulus 1)."""
+    out = []
+    for x in range(Lx):
+        for m in range(Ly):
+            out.append(((0, 0), (1, m if basis == "mixed" else 0)))
+    return out
+
+
+def _add(a, b, ly):
+    return (a[0] + b[0], (a[1] + b[1]) % ly)
+
+
+def _sub(a, b, ly):
+    return (a[0] - b[0], (a[1] - b[1]) % ly)
+
+
+def _apportion(chi: int, weights: dict) -> dict:
+    keys = sorted(weights)
+    w = np.array([weights[k] for k in keys], dtype=np.float64)
+    raw = chi * w / w.sum()
+    base = np.floor(raw).astype(np.int64)
+    rem = int(chi - base.sum())
+    frac = raw - base
+    order = sorted(range(len(keys)), key=lambda i: (-frac[i], i))
+    for i in order[:rem]:
+        base[i] += 1
+    return {k: int(d) for k, d in zip(keys, base) if d > 0}
+
+
+def bond_sectors(n: int, qsite, ly: int, chi: int, N_tot: int, K_tot: int,
+                 sigma_N: float) -> list[dict]:
+    """Sector dimensions {(N, k): dim} on bonds 0..n."""
+    bonds = []
+    width = int(ceil(3.0 * sigma_N))
+    for b in range(n + 1):
+        if b == 0:
+            bonds.append({(0, 0): 1})
+            continue
+        if b == n:
+            bonds.append({(N_tot, K_tot % ly): 1})
+            continue
+        nbar = int(round(b * N_tot / n))
+        lo = max(0, N_tot - (n - b), nbar - width)
+        hi = min(b, N_tot, nbar + width)
+        weights = {(N, k): float(np.exp(-(N - nbar) ** 2 / (2.0 * sigma_N ** 2)))
+                   for N in range(lo, hi + 1) for k in range(ly)}
+        bonds.append(_apportion(chi, weights))
+    changed = True
+    while changed:
+        changed = False
+        for b in range(1, n + 1):
+            prev = bonds[b - 1]
+            for q in list(bonds[b]):
+                cap = sum(prev.get(_sub(q, qsite[b - 1][s], ly), 0) for s in (0, 1))
+                if bonds[b][q] > cap:
+                    changed = True
+                    if cap:
+                        bonds[b][q] = cap
+                    else:
+                        del bonds[b][q]
+        for b in range(n - 1, -1, -1):
+            nxt = bonds[b + 1]
+            for q in list(bonds[b]):
+                cap = sum(nxt.get(_add(q, qsite[b][s], ly), 0) for s in (0, 1))
+                if bonds[b][q] > cap:
+                    changed = True
+                    if cap:
+                        bonds[b][q] = cap
+                    else:
+                        del bonds[b][q]
+    return [dict(sorted(bd.items())) for bd in bonds]
+
+
+def _gauss(rng, shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / sqrt(2.0)
+
+
+def _isometry(rng, rows: int, cols: int) -> np.ndarray:
+    if rows < cols:
+        raise ValueError("isometry needs rows >= cols")
+    q, r = np.linalg.qr(_gauss(rng, (rows, cols)))
+    d = np.diag(r)
+    return q * (d / np.abs(d))[None, :]
+
+
+def left_isometry(rng, bl: dict, br: dict, qs, ly: int) -> dict:
+    """A[a, s, b] with sum_{a,s} conj(A[a,s,b]) A[a,s,b'] = delta_{bb'}; blocks keyed (qa, s, qb)."""
+    out = {}
+    for qb, mb in br.items():
+        parts = [(s, _sub(qb, qs[s], ly)) for s in (0, 1)]
+        parts = [(s, qa) for s, qa in parts if qa in bl]
+        rows = sum(bl[qa] for _, qa in parts)
+        q = _isometry(rng, rows, mb)
+        r0 = 0
+        for s, qa in parts:
+            out[(qa, s, qb)] = q[r0:r0 + bl[qa]].copy()
+            r0 += bl[qa]
+    return out
+
+
+def right_isometry(rng, bl: dict, br: dict, qs, ly: int) -> dict:
+    """B[b, s, c] with sum_{s,c} B[b,s,c] conj(B[b',s,c]) = delta_{bb'}; blocks keyed (qb, s, qc)."""
+    out = {}
+    for qb, mb in bl.items():
+        parts = [(s, _add(qb, qs[s], ly)) for s in (0, 1)]
+        parts = [(s, qc) for s, qc in parts if qc in br]
+        cols = sum(br[qc] for _, qc in parts)
+        q = _isometry(rng, cols, mb).conj().T          # (mb, cols), orthonormal rows
+        c0 = 0
+        for s, qc in parts:
+            out[(qb, s, qc)] = q[:, c0:c0 + br[qc]].copy()
+            c0 += br[qc]
+    return out
+
+
+def random_theta(rng, ba: dict, bc: dict, qs1, qs2, ly: int) -> dict:
+    """Two-site wavefunction theta[a, s1, s2, c], blocks keyed (qa, s1, s2, qc), unnormalised."""
+    out = {}
+    for qa, ma in ba.items():
+        for s1 in (0, 1):
+            for s2 in (0, 1):
+                qc = _add(_add(qa, qs1[s1], ly), qs2[s2], ly)
+                if qc in bc:
+                    out[(qa, s1, s2, qc)] = _gauss(rng, (ma, bc[qc]))
+    return out
+
+
+@dataclass
+class Workload:
+    """A finite cylinder MPS with a two-site window at orbitals (j, j+1)."""
+
+    name: str
+    Ly: int
+    Lx: int
+    flux: tuple          # (p, q): phi = 2 pi p / q
+    t: float
+    V: float
+    chi: int
+    N_tot: int
+    K_tot: int
+    sigma_N: float
+    seed: int
+    basis: str = "mixed"
+    j: int = -1
+    bonds: list = field(default_factory=list, repr=False)
+    qsite: list = field(default_factory=list, repr=False)
+
+    @property
+    def n(self) -> int:
+        return self.Lx * self.Ly
+
+    @property
+    def ly(self) -> int:
+        return self.Ly if self.basis == "mixed" else 1
+
+    def rng(self, i: int) -> np.random.Generator:
+        """Generator of site i (0 <= i < n) or of theta (i = n)."""
+        child = np.random.SeedSequence(self.seed).spawn(self.n + 1)[i]
+        return np.random.default_rng(child)
+
+    def site_tensor(self, i: int) -> dict:
+        """Left isometry for i < j, right isometry for i > j + 1."""
+        if i < self.j:
+            return left_isometry(self.rng(i), self.bonds[i], self.bonds[i + 1], self.qsite[i], self.ly)
+        if i > self.j + 1:
+            return right_isometry(self.rng(i), self.bonds[i], self.bonds[i + 1], self.qsite[i], self.ly)
+        raise ValueError("sites j and j+1 belong to the two-site window")
+
+    def right_canonical_mps(self) -> list:
+        """Right isometries on every site (a normalised random state with the target charge)."""
+        return [right_isometry(self.rng(i), self.bonds[i], self.bonds[i + 1], self.qsite[i], self.ly)
+                for i in range(self.n)]
+
+    def theta(self) -> dict:
+        j = self.j
+        return random_theta(self.rng(self.n), self.bonds[j], self.bonds[j + 2],
+                            self.qsite[j], self.qsite[j + 1], self.ly)
+
+
+def make_workload(name, Ly, Lx, flux, chi, seed, t=1.0, V=1.0, N_tot=None, K_tot=0,
+                  sigma_N=None, basis="mixed", j=None) -> Workload:
+    n = Lx * Ly
+    if N_tot is None:
+        N_tot = (Lx * Ly) // (2 * flux[1])        # half of the lowest band
+    if sigma_N is None:
+        sigma_N = sqrt(Ly / 2.0)
+    if j is None:
+        j = n // 2 - 1
+    ly = Ly if basis == "mixed" else 1
+    qsite = site_charges(Lx, Ly, basis)
+    wl = Workload(name, Ly, Lx, tuple(flux), t, V, chi, N_tot, K_tot % ly, sigma_N, seed, basis, j)
+    wl.qsite = qsite
+    wl.bonds = bond_sectors(n, qsite, ly, chi, N_tot, K_tot % ly, sigma_N)
+    return wl
+
+
+def preset(name: str, basis: str = "mixed") -> Workload:
+    """Named workloads: the centre-bond problems at Ly = 6, 8, 10 and small test cases."""
+    table = {
+        # name: (Ly, Lx, flux, chi, seed)
+        "ly6_chi800": (6, 12, (1, 6), 800, 2),
+        "ly8_chi3200": (8, 16, (1, 8), 3200, 3),
+        "ly10_chi6000": (10, 20, (1, 10), 6000, 5),
+        "ly4_chi64": (4, 8, (1, 4), 64, 11),
+        "ly4_chi200": (4, 8, (1, 4), 200, 12),
+        "ly6_chi200": (6, 12, (1, 6), 200, 13),
+        "ly8_chi400": (8, 16, (1, 8), 400, 14),
+        "ly3_chi16": (3, 4, (1, 3), 16, 15),
+    }
+    Ly, Lx, flux, chi, seed = table[name]
+    return make_workload(name, Ly, Lx, flux, chi, seed, basis=basis)
