@@ -14,7 +14,9 @@ Blocks are plain numpy arrays in dicts keyed by charges: a charge is a tuple (N,
 with 0 <= k < ly.  A site tensor A[a, s, b] is {(qa, s, qb): array (m_a, m_b)}.
 """
 from .synthetic import (Workload, bond_sectors, left_isometry, right_isometry,
-                        random_theta, site_charges, make_workload, preset)
+                        random_theta, site_charges, make_workload, preset,
+                        centre_workload, PRESETS)
 
 __all__ = ["Workload", "bond_sectors", "left_isometry", "right_isometry", "random_theta",
-           "site_charges", "make_workload", "preset"]
+           "site_charges", "make_workload", "preset",
+           "centre_workload", "PRESETS"]

@@ -220,18 +220,32 @@ def make_workload(name, Ly, Lx, flux, chi, seed, t=1.0, V=1.0, N_tot=None, K_tot
     return wl
 
 
+def centre_workload(name, Ly, chi, seed, basis="mixed", V=1.0) -> Workload:
+    """Centre-bond problem at flux 1/Ly: Lx starts at 2 Ly and doubles until the clipped
+    bond dimension at the window reaches 0.95 chi (a dilute cylinder clips the extreme
+    particle-number sectors)."""
+    Lx = 2 * Ly
+    while True:
+        wl = make_workload(name, Ly, Lx, (1, Ly), chi, seed, V=V, basis=basis)
+        if sum(wl.bonds[wl.j].values()) >= 0.95 * chi or Lx >= 64 * Ly:
+            return wl
+        Lx *= 2
+
+
+PRESETS = {
+    # name: (Ly, chi, seed) -- centre-bond problems
+    "ly6_chi800": (6, 800, 2),
+    "ly8_chi3200": (8, 3200, 3),
+    "ly10_chi6000": (10, 6000, 5),
+    "ly4_chi200": (4, 200, 12),
+    "ly6_chi200": (6, 200, 13),
+    "ly8_chi400": (8, 400, 14),
+    "ly4_chi64": (4, 64, 11),
+    "ly3_chi16": (3, 16, 15),
+}
+
+
 def preset(name: str, basis: str = "mixed") -> Workload:
-    """Named workloads: the centre-bond problems at Ly = 6, 8, 10 and small test cases."""
-    table = {
-        # name: (Ly, Lx, flux, chi, seed)
-        "ly6_chi800": (6, 12, (1, 6), 800, 2),
-        "ly8_chi3200": (8, 16, (1, 8), 3200, 3),
-        "ly10_chi6000": (10, 20, (1, 10), 6000, 5),
-        "ly4_chi64": (4, 8, (1, 4), 64, 11),
-        "ly4_chi200": (4, 8, (1, 4), 200, 12),
-        "ly6_chi200": (6, 12, (1, 6), 200, 13),
-        "ly8_chi400": (8, 16, (1, 8), 400, 14),
-        "ly3_chi16": (3, 4, (1, 3), 16, 15),
-    }
-    Ly, Lx, flux, chi, seed = table[name]
-    return make_workload(name, Ly, Lx, flux, chi, seed, basis=basis)
+    """Named centre-bond workloads (see PRESETS)."""
+    Ly, chi, seed = PRESETS[name]
+    return centre_workload(name, Ly, chi, seed, basis=basis)
