@@ -1,0 +1,215 @@
+/*
+ * mrdmrg -- MI355X (gfx950) hot path of mixed real/momentum-space cylinder DMRG.
+ *
+ * Motruk, Zaletel, Mong, Pollmann, "Density matrix renormalization group on a
+ * cylinder in mixed real and momentum space", arXiv:1512.03318.
+ *
+ * The paper's method makes the ring momentum k an onsite Z_Ly charge (Sec. II: the
+ * rotation T_y = prod exp(i k n_{x,k}) factorises over orbitals), so every DMRG tensor
+ * is block sparse in (N, k mod Ly) (Sec. III B: this extra block structure is what
+ * cuts time and memory).  This library runs the inner loop of the (i)DMRG sweep that
+ * the paper relies on but does not restate (Sec. I, III A):
+ *
+ *   H_eff theta [a', s1', s2', c'] =
+ *     sum L[a', w, a] W1[w, s1', s1, w'] W2[w', s2', s2, w''] R[c', w'', c] theta[a, s1, s2, c]
+ *   L'[b', w', b] = sum conj(A[a', s', b']) L[a', w, a] W[w, s', s, w'] A[a, s, b]
+ *   R'[b', w, b]  = sum conj(B[b', s', c']) W[w, s', s, w'] R[c', w', c] B[b, s, c]
+ *
+ * and the Lanczos ground-state solve around the first contraction.  W is the MPO of
+ * eq. MPO (matrix of operators per orbital, built from the finite-state machine of
+ * Sec. IV); its bond states carry the charge the operator string has placed so far.
+ *
+ * ---------------------------------------------------------------------------------
+ * Conventions (all of them are checked; violations return an error code)
+ *
+ * Charges.  A charge is (n, k) with 0 <= k < ly; addition is (n1+n2, (k1+k2) mod ly).
+ *   ly = 1 is a plain U(1) problem (the real-space basis).  A virtual bond carries the
+ *   total charge left of it.  Local states |0>, |1> of an orbital carry qs[0], qs[1].
+ *   Charge rules: A[a,s,b]: q(b) = q(a) + q(s).  theta: q(c) = q(a) + q(s1) + q(s2).
+ *   W[w,s',s,w']: q(w') = q(w) + q(s') - q(s).  L[a',w,a]: q(a') = q(a) + q(w).
+ *   R[c',w,c]: q(c') = q(c) + q(w).
+ *
+ * Bonds.  dm_bond lists sectors strictly increasing in (n, k) with positive dims.
+ *
+ * Data.  Every tensor passed to or returned from a compute call is device memory
+ *   holding complex128 values, interleaved (re, im), in the canonical layout below.
+ *   The caller owns all tensors; compute calls never keep a pointer to them after
+ *   returning, except where stated.  dm_layout() returns every block's offset so a
+ *   caller can pack and unpack data.  Layouts ("panel" = one row-major matrix):
+ *
+ *   DM_LAYOUT_SITE  (A or B, legs a, s, b): one panel per left sector a, in sector
+ *       order; rows m_a; columns the concatenation over s = 0, 1 (when the sector
+ *       b = a + q(s) exists) of m_b columns.  Block (a, s, b) has ld = panel width.
+ *   DM_LAYOUT_THETA (legs a, s1, s2, c): one panel per left sector a; columns the
+ *       concatenation over (s1, s2) = (0,0), (0,1), (1,0), (1,1) (when c exists).
+ *   DM_LAYOUT_ENV_L (L[a', w, a], bra and ket on the same bond): one panel per ket
+ *       sector a; columns m_a; rows the concatenation over MPO states w = 0..D-1 (when
+ *       a' = a + q(w) exists) of m_a' rows.
+ *   DM_LAYOUT_ENV_R (R[c', w, c]): one panel per bra sector c'; rows m_c'; columns the
+ *       concatenation over w = 0..D-1 (when c = c' - q(w) exists) of m_c columns.
+ *   Panels follow each other without padding.
+ *
+ * MPO site tensors are small host arrays: W[w][s'][s][w'] complex128 interleaved.
+ *
+ * Errors.  Every int-returning call returns DM_OK (0) or a negative DM_ERR_* code and
+ *   sets a thread-local message readable with dm_last_error().  No C++ exception
+ *   crosses this boundary.  GPU work is enqueued on the given stream; only
+ *   lanczos_ground and the env_update calls synchronise (they return host scalars or
+ *   free stream-ordered scratch).
+ * ---------------------------------------------------------------------------------
+ */
+#ifndef MRDMRG_H
+#define MRDMRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* dm_stream; /* hipStream_t; NULL is the default stream */
+
+#define DM_OK 0
+#define DM_ERR_ARG (-1)       /* null pointer, negative size, bad enum           */
+#define DM_ERR_CHARGE (-2)    /* a block violates its leg-charge rule            */
+#define DM_ERR_DIM (-3)       /* bonds of two tensors disagree                   */
+#define DM_ERR_LAYOUT (-4)    /* tensor does not match the plan                  */
+#define DM_ERR_DTYPE (-5)     /* unsupported precision                           */
+#define DM_ERR_ALLOC (-6)     /* device or host allocation failed                */
+#define DM_ERR_HIP (-7)       /* a HIP runtime call failed                       */
+#define DM_ERR_NONFINITE (-8) /* Lanczos produced a NaN or Inf                   */
+
+/* Arithmetic of the block GEMMs.  Inputs and outputs stay complex128; Lanczos
+ * scalars, reorthogonalisation and the tridiagonal solve are FP64 in every mode. */
+#define DM_FP64 0
+#define DM_FP32 1
+#define DM_BF16X3 2 /* hi/lo bfloat16 split of FP32 operands, FP32 accumulation */
+
+typedef struct {
+  int32_t n;
+  int32_t k;
+} dm_charge;
+
+typedef struct {
+  int32_t nsec;
+  const dm_charge* q; /* [nsec] */
+  const int32_t* dim; /* [nsec] */
+} dm_bond;
+
+typedef struct {
+  int32_t dl, dr;      /* MPO bond dimensions left / right of the orbital        */
+  const dm_charge* ql; /* [dl] charge of each left MPO state                     */
+  const dm_charge* qr; /* [dr]                                                   */
+  dm_charge qs[2];     /* charges of |0> and |1>                                 */
+  const double* w;     /* host [dl][2][2][dr] complex128 interleaved, W[w,s',s,w'] */
+} dm_mpo_site;
+
+#define DM_LAYOUT_SITE 0
+#define DM_LAYOUT_THETA 1
+#define DM_LAYOUT_ENV_L 2
+#define DM_LAYOUT_ENV_R 3
+
+typedef struct {
+  int32_t kind;         /* DM_LAYOUT_*                                              */
+  int32_t ly;           /* momentum modulus (>= 1)                                  */
+  const dm_bond* x;     /* SITE, THETA: left bond; ENV_L, ENV_R: the bond         */
+  const dm_bond* y;     /* SITE, THETA: right bond; unused for ENV_*                */
+  int32_t nw;           /* ENV_*: number of MPO states                             */
+  const dm_charge* qw;  /* ENV_*: [nw] MPO state charges                          */
+  dm_charge qs1[2];     /* SITE: local charges; THETA: first orbital              */
+  dm_charge qs2[2];     /* THETA: second orbital                                  */
+} dm_layout_desc;
+
+typedef struct {
+  int32_t idx[3]; /* SITE (a, s, b); THETA (a, s1*2+s2, c); ENV_L (a', w, a); ENV_R (c', w, c) */
+  int32_t rows, cols;
+  int64_t off; /* element offset of the block's (0, 0) entry                        */
+  int64_t ld;  /* elements between consecutive rows                                 */
+} dm_block;
+
+/* Canonical layout of a tensor (see above).  Writes the block count and the total
+ * number of complex elements; fills blocks[0..nblocks) when blocks != NULL (the
+ * caller provides room for *nblocks entries: call once with NULL to size it). */
+int dm_layout(const dm_layout_desc* d, int64_t* nblocks, int64_t* nelem, dm_block* blocks);
+
+/* ---- Two-site effective Hamiltonian -------------------------------------------
+ * A plan binds the environments L (bond a, MPO states of w1's left leg) and R (bond c,
+ * MPO states of w2's right leg) and the two MPO site tensors of the window.  It
+ * precomputes the charge-matched block task table (which L block meets which theta
+ * block, which MPO entries mix which intermediate blocks) and copies L and R into
+ * plan-owned device buffers in the plan's precision (plus FP64 copies for the final
+ * Rayleigh quotient in DM_FP32 / DM_BF16X3).  L and R may be freed after creation.
+ * The plan owns its device scratch.  Several plans may run concurrently on different
+ * streams; one plan must not be used by two streams at the same time. */
+typedef struct dm_heff_plan dm_heff_plan;
+
+int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* c,
+                        const dm_mpo_site* w1, const dm_mpo_site* w2,
+                        const void* L, const void* R, int32_t prec,
+                        dm_stream stream, dm_heff_plan** out);
+void dm_heff_plan_destroy(dm_heff_plan* p);
+
+/* Number of complex elements of theta for this plan, and algorithmic flop counts of
+ * one matvec (8 real flops per complex multiply-add): flops[0] = L.theta block GEMMs,
+ * flops[1] = MPO mixing, flops[2] = (.).R block GEMMs. */
+int dm_heff_info(const dm_heff_plan* p, int64_t* theta_elems, double flops[3]);
+
+/* theta_out = H_eff theta.  Both are device complex128 in the THETA layout of (a, c,
+ * w1.qs, w2.qs); they must not overlap.  Asynchronous on `stream`. */
+int heff_apply(dm_heff_plan* p, const void* theta, void* theta_out, dm_stream stream);
+
+/* Lanczos ground state of H_eff (textbook Lanczos, classical Gram-Schmidt against all
+ * previous vectors applied twice, FP64 on the device; lowest eigenpair of the
+ * tridiagonal matrix by bisection and inverse iteration on the device).
+ * theta_inout: start vector in (need not be normalised), normalised Ritz vector out.
+ * Stops after max_iter (1..64) matvecs or when beta_j <= tol * |T|.  In DM_FP32 /
+ * DM_BF16X3 the energy is the FP64 Rayleigh quotient <theta|H_eff|theta> of the Ritz
+ * vector (one extra FP64 matvec); in DM_FP64 it is the Ritz value.  Synchronises. */
+int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double tol,
+                   double* energy, int32_t* iters, dm_stream stream);
+
+/* ---- Environment updates ---------------------------------------------------------
+ * L_out (bond b, MPO states w.qr) from L (bond a, states w.ql) and the left-canonical
+ * site tensor A (SITE layout of a, b, w.qs).  R_out (bond b, states w.ql) from R
+ * (bond c, states w.qr) and the right-canonical B (SITE layout of b, c, w.qs).
+ * Outputs are overwritten.  Synchronises before returning (its scratch is freed). */
+int env_update_left(int32_t ly, const dm_bond* a, const dm_bond* b, const dm_mpo_site* w,
+                    const void* L, const void* A, void* L_out, int32_t prec, dm_stream stream);
+int env_update_right(int32_t ly, const dm_bond* b, const dm_bond* c, const dm_mpo_site* w,
+                     const void* R, const void* B, void* R_out, int32_t prec, dm_stream stream);
+
+/* ---- Many independent problems -------------------------------------------------
+ * A batch merges the task tables of n plans (same precision) so that every phase of
+ * one matvec runs as one launch over all instances; each Lanczos iteration of the
+ * whole batch is one HIP graph replay.  Plans must outlive the batch. */
+typedef struct dm_batch dm_batch;
+int dm_batch_create(int32_t n, dm_heff_plan* const* plans, dm_stream stream, dm_batch** out);
+void dm_batch_destroy(dm_batch* b);
+/* thetas[i]: device start vector / Ritz vector of instance i.  energies, iters: host
+ * arrays of n.  Same algorithm and stopping rule as lanczos_ground per instance.
+ * done_us (may be NULL): host array of n, microseconds from launch until instance i
+ * converged, measured on the device.  Synchronises. */
+int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t max_iter, double tol,
+                           double* energies, int32_t* iters, double* done_us, dm_stream stream);
+
+/* ---- Hofstadter MPO ----------------------------------------------------------------
+ * Builds the exact MPO of eq. H (Sec. III A) on an Ly x Lx cylinder, open in x and
+ * periodic in y, flux 2 pi p/q per plaquette, in the mixed basis of eqs. H_kin and
+ * H_int (basis = 0; orbital x*Ly + m, charges (1, m) mod Ly) or the real-space basis of
+ * eq. H_real (basis = 1; orbital x*Ly + y, charges (1, 0), ly = 1), by the finite-state
+ * machine of Sec. IV with exact merging of proportional states.  The MPO lives in the
+ * library; query site tensors with dm_mpo_site_get (pointers stay valid until
+ * dm_mpo_destroy). */
+typedef struct dm_mpo dm_mpo;
+int dm_mpo_hofstadter(int32_t Ly, int32_t Lx, int32_t p, int32_t q, double t, double V,
+                      int32_t basis, dm_mpo** out);
+int dm_mpo_n_sites(const dm_mpo* m);
+int dm_mpo_site_get(const dm_mpo* m, int32_t i, dm_mpo_site* out);
+void dm_mpo_destroy(dm_mpo* m);
+
+const char* dm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRDMRG_H */

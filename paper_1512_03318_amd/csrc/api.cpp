@@ -1,0 +1,953 @@
+// C ABI: layouts, effective-Hamiltonian plans, matvec, Lanczos and environment updates.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <sstream>
+
+#include "plan.hpp"
+
+using namespace mrd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw DmError{DM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)};     \
+  } while (0)
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    f();
+    return DM_OK;
+  } catch (const DmError& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(DM_ERR_ALLOC, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(DM_ERR_ARG, e.what());
+  }
+}
+
+void* dev_alloc(size_t bytes) {
+  if (bytes == 0) return nullptr;
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    throw DmError{DM_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  return p;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+template <typename T>
+T* upload(const std::vector<T>& v) {
+  if (v.empty()) return nullptr;
+  T* d = (T*)dev_alloc(v.size() * sizeof(T));
+  HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+void upload_stage(GemmStage& st) {
+  st.d_segs = upload(st.segs);
+  st.d_probs = upload(st.probs);
+  st.d_tiles = upload(st.tiles);
+  st.d_rows = upload(st.rows);
+}
+void free_stage(GemmStage& st) {
+  dev_free(st.d_segs);
+  dev_free(st.d_probs);
+  dev_free(st.d_tiles);
+  dev_free(st.d_rows);
+  st.d_segs = nullptr;
+  st.d_probs = nullptr;
+  st.d_tiles = nullptr;
+  st.d_rows = nullptr;
+}
+void upload_stage(MixStage& st) {
+  st.d_tasks = upload(st.tasks);
+  st.d_srcs = upload(st.srcs);
+}
+void free_stage(MixStage& st) {
+  dev_free(st.d_tasks);
+  dev_free(st.d_srcs);
+  st.d_tasks = nullptr;
+  st.d_srcs = nullptr;
+}
+
+size_t elem_bytes(int prec) { return prec == DM_FP64 ? 16 : 8; }
+
+void check_prec(int prec) {
+  if (prec != DM_FP64 && prec != DM_FP32)
+    throw DmError{DM_ERR_DTYPE, "precision " + std::to_string(prec) + " not supported"};
+}
+
+void check_ly(int ly) {
+  if (ly < 1) throw DmError{DM_ERR_ARG, "ly must be >= 1"};
+}
+
+// Copy (FP64) or cast (FP32) n complex elements from a caller's complex128 buffer.
+void stage_in(const void* src, void* dst, int64_t n, int prec, hipStream_t s) {
+  if (n == 0) return;
+  if (prec == DM_FP64)
+    HIPCHK(hipMemcpyAsync(dst, src, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
+  else
+    HIPCHK(launch_cast_d2f((const double*)src, (float*)dst, 2 * n, s));
+}
+void stage_out(const void* src, void* dst, int64_t n, int prec, hipStream_t s) {
+  if (n == 0) return;
+  if (prec == DM_FP64)
+    HIPCHK(hipMemcpyAsync(dst, src, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
+  else
+    HIPCHK(launch_cast_f2d((const float*)src, (double*)dst, 2 * n, s));
+}
+
+template <typename F>
+void by_prec(int prec, F&& f) {
+  if (prec == DM_FP64)
+    f((double*)nullptr);
+  else
+    f((float*)nullptr);
+}
+
+}  // namespace
+
+// =====================================================================================
+// Layout query
+// =====================================================================================
+extern "C" int dm_layout(const dm_layout_desc* d, int64_t* nblocks, int64_t* nelem,
+                         dm_block* blocks) {
+  return guarded([&] {
+    if (!d || !nblocks || !nelem) throw DmError{DM_ERR_ARG, "null argument"};
+    check_ly(d->ly);
+    std::vector<dm_block> out;
+    int64_t total = 0;
+    switch (d->kind) {
+      case DM_LAYOUT_SITE: {
+        Bond a = make_bond(d->x, d->ly), b = make_bond(d->y, d->ly);
+        SiteLayout L = site_layout(a, b, d->qs1, d->ly);
+        for (int i = 0; i < a.size(); ++i)
+          for (int s = 0; s < 2; ++s)
+            if (L.b[i][s] >= 0)
+              out.push_back({{i, s, L.b[i][s]}, a.dim[i], b.dim[L.b[i][s]],
+                             L.P.off[i] + L.coff[i][s], L.P.cols[i]});
+        total = L.P.total;
+        break;
+      }
+      case DM_LAYOUT_THETA: {
+        Bond a = make_bond(d->x, d->ly), c = make_bond(d->y, d->ly);
+        ThetaLayout L = theta_layout(a, c, d->qs1, d->qs2, d->ly);
+        for (int i = 0; i < a.size(); ++i)
+          for (int s = 0; s < 4; ++s)
+            if (L.c[i][s] >= 0)
+              out.push_back({{i, s, L.c[i][s]}, a.dim[i], c.dim[L.c[i][s]],
+                             L.P.off[i] + L.coff[i][s], L.P.cols[i]});
+        total = L.P.total;
+        break;
+      }
+      case DM_LAYOUT_ENV_L:
+      case DM_LAYOUT_ENV_R: {
+        Bond a = make_bond(d->x, d->ly);
+        if (d->nw <= 0 || !d->qw) throw DmError{DM_ERR_ARG, "environment layout needs MPO charges"};
+        std::vector<dm_charge> qw(d->qw, d->qw + d->nw);
+        for (auto& q : qw)
+          if (q.k < 0 || q.k >= d->ly) throw DmError{DM_ERR_CHARGE, "MPO charge k outside [0, ly)"};
+        if (d->kind == DM_LAYOUT_ENV_L) {
+          EnvLLayout L = envl_layout(a, qw, d->ly);
+          for (int i = 0; i < a.size(); ++i)
+            for (int w = 0; w < L.D; ++w) {
+              const int j = L.ap[i * L.D + w];
+              if (j < 0) continue;
+              out.push_back({{j, w, i}, a.dim[j], a.dim[i],
+                             L.P.off[i] + (int64_t)L.roff[i * L.D + w] * a.dim[i], a.dim[i]});
+            }
+          total = L.P.total;
+        } else {
+          EnvRLayout L = envr_layout(a, qw, d->ly);
+          for (int i = 0; i < a.size(); ++i)
+            for (int w = 0; w < L.D; ++w) {
+              const int j = L.c[i * L.D + w];
+              if (j < 0) continue;
+              out.push_back({{i, w, j}, a.dim[i], a.dim[j], L.P.off[i] + L.coff[i * L.D + w],
+                             L.P.cols[i]});
+            }
+          total = L.P.total;
+        }
+        break;
+      }
+      default:
+        throw DmError{DM_ERR_ARG, "unknown layout kind"};
+    }
+    if (blocks) std::copy(out.begin(), out.end(), blocks);
+    *nblocks = (int64_t)out.size();
+    *nelem = total;
+  });
+}
+
+// =====================================================================================
+// Effective Hamiltonian plan
+// =====================================================================================
+struct dm_heff_plan {
+  int ly = 1, prec = DM_FP64;
+  Bond a, c;
+  MpoSite w1, w2;
+  ThetaLayout th;
+  EnvLLayout L;
+  EnvRLayout R;
+  std::vector<int64_t> xoff;  // per a: X panel offset (rows = L.P.rows[a], cols = th.P.cols[a])
+  int64_t xtotal = 0;
+  std::vector<int64_t> zoff;  // per c': Z panel offset (rows zrows[c'], cols R.P.cols[c'])
+  std::vector<int> zrows;
+  std::vector<std::array<int, 4>> zroff;
+  int64_t ztotal = 0;
+  GemmStage s1, s4;
+  MixStage mix;
+  // device buffers (elements in the plan's precision)
+  void* dL = nullptr;
+  void* dR = nullptr;
+  void* dL64 = nullptr;  // FP64 copies for the final Rayleigh quotient (low precision plans)
+  void* dR64 = nullptr;
+  void* dX = nullptr;
+  void* dZ = nullptr;
+  void* dX64 = nullptr;
+  void* dZ64 = nullptr;
+  void* dTin = nullptr;  // low-precision staging of theta in / out
+  void* dTout = nullptr;
+  // Lanczos workspace (FP64)
+  double* dV = nullptr;
+  int Vcap = 0;
+  double* dW = nullptr;
+  double* dPart = nullptr;
+  double* dH1 = nullptr;
+  double* dH2 = nullptr;
+  double* dScal = nullptr;
+  double* dY = nullptr;
+  double* hPinned = nullptr;  // host pinned scratch
+  ~dm_heff_plan() {
+    for (GemmStage* st : {&s1, &s4}) free_stage(*st);
+    free_stage(mix);
+    for (void* p : {dL, dR, dL64, dR64, dX, dZ, dX64, dZ64, dTin, dTout})
+      dev_free(p);
+    for (double* p : {dV, dW, dPart, dH1, dH2, dScal, dY}) dev_free(p);
+    if (hPinned) (void)hipHostFree(hPinned);
+  }
+  int64_t n() const { return th.P.total; }
+};
+
+static void build_heff_tables(dm_heff_plan& p) {
+  const int ly = p.ly;
+  const Bond &a = p.a, &c = p.c;
+  const int dl = p.w1.dl, dm = p.w1.dr, dr = p.w2.dr;
+  // X panels
+  p.xoff.assign(a.size(), 0);
+  p.xtotal = 0;
+  for (int i = 0; i < a.size(); ++i) {
+    p.xoff[i] = p.xtotal;
+    p.xtotal += (int64_t)p.L.P.rows[i] * p.th.P.cols[i];
+  }
+  // Z panels: per c', rows (s1' s2', a'), cols (w'', c)
+  p.zoff.assign(c.size(), 0);
+  p.zrows.assign(c.size(), 0);
+  p.zroff.assign(c.size(), {-1, -1, -1, -1});
+  p.ztotal = 0;
+  std::vector<std::array<int, 4>> zap(c.size(), {-1, -1, -1, -1});
+  for (int ci = 0; ci < c.size(); ++ci) {
+    int rows = 0;
+    for (int s12 = 0; s12 < 4; ++s12) {
+      dm_charge qa = qsub(qsub(c.q[ci], p.w1.qs[s12 >> 1], ly), p.w2.qs[s12 & 1], ly);
+      const int ai = a.find(qa);
+      if (ai < 0 || p.th.c[ai][s12] != ci) continue;
+      zap[ci][s12] = ai;
+      p.zroff[ci][s12] = rows;
+      rows += a.dim[ai];
+    }
+    p.zrows[ci] = rows;
+    p.zoff[ci] = p.ztotal;
+    p.ztotal += (int64_t)rows * p.R.P.cols[ci];
+  }
+  // S1: X_a = Lpanel_a (M_a x m_a) . Theta_a (m_a x N_a)
+  GemmStage& s1 = p.s1;
+  s1.flags = 0;
+  for (int ai = 0; ai < a.size(); ++ai) {
+    const int M = p.L.P.rows[ai], N = p.th.P.cols[ai], K = a.dim[ai];
+    if (M == 0 || N == 0) continue;
+    GemmProb pr{p.xoff[ai], M, N, (int32_t)s1.segs.size(), 1, N, -1};
+    s1.segs.push_back({p.L.P.off[ai], p.th.P.off[ai], K, N, K, 0});
+    add_tiles(s1, (int32_t)s1.probs.size(), M, N);
+    s1.probs.push_back(pr);
+    s1.flops += 8.0 * M * N * K;
+  }
+  // two-site MPO W12[w, s12', s12, w''] = sum_w' W1[w, s1', s1, w'] W2[w', s2', s2, w'']
+  std::vector<std::complex<double>> w12((size_t)dl * 16 * dr);
+  auto W12 = [&](int w, int sp, int s, int wpp) -> std::complex<double>& {
+    return w12[(((size_t)w * 4 + sp) * 4 + s) * dr + wpp];
+  };
+  for (int w = 0; w < dl; ++w)
+    for (int s1p = 0; s1p < 2; ++s1p)
+      for (int s1 = 0; s1 < 2; ++s1)
+        for (int wm = 0; wm < dm; ++wm) {
+          const auto x = p.w1.at(w, s1p, s1, wm);
+          if (x == std::complex<double>(0, 0)) continue;
+          for (int s2p = 0; s2p < 2; ++s2p)
+            for (int s2 = 0; s2 < 2; ++s2)
+              for (int wpp = 0; wpp < dr; ++wpp) {
+                const auto y = p.w2.at(wm, s2p, s2, wpp);
+                if (y == std::complex<double>(0, 0)) continue;
+                W12(w, s1p * 2 + s2p, s1 * 2 + s2, wpp) += x * y;
+              }
+        }
+  // Mix: Z[(s12', a'), (w'', c)] = sum W12[w, s12', s12, w''] X_a[(w, a'), (s12, c)]
+  MixStage& mx = p.mix;
+  for (int ci2 = 0; ci2 < c.size(); ++ci2) {
+    const int K = p.R.P.cols[ci2];
+    for (int s12p = 0; s12p < 4; ++s12p) {
+      const int aip = zap[ci2][s12p];
+      if (aip < 0) continue;
+      for (int wpp = 0; wpp < dr; ++wpp) {
+        const int ci = p.R.c[ci2 * dr + wpp];
+        if (ci < 0) continue;
+        MixTask tk{p.zoff[ci2] + (int64_t)p.zroff[ci2][s12p] * K + p.R.coff[ci2 * dr + wpp], K,
+                   a.dim[aip], c.dim[ci], (int32_t)mx.srcs.size(), 0, 0};
+        for (int w = 0; w < dl; ++w) {
+          const int ai = a.find(qsub(a.q[aip], p.w1.ql[w], ly));
+          if (ai < 0) continue;
+          for (int s12 = 0; s12 < 4; ++s12) {
+            const auto v = W12(w, s12p, s12, wpp);
+            if (v == std::complex<double>(0, 0)) continue;
+            if (p.th.c[ai][s12] != ci || p.L.ap[ai * dl + w] != aip)
+              throw DmError{DM_ERR_CHARGE, "MPO charges inconsistent with the bonds"};
+            const int N = p.th.P.cols[ai];
+            MixSrc sr{p.xoff[ai] + (int64_t)p.L.roff[ai * dl + w] * N + p.th.coff[ai][s12], N, 0,
+                      v.real(), v.imag()};
+            mx.srcs.push_back(sr);
+            tk.nsrc++;
+          }
+        }
+        mx.flops += 8.0 * tk.nsrc * tk.rows * tk.cols;
+        mx.tasks.push_back(tk);
+      }
+    }
+  }
+  // S4: theta'_{c'} rows (s12', a') = Z_{c'} (M x K) . Rpanel_{c'}^T (K x m_c')
+  GemmStage& s4 = p.s4;
+  s4.flags = G_B_T | G_C_ROWMAP;
+  for (int ci2 = 0; ci2 < c.size(); ++ci2) {
+    const int M = p.zrows[ci2], N = c.dim[ci2], K = p.R.P.cols[ci2];
+    if (M == 0) continue;
+    GemmProb pr{0, M, N, (int32_t)s4.segs.size(), 1, 0, (int32_t)s4.rows.size()};
+    for (int s12p = 0; s12p < 4; ++s12p) {
+      const int aip = zap[ci2][s12p];
+      if (aip < 0) continue;
+      const int64_t base = p.th.P.off[aip] + p.th.coff[aip][s12p];
+      for (int r = 0; r < a.dim[aip]; ++r) s4.rows.push_back(base + (int64_t)r * p.th.P.cols[aip]);
+    }
+    s4.segs.push_back({p.zoff[ci2], p.R.P.off[ci2], K, K, K, 0});
+    add_tiles(s4, (int32_t)s4.probs.size(), M, N);
+    s4.probs.push_back(pr);
+    s4.flops += 8.0 * M * N * K;
+  }
+}
+
+extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* c,
+                                   const dm_mpo_site* w1, const dm_mpo_site* w2, const void* L,
+                                   const void* R, int32_t prec, dm_stream stream,
+                                   dm_heff_plan** out) {
+  return guarded([&] {
+    if (!out) throw DmError{DM_ERR_ARG, "null output"};
+    *out = nullptr;
+    check_ly(ly);
+    check_prec(prec);
+    auto p = std::make_unique<dm_heff_plan>();
+    p->ly = ly;
+    p->prec = prec;
+    p->a = make_bond(a, ly);
+    p->c = make_bond(c, ly);
+    p->w1 = make_mpo(w1, ly);
+    p->w2 = make_mpo(w2, ly);
+    if (p->w1.dr != p->w2.dl) throw DmError{DM_ERR_DIM, "W1 right and W2 left MPO dimensions differ"};
+    for (int i = 0; i < p->w1.dr; ++i)
+      if (!qeq(p->w1.qr[i], p->w2.ql[i]))
+        throw DmError{DM_ERR_CHARGE, "W1 right and W2 left MPO charges differ"};
+    p->th = theta_layout(p->a, p->c, p->w1.qs, p->w2.qs, ly);
+    p->L = envl_layout(p->a, p->w1.ql, ly);
+    p->R = envr_layout(p->c, p->w2.qr, ly);
+    if ((p->L.P.total > 0 && !L) || (p->R.P.total > 0 && !R))
+      throw DmError{DM_ERR_ARG, "null environment"};
+    build_heff_tables(*p);
+    validate(p->s1, p->L.P.total, p->n(), p->xtotal);
+    validate(p->mix, p->xtotal, p->ztotal);
+    validate(p->s4, p->ztotal, p->R.P.total, p->n());
+    for (GemmStage* st : {&p->s1, &p->s4}) upload_stage(*st);
+    upload_stage(p->mix);
+    const size_t eb = elem_bytes(prec);
+    p->dL = dev_alloc(p->L.P.total * eb);
+    p->dR = dev_alloc(p->R.P.total * eb);
+    p->dX = dev_alloc(p->xtotal * eb);
+    p->dZ = dev_alloc(p->ztotal * eb);
+    hipStream_t s = (hipStream_t)stream;
+    stage_in(L, p->dL, p->L.P.total, prec, s);
+    stage_in(R, p->dR, p->R.P.total, prec, s);
+    if (prec != DM_FP64) {
+      p->dL64 = dev_alloc(p->L.P.total * 16);
+      p->dR64 = dev_alloc(p->R.P.total * 16);
+      stage_in(L, p->dL64, p->L.P.total, DM_FP64, s);
+      stage_in(R, p->dR64, p->R.P.total, DM_FP64, s);
+      p->dTin = dev_alloc(p->n() * eb);
+      p->dTout = dev_alloc(p->n() * eb);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    *out = p.release();
+  });
+}
+
+extern "C" void dm_heff_plan_destroy(dm_heff_plan* p) { delete p; }
+
+extern "C" int dm_heff_info(const dm_heff_plan* p, int64_t* theta_elems, double flops[3]) {
+  if (!p) return fail(DM_ERR_ARG, "null plan");
+  if (theta_elems) *theta_elems = p->n();
+  if (flops) {
+    flops[0] = p->s1.flops;
+    flops[1] = p->mix.flops;
+    flops[2] = p->s4.flops;
+  }
+  return DM_OK;
+}
+
+// theta_out = H_eff theta in the plan's precision (FP64 in / out).
+static void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStream_t s,
+                     bool force64) {
+  if (p->prec == DM_FP64 || force64) {
+    void* dL = p->prec == DM_FP64 ? p->dL : p->dL64;
+    void* dR = p->prec == DM_FP64 ? p->dR : p->dR64;
+    void* dX = p->dX;
+    void* dZ = p->dZ;
+    if (p->prec != DM_FP64) {
+      if (!p->dX64) p->dX64 = dev_alloc(p->xtotal * 16);
+      if (!p->dZ64) p->dZ64 = dev_alloc(p->ztotal * 16);
+      dX = p->dX64;
+      dZ = p->dZ64;
+    }
+    HIPCHK(launch_gemm<double>(p->s1, (const double*)dL, (const double*)theta, (double*)dX, s));
+    HIPCHK(launch_mix<double>(p->mix, (const double*)dX, (double*)dZ, s));
+    HIPCHK(launch_gemm<double>(p->s4, (const double*)dZ, (const double*)dR, (double*)theta_out, s));
+    return;
+  }
+  stage_in(theta, p->dTin, p->n(), DM_FP32, s);
+  HIPCHK(launch_gemm<float>(p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, s));
+  HIPCHK(launch_mix<float>(p->mix, (const float*)p->dX, (float*)p->dZ, s));
+  HIPCHK(launch_gemm<float>(p->s4, (const float*)p->dZ, (const float*)p->dR, (float*)p->dTout, s));
+  stage_out(p->dTout, theta_out, p->n(), DM_FP32, s);
+}
+
+extern "C" int heff_apply(dm_heff_plan* p, const void* theta, void* theta_out, dm_stream stream) {
+  return guarded([&] {
+    if (!p) throw DmError{DM_ERR_ARG, "null plan"};
+    if (p->n() > 0 && (!theta || !theta_out)) throw DmError{DM_ERR_ARG, "null theta"};
+    if (theta == theta_out && p->n() > 0) throw DmError{DM_ERR_ARG, "theta and theta_out overlap"};
+    heff_run(p, theta, theta_out, (hipStream_t)stream, false);
+  });
+}
+
+// ---- lowest eigenpair of a symmetric tridiagonal matrix (bisection + inverse iteration)
+static int sturm_below(const std::vector<double>& al, const std::vector<double>& be, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  for (size_t i = 0; i < al.size(); ++i) {
+    const double b2 = i ? be[i - 1] * be[i - 1] : 0.0;
+    d = (al[i] - x) - (i ? b2 / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0) ++cnt;
+  }
+  return cnt;
+}
+
+static void tridiag_lowest(const std::vector<double>& al, const std::vector<double>& be,
+                           double* e_out, std::vector<double>& y) {
+  const int k = (int)al.size();
+  y.assign(k, 0.0);
+  if (k == 1) {
+    *e_out = al[0];
+    y[0] = 1.0;
+    return;
+  }
+  double lo = al[0], hi = al[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i ? std::fabs(be[i - 1]) : 0.0) + (i < k - 1 ? std::fabs(be[i]) : 0.0);
+    lo = std::min(lo, al[i] - r);
+    hi = std::max(hi, al[i] + r);
+  }
+  const double scale = std::max(std::fabs(lo), std::fabs(hi));
+  for (int it = 0; it < 2000 && hi - lo > 2e-16 * scale; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_below(al, be, mid) >= 1)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  const double lam = 0.5 * (lo + hi);
+  *e_out = lam;
+  // inverse iteration: (T - lam I) y = y_prev, Gaussian elimination with partial pivoting
+  std::vector<double> v(k, 1.0 / std::sqrt((double)k));
+  for (int it = 0; it < 4; ++it) {
+    std::vector<double> dd(k), du(k, 0.0), du2(k, 0.0), dl(k, 0.0), b = v;
+    for (int i = 0; i < k; ++i) dd[i] = al[i] - lam;
+    for (int i = 0; i < k - 1; ++i) {
+      du[i] = be[i];
+      dl[i] = be[i];
+    }
+    std::vector<int> piv(k, 0);
+    for (int i = 0; i < k - 1; ++i) {
+      if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
+        if (dd[i] == 0.0) dd[i] = 1e-300 * scale + 1e-300;
+        const double f = dl[i] / dd[i];
+        dd[i + 1] -= f * du[i];
+        b[i + 1] -= f * b[i];
+        if (i < k - 2) du2[i] = 0.0;
+      } else {
+        const double f = dd[i] / dl[i];
+        dd[i] = dl[i];
+        const double t = dd[i + 1];
+        dd[i + 1] = du[i] - f * t;
+        if (i < k - 2) {
+          du2[i] = du[i + 1];
+          du[i + 1] = -f * du2[i];
+        }
+        du[i] = t;
+        std::swap(b[i], b[i + 1]);
+        b[i + 1] -= f * b[i];
+      }
+    }
+    if (dd[k - 1] == 0.0) dd[k - 1] = 1e-300 * scale + 1e-300;
+    b[k - 1] /= dd[k - 1];
+    if (k > 1) b[k - 2] = (b[k - 2] - du[k - 2] * b[k - 1]) / dd[k - 2];
+    for (int i = k - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
+    double nrm = 0;
+    for (double x : b) nrm += x * x;
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i < k; ++i) v[i] = b[i] / nrm;
+  }
+  y = v;
+}
+
+static void ensure_lanczos(dm_heff_plan* p, int max_iter) {
+  const int64_t n = p->n();
+  if (p->Vcap < max_iter + 1) {
+    dev_free(p->dV);
+    p->dV = nullptr;
+    p->dV = (double*)dev_alloc((size_t)(max_iter + 1) * n * 16);
+    p->Vcap = max_iter + 1;
+    dev_free(p->dPart);
+    p->dPart = nullptr;
+    const int nb = lz_nblk(n);
+    p->dPart = (double*)dev_alloc((size_t)nb * (2 * (max_iter + 1) + 1) * 8);
+    for (double** q : {&p->dH1, &p->dH2, &p->dY}) {
+      dev_free(*q);
+      *q = nullptr;
+      *q = (double*)dev_alloc((size_t)(2 * (max_iter + 1) + 2) * 8);
+    }
+    if (!p->hPinned) HIPCHK(hipHostMalloc((void**)&p->hPinned, 8 * 512, hipHostMallocDefault));
+  }
+  if (!p->dW) p->dW = (double*)dev_alloc((size_t)n * 16);
+  if (!p->dScal) p->dScal = (double*)dev_alloc(64);
+}
+
+extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double tol,
+                              double* energy, int32_t* iters, dm_stream stream) {
+  return guarded([&] {
+    if (!p || !energy || !iters) throw DmError{DM_ERR_ARG, "null argument"};
+    if (max_iter < 1 || max_iter > 64) throw DmError{DM_ERR_ARG, "max_iter must be in 1..64"};
+    const int64_t n = p->n();
+    if (n == 0) throw DmError{DM_ERR_LAYOUT, "empty theta"};
+    if (!theta_inout) throw DmError{DM_ERR_ARG, "null theta"};
+    ensure_lanczos(p, max_iter);
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = lz_nblk(n);
+    double* V = p->dV;
+    double* w = p->dW;
+    double* hp = p->hPinned;
+    // v0 = theta / |theta|
+    HIPCHK(launch_lz_update_dots(V, n, 0, (double*)theta_inout, n, p->dH1, p->dPart, nb, s));
+    HIPCHK(launch_lz_reduce(p->dPart, nb, 1, p->dH2, s));
+    HIPCHK(hipMemcpyAsync(hp, p->dH2, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!(hp[0] > 0) || !std::isfinite(hp[0])) throw DmError{DM_ERR_NONFINITE, "start vector has zero or non-finite norm"};
+    hp[1] = 1.0 / std::sqrt(hp[0]);
+    HIPCHK(hipMemcpyAsync(p->dScal, hp + 1, 8, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_lz_scale((const double*)theta_inout, n, p->dScal, V, s));
+    std::vector<double> al, be;
+    double tnorm = 0;
+    for (int j = 0; j < max_iter; ++j) {
+      const int nv = j + 1;
+      heff_run(p, V + 2 * (int64_t)j * n, w, s, false);
+      HIPCHK(launch_lz_dots(V, n, nv, w, n, p->dPart, nb, s));
+      HIPCHK(launch_lz_reduce(p->dPart, nb, 2 * nv, p->dH1, s));
+      HIPCHK(launch_lz_update_dots(V, n, nv, w, n, p->dH1, p->dPart, nb, s));
+      HIPCHK(launch_lz_reduce(p->dPart, nb, 2 * nv + 1, p->dH2, s));
+      HIPCHK(hipMemcpyAsync(hp, p->dH1, 16 * nv, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hp + 2 * nv, p->dH2, 8 * (2 * nv + 1), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const double alpha = hp[2 * j];
+      double hh = 0;
+      for (int i = 0; i < 2 * nv; ++i) hh += hp[2 * nv + i] * hp[2 * nv + i];
+      const double nrm2 = hp[2 * nv + 2 * nv];
+      if (!std::isfinite(alpha) || !std::isfinite(nrm2))
+        throw DmError{DM_ERR_NONFINITE, "Lanczos produced a non-finite value"};
+      const double beta = std::sqrt(std::max(nrm2 - hh, 0.0));
+      al.push_back(alpha);
+      const double row = std::fabs(alpha) + beta + (j ? be[j - 1] : 0.0);
+      tnorm = std::max(tnorm, row);
+      if (beta <= tol * tnorm || j == max_iter - 1) break;
+      be.push_back(beta);
+      hp[4 * nv + 8] = 1.0 / beta;
+      HIPCHK(hipMemcpyAsync(p->dScal, hp + 4 * nv + 8, 8, hipMemcpyHostToDevice, s));
+      HIPCHK(launch_lz_update_scale(V, n, nv, w, n, p->dH2, p->dScal, V + 2 * (int64_t)(j + 1) * n, s));
+    }
+    const int k = (int)al.size();
+    double e = 0;
+    std::vector<double> y;
+    be.resize(k > 0 ? k - 1 : 0);
+    tridiag_lowest(al, be, &e, y);
+    HIPCHK(hipMemcpyAsync(p->dY, y.data(), 8 * k, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_lz_combine(V, n, k, n, p->dY, (double*)theta_inout, s));
+    if (p->prec != DM_FP64) {
+      // FP64 Rayleigh quotient of the Ritz vector
+      heff_run(p, theta_inout, w, s, true);
+      HIPCHK(launch_lz_dots((const double*)theta_inout, n, 1, w, n, p->dPart, nb, s));
+      HIPCHK(launch_lz_reduce(p->dPart, nb, 2, p->dH1, s));
+      HIPCHK(launch_lz_update_dots(V, n, 0, (double*)theta_inout, n, p->dH2, p->dPart, nb, s));
+      HIPCHK(launch_lz_reduce(p->dPart, nb, 1, p->dH2, s));
+      HIPCHK(hipMemcpyAsync(hp, p->dH1, 16, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hp + 2, p->dH2, 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      e = hp[0] / hp[2];
+    } else {
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    if (!std::isfinite(e)) throw DmError{DM_ERR_NONFINITE, "non-finite energy"};
+    *energy = e;
+    *iters = k;
+  });
+}
+
+// =====================================================================================
+// Environment updates
+// =====================================================================================
+namespace {
+
+struct EnvPlan {
+  GemmStage t1, t3;
+  MixStage mix;
+  int64_t t1total = 0, t2total = 0;
+  double flops() const { return t1.flops + mix.flops + t3.flops; }
+};
+
+// L'[b', w', b] = sum conj(A[a', s', b']) L[a', w, a] W[w, s', s, w'] A[a, s, b]
+EnvPlan plan_left(int ly, const Bond& a, const Bond& b, const MpoSite& W, const EnvLLayout& L,
+                  const SiteLayout& S, const EnvLLayout& Lo) {
+  EnvPlan ep;
+  const int dl = W.dl, dr = W.dr;
+  std::vector<int64_t> t1off(a.size());
+  for (int ai = 0; ai < a.size(); ++ai) {
+    t1off[ai] = ep.t1total;
+    ep.t1total += (int64_t)L.P.rows[ai] * S.P.cols[ai];
+  }
+  // T1_a = Lpanel_a (M_a x m_a) . Apanel_a (m_a x (s, b))
+  ep.t1.flags = 0;
+  for (int ai = 0; ai < a.size(); ++ai) {
+    const int M = L.P.rows[ai], N = S.P.cols[ai], K = a.dim[ai];
+    if (M == 0 || N == 0) continue;
+    GemmProb pr{t1off[ai], M, N, (int32_t)ep.t1.segs.size(), 1, N, -1};
+    ep.t1.segs.push_back({L.P.off[ai], S.P.off[ai], K, N, K, 0});
+    add_tiles(ep.t1, (int32_t)ep.t1.probs.size(), M, N);
+    ep.t1.probs.push_back(pr);
+    ep.t1.flops += 8.0 * M * N * K;
+  }
+  // T2 panel per b: rows (w', s', a') with b' = b + q(w'), a' = b' - q(s'); cols m_b
+  std::vector<int64_t> t2off(b.size());
+  std::vector<int> t2roff((size_t)b.size() * dr * 2, -1);
+  for (int bi = 0; bi < b.size(); ++bi) {
+    int rows = 0;
+    for (int wp = 0; wp < dr; ++wp) {
+      const int bpi = Lo.ap[bi * dr + wp];
+      if (bpi < 0) continue;
+      for (int sp = 0; sp < 2; ++sp) {
+        const int api = a.find(qsub(b.q[bpi], W.qs[sp], ly));
+        if (api < 0 || S.b[api][sp] != bpi) continue;
+        t2roff[((size_t)bi * dr + wp) * 2 + sp] = rows;
+        rows += a.dim[api];
+      }
+    }
+    t2off[bi] = ep.t2total;
+    ep.t2total += (int64_t)rows * b.dim[bi];
+  }
+  for (int bi = 0; bi < b.size(); ++bi)
+    for (int wp = 0; wp < dr; ++wp) {
+      const int bpi = Lo.ap[bi * dr + wp];
+      if (bpi < 0) continue;
+      for (int sp = 0; sp < 2; ++sp) {
+        const int ro = t2roff[((size_t)bi * dr + wp) * 2 + sp];
+        if (ro < 0) continue;
+        const int api = a.find(qsub(b.q[bpi], W.qs[sp], ly));
+        MixTask tk{t2off[bi] + (int64_t)ro * b.dim[bi], b.dim[bi], a.dim[api], b.dim[bi],
+                   (int32_t)ep.mix.srcs.size(), 0, 0};
+        for (int w = 0; w < dl; ++w) {
+          for (int s = 0; s < 2; ++s) {
+            const auto v = W.at(w, sp, s, wp);
+            if (v == std::complex<double>(0, 0)) continue;
+            const int ai = a.find(qsub(a.q[api], W.ql[w], ly));
+            if (ai < 0 || S.b[ai][s] != bi) continue;
+            if (L.ap[ai * dl + w] != api) throw DmError{DM_ERR_CHARGE, "inconsistent MPO charges"};
+            const int N = S.P.cols[ai];
+            ep.mix.srcs.push_back({t1off[ai] + (int64_t)L.roff[ai * dl + w] * N + S.coff[ai][s], N, 0,
+                                   v.real(), v.imag()});
+            tk.nsrc++;
+          }
+        }
+        ep.mix.flops += 8.0 * tk.nsrc * tk.rows * tk.cols;
+        ep.mix.tasks.push_back(tk);
+      }
+    }
+  // T3: L'_{w'}[b', b] = sum_{s'} conj(A_{a',s',b'})^T (m_b' x m_a') . T2 (m_a' x m_b)
+  ep.t3.flags = G_A_T | G_A_CONJ;
+  for (int bi = 0; bi < b.size(); ++bi)
+    for (int wp = 0; wp < dr; ++wp) {
+      const int bpi = Lo.ap[bi * dr + wp];
+      if (bpi < 0) continue;
+      const int M = b.dim[bpi], N = b.dim[bi];
+      GemmProb pr{Lo.P.off[bi] + (int64_t)Lo.roff[bi * dr + wp] * N, M, N,
+                  (int32_t)ep.t3.segs.size(), 0, N, -1};
+      int K = 0;
+      for (int sp = 0; sp < 2; ++sp) {
+        const int ro = t2roff[((size_t)bi * dr + wp) * 2 + sp];
+        if (ro < 0) continue;
+        const int api = a.find(qsub(b.q[bpi], W.qs[sp], ly));
+        ep.t3.segs.push_back({S.P.off[api] + S.coff[api][sp], t2off[bi] + (int64_t)ro * N,
+                              S.P.cols[api], N, a.dim[api], 0});
+        pr.nseg++;
+        K += a.dim[api];
+      }
+      add_tiles(ep.t3, (int32_t)ep.t3.probs.size(), M, N);
+      ep.t3.probs.push_back(pr);
+      ep.t3.flops += 8.0 * M * N * K;
+    }
+  return ep;
+}
+
+// R'[b', w, b] = sum conj(B[b', s', c']) W[w, s', s, w'] R[c', w', c] B[b, s, c]
+EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const EnvRLayout& R,
+                   const SiteLayout& S, const EnvRLayout& Ro) {
+  EnvPlan ep;
+  const int dl = W.dl, dr = W.dr;
+  // T1 per (c, s): rows (w', c') with c' = c + q(w'); cols m_b, b = c - q(s)
+  std::vector<int64_t> t1off((size_t)c.size() * 2, -1);
+  std::vector<int> t1roff((size_t)c.size() * 2 * dr, -1);
+  ep.t1.flags = G_A_ROWMAP | G_B_T;
+  for (int ci = 0; ci < c.size(); ++ci)
+    for (int s = 0; s < 2; ++s) {
+      const int bi = b.find(qsub(c.q[ci], W.qs[s], ly));
+      if (bi < 0 || S.b[bi][s] != ci) continue;
+      int M = 0;
+      const int32_t rm = (int32_t)ep.t1.rows.size();
+      for (int wp = 0; wp < dr; ++wp) {
+        const int cpi = c.find(qadd(c.q[ci], W.qr[wp], ly));
+        if (cpi < 0) continue;
+        t1roff[((size_t)ci * 2 + s) * dr + wp] = M;
+        const int64_t col = R.coff[cpi * dr + wp];
+        for (int r = 0; r < c.dim[cpi]; ++r)
+          ep.t1.rows.push_back(R.P.off[cpi] + (int64_t)r * R.P.cols[cpi] + col);
+        M += c.dim[cpi];
+      }
+      const int N = b.dim[bi], K = c.dim[ci];
+      t1off[ci * 2 + s] = ep.t1total;
+      ep.t1total += (int64_t)M * N;
+      if (M == 0) continue;
+      GemmProb pr{t1off[ci * 2 + s], M, N, (int32_t)ep.t1.segs.size(), 1, N, rm};
+      ep.t1.segs.push_back({0, S.P.off[bi] + S.coff[bi][s], 0, S.P.cols[bi], K, 0});
+      add_tiles(ep.t1, (int32_t)ep.t1.probs.size(), M, N);
+      ep.t1.probs.push_back(pr);
+      ep.t1.flops += 8.0 * M * N * K;
+    }
+  // T2 per (w, b): rows (s', c') with b' = b + q(w), c' = b' + q(s'); cols m_b
+  std::vector<int64_t> t2off((size_t)dl * b.size(), -1);
+  std::vector<int> t2roff((size_t)dl * b.size() * 2, -1);
+  for (int w = 0; w < dl; ++w)
+    for (int bi = 0; bi < b.size(); ++bi) {
+      const int bpi = b.find(qadd(b.q[bi], W.ql[w], ly));
+      if (bpi < 0) continue;
+      int rows = 0;
+      for (int sp = 0; sp < 2; ++sp) {
+        const int cpi = S.b[bpi][sp];
+        if (cpi < 0) continue;
+        t2roff[((size_t)w * b.size() + bi) * 2 + sp] = rows;
+        rows += c.dim[cpi];
+      }
+      t2off[(size_t)w * b.size() + bi] = ep.t2total;
+      ep.t2total += (int64_t)rows * b.dim[bi];
+    }
+  for (int w = 0; w < dl; ++w)
+    for (int bi = 0; bi < b.size(); ++bi) {
+      const int64_t base = t2off[(size_t)w * b.size() + bi];
+      if (base < 0) continue;
+      const int bpi = b.find(qadd(b.q[bi], W.ql[w], ly));
+      for (int sp = 0; sp < 2; ++sp) {
+        const int ro = t2roff[((size_t)w * b.size() + bi) * 2 + sp];
+        if (ro < 0) continue;
+        const int cpi = S.b[bpi][sp];
+        MixTask tk{base + (int64_t)ro * b.dim[bi], b.dim[bi], c.dim[cpi], b.dim[bi],
+                   (int32_t)ep.mix.srcs.size(), 0, 0};
+        for (int wp = 0; wp < dr; ++wp)
+          for (int s = 0; s < 2; ++s) {
+            const auto v = W.at(w, sp, s, wp);
+            if (v == std::complex<double>(0, 0)) continue;
+            const int ci = c.find(qsub(c.q[cpi], W.qr[wp], ly));
+            if (ci < 0) continue;
+            const int64_t o = t1off[ci * 2 + s];
+            if (o < 0) continue;
+            const int ro1 = t1roff[((size_t)ci * 2 + s) * dr + wp];
+            if (ro1 < 0) throw DmError{DM_ERR_CHARGE, "inconsistent MPO charges"};
+            if (b.find(qsub(c.q[ci], W.qs[s], ly)) != bi)
+              throw DmError{DM_ERR_CHARGE, "inconsistent MPO charges"};
+            ep.mix.srcs.push_back({o + (int64_t)ro1 * b.dim[bi], b.dim[bi], 0, v.real(), v.imag()});
+            tk.nsrc++;
+          }
+        ep.mix.flops += 8.0 * tk.nsrc * tk.rows * tk.cols;
+        ep.mix.tasks.push_back(tk);
+      }
+    }
+  // T3: R'_w[b', b] = sum_{s'} conj(B_{b', s', c'}) (m_b' x m_c') . T2 (m_c' x m_b)
+  ep.t3.flags = G_A_CONJ;
+  for (int w = 0; w < dl; ++w)
+    for (int bi = 0; bi < b.size(); ++bi) {
+      const int64_t base = t2off[(size_t)w * b.size() + bi];
+      if (base < 0) continue;
+      const int bpi = b.find(qadd(b.q[bi], W.ql[w], ly));
+      const int M = b.dim[bpi], N = b.dim[bi];
+      const int col = Ro.coff[bpi * dl + w];
+      GemmProb pr{Ro.P.off[bpi] + col, M, N, (int32_t)ep.t3.segs.size(), 0, Ro.P.cols[bpi], -1};
+      int K = 0;
+      for (int sp = 0; sp < 2; ++sp) {
+        const int ro = t2roff[((size_t)w * b.size() + bi) * 2 + sp];
+        if (ro < 0) continue;
+        const int cpi = S.b[bpi][sp];
+        ep.t3.segs.push_back({S.P.off[bpi] + S.coff[bpi][sp], base + (int64_t)ro * N,
+                              S.P.cols[bpi], N, c.dim[cpi], 0});
+        pr.nseg++;
+        K += c.dim[cpi];
+      }
+      add_tiles(ep.t3, (int32_t)ep.t3.probs.size(), M, N);
+      ep.t3.probs.push_back(pr);
+      ep.t3.flops += 8.0 * M * N * K;
+    }
+  return ep;
+}
+
+// Runs T1 -> mix -> T3 with stream-ordered scratch, FP64 or FP32 arithmetic.
+void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64_t nsite,
+             void* out, int64_t nout, int prec, hipStream_t s) {
+  upload_stage(ep.t1);
+  upload_stage(ep.t3);
+  upload_stage(ep.mix);
+  const size_t eb = elem_bytes(prec);
+  void *t1 = nullptr, *t2 = nullptr, *e32 = nullptr, *s32 = nullptr, *o32 = nullptr;
+  auto amalloc = [&](void** q, size_t bytes) {
+    if (bytes == 0) return;
+    if (hipMallocAsync(q, bytes, s) != hipSuccess) {
+      (void)hipGetLastError();
+      throw DmError{DM_ERR_ALLOC, "hipMallocAsync failed"};
+    }
+  };
+  std::string failure;
+  int code = DM_OK;
+  try {
+    amalloc(&t1, ep.t1total * eb);
+    amalloc(&t2, ep.t2total * eb);
+    if (prec == DM_FP64) {
+      HIPCHK(launch_gemm<double>(ep.t1, (const double*)env, (const double*)site, (double*)t1, s));
+      HIPCHK(launch_mix<double>(ep.mix, (const double*)t1, (double*)t2, s));
+      HIPCHK(launch_gemm<double>(ep.t3, (const double*)site, (const double*)t2, (double*)out, s));
+    } else {
+      amalloc(&e32, nenv * eb);
+      amalloc(&s32, nsite * eb);
+      amalloc(&o32, nout * eb);
+      stage_in(env, e32, nenv, DM_FP32, s);
+      stage_in(site, s32, nsite, DM_FP32, s);
+      HIPCHK(launch_gemm<float>(ep.t1, (const float*)e32, (const float*)s32, (float*)t1, s));
+      HIPCHK(launch_mix<float>(ep.mix, (const float*)t1, (float*)t2, s));
+      HIPCHK(launch_gemm<float>(ep.t3, (const float*)s32, (const float*)t2, (float*)o32, s));
+      stage_out(o32, out, nout, DM_FP32, s);
+    }
+  } catch (const DmError& e) {
+    failure = e.msg;
+    code = e.code;
+  }
+  for (void* q : {t1, t2, e32, s32, o32})
+    if (q) (void)hipFreeAsync(q, s);
+  const hipError_t se = hipStreamSynchronize(s);
+  free_stage(ep.t1);
+  free_stage(ep.t3);
+  free_stage(ep.mix);
+  if (code != DM_OK) throw DmError{code, failure};
+  if (se != hipSuccess) throw DmError{DM_ERR_HIP, std::string("stream sync: ") + hipGetErrorString(se)};
+}
+
+}  // namespace
+
+extern "C" int env_update_left(int32_t ly, const dm_bond* a, const dm_bond* b,
+                               const dm_mpo_site* w, const void* L, const void* A, void* L_out,
+                               int32_t prec, dm_stream stream) {
+  return guarded([&] {
+    check_ly(ly);
+    check_prec(prec);
+    Bond ba = make_bond(a, ly), bb = make_bond(b, ly);
+    MpoSite W = make_mpo(w, ly);
+    EnvLLayout Li = envl_layout(ba, W.ql, ly);
+    EnvLLayout Lo = envl_layout(bb, W.qr, ly);
+    SiteLayout S = site_layout(ba, bb, W.qs, ly);
+    if ((Li.P.total && !L) || (S.P.total && !A) || (Lo.P.total && !L_out))
+      throw DmError{DM_ERR_ARG, "null tensor"};
+    EnvPlan ep = plan_left(ly, ba, bb, W, Li, S, Lo);
+    validate(ep.t1, Li.P.total, S.P.total, ep.t1total);
+    validate(ep.mix, ep.t1total, ep.t2total);
+    validate(ep.t3, S.P.total, ep.t2total, Lo.P.total);
+    run_env(ep, L, Li.P.total, A, S.P.total, L_out, Lo.P.total, prec, (hipStream_t)stream);
+  });
+}
+
+extern "C" int env_update_right(int32_t ly, const dm_bond* b, const dm_bond* c,
+                                const dm_mpo_site* w, const void* R, const void* B, void* R_out,
+                                int32_t prec, dm_stream stream) {
+  return guarded([&] {
+    check_ly(ly);
+    check_prec(prec);
+    Bond bb = make_bond(b, ly), bc = make_bond(c, ly);
+    MpoSite W = make_mpo(w, ly);
+    EnvRLayout Ri = envr_layout(bc, W.qr, ly);
+    EnvRLayout Ro = envr_layout(bb, W.ql, ly);
+    SiteLayout S = site_layout(bb, bc, W.qs, ly);
+    if ((Ri.P.total && !R) || (S.P.total && !B) || (Ro.P.total && !R_out))
+      throw DmError{DM_ERR_ARG, "null tensor"};
+    EnvPlan ep = plan_right(ly, bb, bc, W, Ri, S, Ro);
+    validate(ep.t1, Ri.P.total, S.P.total, ep.t1total);
+    validate(ep.mix, ep.t1total, ep.t2total);
+    validate(ep.t3, S.P.total, ep.t2total, Ro.P.total);
+    run_env(ep, R, Ri.P.total, B, S.P.total, R_out, Ro.P.total, prec, (hipStream_t)stream);
+  });
+}
+
+extern "C" const char* dm_last_error(void) { return g_err.c_str(); }
+
+void mrd::set_last_error(const std::string& msg) { g_err = msg; }

@@ -1,0 +1,122 @@
+// Internal declarations shared by the host planner (api.hip) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_complex.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mrd {
+
+// ---------------------------------------------------------------------------------
+// Grouped complex GEMM descriptors.
+//
+// One problem computes C[M x N] = sum over its K-segments of op(A_seg) op(B_seg):
+//   A(i, k): affine      a_off + i * lda + k          (A_T: a_off + k * lda + i)
+//            row table   arow[a_rowmap + i] + a_off + k
+//   B(k, j): affine      b_off + k * ldb + j          (B_T: b_off + j * ldb + k)
+//   C(i, j): affine      c_off + i * ldc + j,  row table crow[c_rowmap + i] + j
+// All offsets count complex elements.  A_CONJ conjugates A.  The K-segments of one
+// problem are summed in order into one accumulator; C is overwritten.
+// ---------------------------------------------------------------------------------
+enum GemmFlags : int32_t {
+  G_A_T = 1,
+  G_A_CONJ = 2,
+  G_B_T = 4,
+  G_A_ROWMAP = 8,
+  G_C_ROWMAP = 16,
+};
+
+struct GemmSeg {
+  int64_t a_off;
+  int64_t b_off;
+  int32_t lda, ldb;
+  int32_t k;
+  int32_t pad;
+};
+
+struct GemmProb {
+  int64_t c_off;
+  int32_t M, N;
+  int32_t seg0, nseg;
+  int32_t ldc;
+  int32_t rowmap;  // start in the row table (A or C, by flags), -1 if none
+};
+
+// One output tile of one problem: rows [tm*TM, ...), cols [tn*TN, ...).
+struct GemmTile {
+  int32_t prob;
+  int32_t tm, tn;
+  int32_t pad;
+};
+
+// Sparse mixing: dst[r, c] = sum_s coef_s * src_s[r, c] over a rows x cols sub-block.
+struct MixTask {
+  int64_t dst;
+  int32_t ld_dst, rows, cols;
+  int32_t src0, nsrc;
+  int32_t pad;
+};
+struct MixSrc {
+  int64_t off;
+  int32_t ld;
+  int32_t pad;
+  double re, im;
+};
+
+// Host-side task table of one contraction stage, with its device copy.
+struct GemmStage {
+  int32_t flags = 0;
+  std::vector<GemmSeg> segs;
+  std::vector<GemmProb> probs;
+  std::vector<GemmTile> tiles;
+  std::vector<int64_t> rows;  // row table
+  double flops = 0.0;         // algorithmic: 8 * M * N * K per problem
+  // device
+  GemmSeg* d_segs = nullptr;
+  GemmProb* d_probs = nullptr;
+  GemmTile* d_tiles = nullptr;
+  int64_t* d_rows = nullptr;
+};
+
+struct MixStage {
+  std::vector<MixTask> tasks;
+  std::vector<MixSrc> srcs;
+  double flops = 0.0;  // 8 flops per complex multiply-add
+  MixTask* d_tasks = nullptr;
+  MixSrc* d_srcs = nullptr;
+};
+
+constexpr int TILE_M = 32;
+constexpr int TILE_N = 32;
+
+// Kernel launchers (kernels.hip).  T = double or float (complex interleaved).
+template <typename T>
+hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, hipStream_t s);
+template <typename T>
+hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s);
+hipError_t launch_cast_d2f(const double* in, float* out, int64_t n_real, hipStream_t s);
+hipError_t launch_cast_f2d(const float* in, double* out, int64_t n_real, hipStream_t s);
+
+// Lanczos helpers (FP64 complex vectors of n elements, Krylov basis V[j] = V + j*ld).
+hipError_t launch_lz_dots(const double* V, int64_t ld, int32_t nv, const double* w, int64_t n,
+                          double* partial, int32_t nblk, hipStream_t s);
+hipError_t launch_lz_reduce(const double* partial, int32_t nblk, int32_t nv, double* out,
+                            hipStream_t s);
+hipError_t launch_lz_update_dots(const double* V, int64_t ld, int32_t nv, double* w, int64_t n,
+                                 const double* h, double* partial, int32_t nblk, hipStream_t s);
+hipError_t launch_lz_update_scale(const double* V, int64_t ld, int32_t nv, const double* w,
+                                  int64_t n, const double* h, const double* scal, double* out,
+                                  hipStream_t s);
+hipError_t launch_lz_scale(const double* x, int64_t n, const double* scal, double* out,
+                           hipStream_t s);
+hipError_t launch_lz_combine(const double* V, int64_t ld, int32_t nv, int64_t n,
+                             const double* y, double* out, hipStream_t s);
+int lz_nblk(int64_t n);
+
+// Thread-local message returned by dm_last_error().
+void set_last_error(const std::string& msg);
+
+}  // namespace mrd

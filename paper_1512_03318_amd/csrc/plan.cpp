@@ -1,0 +1,216 @@
+// Host planner: bond / MPO validation and the canonical layouts.
+#include "plan.hpp"
+
+#include <cmath>
+#include <sstream>
+
+namespace mrd {
+
+static DmError err(int code, const std::string& m) { return DmError{code, m}; }
+
+Bond make_bond(const dm_bond* b, int ly) {
+  if (!b) throw err(DM_ERR_ARG, "null bond");
+  if (b->nsec < 0 || (b->nsec > 0 && (!b->q || !b->dim))) throw err(DM_ERR_ARG, "bad bond arrays");
+  Bond out;
+  out.ly = ly;
+  for (int i = 0; i < b->nsec; ++i) {
+    const dm_charge q = b->q[i];
+    if (q.k < 0 || q.k >= ly) {
+      std::ostringstream s;
+      s << "bond sector " << i << " has k=" << q.k << " outside [0," << ly << ")";
+      throw err(DM_ERR_CHARGE, s.str());
+    }
+    if (b->dim[i] <= 0) throw err(DM_ERR_DIM, "bond sector with non-positive dimension");
+    if (i > 0) {
+      const dm_charge p = b->q[i - 1];
+      if (!(p.n < q.n || (p.n == q.n && p.k < q.k)))
+        throw err(DM_ERR_ARG, "bond sectors must be strictly increasing in (n, k)");
+    }
+    out.q.push_back(q);
+    out.dim.push_back(b->dim[i]);
+    out.index[((int64_t)q.n << 32) ^ (int64_t)(uint32_t)q.k] = i;
+  }
+  return out;
+}
+
+MpoSite make_mpo(const dm_mpo_site* m, int ly) {
+  if (!m || !m->w || !m->ql || !m->qr || m->dl <= 0 || m->dr <= 0)
+    throw err(DM_ERR_ARG, "bad MPO site tensor");
+  MpoSite o;
+  o.dl = m->dl;
+  o.dr = m->dr;
+  o.ql.assign(m->ql, m->ql + m->dl);
+  o.qr.assign(m->qr, m->qr + m->dr);
+  o.qs[0] = m->qs[0];
+  o.qs[1] = m->qs[1];
+  for (auto* v : {&o.ql, &o.qr})
+    for (auto& q : *v)
+      if (q.k < 0 || q.k >= ly) throw err(DM_ERR_CHARGE, "MPO state charge k outside [0, ly)");
+  for (int s = 0; s < 2; ++s)
+    if (o.qs[s].k < 0 || o.qs[s].k >= ly) throw err(DM_ERR_CHARGE, "local charge k outside [0, ly)");
+  const size_t n = (size_t)o.dl * 4 * o.dr;
+  o.w.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    const double re = m->w[2 * i], im = m->w[2 * i + 1];
+    if (!std::isfinite(re) || !std::isfinite(im)) throw err(DM_ERR_NONFINITE, "non-finite MPO entry");
+    o.w[i] = {re, im};
+  }
+  for (int a = 0; a < o.dl; ++a)
+    for (int sp = 0; sp < 2; ++sp)
+      for (int s = 0; s < 2; ++s)
+        for (int b = 0; b < o.dr; ++b) {
+          if (o.at(a, sp, s, b) == std::complex<double>(0, 0)) continue;
+          const dm_charge want = qsub(qadd(o.ql[a], o.qs[sp], ly), o.qs[s], ly);
+          if (!qeq(want, o.qr[b])) {
+            std::ostringstream st;
+            st << "MPO entry W[" << a << "," << sp << "," << s << "," << b
+               << "] breaks q(w') = q(w) + q(s') - q(s)";
+            throw err(DM_ERR_CHARGE, st.str());
+          }
+        }
+  return o;
+}
+
+SiteLayout site_layout(const Bond& a, const Bond& b, const dm_charge qs[2], int ly) {
+  SiteLayout L;
+  for (int i = 0; i < a.size(); ++i) {
+    std::array<int, 2> bi{-1, -1}, co{0, 0};
+    int cols = 0;
+    for (int s = 0; s < 2; ++s) {
+      const int j = b.find(qadd(a.q[i], qs[s], ly));
+      if (j < 0) continue;
+      bi[s] = j;
+      co[s] = cols;
+      cols += b.dim[j];
+    }
+    L.b.push_back(bi);
+    L.coff.push_back(co);
+    L.P.push(a.dim[i], cols);
+  }
+  return L;
+}
+
+ThetaLayout theta_layout(const Bond& a, const Bond& c, const dm_charge qs1[2],
+                         const dm_charge qs2[2], int ly) {
+  ThetaLayout L;
+  for (int i = 0; i < a.size(); ++i) {
+    std::array<int, 4> ci{-1, -1, -1, -1}, co{0, 0, 0, 0};
+    int cols = 0;
+    for (int s12 = 0; s12 < 4; ++s12) {
+      const int j = c.find(qadd(qadd(a.q[i], qs1[s12 >> 1], ly), qs2[s12 & 1], ly));
+      if (j < 0) continue;
+      ci[s12] = j;
+      co[s12] = cols;
+      cols += c.dim[j];
+    }
+    L.c.push_back(ci);
+    L.coff.push_back(co);
+    L.P.push(a.dim[i], cols);
+  }
+  return L;
+}
+
+EnvLLayout envl_layout(const Bond& a, const std::vector<dm_charge>& qw, int ly) {
+  EnvLLayout L;
+  L.D = (int)qw.size();
+  for (int i = 0; i < a.size(); ++i) {
+    int rows = 0;
+    for (int w = 0; w < L.D; ++w) {
+      const int j = a.find(qadd(a.q[i], qw[w], ly));
+      L.ap.push_back(j);
+      L.roff.push_back(j < 0 ? -1 : rows);
+      if (j >= 0) rows += a.dim[j];
+    }
+    L.P.push(rows, a.dim[i]);
+  }
+  return L;
+}
+
+EnvRLayout envr_layout(const Bond& c, const std::vector<dm_charge>& qw, int ly) {
+  EnvRLayout L;
+  L.D = (int)qw.size();
+  for (int i = 0; i < c.size(); ++i) {
+    int cols = 0;
+    for (int w = 0; w < L.D; ++w) {
+      const int j = c.find(qsub(c.q[i], qw[w], ly));
+      L.c.push_back(j);
+      L.coff.push_back(j < 0 ? -1 : cols);
+      if (j >= 0) cols += c.dim[j];
+    }
+    L.P.push(c.dim[i], cols);
+  }
+  return L;
+}
+
+void add_tiles(GemmStage& st, int32_t prob, int M, int N) {
+  const int tm = (M + TILE_M - 1) / TILE_M, tn = (N + TILE_N - 1) / TILE_N;
+  if (M > 0 && N == 0) return;
+  for (int a = 0; a < tm; ++a)
+    for (int b = 0; b < tn; ++b) st.tiles.push_back({prob, a, b, 0});
+}
+
+static void range_check(int64_t lo, int64_t hi, int64_t size, const char* what) {
+  if (lo < 0 || hi >= size) {
+    std::ostringstream s;
+    s << "internal task table out of bounds (" << what << ": [" << lo << ", " << hi << "] of " << size << ")";
+    throw err(DM_ERR_LAYOUT, s.str());
+  }
+}
+
+void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_size) {
+  for (const GemmTile& t : st.tiles) {
+    if (t.prob < 0 || t.prob >= (int)st.probs.size()) throw err(DM_ERR_LAYOUT, "bad tile");
+    const GemmProb& p = st.probs[t.prob];
+    if (t.tm * TILE_M >= p.M || t.tn * TILE_N >= p.N) throw err(DM_ERR_LAYOUT, "empty tile");
+  }
+  for (const GemmProb& p : st.probs) {
+    if (p.M <= 0 || p.N <= 0) throw err(DM_ERR_LAYOUT, "empty problem");
+    if (p.seg0 < 0 || p.nseg < 0 || p.seg0 + p.nseg > (int)st.segs.size()) throw err(DM_ERR_LAYOUT, "bad segments");
+    const bool arow = st.flags & G_A_ROWMAP, crow = st.flags & G_C_ROWMAP;
+    if ((arow || crow) && (p.rowmap < 0 || p.rowmap + p.M > (int64_t)st.rows.size()))
+      throw err(DM_ERR_LAYOUT, "bad row table");
+    for (int q = 0; q < p.nseg; ++q) {
+      const GemmSeg& g = st.segs[p.seg0 + q];
+      if (g.k < 0) throw err(DM_ERR_LAYOUT, "negative K");
+      if (g.k == 0) continue;
+      if (arow) {
+        for (int i = 0; i < p.M; ++i) range_check(st.rows[p.rowmap + i] + g.a_off, st.rows[p.rowmap + i] + g.a_off + g.k - 1, a_size, "A");
+      } else if (st.flags & G_A_T) {
+        range_check(g.a_off, g.a_off + (int64_t)(g.k - 1) * g.lda + p.M - 1, a_size, "A");
+        if (g.lda < p.M) throw err(DM_ERR_LAYOUT, "lda");
+      } else {
+        range_check(g.a_off, g.a_off + (int64_t)(p.M - 1) * g.lda + g.k - 1, a_size, "A");
+        if (g.lda < g.k) throw err(DM_ERR_LAYOUT, "lda");
+      }
+      if (st.flags & G_B_T) {
+        range_check(g.b_off, g.b_off + (int64_t)(p.N - 1) * g.ldb + g.k - 1, b_size, "B");
+        if (g.ldb < g.k) throw err(DM_ERR_LAYOUT, "ldb");
+      } else {
+        range_check(g.b_off, g.b_off + (int64_t)(g.k - 1) * g.ldb + p.N - 1, b_size, "B");
+        if (g.ldb < p.N) throw err(DM_ERR_LAYOUT, "ldb");
+      }
+    }
+    if (crow) {
+      for (int i = 0; i < p.M; ++i) range_check(st.rows[p.rowmap + i], st.rows[p.rowmap + i] + p.N - 1, c_size, "C");
+    } else {
+      range_check(p.c_off, p.c_off + (int64_t)(p.M - 1) * p.ldc + p.N - 1, c_size, "C");
+      if (p.ldc < p.N) throw err(DM_ERR_LAYOUT, "ldc");
+    }
+  }
+}
+
+void validate(const MixStage& st, int64_t src_size, int64_t dst_size) {
+  for (const MixTask& t : st.tasks) {
+    if (t.rows <= 0 || t.cols <= 0) throw err(DM_ERR_LAYOUT, "empty mixing task");
+    range_check(t.dst, t.dst + (int64_t)(t.rows - 1) * t.ld_dst + t.cols - 1, dst_size, "mix dst");
+    if (t.ld_dst < t.cols) throw err(DM_ERR_LAYOUT, "mix ld");
+    if (t.src0 < 0 || t.nsrc < 0 || t.src0 + t.nsrc > (int)st.srcs.size()) throw err(DM_ERR_LAYOUT, "mix sources");
+    for (int q = 0; q < t.nsrc; ++q) {
+      const MixSrc& s = st.srcs[t.src0 + q];
+      range_check(s.off, s.off + (int64_t)(t.rows - 1) * s.ld + t.cols - 1, src_size, "mix src");
+      if (s.ld < t.cols) throw err(DM_ERR_LAYOUT, "mix src ld");
+    }
+  }
+}
+
+}  // namespace mrd

@@ -1,0 +1,108 @@
+"""GPU parity of the two-site matvec, the environment updates and Lanczos against the
+FP64 oracle, on seeded synthetic cylinders (inputs built by the oracle, same on both
+sides)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import blocksparse as bs
+from oracle import lanczos as olz
+from oracle import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1512_03318_amd as pk  # noqa: E402
+from gpu_helpers import WindowGPU, max_rel, mpo_site, to_dev  # noqa: E402
+
+CASES = ["ly3_chi16", "ly4_chi64", "ly6_chi200"]
+_cache = {}
+
+
+def problem(name):
+    if name not in _cache:
+        wl = workloads.preset(name)
+        L, W1, W2, R, th, keys, mpo = synth.window_problem(wl)
+        _cache[name] = (wl, L, W1, W2, R, th, keys, mpo)
+    return _cache[name]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("prec,tol", [(pk.DM_FP64, 1e-12), (pk.DM_FP32, 2e-5)])
+def test_heff_apply_parity(name, prec, tol):
+    wl, L, W1, W2, R, th, keys, mpo = problem(name)
+    say(f"heff_apply {name} prec={prec} n={sum(m*n for _, (m, n) in keys)}")
+    g = WindowGPU(wl, L, R, mpo)
+    plan = g.plan(prec)
+    x = to_dev(g.pack_theta(th))
+    y = torch.empty_like(x)
+    pk.heff_apply(plan, x, y)
+    torch.cuda.synchronize()
+    got = g.unpack_theta(y.cpu().numpy())
+    ref = bs.heff_apply(L, W1, W2, R, th)
+    assert max_rel(got, ref, keys) < tol
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_lanczos_parity_fp64(name):
+    wl, L, W1, W2, R, th, keys, mpo = problem(name)
+    say(f"lanczos {name}")
+    g = WindowGPU(wl, L, R, mpo)
+    plan = g.plan(pk.DM_FP64)
+    x = to_dev(g.pack_theta(th))
+    e, k = pk.lanczos_ground(plan, x, 30, 1e-14)
+    mv = lambda v: bs.flatten(bs.heff_apply(L, W1, W2, R, bs.unflatten(v, keys)), keys)
+    eo, vo, ko, _, _ = olz.lanczos(mv, bs.flatten(th, keys), max_iter=30)
+    assert k == ko
+    assert abs(e - eo) <= 1e-10 * abs(eo)
+    v = bs.flatten(g.unpack_theta(x.cpu().numpy()), keys)
+    assert 1 - abs(np.vdot(vo, v)) < 1e-8
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("prec,tol", [(pk.DM_FP64, 1e-12), (pk.DM_FP32, 2e-5)])
+def test_env_updates_parity(name, prec, tol):
+    wl, L, W1, W2, R, th, keys, mpo = problem(name)
+    j, ly = wl.j, wl.ly
+    say(f"env updates {name} prec={prec}")
+    # left: L at bond j -> bond j+1 with a fresh left isometry on site j
+    rng = np.random.default_rng(99)
+    A = workloads.left_isometry(rng, wl.bonds[j], wl.bonds[j + 1], wl.qsite[j], ly)
+    a, b = pk.Bond(wl.bonds[j]), pk.Bond(wl.bonds[j + 1])
+    W = mpo_site(mpo, j)
+    Lf = to_dev(pk.pack(L, pk.LAYOUT_ENV_L, ly, a, qw=mpo.qbond[j]))
+    Af = to_dev(pk.pack(A, pk.LAYOUT_SITE, ly, a, b, qs1=[tuple(q) for q in mpo.qsite[j]]))
+    _, nout = pk.layout(pk.LAYOUT_ENV_L, ly, b, qw=mpo.qbond[j + 1])
+    Lo = torch.empty(nout, dtype=torch.complex128, device="cuda")
+    pk.env_update_left(ly, a, b, W, Lf, Af, Lo, prec)
+    got = pk.unpack(Lo.cpu().numpy(), pk.LAYOUT_ENV_L, ly, b, qw=mpo.qbond[j + 1])
+    ref = bs.env_left_update(L, A, mpo.W[j])
+    num = max(np.abs(got[k] - ref.get(k, 0)).max() for k in got)
+    den = max(np.abs(v).max() for v in ref.values())
+    assert set(ref) <= set(got)
+    assert num / den < tol
+    # right: R at bond j+2 -> bond j+1 with a fresh right isometry on site j+1
+    B = workloads.right_isometry(rng, wl.bonds[j + 1], wl.bonds[j + 2], wl.qsite[j + 1], ly)
+    b, c = pk.Bond(wl.bonds[j + 1]), pk.Bond(wl.bonds[j + 2])
+    W = mpo_site(mpo, j + 1)
+    Rf = to_dev(pk.pack(R, pk.LAYOUT_ENV_R, ly, c, qw=mpo.qbond[j + 2]))
+    Bf = to_dev(pk.pack(B, pk.LAYOUT_SITE, ly, b, c, qs1=[tuple(q) for q in mpo.qsite[j + 1]]))
+    _, nout = pk.layout(pk.LAYOUT_ENV_R, ly, b, qw=mpo.qbond[j + 1])
+    Ro = torch.empty(nout, dtype=torch.complex128, device="cuda")
+    pk.env_update_right(ly, b, c, W, Rf, Bf, Ro, prec)
+    got = pk.unpack(Ro.cpu().numpy(), pk.LAYOUT_ENV_R, ly, b, qw=mpo.qbond[j + 1])
+    ref = bs.env_right_update(R, B, mpo.W[j + 1])
+    num = max(np.abs(got[k] - ref.get(k, 0)).max() for k in got)
+    den = max(np.abs(v).max() for v in ref.values())
+    assert set(ref) <= set(got)
+    assert num / den < tol
