@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""Benchmark of the mixed real/momentum-space cylinder DMRG hot path on one MI355X.
+
+One step = one bond update of the sweep, every row of the hot path on one batch of
+synthetic input (Ly=8, chi=3200 centre window, flux 1/8, t = V = 1):
+
+  plan      charge matching of L, W1, W2, R, theta into block task tables (host) and
+            precision staging of L and R (device);
+  lanczos   30-step Lanczos ground state of H_eff (each step one matvec: L.theta block
+            GEMMs, MPO mixing, (.).R block GEMMs), FP64 reorthogonalisation and
+            tridiagonal solve, plus the FP64 Rayleigh quotient in low precision;
+  env       env_update_left and env_update_right through the window.
+
+Inputs are resident in HBM before the timed region: the library's own Hofstadter MPO,
+environments contracted on the GPU from seeded isometries (workloads), and a seeded
+random start vector.  value = algorithmic GFLOP of the step / step time, where the
+flops are counted from the library's task tables (8 real flops per complex
+multiply-add, no padding).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64]
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H_eff matvec GFLOP/s & Lanczos time at Ly=8 χ=3200: FP32/BF16x3 vs FP64"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA, MI355X
+HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_inputs(pk, torch, wl, stream):
+    """Environments at the window from seeded isometries, contracted on the GPU."""
+    import workloads
+    mpo = pk.HofstadterMPO(wl.Ly, wl.Lx, wl.flux[0], wl.flux[1], wl.t, wl.V, wl.basis)
+    ly, j, n = wl.ly, wl.j, wl.n
+    dev = torch.device("cuda:0")
+    bonds = [pk.Bond(b) for b in wl.bonds]
+    sites = [mpo.site(i) for i in range(n)]
+
+    def dev_of(flat):
+        return torch.from_numpy(flat).to(dev)
+
+    L = torch.ones(1, dtype=torch.complex128, device=dev)
+    for i in range(j):
+        A = dev_of(pk.pack(wl.site_tensor(i), pk.LAYOUT_SITE, ly, bonds[i], bonds[i + 1], qs1=sites[i].qs))
+        _, nout = pk.layout(pk.LAYOUT_ENV_L, ly, bonds[i + 1], qw=sites[i].qr)
+        Lo = torch.empty(nout, dtype=torch.complex128, device=dev)
+        pk.env_update_left(ly, bonds[i], bonds[i + 1], sites[i], L, A, Lo, pk.DM_FP64, stream)
+        L = Lo
+        if i % 32 == 31:
+            log(f"  left environment: {i + 1}/{j} sites")
+    R = torch.ones(1, dtype=torch.complex128, device=dev)
+    for i in range(n - 1, j + 1, -1):
+        B = dev_of(pk.pack(wl.site_tensor(i), pk.LAYOUT_SITE, ly, bonds[i], bonds[i + 1], qs1=sites[i].qs))
+        _, nout = pk.layout(pk.LAYOUT_ENV_R, ly, bonds[i], qw=sites[i].ql)
+        Ro = torch.empty(nout, dtype=torch.complex128, device=dev)
+        pk.env_update_right(ly, bonds[i], bonds[i + 1], sites[i], R, B, Ro, pk.DM_FP64, stream)
+        R = Ro
+        if i % 32 == 0:
+            log(f"  right environment: {n - i}/{n - j - 2} sites")
+    a, b, c = bonds[j], bonds[j + 1], bonds[j + 2]
+    w1, w2 = sites[j], sites[j + 1]
+    theta = dev_of(pk.pack(wl.theta(), pk.LAYOUT_THETA, ly, a, c, qs1=w1.qs, qs2=w2.qs))
+    import numpy as np
+    rng = np.random.default_rng(1234)
+    Aj = dev_of(pk.pack(workloads.left_isometry(rng, wl.bonds[j], wl.bonds[j + 1], wl.qsite[j], ly),
+                        pk.LAYOUT_SITE, ly, a, b, qs1=w1.qs))
+    Bj = dev_of(pk.pack(workloads.right_isometry(rng, wl.bonds[j + 1], wl.bonds[j + 2], wl.qsite[j + 1], ly),
+                        pk.LAYOUT_SITE, ly, b, c, qs1=w2.qs))
+    _, nl = pk.layout(pk.LAYOUT_ENV_L, ly, b, qw=w1.qr)
+    _, nr = pk.layout(pk.LAYOUT_ENV_R, ly, b, qw=w2.ql)
+    out = dict(ly=ly, a=a, b=b, c=c, w1=w1, w2=w2, L=L, R=R, theta=theta, Aj=Aj, Bj=Bj,
+               Lnext=torch.empty(nl, dtype=torch.complex128, device=dev),
+               Rnext=torch.empty(nr, dtype=torch.complex128, device=dev),
+               D=(w1.W.shape[0], w1.W.shape[3], w2.W.shape[3]))
+    out["env_flops"] = (pk.env_flops(True, ly, a, b, w1), pk.env_flops(False, ly, b, c, w2))
+    return out
+
+
+def run_step(pk, inp, prec, iters, stream, profile=False):
+    """One bond update; returns (energy, iterations, plan, host times)."""
+    t0 = time.perf_counter()
+    plan = pk.HeffPlan(inp["ly"], inp["a"], inp["c"], inp["w1"], inp["w2"], inp["L"], inp["R"],
+                       prec, stream)
+    if profile:
+        plan.profile(True)
+    th = inp["theta"].clone()
+    t1 = time.perf_counter()
+    e, k = pk.lanczos_ground(plan, th, iters, 1e-14, stream)
+    t2 = time.perf_counter()
+    pk.env_update_left(inp["ly"], inp["a"], inp["b"], inp["w1"], inp["L"], inp["Aj"], inp["Lnext"], prec, stream)
+    pk.env_update_right(inp["ly"], inp["b"], inp["c"], inp["w2"], inp["R"], inp["Bj"], inp["Rnext"], prec, stream)
+    t3 = time.perf_counter()
+    return e, k, plan, (t1 - t0, t2 - t1, t3 - t2)
+
+
+def step_flops(plan, k, prec, env_flops, pk):
+    mv = sum(plan.flops)
+    n_mv = k + (1 if prec != pk.DM_FP64 else 0)
+    return n_mv * mv + sum(env_flops)
+
+
+def matvec_time(pk, torch, inp, prec, stream, reps=20):
+    plan = pk.HeffPlan(inp["ly"], inp["a"], inp["c"], inp["w1"], inp["w2"], inp["L"], inp["R"], prec, stream)
+    x = inp["theta"]
+    y = torch.empty_like(x)
+    for _ in range(3):
+        pk.heff_apply(plan, x, y, stream)
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(s)
+    for _ in range(reps):
+        pk.heff_apply(plan, x, y, stream)
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) / reps, sum(plan.flops), plan.flops
+
+
+def cpu_baseline(wl, iters=30):
+    """The FP64 oracle on the host: a 30-step oracle Lanczos of the same window with
+    random environments of the exact block structure (bounded sample)."""
+    import numpy as np
+
+    import workloads
+    from oracle import blocksparse as bs
+    from oracle import lanczos as olz
+    from oracle import mpo as omp
+    from oracle import synth
+    m = omp.build(synth.cylinder_of(wl), wl.basis)
+    j = wl.j
+    rng = np.random.default_rng(7)
+    L = workloads.random_env(rng, wl.bonds[j], m.qbond[j], wl.ly, "L")
+    R = workloads.random_env(rng, wl.bonds[j + 2], m.qbond[j + 2], wl.ly, "R")
+    keys = bs.theta_keys(wl.bonds[j], wl.bonds[j + 2], wl.qsite[j], wl.qsite[j + 1], wl.ly)
+    th = bs.flatten(wl.theta(), keys)
+    nmv = [0]
+
+    def mv(v):
+        nmv[0] += 1
+        return bs.flatten(bs.heff_apply(L, m.W[j], m.W[j + 1], R, bs.unflatten(v, keys)), keys)
+
+    # flops of one matvec from the oracle's own block structure (8 per complex MAC)
+    flops = 0.0
+    byl = {}
+    for (qa, s1, s2, qc), blk in wl.theta().items():
+        byl.setdefault(qa, []).append(blk.shape[1])
+    for (qap, w, qa), lb in L.items():
+        for nc in byl.get(qa, []):
+            flops += 8.0 * lb.shape[0] * lb.shape[1] * nc
+    t0 = time.perf_counter()
+    olz.lanczos(mv, th, max_iter=iters)
+    dt = time.perf_counter() - t0
+    # the (.).R half has the same shape class; count it from R blocks and theta rows
+    byr = {}
+    for (qa, s1, s2, qc), blk in wl.theta().items():
+        byr.setdefault(qc, []).append(blk.shape[0])
+    for (qcp, w, qc), rb in R.items():
+        for na in byr.get(qcp, []):
+            flops += 8.0 * rb.shape[0] * rb.shape[1] * na
+    cores = len(os.sched_getaffinity(0))
+    return {"value": round(nmv[0] * flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{iters}-step FP64 oracle Lanczos (numpy, per-block matmuls) of the same "
+                      f"window, random environments of the exact block structure, {dt:.1f} s; "
+                      f"block-GEMM flops only"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ly8_chi3200")
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--iters", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no "
+              f"multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1512_03318_amd as pk
+    import workloads
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    prec = {"fp64": pk.DM_FP64, "fp32": pk.DM_FP32}[args.prec]
+
+    wl = workloads.preset(args.workload)
+    t0 = time.perf_counter()
+    inp = build_inputs(pk, torch, wl, stream)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s: {args.workload} Lx={wl.Lx} "
+        f"chi={sum(wl.bonds[wl.j].values())} sectors={len(wl.bonds[wl.j])} D={inp['D']}")
+
+    for i in range(args.warmup):
+        e, k, _, ts = run_step(pk, inp, prec, args.iters, stream)
+        log(f"warmup {i}: E={e:.12f} iters={k} plan/lanczos/env s = {ts}")
+    torch.cuda.synchronize()
+    host = []
+    flops = 0.0
+    prof = [0.0, 0.0, 0.0]
+    nmv = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        e, k, plan, ts = run_step(pk, inp, prec, args.iters, stream, profile=True)
+        ms, nm = plan.profile_read()
+        prof = [p + q for p, q in zip(prof, ms)]
+        nmv += nm
+        flops += step_flops(plan, k, prec, inp["env_flops"], pk)
+        host.append(ts)
+        stage_flops = plan.flops
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    value = flops / elapsed / 1e9
+    lanczos_ms = 1e3 * statistics.median(t[1] for t in host)
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step, {value:.1f} GFLOP/s, lanczos {lanczos_ms:.2f} ms, E={e:.12f}")
+
+    # dominant kernel: the stage with the most device time
+    names = ["L.theta block GEMM", "MPO mixing", "(.).R block GEMM"]
+    dom = max(range(3), key=lambda s: prof[s])
+    avg_ms = prof[dom] / max(nmv, 1)
+    achieved = stage_flops[dom] / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": f"gemm_kernel ({names[dom]}, {args.prec})",
+                "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS[args.prec], 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4),
+                "stage_ms_per_matvec": [round(p / max(nmv, 1), 4) for p in prof]}
+
+    mv_ms, mv_flops, _ = matvec_time(pk, torch, inp, prec, stream)
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c64" if prec == pk.DM_FP32 else "c128", "data": "synthetic",
+           "config": {"workload": args.workload, "Ly": wl.Ly, "Lx": wl.Lx, "flux": f"{wl.flux[0]}/{wl.flux[1]}",
+                      "chi": int(sum(wl.bonds[wl.j].values())), "sectors": len(wl.bonds[wl.j]),
+                      "mpo_D": list(inp["D"]), "lanczos_iters": args.iters, "precision": args.prec,
+                      "lanczos_fp64": True},
+           "energy": e, "lanczos_steps": k,
+           "lanczos_ms": round(lanczos_ms, 3),
+           "matvec_ms": round(mv_ms, 4), "matvec_gflops": round(mv_flops / mv_ms / 1e6, 2),
+           "matvec_gflop": round(mv_flops / 1e9, 4),
+           "roofline": roofline}
+    if not args.no_fp64_compare and prec != pk.DM_FP64:
+        f_ms, _, _ = matvec_time(pk, torch, inp, pk.DM_FP64, stream)
+        e64, k64, _, ts64 = run_step(pk, inp, pk.DM_FP64, args.iters, stream)
+        torch.cuda.synchronize()
+        hs = []
+        for _ in range(2):
+            e64, k64, _, ts64 = run_step(pk, inp, pk.DM_FP64, args.iters, stream)
+            hs.append(ts64)
+        out["fp64"] = {"matvec_ms": round(f_ms, 4), "matvec_gflops": round(mv_flops / f_ms / 1e6, 2),
+                       "lanczos_ms": round(1e3 * statistics.median(t[1] for t in hs), 3),
+                       "step_ms": round(1e3 * statistics.median(sum(t) for t in hs), 3),
+                       "energy": e64, "rel_energy_diff_cold_start": abs(e - e64) / abs(e64)}
+        out["speedup_vs_fp64"] = {"matvec": round(f_ms / mv_ms, 3),
+                                  "lanczos": round(out["fp64"]["lanczos_ms"] / lanczos_ms, 3)}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

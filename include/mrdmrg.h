@@ -154,6 +154,14 @@ void dm_heff_plan_destroy(dm_heff_plan* p);
  * flops[1] = MPO mixing, flops[2] = (.).R block GEMMs. */
 int dm_heff_info(const dm_heff_plan* p, int64_t* theta_elems, double flops[3]);
 
+/* Device-time profile of the matvec stages.  While enabled, every matvec of the plan
+ * (heff_apply and the ones inside lanczos_ground) records HIP events on its stream
+ * around each stage; dm_heff_profile_read synchronises and returns the accumulated
+ * milliseconds of stage 0 (L.theta GEMMs), 1 (MPO mixing), 2 ((.).R GEMMs) and the
+ * number of matvecs recorded.  enable = 0 stops recording and clears the totals. */
+int dm_heff_profile(dm_heff_plan* p, int32_t enable);
+int dm_heff_profile_read(dm_heff_plan* p, double ms[3], int64_t* matvecs);
+
 /* theta_out = H_eff theta.  Both are device complex128 in the THETA layout of (a, c,
  * w1.qs, w2.qs); they must not overlap.  Asynchronous on `stream`. */
 int heff_apply(dm_heff_plan* p, const void* theta, void* theta_out, dm_stream stream);
@@ -177,6 +185,12 @@ int env_update_left(int32_t ly, const dm_bond* a, const dm_bond* b, const dm_mpo
                     const void* L, const void* A, void* L_out, int32_t prec, dm_stream stream);
 int env_update_right(int32_t ly, const dm_bond* b, const dm_bond* c, const dm_mpo_site* w,
                      const void* R, const void* B, void* R_out, int32_t prec, dm_stream stream);
+
+/* Algorithmic flops of one environment update, 8 per complex multiply-add, counted on
+ * the same task tables the update runs.  left = 1: env_update_left from bond x (= a) to
+ * bond y (= b); left = 0: env_update_right from bond y (= c) to bond x (= b). */
+int dm_env_flops(int32_t left, int32_t ly, const dm_bond* x, const dm_bond* y,
+                 const dm_mpo_site* w, double* flops);
 
 /* ---- Many independent problems -------------------------------------------------
  * A batch merges the task tables of n plans (same precision) so that every phase of

@@ -8,11 +8,11 @@ library's canonical layouts (offsets come from ``dm_layout``).  Every arithmetic
 runs in the library.  Importing this package fails if the library is missing.
 """
 from .binding import (DM_BF16X3, DM_FP32, DM_FP64, Bond, HeffPlan, Batch, HofstadterMPO,
-                      LibraryError, MpoSite, env_update_left, env_update_right, heff_apply,
+                      LibraryError, MpoSite, env_flops, env_update_left, env_update_right, heff_apply,
                       lanczos_ground, lanczos_ground_batched, layout, lib, pack, unpack,
                       LAYOUT_SITE, LAYOUT_THETA, LAYOUT_ENV_L, LAYOUT_ENV_R)
 
 __all__ = ["DM_BF16X3", "DM_FP32", "DM_FP64", "Bond", "HeffPlan", "Batch", "HofstadterMPO",
-           "LibraryError", "MpoSite", "env_update_left", "env_update_right", "heff_apply",
+           "LibraryError", "MpoSite", "env_flops", "env_update_left", "env_update_right", "heff_apply",
            "lanczos_ground", "lanczos_ground_batched", "layout", "lib", "pack", "unpack",
            "LAYOUT_SITE", "LAYOUT_THETA", "LAYOUT_ENV_L", "LAYOUT_ENV_R"]

@@ -70,6 +70,10 @@ _sigs = {
     "dm_mpo_n_sites": (_i32, [_vp]),
     "dm_mpo_site_get": (_i32, [_vp, _i32, C.POINTER(DmMpoSite)]),
     "dm_mpo_destroy": (None, [_vp]),
+    "dm_heff_profile": (_i32, [_vp, _i32]),
+    "dm_heff_profile_read": (_i32, [_vp, C.POINTER(_f64), C.POINTER(_i64)]),
+    "dm_env_flops": (_i32, [_i32, _i32, C.POINTER(DmBond), C.POINTER(DmBond), C.POINTER(DmMpoSite),
+                            C.POINTER(_f64)]),
     "dm_last_error": (C.c_char_p, []),
 }
 for _name, (_res, _args) in _sigs.items():
@@ -212,10 +216,26 @@ class HeffPlan:
         self.n = n.value
         self.flops = tuple(fl)
 
+    def profile(self, enable=True):
+        _check(lib.dm_heff_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(ms per stage [L.theta GEMMs, mixing, (.).R GEMMs] accumulated, matvecs recorded)."""
+        ms = (_f64 * 3)()
+        n = _i64()
+        _check(lib.dm_heff_profile_read(self.h, ms, C.byref(n)))
+        return list(ms), n.value
+
     def __del__(self):
         if getattr(self, "h", None):
             lib.dm_heff_plan_destroy(self.h)
             self.h = None
+
+
+def env_flops(left: bool, ly, x: Bond, y: Bond, w: MpoSite) -> float:
+    f = _f64()
+    _check(lib.dm_env_flops(1 if left else 0, ly, C.byref(x.c), C.byref(y.c), C.byref(w.c), C.byref(f)))
+    return f.value
 
 
 def heff_apply(plan: HeffPlan, theta, theta_out, stream=None):

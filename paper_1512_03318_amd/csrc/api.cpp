@@ -236,7 +236,13 @@ struct dm_heff_plan {
   double* dScal = nullptr;
   double* dY = nullptr;
   double* hPinned = nullptr;  // host pinned scratch
+  // profiling: events around the three stages of each recorded matvec
+  bool profiling = false;
+  std::vector<std::array<hipEvent_t, 4>> ev;
+  size_t ev_used = 0;
   ~dm_heff_plan() {
+    for (auto& e : ev)
+      for (hipEvent_t x : e) (void)hipEventDestroy(x);
     for (GemmStage* st : {&s1, &s4}) free_stage(*st);
     free_stage(mix);
     for (void* p : {dL, dR, dL64, dR64, dX, dZ, dX64, dZ64, dTin, dTout})
@@ -426,9 +432,23 @@ extern "C" int dm_heff_info(const dm_heff_plan* p, int64_t* theta_elems, double 
   return DM_OK;
 }
 
+static hipEvent_t* prof_slot(dm_heff_plan* p) {
+  if (!p->profiling) return nullptr;
+  if (p->ev_used == p->ev.size()) {
+    std::array<hipEvent_t, 4> e;
+    for (auto& x : e) HIPCHK(hipEventCreate(&x));
+    p->ev.push_back(e);
+  }
+  return p->ev[p->ev_used++].data();
+}
+
 // theta_out = H_eff theta in the plan's precision (FP64 in / out).
 static void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStream_t s,
                      bool force64) {
+  hipEvent_t* ev = force64 ? nullptr : prof_slot(p);
+  auto mark = [&](int i) {
+    if (ev) HIPCHK(hipEventRecord(ev[i], s));
+  };
   if (p->prec == DM_FP64 || force64) {
     void* dL = p->prec == DM_FP64 ? p->dL : p->dL64;
     void* dR = p->prec == DM_FP64 ? p->dR : p->dR64;
@@ -440,16 +460,47 @@ static void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStr
       dX = p->dX64;
       dZ = p->dZ64;
     }
+    mark(0);
     HIPCHK(launch_gemm<double>(p->s1, (const double*)dL, (const double*)theta, (double*)dX, s));
+    mark(1);
     HIPCHK(launch_mix<double>(p->mix, (const double*)dX, (double*)dZ, s));
+    mark(2);
     HIPCHK(launch_gemm<double>(p->s4, (const double*)dZ, (const double*)dR, (double*)theta_out, s));
+    mark(3);
     return;
   }
   stage_in(theta, p->dTin, p->n(), DM_FP32, s);
+  mark(0);
   HIPCHK(launch_gemm<float>(p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, s));
+  mark(1);
   HIPCHK(launch_mix<float>(p->mix, (const float*)p->dX, (float*)p->dZ, s));
+  mark(2);
   HIPCHK(launch_gemm<float>(p->s4, (const float*)p->dZ, (const float*)p->dR, (float*)p->dTout, s));
+  mark(3);
   stage_out(p->dTout, theta_out, p->n(), DM_FP32, s);
+}
+
+extern "C" int dm_heff_profile(dm_heff_plan* p, int32_t enable) {
+  if (!p) return fail(DM_ERR_ARG, "null plan");
+  p->profiling = enable != 0;
+  p->ev_used = 0;
+  return DM_OK;
+}
+
+extern "C" int dm_heff_profile_read(dm_heff_plan* p, double ms[3], int64_t* matvecs) {
+  return guarded([&] {
+    if (!p || !ms) throw DmError{DM_ERR_ARG, "null argument"};
+    ms[0] = ms[1] = ms[2] = 0.0;
+    for (size_t i = 0; i < p->ev_used; ++i) {
+      HIPCHK(hipEventSynchronize(p->ev[i][3]));
+      for (int st = 0; st < 3; ++st) {
+        float t = 0;
+        HIPCHK(hipEventElapsedTime(&t, p->ev[i][st], p->ev[i][st + 1]));
+        ms[st] += t;
+      }
+    }
+    if (matvecs) *matvecs = (int64_t)p->ev_used;
+  });
 }
 
 extern "C" int heff_apply(dm_heff_plan* p, const void* theta, void* theta_out, dm_stream stream) {
@@ -945,6 +996,25 @@ extern "C" int env_update_right(int32_t ly, const dm_bond* b, const dm_bond* c,
     validate(ep.mix, ep.t1total, ep.t2total);
     validate(ep.t3, S.P.total, ep.t2total, Ro.P.total);
     run_env(ep, R, Ri.P.total, B, S.P.total, R_out, Ro.P.total, prec, (hipStream_t)stream);
+  });
+}
+
+extern "C" int dm_env_flops(int32_t left, int32_t ly, const dm_bond* x, const dm_bond* y,
+                            const dm_mpo_site* w, double* flops) {
+  return guarded([&] {
+    if (!flops) throw DmError{DM_ERR_ARG, "null output"};
+    check_ly(ly);
+    Bond bx = make_bond(x, ly), by = make_bond(y, ly);
+    MpoSite W = make_mpo(w, ly);
+    if (left) {
+      EnvLLayout Li = envl_layout(bx, W.ql, ly), Lo = envl_layout(by, W.qr, ly);
+      SiteLayout S = site_layout(bx, by, W.qs, ly);
+      *flops = plan_left(ly, bx, by, W, Li, S, Lo).flops();
+    } else {
+      EnvRLayout Ri = envr_layout(by, W.qr, ly), Ro = envr_layout(bx, W.ql, ly);
+      SiteLayout S = site_layout(bx, by, W.qs, ly);
+      *flops = plan_right(ly, bx, by, W, Ri, S, Ro).flops();
+    }
   });
 }
 

@@ -151,6 +151,19 @@ def random_theta(rng, ba: dict, bc: dict, qs1, qs2, ly: int) -> dict:
     return out
 
 
+def random_env(rng, bond: dict, qw, ly: int, side: str) -> dict:
+    """Random environment blocks with the block structure of a left (side="L",
+    q(a') = q(a) + q(w)) or right (side="R", same rule on (c', c)) environment on
+    ``bond`` with MPO state charges ``qw`` (given by the caller).  Keys (q', w, q)."""
+    out = {}
+    for w, qwv in enumerate(qw):
+        for q, m in bond.items():
+            qp = _add(q, (int(qwv[0]), int(qwv[1])), ly)
+            if qp in bond:
+                out[(qp, w, q)] = _gauss(rng, (bond[qp], m))
+    return out
+
+
 @dataclass
 class Workload:
     """A finite cylinder MPS with a two-site window at orbitals (j, j+1)."""
