@@ -66,16 +66,22 @@ void upload_stage(GemmStage& st) {
   st.d_probs = upload(st.probs);
   st.d_tiles = upload(st.tiles);
   st.d_rows = upload(st.rows);
+  st.d_asrc = upload(st.asrc);
+  st.d_red_tiles = upload(st.red_tiles);
 }
 void free_stage(GemmStage& st) {
   dev_free(st.d_segs);
   dev_free(st.d_probs);
   dev_free(st.d_tiles);
   dev_free(st.d_rows);
+  dev_free(st.d_asrc);
+  dev_free(st.d_red_tiles);
+  st.d_red_tiles = nullptr;
   st.d_segs = nullptr;
   st.d_probs = nullptr;
   st.d_tiles = nullptr;
   st.d_rows = nullptr;
+  st.d_asrc = nullptr;
 }
 void upload_stage(MixStage& st) {
   st.d_tasks = upload(st.tasks);
@@ -209,21 +215,23 @@ struct dm_heff_plan {
   EnvRLayout R;
   std::vector<int64_t> xoff;  // per a: X panel offset (rows = L.P.rows[a], cols = th.P.cols[a])
   int64_t xtotal = 0;
-  std::vector<int64_t> zoff;  // per c': Z panel offset (rows zrows[c'], cols R.P.cols[c'])
-  std::vector<int> zrows;
-  std::vector<std::array<int, 4>> zroff;
-  int64_t ztotal = 0;
   GemmStage s1, s4;
   MixStage mix;
+  double mix_flops = 0;
+  std::vector<int64_t> zoff;  // per c': Z panel offset (rows zrows[c'], cols R.P.cols[c'])
+  std::vector<int> zrows;
+  int64_t ztotal = 0;
+  void* dZ = nullptr;
+  void* dZ64 = nullptr;
   // device buffers (elements in the plan's precision)
   void* dL = nullptr;
   void* dR = nullptr;
   void* dL64 = nullptr;  // FP64 copies for the final Rayleigh quotient (low precision plans)
   void* dR64 = nullptr;
   void* dX = nullptr;
-  void* dZ = nullptr;
   void* dX64 = nullptr;
-  void* dZ64 = nullptr;
+  void* dSplit = nullptr;    // K-split partial tiles of the (.)R stage
+  void* dSplit64 = nullptr;
   void* dTin = nullptr;  // low-precision staging of theta in / out
   void* dTout = nullptr;
   // Lanczos workspace (FP64)
@@ -245,7 +253,7 @@ struct dm_heff_plan {
       for (hipEvent_t x : e) (void)hipEventDestroy(x);
     for (GemmStage* st : {&s1, &s4}) free_stage(*st);
     free_stage(mix);
-    for (void* p : {dL, dR, dL64, dR64, dX, dZ, dX64, dZ64, dTin, dTout})
+    for (void* p : {dL, dR, dL64, dR64, dX, dX64, dSplit, dSplit64, dTin, dTout, dZ, dZ64})
       dev_free(p);
     for (double* p : {dV, dW, dPart, dH1, dH2, dScal, dY}) dev_free(p);
     if (hPinned) (void)hipHostFree(hPinned);
@@ -264,26 +272,14 @@ static void build_heff_tables(dm_heff_plan& p) {
     p.xoff[i] = p.xtotal;
     p.xtotal += (int64_t)p.L.P.rows[i] * p.th.P.cols[i];
   }
-  // Z panels: per c', rows (s1' s2', a'), cols (w'', c)
-  p.zoff.assign(c.size(), 0);
-  p.zrows.assign(c.size(), 0);
-  p.zroff.assign(c.size(), {-1, -1, -1, -1});
-  p.ztotal = 0;
+  // zap[c'][s12'] = a' with theta block (a', s12', c'), or -1
   std::vector<std::array<int, 4>> zap(c.size(), {-1, -1, -1, -1});
-  for (int ci = 0; ci < c.size(); ++ci) {
-    int rows = 0;
+  for (int ci = 0; ci < c.size(); ++ci)
     for (int s12 = 0; s12 < 4; ++s12) {
       dm_charge qa = qsub(qsub(c.q[ci], p.w1.qs[s12 >> 1], ly), p.w2.qs[s12 & 1], ly);
       const int ai = a.find(qa);
-      if (ai < 0 || p.th.c[ai][s12] != ci) continue;
-      zap[ci][s12] = ai;
-      p.zroff[ci][s12] = rows;
-      rows += a.dim[ai];
+      if (ai >= 0 && p.th.c[ai][s12] == ci) zap[ci][s12] = ai;
     }
-    p.zrows[ci] = rows;
-    p.zoff[ci] = p.ztotal;
-    p.ztotal += (int64_t)rows * p.R.P.cols[ci];
-  }
   // S1: X_a = Lpanel_a (M_a x m_a) . Theta_a (m_a x N_a)
   GemmStage& s1 = p.s1;
   s1.flags = 0;
@@ -292,8 +288,8 @@ static void build_heff_tables(dm_heff_plan& p) {
     if (M == 0 || N == 0) continue;
     GemmProb pr{p.xoff[ai], M, N, (int32_t)s1.segs.size(), 1, N, -1};
     s1.segs.push_back({p.L.P.off[ai], p.th.P.off[ai], K, N, K, 0});
-    add_tiles(s1, (int32_t)s1.probs.size(), M, N);
     s1.probs.push_back(pr);
+    add_tiles(s1, (int32_t)s1.probs.size() - 1, M, N);
     s1.flops += 8.0 * M * N * K;
   }
   // two-site MPO W12[w, s12', s12, w''] = sum_w' W1[w, s1', s1, w'] W2[w', s2', s2, w'']
@@ -315,17 +311,34 @@ static void build_heff_tables(dm_heff_plan& p) {
                 W12(w, s1p * 2 + s2p, s1 * 2 + s2, wpp) += x * y;
               }
         }
-  // Mix: Z[(s12', a'), (w'', c)] = sum W12[w, s12', s12, w''] X_a[(w, a'), (s12, c)]
+  // Mixing: Z_{c'}[(s12', a'), (w'', c)] = sum_{w, s12} W12[w, s12', s12, w''] X_a[(w, a'), (s12, c)]
+  // Z panel per output sector c': rows (s12', a') stacked, columns the R panel's (w'', c).
+  p.zoff.assign(c.size(), 0);
+  p.zrows.assign(c.size(), 0);
+  p.ztotal = 0;
+  std::vector<std::array<int, 4>> zroff(c.size(), {-1, -1, -1, -1});
+  for (int ci2 = 0; ci2 < c.size(); ++ci2) {
+    int rows = 0;
+    for (int s12p = 0; s12p < 4; ++s12p) {
+      const int aip = zap[ci2][s12p];
+      if (aip < 0) continue;
+      zroff[ci2][s12p] = rows;
+      rows += a.dim[aip];
+    }
+    p.zrows[ci2] = rows;
+    p.zoff[ci2] = p.ztotal;
+    p.ztotal += (int64_t)rows * p.R.P.cols[ci2];
+  }
   MixStage& mx = p.mix;
   for (int ci2 = 0; ci2 < c.size(); ++ci2) {
-    const int K = p.R.P.cols[ci2];
+    const int Kc = p.R.P.cols[ci2];
     for (int s12p = 0; s12p < 4; ++s12p) {
       const int aip = zap[ci2][s12p];
       if (aip < 0) continue;
       for (int wpp = 0; wpp < dr; ++wpp) {
         const int ci = p.R.c[ci2 * dr + wpp];
         if (ci < 0) continue;
-        MixTask tk{p.zoff[ci2] + (int64_t)p.zroff[ci2][s12p] * K + p.R.coff[ci2 * dr + wpp], K,
+        MixTask tk{p.zoff[ci2] + (int64_t)zroff[ci2][s12p] * Kc + p.R.coff[ci2 * dr + wpp], Kc,
                    a.dim[aip], c.dim[ci], (int32_t)mx.srcs.size(), 0, 0};
         for (int w = 0; w < dl; ++w) {
           const int ai = a.find(qsub(a.q[aip], p.w1.ql[w], ly));
@@ -335,10 +348,9 @@ static void build_heff_tables(dm_heff_plan& p) {
             if (v == std::complex<double>(0, 0)) continue;
             if (p.th.c[ai][s12] != ci || p.L.ap[ai * dl + w] != aip)
               throw DmError{DM_ERR_CHARGE, "MPO charges inconsistent with the bonds"};
-            const int N = p.th.P.cols[ai];
-            MixSrc sr{p.xoff[ai] + (int64_t)p.L.roff[ai * dl + w] * N + p.th.coff[ai][s12], N, 0,
-                      v.real(), v.imag()};
-            mx.srcs.push_back(sr);
+            const int Na = p.th.P.cols[ai];
+            mx.srcs.push_back({p.xoff[ai] + (int64_t)p.L.roff[ai * dl + w] * Na + p.th.coff[ai][s12],
+                               Na, 0, v.real(), v.imag()});
             tk.nsrc++;
           }
         }
@@ -347,22 +359,26 @@ static void build_heff_tables(dm_heff_plan& p) {
       }
     }
   }
-  // S4: theta'_{c'} rows (s12', a') = Z_{c'} (M x K) . Rpanel_{c'}^T (K x m_c')
+  p.mix_flops = mx.flops;
+  // (.)R stage, one problem per output sector c':
+  //   theta'[(s12', a'), c'] = Z_{c'} (M x K) . Rpanel_{c'}^T (K x m_c'), K = R panel width,
+  // rows scattered to the theta blocks through the row table.  K-split over workgroups.
   GemmStage& s4 = p.s4;
   s4.flags = G_B_T | G_C_ROWMAP;
+  s4.deep = true;
   for (int ci2 = 0; ci2 < c.size(); ++ci2) {
     const int M = p.zrows[ci2], N = c.dim[ci2], K = p.R.P.cols[ci2];
     if (M == 0) continue;
-    GemmProb pr{0, M, N, (int32_t)s4.segs.size(), 1, 0, (int32_t)s4.rows.size()};
+    GemmProb pr{0, M, N, (int32_t)s4.segs.size(), K > 0 ? 1 : 0, 0, (int32_t)s4.rows.size()};
     for (int s12p = 0; s12p < 4; ++s12p) {
       const int aip = zap[ci2][s12p];
       if (aip < 0) continue;
       const int64_t base = p.th.P.off[aip] + p.th.coff[aip][s12p];
       for (int r = 0; r < a.dim[aip]; ++r) s4.rows.push_back(base + (int64_t)r * p.th.P.cols[aip]);
     }
-    s4.segs.push_back({p.zoff[ci2], p.R.P.off[ci2], K, K, K, 0});
-    add_tiles(s4, (int32_t)s4.probs.size(), M, N);
+    if (K > 0) s4.segs.push_back({p.zoff[ci2], p.R.P.off[ci2], K, K, K, 0});
     s4.probs.push_back(pr);
+    add_tiles(s4, (int32_t)s4.probs.size() - 1, M, N);
     s4.flops += 8.0 * M * N * K;
   }
 }
@@ -403,6 +419,7 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     p->dR = dev_alloc(p->R.P.total * eb);
     p->dX = dev_alloc(p->xtotal * eb);
     p->dZ = dev_alloc(p->ztotal * eb);
+    p->dSplit = dev_alloc(p->s4.nslots * 1024 * eb);
     hipStream_t s = (hipStream_t)stream;
     stage_in(L, p->dL, p->L.P.total, prec, s);
     stage_in(R, p->dR, p->R.P.total, prec, s);
@@ -426,7 +443,7 @@ extern "C" int dm_heff_info(const dm_heff_plan* p, int64_t* theta_elems, double 
   if (theta_elems) *theta_elems = p->n();
   if (flops) {
     flops[0] = p->s1.flops;
-    flops[1] = p->mix.flops;
+    flops[1] = p->mix_flops;
     flops[2] = p->s4.flops;
   }
   return DM_OK;
@@ -454,28 +471,33 @@ static void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStr
     void* dR = p->prec == DM_FP64 ? p->dR : p->dR64;
     void* dX = p->dX;
     void* dZ = p->dZ;
+    void* dP = p->dSplit;
     if (p->prec != DM_FP64) {
       if (!p->dX64) p->dX64 = dev_alloc(p->xtotal * 16);
       if (!p->dZ64) p->dZ64 = dev_alloc(p->ztotal * 16);
+      if (!p->dSplit64) p->dSplit64 = dev_alloc(p->s4.nslots * 1024 * 16);
       dX = p->dX64;
       dZ = p->dZ64;
+      dP = p->dSplit64;
     }
     mark(0);
-    HIPCHK(launch_gemm<double>(p->s1, (const double*)dL, (const double*)theta, (double*)dX, s));
+    HIPCHK(launch_gemm<double>(p->s1, (const double*)dL, (const double*)theta, (double*)dX, nullptr, s));
     mark(1);
     HIPCHK(launch_mix<double>(p->mix, (const double*)dX, (double*)dZ, s));
     mark(2);
-    HIPCHK(launch_gemm<double>(p->s4, (const double*)dZ, (const double*)dR, (double*)theta_out, s));
+    HIPCHK(launch_gemm<double>(p->s4, (const double*)dZ, (const double*)dR, (double*)theta_out,
+                               (double*)dP, s));
     mark(3);
     return;
   }
   stage_in(theta, p->dTin, p->n(), DM_FP32, s);
   mark(0);
-  HIPCHK(launch_gemm<float>(p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, s));
+  HIPCHK(launch_gemm<float>(p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, nullptr, s));
   mark(1);
   HIPCHK(launch_mix<float>(p->mix, (const float*)p->dX, (float*)p->dZ, s));
   mark(2);
-  HIPCHK(launch_gemm<float>(p->s4, (const float*)p->dZ, (const float*)p->dR, (float*)p->dTout, s));
+  HIPCHK(launch_gemm<float>(p->s4, (const float*)p->dZ, (const float*)p->dR, (float*)p->dTout,
+                            (float*)p->dSplit, s));
   mark(3);
   stage_out(p->dTout, theta_out, p->n(), DM_FP32, s);
 }
@@ -723,8 +745,8 @@ EnvPlan plan_left(int ly, const Bond& a, const Bond& b, const MpoSite& W, const 
     if (M == 0 || N == 0) continue;
     GemmProb pr{t1off[ai], M, N, (int32_t)ep.t1.segs.size(), 1, N, -1};
     ep.t1.segs.push_back({L.P.off[ai], S.P.off[ai], K, N, K, 0});
-    add_tiles(ep.t1, (int32_t)ep.t1.probs.size(), M, N);
     ep.t1.probs.push_back(pr);
+    add_tiles(ep.t1, (int32_t)ep.t1.probs.size() - 1, M, N);
     ep.t1.flops += 8.0 * M * N * K;
   }
   // T2 panel per b: rows (w', s', a') with b' = b + q(w'), a' = b' - q(s'); cols m_b
@@ -791,8 +813,8 @@ EnvPlan plan_left(int ly, const Bond& a, const Bond& b, const MpoSite& W, const 
         pr.nseg++;
         K += a.dim[api];
       }
-      add_tiles(ep.t3, (int32_t)ep.t3.probs.size(), M, N);
       ep.t3.probs.push_back(pr);
+      add_tiles(ep.t3, (int32_t)ep.t3.probs.size() - 1, M, N);
       ep.t3.flops += 8.0 * M * N * K;
     }
   return ep;
@@ -828,8 +850,8 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
       if (M == 0) continue;
       GemmProb pr{t1off[ci * 2 + s], M, N, (int32_t)ep.t1.segs.size(), 1, N, rm};
       ep.t1.segs.push_back({0, S.P.off[bi] + S.coff[bi][s], 0, S.P.cols[bi], K, 0});
-      add_tiles(ep.t1, (int32_t)ep.t1.probs.size(), M, N);
       ep.t1.probs.push_back(pr);
+      add_tiles(ep.t1, (int32_t)ep.t1.probs.size() - 1, M, N);
       ep.t1.flops += 8.0 * M * N * K;
     }
   // T2 per (w, b): rows (s', c') with b' = b + q(w), c' = b' + q(s'); cols m_b
@@ -899,8 +921,8 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
         pr.nseg++;
         K += c.dim[cpi];
       }
-      add_tiles(ep.t3, (int32_t)ep.t3.probs.size(), M, N);
       ep.t3.probs.push_back(pr);
+      add_tiles(ep.t3, (int32_t)ep.t3.probs.size() - 1, M, N);
       ep.t3.flops += 8.0 * M * N * K;
     }
   return ep;
@@ -927,18 +949,18 @@ void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64
     amalloc(&t1, ep.t1total * eb);
     amalloc(&t2, ep.t2total * eb);
     if (prec == DM_FP64) {
-      HIPCHK(launch_gemm<double>(ep.t1, (const double*)env, (const double*)site, (double*)t1, s));
+      HIPCHK(launch_gemm<double>(ep.t1, (const double*)env, (const double*)site, (double*)t1, nullptr, s));
       HIPCHK(launch_mix<double>(ep.mix, (const double*)t1, (double*)t2, s));
-      HIPCHK(launch_gemm<double>(ep.t3, (const double*)site, (const double*)t2, (double*)out, s));
+      HIPCHK(launch_gemm<double>(ep.t3, (const double*)site, (const double*)t2, (double*)out, nullptr, s));
     } else {
       amalloc(&e32, nenv * eb);
       amalloc(&s32, nsite * eb);
       amalloc(&o32, nout * eb);
       stage_in(env, e32, nenv, DM_FP32, s);
       stage_in(site, s32, nsite, DM_FP32, s);
-      HIPCHK(launch_gemm<float>(ep.t1, (const float*)e32, (const float*)s32, (float*)t1, s));
+      HIPCHK(launch_gemm<float>(ep.t1, (const float*)e32, (const float*)s32, (float*)t1, nullptr, s));
       HIPCHK(launch_mix<float>(ep.mix, (const float*)t1, (float*)t2, s));
-      HIPCHK(launch_gemm<float>(ep.t3, (const float*)s32, (const float*)t2, (float*)o32, s));
+      HIPCHK(launch_gemm<float>(ep.t3, (const float*)s32, (const float*)t2, (float*)o32, nullptr, s));
       stage_out(o32, out, nout, DM_FP32, s);
     }
   } catch (const DmError& e) {

@@ -21,20 +21,24 @@ namespace mrd {
 // All offsets count complex elements.  A_CONJ conjugates A.  The K-segments of one
 // problem are summed in order into one accumulator; C is overwritten.
 // ---------------------------------------------------------------------------------
+//   A_MIX:   A(i, k) = sum_q coef_q X[src_q.off + i * src_q.ld + k] over the segment's
+//            sources (a_off = first source, nsrc = count) -- the sparse MPO mixing is
+//            folded into the operand load, so the mixed intermediate is never stored.
 enum GemmFlags : int32_t {
   G_A_T = 1,
   G_A_CONJ = 2,
   G_B_T = 4,
   G_A_ROWMAP = 8,
   G_C_ROWMAP = 16,
+  G_A_MIX = 32,
 };
 
 struct GemmSeg {
-  int64_t a_off;
+  int64_t a_off;  // A_MIX: index of the first source in the stage's source list
   int64_t b_off;
   int32_t lda, ldb;
   int32_t k;
-  int32_t pad;
+  int32_t nsrc;   // A_MIX: number of sources
 };
 
 struct GemmProb {
@@ -43,13 +47,16 @@ struct GemmProb {
   int32_t seg0, nseg;
   int32_t ldc;
   int32_t rowmap;  // start in the row table (A or C, by flags), -1 if none
+  int32_t nks;     // DEEP: K-splits; split ks takes segments ks, ks + nks, ...
+  int32_t slot0;   // DEEP with nks > 1: first partial-tile slot of this problem
 };
 
-// One output tile of one problem: rows [tm*TM, ...), cols [tn*TN, ...).
+// One output tile of one problem: rows [tm*TM, ...), cols [tn*TN, ...) with the tile
+// size of the stage (gemm_tile_m / gemm_tile_n); ks = K-split index (DEEP).
 struct GemmTile {
   int32_t prob;
   int32_t tm, tn;
-  int32_t pad;
+  int32_t ks;
 };
 
 // Sparse mixing: dst[r, c] = sum_s coef_s * src_s[r, c] over a rows x cols sub-block.
@@ -69,16 +76,22 @@ struct MixSrc {
 // Host-side task table of one contraction stage, with its device copy.
 struct GemmStage {
   int32_t flags = 0;
+  bool deep = false;  // one workgroup per tile, K-segments split over its 4 waves
   std::vector<GemmSeg> segs;
   std::vector<GemmProb> probs;
   std::vector<GemmTile> tiles;
   std::vector<int64_t> rows;  // row table
-  double flops = 0.0;         // algorithmic: 8 * M * N * K per problem
+  std::vector<MixSrc> asrc;   // A_MIX sources
+  std::vector<GemmTile> red_tiles;  // DEEP: tiles whose K-split partials are summed
+  int64_t nslots = 0;               // DEEP: partial tiles (32 x 32 each, per split)
+  double flops = 0.0;         // algorithmic: 8 * M * N * K per problem (+ mixing MACs)
   // device
   GemmSeg* d_segs = nullptr;
   GemmProb* d_probs = nullptr;
   GemmTile* d_tiles = nullptr;
   int64_t* d_rows = nullptr;
+  MixSrc* d_asrc = nullptr;
+  GemmTile* d_red_tiles = nullptr;
 };
 
 struct MixStage {
@@ -89,12 +102,14 @@ struct MixStage {
   MixSrc* d_srcs = nullptr;
 };
 
-constexpr int TILE_M = 32;
-constexpr int TILE_N = 32;
+// Output tile of one workgroup: 64 x 64 for short-K stages, 32 x 32 for DEEP stages.
+int gemm_tile_m(bool deep);
+int gemm_tile_n(bool deep);
 
 // Kernel launchers (kernels.hip).  T = double or float (complex interleaved).
+// part: scratch of st.nslots * 1024 complex elements (DEEP stages with K-splits).
 template <typename T>
-hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, hipStream_t s);
+hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* part, hipStream_t s);
 template <typename T>
 hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s);
 hipError_t launch_cast_d2f(const double* in, float* out, int64_t n_real, hipStream_t s);

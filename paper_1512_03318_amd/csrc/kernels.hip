@@ -56,145 +56,336 @@ __device__ __forceinline__ void stc(T* base, int64_t off, T re, T im) {
 }
 
 // ---------------------------------------------------------------------------------
-// Grouped complex GEMM.  One wavefront computes one 32 x 32 output tile as 2 x 2
-// MFMA 16x16x4 blocks.  Operands are read straight from global memory (the blocks are
-// small, K is short, and L1/L2 serve the reuse between the waves of a tile column);
-// the next K-step is prefetched into registers while the current one is multiplied.
+// Grouped complex GEMM on MFMA 16x16x4 with LDS staging.
+//
+// A workgroup (4 waves) owns one BM x BN output tile of one problem and walks the
+// problem's K-segments in chunks of KC (32 WIDE, 64 DEEP).  Each chunk of A (BM x KC) and B (KC x BN)
+// is loaded cooperatively with coalesced accesses -- consecutive threads read
+// consecutive elements along the operand's contiguous dimension -- then stored to LDS
+// as separate real / imaginary planes indexed [k][row], so that MFMA operands are
+// conflict-free LDS reads.  The global loads of the next chunk are issued before the
+// current chunk is multiplied.
+//
+//   WIDE (BM = BN = 64): waves own the four 32 x 32 quadrants and run the full K.
+//   DEEP (BM = BN = 32): every wave runs the whole 32 x 32 tile on its own quarter of
+//        each chunk (k in [16w, 16w + 16)); the four partial tiles are summed in fixed
+//        order (wave 0 + 1 + 2 + 3) through LDS, so results are reproducible.
 //
 // MFMA 16x16x4 operand layout (one element per lane): A(i, k) with i = lane % 16,
 // k = lane / 16; B(k, j) with j = lane % 16, k = lane / 16.  Result: lane holds four
-// rows (Mfma<T>::row) of column lane % 16.
+// rows (Mfma<T>::row) of column lane % 16.  Complex product: Cr += Ar Br - Ai Bi,
+// Ci += Ar Bi + Ai Br (A already conjugated when staged, for A_CONJ).
 // ---------------------------------------------------------------------------------
-template <typename T, int FLAGS>
+template <typename T, int FLAGS, bool DEEP>
+struct GemmCfg {
+  static constexpr int KC = DEEP ? 64 : 32;  // K chunk staged per step
+  static constexpr int BM = DEEP ? 32 : 64;
+  static constexpr int BN = DEEP ? 32 : 64;
+  static constexpr int NA = BM * KC / 256;  // A elements staged per thread per chunk
+  static constexpr int NB = KC * BN / 256;
+  // K-contiguous A (row-major, row table, mixed): consecutive threads walk k
+  static constexpr bool A_KC = !(FLAGS & G_A_T);
+  static constexpr bool B_KC = (FLAGS & G_B_T) != 0;
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD b % 8); give
+// each XCD a contiguous run of the tile list, so tiles of one output sector (which share
+// operand panels) meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+template <typename T, int FLAGS, bool DEEP>
 __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ segs,
                                                    const GemmProb* __restrict__ probs,
                                                    const GemmTile* __restrict__ tiles,
-                                                   int32_t ntiles,
                                                    const int64_t* __restrict__ rows,
+                                                   const MixSrc* __restrict__ asrc,
                                                    const T* __restrict__ A,
                                                    const T* __restrict__ B,
-                                                   T* __restrict__ C) {
+                                                   T* __restrict__ C,
+                                                   T* __restrict__ part) {
+  typedef GemmCfg<T, FLAGS, DEEP> G;
   typedef typename Mfma<T>::acc_t acc_t;
-  const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= ntiles) return;
-  const GemmTile tile = tiles[t];
+  constexpr int BM = G::BM, BN = G::BN, NA = G::NA, NB = G::NB, KC = G::KC;
+  // staging planes sA[2][KC][BM + 1], sB[2][KC][BN + 1]; DEEP reuses the space for the
+  // cross-wave reduction red[3][32][64] after the K loop
+  constexpr int SA = 2 * KC * (BM + 1), SB = 2 * KC * (BN + 1), SR = DEEP ? 3 * 32 * 64 : 0;
+  __shared__ T smem[(SA + SB) > SR ? (SA + SB) : SR];
+  T (*sA)[KC][BM + 1] = reinterpret_cast<T (*)[KC][BM + 1]>(smem);
+  T (*sB)[KC][BN + 1] = reinterpret_cast<T (*)[KC][BN + 1]>(smem + SA);
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const GemmTile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const GemmProb P = probs[tile.prob];
-  const int i0 = tile.tm * TILE_M;
-  const int j0 = tile.tn * TILE_N;
-  const int li = lane & 15;
-  const int lk = lane >> 4;
+  const int i0 = tile.tm * BM, j0 = tile.tn * BN;
+  // K-split (DEEP): in every segment this workgroup takes chunks ks, ks + nks, ...
+  const int kfirst = DEEP ? tile.ks * KC : 0;
+  const int kstep = DEEP ? P.nks * KC : KC;
+  constexpr int KW = KC / 4;  // DEEP: k range of one wave inside a chunk
+
+  // element e = tid + 256 q of a chunk -> (row, k) of A and (k, col) of B
+  auto a_rk = [&](int q, int& r, int& k) {
+    const int e = tid + 256 * q;
+    if (G::A_KC) { r = e / KC; k = e % KC; } else { k = e / BM; r = e % BM; }
+  };
+  auto b_kc = [&](int q, int& k, int& c) {
+    const int e = tid + 256 * q;
+    if (G::B_KC) { c = e / KC; k = e % KC; } else { k = e / BN; c = e % BN; }
+  };
+  int64_t arow[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    int r, k;
+    a_rk(q, r, k);
+    arow[q] = 0;
+    if ((FLAGS & G_A_ROWMAP) && i0 + r < P.M) arow[q] = rows[P.rowmap + i0 + r];
+  }
+
+  Cplx<T> ra[NA], rb[NB];
+  auto load_chunk = [&](const GemmSeg& S, int k0) {
+    const int kc = min(KC, S.k - k0);
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      int r, k;
+      a_rk(q, r, k);
+      const int i = i0 + r;
+      Cplx<T> v{0, 0};
+      if (i < P.M && k < kc) {
+        const int kk = k0 + k;
+        if (FLAGS & G_A_MIX) {
+          for (int s = 0; s < S.nsrc; ++s) {
+            const MixSrc src = asrc[S.a_off + s];
+            const Cplx<T> x = ldc(A, src.off + (int64_t)i * src.ld + kk);
+            const T cr = (T)src.re, ci = (T)src.im;
+            v.re += cr * x.re - ci * x.im;
+            v.im += cr * x.im + ci * x.re;
+          }
+        } else if (FLAGS & G_A_ROWMAP) {
+          v = ldc(A, arow[q] + S.a_off + kk);
+        } else if (FLAGS & G_A_T) {
+          v = ldc(A, S.a_off + (int64_t)kk * S.lda + i);
+        } else {
+          v = ldc(A, S.a_off + (int64_t)i * S.lda + kk);
+        }
+        if (FLAGS & G_A_CONJ) v.im = -v.im;
+      }
+      ra[q] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      int k, c;
+      b_kc(q, k, c);
+      const int j = j0 + c;
+      Cplx<T> v{0, 0};
+      if (j < P.N && k < kc) {
+        const int kk = k0 + k;
+        v = (FLAGS & G_B_T) ? ldc(B, S.b_off + (int64_t)j * S.ldb + kk)
+                            : ldc(B, S.b_off + (int64_t)kk * S.ldb + j);
+      }
+      rb[q] = v;
+    }
+  };
 
   acc_t cre[2][2], cim[2][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      cre[a][b] = acc_t{0, 0, 0, 0};
-      cim[a][b] = acc_t{0, 0, 0, 0};
+    for (int y = 0; y < 2; ++y) {
+      cre[x][y] = acc_t{0, 0, 0, 0};
+      cim[x][y] = acc_t{0, 0, 0, 0};
     }
+  // sub-tile of this wave
+  const int wr = DEEP ? 0 : (wave & 1) * 32;
+  const int wc = DEEP ? 0 : (wave >> 1) * 32;
 
-  const int ia0 = i0 + li, ia1 = i0 + 16 + li;
-  const int jb0 = j0 + li, jb1 = j0 + 16 + li;
-  const bool va0 = ia0 < P.M, va1 = ia1 < P.M;
-  const bool vb0 = jb0 < P.N, vb1 = jb1 < P.N;
-  int64_t arow0 = 0, arow1 = 0;
-  if (FLAGS & G_A_ROWMAP) {
-    if (va0) arow0 = rows[P.rowmap + ia0];
-    if (va1) arow1 = rows[P.rowmap + ia1];
+  // first (segment, chunk) of this workgroup
+  int sg = 0, k0 = kfirst;
+  GemmSeg S;
+  while (sg < P.nseg) {
+    S = segs[P.seg0 + sg];
+    if (k0 < S.k) break;
+    ++sg;
+    k0 = kfirst;
   }
-
-  for (int sgi = 0; sgi < P.nseg; ++sgi) {
-    const GemmSeg S = segs[P.seg0 + sgi];
-    auto addrA = [&](int i, int64_t arow, int k) -> int64_t {
-      if (FLAGS & G_A_ROWMAP) return arow + S.a_off + k;
-      if (FLAGS & G_A_T) return S.a_off + (int64_t)k * S.lda + i;
-      return S.a_off + (int64_t)i * S.lda + k;
-    };
-    auto addrB = [&](int k, int j) -> int64_t {
-      if (FLAGS & G_B_T) return S.b_off + (int64_t)j * S.ldb + k;
-      return S.b_off + (int64_t)k * S.ldb + j;
-    };
-    auto load = [&](int k0, Cplx<T>& a0, Cplx<T>& a1, Cplx<T>& b0, Cplx<T>& b1) {
-      const int k = k0 + lk;
-      const bool vk = k < S.k;
-      a0 = (vk && va0) ? ldc(A, addrA(ia0, arow0, k)) : Cplx<T>{0, 0};
-      a1 = (vk && va1) ? ldc(A, addrA(ia1, arow1, k)) : Cplx<T>{0, 0};
-      b0 = (vk && vb0) ? ldc(B, addrB(k, jb0)) : Cplx<T>{0, 0};
-      b1 = (vk && vb1) ? ldc(B, addrB(k, jb1)) : Cplx<T>{0, 0};
-    };
-    Cplx<T> a0, a1, b0, b1;
-    load(0, a0, a1, b0, b1);
-    for (int k0 = 0; k0 < S.k; k0 += 4) {
-      Cplx<T> na0, na1, nb0, nb1;
-      if (k0 + 4 < S.k) load(k0 + 4, na0, na1, nb0, nb1);
-      const T ai0 = (FLAGS & G_A_CONJ) ? -a0.im : a0.im;
-      const T ai1 = (FLAGS & G_A_CONJ) ? -a1.im : a1.im;
-      const Cplx<T> av[2] = {{a0.re, ai0}, {a1.re, ai1}};
-      const Cplx<T> bv[2] = {b0, b1};
+  if (sg < P.nseg) load_chunk(S, k0);
+  while (sg < P.nseg) {
+    const int kc = min(KC, S.k - k0);
+    __syncthreads();  // previous chunk fully consumed
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+    for (int q = 0; q < NA; ++q) {
+      int r, k;
+      a_rk(q, r, k);
+      sA[0][k][r] = ra[q].re;
+      sA[1][k][r] = ra[q].im;
+    }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          cre[a][b] = Mfma<T>::mac(av[a].re, bv[b].re, cre[a][b]);
-          cim[a][b] = Mfma<T>::mac(av[a].re, bv[b].im, cim[a][b]);
+    for (int q = 0; q < NB; ++q) {
+      int k, c;
+      b_kc(q, k, c);
+      sB[0][k][c] = rb[q].re;
+      sB[1][k][c] = rb[q].im;
+    }
+    __syncthreads();
+    // advance and prefetch the next chunk while this one is multiplied
+    k0 += kstep;
+    while (k0 >= S.k) {
+      if (++sg >= P.nseg) break;
+      S = segs[P.seg0 + sg];
+      k0 = kfirst;
+    }
+    if (sg < P.nseg) load_chunk(S, k0);
+    const int kbeg = DEEP ? wave * KW : 0;
+    const int kend = DEEP ? min(kbeg + KW, kc) : kc;
+    for (int kb = kbeg; kb < kend; kb += 4) {
+      const int k = kb + lk;
+      T are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        are[x] = sA[0][k][wr + x * 16 + li];
+        aim[x] = sA[1][k][wr + x * 16 + li];
+      }
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        bre[y] = sB[0][k][wc + y * 16 + li];
+        bim[y] = sB[1][k][wc + y * 16 + li];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          cre[x][y] = Mfma<T>::mac(are[x], bre[y], cre[x][y]);
+          cim[x][y] = Mfma<T>::mac(are[x], bim[y], cim[x][y]);
         }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          cre[a][b] = Mfma<T>::mac(-av[a].im, bv[b].im, cre[a][b]);
-          cim[a][b] = Mfma<T>::mac(av[a].im, bv[b].re, cim[a][b]);
+        for (int y = 0; y < 2; ++y) {
+          cre[x][y] = Mfma<T>::mac(-aim[x], bim[y], cre[x][y]);
+          cim[x][y] = Mfma<T>::mac(aim[x], bre[y], cim[x][y]);
         }
-      a0 = na0;
-      a1 = na1;
-      b0 = nb0;
-      b1 = nb1;
     }
   }
 
+  if constexpr (DEEP) {
+    // fixed-order reduction of the four partial tiles
+    T (*red)[32][64] = reinterpret_cast<T (*)[32][64]>(smem);
+    __syncthreads();  // staging buffers are no longer read
+    if (wave > 0) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            red[wave - 1][((x * 2 + y) * 4 + r) * 2][lane] = cre[x][y][r];
+            red[wave - 1][((x * 2 + y) * 4 + r) * 2 + 1][lane] = cim[x][y][r];
+          }
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = ((x * 2 + y) * 4 + r) * 2;
+          cre[x][y][r] = ((cre[x][y][r] + red[0][e][lane]) + red[1][e][lane]) + red[2][e][lane];
+          cim[x][y][r] = ((cim[x][y][r] + red[0][e + 1][lane]) + red[1][e + 1][lane]) + red[2][e + 1][lane];
+        }
+    if (P.nks > 1) {
+      // partial tile of this K-split, summed later by gemm_split_reduce_kernel
+      const int tiles_n = (P.N + BN - 1) / BN;
+      T* dst = part + 2 * ((int64_t)P.slot0 + ((int64_t)tile.tm * tiles_n + tile.tn) * P.nks + tile.ks) * 1024;
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            const int rr = x * 16 + Mfma<T>::row(lk, r), cc = y * 16 + li;
+            stc(dst, rr * 32 + cc, cre[x][y][r], cim[x][y][r]);
+          }
+      return;
+    }
+  }
+  // store this wave's 32 x 32 sub-tile
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = i0 + a * 16 + Mfma<T>::row(lk, r);
+      const int i = i0 + wr + x * 16 + Mfma<T>::row(lk, r);
       if (i >= P.M) continue;
-      const int64_t rb = (FLAGS & G_C_ROWMAP) ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
+      const int64_t rbase = (FLAGS & G_C_ROWMAP) ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int j = j0 + b * 16 + li;
-        if (j < P.N) stc(C, rb + j, cre[a][b][r], cim[a][b][r]);
+      for (int y = 0; y < 2; ++y) {
+        const int j = j0 + wc + y * 16 + li;
+        if (j < P.N) stc(C, rbase + j, cre[x][y][r], cim[x][y][r]);
       }
     }
   }
 }
 
-template <typename T>
-hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, hipStream_t s) {
-  const int32_t nt = (int32_t)st.tiles.size();
-  if (nt == 0) return hipSuccess;
-  dim3 grid((nt + 3) / 4), block(256);
-#define MRD_GEMM_CASE(F)                                                                \
-  case F:                                                                               \
-    hipLaunchKernelGGL((gemm_kernel<T, F>), grid, block, 0, s, st.d_segs, st.d_probs,   \
-                       st.d_tiles, nt, st.d_rows, A, B, C);                             \
-    break;
-  switch (st.flags) {
-    MRD_GEMM_CASE(0)
-    MRD_GEMM_CASE(G_B_T | G_C_ROWMAP)
-    MRD_GEMM_CASE(G_A_T | G_A_CONJ)
-    MRD_GEMM_CASE(G_A_ROWMAP | G_B_T)
-    MRD_GEMM_CASE(G_A_CONJ)
-    default:
-      return hipErrorInvalidValue;
+// Sums the K-split partial tiles of one output tile in split order and stores it.
+template <typename T, int FLAGS>
+__global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const GemmProb* __restrict__ probs,
+                                                                const GemmTile* __restrict__ tiles,
+                                                                const int64_t* __restrict__ rows,
+                                                                const T* __restrict__ part,
+                                                                T* __restrict__ C) {
+  const GemmTile tile = tiles[blockIdx.x];
+  const GemmProb P = probs[tile.prob];
+  const int tiles_n = (P.N + 31) / 32;
+  const int64_t base = (int64_t)P.slot0 + ((int64_t)tile.tm * tiles_n + tile.tn) * P.nks;
+  for (int e = threadIdx.x; e < 1024; e += 256) {
+    const int r = e >> 5, c = e & 31;
+    const int i = tile.tm * 32 + r, j = tile.tn * 32 + c;
+    if (i >= P.M || j >= P.N) continue;
+    T re = 0, im = 0;
+    for (int ks = 0; ks < P.nks; ++ks) {
+      const Cplx<T> v = ldc(part, (base + ks) * 1024 + e);
+      re += v.re;
+      im += v.im;
+    }
+    const int64_t rb = (FLAGS & G_C_ROWMAP) ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
+    stc(C, rb + j, re, im);
   }
-#undef MRD_GEMM_CASE
-  return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* part, hipStream_t s) {
+  const int32_t nt = (int32_t)st.tiles.size();
+  if (nt == 0) return hipSuccess;
+  if (st.nslots > 0 && !part) return hipErrorInvalidValue;
+  dim3 grid(nt), block(256);
+#define MRD_GEMM_CASE(F, D)                                                                \
+  if (st.flags == (F) && st.deep == (D)) {                                                 \
+    hipLaunchKernelGGL((gemm_kernel<T, F, D>), grid, block, 0, s, st.d_segs, st.d_probs,   \
+                       st.d_tiles, st.d_rows, st.d_asrc, A, B, C, part);                   \
+    if (D && !st.red_tiles.empty())                                                        \
+      hipLaunchKernelGGL((gemm_split_reduce_kernel<T, F>), dim3(st.red_tiles.size()),      \
+                         block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C);     \
+    return hipGetLastError();                                                              \
+  }
+  MRD_GEMM_CASE(0, false)
+  MRD_GEMM_CASE(G_A_T | G_A_CONJ, false)
+  MRD_GEMM_CASE(G_A_ROWMAP | G_B_T, false)
+  MRD_GEMM_CASE(G_A_CONJ, false)
+  MRD_GEMM_CASE(G_B_T | G_C_ROWMAP, true)
+#undef MRD_GEMM_CASE
+  return hipErrorInvalidValue;
+}
+
+int gemm_tile_m(bool deep) { return deep ? 32 : 64; }
+int gemm_tile_n(bool deep) { return deep ? 32 : 64; }
+
 template hipError_t launch_gemm<double>(const GemmStage&, const double*, const double*, double*,
-                                        hipStream_t);
-template hipError_t launch_gemm<float>(const GemmStage&, const float*, const float*, float*,
+                                        double*, hipStream_t);
+template hipError_t launch_gemm<float>(const GemmStage&, const float*, const float*, float*, float*,
                                        hipStream_t);
 
 // ---------------------------------------------------------------------------------

@@ -1,6 +1,7 @@
 // Host planner: bond / MPO validation and the canonical layouts.
 #include "plan.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <sstream>
 
@@ -143,10 +144,27 @@ EnvRLayout envr_layout(const Bond& c, const std::vector<dm_charge>& qw, int ly) 
 }
 
 void add_tiles(GemmStage& st, int32_t prob, int M, int N) {
-  const int tm = (M + TILE_M - 1) / TILE_M, tn = (N + TILE_N - 1) / TILE_N;
+  const int TM = gemm_tile_m(st.deep), TN = gemm_tile_n(st.deep);
+  const int tm = (M + TM - 1) / TM, tn = (N + TN - 1) / TN;
   if (M > 0 && N == 0) return;
+  GemmProb& P = st.probs[prob];
+  P.nks = 1;
+  P.slot0 = -1;
+  if (st.deep) {
+    // split long K over several workgroups: at least 4 chunks of 64 per split, at most 8
+    int chunks = 0;
+    for (int q = 0; q < P.nseg; ++q) chunks += (st.segs[P.seg0 + q].k + 63) / 64;
+    P.nks = std::max(1, std::min(8, chunks / 4));
+    if (P.nks > 1) {  // partial tile of (tm, tn, ks): slot0 + (tm * tiles_n + tn) * nks + ks
+      P.slot0 = (int32_t)st.nslots;
+      st.nslots += (int64_t)tm * tn * P.nks;
+    }
+  }
   for (int a = 0; a < tm; ++a)
-    for (int b = 0; b < tn; ++b) st.tiles.push_back({prob, a, b, 0});
+    for (int b = 0; b < tn; ++b) {
+      for (int ks = 0; ks < P.nks; ++ks) st.tiles.push_back({prob, a, b, ks});
+      if (P.nks > 1) st.red_tiles.push_back({prob, a, b, 0});
+    }
 }
 
 static void range_check(int64_t lo, int64_t hi, int64_t size, const char* what) {
@@ -158,10 +176,21 @@ static void range_check(int64_t lo, int64_t hi, int64_t size, const char* what) 
 }
 
 void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_size) {
+  for (const std::vector<GemmTile>* tl : {&st.tiles, &st.red_tiles})
+    for (const GemmTile& t : *tl) {
+      if (t.prob < 0 || t.prob >= (int)st.probs.size()) throw err(DM_ERR_LAYOUT, "bad tile");
+      const GemmProb& p = st.probs[t.prob];
+      if (t.ks < 0 || t.ks >= std::max(1, p.nks)) throw err(DM_ERR_LAYOUT, "bad K-split");
+      if (p.nks > 1) {
+        const int tn = (p.N + 31) / 32;
+        const int64_t slot = (int64_t)p.slot0 + ((int64_t)t.tm * tn + t.tn) * p.nks + t.ks;
+        if (!st.deep || p.slot0 < 0 || slot >= st.nslots) throw err(DM_ERR_LAYOUT, "bad partial slot");
+      }
+    }
   for (const GemmTile& t : st.tiles) {
-    if (t.prob < 0 || t.prob >= (int)st.probs.size()) throw err(DM_ERR_LAYOUT, "bad tile");
     const GemmProb& p = st.probs[t.prob];
-    if (t.tm * TILE_M >= p.M || t.tn * TILE_N >= p.N) throw err(DM_ERR_LAYOUT, "empty tile");
+    if (t.tm * gemm_tile_m(st.deep) >= p.M || t.tn * gemm_tile_n(st.deep) >= p.N)
+      throw err(DM_ERR_LAYOUT, "empty tile");
   }
   for (const GemmProb& p : st.probs) {
     if (p.M <= 0 || p.N <= 0) throw err(DM_ERR_LAYOUT, "empty problem");
@@ -173,7 +202,15 @@ void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_siz
       const GemmSeg& g = st.segs[p.seg0 + q];
       if (g.k < 0) throw err(DM_ERR_LAYOUT, "negative K");
       if (g.k == 0) continue;
-      if (arow) {
+      if (st.flags & G_A_MIX) {
+        if (g.a_off < 0 || g.nsrc < 0 || g.a_off + g.nsrc > (int64_t)st.asrc.size())
+          throw err(DM_ERR_LAYOUT, "bad mixing sources");
+        for (int q = 0; q < g.nsrc; ++q) {
+          const MixSrc& m = st.asrc[g.a_off + q];
+          range_check(m.off, m.off + (int64_t)(p.M - 1) * m.ld + g.k - 1, a_size, "A mix");
+          if (m.ld < g.k) throw err(DM_ERR_LAYOUT, "mix ld");
+        }
+      } else if (arow) {
         for (int i = 0; i < p.M; ++i) range_check(st.rows[p.rowmap + i] + g.a_off, st.rows[p.rowmap + i] + g.a_off + g.k - 1, a_size, "A");
       } else if (st.flags & G_A_T) {
         range_check(g.a_off, g.a_off + (int64_t)(g.k - 1) * g.lda + p.M - 1, a_size, "A");

@@ -101,6 +101,8 @@ struct EnvRLayout {
 };
 EnvRLayout envr_layout(const Bond& c, const std::vector<dm_charge>& qw, int ly);
 
+// Appends the output tiles of problem `prob` (already in st.probs) and sets its
+// K-split fields.
 void add_tiles(GemmStage& st, int32_t prob, int M, int N);
 
 // Host check that every access of a stage stays inside its buffers (sizes in complex
