@@ -1,5 +1,6 @@
 // C ABI: layouts, effective-Hamiltonian plans, matvec, Lanczos and environment updates.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -235,15 +236,17 @@ struct dm_heff_plan {
   void* dTin = nullptr;  // low-precision staging of theta in / out
   void* dTout = nullptr;
   // Lanczos workspace (FP64)
-  double* dV = nullptr;
+  double* dV = nullptr;       // Krylov basis, Vcap vectors of n
   int Vcap = 0;
-  double* dW = nullptr;
-  double* dPart = nullptr;
-  double* dH1 = nullptr;
-  double* dH2 = nullptr;
-  double* dScal = nullptr;
-  double* dY = nullptr;
-  double* hPinned = nullptr;  // host pinned scratch
+  double* dW = nullptr;       // H v_j
+  double* dVcur = nullptr;    // v_j (fixed address: the matvec input of every step)
+  double* dPart = nullptr;    // per-block partial sums
+  LzState* dState = nullptr;
+  LzState* hState = nullptr;  // pinned host copy
+  hipGraph_t graph = nullptr; // one Lanczos step (matvec + projections), captured once
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool use_graph = true;
   // profiling: events around the three stages of each recorded matvec
   bool profiling = false;
   std::vector<std::array<hipEvent_t, 4>> ev;
@@ -255,8 +258,12 @@ struct dm_heff_plan {
     free_stage(mix);
     for (void* p : {dL, dR, dL64, dR64, dX, dX64, dSplit, dSplit64, dTin, dTout, dZ, dZ64})
       dev_free(p);
-    for (double* p : {dV, dW, dPart, dH1, dH2, dScal, dY}) dev_free(p);
-    if (hPinned) (void)hipHostFree(hPinned);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (double* p : {dV, dW, dVcur, dPart}) dev_free(p);
+    dev_free(dState);
+    if (hState) (void)hipHostFree(hState);
   }
   int64_t n() const { return th.P.total; }
 };
@@ -431,6 +438,10 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       p->dTin = dev_alloc(p->n() * eb);
       p->dTout = dev_alloc(p->n() * eb);
     }
+    {
+      const char* g = getenv("MRDMRG_NO_GRAPH");
+      p->use_graph = !(g && g[0] == '1');
+    }
     HIPCHK(hipStreamSynchronize(s));
     *out = p.release();
   });
@@ -461,8 +472,8 @@ static hipEvent_t* prof_slot(dm_heff_plan* p) {
 
 // theta_out = H_eff theta in the plan's precision (FP64 in / out).
 static void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStream_t s,
-                     bool force64) {
-  hipEvent_t* ev = force64 ? nullptr : prof_slot(p);
+                     bool force64, const int32_t* skip = nullptr, bool capturing = false) {
+  hipEvent_t* ev = (force64 || capturing) ? nullptr : prof_slot(p);
   auto mark = [&](int i) {
     if (ev) HIPCHK(hipEventRecord(ev[i], s));
   };
@@ -481,25 +492,25 @@ static void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStr
       dP = p->dSplit64;
     }
     mark(0);
-    HIPCHK(launch_gemm<double>(p->s1, (const double*)dL, (const double*)theta, (double*)dX, nullptr, s));
+    HIPCHK(launch_gemm<double>(p->s1, (const double*)dL, (const double*)theta, (double*)dX, nullptr, s, skip));
     mark(1);
-    HIPCHK(launch_mix<double>(p->mix, (const double*)dX, (double*)dZ, s));
+    HIPCHK(launch_mix<double>(p->mix, (const double*)dX, (double*)dZ, s, skip));
     mark(2);
     HIPCHK(launch_gemm<double>(p->s4, (const double*)dZ, (const double*)dR, (double*)theta_out,
-                               (double*)dP, s));
+                               (double*)dP, s, skip));
     mark(3);
     return;
   }
-  stage_in(theta, p->dTin, p->n(), DM_FP32, s);
+  HIPCHK(launch_cast_d2f((const double*)theta, (float*)p->dTin, 2 * p->n(), s, skip));
   mark(0);
-  HIPCHK(launch_gemm<float>(p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, nullptr, s));
+  HIPCHK(launch_gemm<float>(p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, nullptr, s, skip));
   mark(1);
-  HIPCHK(launch_mix<float>(p->mix, (const float*)p->dX, (float*)p->dZ, s));
+  HIPCHK(launch_mix<float>(p->mix, (const float*)p->dX, (float*)p->dZ, s, skip));
   mark(2);
   HIPCHK(launch_gemm<float>(p->s4, (const float*)p->dZ, (const float*)p->dR, (float*)p->dTout,
-                            (float*)p->dSplit, s));
+                            (float*)p->dSplit, s, skip));
   mark(3);
-  stage_out(p->dTout, theta_out, p->n(), DM_FP32, s);
+  HIPCHK(launch_cast_f2d((const float*)p->dTout, (double*)theta_out, 2 * p->n(), s, skip));
 }
 
 extern "C" int dm_heff_profile(dm_heff_plan* p, int32_t enable) {
@@ -534,185 +545,85 @@ extern "C" int heff_apply(dm_heff_plan* p, const void* theta, void* theta_out, d
   });
 }
 
-// ---- lowest eigenpair of a symmetric tridiagonal matrix (bisection + inverse iteration)
-static int sturm_below(const std::vector<double>& al, const std::vector<double>& be, double x) {
-  int cnt = 0;
-  double d = 1.0;
-  for (size_t i = 0; i < al.size(); ++i) {
-    const double b2 = i ? be[i - 1] * be[i - 1] : 0.0;
-    d = (al[i] - x) - (i ? b2 / d : 0.0);
-    if (d == 0.0) d = -1e-300;
-    if (d < 0) ++cnt;
-  }
-  return cnt;
-}
-
-static void tridiag_lowest(const std::vector<double>& al, const std::vector<double>& be,
-                           double* e_out, std::vector<double>& y) {
-  const int k = (int)al.size();
-  y.assign(k, 0.0);
-  if (k == 1) {
-    *e_out = al[0];
-    y[0] = 1.0;
-    return;
-  }
-  double lo = al[0], hi = al[0];
-  for (int i = 0; i < k; ++i) {
-    const double r = (i ? std::fabs(be[i - 1]) : 0.0) + (i < k - 1 ? std::fabs(be[i]) : 0.0);
-    lo = std::min(lo, al[i] - r);
-    hi = std::max(hi, al[i] + r);
-  }
-  const double scale = std::max(std::fabs(lo), std::fabs(hi));
-  for (int it = 0; it < 2000 && hi - lo > 2e-16 * scale; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    if (sturm_below(al, be, mid) >= 1)
-      hi = mid;
-    else
-      lo = mid;
-  }
-  const double lam = 0.5 * (lo + hi);
-  *e_out = lam;
-  // inverse iteration: (T - lam I) y = y_prev, Gaussian elimination with partial pivoting
-  std::vector<double> v(k, 1.0 / std::sqrt((double)k));
-  for (int it = 0; it < 4; ++it) {
-    std::vector<double> dd(k), du(k, 0.0), du2(k, 0.0), dl(k, 0.0), b = v;
-    for (int i = 0; i < k; ++i) dd[i] = al[i] - lam;
-    for (int i = 0; i < k - 1; ++i) {
-      du[i] = be[i];
-      dl[i] = be[i];
-    }
-    std::vector<int> piv(k, 0);
-    for (int i = 0; i < k - 1; ++i) {
-      if (std::fabs(dd[i]) >= std::fabs(dl[i])) {
-        if (dd[i] == 0.0) dd[i] = 1e-300 * scale + 1e-300;
-        const double f = dl[i] / dd[i];
-        dd[i + 1] -= f * du[i];
-        b[i + 1] -= f * b[i];
-        if (i < k - 2) du2[i] = 0.0;
-      } else {
-        const double f = dd[i] / dl[i];
-        dd[i] = dl[i];
-        const double t = dd[i + 1];
-        dd[i + 1] = du[i] - f * t;
-        if (i < k - 2) {
-          du2[i] = du[i + 1];
-          du[i + 1] = -f * du2[i];
-        }
-        du[i] = t;
-        std::swap(b[i], b[i + 1]);
-        b[i + 1] -= f * b[i];
-      }
-    }
-    if (dd[k - 1] == 0.0) dd[k - 1] = 1e-300 * scale + 1e-300;
-    b[k - 1] /= dd[k - 1];
-    if (k > 1) b[k - 2] = (b[k - 2] - du[k - 2] * b[k - 1]) / dd[k - 2];
-    for (int i = k - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
-    double nrm = 0;
-    for (double x : b) nrm += x * x;
-    nrm = std::sqrt(nrm);
-    for (int i = 0; i < k; ++i) v[i] = b[i] / nrm;
-  }
-  y = v;
-}
-
 static void ensure_lanczos(dm_heff_plan* p, int max_iter) {
   const int64_t n = p->n();
   if (p->Vcap < max_iter + 1) {
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
     dev_free(p->dV);
     p->dV = nullptr;
-    p->dV = (double*)dev_alloc((size_t)(max_iter + 1) * n * 16);
-    p->Vcap = max_iter + 1;
     dev_free(p->dPart);
     p->dPart = nullptr;
-    const int nb = lz_nblk(n);
-    p->dPart = (double*)dev_alloc((size_t)nb * (2 * (max_iter + 1) + 1) * 8);
-    for (double** q : {&p->dH1, &p->dH2, &p->dY}) {
-      dev_free(*q);
-      *q = nullptr;
-      *q = (double*)dev_alloc((size_t)(2 * (max_iter + 1) + 2) * 8);
-    }
-    if (!p->hPinned) HIPCHK(hipHostMalloc((void**)&p->hPinned, 8 * 512, hipHostMallocDefault));
+    const int cap = std::max(max_iter + 1, 31);
+    p->dV = (double*)dev_alloc((size_t)cap * n * 16);
+    p->Vcap = cap;
+    const int nb = std::max(lz_nblk(n), lz_nblk1(n));
+    p->dPart = (double*)dev_alloc((size_t)nb * (2 * cap + 1) * 8);
   }
   if (!p->dW) p->dW = (double*)dev_alloc((size_t)n * 16);
-  if (!p->dScal) p->dScal = (double*)dev_alloc(64);
+  if (!p->dVcur) p->dVcur = (double*)dev_alloc((size_t)n * 16);
+  if (!p->dState) p->dState = (LzState*)dev_alloc(sizeof(LzState));
+  if (!p->hState) HIPCHK(hipHostMalloc((void**)&p->hState, sizeof(LzState), hipHostMallocDefault));
+  if (p->prec != DM_FP64) {
+    if (!p->dX64) p->dX64 = dev_alloc(p->xtotal * 16);
+    if (!p->dZ64) p->dZ64 = dev_alloc(p->ztotal * 16);
+    if (!p->dSplit64) p->dSplit64 = dev_alloc(p->s4.nslots * 1024 * 16);
+  }
+}
+
+// One Lanczos step: w = H v_j, projections, scalars, v_{j+1}.  Fixed arguments.
+static void lanczos_step(dm_heff_plan* p, hipStream_t s, bool capturing) {
+  const int64_t n = p->n();
+  heff_run(p, p->dVcur, p->dW, s, false, &p->dState->stop, capturing);
+  HIPCHK(lz_launch_step_tail(p->dV, n, p->dW, n, p->dState, p->dPart, p->dVcur, p->Vcap - 1, s));
 }
 
 extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double tol,
                               double* energy, int32_t* iters, dm_stream stream) {
   return guarded([&] {
     if (!p || !energy || !iters) throw DmError{DM_ERR_ARG, "null argument"};
-    if (max_iter < 1 || max_iter > 64) throw DmError{DM_ERR_ARG, "max_iter must be in 1..64"};
+    if (max_iter < 1 || max_iter > LZ_MAX) throw DmError{DM_ERR_ARG, "max_iter must be in 1..64"};
     const int64_t n = p->n();
     if (n == 0) throw DmError{DM_ERR_LAYOUT, "empty theta"};
     if (!theta_inout) throw DmError{DM_ERR_ARG, "null theta"};
     ensure_lanczos(p, max_iter);
     hipStream_t s = (hipStream_t)stream;
-    const int nb = lz_nblk(n);
-    double* V = p->dV;
-    double* w = p->dW;
-    double* hp = p->hPinned;
-    // v0 = theta / |theta|
-    HIPCHK(launch_lz_update_dots(V, n, 0, (double*)theta_inout, n, p->dH1, p->dPart, nb, s));
-    HIPCHK(launch_lz_reduce(p->dPart, nb, 1, p->dH2, s));
-    HIPCHK(hipMemcpyAsync(hp, p->dH2, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (!(hp[0] > 0) || !std::isfinite(hp[0])) throw DmError{DM_ERR_NONFINITE, "start vector has zero or non-finite norm"};
-    hp[1] = 1.0 / std::sqrt(hp[0]);
-    HIPCHK(hipMemcpyAsync(p->dScal, hp + 1, 8, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_lz_scale((const double*)theta_inout, n, p->dScal, V, s));
-    std::vector<double> al, be;
-    double tnorm = 0;
-    for (int j = 0; j < max_iter; ++j) {
-      const int nv = j + 1;
-      heff_run(p, V + 2 * (int64_t)j * n, w, s, false);
-      HIPCHK(launch_lz_dots(V, n, nv, w, n, p->dPart, nb, s));
-      HIPCHK(launch_lz_reduce(p->dPart, nb, 2 * nv, p->dH1, s));
-      HIPCHK(launch_lz_update_dots(V, n, nv, w, n, p->dH1, p->dPart, nb, s));
-      HIPCHK(launch_lz_reduce(p->dPart, nb, 2 * nv + 1, p->dH2, s));
-      HIPCHK(hipMemcpyAsync(hp, p->dH1, 16 * nv, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hp + 2 * nv, p->dH2, 8 * (2 * nv + 1), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      const double alpha = hp[2 * j];
-      double hh = 0;
-      for (int i = 0; i < 2 * nv; ++i) hh += hp[2 * nv + i] * hp[2 * nv + i];
-      const double nrm2 = hp[2 * nv + 2 * nv];
-      if (!std::isfinite(alpha) || !std::isfinite(nrm2))
-        throw DmError{DM_ERR_NONFINITE, "Lanczos produced a non-finite value"};
-      const double beta = std::sqrt(std::max(nrm2 - hh, 0.0));
-      al.push_back(alpha);
-      const double row = std::fabs(alpha) + beta + (j ? be[j - 1] : 0.0);
-      tnorm = std::max(tnorm, row);
-      if (beta <= tol * tnorm || j == max_iter - 1) break;
-      be.push_back(beta);
-      hp[4 * nv + 8] = 1.0 / beta;
-      HIPCHK(hipMemcpyAsync(p->dScal, hp + 4 * nv + 8, 8, hipMemcpyHostToDevice, s));
-      HIPCHK(launch_lz_update_scale(V, n, nv, w, n, p->dH2, p->dScal, V + 2 * (int64_t)(j + 1) * n, s));
+    HIPCHK(lz_launch_init(p->dState, max_iter, tol, s));
+    HIPCHK(lz_launch_start((const double*)theta_inout, n, p->dState, p->dPart, p->dV, p->dVcur, s));
+    const bool graph = p->use_graph && !p->profiling;
+    if (graph && !p->graph_exec) {
+      if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+      HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        lanczos_step(p, p->cap_stream, true);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(p->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(p->cap_stream, &p->graph));
+      HIPCHK(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
     }
-    const int k = (int)al.size();
-    double e = 0;
-    std::vector<double> y;
-    be.resize(k > 0 ? k - 1 : 0);
-    tridiag_lowest(al, be, &e, y);
-    HIPCHK(hipMemcpyAsync(p->dY, y.data(), 8 * k, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_lz_combine(V, n, k, n, p->dY, (double*)theta_inout, s));
+    for (int j = 0; j < max_iter; ++j) {
+      if (graph)
+        HIPCHK(hipGraphLaunch(p->graph_exec, s));
+      else
+        lanczos_step(p, s, false);
+    }
+    HIPCHK(lz_launch_finish(p->dV, n, n, p->dState, (double*)theta_inout, s));
     if (p->prec != DM_FP64) {
       // FP64 Rayleigh quotient of the Ritz vector
-      heff_run(p, theta_inout, w, s, true);
-      HIPCHK(launch_lz_dots((const double*)theta_inout, n, 1, w, n, p->dPart, nb, s));
-      HIPCHK(launch_lz_reduce(p->dPart, nb, 2, p->dH1, s));
-      HIPCHK(launch_lz_update_dots(V, n, 0, (double*)theta_inout, n, p->dH2, p->dPart, nb, s));
-      HIPCHK(launch_lz_reduce(p->dPart, nb, 1, p->dH2, s));
-      HIPCHK(hipMemcpyAsync(hp, p->dH1, 16, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hp + 2, p->dH2, 8, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      e = hp[0] / hp[2];
-    } else {
-      HIPCHK(hipStreamSynchronize(s));
+      heff_run(p, theta_inout, p->dW, s, true);
+      HIPCHK(lz_launch_rq((const double*)theta_inout, p->dW, n, p->dState, p->dPart, s));
     }
-    if (!std::isfinite(e)) throw DmError{DM_ERR_NONFINITE, "non-finite energy"};
-    *energy = e;
-    *iters = k;
+    HIPCHK(hipMemcpyAsync(p->hState, p->dState, sizeof(LzState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (p->hState->bad) throw DmError{DM_ERR_NONFINITE, "Lanczos produced a zero, NaN or Inf norm"};
+    *energy = p->hState->energy;
+    *iters = p->hState->k;
   });
 }
 

@@ -108,28 +108,42 @@ int gemm_tile_n(bool deep);
 
 // Kernel launchers (kernels.hip).  T = double or float (complex interleaved).
 // part: scratch of st.nslots * 1024 complex elements (DEEP stages with K-splits).
+// skip (may be null): the kernels return at once when *skip != 0 (a stopped Lanczos).
 template <typename T>
-hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* part, hipStream_t s);
+hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* part, hipStream_t s,
+                       const int32_t* skip = nullptr);
 template <typename T>
-hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s);
-hipError_t launch_cast_d2f(const double* in, float* out, int64_t n_real, hipStream_t s);
-hipError_t launch_cast_f2d(const float* in, double* out, int64_t n_real, hipStream_t s);
+hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s,
+                      const int32_t* skip = nullptr);
+hipError_t launch_cast_d2f(const double* in, float* out, int64_t n_real, hipStream_t s,
+                           const int32_t* skip = nullptr);
+hipError_t launch_cast_f2d(const float* in, double* out, int64_t n_real, hipStream_t s,
+                           const int32_t* skip = nullptr);
 
-// Lanczos helpers (FP64 complex vectors of n elements, Krylov basis V[j] = V + j*ld).
-hipError_t launch_lz_dots(const double* V, int64_t ld, int32_t nv, const double* w, int64_t n,
-                          double* partial, int32_t nblk, hipStream_t s);
-hipError_t launch_lz_reduce(const double* partial, int32_t nblk, int32_t nv, double* out,
-                            hipStream_t s);
-hipError_t launch_lz_update_dots(const double* V, int64_t ld, int32_t nv, double* w, int64_t n,
-                                 const double* h, double* partial, int32_t nblk, hipStream_t s);
-hipError_t launch_lz_update_scale(const double* V, int64_t ld, int32_t nv, const double* w,
-                                  int64_t n, const double* h, const double* scal, double* out,
-                                  hipStream_t s);
-hipError_t launch_lz_scale(const double* x, int64_t n, const double* scal, double* out,
-                           hipStream_t s);
-hipError_t launch_lz_combine(const double* V, int64_t ld, int32_t nv, int64_t n,
-                             const double* y, double* out, hipStream_t s);
+// Device-resident Lanczos state (lanczos.hip).  Krylov basis V[j] = V + j * ld.
+constexpr int LZ_MAX = 64;
+struct LzState {
+  double alpha[LZ_MAX + 1];
+  double beta[LZ_MAX + 1];
+  double h1[2 * (LZ_MAX + 1) + 2];  // <v_i, w>
+  double h2[2 * (LZ_MAX + 1) + 2];  // second projection, then |w1|^2
+  double y[LZ_MAX + 1];             // lowest eigenvector of T_k
+  double rq[2];                     // Rayleigh quotient numerator / denominator
+  double scal0;                     // |theta_0|^2
+  double inv_beta, tnorm, tol, energy;
+  int32_t iter, k, stop, max_iter, bad;
+};
 int lz_nblk(int64_t n);
+int lz_nblk1(int64_t n);
+hipError_t lz_launch_init(LzState* st, int32_t max_iter, double tol, hipStream_t s);
+hipError_t lz_launch_start(const double* x, int64_t n, LzState* st, double* partial, double* V,
+                           double* vcur, hipStream_t s);
+hipError_t lz_launch_step_tail(double* V, int64_t ld, double* w, int64_t n, LzState* st,
+                               double* partial, double* vcur, int32_t max_iter, hipStream_t s);
+hipError_t lz_launch_finish(const double* V, int64_t ld, int64_t n, LzState* st, double* out,
+                            hipStream_t s);
+hipError_t lz_launch_rq(const double* x, const double* w, int64_t n, LzState* st, double* partial,
+                        hipStream_t s);
 
 // Thread-local message returned by dm_last_error().
 void set_last_error(const std::string& msg);

@@ -1,5 +1,5 @@
 // HIP kernels for gfx950 (CDNA4): grouped complex block GEMMs on MFMA, sparse MPO
-// mixing, precision casts and the FP64 Lanczos vector kernels.
+// mixing and precision casts.
 //
 // Complex data is interleaved (re, im).  A complex product on real MFMA is four real
 // products: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
@@ -105,7 +105,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
                                                    const T* __restrict__ A,
                                                    const T* __restrict__ B,
                                                    T* __restrict__ C,
-                                                   T* __restrict__ part) {
+                                                   T* __restrict__ part,
+                                                   const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   typedef GemmCfg<T, FLAGS, DEEP> G;
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int BM = G::BM, BN = G::BN, NA = G::NA, NB = G::NB, KC = G::KC;
@@ -336,7 +338,9 @@ __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const GemmProb* 
                                                                 const GemmTile* __restrict__ tiles,
                                                                 const int64_t* __restrict__ rows,
                                                                 const T* __restrict__ part,
-                                                                T* __restrict__ C) {
+                                                                T* __restrict__ C,
+                                                                const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const GemmTile tile = tiles[blockIdx.x];
   const GemmProb P = probs[tile.prob];
   const int tiles_n = (P.N + 31) / 32;
@@ -357,7 +361,8 @@ __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const GemmProb* 
 }
 
 template <typename T>
-hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* part, hipStream_t s) {
+hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* part, hipStream_t s,
+                       const int32_t* skip) {
   const int32_t nt = (int32_t)st.tiles.size();
   if (nt == 0) return hipSuccess;
   if (st.nslots > 0 && !part) return hipErrorInvalidValue;
@@ -365,10 +370,10 @@ hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* par
 #define MRD_GEMM_CASE(F, D)                                                                \
   if (st.flags == (F) && st.deep == (D)) {                                                 \
     hipLaunchKernelGGL((gemm_kernel<T, F, D>), grid, block, 0, s, st.d_segs, st.d_probs,   \
-                       st.d_tiles, st.d_rows, st.d_asrc, A, B, C, part);                   \
+                       st.d_tiles, st.d_rows, st.d_asrc, A, B, C, part, skip);             \
     if (D && !st.red_tiles.empty())                                                        \
       hipLaunchKernelGGL((gemm_split_reduce_kernel<T, F>), dim3(st.red_tiles.size()),      \
-                         block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C);     \
+                         block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C, skip);\
     return hipGetLastError();                                                              \
   }
   MRD_GEMM_CASE(0, false)
@@ -384,9 +389,9 @@ int gemm_tile_m(bool deep) { return deep ? 32 : 64; }
 int gemm_tile_n(bool deep) { return deep ? 32 : 64; }
 
 template hipError_t launch_gemm<double>(const GemmStage&, const double*, const double*, double*,
-                                        double*, hipStream_t);
+                                        double*, hipStream_t, const int32_t*);
 template hipError_t launch_gemm<float>(const GemmStage&, const float*, const float*, float*, float*,
-                                       hipStream_t);
+                                       hipStream_t, const int32_t*);
 
 // ---------------------------------------------------------------------------------
 // Sparse MPO mixing: each workgroup owns one destination sub-block and sums its few
@@ -396,7 +401,9 @@ template <typename T>
 __global__ void __launch_bounds__(256) mix_kernel(const MixTask* __restrict__ tasks,
                                                   const MixSrc* __restrict__ srcs,
                                                   const T* __restrict__ src,
-                                                  T* __restrict__ dst) {
+                                                  T* __restrict__ dst,
+                                                  const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const MixTask tk = tasks[blockIdx.x];
   const int n = tk.rows * tk.cols;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
@@ -415,24 +422,30 @@ __global__ void __launch_bounds__(256) mix_kernel(const MixTask* __restrict__ ta
 }
 
 template <typename T>
-hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s) {
+hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s, const int32_t* skip) {
   if (st.tasks.empty()) return hipSuccess;
   hipLaunchKernelGGL((mix_kernel<T>), dim3((uint32_t)st.tasks.size()), dim3(256), 0, s,
-                     st.d_tasks, st.d_srcs, src, dst);
+                     st.d_tasks, st.d_srcs, src, dst, skip);
   return hipGetLastError();
 }
-template hipError_t launch_mix<double>(const MixStage&, const double*, double*, hipStream_t);
-template hipError_t launch_mix<float>(const MixStage&, const float*, float*, hipStream_t);
+template hipError_t launch_mix<double>(const MixStage&, const double*, double*, hipStream_t,
+                                       const int32_t*);
+template hipError_t launch_mix<float>(const MixStage&, const float*, float*, hipStream_t,
+                                      const int32_t*);
 
 // ---------------------------------------------------------------------------------
 // Precision casts.
 // ---------------------------------------------------------------------------------
-__global__ void cast_d2f_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+__global__ void cast_d2f_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n,
+                                const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     out[i] = (float)in[i];
 }
-__global__ void cast_f2d_kernel(const float* __restrict__ in, double* __restrict__ out, int64_t n) {
+__global__ void cast_f2d_kernel(const float* __restrict__ in, double* __restrict__ out, int64_t n,
+                                const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     out[i] = (double)in[i];
@@ -443,242 +456,16 @@ static dim3 grid_for(int64_t n) {
   if (b < 1) b = 1;
   return dim3((uint32_t)b);
 }
-hipError_t launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t s) {
+hipError_t launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t s,
+                           const int32_t* skip) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(cast_d2f_kernel, grid_for(n), dim3(256), 0, s, in, out, n);
+  hipLaunchKernelGGL(cast_d2f_kernel, grid_for(n), dim3(256), 0, s, in, out, n, skip);
   return hipGetLastError();
 }
-hipError_t launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t s) {
+hipError_t launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t s,
+                           const int32_t* skip) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(cast_f2d_kernel, grid_for(n), dim3(256), 0, s, in, out, n);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------------
-// Lanczos vector kernels, FP64 complex.  Each workgroup owns a contiguous chunk of
-// LZ_CHUNK elements; per-workgroup partial sums are reduced afterwards in a fixed
-// order, so results are bitwise reproducible run to run.
-// ---------------------------------------------------------------------------------
-constexpr int LZ_EPT = 4;
-constexpr int LZ_CHUNK = 256 * LZ_EPT;
-
-int lz_nblk(int64_t n) { return (int)((n + LZ_CHUNK - 1) / LZ_CHUNK); }
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// partial[blk * (2*nv) + 2*i + {0,1}] = sum over the chunk of conj(V_i[e]) w[e]
-__global__ void __launch_bounds__(256) lz_dots_kernel(const double* __restrict__ V, int64_t ld,
-                                                      int32_t nv, const double* __restrict__ w,
-                                                      int64_t n, double* __restrict__ partial) {
-  __shared__ double red[4][2];
-  const int64_t e0 = (int64_t)blockIdx.x * LZ_CHUNK + threadIdx.x;
-  double wr[LZ_EPT], wi[LZ_EPT];
-#pragma unroll
-  for (int q = 0; q < LZ_EPT; ++q) {
-    const int64_t e = e0 + q * 256;
-    wr[q] = e < n ? w[2 * e] : 0.0;
-    wi[q] = e < n ? w[2 * e + 1] : 0.0;
-  }
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = 0; i < nv; ++i) {
-    const double* v = V + 2 * (int64_t)i * ld;
-    double sr = 0, si = 0;
-#pragma unroll
-    for (int q = 0; q < LZ_EPT; ++q) {
-      const int64_t e = e0 + q * 256;
-      if (e < n) {
-        const double vr = v[2 * e], vi = v[2 * e + 1];
-        sr += vr * wr[q] + vi * wi[q];
-        si += vr * wi[q] - vi * wr[q];
-      }
-    }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) {
-      red[wv][0] = sr;
-      red[wv][1] = si;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      partial[(int64_t)blockIdx.x * 2 * nv + 2 * i] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
-      partial[(int64_t)blockIdx.x * 2 * nv + 2 * i + 1] = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
-    }
-    __syncthreads();
-  }
-}
-
-// out[c] = sum over blocks of partial[blk * ncomp + c], fixed pairwise order.
-__global__ void __launch_bounds__(256) lz_reduce_kernel(const double* __restrict__ partial,
-                                                        int32_t nblk, int32_t ncomp,
-                                                        double* __restrict__ out) {
-  __shared__ double sm[256];
-  const int c = blockIdx.x;
-  double s = 0;
-  for (int b = threadIdx.x; b < nblk; b += 256) s += partial[(int64_t)b * ncomp + c];
-  sm[threadIdx.x] = s;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[c] = sm[0];
-}
-
-// w[e] -= sum_i h_i V_i[e]; then partial dots conj(V_i) w_new and |w_new|^2 (slot nv).
-__global__ void __launch_bounds__(256) lz_update_dots_kernel(const double* __restrict__ V,
-                                                             int64_t ld, int32_t nv,
-                                                             double* __restrict__ w, int64_t n,
-                                                             const double* __restrict__ h,
-                                                             double* __restrict__ partial) {
-  __shared__ double red[4][2];
-  const int64_t e0 = (int64_t)blockIdx.x * LZ_CHUNK + threadIdx.x;
-  double wr[LZ_EPT], wi[LZ_EPT];
-#pragma unroll
-  for (int q = 0; q < LZ_EPT; ++q) {
-    const int64_t e = e0 + q * 256;
-    wr[q] = e < n ? w[2 * e] : 0.0;
-    wi[q] = e < n ? w[2 * e + 1] : 0.0;
-  }
-  for (int i = 0; i < nv; ++i) {
-    const double* v = V + 2 * (int64_t)i * ld;
-    const double hr = h[2 * i], hi = h[2 * i + 1];
-#pragma unroll
-    for (int q = 0; q < LZ_EPT; ++q) {
-      const int64_t e = e0 + q * 256;
-      if (e < n) {
-        const double vr = v[2 * e], vi = v[2 * e + 1];
-        wr[q] -= hr * vr - hi * vi;
-        wi[q] -= hr * vi + hi * vr;
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < LZ_EPT; ++q) {
-    const int64_t e = e0 + q * 256;
-    if (e < n) {
-      w[2 * e] = wr[q];
-      w[2 * e + 1] = wi[q];
-    }
-  }
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ncomp = 2 * nv + 1;
-  for (int i = 0; i <= nv; ++i) {
-    double sr = 0, si = 0;
-    if (i < nv) {
-      const double* v = V + 2 * (int64_t)i * ld;
-#pragma unroll
-      for (int q = 0; q < LZ_EPT; ++q) {
-        const int64_t e = e0 + q * 256;
-        if (e < n) {
-          const double vr = v[2 * e], vi = v[2 * e + 1];
-          sr += vr * wr[q] + vi * wi[q];
-          si += vr * wi[q] - vi * wr[q];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < LZ_EPT; ++q) sr += wr[q] * wr[q] + wi[q] * wi[q];
-    }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) {
-      red[wv][0] = sr;
-      red[wv][1] = si;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      partial[(int64_t)blockIdx.x * ncomp + 2 * i] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
-      if (i < nv)
-        partial[(int64_t)blockIdx.x * ncomp + 2 * i + 1] =
-            (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
-    }
-    __syncthreads();
-  }
-}
-
-// out[e] = (w[e] - sum_i h_i V_i[e]) * scal[0]
-__global__ void __launch_bounds__(256) lz_update_scale_kernel(const double* __restrict__ V,
-                                                              int64_t ld, int32_t nv,
-                                                              const double* __restrict__ w,
-                                                              int64_t n,
-                                                              const double* __restrict__ h,
-                                                              const double* __restrict__ scal,
-                                                              double* __restrict__ out) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  double wr = w[2 * e], wi = w[2 * e + 1];
-  for (int i = 0; i < nv; ++i) {
-    const double* v = V + 2 * (int64_t)i * ld;
-    const double hr = h[2 * i], hi = h[2 * i + 1];
-    const double vr = v[2 * e], vi = v[2 * e + 1];
-    wr -= hr * vr - hi * vi;
-    wi -= hr * vi + hi * vr;
-  }
-  const double s = scal[0];
-  out[2 * e] = wr * s;
-  out[2 * e + 1] = wi * s;
-}
-
-__global__ void lz_scale_kernel(const double* __restrict__ x, int64_t n,
-                                const double* __restrict__ scal, double* __restrict__ out) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const double s = scal[0];
-  out[2 * e] = x[2 * e] * s;
-  out[2 * e + 1] = x[2 * e + 1] * s;
-}
-
-// out[e] = sum_i y_i V_i[e] (real coefficients)
-__global__ void lz_combine_kernel(const double* __restrict__ V, int64_t ld, int32_t nv, int64_t n,
-                                  const double* __restrict__ y, double* __restrict__ out) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  double r = 0, im = 0;
-  for (int i = 0; i < nv; ++i) {
-    const double* v = V + 2 * (int64_t)i * ld;
-    r += y[i] * v[2 * e];
-    im += y[i] * v[2 * e + 1];
-  }
-  out[2 * e] = r;
-  out[2 * e + 1] = im;
-}
-
-hipError_t launch_lz_dots(const double* V, int64_t ld, int32_t nv, const double* w, int64_t n,
-                          double* partial, int32_t nblk, hipStream_t s) {
-  hipLaunchKernelGGL(lz_dots_kernel, dim3(nblk), dim3(256), 0, s, V, ld, nv, w, n, partial);
-  return hipGetLastError();
-}
-hipError_t launch_lz_reduce(const double* partial, int32_t nblk, int32_t ncomp, double* out,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(ncomp), dim3(256), 0, s, partial, nblk, ncomp, out);
-  return hipGetLastError();
-}
-hipError_t launch_lz_update_dots(const double* V, int64_t ld, int32_t nv, double* w, int64_t n,
-                                 const double* h, double* partial, int32_t nblk, hipStream_t s) {
-  hipLaunchKernelGGL(lz_update_dots_kernel, dim3(nblk), dim3(256), 0, s, V, ld, nv, w, n, h,
-                     partial);
-  return hipGetLastError();
-}
-hipError_t launch_lz_update_scale(const double* V, int64_t ld, int32_t nv, const double* w,
-                                  int64_t n, const double* h, const double* scal, double* out,
-                                  hipStream_t s) {
-  hipLaunchKernelGGL(lz_update_scale_kernel, grid_for(n).x < 1 ? dim3(1) : dim3((uint32_t)((n + 255) / 256)),
-                     dim3(256), 0, s, V, ld, nv, w, n, h, scal, out);
-  return hipGetLastError();
-}
-hipError_t launch_lz_scale(const double* x, int64_t n, const double* scal, double* out,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(lz_scale_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, x, n,
-                     scal, out);
-  return hipGetLastError();
-}
-hipError_t launch_lz_combine(const double* V, int64_t ld, int32_t nv, int64_t n, const double* y,
-                             double* out, hipStream_t s) {
-  hipLaunchKernelGGL(lz_combine_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, V, ld,
-                     nv, n, y, out);
+  hipLaunchKernelGGL(cast_f2d_kernel, grid_for(n), dim3(256), 0, s, in, out, n, skip);
   return hipGetLastError();
 }
 

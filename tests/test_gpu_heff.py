@@ -106,3 +106,44 @@ def test_env_updates_parity(name, prec, tol):
     den = max(np.abs(v).max() for v in ref.values())
     assert set(ref) <= set(got)
     assert num / den < tol
+
+
+def test_lanczos_graph_replays_equal_eager():
+    """Each Lanczos step is one HIP graph replay; replays (several calls, with eager work
+    and synchronisation in between) must give exactly the eager result."""
+    import os
+    wl, L, W1, W2, R, th, keys, mpo = problem("ly6_chi200")
+    say("lanczos graph vs eager")
+    g = WindowGPU(wl, L, R, mpo)
+    os.environ["MRDMRG_NO_GRAPH"] = "1"
+    try:
+        eager = g.plan(pk.DM_FP64)
+    finally:
+        os.environ.pop("MRDMRG_NO_GRAPH")
+    graphed = g.plan(pk.DM_FP64)
+    x0 = to_dev(g.pack_theta(th))
+    xe = x0.clone()
+    ee, ke = pk.lanczos_ground(eager, xe, 30, 1e-14)
+    for rep in range(3):
+        xg = x0.clone()
+        eg, kg = pk.lanczos_ground(graphed, xg, 30, 1e-14)
+        y = torch.empty_like(x0)
+        pk.heff_apply(graphed, x0, y)          # eager work between replays
+        torch.cuda.synchronize()
+        assert kg == ke and eg == ee, (rep, eg, ee)
+        assert torch.equal(xg, xe)
+
+
+def test_lanczos_breakdown_on_exact_eigenvector():
+    """A start vector in a one-dimensional invariant subspace stops after one step."""
+    wl, L, W1, W2, R, th, keys, mpo = problem("ly3_chi16")
+    g = WindowGPU(wl, L, R, mpo)
+    plan = g.plan(pk.DM_FP64)
+    mv = lambda v: bs.flatten(bs.heff_apply(L, W1, W2, R, bs.unflatten(v, keys)), keys)
+    dim = sum(m * n for _, (m, n) in keys)
+    H = np.array([mv(np.eye(dim)[i]) for i in range(dim)]).T
+    lam, vec = np.linalg.eigh((H + H.conj().T) / 2)
+    x = to_dev(g.pack_theta(bs.unflatten(vec[:, 0].copy(), keys)))
+    e, k = pk.lanczos_ground(plan, x, 30, 1e-10)
+    assert k == 1
+    assert abs(e - lam[0]) < 1e-10 * max(1, abs(lam[0]))
