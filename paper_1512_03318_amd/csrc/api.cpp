@@ -1,6 +1,9 @@
 // C ABI: layouts, effective-Hamiltonian plans, matvec, Lanczos and environment updates.
 #include <algorithm>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -40,60 +43,124 @@ int guarded(F&& f) {
   }
 }
 
-void* dev_alloc(size_t bytes) {
-  if (bytes == 0) return nullptr;
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    throw DmError{DM_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+// Caching device allocator for plan buffers.  A DMRG sweep creates and destroys one
+// plan per bond with similar sizes; reusing freed blocks avoids hipMalloc / hipFree
+// (each of which can cost milliseconds) on every bond.  Blocks are rounded up to 1/8 of
+// their power of two, kept per device, and released with hipFree beyond 24 GiB cached.
+// Callers guarantee that no kernel still uses a block when it is returned.
+class DevicePool {
+ public:
+  void* get(size_t bytes) {
+    if (bytes == 0) return nullptr;
+    const size_t r = round(bytes);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+      std::lock_guard<std::mutex> g(m_);
+      auto& fl = free_[dev];
+      auto it = fl.lower_bound(r);
+      if (it != fl.end() && it->first <= r + r / 4) {
+        void* p = it->second;
+        cached_ -= it->first;
+        fl.erase(it);
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, r) != hipSuccess) {
+      (void)hipGetLastError();
+      trim(0);
+      if (hipMalloc(&p, r) != hipSuccess) {
+        (void)hipGetLastError();
+        throw DmError{DM_ERR_ALLOC, "hipMalloc of " + std::to_string(r) + " bytes failed"};
+      }
+    }
+    std::lock_guard<std::mutex> g(m_);
+    size_[p] = {r, dev};
+    return p;
   }
-  return p;
+  void put(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(m_);
+    auto it = size_.find(p);
+    if (it == size_.end()) return;
+    free_[it->second.second].emplace(it->second.first, p);
+    cached_ += it->second.first;
+    if (cached_ > kMaxCached) trim_locked(kMaxCached);
+  }
+
+ private:
+  static constexpr size_t kMaxCached = size_t(24) << 30;
+  static size_t round(size_t b) {
+    if (b <= (size_t(1) << 20)) return (b + 4095) & ~size_t(4095);
+    size_t top = size_t(1) << (63 - __builtin_clzll(b));
+    const size_t step = top / 8;
+    return (b + step - 1) / step * step;
+  }
+  void trim(size_t limit) {
+    std::lock_guard<std::mutex> g(m_);
+    trim_locked(limit);
+  }
+  void trim_locked(size_t limit) {
+    for (auto& kv : free_) {
+      auto& fl = kv.second;
+      while (cached_ > limit && !fl.empty()) {
+        auto last = std::prev(fl.end());
+        (void)hipFree(last->second);
+        size_.erase(last->second);
+        cached_ -= last->first;
+        fl.erase(last);
+      }
+    }
+  }
+  std::mutex m_;
+  std::map<int, std::multimap<size_t, void*>> free_;
+  std::unordered_map<void*, std::pair<size_t, int>> size_;
+  size_t cached_ = 0;
+};
+
+DevicePool& pool() {
+  static DevicePool* p = new DevicePool();  // never destroyed: outlives static teardown
+  return *p;
 }
 
-void dev_free(void* p) {
-  if (p) (void)hipFree(p);
-}
+void* dev_alloc(size_t bytes) { return pool().get(bytes); }
+void dev_free(void* p) { pool().put(p); }
 
-template <typename T>
-T* upload(const std::vector<T>& v) {
-  if (v.empty()) return nullptr;
-  T* d = (T*)dev_alloc(v.size() * sizeof(T));
-  HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-  return d;
-}
-
-void upload_stage(GemmStage& st) {
-  st.d_segs = upload(st.segs);
-  st.d_probs = upload(st.probs);
-  st.d_tiles = upload(st.tiles);
-  st.d_rows = upload(st.rows);
-  st.d_asrc = upload(st.asrc);
-  st.d_red_tiles = upload(st.red_tiles);
-}
-void free_stage(GemmStage& st) {
-  dev_free(st.d_segs);
-  dev_free(st.d_probs);
-  dev_free(st.d_tiles);
-  dev_free(st.d_rows);
-  dev_free(st.d_asrc);
-  dev_free(st.d_red_tiles);
-  st.d_red_tiles = nullptr;
-  st.d_segs = nullptr;
-  st.d_probs = nullptr;
-  st.d_tiles = nullptr;
-  st.d_rows = nullptr;
-  st.d_asrc = nullptr;
-}
-void upload_stage(MixStage& st) {
-  st.d_tasks = upload(st.tasks);
-  st.d_srcs = upload(st.srcs);
-}
-void free_stage(MixStage& st) {
-  dev_free(st.d_tasks);
-  dev_free(st.d_srcs);
-  st.d_tasks = nullptr;
-  st.d_srcs = nullptr;
-}
+// All task tables of one or more stages in one device block, uploaded with one copy.
+struct TableUpload {
+  std::vector<char> host;
+  std::vector<std::pair<size_t, void**>> fix;  // offset -> device pointer to patch
+  template <typename T>
+  void add(const std::vector<T>& v, T** dst) {
+    *dst = nullptr;
+    if (v.empty()) return;
+    const size_t off = (host.size() + 255) & ~size_t(255);
+    host.resize(off + v.size() * sizeof(T));
+    std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+    fix.emplace_back(off, (void**)dst);
+  }
+  void add(GemmStage& st) {
+    add(st.segs, &st.d_segs);
+    add(st.probs, &st.d_probs);
+    add(st.tiles, &st.d_tiles);
+    add(st.rows, &st.d_rows);
+    add(st.asrc, &st.d_asrc);
+    add(st.red_tiles, &st.d_red_tiles);
+  }
+  void add(MixStage& st) {
+    add(st.tasks, &st.d_tasks);
+    add(st.srcs, &st.d_srcs);
+  }
+  // Synchronous copy into a pool block; returns the block (free it with dev_free).
+  void* commit() {
+    if (host.empty()) return nullptr;
+    char* d = (char*)dev_alloc(host.size());
+    HIPCHK(hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice));
+    for (auto& f : fix) *f.second = d + f.first;
+    return d;
+  }
+};
 
 size_t elem_bytes(int prec) { return prec == DM_FP64 ? 16 : 8; }
 
@@ -218,6 +285,8 @@ struct dm_heff_plan {
   int64_t xtotal = 0;
   GemmStage s1, s4;
   MixStage mix;
+  void* dTables = nullptr;      // all task tables (one pool block)
+  hipEvent_t done = nullptr;    // recorded after every use; waited on before release
   double mix_flops = 0;
   std::vector<int64_t> zoff;  // per c': Z panel offset (rows zrows[c'], cols R.P.cols[c'])
   std::vector<int> zrows;
@@ -252,10 +321,13 @@ struct dm_heff_plan {
   std::vector<std::array<hipEvent_t, 4>> ev;
   size_t ev_used = 0;
   ~dm_heff_plan() {
+    if (done) {
+      (void)hipEventSynchronize(done);  // no kernel of this plan may still run
+      (void)hipEventDestroy(done);
+    }
     for (auto& e : ev)
       for (hipEvent_t x : e) (void)hipEventDestroy(x);
-    for (GemmStage* st : {&s1, &s4}) free_stage(*st);
-    free_stage(mix);
+    dev_free(dTables);
     for (void* p : {dL, dR, dL64, dR64, dX, dX64, dSplit, dSplit64, dTin, dTout, dZ, dZ64})
       dev_free(p);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -419,8 +491,14 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     validate(p->s1, p->L.P.total, p->n(), p->xtotal);
     validate(p->mix, p->xtotal, p->ztotal);
     validate(p->s4, p->ztotal, p->R.P.total, p->n());
-    for (GemmStage* st : {&p->s1, &p->s4}) upload_stage(*st);
-    upload_stage(p->mix);
+    {
+      TableUpload up;
+      up.add(p->s1);
+      up.add(p->s4);
+      up.add(p->mix);
+      p->dTables = up.commit();
+    }
+    HIPCHK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
     const size_t eb = elem_bytes(prec);
     p->dL = dev_alloc(p->L.P.total * eb);
     p->dR = dev_alloc(p->R.P.total * eb);
@@ -439,9 +517,13 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       p->dTout = dev_alloc(p->n() * eb);
     }
     {
-      const char* g = getenv("MRDMRG_NO_GRAPH");
-      p->use_graph = !(g && g[0] == '1');
+      // One Lanczos step per HIP graph replay is available but off by default: on
+      // gfx950 at these sizes the step is GPU-bound and replays measured no faster than
+      // stream launches, while capturing costs milliseconds per plan.
+      const char* g = getenv("MRDMRG_GRAPH");
+      p->use_graph = g && g[0] == '1';
     }
+    HIPCHK(hipEventRecord(p->done, s));
     HIPCHK(hipStreamSynchronize(s));
     *out = p.release();
   });
@@ -542,6 +624,7 @@ extern "C" int heff_apply(dm_heff_plan* p, const void* theta, void* theta_out, d
     if (p->n() > 0 && (!theta || !theta_out)) throw DmError{DM_ERR_ARG, "null theta"};
     if (theta == theta_out && p->n() > 0) throw DmError{DM_ERR_ARG, "theta and theta_out overlap"};
     heff_run(p, theta, theta_out, (hipStream_t)stream, false);
+    HIPCHK(hipEventRecord(p->done, (hipStream_t)stream));
   });
 }
 
@@ -559,8 +642,7 @@ static void ensure_lanczos(dm_heff_plan* p, int max_iter) {
     const int cap = std::max(max_iter + 1, 31);
     p->dV = (double*)dev_alloc((size_t)cap * n * 16);
     p->Vcap = cap;
-    const int nb = std::max(lz_nblk(n), lz_nblk1(n));
-    p->dPart = (double*)dev_alloc((size_t)nb * (2 * cap + 1) * 8);
+    p->dPart = (double*)dev_alloc((size_t)lz_nblk1(n) * (2 * cap + 2) * 8);
   }
   if (!p->dW) p->dW = (double*)dev_alloc((size_t)n * 16);
   if (!p->dVcur) p->dVcur = (double*)dev_alloc((size_t)n * 16);
@@ -620,6 +702,7 @@ extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_it
       HIPCHK(lz_launch_rq((const double*)theta_inout, p->dW, n, p->dState, p->dPart, s));
     }
     HIPCHK(hipMemcpyAsync(p->hState, p->dState, sizeof(LzState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(p->done, s));
     HIPCHK(hipStreamSynchronize(s));
     if (p->hState->bad) throw DmError{DM_ERR_NONFINITE, "Lanczos produced a zero, NaN or Inf norm"};
     *energy = p->hState->energy;
@@ -842,11 +925,8 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
 // Runs T1 -> mix -> T3 with stream-ordered scratch, FP64 or FP32 arithmetic.
 void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64_t nsite,
              void* out, int64_t nout, int prec, hipStream_t s) {
-  upload_stage(ep.t1);
-  upload_stage(ep.t3);
-  upload_stage(ep.mix);
   const size_t eb = elem_bytes(prec);
-  void *t1 = nullptr, *t2 = nullptr, *e32 = nullptr, *s32 = nullptr, *o32 = nullptr;
+  void *t1 = nullptr, *t2 = nullptr, *e32 = nullptr, *s32 = nullptr, *o32 = nullptr, *tab = nullptr;
   auto amalloc = [&](void** q, size_t bytes) {
     if (bytes == 0) return;
     if (hipMallocAsync(q, bytes, s) != hipSuccess) {
@@ -856,7 +936,16 @@ void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64
   };
   std::string failure;
   int code = DM_OK;
+  TableUpload up;  // host copy lives until the stream is synchronised below
   try {
+    up.add(ep.t1);
+    up.add(ep.t3);
+    up.add(ep.mix);
+    if (!up.host.empty()) {
+      amalloc(&tab, up.host.size());
+      HIPCHK(hipMemcpyAsync(tab, up.host.data(), up.host.size(), hipMemcpyHostToDevice, s));
+      for (auto& f : up.fix) *f.second = (char*)tab + f.first;
+    }
     amalloc(&t1, ep.t1total * eb);
     amalloc(&t2, ep.t2total * eb);
     if (prec == DM_FP64) {
@@ -878,12 +967,9 @@ void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64
     failure = e.msg;
     code = e.code;
   }
-  for (void* q : {t1, t2, e32, s32, o32})
+  for (void* q : {t1, t2, e32, s32, o32, tab})
     if (q) (void)hipFreeAsync(q, s);
   const hipError_t se = hipStreamSynchronize(s);
-  free_stage(ep.t1);
-  free_stage(ep.t3);
-  free_stage(ep.mix);
   if (code != DM_OK) throw DmError{code, failure};
   if (se != hipSuccess) throw DmError{DM_ERR_HIP, std::string("stream sync: ") + hipGetErrorString(se)};
 }

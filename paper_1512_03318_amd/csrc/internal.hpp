@@ -133,6 +133,7 @@ struct LzState {
   double inv_beta, tnorm, tol, energy;
   int32_t iter, k, stop, max_iter, bad;
 };
+// partial sums buffer: lz_nblk1(n) * (2 * max_iter + 2) doubles
 int lz_nblk(int64_t n);
 int lz_nblk1(int64_t n);
 hipError_t lz_launch_init(LzState* st, int32_t max_iter, double tol, hipStream_t s);

@@ -6,28 +6,31 @@
 //   v_0 = theta / |theta|
 //   step j:  w = H v_j
 //            h1 = V^H w,  alpha_j = Re h1_j            (V = [v_0 .. v_j])
-//            w1 = w - V h1,  h2 = V^H w1
+//            w1 = w - V h1,  h2 = V^H w1        (four streaming passes over V)
 //            beta_j = |w1 - V h2| = sqrt(|w1|^2 - |h2|^2)
 //            stop if beta_j <= tol * |T| (|T| = max_i |alpha_i| + beta_i + beta_{i-1})
 //            or j = max_iter - 1;  else v_{j+1} = (w1 - V h2) / beta_j
-//   lowest eigenpair (E, y) of T_k by bisection on Sturm counts and inverse iteration,
-//   Ritz vector V y.
+//   lowest eigenpair (E, y) of T_k by multisection on Sturm counts and inverse
+//   iteration, Ritz vector V y.
 //
 // All scalars live in LzState on the device.  Every kernel of one step reads the step
 // index and the stop flag from there, so the launches of a step have fixed arguments
 // (the step can be captured once as a HIP graph and replayed) and a breakdown turns
 // the remaining launches into no-ops without a host round trip.  Partial sums are
 // reduced in a fixed order: results are reproducible run to run.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mrd {
 
 constexpr int LZ_EPT = 4;                 // elements per thread in streaming kernels
 constexpr int LZ_CHUNK = 256 * LZ_EPT;
-constexpr int LZ_REG = 32;                // Krylov vectors cached in registers
 
 int lz_nblk(int64_t n) { return (int)((n + LZ_CHUNK - 1) / LZ_CHUNK); }
 int lz_nblk1(int64_t n) { return (int)((n + 255) / 256); }
+// dot-product blocks along the vector: about 16 elements per thread
+static int lz_dots_nblk(int64_t n) { return (int)std::max<int64_t>(1, (n + 4095) / 4096); }
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -72,12 +75,14 @@ __global__ void __launch_bounds__(256) lz_norm_kernel(const double* __restrict__
 
 // out[c] = sum_b partial[b * ncomp + c] in a fixed order, c < ncomp.
 // ncomp = fixed if >= 0, else 2 * (st->iter + 1) + extra (the current step's width).
+// With at_2nv, the result goes to out + 2 * (st->iter + 1) (the |w|^2 slot of h2).
 __global__ void __launch_bounds__(256) lz_reduce_kernel(const double* __restrict__ partial,
                                                         int32_t nblk, int32_t fixed, int32_t extra,
                                                         const LzState* __restrict__ st,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, int32_t at_2nv) {
   __shared__ double sm[256];
-  if (fixed < 0 && st->stop) return;
+  if ((fixed < 0 || at_2nv) && st->stop) return;
+  if (at_2nv) out += 2 * (st->iter + 1);
   const int ncomp = fixed >= 0 ? fixed : 2 * (st->iter + 1) + extra;
   const int c = blockIdx.x;
   if (c >= ncomp) return;
@@ -114,108 +119,88 @@ __global__ void lz_start_scale_kernel(const double* __restrict__ x, int64_t n,
   vcur[2 * e + 1] = b;
 }
 
-// partial[blk][2i + {0,1}] = sum over the chunk of conj(V_i) w, i <= iter.
-__global__ void __launch_bounds__(256) lz_dots_kernel(const double* __restrict__ V, int64_t ld,
-                                                      const double* __restrict__ w, int64_t n,
-                                                      const LzState* __restrict__ st,
-                                                      double* __restrict__ partial) {
-  __shared__ double sh[4];
-  if (st->stop) return;
-  const int nv = st->iter + 1;
-  double wr[LZ_EPT], wi[LZ_EPT];
+constexpr int LZ_G = 4;  // Krylov vectors per dot-product block
+
+// Block sums of NVAL per-thread values with one barrier (wave shuffles, then the four
+// wave partials in a fixed order); out[c] for c < nval.
+template <int NVAL>
+__device__ __forceinline__ void block_sums(const double (&v)[NVAL], int nval, double* sh,
+                                           double* out) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-  for (int q = 0; q < LZ_EPT; ++q) {
-    const int64_t e = (int64_t)blockIdx.x * LZ_CHUNK + q * 256 + threadIdx.x;
-    wr[q] = e < n ? w[2 * e] : 0.0;
-    wi[q] = e < n ? w[2 * e + 1] : 0.0;
+  for (int c = 0; c < NVAL; ++c) {
+    const double x = wave_sum(v[c]);
+    if (lane == 0) sh[c * 4 + wv] = x;
   }
-  for (int i = 0; i < nv; ++i) {
-    const double* v = V + 2 * (int64_t)i * ld;
-    double sr = 0, si = 0;
-#pragma unroll
-    for (int q = 0; q < LZ_EPT; ++q) {
-      const int64_t e = (int64_t)blockIdx.x * LZ_CHUNK + q * 256 + threadIdx.x;
-      if (e < n) {
-        const double vr = v[2 * e], vi = v[2 * e + 1];
-        sr += vr * wr[q] + vi * wi[q];
-        si += vr * wi[q] - vi * wr[q];
-      }
-    }
-    sr = block_sum(sr, sh);
-    si = block_sum(si, sh);
-    if (threadIdx.x == 0) {
-      partial[(int64_t)blockIdx.x * 2 * nv + 2 * i] = sr;
-      partial[(int64_t)blockIdx.x * 2 * nv + 2 * i + 1] = si;
-    }
+  __syncthreads();
+  if (threadIdx.x < nval) {
+    const int c = threadIdx.x;
+    out[c] = (sh[c * 4] + sh[c * 4 + 1]) + (sh[c * 4 + 2] + sh[c * 4 + 3]);
   }
 }
 
-// One element per thread.  w -= V h1 (written back), then the partial projections
-// conj(V_i) w and |w|^2 (component 2 nv).  The first LZ_REG Krylov elements of the
-// thread are kept in registers between the two passes, so V is read once from memory.
-__global__ void __launch_bounds__(256) lz_project_kernel(const double* __restrict__ V, int64_t ld,
-                                                         double* __restrict__ w, int64_t n,
-                                                         const LzState* __restrict__ st,
-                                                         double* __restrict__ partial) {
+// partial[blockIdx.y][2i + {0,1}] = sum of conj(V_i) x over the elements
+// e = (blockIdx.y + gridDim.y q) * 256 + thread, q = 0, 1, ..., for the LZ_G vectors
+// i = LZ_G * blockIdx.x + g < nv (nv = iter + 1).  Each thread accumulates many
+// elements before the single block reduction; consecutive blocks (same y, next group)
+// read the same x elements, which stay in L2.
+__global__ void __launch_bounds__(256) lz_dots_kernel(const double* __restrict__ V, int64_t ld,
+                                                      const double* __restrict__ x, int64_t n,
+                                                      const LzState* __restrict__ st,
+                                                      double* __restrict__ partial) {
+  __shared__ double sh[4 * 2 * LZ_G];
+  if (st->stop) return;
+  const int nv = st->iter + 1;
+  const int i0 = blockIdx.x * LZ_G;
+  if (i0 >= nv) return;
+  const double2* xv = reinterpret_cast<const double2*>(x);
+  const double2* vv[LZ_G];
+#pragma unroll
+  for (int g = 0; g < LZ_G; ++g)
+    vv[g] = reinterpret_cast<const double2*>(V) + (int64_t)min(i0 + g, nv - 1) * ld;
+  double acc[2 * LZ_G];
+#pragma unroll
+  for (int c = 0; c < 2 * LZ_G; ++c) acc[c] = 0.0;
+  const int64_t stride = (int64_t)gridDim.y * 256;
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < n; e += stride) {
+    const double2 xe = xv[e];
+#pragma unroll
+    for (int g = 0; g < LZ_G; ++g) {
+      const double2 v = vv[g][e];
+      acc[2 * g] += v.x * xe.x + v.y * xe.y;
+      acc[2 * g + 1] += v.x * xe.y - v.y * xe.x;
+    }
+  }
+  block_sums(acc, 2 * min(LZ_G, nv - i0), sh, partial + blockIdx.y * (int64_t)(2 * nv) + 2 * i0);
+}
+
+// w -= V h1 over the nv = iter + 1 Krylov vectors; partial[chunk] = |w_new|^2 over the chunk.
+__global__ void __launch_bounds__(256) lz_sub_kernel(const double* __restrict__ V, int64_t ld,
+                                                     double* __restrict__ w, int64_t n,
+                                                     const LzState* __restrict__ st,
+                                                     double* __restrict__ partial) {
   __shared__ double sh[4];
   if (st->stop) return;
   const int nv = st->iter + 1;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const bool in = e < n;
-  double wr = in ? w[2 * e] : 0.0, wi = in ? w[2 * e + 1] : 0.0;
-  double vr[LZ_REG], vi[LZ_REG];
-#pragma unroll
-  for (int i = 0; i < LZ_REG; ++i) {
-    vr[i] = 0.0;
-    vi[i] = 0.0;
-    if (i < nv && in) {
-      vr[i] = V[2 * ((int64_t)i * ld + e)];
-      vi[i] = V[2 * ((int64_t)i * ld + e) + 1];
-    }
-  }
   const double* h1 = st->h1;
+  double nn = 0;
 #pragma unroll
-  for (int i = 0; i < LZ_REG; ++i) {
-    if (i < nv) {
+  for (int q = 0; q < LZ_EPT; ++q) {
+    const int64_t e = (int64_t)blockIdx.x * LZ_CHUNK + q * 256 + threadIdx.x;
+    if (e >= n) continue;
+    double wr = w[2 * e], wi = w[2 * e + 1];
+    for (int i = 0; i < nv; ++i) {
       const double hr = h1[2 * i], hi = h1[2 * i + 1];
-      wr -= hr * vr[i] - hi * vi[i];
-      wi -= hr * vi[i] + hi * vr[i];
+      const double vr = V[2 * ((int64_t)i * ld + e)], vi = V[2 * ((int64_t)i * ld + e) + 1];
+      wr -= hr * vr - hi * vi;
+      wi -= hr * vi + hi * vr;
     }
-  }
-  for (int i = LZ_REG; i < nv; ++i) {
-    const double hr = h1[2 * i], hi = h1[2 * i + 1];
-    const double ar = in ? V[2 * ((int64_t)i * ld + e)] : 0.0, ai = in ? V[2 * ((int64_t)i * ld + e) + 1] : 0.0;
-    wr -= hr * ar - hi * ai;
-    wi -= hr * ai + hi * ar;
-  }
-  if (in) {
     w[2 * e] = wr;
     w[2 * e + 1] = wi;
+    nn += wr * wr + wi * wi;
   }
-  const int ncomp = 2 * nv + 1;
-  double* out = partial + (int64_t)blockIdx.x * ncomp;
-#pragma unroll
-  for (int i = 0; i < LZ_REG; ++i) {
-    if (i < nv) {
-      const double sr = block_sum(vr[i] * wr + vi[i] * wi, sh);
-      const double si = block_sum(vr[i] * wi - vi[i] * wr, sh);
-      if (threadIdx.x == 0) {
-        out[2 * i] = sr;
-        out[2 * i + 1] = si;
-      }
-    }
-  }
-  for (int i = LZ_REG; i < nv; ++i) {
-    const double ar = in ? V[2 * ((int64_t)i * ld + e)] : 0.0, ai = in ? V[2 * ((int64_t)i * ld + e) + 1] : 0.0;
-    const double sr = block_sum(ar * wr + ai * wi, sh);
-    const double si = block_sum(ar * wi - ai * wr, sh);
-    if (threadIdx.x == 0) {
-      out[2 * i] = sr;
-      out[2 * i + 1] = si;
-    }
-  }
-  const double nn = block_sum(wr * wr + wi * wi, sh);
-  if (threadIdx.x == 0) out[2 * nv] = nn;
+  nn = block_sum(nn, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = nn;
 }
 
 // Scalar part of step j = st->iter: alpha_j, beta_j, |T|, stopping rule.
@@ -285,46 +270,73 @@ __device__ int lz_sturm(const double* al, const double* be, int k, double x) {
   return cnt;
 }
 
-// Lowest eigenpair of T_k (one thread): bisection to full precision, then inverse
-// iteration with partial pivoting (four sweeps).  Writes st->energy and st->y.
-__global__ void lz_tridiag_kernel(LzState* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Lowest eigenpair of T_k.  One wavefront brackets the lowest eigenvalue by
+// multisection: each lane counts (Sturm sequence) the eigenvalues below its own point
+// of a 64-point grid of the current interval, so every round shrinks it 65-fold; then
+// lane 0 runs inverse iteration with partial pivoting (four sweeps).  Writes st->energy
+// and st->y.
+__global__ void __launch_bounds__(64) lz_tridiag_kernel(LzState* st) {
+  __shared__ int cnt[64];
+  __shared__ double bounds[2];
+  __shared__ double dd[LZ_MAX], du[LZ_MAX], du2[LZ_MAX], dl[LZ_MAX], b[LZ_MAX], ys[LZ_MAX];
+  const int lane = threadIdx.x;
   const int k = st->k;
   const double* al = st->alpha;
   const double* be = st->beta;
   double* y = st->y;
   if (k <= 0) return;
   if (k == 1) {
-    st->energy = al[0];
-    y[0] = 1.0;
+    if (lane == 0) {
+      st->energy = al[0];
+      y[0] = 1.0;
+    }
     return;
   }
-  double lo = al[0], hi = al[0];
-  for (int i = 0; i < k; ++i) {
-    const double r = (i ? fabs(be[i - 1]) : 0.0) + (i < k - 1 ? fabs(be[i]) : 0.0);
-    lo = fmin(lo, al[i] - r);
-    hi = fmax(hi, al[i] + r);
+  if (lane == 0) {
+    double lo = al[0], hi = al[0];
+    for (int i = 0; i < k; ++i) {
+      const double r = (i ? fabs(be[i - 1]) : 0.0) + (i < k - 1 ? fabs(be[i]) : 0.0);
+      lo = fmin(lo, al[i] - r);
+      hi = fmax(hi, al[i] + r);
+    }
+    bounds[0] = lo;
+    bounds[1] = hi;
   }
-  const double scale = fmax(fabs(lo), fabs(hi));
-  for (int it = 0; it < 2000 && hi - lo > 2e-16 * scale; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    if (lz_sturm(al, be, k, mid) >= 1)
-      hi = mid;
-    else
-      lo = mid;
+  __syncthreads();
+  const double scale = fmax(fabs(bounds[0]), fabs(bounds[1]));
+  for (int round = 0; round < 64; ++round) {
+    const double lo = bounds[0], hi = bounds[1];
+    if (!(hi - lo > 2e-16 * scale)) break;
+    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    cnt[lane] = lz_sturm(al, be, k, x);
+    __syncthreads();
+    if (lane == 0) {
+      // first grid point with at least one eigenvalue below it
+      int m = 64;
+      for (int q = 0; q < 64; ++q)
+        if (cnt[q] >= 1) {
+          m = q;
+          break;
+        }
+      const double nlo = m == 0 ? lo : lo + (hi - lo) * (double)m / 65.0;
+      const double nhi = m == 64 ? hi : lo + (hi - lo) * (double)(m + 1) / 65.0;
+      bounds[0] = nlo;
+      bounds[1] = nhi;
+    }
+    __syncthreads();
+    if (bounds[0] == lo && bounds[1] == hi) break;  // no progress at this precision
   }
-  const double lam = 0.5 * (lo + hi);
+  if (lane != 0) return;
+  const double lam = 0.5 * (bounds[0] + bounds[1]);
   st->energy = lam;
-  double dd[LZ_MAX], du[LZ_MAX], du2[LZ_MAX], dl[LZ_MAX], b[LZ_MAX];
-  for (int i = 0; i < k; ++i) y[i] = 1.0 / sqrt((double)k);
+  for (int i = 0; i < k; ++i) ys[i] = 1.0 / sqrt((double)k);
   for (int sweep = 0; sweep < 4; ++sweep) {
     for (int i = 0; i < k; ++i) {
       dd[i] = al[i] - lam;
       du[i] = i < k - 1 ? be[i] : 0.0;
       dl[i] = i < k - 1 ? be[i] : 0.0;
       du2[i] = 0.0;
-      b[i] = y[i];
+      b[i] = ys[i];
     }
     for (int i = 0; i < k - 1; ++i) {
       if (fabs(dd[i]) >= fabs(dl[i])) {
@@ -354,8 +366,9 @@ __global__ void lz_tridiag_kernel(LzState* st) {
     double nrm = 0;
     for (int i = 0; i < k; ++i) nrm += b[i] * b[i];
     nrm = sqrt(nrm);
-    for (int i = 0; i < k; ++i) y[i] = b[i] / nrm;
+    for (int i = 0; i < k; ++i) ys[i] = b[i] / nrm;
   }
+  for (int i = 0; i < k; ++i) y[i] = ys[i];
 }
 
 // out = sum_{i < k} y_i V_i
@@ -415,19 +428,23 @@ hipError_t lz_launch_start(const double* x, int64_t n, LzState* st, double* part
                            double* vcur, hipStream_t s) {
   const int nb = lz_nblk(n);
   hipLaunchKernelGGL(lz_norm_kernel, dim3(nb), dim3(256), 0, s, x, n, partial);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(1), dim3(256), 0, s, partial, nb, 1, 0, st, &st->scal0);
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(1), dim3(256), 0, s, partial, nb, 1, 0, st, &st->scal0, 0);
   hipLaunchKernelGGL(lz_start_scale_kernel, g1(n), dim3(256), 0, s, x, n, st, V, vcur);
   return hipGetLastError();
 }
 
 hipError_t lz_launch_step_tail(double* V, int64_t ld, double* w, int64_t n, LzState* st,
                                double* partial, double* vcur, int32_t max_iter, hipStream_t s) {
-  const int nb = lz_nblk(n), nb1 = lz_nblk1(n);
+  const int nb = lz_nblk(n), nb1 = lz_dots_nblk(n);
   const int maxc = 2 * max_iter + 1;
-  hipLaunchKernelGGL(lz_dots_kernel, dim3(nb), dim3(256), 0, s, V, ld, w, n, st, partial);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc), dim3(256), 0, s, partial, nb, -1, 0, st, st->h1);
-  hipLaunchKernelGGL(lz_project_kernel, dim3(nb1), dim3(256), 0, s, V, ld, w, n, st, partial);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc), dim3(256), 0, s, partial, nb1, -1, 1, st, st->h2);
+  const dim3 gd((max_iter + LZ_G - 1) / LZ_G, nb1);
+  double* pnorm = partial + (size_t)nb1 * maxc;
+  hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, V, ld, w, n, st, partial);
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc), dim3(256), 0, s, partial, nb1, -1, 0, st, st->h1, 0);
+  hipLaunchKernelGGL(lz_sub_kernel, dim3(nb), dim3(256), 0, s, V, ld, w, n, st, pnorm);
+  hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, V, ld, w, n, st, partial);
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc), dim3(256), 0, s, partial, nb1, -1, 0, st, st->h2, 0);
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(1), dim3(256), 0, s, pnorm, nb, 1, 0, st, st->h2, 1);
   hipLaunchKernelGGL(lz_scalar_kernel, dim3(1), dim3(64), 0, s, st);
   hipLaunchKernelGGL(lz_next_kernel, g1(n), dim3(256), 0, s, V, ld, w, n, st, vcur);
   return hipGetLastError();
@@ -444,7 +461,7 @@ hipError_t lz_launch_rq(const double* x, const double* w, int64_t n, LzState* st
                         hipStream_t s) {
   const int nb = lz_nblk(n);
   hipLaunchKernelGGL(lz_rq_kernel, dim3(nb), dim3(256), 0, s, x, w, n, partial);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(2), dim3(256), 0, s, partial, nb, 2, 0, st, st->rq);
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(2), dim3(256), 0, s, partial, nb, 2, 0, st, st->rq, 0);
   hipLaunchKernelGGL(lz_rq_final_kernel, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }

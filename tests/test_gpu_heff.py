@@ -115,12 +115,12 @@ def test_lanczos_graph_replays_equal_eager():
     wl, L, W1, W2, R, th, keys, mpo = problem("ly6_chi200")
     say("lanczos graph vs eager")
     g = WindowGPU(wl, L, R, mpo)
-    os.environ["MRDMRG_NO_GRAPH"] = "1"
+    eager = g.plan(pk.DM_FP64)
+    os.environ["MRDMRG_GRAPH"] = "1"
     try:
-        eager = g.plan(pk.DM_FP64)
+        graphed = g.plan(pk.DM_FP64)
     finally:
-        os.environ.pop("MRDMRG_NO_GRAPH")
-    graphed = g.plan(pk.DM_FP64)
+        os.environ.pop("MRDMRG_GRAPH")
     x0 = to_dev(g.pack_theta(th))
     xe = x0.clone()
     ee, ke = pk.lanczos_ground(eager, xe, 30, 1e-14)
