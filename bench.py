@@ -87,11 +87,13 @@ def build_inputs(pk, torch, wl, stream):
     return out
 
 
-def run_step(pk, inp, prec, iters, stream):
+def run_step(pk, inp, prec, iters, stream, profile=False):
     """One bond update; returns (energy, iterations, plan, host times)."""
     t0 = time.perf_counter()
     plan = pk.HeffPlan(inp["ly"], inp["a"], inp["c"], inp["w1"], inp["w2"], inp["L"], inp["R"],
                        prec, stream)
+    if profile:
+        plan.profile(True)
     th = inp["theta"].clone()
     t1 = time.perf_counter()
     e, k = pk.lanczos_ground(plan, th, iters, 1e-14, stream)
@@ -211,9 +213,15 @@ def main():
     torch.cuda.synchronize()
     host = []
     flops = 0.0
+    prof = [0.0, 0.0, 0.0, 0.0]
+    nmv = 0
     t0 = time.perf_counter()
     for i in range(args.steps):
-        e, k, plan, ts = run_step(pk, inp, prec, args.iters, stream)
+        # per-kernel HIP events on the launch stream, recorded inside the timed steps
+        e, k, plan, ts = run_step(pk, inp, prec, args.iters, stream, profile=True)
+        ms, nm = plan.profile_read()
+        prof = [p + q for p, q in zip(prof, ms)]
+        nmv += nm
         flops += step_flops(plan, k, prec, inp["env_flops"], pk)
         host.append(ts)
         stage_flops = plan.flops
@@ -224,24 +232,13 @@ def main():
     lanczos_ms = 1e3 * statistics.median(t[1] for t in host)
     log(f"timed {args.steps} steps: {ms_step:.2f} ms/step, {value:.1f} GFLOP/s, lanczos {lanczos_ms:.2f} ms, E={e:.12f}")
 
-    # per-stage device time (HIP events on the launch stream) over a separate run of
-    # matvecs in the same launch configuration as inside the Lanczos steps
-    pplan = pk.HeffPlan(inp["ly"], inp["a"], inp["c"], inp["w1"], inp["w2"], inp["L"], inp["R"],
-                        prec, stream)
-    xx = inp["theta"]
-    yy = torch.empty_like(xx)
-    for _ in range(3):
-        pk.heff_apply(pplan, xx, yy, stream)
-    pplan.profile(True)
-    for _ in range(20):
-        pk.heff_apply(pplan, xx, yy, stream)
-    prof, nmv = pplan.profile_read()
-    # dominant kernel: the stage with the most device time
-    names = ["L.theta block GEMM", "MPO mixing", "(.).R block GEMM"]
+    # dominant kernel: the one with the most device time
+    names = ["L.theta block GEMM", "MPO mixing", "(.).R block GEMM", "K-split reduction"]
     dom = max(range(3), key=lambda s: prof[s])
     avg_ms = prof[dom] / max(nmv, 1)
     achieved = stage_flops[dom] / (avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": f"gemm_kernel ({names[dom]}, {args.prec})",
+    kern = {0: "gemm_kernel<T, 0, false>", 1: "mix_kernel<T>", 2: "gemm_kernel<T, 20, true>"}[dom]
+    roofline = {"bound": "mfma", "kernel": f"{kern} ({names[dom]}, {args.prec})",
                 "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_TFLOPS[args.prec], 4), "traffic": None,
                 "avg_launch_ms": round(avg_ms, 4),

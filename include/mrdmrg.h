@@ -156,11 +156,13 @@ int dm_heff_info(const dm_heff_plan* p, int64_t* theta_elems, double flops[3]);
 
 /* Device-time profile of the matvec stages.  While enabled, every matvec of the plan
  * (heff_apply and the ones inside lanczos_ground) records HIP events on its stream
- * around each stage; dm_heff_profile_read synchronises and returns the accumulated
- * milliseconds of stage 0 (L.theta GEMMs), 1 (MPO mixing), 2 ((.).R GEMMs) and the
- * number of matvecs recorded.  enable = 0 stops recording and clears the totals. */
+ * around each kernel; dm_heff_profile_read synchronises and returns the accumulated
+ * milliseconds of 0: the L.theta GEMM kernel, 1: the MPO mixing kernel, 2: the (.).R
+ * GEMM kernel, 3: the reduction of its K-split partial tiles, and the number of
+ * matvecs recorded.  enable = 0 stops recording and clears the totals.  Profiling
+ * keeps lanczos_ground on plain stream launches (no graph replay). */
 int dm_heff_profile(dm_heff_plan* p, int32_t enable);
-int dm_heff_profile_read(dm_heff_plan* p, double ms[3], int64_t* matvecs);
+int dm_heff_profile_read(dm_heff_plan* p, double ms[4], int64_t* matvecs);
 
 /* theta_out = H_eff theta.  Both are device complex128 in the THETA layout of (a, c,
  * w1.qs, w2.qs); they must not overlap.  Asynchronous on `stream`. */

@@ -220,8 +220,9 @@ class HeffPlan:
         _check(lib.dm_heff_profile(self.h, 1 if enable else 0))
 
     def profile_read(self):
-        """(ms per stage [L.theta GEMMs, mixing, (.).R GEMMs] accumulated, matvecs recorded)."""
-        ms = (_f64 * 3)()
+        """(ms per kernel [L.theta GEMM, mixing, (.).R GEMM, K-split reduction] accumulated,
+        matvecs recorded)."""
+        ms = (_f64 * 4)()
         n = _i64()
         _check(lib.dm_heff_profile_read(self.h, ms, C.byref(n)))
         return list(ms), n.value

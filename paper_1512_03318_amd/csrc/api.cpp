@@ -318,7 +318,7 @@ struct dm_heff_plan {
   bool use_graph = true;
   // profiling: events around the three stages of each recorded matvec
   bool profiling = false;
-  std::vector<std::array<hipEvent_t, 4>> ev;
+  std::vector<std::array<hipEvent_t, 5>> ev;
   size_t ev_used = 0;
   ~dm_heff_plan() {
     if (done) {
@@ -545,7 +545,7 @@ extern "C" int dm_heff_info(const dm_heff_plan* p, int64_t* theta_elems, double 
 static hipEvent_t* prof_slot(dm_heff_plan* p) {
   if (!p->profiling) return nullptr;
   if (p->ev_used == p->ev.size()) {
-    std::array<hipEvent_t, 4> e;
+    std::array<hipEvent_t, 5> e;
     for (auto& x : e) HIPCHK(hipEventCreate(&x));
     p->ev.push_back(e);
   }
@@ -579,8 +579,8 @@ static void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStr
     HIPCHK(launch_mix<double>(p->mix, (const double*)dX, (double*)dZ, s, skip));
     mark(2);
     HIPCHK(launch_gemm<double>(p->s4, (const double*)dZ, (const double*)dR, (double*)theta_out,
-                               (double*)dP, s, skip));
-    mark(3);
+                               (double*)dP, s, skip, [&] { mark(3); }));
+    mark(4);
     return;
   }
   HIPCHK(launch_cast_d2f((const double*)theta, (float*)p->dTin, 2 * p->n(), s, skip));
@@ -590,8 +590,8 @@ static void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStr
   HIPCHK(launch_mix<float>(p->mix, (const float*)p->dX, (float*)p->dZ, s, skip));
   mark(2);
   HIPCHK(launch_gemm<float>(p->s4, (const float*)p->dZ, (const float*)p->dR, (float*)p->dTout,
-                            (float*)p->dSplit, s, skip));
-  mark(3);
+                            (float*)p->dSplit, s, skip, [&] { mark(3); }));
+  mark(4);
   HIPCHK(launch_cast_f2d((const float*)p->dTout, (double*)theta_out, 2 * p->n(), s, skip));
 }
 
@@ -602,13 +602,13 @@ extern "C" int dm_heff_profile(dm_heff_plan* p, int32_t enable) {
   return DM_OK;
 }
 
-extern "C" int dm_heff_profile_read(dm_heff_plan* p, double ms[3], int64_t* matvecs) {
+extern "C" int dm_heff_profile_read(dm_heff_plan* p, double ms[4], int64_t* matvecs) {
   return guarded([&] {
     if (!p || !ms) throw DmError{DM_ERR_ARG, "null argument"};
-    ms[0] = ms[1] = ms[2] = 0.0;
+    ms[0] = ms[1] = ms[2] = ms[3] = 0.0;
     for (size_t i = 0; i < p->ev_used; ++i) {
-      HIPCHK(hipEventSynchronize(p->ev[i][3]));
-      for (int st = 0; st < 3; ++st) {
+      HIPCHK(hipEventSynchronize(p->ev[i][4]));
+      for (int st = 0; st < 4; ++st) {
         float t = 0;
         HIPCHK(hipEventElapsedTime(&t, p->ev[i][st], p->ev[i][st + 1]));
         ms[st] += t;

@@ -5,6 +5,7 @@
 #include <hip/hip_complex.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -109,9 +110,12 @@ int gemm_tile_n(bool deep);
 // Kernel launchers (kernels.hip).  T = double or float (complex interleaved).
 // part: scratch of st.nslots * 1024 complex elements (DEEP stages with K-splits).
 // skip (may be null): the kernels return at once when *skip != 0 (a stopped Lanczos).
+// between (may be empty) runs on the host after the main kernel is enqueued and before
+// the K-split reduction (used to record a profiling event).
 template <typename T>
 hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* part, hipStream_t s,
-                       const int32_t* skip = nullptr);
+                       const int32_t* skip = nullptr,
+                       const std::function<void()>& between = std::function<void()>());
 template <typename T>
 hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s,
                       const int32_t* skip = nullptr);

@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const GemmProb* 
 
 template <typename T>
 hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* part, hipStream_t s,
-                       const int32_t* skip) {
+                       const int32_t* skip, const std::function<void()>& between) {
   const int32_t nt = (int32_t)st.tiles.size();
   if (nt == 0) return hipSuccess;
   if (st.nslots > 0 && !part) return hipErrorInvalidValue;
@@ -371,6 +371,7 @@ hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* par
   if (st.flags == (F) && st.deep == (D)) {                                                 \
     hipLaunchKernelGGL((gemm_kernel<T, F, D>), grid, block, 0, s, st.d_segs, st.d_probs,   \
                        st.d_tiles, st.d_rows, st.d_asrc, A, B, C, part, skip);             \
+    if (between) between();                                                                \
     if (D && !st.red_tiles.empty())                                                        \
       hipLaunchKernelGGL((gemm_split_reduce_kernel<T, F>), dim3(st.red_tiles.size()),      \
                          block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C, skip);\
@@ -389,9 +390,10 @@ int gemm_tile_m(bool deep) { return deep ? 32 : 64; }
 int gemm_tile_n(bool deep) { return deep ? 32 : 64; }
 
 template hipError_t launch_gemm<double>(const GemmStage&, const double*, const double*, double*,
-                                        double*, hipStream_t, const int32_t*);
+                                        double*, hipStream_t, const int32_t*,
+                                        const std::function<void()>&);
 template hipError_t launch_gemm<float>(const GemmStage&, const float*, const float*, float*, float*,
-                                       hipStream_t, const int32_t*);
+                                       hipStream_t, const int32_t*, const std::function<void()>&);
 
 // ---------------------------------------------------------------------------------
 // Sparse MPO mixing: each workgroup owns one destination sub-block and sums its few
