@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="ly8_chi3200")
-    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
@@ -198,7 +198,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    prec = {"fp64": pk.DM_FP64, "fp32": pk.DM_FP32}[args.prec]
+    prec = {"fp64": pk.DM_FP64, "fp32": pk.DM_FP32, "bf16x3": pk.DM_BF16X3}[args.prec]
 
     wl = workloads.preset(args.workload)
     t0 = time.perf_counter()
@@ -248,7 +248,7 @@ def main():
     out = {"metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "c64" if prec == pk.DM_FP32 else "c128", "data": "synthetic",
+           "dtype": {pk.DM_FP64: "c128", pk.DM_FP32: "c64", pk.DM_BF16X3: "c64 (bf16x3 products)"}[prec], "data": "synthetic",
            "config": {"workload": args.workload, "Ly": wl.Ly, "Lx": wl.Lx, "flux": f"{wl.flux[0]}/{wl.flux[1]}",
                       "chi": int(sum(wl.bonds[wl.j].values())), "sectors": len(wl.bonds[wl.j]),
                       "mpo_D": list(inp["D"]), "lanczos_iters": args.iters, "precision": args.prec,

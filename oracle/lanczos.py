@@ -64,3 +64,27 @@ def _lowest(alphas, betas):
     e, y = eigh_tridiagonal(np.array(alphas), np.array(betas[:len(alphas) - 1]),
                             select="i", select_range=(0, 0))
     return float(e[0]), y[:, 0]
+
+
+def ground_state(matvec, v0: np.ndarray, tol_res: float = 1e-10, krylov: int = 30,
+                 max_restarts: int = 200):
+    """Lowest eigenpair to a residual |H v - E v| <= tol_res * |H| by explicitly restarted
+    Lanczos: each cycle runs ``lanczos`` for ``krylov`` steps from the previous cycle's
+    Ritz vector.  |H| is estimated by the largest |alpha_i| + beta_i + beta_{i-1} seen.
+    Returns (E, v, residual norm, matvecs)."""
+    v = v0 / np.linalg.norm(v0)
+    hnorm = 0.0
+    n_mv = 0
+    e = float("nan")
+    res = float("inf")
+    for _ in range(max_restarts):
+        e, v, k, al, be = lanczos(matvec, v, max_iter=krylov)
+        n_mv += k
+        b = np.concatenate([be, [0.0]])
+        hnorm = max(hnorm, float(np.max(np.abs(al) + b + np.concatenate([[0.0], be]))))
+        r = matvec(v) - e * v
+        n_mv += 1
+        res = float(np.linalg.norm(r))
+        if res <= tol_res * hnorm:
+            break
+    return e, v, res, n_mv

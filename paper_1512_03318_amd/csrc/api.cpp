@@ -165,7 +165,7 @@ struct TableUpload {
 size_t elem_bytes(int prec) { return prec == DM_FP64 ? 16 : 8; }
 
 void check_prec(int prec) {
-  if (prec != DM_FP64 && prec != DM_FP32)
+  if (prec != DM_FP64 && prec != DM_FP32 && prec != DM_BF16X3)
     throw DmError{DM_ERR_DTYPE, "precision " + std::to_string(prec) + " not supported"};
 }
 
@@ -187,6 +187,14 @@ void stage_out(const void* src, void* dst, int64_t n, int prec, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(dst, src, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
   else
     HIPCHK(launch_cast_f2d((const float*)src, (double*)dst, 2 * n, s));
+}
+
+// FP32-storage GEMM stage: FP32 MFMA (DM_FP32) or bf16 hi/lo split MFMA (DM_BF16X3).
+hipError_t gemm_lp(int prec, const GemmStage& st, const float* A, const float* B, float* C,
+                   float* part, hipStream_t s, const int32_t* skip = nullptr,
+                   const std::function<void()>& between = std::function<void()>()) {
+  if (prec == DM_BF16X3) return launch_gemm_bf16x3(st, A, B, C, part, s, skip, between);
+  return launch_gemm<float>(st, A, B, C, part, s, skip, between);
 }
 
 template <typename F>
@@ -585,12 +593,12 @@ static void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStr
   }
   HIPCHK(launch_cast_d2f((const double*)theta, (float*)p->dTin, 2 * p->n(), s, skip));
   mark(0);
-  HIPCHK(launch_gemm<float>(p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, nullptr, s, skip));
+  HIPCHK(gemm_lp(p->prec, p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, nullptr, s, skip));
   mark(1);
   HIPCHK(launch_mix<float>(p->mix, (const float*)p->dX, (float*)p->dZ, s, skip));
   mark(2);
-  HIPCHK(launch_gemm<float>(p->s4, (const float*)p->dZ, (const float*)p->dR, (float*)p->dTout,
-                            (float*)p->dSplit, s, skip, [&] { mark(3); }));
+  HIPCHK(gemm_lp(p->prec, p->s4, (const float*)p->dZ, (const float*)p->dR, (float*)p->dTout,
+                 (float*)p->dSplit, s, skip, [&] { mark(3); }));
   mark(4);
   HIPCHK(launch_cast_f2d((const float*)p->dTout, (double*)theta_out, 2 * p->n(), s, skip));
 }
@@ -958,9 +966,9 @@ void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64
       amalloc(&o32, nout * eb);
       stage_in(env, e32, nenv, DM_FP32, s);
       stage_in(site, s32, nsite, DM_FP32, s);
-      HIPCHK(launch_gemm<float>(ep.t1, (const float*)e32, (const float*)s32, (float*)t1, nullptr, s));
+      HIPCHK(gemm_lp(prec, ep.t1, (const float*)e32, (const float*)s32, (float*)t1, nullptr, s));
       HIPCHK(launch_mix<float>(ep.mix, (const float*)t1, (float*)t2, s));
-      HIPCHK(launch_gemm<float>(ep.t3, (const float*)s32, (const float*)t2, (float*)o32, nullptr, s));
+      HIPCHK(gemm_lp(prec, ep.t3, (const float*)s32, (const float*)t2, (float*)o32, nullptr, s));
       stage_out(o32, out, nout, DM_FP32, s);
     }
   } catch (const DmError& e) {

@@ -1,0 +1,66 @@
+// Device helpers shared by the GEMM kernels of every precision.
+#pragma once
+
+#include "internal.hpp"
+
+namespace mrd {
+
+template <typename T>
+struct Cplx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ Cplx<T> ldc(const T* base, int64_t off) {
+  // one complex element = two consecutive reals
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 v = *reinterpret_cast<const v2*>(base + 2 * off);
+  return {v.x, v.y};
+}
+
+template <typename T>
+__device__ __forceinline__ void stc(T* base, int64_t off, T re, T im) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 v;
+  v.x = re;
+  v.y = im;
+  *reinterpret_cast<v2*>(base + 2 * off) = v;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD b % 8); give
+// each XCD a contiguous run of the tile list, so tiles of one output sector (which share
+// operand panels) meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+// Sums the K-split partial tiles of one output tile in split order and stores it.
+template <typename T, int FLAGS>
+__global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const GemmProb* __restrict__ probs,
+                                                                const GemmTile* __restrict__ tiles,
+                                                                const int64_t* __restrict__ rows,
+                                                                const T* __restrict__ part,
+                                                                T* __restrict__ C,
+                                                                const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const GemmTile tile = tiles[blockIdx.x];
+  const GemmProb P = probs[tile.prob];
+  const int tiles_n = (P.N + 31) / 32;
+  const int64_t base = (int64_t)P.slot0 + ((int64_t)tile.tm * tiles_n + tile.tn) * P.nks;
+  for (int e = threadIdx.x; e < 1024; e += 256) {
+    const int r = e >> 5, c = e & 31;
+    const int i = tile.tm * 32 + r, j = tile.tn * 32 + c;
+    if (i >= P.M || j >= P.N) continue;
+    T re = 0, im = 0;
+    for (int ks = 0; ks < P.nks; ++ks) {
+      const Cplx<T> v = ldc(part, (base + ks) * 1024 + e);
+      re += v.re;
+      im += v.im;
+    }
+    const int64_t rb = (FLAGS & G_C_ROWMAP) ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
+    stc(C, rb + j, re, im);
+  }
+}
+
+}  // namespace mrd

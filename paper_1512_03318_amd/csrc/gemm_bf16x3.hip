@@ -1,0 +1,317 @@
+// Split-precision (BF16x3) grouped complex GEMM for gfx950.
+//
+// Operands stay FP32 in HBM.  While a chunk is staged into LDS every FP32 value x is
+// split into two bfloat16 parts, hi = bf16(x) and lo = bf16(x - hi) (round to nearest
+// even both times), so that x = hi + lo up to a relative 2^-17.  A real product is then
+// taken as three bf16 products on the 16x16x32 bf16 MFMA with FP32 accumulation,
+//   x y  ~  xh yh + xh yl + xl yh,
+// dropping xl yl (relative <= 2^-18) -- about 16 significant bits per product instead of
+// FP32's 24, at the rate of the bf16 matrix cores.  The complex product takes four real
+// products (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br), so twelve MFMAs per 16x16x32
+// complex sub-block.  The task tables, tiles and K-split are those of the FP32/FP64
+// kernels, so the host planner is shared.
+//
+// MFMA 16x16x32 bf16 operands (8 bf16 per lane): A(i, k) with i = lane % 16 and
+// k = 8 (lane / 16) + t, B(k, j) with j = lane % 16 and the same k; result row
+// 4 (lane / 16) + r, column lane % 16 (measured on gfx950).  LDS therefore holds each
+// operand as [row][k] planes (k contiguous), one plane per part: re_hi, re_lo, im_hi,
+// im_lo; a lane reads its 8 k values with one 16-byte load.
+#include "device.hpp"
+
+namespace mrd {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+template <int FLAGS, bool DEEP>
+struct Bf3Cfg {
+  static constexpr int KC = DEEP ? 128 : 32;  // K chunk; DEEP: 32 per wave
+  static constexpr int BM = DEEP ? 32 : 64;
+  static constexpr int BN = BM;
+  static constexpr int LD = KC + 8;            // LDS row stride (bf16), 16-byte pad
+  static constexpr int QA = BM * KC / 4 / 256;  // k-quads of A staged per thread
+  static constexpr int QB = BN * KC / 4 / 256;
+  static constexpr bool A_KC = !(FLAGS & G_A_T);
+  static constexpr bool B_KC = (FLAGS & G_B_T) != 0;
+  static constexpr int PLANE_A = BM * LD, PLANE_B = BN * LD;  // bf16 per plane
+  static constexpr int STAGE_BYTES = 2 * 4 * (PLANE_A + PLANE_B);
+  static constexpr int RED_BYTES = DEEP ? 3 * 32 * 64 * 4 : 0;
+  static constexpr int SMEM = STAGE_BYTES > RED_BYTES ? STAGE_BYTES : RED_BYTES;
+};
+
+// quad q of this thread -> (row, first k of the quad) of an R x KC chunk
+template <bool KCONTIG, int R, int KC>
+__device__ __forceinline__ void quad_rk(int tid, int q, int& r, int& k) {
+  const int e = tid + 256 * q;
+  if (KCONTIG) { r = e / (KC / 4); k = 4 * (e % (KC / 4)); }
+  else { r = e % R; k = 4 * (e / R); }
+}
+
+// split four complex values into the four bf16 planes of one LDS row segment
+__device__ __forceinline__ void split_store(const Cplx<float> (&v)[4], __bf16* plane, int plane_sz,
+                                            int off) {
+  bf16x4 rh, rl, ih, il;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const __bf16 a = (__bf16)v[t].re, b = (__bf16)v[t].im;
+    rh[t] = a;
+    rl[t] = (__bf16)(v[t].re - (float)a);
+    ih[t] = b;
+    il[t] = (__bf16)(v[t].im - (float)b);
+  }
+  *reinterpret_cast<bf16x4*>(plane + off) = rh;
+  *reinterpret_cast<bf16x4*>(plane + plane_sz + off) = rl;
+  *reinterpret_cast<bf16x4*>(plane + 2 * plane_sz + off) = ih;
+  *reinterpret_cast<bf16x4*>(plane + 3 * plane_sz + off) = il;
+}
+
+template <int FLAGS, bool DEEP>
+__global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict__ segs,
+                                                       const GemmProb* __restrict__ probs,
+                                                       const GemmTile* __restrict__ tiles,
+                                                       const int64_t* __restrict__ rows,
+                                                       const float* __restrict__ A,
+                                                       const float* __restrict__ B,
+                                                       float* __restrict__ C,
+                                                       float* __restrict__ part,
+                                                       const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  typedef Bf3Cfg<FLAGS, DEEP> G;
+  constexpr int BM = G::BM, BN = G::BN, KC = G::KC, LD = G::LD, QA = G::QA, QB = G::QB;
+  __shared__ __attribute__((aligned(16))) char smem[G::SMEM];
+  __bf16* sA = reinterpret_cast<__bf16*>(smem);          // [4 parts][BM][LD]
+  __bf16* sB = sA + 4 * G::PLANE_A;                      // [4 parts][BN][LD]
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const GemmTile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+  const GemmProb P = probs[tile.prob];
+  const int i0 = tile.tm * BM, j0 = tile.tn * BN;
+  const int kfirst = DEEP ? tile.ks * KC : 0;
+  const int kstep = DEEP ? P.nks * KC : KC;
+
+  int64_t arow[QA];
+#pragma unroll
+  for (int q = 0; q < QA; ++q) {
+    int r, k;
+    quad_rk<G::A_KC, BM, KC>(tid, q, r, k);
+    arow[q] = 0;
+    if ((FLAGS & G_A_ROWMAP) && i0 + r < P.M) arow[q] = rows[P.rowmap + i0 + r];
+  }
+
+  Cplx<float> ra[QA][4], rb[QB][4];
+  auto load_chunk = [&](const GemmSeg& S, int k0) {
+    const int kc = min(KC, S.k - k0);
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      int r, k;
+      quad_rk<G::A_KC, BM, KC>(tid, q, r, k);
+      const int i = i0 + r;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        Cplx<float> v{0.f, 0.f};
+        if (i < P.M && k + t < kc) {
+          const int kk = k0 + k + t;
+          if (FLAGS & G_A_ROWMAP) v = ldc(A, arow[q] + S.a_off + kk);
+          else if (FLAGS & G_A_T) v = ldc(A, S.a_off + (int64_t)kk * S.lda + i);
+          else v = ldc(A, S.a_off + (int64_t)i * S.lda + kk);
+          if (FLAGS & G_A_CONJ) v.im = -v.im;
+        }
+        ra[q][t] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      int c, k;
+      quad_rk<G::B_KC, BN, KC>(tid, q, c, k);
+      const int j = j0 + c;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        Cplx<float> v{0.f, 0.f};
+        if (j < P.N && k + t < kc) {
+          const int kk = k0 + k + t;
+          v = (FLAGS & G_B_T) ? ldc(B, S.b_off + (int64_t)j * S.ldb + kk)
+                              : ldc(B, S.b_off + (int64_t)kk * S.ldb + j);
+        }
+        rb[q][t] = v;
+      }
+    }
+  };
+
+  f32x4 cre[2][2], cim[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      cre[x][y] = f32x4{0, 0, 0, 0};
+      cim[x][y] = f32x4{0, 0, 0, 0};
+    }
+  const int wr = DEEP ? 0 : (wave & 1) * 32;
+  const int wc = DEEP ? 0 : (wave >> 1) * 32;
+
+  int sg = 0, k0 = kfirst;
+  GemmSeg S;
+  while (sg < P.nseg) {
+    S = segs[P.seg0 + sg];
+    if (k0 < S.k) break;
+    ++sg;
+    k0 = kfirst;
+  }
+  if (sg < P.nseg) load_chunk(S, k0);
+  while (sg < P.nseg) {
+    const int kc = min(KC, S.k - k0);
+    __syncthreads();  // previous chunk fully consumed
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      int r, k;
+      quad_rk<G::A_KC, BM, KC>(tid, q, r, k);
+      split_store(ra[q], sA, G::PLANE_A, r * LD + k);
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      int c, k;
+      quad_rk<G::B_KC, BN, KC>(tid, q, c, k);
+      split_store(rb[q], sB, G::PLANE_B, c * LD + k);
+    }
+    __syncthreads();
+    k0 += kstep;
+    while (k0 >= S.k) {
+      if (++sg >= P.nseg) break;
+      S = segs[P.seg0 + sg];
+      k0 = kfirst;
+    }
+    if (sg < P.nseg) load_chunk(S, k0);
+    // k positions >= kc were staged as zeros, so whole 32-wide steps are exact
+    const int kbeg = DEEP ? wave * 32 : 0;
+    const int kend = DEEP ? min(kbeg + 32, kc) : kc;
+    for (int kb = kbeg; kb < kend; kb += 32) {
+      bf16x8 a[2][4], b[2][4];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          a[x][p] = *reinterpret_cast<const bf16x8*>(sA + p * G::PLANE_A + (wr + x * 16 + li) * LD + kb + 8 * lk);
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+          b[y][p] = *reinterpret_cast<const bf16x8*>(sB + p * G::PLANE_B + (wc + y * 16 + li) * LD + kb + 8 * lk);
+      // parts: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const bf16x8 nih = neg8(a[x][2]), nil = neg8(a[x][3]);
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          cre[x][y] = mfma_bf16(a[x][1], b[y][0], cre[x][y]);
+          cim[x][y] = mfma_bf16(a[x][1], b[y][2], cim[x][y]);
+          cre[x][y] = mfma_bf16(a[x][0], b[y][1], cre[x][y]);
+          cim[x][y] = mfma_bf16(a[x][0], b[y][3], cim[x][y]);
+          cre[x][y] = mfma_bf16(nil, b[y][2], cre[x][y]);
+          cim[x][y] = mfma_bf16(a[x][3], b[y][0], cim[x][y]);
+          cre[x][y] = mfma_bf16(nih, b[y][3], cre[x][y]);
+          cim[x][y] = mfma_bf16(a[x][2], b[y][1], cim[x][y]);
+          cre[x][y] = mfma_bf16(a[x][0], b[y][0], cre[x][y]);
+          cim[x][y] = mfma_bf16(a[x][0], b[y][2], cim[x][y]);
+          cre[x][y] = mfma_bf16(nih, b[y][2], cre[x][y]);
+          cim[x][y] = mfma_bf16(a[x][2], b[y][0], cim[x][y]);
+        }
+      }
+    }
+  }
+
+  if constexpr (DEEP) {
+    float (*red)[32][64] = reinterpret_cast<float (*)[32][64]>(smem);
+    __syncthreads();  // staging planes are no longer read
+    if (wave > 0) {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            red[wave - 1][((x * 2 + y) * 4 + r) * 2][lane] = cre[x][y][r];
+            red[wave - 1][((x * 2 + y) * 4 + r) * 2 + 1][lane] = cim[x][y][r];
+          }
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = ((x * 2 + y) * 4 + r) * 2;
+          cre[x][y][r] = ((cre[x][y][r] + red[0][e][lane]) + red[1][e][lane]) + red[2][e][lane];
+          cim[x][y][r] = ((cim[x][y][r] + red[0][e + 1][lane]) + red[1][e + 1][lane]) + red[2][e + 1][lane];
+        }
+    if (P.nks > 1) {
+      const int tiles_n = (P.N + BN - 1) / BN;
+      float* dst = part + 2 * ((int64_t)P.slot0 + ((int64_t)tile.tm * tiles_n + tile.tn) * P.nks + tile.ks) * 1024;
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            stc(dst, (x * 16 + 4 * lk + r) * 32 + y * 16 + li, cre[x][y][r], cim[x][y][r]);
+      return;
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + wr + x * 16 + 4 * lk + r;
+      if (i >= P.M) continue;
+      const int64_t rbase = (FLAGS & G_C_ROWMAP) ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int j = j0 + wc + y * 16 + li;
+        if (j < P.N) stc(C, rbase + j, cre[x][y][r], cim[x][y][r]);
+      }
+    }
+  }
+}
+
+hipError_t launch_gemm_bf16x3(const GemmStage& st, const float* A, const float* B, float* C,
+                              float* part, hipStream_t s, const int32_t* skip,
+                              const std::function<void()>& between) {
+  const int32_t nt = (int32_t)st.tiles.size();
+  if (nt == 0) return hipSuccess;
+  if (st.nslots > 0 && !part) return hipErrorInvalidValue;
+  if (st.flags & G_A_MIX) return hipErrorInvalidValue;
+  dim3 grid(nt), block(256);
+#define MRD_BF3_CASE(F, D)                                                                  \
+  if (st.flags == (F) && st.deep == (D)) {                                                  \
+    hipLaunchKernelGGL((gemm_bf3_kernel<F, D>), grid, block, 0, s, st.d_segs, st.d_probs,   \
+                       st.d_tiles, st.d_rows, A, B, C, part, skip);                         \
+    if (between) between();                                                                 \
+    if (D && !st.red_tiles.empty())                                                         \
+      hipLaunchKernelGGL((gemm_split_reduce_kernel<float, F>), dim3(st.red_tiles.size()),   \
+                         block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C, skip);\
+    return hipGetLastError();                                                               \
+  }
+  MRD_BF3_CASE(0, false)
+  MRD_BF3_CASE(G_A_T | G_A_CONJ, false)
+  MRD_BF3_CASE(G_A_ROWMAP | G_B_T, false)
+  MRD_BF3_CASE(G_A_CONJ, false)
+  MRD_BF3_CASE(G_B_T | G_C_ROWMAP, true)
+#undef MRD_BF3_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mrd

@@ -116,6 +116,10 @@ template <typename T>
 hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* part, hipStream_t s,
                        const int32_t* skip = nullptr,
                        const std::function<void()>& between = std::function<void()>());
+// BF16x3 form of launch_gemm on FP32 operands (gemm_bf16x3.hip); same tables and tiles.
+hipError_t launch_gemm_bf16x3(const GemmStage& st, const float* A, const float* B, float* C,
+                              float* part, hipStream_t s, const int32_t* skip = nullptr,
+                              const std::function<void()>& between = std::function<void()>());
 template <typename T>
 hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s,
                       const int32_t* skip = nullptr);

@@ -48,3 +48,18 @@ def max_rel(got: dict, ref: dict, keys):
     num = max((np.abs(got[k] - ref.get(k, 0)).max() for k, _ in keys if got[k].size), default=0.0)
     den = max((np.abs(ref[k]).max() for k, _ in keys if k in ref and ref[k].size), default=1.0)
     return num / den
+
+
+_problems = {}
+
+
+def problem(name):
+    """(wl, L, W1, W2, R, theta, keys, mpo) of a preset window, built once per process by
+    the oracle from the seeded workload."""
+    if name not in _problems:
+        import workloads
+        from oracle import synth
+        wl = workloads.preset(name)
+        L, W1, W2, R, th, keys, mpo = synth.window_problem(wl)
+        _problems[name] = (wl, L, W1, W2, R, th, keys, mpo)
+    return _problems[name]

@@ -9,7 +9,6 @@ import pytest
 import workloads
 from oracle import blocksparse as bs
 from oracle import lanczos as olz
-from oracle import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -18,18 +17,11 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import paper_1512_03318_amd as pk  # noqa: E402
-from gpu_helpers import WindowGPU, max_rel, mpo_site, to_dev  # noqa: E402
+from gpu_helpers import WindowGPU, max_rel, mpo_site, problem, to_dev  # noqa: E402
 
 CASES = ["ly3_chi16", "ly4_chi64", "ly6_chi200"]
-_cache = {}
-
-
-def problem(name):
-    if name not in _cache:
-        wl = workloads.preset(name)
-        L, W1, W2, R, th, keys, mpo = synth.window_problem(wl)
-        _cache[name] = (wl, L, W1, W2, R, th, keys, mpo)
-    return _cache[name]
+# FP32: 2^-24 per product; BF16x3: three bf16 products per real product, about 2^-17
+PRECS = [(pk.DM_FP64, 1e-12), (pk.DM_FP32, 2e-5), (pk.DM_BF16X3, 1e-4)]
 
 
 def say(*a):
@@ -38,7 +30,7 @@ def say(*a):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("prec,tol", [(pk.DM_FP64, 1e-12), (pk.DM_FP32, 2e-5)])
+@pytest.mark.parametrize("prec,tol", PRECS)
 def test_heff_apply_parity(name, prec, tol):
     wl, L, W1, W2, R, th, keys, mpo = problem(name)
     say(f"heff_apply {name} prec={prec} n={sum(m*n for _, (m, n) in keys)}")
@@ -70,7 +62,7 @@ def test_lanczos_parity_fp64(name):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("prec,tol", [(pk.DM_FP64, 1e-12), (pk.DM_FP32, 2e-5)])
+@pytest.mark.parametrize("prec,tol", PRECS)
 def test_env_updates_parity(name, prec, tol):
     wl, L, W1, W2, R, th, keys, mpo = problem(name)
     j, ly = wl.j, wl.ly

@@ -189,6 +189,27 @@ def test_lanczos_full_dimension_matches_library():
     assert np.linalg.eigvalsh(t)[-1] <= lam[-1] + 1e-12       # interlacing at the top
 
 
+def test_restarted_lanczos_ground_state():
+    """Restarted Lanczos converges to LAPACK's lowest eigenpair (n = 300 >> 30 steps),
+    including the effective Hamiltonian of a small window against its dense matrix."""
+    rng = np.random.default_rng(3)
+    n = 300
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    h = (a + a.conj().T) / 2
+    e, x, res, nmv = lanczos.ground_state(lambda v: h @ v, rng.standard_normal(n) + 0j, tol_res=1e-11)
+    lam, vec = np.linalg.eigh(h)
+    assert nmv > 30 and abs(e - lam[0]) < 1e-11 and 1 - abs(np.vdot(vec[:, 0], x)) < 1e-12
+    assert np.linalg.norm(h @ x - e * x) == pytest.approx(res, rel=1e-6)
+    wl = workloads.preset("ly3_chi16")
+    L, W1, W2, R, th, keys, _ = synth.window_problem(wl)
+    mv = lambda v: bs.flatten(bs.heff_apply(L, W1, W2, R, bs.unflatten(v, keys)), keys)
+    dim = sum(m * n for _, (m, n) in keys)
+    H = np.array([mv(np.eye(dim)[i]) for i in range(dim)]).T
+    lam = np.linalg.eigvalsh((H + H.conj().T) / 2)
+    e, x, res, _ = lanczos.ground_state(mv, bs.flatten(th, keys), tol_res=1e-12)
+    assert abs(e - lam[0]) < 1e-10 * abs(lam[0])
+
+
 def test_lanczos_breakdown_on_eigenvector():
     h = np.diag(np.arange(6, dtype=float)).astype(complex)
     v = np.zeros(6, complex)
