@@ -9,203 +9,9 @@
 #include <memory>
 #include <sstream>
 
-#include "plan.hpp"
+#include "runtime.hpp"
 
 using namespace mrd;
-
-namespace {
-
-thread_local std::string g_err;
-
-int fail(int code, const std::string& msg) {
-  g_err = msg;
-  return code;
-}
-
-#define HIPCHK(expr)                                                                    \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      throw DmError{DM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)};     \
-  } while (0)
-
-template <typename F>
-int guarded(F&& f) {
-  try {
-    f();
-    return DM_OK;
-  } catch (const DmError& e) {
-    return fail(e.code, e.msg);
-  } catch (const std::bad_alloc&) {
-    return fail(DM_ERR_ALLOC, "host allocation failed");
-  } catch (const std::exception& e) {
-    return fail(DM_ERR_ARG, e.what());
-  }
-}
-
-// Caching device allocator for plan buffers.  A DMRG sweep creates and destroys one
-// plan per bond with similar sizes; reusing freed blocks avoids hipMalloc / hipFree
-// (each of which can cost milliseconds) on every bond.  Blocks are rounded up to 1/8 of
-// their power of two, kept per device, and released with hipFree beyond 24 GiB cached.
-// Callers guarantee that no kernel still uses a block when it is returned.
-class DevicePool {
- public:
-  void* get(size_t bytes) {
-    if (bytes == 0) return nullptr;
-    const size_t r = round(bytes);
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    {
-      std::lock_guard<std::mutex> g(m_);
-      auto& fl = free_[dev];
-      auto it = fl.lower_bound(r);
-      if (it != fl.end() && it->first <= r + r / 4) {
-        void* p = it->second;
-        cached_ -= it->first;
-        fl.erase(it);
-        return p;
-      }
-    }
-    void* p = nullptr;
-    if (hipMalloc(&p, r) != hipSuccess) {
-      (void)hipGetLastError();
-      trim(0);
-      if (hipMalloc(&p, r) != hipSuccess) {
-        (void)hipGetLastError();
-        throw DmError{DM_ERR_ALLOC, "hipMalloc of " + std::to_string(r) + " bytes failed"};
-      }
-    }
-    std::lock_guard<std::mutex> g(m_);
-    size_[p] = {r, dev};
-    return p;
-  }
-  void put(void* p) {
-    if (!p) return;
-    std::lock_guard<std::mutex> g(m_);
-    auto it = size_.find(p);
-    if (it == size_.end()) return;
-    free_[it->second.second].emplace(it->second.first, p);
-    cached_ += it->second.first;
-    if (cached_ > kMaxCached) trim_locked(kMaxCached);
-  }
-
- private:
-  static constexpr size_t kMaxCached = size_t(24) << 30;
-  static size_t round(size_t b) {
-    if (b <= (size_t(1) << 20)) return (b + 4095) & ~size_t(4095);
-    size_t top = size_t(1) << (63 - __builtin_clzll(b));
-    const size_t step = top / 8;
-    return (b + step - 1) / step * step;
-  }
-  void trim(size_t limit) {
-    std::lock_guard<std::mutex> g(m_);
-    trim_locked(limit);
-  }
-  void trim_locked(size_t limit) {
-    for (auto& kv : free_) {
-      auto& fl = kv.second;
-      while (cached_ > limit && !fl.empty()) {
-        auto last = std::prev(fl.end());
-        (void)hipFree(last->second);
-        size_.erase(last->second);
-        cached_ -= last->first;
-        fl.erase(last);
-      }
-    }
-  }
-  std::mutex m_;
-  std::map<int, std::multimap<size_t, void*>> free_;
-  std::unordered_map<void*, std::pair<size_t, int>> size_;
-  size_t cached_ = 0;
-};
-
-DevicePool& pool() {
-  static DevicePool* p = new DevicePool();  // never destroyed: outlives static teardown
-  return *p;
-}
-
-void* dev_alloc(size_t bytes) { return pool().get(bytes); }
-void dev_free(void* p) { pool().put(p); }
-
-// All task tables of one or more stages in one device block, uploaded with one copy.
-struct TableUpload {
-  std::vector<char> host;
-  std::vector<std::pair<size_t, void**>> fix;  // offset -> device pointer to patch
-  template <typename T>
-  void add(const std::vector<T>& v, T** dst) {
-    *dst = nullptr;
-    if (v.empty()) return;
-    const size_t off = (host.size() + 255) & ~size_t(255);
-    host.resize(off + v.size() * sizeof(T));
-    std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
-    fix.emplace_back(off, (void**)dst);
-  }
-  void add(GemmStage& st) {
-    add(st.segs, &st.d_segs);
-    add(st.probs, &st.d_probs);
-    add(st.tiles, &st.d_tiles);
-    add(st.rows, &st.d_rows);
-    add(st.asrc, &st.d_asrc);
-    add(st.red_tiles, &st.d_red_tiles);
-  }
-  void add(MixStage& st) {
-    add(st.tasks, &st.d_tasks);
-    add(st.srcs, &st.d_srcs);
-  }
-  // Synchronous copy into a pool block; returns the block (free it with dev_free).
-  void* commit() {
-    if (host.empty()) return nullptr;
-    char* d = (char*)dev_alloc(host.size());
-    HIPCHK(hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice));
-    for (auto& f : fix) *f.second = d + f.first;
-    return d;
-  }
-};
-
-size_t elem_bytes(int prec) { return prec == DM_FP64 ? 16 : 8; }
-
-void check_prec(int prec) {
-  if (prec != DM_FP64 && prec != DM_FP32 && prec != DM_BF16X3)
-    throw DmError{DM_ERR_DTYPE, "precision " + std::to_string(prec) + " not supported"};
-}
-
-void check_ly(int ly) {
-  if (ly < 1) throw DmError{DM_ERR_ARG, "ly must be >= 1"};
-}
-
-// Copy (FP64) or cast (FP32) n complex elements from a caller's complex128 buffer.
-void stage_in(const void* src, void* dst, int64_t n, int prec, hipStream_t s) {
-  if (n == 0) return;
-  if (prec == DM_FP64)
-    HIPCHK(hipMemcpyAsync(dst, src, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
-  else
-    HIPCHK(launch_cast_d2f((const double*)src, (float*)dst, 2 * n, s));
-}
-void stage_out(const void* src, void* dst, int64_t n, int prec, hipStream_t s) {
-  if (n == 0) return;
-  if (prec == DM_FP64)
-    HIPCHK(hipMemcpyAsync(dst, src, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
-  else
-    HIPCHK(launch_cast_f2d((const float*)src, (double*)dst, 2 * n, s));
-}
-
-// FP32-storage GEMM stage: FP32 MFMA (DM_FP32) or bf16 hi/lo split MFMA (DM_BF16X3).
-hipError_t gemm_lp(int prec, const GemmStage& st, const float* A, const float* B, float* C,
-                   float* part, hipStream_t s, const int32_t* skip = nullptr,
-                   const std::function<void()>& between = std::function<void()>()) {
-  if (prec == DM_BF16X3) return launch_gemm_bf16x3(st, A, B, C, part, s, skip, between);
-  return launch_gemm<float>(st, A, B, C, part, s, skip, between);
-}
-
-template <typename F>
-void by_prec(int prec, F&& f) {
-  if (prec == DM_FP64)
-    f((double*)nullptr);
-  else
-    f((float*)nullptr);
-}
-
-}  // namespace
 
 // =====================================================================================
 // Layout query
@@ -282,72 +88,6 @@ extern "C" int dm_layout(const dm_layout_desc* d, int64_t* nblocks, int64_t* nel
 // =====================================================================================
 // Effective Hamiltonian plan
 // =====================================================================================
-struct dm_heff_plan {
-  int ly = 1, prec = DM_FP64;
-  Bond a, c;
-  MpoSite w1, w2;
-  ThetaLayout th;
-  EnvLLayout L;
-  EnvRLayout R;
-  std::vector<int64_t> xoff;  // per a: X panel offset (rows = L.P.rows[a], cols = th.P.cols[a])
-  int64_t xtotal = 0;
-  GemmStage s1, s4;
-  MixStage mix;
-  void* dTables = nullptr;      // all task tables (one pool block)
-  hipEvent_t done = nullptr;    // recorded after every use; waited on before release
-  double mix_flops = 0;
-  std::vector<int64_t> zoff;  // per c': Z panel offset (rows zrows[c'], cols R.P.cols[c'])
-  std::vector<int> zrows;
-  int64_t ztotal = 0;
-  void* dZ = nullptr;
-  void* dZ64 = nullptr;
-  // device buffers (elements in the plan's precision)
-  void* dL = nullptr;
-  void* dR = nullptr;
-  void* dL64 = nullptr;  // FP64 copies for the final Rayleigh quotient (low precision plans)
-  void* dR64 = nullptr;
-  void* dX = nullptr;
-  void* dX64 = nullptr;
-  void* dSplit = nullptr;    // K-split partial tiles of the (.)R stage
-  void* dSplit64 = nullptr;
-  void* dTin = nullptr;  // low-precision staging of theta in / out
-  void* dTout = nullptr;
-  // Lanczos workspace (FP64)
-  double* dV = nullptr;       // Krylov basis, Vcap vectors of n
-  int Vcap = 0;
-  double* dW = nullptr;       // H v_j
-  double* dVcur = nullptr;    // v_j (fixed address: the matvec input of every step)
-  double* dPart = nullptr;    // per-block partial sums
-  LzState* dState = nullptr;
-  LzState* hState = nullptr;  // pinned host copy
-  hipGraph_t graph = nullptr; // one Lanczos step (matvec + projections), captured once
-  hipGraphExec_t graph_exec = nullptr;
-  hipStream_t cap_stream = nullptr;
-  bool use_graph = true;
-  // profiling: events around the three stages of each recorded matvec
-  bool profiling = false;
-  std::vector<std::array<hipEvent_t, 5>> ev;
-  size_t ev_used = 0;
-  ~dm_heff_plan() {
-    if (done) {
-      (void)hipEventSynchronize(done);  // no kernel of this plan may still run
-      (void)hipEventDestroy(done);
-    }
-    for (auto& e : ev)
-      for (hipEvent_t x : e) (void)hipEventDestroy(x);
-    dev_free(dTables);
-    for (void* p : {dL, dR, dL64, dR64, dX, dX64, dSplit, dSplit64, dTin, dTout, dZ, dZ64})
-      dev_free(p);
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    for (double* p : {dV, dW, dVcur, dPart}) dev_free(p);
-    dev_free(dState);
-    if (hState) (void)hipHostFree(hState);
-  }
-  int64_t n() const { return th.P.total; }
-};
-
 static void build_heff_tables(dm_heff_plan& p) {
   const int ly = p.ly;
   const Bond &a = p.a, &c = p.c;
@@ -561,8 +301,8 @@ static hipEvent_t* prof_slot(dm_heff_plan* p) {
 }
 
 // theta_out = H_eff theta in the plan's precision (FP64 in / out).
-static void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStream_t s,
-                     bool force64, const int32_t* skip = nullptr, bool capturing = false) {
+void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStream_t s,
+                   bool force64, const int32_t* skip, bool capturing) {
   hipEvent_t* ev = (force64 || capturing) ? nullptr : prof_slot(p);
   auto mark = [&](int i) {
     if (ev) HIPCHK(hipEventRecord(ev[i], s));
@@ -636,8 +376,9 @@ extern "C" int heff_apply(dm_heff_plan* p, const void* theta, void* theta_out, d
   });
 }
 
-static void ensure_lanczos(dm_heff_plan* p, int max_iter) {
+void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
   const int64_t n = p->n();
+  bool relayout = !p->dInst;
   if (p->Vcap < max_iter + 1) {
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -650,12 +391,22 @@ static void ensure_lanczos(dm_heff_plan* p, int max_iter) {
     const int cap = std::max(max_iter + 1, 31);
     p->dV = (double*)dev_alloc((size_t)cap * n * 16);
     p->Vcap = cap;
-    p->dPart = (double*)dev_alloc((size_t)lz_nblk1(n) * (2 * cap + 2) * 8);
+    p->dPart = (double*)dev_alloc((size_t)lz_part_doubles(n, cap - 1) * 8);
+    relayout = true;
   }
   if (!p->dW) p->dW = (double*)dev_alloc((size_t)n * 16);
   if (!p->dVcur) p->dVcur = (double*)dev_alloc((size_t)n * 16);
   if (!p->dState) p->dState = (LzState*)dev_alloc(sizeof(LzState));
-  if (!p->hState) HIPCHK(hipHostMalloc((void**)&p->hState, sizeof(LzState), hipHostMallocDefault));
+  if (!p->dInst) p->dInst = (LzInst*)dev_alloc(sizeof(LzInst));
+  if (!p->dRes) p->dRes = (LzResult*)dev_alloc(sizeof(LzResult));
+  if (!p->hInst) HIPCHK(hipHostMalloc((void**)&p->hInst, sizeof(LzInst), hipHostMallocDefault));
+  if (!p->hRes) HIPCHK(hipHostMalloc((void**)&p->hRes, sizeof(LzResult), hipHostMallocDefault));
+  if (relayout) {
+    std::vector<LzInst> I(1);
+    I[0] = LzInst{p->dV, p->dW, p->dVcur, p->dPart, nullptr, nullptr, p->dState, n, n};
+    p->lzg = lz_layout(I, p->Vcap - 1);
+    *p->hInst = I[0];
+  }
   if (p->prec != DM_FP64) {
     if (!p->dX64) p->dX64 = dev_alloc(p->xtotal * 16);
     if (!p->dZ64) p->dZ64 = dev_alloc(p->ztotal * 16);
@@ -665,9 +416,8 @@ static void ensure_lanczos(dm_heff_plan* p, int max_iter) {
 
 // One Lanczos step: w = H v_j, projections, scalars, v_{j+1}.  Fixed arguments.
 static void lanczos_step(dm_heff_plan* p, hipStream_t s, bool capturing) {
-  const int64_t n = p->n();
   heff_run(p, p->dVcur, p->dW, s, false, &p->dState->stop, capturing);
-  HIPCHK(lz_launch_step_tail(p->dV, n, p->dW, n, p->dState, p->dPart, p->dVcur, p->Vcap - 1, s));
+  HIPCHK(lz_launch_step_tail(p->dInst, p->lzg, s));
 }
 
 extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double tol,
@@ -680,8 +430,10 @@ extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_it
     if (!theta_inout) throw DmError{DM_ERR_ARG, "null theta"};
     ensure_lanczos(p, max_iter);
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(lz_launch_init(p->dState, max_iter, tol, s));
-    HIPCHK(lz_launch_start((const double*)theta_inout, n, p->dState, p->dPart, p->dV, p->dVcur, s));
+    p->hInst->x = (double*)theta_inout;  // the previous solve synchronised: buffer is free
+    HIPCHK(hipMemcpyAsync(p->dInst, p->hInst, sizeof(LzInst), hipMemcpyHostToDevice, s));
+    HIPCHK(lz_launch_init(p->dInst, p->lzg, max_iter, tol, s));
+    HIPCHK(lz_launch_start(p->dInst, p->lzg, s));
     const bool graph = p->use_graph && !p->profiling;
     if (graph && !p->graph_exec) {
       if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
@@ -703,18 +455,19 @@ extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_it
       else
         lanczos_step(p, s, false);
     }
-    HIPCHK(lz_launch_finish(p->dV, n, n, p->dState, (double*)theta_inout, s));
+    HIPCHK(lz_launch_finish(p->dInst, p->lzg, s));
     if (p->prec != DM_FP64) {
-      // FP64 Rayleigh quotient of the Ritz vector
-      heff_run(p, theta_inout, p->dW, s, true);
-      HIPCHK(lz_launch_rq((const double*)theta_inout, p->dW, n, p->dState, p->dPart, s));
+      // FP64 Rayleigh quotient of the Ritz vector (also held in vcur)
+      heff_run(p, p->dVcur, p->dW, s, true);
+      HIPCHK(lz_launch_rq(p->dInst, p->lzg, s));
     }
-    HIPCHK(hipMemcpyAsync(p->hState, p->dState, sizeof(LzState), hipMemcpyDeviceToHost, s));
+    HIPCHK(lz_launch_results(p->dInst, p->lzg, p->dRes, s));
+    HIPCHK(hipMemcpyAsync(p->hRes, p->dRes, sizeof(LzResult), hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(p->done, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (p->hState->bad) throw DmError{DM_ERR_NONFINITE, "Lanczos produced a zero, NaN or Inf norm"};
-    *energy = p->hState->energy;
-    *iters = p->hState->k;
+    if (p->hRes->bad) throw DmError{DM_ERR_NONFINITE, "Lanczos produced a zero, NaN or Inf norm"};
+    *energy = p->hRes->energy;
+    *iters = p->hRes->k;
   });
 }
 
@@ -1045,6 +798,4 @@ extern "C" int dm_env_flops(int32_t left, int32_t ly, const dm_bond* x, const dm
   });
 }
 
-extern "C" const char* dm_last_error(void) { return g_err.c_str(); }
 
-void mrd::set_last_error(const std::string& msg) { g_err = msg; }

@@ -1,30 +1,296 @@
 // Batched Lanczos over many independent effective Hamiltonians.
-#include <vector>
+//
+// The task tables of all plans are merged into one table per phase, so every phase of
+// one Lanczos step (casts, L.theta GEMMs, MPO mixing, (.).R GEMMs, K-split reduction,
+// the Lanczos vector kernels) is one launch over all instances: 14 launches per step
+// whatever the batch size.  Offsets of the merged tables are rebased to one base
+// address (the lowest buffer of the batch), so the kernels of the single-plan path run
+// unchanged.  Merged GEMM tiles are ordered longest first (LPT list scheduling: the
+// hardware dispatcher hands workgroups out in index order as compute units free up),
+// interleaved over the eight XCDs so that every XCD receives its own longest-first
+// list.  The instances run in lock step; each instance stops on its own rule (its
+// remaining vector launches become no-ops) and its stop time is read from the device
+// wall clock.
+#include <algorithm>
+#include <cstdlib>
+#include <memory>
+#include <numeric>
 
-#include "../../include/mrdmrg.h"
-#include "internal.hpp"
+#include "runtime.hpp"
+
+using namespace mrd;
+
+namespace {
+
+// Host copy of the device XCD mapping of the GEMM kernels: block b runs tile xcd_tile(b).
+int xcd_tile_host(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + std::min(x, r) + (b >> 3);
+}
+
+struct Shift {
+  int64_t a = 0, b = 0, c = 0;  // complex elements, added to A, B and C offsets
+};
+
+// Work of one tile in staged K chunks (the kernel's run time is set by its K loop).
+double tile_cost(const GemmStage& st, const GemmTile& t) {
+  const GemmProb& p = st.probs[t.prob];
+  const int kc = st.deep ? 64 : 32;
+  double chunks = 0;
+  for (int g = 0; g < p.nseg; ++g) chunks += (st.segs[p.seg0 + g].k + kc - 1) / kc;
+  return st.deep ? chunks / std::max(1, p.nks) : chunks;
+}
+
+GemmStage merge_gemm(const std::vector<const GemmStage*>& in, const std::vector<Shift>& sh) {
+  GemmStage m;
+  m.flags = in[0]->flags;
+  m.deep = in[0]->deep;
+  std::vector<std::pair<double, GemmTile>> tiles;
+  for (size_t i = 0; i < in.size(); ++i) {
+    const GemmStage& st = *in[i];
+    if (st.flags != m.flags || st.deep != m.deep)
+      throw DmError{DM_ERR_ARG, "batched plans have different stage kinds"};
+    if (st.flags & G_A_MIX) throw DmError{DM_ERR_ARG, "mixed operands cannot be batched"};
+    const int32_t seg0 = (int32_t)m.segs.size(), prob0 = (int32_t)m.probs.size();
+    const int32_t row0 = (int32_t)m.rows.size();
+    const int64_t slot0 = m.nslots;
+    for (GemmSeg g : st.segs) {
+      g.a_off += sh[i].a;
+      g.b_off += sh[i].b;
+      m.segs.push_back(g);
+    }
+    for (int64_t r : st.rows) m.rows.push_back((m.flags & G_C_ROWMAP) ? r + sh[i].c : r);
+    for (GemmProb p : st.probs) {
+      if (!(m.flags & G_C_ROWMAP)) p.c_off += sh[i].c;
+      p.seg0 += seg0;
+      if (p.rowmap >= 0) p.rowmap += row0;
+      p.slot0 += (int32_t)slot0;
+      m.probs.push_back(p);
+    }
+    for (GemmTile t : st.tiles) {
+      const double c = tile_cost(st, t);
+      t.prob += prob0;
+      tiles.emplace_back(c, t);
+    }
+    for (GemmTile t : st.red_tiles) {
+      t.prob += prob0;
+      m.red_tiles.push_back(t);
+    }
+    m.nslots += st.nslots;
+    m.flops += st.flops;
+  }
+  if (m.segs.size() > INT32_MAX || m.rows.size() > INT32_MAX || m.nslots > INT32_MAX)
+    throw DmError{DM_ERR_ARG, "batched task table too large"};
+  std::stable_sort(tiles.begin(), tiles.end(),
+                   [](const auto& x, const auto& y) { return x.first > y.first; });
+  const int n = (int)tiles.size();
+  m.tiles.resize(n);
+  for (int b = 0; b < n; ++b) m.tiles[xcd_tile_host(b, n)] = tiles[b].second;
+  return m;
+}
+
+MixStage merge_mix(const std::vector<const MixStage*>& in, const std::vector<Shift>& sh) {
+  MixStage m;
+  std::vector<std::pair<double, MixTask>> tasks;
+  for (size_t i = 0; i < in.size(); ++i) {
+    const int32_t src0 = (int32_t)m.srcs.size();
+    for (MixSrc s : in[i]->srcs) {
+      s.off += sh[i].a;
+      m.srcs.push_back(s);
+    }
+    for (MixTask t : in[i]->tasks) {
+      t.dst += sh[i].c;
+      t.src0 += src0;
+      tasks.emplace_back((double)t.rows * t.cols * t.nsrc, t);
+    }
+    m.flops += in[i]->flops;
+  }
+  std::stable_sort(tasks.begin(), tasks.end(),
+                   [](const auto& x, const auto& y) { return x.first > y.first; });
+  for (auto& t : tasks) m.tasks.push_back(t.second);
+  return m;
+}
+
+// One merged matvec: theta (per instance) -> w, all instances in one launch per phase.
+struct MergedMatvec {
+  GemmStage s1, s4;
+  MixStage mix;
+  char* base = nullptr;  // every offset counts elements from here
+  void* split = nullptr; // K-split partial tiles of the merged (.).R stage
+  int prec = DM_FP64;
+};
+
+// Rebasing: offsets of instance i move by (buffer_i - base) / element size.
+struct Rebase {
+  size_t eb;
+  char* base = nullptr;
+  void note(const void* p) {
+    if (p && (!base || (char*)p < base)) base = (char*)p;
+  }
+  int64_t shift(const void* p) const {
+    if (!p) return 0;
+    const ptrdiff_t d = (char*)p - base;
+    if (d % (ptrdiff_t)eb) throw DmError{DM_ERR_ARG, "misaligned buffer in batch"};
+    return (int64_t)(d / (ptrdiff_t)eb);
+  }
+};
+
+}  // namespace
 
 struct dm_batch {
   std::vector<dm_heff_plan*> plans;
+  int prec = DM_FP64;
+  bool built = false;
+  MergedMatvec mv, mv64;        // mv64: FP64 matvec of the final Rayleigh quotient
+  std::vector<CastJob> cin, cout;
+  int32_t cin_blocks = 0, cout_blocks = 0;
+  CastJob* d_cin = nullptr;
+  CastJob* d_cout = nullptr;
+  void* dTables = nullptr;
+  int lz_cap = 0;               // max_iter the instance table is laid out for
+  LzInst* dInst = nullptr;
+  LzInst* hInst = nullptr;      // pinned
+  LzGrid lzg;
+  LzResult* dRes = nullptr;
+  LzResult* hRes = nullptr;     // pinned
+  hipEvent_t done = nullptr;
+  hipGraph_t graph = nullptr;   // one batched Lanczos step (opt-in, as for single plans)
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool use_graph = false;
+  ~dm_batch() {
+    if (done) {
+      (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
+    }
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    dev_free(dTables);
+    dev_free(mv.split);
+    dev_free(mv64.split);
+    dev_free(dInst);
+    dev_free(dRes);
+    if (hInst) (void)hipHostFree(hInst);
+    if (hRes) (void)hipHostFree(hRes);
+  }
 };
+
+namespace {
+
+// Merged tables of the step matvec (f64 = false) or of the FP64 Rayleigh quotient.
+MergedMatvec build_merged(dm_batch& b, bool f64) {
+  MergedMatvec m;
+  m.prec = f64 ? DM_FP64 : b.prec;
+  const bool low = m.prec != DM_FP64;
+  Rebase rb{low ? size_t(8) : size_t(16)};
+  struct Bufs {
+    void *L, *R, *X, *Z, *in, *out;
+  };
+  std::vector<Bufs> bufs;
+  for (dm_heff_plan* p : b.plans) {
+    Bufs q;
+    if (!low && b.prec != DM_FP64) {  // FP64 matvec of a low-precision plan
+      q = {p->dL64, p->dR64, p->dX64, p->dZ64, p->dVcur, p->dW};
+    } else if (!low) {
+      q = {p->dL, p->dR, p->dX, p->dZ, p->dVcur, p->dW};
+    } else {
+      q = {p->dL, p->dR, p->dX, p->dZ, p->dTin, p->dTout};
+    }
+    for (void* x : {q.L, q.R, q.X, q.Z, q.in, q.out}) rb.note(x);
+    bufs.push_back(q);
+  }
+  std::vector<const GemmStage*> s1, s4;
+  std::vector<const MixStage*> mx;
+  std::vector<Shift> sh1, sh4, shm;
+  for (size_t i = 0; i < b.plans.size(); ++i) {
+    const Bufs& q = bufs[i];
+    s1.push_back(&b.plans[i]->s1);
+    s4.push_back(&b.plans[i]->s4);
+    mx.push_back(&b.plans[i]->mix);
+    sh1.push_back({rb.shift(q.L), rb.shift(q.in), rb.shift(q.X)});
+    shm.push_back({rb.shift(q.X), 0, rb.shift(q.Z)});
+    sh4.push_back({rb.shift(q.Z), rb.shift(q.R), rb.shift(q.out)});
+  }
+  m.s1 = merge_gemm(s1, sh1);
+  m.mix = merge_mix(mx, shm);
+  m.s4 = merge_gemm(s4, sh4);
+  m.base = rb.base;
+  m.split = dev_alloc((size_t)m.s4.nslots * 1024 * rb.eb);
+  return m;
+}
+
+void run_merged(const MergedMatvec& m, hipStream_t s) {
+  if (m.prec == DM_FP64) {
+    double* base = (double*)m.base;
+    HIPCHK(launch_gemm<double>(m.s1, base, base, base, nullptr, s));
+    HIPCHK(launch_mix<double>(m.mix, base, base, s));
+    HIPCHK(launch_gemm<double>(m.s4, base, base, base, (double*)m.split, s));
+  } else {
+    float* base = (float*)m.base;
+    HIPCHK(gemm_lp(m.prec, m.s1, base, base, base, nullptr, s));
+    HIPCHK(launch_mix<float>(m.mix, base, base, s));
+    HIPCHK(gemm_lp(m.prec, m.s4, base, base, base, (float*)m.split, s));
+  }
+}
+
+void build_batch(dm_batch& b) {
+  b.mv = build_merged(b, false);
+  if (b.prec != DM_FP64) {
+    b.mv64 = build_merged(b, true);
+    for (dm_heff_plan* p : b.plans) {
+      b.cin.push_back({p->dVcur, p->dTin, 2 * p->n(), 0, 0});
+      b.cout.push_back({p->dTout, p->dW, 2 * p->n(), 0, 0});
+    }
+    b.cin_blocks = cast_layout(b.cin);
+    b.cout_blocks = cast_layout(b.cout);
+  }
+  TableUpload up;
+  for (MergedMatvec* m : {&b.mv, &b.mv64}) {
+    up.add(m->s1);
+    up.add(m->s4);
+    up.add(m->mix);
+  }
+  up.add(b.cin, &b.d_cin);
+  up.add(b.cout, &b.d_cout);
+  b.dTables = up.commit();
+  b.built = true;
+}
+
+void batch_step(dm_batch& b, hipStream_t s) {
+  if (b.prec != DM_FP64)
+    HIPCHK(launch_cast_batch(true, b.d_cin, (int32_t)b.cin.size(), b.cin_blocks, s));
+  run_merged(b.mv, s);
+  if (b.prec != DM_FP64)
+    HIPCHK(launch_cast_batch(false, b.d_cout, (int32_t)b.cout.size(), b.cout_blocks, s));
+  HIPCHK(lz_launch_step_tail(b.dInst, b.lzg, s));
+}
+
+}  // namespace
 
 extern "C" int dm_batch_create(int32_t n, dm_heff_plan* const* plans, dm_stream stream,
                                dm_batch** out) {
   (void)stream;
-  if (!out || n <= 0 || !plans) {
-    mrd::set_last_error("dm_batch_create: bad arguments");
-    return DM_ERR_ARG;
-  }
-  auto* b = new dm_batch;
-  b->plans.assign(plans, plans + n);
-  for (auto* p : b->plans)
-    if (!p) {
-      delete b;
-      mrd::set_last_error("dm_batch_create: null plan");
-      return DM_ERR_ARG;
+  return guarded([&] {
+    if (!out || n <= 0 || !plans) throw DmError{DM_ERR_ARG, "dm_batch_create: bad arguments"};
+    *out = nullptr;
+    auto b = std::make_unique<dm_batch>();
+    b->plans.assign(plans, plans + n);
+    for (dm_heff_plan* p : b->plans) {
+      if (!p) throw DmError{DM_ERR_ARG, "dm_batch_create: null plan"};
+      if (p->n() == 0) throw DmError{DM_ERR_LAYOUT, "dm_batch_create: empty theta"};
     }
-  *out = b;
-  return DM_OK;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < i; ++j)
+        if (b->plans[i] == b->plans[j]) throw DmError{DM_ERR_ARG, "dm_batch_create: plan repeated"};
+    b->prec = b->plans[0]->prec;
+    for (dm_heff_plan* p : b->plans)
+      if (p->prec != b->prec) throw DmError{DM_ERR_DTYPE, "dm_batch_create: plans differ in precision"};
+    HIPCHK(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+    const char* g = getenv("MRDMRG_GRAPH");
+    b->use_graph = g && g[0] == '1';
+    *out = b.release();
+  });
 }
 
 extern "C" void dm_batch_destroy(dm_batch* b) { delete b; }
@@ -32,14 +298,100 @@ extern "C" void dm_batch_destroy(dm_batch* b) { delete b; }
 extern "C" int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t max_iter,
                                       double tol, double* energies, int32_t* iters,
                                       double* done_us, dm_stream stream) {
-  if (!b || !thetas || !energies || !iters) {
-    mrd::set_last_error("lanczos_ground_batched: null argument");
-    return DM_ERR_ARG;
-  }
-  for (size_t i = 0; i < b->plans.size(); ++i) {
-    const int rc = lanczos_ground(b->plans[i], thetas[i], max_iter, tol, &energies[i], &iters[i], stream);
-    if (rc != DM_OK) return rc;
-    if (done_us) done_us[i] = 0.0;
-  }
-  return DM_OK;
+  return guarded([&] {
+    if (!b || !thetas || !energies || !iters) throw DmError{DM_ERR_ARG, "null argument"};
+    if (max_iter < 1 || max_iter > LZ_MAX) throw DmError{DM_ERR_ARG, "max_iter must be in 1..64"};
+    const int n = (int)b->plans.size();
+    for (int i = 0; i < n; ++i)
+      if (!thetas[i]) throw DmError{DM_ERR_ARG, "null theta"};
+    hipStream_t s = (hipStream_t)stream;
+    for (dm_heff_plan* p : b->plans) ensure_lanczos(p, max_iter);
+    if (!b->built) build_batch(*b);
+    if (b->lz_cap != max_iter) {
+      if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+      if (b->graph) (void)hipGraphDestroy(b->graph);
+      b->graph_exec = nullptr;
+      b->graph = nullptr;
+      dev_free(b->dInst);
+      dev_free(b->dRes);
+      if (b->hInst) (void)hipHostFree(b->hInst);
+      if (b->hRes) (void)hipHostFree(b->hRes);
+      b->dInst = nullptr;
+      b->dRes = nullptr;
+      b->hInst = nullptr;
+      b->hRes = nullptr;
+      b->dInst = (LzInst*)dev_alloc(n * sizeof(LzInst));
+      b->dRes = (LzResult*)dev_alloc(n * sizeof(LzResult));
+      HIPCHK(hipHostMalloc((void**)&b->hInst, n * sizeof(LzInst), hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&b->hRes, n * sizeof(LzResult), hipHostMallocDefault));
+      b->lz_cap = max_iter;
+    }
+    // the instance table is rebuilt every solve: Krylov buffers may have been regrown by
+    // single-plan solves in between, and the start vectors change
+    std::vector<LzInst> I(n);
+    for (int i = 0; i < n; ++i) {
+      dm_heff_plan* p = b->plans[i];
+      I[i] = LzInst{p->dV, p->dW, p->dVcur, p->dPart, nullptr, (double*)thetas[i], p->dState,
+                    p->n(), p->n()};
+    }
+    const LzGrid g = lz_layout(I, max_iter);
+    const bool same = b->graph_exec && std::equal(I.begin(), I.end(), b->hInst, [](const LzInst& x, const LzInst& y) {
+      return x.V == y.V && x.w == y.w && x.vcur == y.vcur && x.part == y.part && x.st == y.st;
+    });
+    if (!same && b->graph_exec) {
+      (void)hipGraphExecDestroy(b->graph_exec);
+      (void)hipGraphDestroy(b->graph);
+      b->graph_exec = nullptr;
+      b->graph = nullptr;
+    }
+    std::copy(I.begin(), I.end(), b->hInst);  // previous solve synchronised: buffer free
+    b->lzg = g;
+    HIPCHK(hipMemcpyAsync(b->dInst, b->hInst, n * sizeof(LzInst), hipMemcpyHostToDevice, s));
+    HIPCHK(lz_launch_init(b->dInst, b->lzg, max_iter, tol, s));
+    HIPCHK(lz_launch_start(b->dInst, b->lzg, s));
+    if (b->use_graph && !b->graph_exec) {
+      if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+      HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        batch_step(*b, b->cap_stream);
+      } catch (...) {
+        hipGraph_t gr = nullptr;
+        (void)hipStreamEndCapture(b->cap_stream, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(b->cap_stream, &b->graph));
+      HIPCHK(hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0));
+    }
+    for (int j = 0; j < max_iter; ++j) {
+      if (b->use_graph)
+        HIPCHK(hipGraphLaunch(b->graph_exec, s));
+      else
+        batch_step(*b, s);
+    }
+    HIPCHK(lz_launch_finish(b->dInst, b->lzg, s));
+    if (b->prec != DM_FP64) {
+      run_merged(b->mv64, s);  // FP64 H vcur -> w for every instance
+      HIPCHK(lz_launch_rq(b->dInst, b->lzg, s));
+    }
+    HIPCHK(lz_launch_results(b->dInst, b->lzg, b->dRes, s));
+    HIPCHK(hipMemcpyAsync(b->hRes, b->dRes, n * sizeof(LzResult), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(b->done, s));
+    for (dm_heff_plan* p : b->plans) HIPCHK(hipEventRecord(p->done, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int rate_khz = 0;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    bool bad = false;
+    for (int i = 0; i < n; ++i) {
+      const LzResult& r = b->hRes[i];
+      energies[i] = r.energy;
+      iters[i] = r.k;
+      bad = bad || r.bad;
+      if (done_us)
+        done_us[i] = rate_khz > 0 ? (double)(r.t1 - r.t0) * 1e3 / rate_khz : 0.0;
+    }
+    if (bad) throw DmError{DM_ERR_NONFINITE, "Lanczos produced a zero, NaN or Inf norm"};
+  });
 }

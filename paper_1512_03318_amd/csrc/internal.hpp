@@ -128,7 +128,7 @@ hipError_t launch_cast_d2f(const double* in, float* out, int64_t n_real, hipStre
 hipError_t launch_cast_f2d(const float* in, double* out, int64_t n_real, hipStream_t s,
                            const int32_t* skip = nullptr);
 
-// Device-resident Lanczos state (lanczos.hip).  Krylov basis V[j] = V + j * ld.
+// Device-resident Lanczos state (lanczos.hip), one per instance.
 constexpr int LZ_MAX = 64;
 struct LzState {
   double alpha[LZ_MAX + 1];
@@ -139,20 +139,60 @@ struct LzState {
   double rq[2];                     // Rayleigh quotient numerator / denominator
   double scal0;                     // |theta_0|^2
   double inv_beta, tnorm, tol, energy;
-  int32_t iter, k, stop, max_iter, bad;
+  int32_t iter, k, stop, max_iter, bad, pad;
+  uint64_t t0, t1;                  // device wall clock at start and when the solve stopped
 };
-// partial sums buffer: lz_nblk1(n) * (2 * max_iter + 2) doubles
-int lz_nblk(int64_t n);
-int lz_nblk1(int64_t n);
-hipError_t lz_launch_init(LzState* st, int32_t max_iter, double tol, hipStream_t s);
-hipError_t lz_launch_start(const double* x, int64_t n, LzState* st, double* partial, double* V,
-                           double* vcur, hipStream_t s);
-hipError_t lz_launch_step_tail(double* V, int64_t ld, double* w, int64_t n, LzState* st,
-                               double* partial, double* vcur, int32_t max_iter, hipStream_t s);
-hipError_t lz_launch_finish(const double* V, int64_t ld, int64_t n, LzState* st, double* out,
-                            hipStream_t s);
-hipError_t lz_launch_rq(const double* x, const double* w, int64_t n, LzState* st, double* partial,
-                        hipStream_t s);
+
+// One Lanczos instance of a (possibly batched) launch.  Every Lanczos kernel runs over
+// all instances of its table at once: a flat grid whose blocks are assigned to
+// instances by the first-block offsets c0 / g0 / d0 (found by binary search).
+struct LzInst {
+  double* V;       // Krylov basis, vector j at V + 2 j ld (doubles)
+  double* w;       // H v_j
+  double* vcur;    // v_j (matvec input of every step)
+  double* part;    // dot-product partials: nb1 x (2 max_iter + 1)
+  double* pnorm;   // norm / Rayleigh-quotient partials: 2 nb
+  double* x;       // caller's start vector in, Ritz vector out
+  LzState* st;
+  int64_t ld, n;   // n complex elements
+  int32_t nb, nb1; // chunk blocks (1024 elements), dot-product blocks
+  int32_t c0, g0, d0, pad;  // first chunk / 256-element / dot-product block of this instance
+};
+// Launch shape of an instance table (host side).
+struct LzGrid {
+  int32_t nins = 0, nchunk = 0, n256 = 0, ndots = 0;
+  int32_t max_iter = 0;  // capacity: Krylov vectors - 1 of every instance
+};
+struct LzResult {
+  double energy;
+  int32_t k, bad;
+  uint64_t t0, t1;
+};
+// Fills nb, nb1, pnorm and the block offsets of I (V, w, vcur, part, x, st, ld, n set by
+// the caller; part must hold nb1 (2 max_iter + 1) + 2 nb doubles, see lz_part_doubles).
+LzGrid lz_layout(std::vector<LzInst>& I, int32_t max_iter);
+int64_t lz_part_doubles(int64_t n, int32_t max_iter);
+// Resets the states for a solve of at most max_iter (<= g.max_iter) steps.
+hipError_t lz_launch_init(const LzInst* I, const LzGrid& g, int32_t max_iter, double tol,
+                          hipStream_t s);
+hipError_t lz_launch_start(const LzInst* I, const LzGrid& g, hipStream_t s);
+hipError_t lz_launch_step_tail(const LzInst* I, const LzGrid& g, hipStream_t s);
+// Lowest Ritz pair; the Ritz vector goes to x and to vcur.
+hipError_t lz_launch_finish(const LzInst* I, const LzGrid& g, hipStream_t s);
+// energy = <vcur, w> / <vcur, vcur> (w = FP64 H vcur computed by the caller).
+hipError_t lz_launch_rq(const LzInst* I, const LzGrid& g, hipStream_t s);
+hipError_t lz_launch_results(const LzInst* I, const LzGrid& g, LzResult* out, hipStream_t s);
+
+// Batched casts between FP64 and FP32 storage (kernels.hip): job i converts n reals.
+struct CastJob {
+  const void* src;
+  void* dst;
+  int64_t n;
+  int32_t c0, pad;  // first block of this job
+};
+int32_t cast_layout(std::vector<CastJob>& jobs);  // fills c0, returns the total blocks
+hipError_t launch_cast_batch(bool d2f, const CastJob* jobs, int32_t njobs, int32_t nblocks,
+                             hipStream_t s);
 
 // Thread-local message returned by dm_last_error().
 void set_last_error(const std::string& msg);

@@ -413,4 +413,44 @@ hipError_t launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t 
   return hipGetLastError();
 }
 
+// One launch over many (src, dst, n) conversion jobs; block b serves the job whose first
+// block c0 is the largest one <= b, 1024 reals per block.
+template <bool D2F>
+__global__ void __launch_bounds__(256) cast_batch_kernel(const CastJob* __restrict__ jobs, int njobs) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].c0 <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const CastJob j = jobs[lo];
+  const int64_t base = (int64_t)(blockIdx.x - j.c0) * 1024 + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = base + 256 * q;
+    if (i >= j.n) break;
+    if (D2F) static_cast<float*>(j.dst)[i] = (float)static_cast<const double*>(j.src)[i];
+    else static_cast<double*>(j.dst)[i] = (double)static_cast<const float*>(j.src)[i];
+  }
+}
+
+int32_t cast_layout(std::vector<CastJob>& jobs) {
+  int32_t nb = 0;
+  for (auto& j : jobs) {
+    j.c0 = nb;
+    nb += (int32_t)((j.n + 1023) / 1024);
+  }
+  return nb;
+}
+
+hipError_t launch_cast_batch(bool d2f, const CastJob* jobs, int32_t njobs, int32_t nblocks,
+                             hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  if (d2f)
+    hipLaunchKernelGGL(cast_batch_kernel<true>, dim3(nblocks), dim3(256), 0, s, jobs, njobs);
+  else
+    hipLaunchKernelGGL(cast_batch_kernel<false>, dim3(nblocks), dim3(256), 0, s, jobs, njobs);
+  return hipGetLastError();
+}
+
 }  // namespace mrd

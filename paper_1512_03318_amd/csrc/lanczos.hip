@@ -18,6 +18,9 @@
 // (the step can be captured once as a HIP graph and replayed) and a breakdown turns
 // the remaining launches into no-ops without a host round trip.  Partial sums are
 // reduced in a fixed order: results are reproducible run to run.
+//
+// Each kernel runs over a table of independent instances (LzInst): one launch per
+// phase serves a single plan or a whole batch of them.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -27,10 +30,45 @@ namespace mrd {
 constexpr int LZ_EPT = 4;                 // elements per thread in streaming kernels
 constexpr int LZ_CHUNK = 256 * LZ_EPT;
 
-int lz_nblk(int64_t n) { return (int)((n + LZ_CHUNK - 1) / LZ_CHUNK); }
-int lz_nblk1(int64_t n) { return (int)((n + 255) / 256); }
+static int lz_nblk(int64_t n) { return (int)((n + LZ_CHUNK - 1) / LZ_CHUNK); }
+static int lz_nblk256(int64_t n) { return (int)((n + 255) / 256); }
 // dot-product blocks along the vector: about 16 elements per thread
 static int lz_dots_nblk(int64_t n) { return (int)std::max<int64_t>(1, (n + 4095) / 4096); }
+
+int64_t lz_part_doubles(int64_t n, int32_t max_iter) {
+  return (int64_t)lz_dots_nblk(n) * (2 * max_iter + 1) + 2 * (int64_t)lz_nblk(n);
+}
+
+LzGrid lz_layout(std::vector<LzInst>& I, int32_t max_iter) {
+  LzGrid g;
+  g.nins = (int32_t)I.size();
+  g.max_iter = max_iter;
+  for (auto& x : I) {
+    x.nb = lz_nblk(x.n);
+    x.nb1 = lz_dots_nblk(x.n);
+    x.pnorm = x.part + (int64_t)x.nb1 * (2 * max_iter + 1);
+    x.c0 = g.nchunk;
+    x.g0 = g.n256;
+    x.d0 = g.ndots;
+    g.nchunk += x.nb;
+    g.n256 += lz_nblk256(x.n);
+    g.ndots += x.nb1;
+  }
+  return g;
+}
+
+// Instance owning flat block b of a grid laid out by the offsets F (0: c0, 1: g0, 2: d0).
+template <int F>
+__device__ __forceinline__ int lz_find(const LzInst* __restrict__ I, int nins, int b) {
+  int lo = 0, hi = nins - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int v = F == 0 ? I[mid].c0 : (F == 1 ? I[mid].g0 : I[mid].d0);
+    if (v <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -47,8 +85,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
-__global__ void lz_init_kernel(LzState* st, int32_t max_iter, double tol) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+
+__global__ void lz_init_kernel(const LzInst* __restrict__ I, int32_t max_iter, double tol) {
+  if (threadIdx.x != 0) return;
+  LzState* st = I[blockIdx.x].st;
   st->iter = 0;
   st->k = 0;
   st->stop = 0;
@@ -57,37 +97,62 @@ __global__ void lz_init_kernel(LzState* st, int32_t max_iter, double tol) {
   st->tol = tol;
   st->tnorm = 0.0;
   st->energy = 0.0;
+  st->t0 = wall_clock64();
+  st->t1 = st->t0;
 }
 
-// partial[blk] = sum over the block's chunk of |x|^2
-__global__ void __launch_bounds__(256) lz_norm_kernel(const double* __restrict__ x, int64_t n,
-                                                      double* __restrict__ partial) {
+__device__ __forceinline__ void lz_mark_stop(LzState* st) {
+  st->stop = 1;
+  st->t1 = wall_clock64();
+}
+
+// pnorm[chunk] = sum over the chunk of |x|^2 (start vector)
+__global__ void __launch_bounds__(256) lz_norm_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4];
+  const int q0 = lz_find<0>(I, nins, blockIdx.x);
+  const LzInst& in = I[q0];
+  const int blk = blockIdx.x - in.c0;
+  const double* x = in.x;
   double s = 0;
 #pragma unroll
   for (int q = 0; q < LZ_EPT; ++q) {
-    const int64_t e = (int64_t)blockIdx.x * LZ_CHUNK + q * 256 + threadIdx.x;
-    if (e < n) s += x[2 * e] * x[2 * e] + x[2 * e + 1] * x[2 * e + 1];
+    const int64_t e = (int64_t)blk * LZ_CHUNK + q * 256 + threadIdx.x;
+    if (e < in.n) s += x[2 * e] * x[2 * e] + x[2 * e + 1] * x[2 * e + 1];
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) in.pnorm[blk] = s;
 }
 
-// out[c] = sum_b partial[b * ncomp + c] in a fixed order, c < ncomp.
-// ncomp = fixed if >= 0, else 2 * (st->iter + 1) + extra (the current step's width).
-// With at_2nv, the result goes to out + 2 * (st->iter + 1) (the |w|^2 slot of h2).
-__global__ void __launch_bounds__(256) lz_reduce_kernel(const double* __restrict__ partial,
-                                                        int32_t nblk, int32_t fixed, int32_t extra,
-                                                        const LzState* __restrict__ st,
-                                                        double* __restrict__ out, int32_t at_2nv) {
+enum LzReduce : int32_t {
+  LZR_SCAL0 = 0,  // sum of pnorm -> scal0
+  LZR_H1 = 1,     // dot partials -> h1 (2 nv components)
+  LZR_H2 = 2,     // dot partials -> h2
+  LZR_NORM = 3,   // sum of pnorm -> h2[2 nv] (|w1|^2)
+  LZR_RQ = 4,     // pnorm pairs -> rq[0..1]
+};
+
+// Fixed-order reduction of one component (blockIdx.x) of instance blockIdx.y.
+__global__ void __launch_bounds__(256) lz_reduce_kernel(const LzInst* __restrict__ I, int32_t mode) {
   __shared__ double sm[256];
-  if ((fixed < 0 || at_2nv) && st->stop) return;
-  if (at_2nv) out += 2 * (st->iter + 1);
-  const int ncomp = fixed >= 0 ? fixed : 2 * (st->iter + 1) + extra;
+  const LzInst& in = I[blockIdx.y];
+  LzState* st = in.st;
+  const bool step = mode == LZR_H1 || mode == LZR_H2 || mode == LZR_NORM;
+  if (step && st->stop) return;
+  const int nv = st->iter + 1;
+  const double* src;
+  int nblk, ncomp;
+  double* out;
+  switch (mode) {
+    case LZR_SCAL0: src = in.pnorm; nblk = in.nb; ncomp = 1; out = &st->scal0; break;
+    case LZR_H1: src = in.part; nblk = in.nb1; ncomp = 2 * nv; out = st->h1; break;
+    case LZR_H2: src = in.part; nblk = in.nb1; ncomp = 2 * nv; out = st->h2; break;
+    case LZR_NORM: src = in.pnorm; nblk = in.nb; ncomp = 1; out = st->h2 + 2 * nv; break;
+    default: src = in.pnorm; nblk = in.nb; ncomp = 2; out = st->rq; break;
+  }
   const int c = blockIdx.x;
   if (c >= ncomp) return;
   double s = 0;
-  for (int b = threadIdx.x; b < nblk; b += 256) s += partial[(int64_t)b * ncomp + c];
+  for (int b = threadIdx.x; b < nblk; b += 256) s += src[(int64_t)b * ncomp + c];
   sm[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -97,26 +162,27 @@ __global__ void __launch_bounds__(256) lz_reduce_kernel(const double* __restrict
   if (threadIdx.x == 0) out[c] = sm[0];
 }
 
-// v_0 = x / |x| into V[0] and vcur; |x|^2 in st->scal0.
-__global__ void lz_start_scale_kernel(const double* __restrict__ x, int64_t n,
-                                      LzState* __restrict__ st, double* __restrict__ v0,
-                                      double* __restrict__ vcur) {
+// v_0 = x / |x| into V[0] and vcur.
+__global__ void lz_start_scale_kernel(const LzInst* __restrict__ I, int nins) {
+  const int q0 = lz_find<1>(I, nins, blockIdx.x);
+  const LzInst& in = I[q0];
+  LzState* st = in.st;
   const double nrm2 = st->scal0;
   if (!(nrm2 > 0.0) || !isfinite(nrm2)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == in.g0 && threadIdx.x == 0) {
       st->bad = 1;
-      st->stop = 1;
+      lz_mark_stop(st);
     }
     return;
   }
   const double s = 1.0 / sqrt(nrm2);
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const double a = x[2 * e] * s, b = x[2 * e + 1] * s;
-  v0[2 * e] = a;
-  v0[2 * e + 1] = b;
-  vcur[2 * e] = a;
-  vcur[2 * e + 1] = b;
+  const int64_t e = (int64_t)(blockIdx.x - in.g0) * 256 + threadIdx.x;
+  if (e >= in.n) return;
+  const double a = in.x[2 * e] * s, b = in.x[2 * e + 1] * s;
+  in.V[2 * e] = a;
+  in.V[2 * e + 1] = b;
+  in.vcur[2 * e] = a;
+  in.vcur[2 * e + 1] = b;
 }
 
 constexpr int LZ_G = 4;  // Krylov vectors per dot-product block
@@ -139,30 +205,30 @@ __device__ __forceinline__ void block_sums(const double (&v)[NVAL], int nval, do
   }
 }
 
-// partial[blockIdx.y][2i + {0,1}] = sum of conj(V_i) x over the elements
-// e = (blockIdx.y + gridDim.y q) * 256 + thread, q = 0, 1, ..., for the LZ_G vectors
-// i = LZ_G * blockIdx.x + g < nv (nv = iter + 1).  Each thread accumulates many
-// elements before the single block reduction; consecutive blocks (same y, next group)
-// read the same x elements, which stay in L2.
-__global__ void __launch_bounds__(256) lz_dots_kernel(const double* __restrict__ V, int64_t ld,
-                                                      const double* __restrict__ x, int64_t n,
-                                                      const LzState* __restrict__ st,
-                                                      double* __restrict__ partial) {
+// part[y][2i + {0,1}] = sum of conj(V_i) w over the elements e = (y + nb1 q) * 256 +
+// thread, q = 0, 1, ..., for the LZ_G vectors i = LZ_G * blockIdx.x + g < nv (nv =
+// iter + 1), y = this block's dot-product block within its instance.  Each thread
+// accumulates many elements before the single block reduction; consecutive blocks
+// (same y, next group) read the same w elements, which stay in L2.
+__global__ void __launch_bounds__(256) lz_dots_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4 * 2 * LZ_G];
-  if (st->stop) return;
-  const int nv = st->iter + 1;
+  const int q0 = lz_find<2>(I, nins, blockIdx.y);
+  const LzInst& in = I[q0];
+  if (in.st->stop) return;
+  const int nv = in.st->iter + 1;
   const int i0 = blockIdx.x * LZ_G;
   if (i0 >= nv) return;
-  const double2* xv = reinterpret_cast<const double2*>(x);
+  const int y = blockIdx.y - in.d0;
+  const double2* xv = reinterpret_cast<const double2*>(in.w);
   const double2* vv[LZ_G];
 #pragma unroll
   for (int g = 0; g < LZ_G; ++g)
-    vv[g] = reinterpret_cast<const double2*>(V) + (int64_t)min(i0 + g, nv - 1) * ld;
+    vv[g] = reinterpret_cast<const double2*>(in.V) + (int64_t)min(i0 + g, nv - 1) * in.ld;
   double acc[2 * LZ_G];
 #pragma unroll
   for (int c = 0; c < 2 * LZ_G; ++c) acc[c] = 0.0;
-  const int64_t stride = (int64_t)gridDim.y * 256;
-  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < n; e += stride) {
+  const int64_t stride = (int64_t)in.nb1 * 256, n = in.n;
+  for (int64_t e = (int64_t)y * 256 + threadIdx.x; e < n; e += stride) {
     const double2 xe = xv[e];
 #pragma unroll
     for (int g = 0; g < LZ_G; ++g) {
@@ -171,23 +237,27 @@ __global__ void __launch_bounds__(256) lz_dots_kernel(const double* __restrict__
       acc[2 * g + 1] += v.x * xe.y - v.y * xe.x;
     }
   }
-  block_sums(acc, 2 * min(LZ_G, nv - i0), sh, partial + blockIdx.y * (int64_t)(2 * nv) + 2 * i0);
+  block_sums(acc, 2 * min(LZ_G, nv - i0), sh, in.part + y * (int64_t)(2 * nv) + 2 * i0);
 }
 
-// w -= V h1 over the nv = iter + 1 Krylov vectors; partial[chunk] = |w_new|^2 over the chunk.
-__global__ void __launch_bounds__(256) lz_sub_kernel(const double* __restrict__ V, int64_t ld,
-                                                     double* __restrict__ w, int64_t n,
-                                                     const LzState* __restrict__ st,
-                                                     double* __restrict__ partial) {
+// w -= V h1 over the nv = iter + 1 Krylov vectors; pnorm[chunk] = |w_new|^2 over the chunk.
+__global__ void __launch_bounds__(256) lz_sub_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4];
+  const int q0 = lz_find<0>(I, nins, blockIdx.x);
+  const LzInst& in = I[q0];
+  const LzState* st = in.st;
   if (st->stop) return;
   const int nv = st->iter + 1;
   const double* h1 = st->h1;
+  const double* V = in.V;
+  double* w = in.w;
+  const int64_t ld = in.ld;
+  const int blk = blockIdx.x - in.c0;
   double nn = 0;
 #pragma unroll
   for (int q = 0; q < LZ_EPT; ++q) {
-    const int64_t e = (int64_t)blockIdx.x * LZ_CHUNK + q * 256 + threadIdx.x;
-    if (e >= n) continue;
+    const int64_t e = (int64_t)blk * LZ_CHUNK + q * 256 + threadIdx.x;
+    if (e >= in.n) continue;
     double wr = w[2 * e], wi = w[2 * e + 1];
     for (int i = 0; i < nv; ++i) {
       const double hr = h1[2 * i], hi = h1[2 * i + 1];
@@ -200,12 +270,13 @@ __global__ void __launch_bounds__(256) lz_sub_kernel(const double* __restrict__ 
     nn += wr * wr + wi * wi;
   }
   nn = block_sum(nn, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = nn;
+  if (threadIdx.x == 0) in.pnorm[blk] = nn;
 }
 
-// Scalar part of step j = st->iter: alpha_j, beta_j, |T|, stopping rule.
-__global__ void lz_scalar_kernel(LzState* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0 || st->stop) return;
+// Scalar part of step j = st->iter of instance blockIdx.x: alpha_j, beta_j, |T|, stopping rule.
+__global__ void lz_scalar_kernel(const LzInst* __restrict__ I) {
+  LzState* st = I[blockIdx.x].st;
+  if (threadIdx.x != 0 || st->stop) return;
   const int j = st->iter, nv = j + 1;
   const double alpha = st->h1[2 * j];
   double hh = 0;
@@ -213,7 +284,7 @@ __global__ void lz_scalar_kernel(LzState* st) {
   const double nrm2 = st->h2[2 * nv];
   if (!isfinite(alpha) || !isfinite(nrm2)) {
     st->bad = 1;
-    st->stop = 1;
+    lz_mark_stop(st);
     return;
   }
   const double beta = sqrt(fmax(nrm2 - hh, 0.0));
@@ -222,7 +293,7 @@ __global__ void lz_scalar_kernel(LzState* st) {
   const double row = fabs(alpha) + beta + (j > 0 ? st->beta[j - 1] : 0.0);
   st->tnorm = fmax(st->tnorm, row);
   if (beta <= st->tol * st->tnorm || j == st->max_iter - 1) {
-    st->stop = 1;
+    lz_mark_stop(st);
     return;
   }
   st->beta[j] = beta;
@@ -231,15 +302,17 @@ __global__ void lz_scalar_kernel(LzState* st) {
 }
 
 // v_{j+1} = (w - V h2) / beta_j into V[j+1] and vcur (runs only if the step continued).
-__global__ void __launch_bounds__(256) lz_next_kernel(double* __restrict__ V, int64_t ld,
-                                                      const double* __restrict__ w, int64_t n,
-                                                      const LzState* __restrict__ st,
-                                                      double* __restrict__ vcur) {
+__global__ void __launch_bounds__(256) lz_next_kernel(const LzInst* __restrict__ I, int nins) {
+  const int q0 = lz_find<1>(I, nins, blockIdx.x);
+  const LzInst& in = I[q0];
+  const LzState* st = in.st;
   if (st->stop) return;
   const int nv = st->iter;  // already advanced: vectors 0 .. j
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  double wr = w[2 * e], wi = w[2 * e + 1];
+  const int64_t e = (int64_t)(blockIdx.x - in.g0) * 256 + threadIdx.x;
+  if (e >= in.n) return;
+  const double* V = in.V;
+  const int64_t ld = in.ld;
+  double wr = in.w[2 * e], wi = in.w[2 * e + 1];
   const double* h2 = st->h2;
   for (int i = 0; i < nv; ++i) {
     const double hr = h2[2 * i], hi = h2[2 * i + 1];
@@ -250,11 +323,11 @@ __global__ void __launch_bounds__(256) lz_next_kernel(double* __restrict__ V, in
   const double s = st->inv_beta;
   wr *= s;
   wi *= s;
-  double* out = V + 2 * (int64_t)nv * ld;
+  double* out = in.V + 2 * (int64_t)nv * ld;
   out[2 * e] = wr;
   out[2 * e + 1] = wi;
-  vcur[2 * e] = wr;
-  vcur[2 * e + 1] = wi;
+  in.vcur[2 * e] = wr;
+  in.vcur[2 * e + 1] = wi;
 }
 
 // Sturm count: number of eigenvalues of T_k below x.
@@ -275,7 +348,8 @@ __device__ int lz_sturm(const double* al, const double* be, int k, double x) {
 // of a 64-point grid of the current interval, so every round shrinks it 65-fold; then
 // lane 0 runs inverse iteration with partial pivoting (four sweeps).  Writes st->energy
 // and st->y.
-__global__ void __launch_bounds__(64) lz_tridiag_kernel(LzState* st) {
+__global__ void __launch_bounds__(64) lz_tridiag_kernel(const LzInst* __restrict__ I) {
+  LzState* st = I[blockIdx.x].st;
   __shared__ int cnt[64];
   __shared__ double bounds[2];
   __shared__ double dd[LZ_MAX], du[LZ_MAX], du2[LZ_MAX], dl[LZ_MAX], b[LZ_MAX], ys[LZ_MAX];
@@ -371,32 +445,38 @@ __global__ void __launch_bounds__(64) lz_tridiag_kernel(LzState* st) {
   for (int i = 0; i < k; ++i) y[i] = ys[i];
 }
 
-// out = sum_{i < k} y_i V_i
-__global__ void lz_combine_kernel(const double* __restrict__ V, int64_t ld, int64_t n,
-                                  const LzState* __restrict__ st, double* __restrict__ out) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n) return;
+// Ritz vector sum_{i < k} y_i V_i into x and vcur.
+__global__ void lz_combine_kernel(const LzInst* __restrict__ I, int nins) {
+  const int q0 = lz_find<1>(I, nins, blockIdx.x);
+  const LzInst& in = I[q0];
+  const int64_t e = (int64_t)(blockIdx.x - in.g0) * 256 + threadIdx.x;
+  if (e >= in.n) return;
+  const LzState* st = in.st;
   const int k = st->k;
   double r = 0, im = 0;
   for (int i = 0; i < k; ++i) {
     const double yi = st->y[i];
-    r += yi * V[2 * ((int64_t)i * ld + e)];
-    im += yi * V[2 * ((int64_t)i * ld + e) + 1];
+    r += yi * in.V[2 * ((int64_t)i * in.ld + e)];
+    im += yi * in.V[2 * ((int64_t)i * in.ld + e) + 1];
   }
-  out[2 * e] = r;
-  out[2 * e + 1] = im;
+  in.x[2 * e] = r;
+  in.x[2 * e + 1] = im;
+  in.vcur[2 * e] = r;
+  in.vcur[2 * e + 1] = im;
 }
 
-// partial[blk] = (Re <x, w>, |x|^2) over the chunk (Rayleigh quotient).
-__global__ void __launch_bounds__(256) lz_rq_kernel(const double* __restrict__ x,
-                                                    const double* __restrict__ w, int64_t n,
-                                                    double* __restrict__ partial) {
+// pnorm[2 chunk + {0,1}] = (Re <vcur, w>, |vcur|^2) over the chunk (Rayleigh quotient).
+__global__ void __launch_bounds__(256) lz_rq_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4];
+  const int q0 = lz_find<0>(I, nins, blockIdx.x);
+  const LzInst& in = I[q0];
+  const int blk = blockIdx.x - in.c0;
+  const double *x = in.vcur, *w = in.w;
   double s = 0, q2 = 0;
 #pragma unroll
   for (int q = 0; q < LZ_EPT; ++q) {
-    const int64_t e = (int64_t)blockIdx.x * LZ_CHUNK + q * 256 + threadIdx.x;
-    if (e < n) {
+    const int64_t e = (int64_t)blk * LZ_CHUNK + q * 256 + threadIdx.x;
+    if (e < in.n) {
       s += x[2 * e] * w[2 * e] + x[2 * e + 1] * w[2 * e + 1];
       q2 += x[2 * e] * x[2 * e] + x[2 * e + 1] * x[2 * e + 1];
     }
@@ -404,65 +484,75 @@ __global__ void __launch_bounds__(256) lz_rq_kernel(const double* __restrict__ x
   s = block_sum(s, sh);
   q2 = block_sum(q2, sh);
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = s;
-    partial[2 * blockIdx.x + 1] = q2;
+    in.pnorm[2 * blk] = s;
+    in.pnorm[2 * blk + 1] = q2;
   }
 }
 
-__global__ void lz_rq_final_kernel(LzState* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void lz_rq_final_kernel(const LzInst* __restrict__ I) {
+  if (threadIdx.x != 0) return;
+  LzState* st = I[blockIdx.x].st;
   const double e = st->rq[0] / st->rq[1];
   if (!isfinite(e)) st->bad = 1;
   st->energy = e;
 }
 
+__global__ void lz_results_kernel(const LzInst* __restrict__ I, LzResult* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const LzState* st = I[blockIdx.x].st;
+  LzResult r;
+  r.energy = st->energy;
+  r.k = st->k;
+  r.bad = st->bad;
+  r.t0 = st->t0;
+  r.t1 = st->t1;
+  out[blockIdx.x] = r;
+}
+
 // ---------------------------------------------------------------------------------
-static dim3 g1(int64_t n) { return dim3((uint32_t)((n + 255) / 256)); }
-
-hipError_t lz_launch_init(LzState* st, int32_t max_iter, double tol, hipStream_t s) {
-  hipLaunchKernelGGL(lz_init_kernel, dim3(1), dim3(64), 0, s, st, max_iter, tol);
+hipError_t lz_launch_init(const LzInst* I, const LzGrid& g, int32_t max_iter, double tol,
+                          hipStream_t s) {
+  if (max_iter < 1 || max_iter > g.max_iter) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lz_init_kernel, dim3(g.nins), dim3(64), 0, s, I, max_iter, tol);
   return hipGetLastError();
 }
 
-hipError_t lz_launch_start(const double* x, int64_t n, LzState* st, double* partial, double* V,
-                           double* vcur, hipStream_t s) {
-  const int nb = lz_nblk(n);
-  hipLaunchKernelGGL(lz_norm_kernel, dim3(nb), dim3(256), 0, s, x, n, partial);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(1), dim3(256), 0, s, partial, nb, 1, 0, st, &st->scal0, 0);
-  hipLaunchKernelGGL(lz_start_scale_kernel, g1(n), dim3(256), 0, s, x, n, st, V, vcur);
+hipError_t lz_launch_start(const LzInst* I, const LzGrid& g, hipStream_t s) {
+  hipLaunchKernelGGL(lz_norm_kernel, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(1, g.nins), dim3(256), 0, s, I, (int32_t)LZR_SCAL0);
+  hipLaunchKernelGGL(lz_start_scale_kernel, dim3(g.n256), dim3(256), 0, s, I, g.nins);
   return hipGetLastError();
 }
 
-hipError_t lz_launch_step_tail(double* V, int64_t ld, double* w, int64_t n, LzState* st,
-                               double* partial, double* vcur, int32_t max_iter, hipStream_t s) {
-  const int nb = lz_nblk(n), nb1 = lz_dots_nblk(n);
-  const int maxc = 2 * max_iter + 1;
-  const dim3 gd((max_iter + LZ_G - 1) / LZ_G, nb1);
-  double* pnorm = partial + (size_t)nb1 * maxc;
-  hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, V, ld, w, n, st, partial);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc), dim3(256), 0, s, partial, nb1, -1, 0, st, st->h1, 0);
-  hipLaunchKernelGGL(lz_sub_kernel, dim3(nb), dim3(256), 0, s, V, ld, w, n, st, pnorm);
-  hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, V, ld, w, n, st, partial);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc), dim3(256), 0, s, partial, nb1, -1, 0, st, st->h2, 0);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(1), dim3(256), 0, s, pnorm, nb, 1, 0, st, st->h2, 1);
-  hipLaunchKernelGGL(lz_scalar_kernel, dim3(1), dim3(64), 0, s, st);
-  hipLaunchKernelGGL(lz_next_kernel, g1(n), dim3(256), 0, s, V, ld, w, n, st, vcur);
+hipError_t lz_launch_step_tail(const LzInst* I, const LzGrid& g, hipStream_t s) {
+  const int maxc = 2 * g.max_iter + 1;
+  const dim3 gd((g.max_iter + LZ_G - 1) / LZ_G, g.ndots);
+  hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, I, g.nins);
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H1);
+  hipLaunchKernelGGL(lz_sub_kernel, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+  hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, I, g.nins);
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H2);
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(1, g.nins), dim3(256), 0, s, I, (int32_t)LZR_NORM);
+  hipLaunchKernelGGL(lz_scalar_kernel, dim3(g.nins), dim3(64), 0, s, I);
+  hipLaunchKernelGGL(lz_next_kernel, dim3(g.n256), dim3(256), 0, s, I, g.nins);
   return hipGetLastError();
 }
 
-hipError_t lz_launch_finish(const double* V, int64_t ld, int64_t n, LzState* st, double* out,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(lz_tridiag_kernel, dim3(1), dim3(64), 0, s, st);
-  hipLaunchKernelGGL(lz_combine_kernel, g1(n), dim3(256), 0, s, V, ld, n, st, out);
+hipError_t lz_launch_finish(const LzInst* I, const LzGrid& g, hipStream_t s) {
+  hipLaunchKernelGGL(lz_tridiag_kernel, dim3(g.nins), dim3(64), 0, s, I);
+  hipLaunchKernelGGL(lz_combine_kernel, dim3(g.n256), dim3(256), 0, s, I, g.nins);
   return hipGetLastError();
 }
 
-hipError_t lz_launch_rq(const double* x, const double* w, int64_t n, LzState* st, double* partial,
-                        hipStream_t s) {
-  const int nb = lz_nblk(n);
-  hipLaunchKernelGGL(lz_rq_kernel, dim3(nb), dim3(256), 0, s, x, w, n, partial);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(2), dim3(256), 0, s, partial, nb, 2, 0, st, st->rq, 0);
-  hipLaunchKernelGGL(lz_rq_final_kernel, dim3(1), dim3(64), 0, s, st);
+hipError_t lz_launch_rq(const LzInst* I, const LzGrid& g, hipStream_t s) {
+  hipLaunchKernelGGL(lz_rq_kernel, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+  hipLaunchKernelGGL(lz_reduce_kernel, dim3(2, g.nins), dim3(256), 0, s, I, (int32_t)LZR_RQ);
+  hipLaunchKernelGGL(lz_rq_final_kernel, dim3(g.nins), dim3(64), 0, s, I);
+  return hipGetLastError();
+}
+
+hipError_t lz_launch_results(const LzInst* I, const LzGrid& g, LzResult* out, hipStream_t s) {
+  hipLaunchKernelGGL(lz_results_kernel, dim3(g.nins), dim3(64), 0, s, I, out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,178 @@
+// Host runtime shared by the plan, Lanczos, environment and batch entry points:
+// error handling, the caching device allocator, task-table uploads, precision staging
+// and the effective-Hamiltonian plan object.
+#pragma once
+
+#include <array>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace mrd {
+
+// Sets the thread-local message of dm_last_error() and returns code.
+int fail(int code, const std::string& msg);
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::mrd::DmError{DM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// Runs f, turning exceptions into error codes (no exception crosses the C ABI).
+template <typename F>
+int guarded(F&& f) {
+  try {
+    f();
+    return DM_OK;
+  } catch (const DmError& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(DM_ERR_ALLOC, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(DM_ERR_ARG, e.what());
+  }
+}
+
+// Caching device allocator (runtime.cpp): blocks are reused across plans.
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+
+// All task tables of one or more stages in one device block, uploaded with one copy.
+struct TableUpload {
+  std::vector<char> host;
+  std::vector<std::pair<size_t, void**>> fix;  // offset -> device pointer to patch
+  template <typename T>
+  void add(const std::vector<T>& v, T** dst) {
+    *dst = nullptr;
+    if (v.empty()) return;
+    const size_t off = (host.size() + 255) & ~size_t(255);
+    host.resize(off + v.size() * sizeof(T));
+    std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+    fix.emplace_back(off, (void**)dst);
+  }
+  void add(GemmStage& st) {
+    add(st.segs, &st.d_segs);
+    add(st.probs, &st.d_probs);
+    add(st.tiles, &st.d_tiles);
+    add(st.rows, &st.d_rows);
+    add(st.asrc, &st.d_asrc);
+    add(st.red_tiles, &st.d_red_tiles);
+  }
+  void add(MixStage& st) {
+    add(st.tasks, &st.d_tasks);
+    add(st.srcs, &st.d_srcs);
+  }
+  // Synchronous copy into a pool block; returns the block (free it with dev_free).
+  void* commit() {
+    if (host.empty()) return nullptr;
+    char* d = (char*)dev_alloc(host.size());
+    HIPCHK(hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice));
+    for (auto& f : fix) *f.second = d + f.first;
+    return d;
+  }
+};
+
+size_t elem_bytes(int prec);
+void check_prec(int prec);
+void check_ly(int ly);
+// Copy (FP64) or cast (FP32 storage) n complex elements from a complex128 buffer, and back.
+void stage_in(const void* src, void* dst, int64_t n, int prec, hipStream_t s);
+void stage_out(const void* src, void* dst, int64_t n, int prec, hipStream_t s);
+// FP32-storage GEMM stage: FP32 MFMA (DM_FP32) or bf16 hi/lo split MFMA (DM_BF16X3).
+hipError_t gemm_lp(int prec, const GemmStage& st, const float* A, const float* B, float* C,
+                   float* part, hipStream_t s, const int32_t* skip = nullptr,
+                   const std::function<void()>& between = std::function<void()>());
+
+}  // namespace mrd
+
+// =====================================================================================
+// Effective Hamiltonian plan
+// =====================================================================================
+struct dm_heff_plan {
+  int ly = 1, prec = DM_FP64;
+  mrd::Bond a, c;
+  mrd::MpoSite w1, w2;
+  mrd::ThetaLayout th;
+  mrd::EnvLLayout L;
+  mrd::EnvRLayout R;
+  std::vector<int64_t> xoff;  // per a: X panel offset (rows = L.P.rows[a], cols = th.P.cols[a])
+  int64_t xtotal = 0;
+  mrd::GemmStage s1, s4;
+  mrd::MixStage mix;
+  void* dTables = nullptr;      // all task tables (one pool block)
+  hipEvent_t done = nullptr;    // recorded after every use; waited on before release
+  double mix_flops = 0;
+  std::vector<int64_t> zoff;  // per c': Z panel offset (rows zrows[c'], cols R.P.cols[c'])
+  std::vector<int> zrows;
+  int64_t ztotal = 0;
+  void* dZ = nullptr;
+  void* dZ64 = nullptr;
+  // device buffers (elements in the plan's precision)
+  void* dL = nullptr;
+  void* dR = nullptr;
+  void* dL64 = nullptr;  // FP64 copies for the final Rayleigh quotient (low precision plans)
+  void* dR64 = nullptr;
+  void* dX = nullptr;
+  void* dX64 = nullptr;
+  void* dSplit = nullptr;    // K-split partial tiles of the (.)R stage
+  void* dSplit64 = nullptr;
+  void* dTin = nullptr;  // low-precision staging of theta in / out
+  void* dTout = nullptr;
+  // Lanczos workspace (FP64)
+  double* dV = nullptr;       // Krylov basis, Vcap vectors of n
+  int Vcap = 0;
+  double* dW = nullptr;       // H v_j
+  double* dVcur = nullptr;    // v_j (fixed address: the matvec input of every step)
+  double* dPart = nullptr;    // per-block partial sums
+  mrd::LzState* dState = nullptr;
+  mrd::LzInst* dInst = nullptr;    // this plan as a one-instance Lanczos table
+  mrd::LzInst* hInst = nullptr;    // pinned host copy (start vector pointer set per solve)
+  mrd::LzGrid lzg;
+  mrd::LzResult* dRes = nullptr;
+  mrd::LzResult* hRes = nullptr;   // pinned
+  hipGraph_t graph = nullptr; // one Lanczos step (matvec + projections), captured once
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool use_graph = true;
+  // profiling: events around the three stages of each recorded matvec
+  bool profiling = false;
+  std::vector<std::array<hipEvent_t, 5>> ev;
+  size_t ev_used = 0;
+  ~dm_heff_plan() {
+    if (done) {
+      (void)hipEventSynchronize(done);  // no kernel of this plan may still run
+      (void)hipEventDestroy(done);
+    }
+    for (auto& e : ev)
+      for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    mrd::dev_free(dTables);
+    for (void* p : {dL, dR, dL64, dR64, dX, dX64, dSplit, dSplit64, dTin, dTout, dZ, dZ64})
+      mrd::dev_free(p);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (double* p : {dV, dW, dVcur, dPart}) mrd::dev_free(p);
+    mrd::dev_free(dState);
+    mrd::dev_free(dInst);
+    mrd::dev_free(dRes);
+    if (hInst) (void)hipHostFree(hInst);
+    if (hRes) (void)hipHostFree(hRes);
+  }
+  int64_t n() const { return th.P.total; }
+};
+
+
+namespace mrd {
+// theta_out = H_eff theta in the plan's precision (FP64 in / out); force64 uses the
+// FP64 copies of L and R.  skip (may be null): device flag that turns the launches into
+// no-ops.  capturing: no profiling events (inside HIP graph capture).
+void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStream_t s, bool force64,
+              const int32_t* skip = nullptr, bool capturing = false);
+// Lanczos workspace of a plan for up to max_iter steps.
+void ensure_lanczos(dm_heff_plan* p, int max_iter);
+}  // namespace mrd
