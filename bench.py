@@ -175,6 +175,224 @@ def cpu_baseline(wl, iters=30):
                       f"block-GEMM flops only"}
 
 
+def window_costs(pk, torch, ly, a, b, c, w1, w2, L, R, theta, A, B, prec, stream, reps=5):
+    """Median device times (ms) of one matvec and of the two environment updates of a
+    window, with their task-table flops and the stored elements of L, R and theta."""
+    plan = pk.HeffPlan(ly, a, c, w1, w2, L, R, prec, stream)
+    y = torch.empty_like(theta)
+    _, nl = pk.layout(pk.LAYOUT_ENV_L, ly, b, qw=w1.qr)
+    _, nr = pk.layout(pk.LAYOUT_ENV_R, ly, b, qw=w2.ql)
+    Lo = torch.empty(nl, dtype=torch.complex128, device=theta.device)
+    Ro = torch.empty(nr, dtype=torch.complex128, device=theta.device)
+    s = torch.cuda.current_stream()
+
+    def med(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[reps // 2]
+
+    t_mv = med(lambda: pk.heff_apply(plan, theta, y, stream))
+    t_l = med(lambda: pk.env_update_left(ly, a, b, w1, L, A, Lo, prec, stream))
+    t_r = med(lambda: pk.env_update_right(ly, b, c, w2, R, B, Ro, prec, stream))
+    return {"matvec_ms": round(t_mv, 4), "env_left_ms": round(t_l, 4), "env_right_ms": round(t_r, 4),
+            "matvec_gflop": round(sum(plan.flops) / 1e9, 4),
+            "env_gflop": round((pk.env_flops(True, ly, a, b, w1) + pk.env_flops(False, ly, b, c, w2)) / 1e9, 4),
+            "elements_L_R_theta": int(L.numel() + R.numel() + theta.numel()),
+            "sectors": len(a.q) if hasattr(a, "q") else None}
+
+
+def compare_real(pk, torch, wl, inp, prec, stream):
+    """The same window in the real-space basis (charge N only, real-space MPO of the same
+    cylinder, same chi and sector rule): cost ratios real / mixed.  Environments of the
+    exact block structure with seeded Gaussian entries (costs do not depend on values)."""
+    import numpy as np
+
+    import workloads
+    mixed = window_costs(pk, torch, inp["ly"], inp["a"], inp["b"], inp["c"], inp["w1"], inp["w2"],
+                         inp["L"], inp["R"], inp["theta"], inp["Aj"], inp["Bj"], prec, stream)
+    wr = workloads.make_workload(wl.name + "_real", wl.Ly, wl.Lx, wl.flux, wl.chi, wl.seed, basis="real")
+    mpo = pk.HofstadterMPO(wr.Ly, wr.Lx, wr.flux[0], wr.flux[1], wr.t, wr.V, "real")
+    j = wr.j
+    w1, w2 = mpo.site(j), mpo.site(j + 1)
+    a, b, c = (pk.Bond(wr.bonds[k]) for k in (j, j + 1, j + 2))
+    rng = np.random.default_rng(55)
+    dev = inp["theta"].device
+
+    def up(x):
+        return torch.from_numpy(x).to(dev)
+
+    L = up(pk.pack(workloads.random_env(rng, wr.bonds[j], w1.ql, 1, "L"), pk.LAYOUT_ENV_L, 1, a, qw=w1.ql))
+    R = up(pk.pack(workloads.random_env(rng, wr.bonds[j + 2], w2.qr, 1, "R"), pk.LAYOUT_ENV_R, 1, c, qw=w2.qr))
+    th = up(pk.pack(workloads.random_theta(rng, wr.bonds[j], wr.bonds[j + 2], w1.qs, w2.qs, 1),
+                    pk.LAYOUT_THETA, 1, a, c, qs1=w1.qs, qs2=w2.qs))
+    A = up(pk.pack(workloads.left_isometry(rng, wr.bonds[j], wr.bonds[j + 1], wr.qsite[j], 1),
+                   pk.LAYOUT_SITE, 1, a, b, qs1=w1.qs))
+    B = up(pk.pack(workloads.right_isometry(rng, wr.bonds[j + 1], wr.bonds[j + 2], wr.qsite[j + 1], 1),
+                   pk.LAYOUT_SITE, 1, b, c, qs1=w2.qs))
+    real = window_costs(pk, torch, 1, a, b, c, w1, w2, L, R, th, A, B, prec, stream)
+    mixed["sectors"] = len(wl.bonds[wl.j])
+    real["sectors"] = len(wr.bonds[j])
+    mixed["mpo_D"] = list(inp["D"])
+    real["mpo_D"] = [w1.W.shape[0], w1.W.shape[3], w2.W.shape[3]]
+    ratio = {k: round(real[k] / mixed[k], 2) for k in
+             ("matvec_gflop", "env_gflop", "elements_L_R_theta", "matvec_ms", "env_left_ms", "env_right_ms")}
+    return {"mixed": mixed, "real": real, "real_over_mixed": ratio,
+            "chi_real": int(sum(wr.bonds[j].values())), "chi_mixed": int(sum(wl.bonds[wl.j].values()))}
+
+
+# ---------------------------------------------------------------------------------
+# Many independent windows in one batched Lanczos (64 windows, Ly in {4, 6, 8},
+# chi in [200, 2000], seeds from SeedSequence(4).spawn(64)).
+# ---------------------------------------------------------------------------------
+def batched_specs(n=64, seed=4):
+    import numpy as np
+    out = []
+    for i, ss in enumerate(np.random.SeedSequence(seed).spawn(n)):
+        r = np.random.default_rng(ss)
+        Ly = int(r.choice([4, 6, 8]))
+        chi = int(r.integers(200, 2001))
+        out.append((i, Ly, chi, int(ss.generate_state(1)[0])))
+    return out
+
+
+_MPO_CACHE = {}
+
+
+def _mpo(pk, wl):
+    key = (wl.Ly, wl.Lx)
+    if key not in _MPO_CACHE:
+        _MPO_CACHE[key] = pk.HofstadterMPO(wl.Ly, wl.Lx, wl.flux[0], wl.flux[1], wl.t, wl.V, wl.basis)
+    return _MPO_CACHE[key]
+
+
+def batched_instance_host(spec):
+    """Host part of one window: seeded isometries of every site outside the window and
+    the start vector, packed in the library's layouts (runs in a worker process)."""
+    from threadpoolctl import threadpool_limits
+
+    import paper_1512_03318_amd as pk
+    import workloads
+    with threadpool_limits(1):  # one BLAS thread per worker: the workers share the cores
+        return _instance_host(pk, workloads, spec)
+
+
+def _instance_host(pk, workloads, spec):
+    i, Ly, chi, seed = spec
+    wl = workloads.centre_workload(f"window{i}", Ly, chi, seed)
+    mpo = _mpo(pk, wl)
+    ly, j, n = wl.ly, wl.j, wl.n
+    bonds = [pk.Bond(b) for b in wl.bonds]
+    qs = [mpo.site(k).qs for k in range(n)]
+    left = [pk.pack(wl.site_tensor(k), pk.LAYOUT_SITE, ly, bonds[k], bonds[k + 1], qs1=qs[k])
+            for k in range(j)]
+    right = [pk.pack(wl.site_tensor(k), pk.LAYOUT_SITE, ly, bonds[k], bonds[k + 1], qs1=qs[k])
+             for k in range(n - 1, j + 1, -1)]
+    theta = pk.pack(wl.theta(), pk.LAYOUT_THETA, ly, bonds[j], bonds[j + 2], qs1=qs[j], qs2=qs[j + 1])
+    return spec, left, right, theta
+
+
+def batched_main(args):
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    specs = batched_specs()
+    # workers are forked and given all their jobs before this process touches the GPU
+    workers = max(1, min(8, len(os.sched_getaffinity(0))))
+    pool = ProcessPoolExecutor(max_workers=workers)
+    futs = [pool.submit(batched_instance_host, sp) for sp in specs]
+
+    import torch
+
+    import paper_1512_03318_amd as pk
+    import workloads
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    prec = {"fp64": pk.DM_FP64, "fp32": pk.DM_FP32, "bf16x3": pk.DM_BF16X3}[args.prec]
+    t0 = time.perf_counter()
+    plans, x0, shapes = [], [], []
+    while futs:
+        (i, Ly, chi, seed), left, right, theta = futs.pop(0).result()  # drop each result once used
+        wl = workloads.centre_workload(f"window{i}", Ly, chi, seed)
+        mpo = _mpo(pk, wl)
+        ly, j, n = wl.ly, wl.j, wl.n
+        bonds = [pk.Bond(b) for b in wl.bonds]
+        sites = [mpo.site(k) for k in range(n)]
+        L = torch.ones(1, dtype=torch.complex128, device=dev)
+        for k in range(j):
+            _, nout = pk.layout(pk.LAYOUT_ENV_L, ly, bonds[k + 1], qw=sites[k].qr)
+            Lo = torch.empty(nout, dtype=torch.complex128, device=dev)
+            pk.env_update_left(ly, bonds[k], bonds[k + 1], sites[k], L, torch.from_numpy(left[k]).to(dev),
+                               Lo, pk.DM_FP64, stream)
+            L = Lo
+        R = torch.ones(1, dtype=torch.complex128, device=dev)
+        for q, k in enumerate(range(n - 1, j + 1, -1)):
+            _, nout = pk.layout(pk.LAYOUT_ENV_R, ly, bonds[k], qw=sites[k].ql)
+            Ro = torch.empty(nout, dtype=torch.complex128, device=dev)
+            pk.env_update_right(ly, bonds[k], bonds[k + 1], sites[k], R, torch.from_numpy(right[q]).to(dev),
+                                Ro, pk.DM_FP64, stream)
+            R = Ro
+        plans.append(pk.HeffPlan(ly, bonds[j], bonds[j + 2], sites[j], sites[j + 1], L, R, prec, stream))
+        x0.append(torch.from_numpy(theta).to(dev))
+        shapes.append({"Ly": Ly, "chi": int(sum(wl.bonds[j].values())), "Lx": wl.Lx,
+                       "sectors": len(wl.bonds[j]), "n": int(theta.size)})
+        if i % 8 == 7:
+            log(f"  windows ready: {i + 1}/{len(specs)} ({time.perf_counter() - t0:.1f} s)")
+    pool.shutdown()
+    torch.cuda.synchronize()
+    log(f"{len(plans)} windows ready in {time.perf_counter() - t0:.1f} s")
+
+    batch = pk.Batch(plans, stream)
+    iters = args.iters
+
+    def solve_batched():
+        xs = [x.clone() for x in x0]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        e, k, us = pk.lanczos_ground_batched(batch, xs, iters, 1e-14, stream)
+        return time.perf_counter() - t, e, k, us
+
+    for _ in range(args.warmup):
+        solve_batched()
+    runs = [solve_batched() for _ in range(args.steps)]
+    wall = sorted(r[0] for r in runs)[len(runs) // 2]
+    _, e_b, k_b, us = runs[-1]
+    flops = sum(k * sum(p.flops) for k, p in zip(k_b, plans))
+    if prec != pk.DM_FP64:
+        flops += sum(sum(p.flops) for p in plans)
+    # the same solves one plan at a time
+    xs = [x.clone() for x in x0]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    e_s = [pk.lanczos_ground(p, x, iters, 1e-14, stream)[0] for p, x in zip(plans, xs)]
+    seq = time.perf_counter() - t
+    us_sorted = sorted(us)
+    out = {"metric": "batched Lanczos ground states of 64 independent windows (Ly in {4,6,8}, "
+                     "chi in [200,2000]) per second",
+           "value": round(len(plans) / wall, 2), "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {pk.DM_FP64: "c128", pk.DM_FP32: "c64", pk.DM_BF16X3: "c64 (bf16x3 products)"}[prec],
+           "data": "synthetic",
+           "config": {"workload": "batch64_ly4-8_chi200-2000", "instances": len(plans),
+                      "lanczos_iters": iters, "precision": args.prec},
+           "gflops": round(flops / wall / 1e9, 1),
+           "p50_done_ms": round(us_sorted[len(us) // 2] / 1e3, 3),
+           "p99_done_ms": round(us_sorted[min(len(us) - 1, int(0.99 * len(us)))] / 1e3, 3),
+           "sequential_ms": round(1e3 * seq, 3),
+           "speedup_vs_sequential": round(seq / wall, 3),
+           "max_rel_energy_diff_vs_sequential": max(abs(a - b) / abs(b) for a, b in zip(e_b, e_s)),
+           "chi_range": [min(s["chi"] for s in shapes), max(s["chi"] for s in shapes)],
+           "theta_elems_range": [min(s["n"] for s in shapes), max(s["n"] for s in shapes)]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,11 +403,18 @@ def main():
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--compare-real", action="store_true",
+                    help="also time the same window in the real-space basis (cost ratios)")
+    ap.add_argument("--batched", action="store_true",
+                    help="64 independent windows in one batched Lanczos instead of one bond update")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no "
               f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.batched:
+        batched_main(args)
+        return
 
     import torch
 
@@ -272,6 +497,9 @@ def main():
                        "energy": e64, "rel_energy_diff_cold_start": abs(e - e64) / abs(e64)}
         out["speedup_vs_fp64"] = {"matvec": round(f_ms / mv_ms, 3),
                                   "lanczos": round(out["fp64"]["lanczos_ms"] / lanczos_ms, 3)}
+    if args.compare_real:
+        log("real-space basis comparison ...")
+        out["real_space"] = compare_real(pk, torch, wl, inp, prec, stream)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl)

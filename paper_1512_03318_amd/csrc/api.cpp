@@ -156,7 +156,25 @@ static void build_heff_tables(dm_heff_plan& p) {
     p.zoff[ci2] = p.ztotal;
     p.ztotal += (int64_t)rows * p.R.P.cols[ci2];
   }
+  // nonzeros of W12 per (s12', w''): (w, s12, value)
+  struct Nz {
+    int w, s12;
+    std::complex<double> v;
+  };
+  std::vector<std::vector<Nz>> nz((size_t)4 * dr);
+  for (int w = 0; w < dl; ++w)
+    for (int s12p = 0; s12p < 4; ++s12p)
+      for (int s12 = 0; s12 < 4; ++s12)
+        for (int wpp = 0; wpp < dr; ++wpp) {
+          const auto v = W12(w, s12p, s12, wpp);
+          if (v != std::complex<double>(0, 0)) nz[(size_t)s12p * dr + wpp].push_back({w, s12, v});
+        }
+  // ket sector a = a' - q(w), or -1
+  std::vector<int> a_of((size_t)a.size() * dl);
+  for (int aip = 0; aip < a.size(); ++aip)
+    for (int w = 0; w < dl; ++w) a_of[(size_t)aip * dl + w] = a.find(qsub(a.q[aip], p.w1.ql[w], ly));
   MixStage& mx = p.mix;
+  std::vector<int64_t> task_key;  // (a', c) slab of each task
   for (int ci2 = 0; ci2 < c.size(); ++ci2) {
     const int Kc = p.R.P.cols[ci2];
     for (int s12p = 0; s12p < 4; ++s12p) {
@@ -167,12 +185,12 @@ static void build_heff_tables(dm_heff_plan& p) {
         if (ci < 0) continue;
         MixTask tk{p.zoff[ci2] + (int64_t)zroff[ci2][s12p] * Kc + p.R.coff[ci2 * dr + wpp], Kc,
                    a.dim[aip], c.dim[ci], (int32_t)mx.srcs.size(), 0, 0};
-        for (int w = 0; w < dl; ++w) {
-          const int ai = a.find(qsub(a.q[aip], p.w1.ql[w], ly));
+        for (const Nz& e : nz[(size_t)s12p * dr + wpp]) {
+          const int w = e.w, s12 = e.s12;
+          const auto v = e.v;
+          const int ai = a_of[(size_t)aip * dl + w];
           if (ai < 0) continue;
-          for (int s12 = 0; s12 < 4; ++s12) {
-            const auto v = W12(w, s12p, s12, wpp);
-            if (v == std::complex<double>(0, 0)) continue;
+          {
             if (p.th.c[ai][s12] != ci || p.L.ap[ai * dl + w] != aip)
               throw DmError{DM_ERR_CHARGE, "MPO charges inconsistent with the bonds"};
             const int Na = p.th.P.cols[ai];
@@ -183,8 +201,21 @@ static void build_heff_tables(dm_heff_plan& p) {
         }
         mx.flops += 8.0 * tk.nsrc * tk.rows * tk.cols;
         mx.tasks.push_back(tk);
+        task_key.push_back(((int64_t)aip << 32) | (uint32_t)ci);
       }
     }
+  }
+  // Every source of a task lies in the X slab (a', c): rows (w, a'), columns (s12, c).
+  // Tasks are ordered by slab, so the tasks that re-read one slab run at about the same
+  // time (workgroups are dispatched in list order) and find it in cache.
+  {
+    std::vector<int> ord(mx.tasks.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return task_key[x] < task_key[y]; });
+    std::vector<MixTask> sorted;
+    sorted.reserve(ord.size());
+    for (int i : ord) sorted.push_back(mx.tasks[i]);
+    mx.tasks.swap(sorted);
   }
   p.mix_flops = mx.flops;
   // (.)R stage, one problem per output sector c':
@@ -476,6 +507,12 @@ extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_it
 // =====================================================================================
 namespace {
 
+// One nonzero of an MPO site tensor with the two indices a loop runs over.
+struct MpoNz {
+  int w, s;
+  std::complex<double> v;
+};
+
 struct EnvPlan {
   GemmStage t1, t3;
   MixStage mix;
@@ -522,6 +559,18 @@ EnvPlan plan_left(int ly, const Bond& a, const Bond& b, const MpoSite& W, const 
     t2off[bi] = ep.t2total;
     ep.t2total += (int64_t)rows * b.dim[bi];
   }
+  // nonzeros of W per (s', w'): (w, s, value); ket sector a = a' - q(w)
+  std::vector<std::vector<MpoNz>> nz((size_t)2 * dr);
+  for (int w = 0; w < dl; ++w)
+    for (int sp = 0; sp < 2; ++sp)
+      for (int s = 0; s < 2; ++s)
+        for (int wp = 0; wp < dr; ++wp) {
+          const auto v = W.at(w, sp, s, wp);
+          if (v != std::complex<double>(0, 0)) nz[(size_t)sp * dr + wp].push_back({w, s, v});
+        }
+  std::vector<int> a_of((size_t)a.size() * dl);
+  for (int api = 0; api < a.size(); ++api)
+    for (int w = 0; w < dl; ++w) a_of[(size_t)api * dl + w] = a.find(qsub(a.q[api], W.ql[w], ly));
   for (int bi = 0; bi < b.size(); ++bi)
     for (int wp = 0; wp < dr; ++wp) {
       const int bpi = Lo.ap[bi * dr + wp];
@@ -532,11 +581,11 @@ EnvPlan plan_left(int ly, const Bond& a, const Bond& b, const MpoSite& W, const 
         const int api = a.find(qsub(b.q[bpi], W.qs[sp], ly));
         MixTask tk{t2off[bi] + (int64_t)ro * b.dim[bi], b.dim[bi], a.dim[api], b.dim[bi],
                    (int32_t)ep.mix.srcs.size(), 0, 0};
-        for (int w = 0; w < dl; ++w) {
-          for (int s = 0; s < 2; ++s) {
-            const auto v = W.at(w, sp, s, wp);
-            if (v == std::complex<double>(0, 0)) continue;
-            const int ai = a.find(qsub(a.q[api], W.ql[w], ly));
+        for (const MpoNz& e : nz[(size_t)sp * dr + wp]) {
+          const int w = e.w, s = e.s;
+          const auto v = e.v;
+          {
+            const int ai = a_of[(size_t)api * dl + w];
             if (ai < 0 || S.b[ai][s] != bi) continue;
             if (L.ap[ai * dl + w] != api) throw DmError{DM_ERR_CHARGE, "inconsistent MPO charges"};
             const int N = S.P.cols[ai];
@@ -626,6 +675,20 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
       t2off[(size_t)w * b.size() + bi] = ep.t2total;
       ep.t2total += (int64_t)rows * b.dim[bi];
     }
+  // nonzeros of W per (w, s'): (w', s, value); c = c' - q(w'); b = c - q(s)
+  std::vector<std::vector<MpoNz>> nz((size_t)dl * 2);
+  for (int w = 0; w < dl; ++w)
+    for (int sp = 0; sp < 2; ++sp)
+      for (int wp = 0; wp < dr; ++wp)
+        for (int s = 0; s < 2; ++s) {
+          const auto v = W.at(w, sp, s, wp);
+          if (v != std::complex<double>(0, 0)) nz[(size_t)w * 2 + sp].push_back({wp, s, v});
+        }
+  std::vector<int> c_of((size_t)c.size() * dr), b_of((size_t)c.size() * 2);
+  for (int cpi = 0; cpi < c.size(); ++cpi)
+    for (int wp = 0; wp < dr; ++wp) c_of[(size_t)cpi * dr + wp] = c.find(qsub(c.q[cpi], W.qr[wp], ly));
+  for (int ci = 0; ci < c.size(); ++ci)
+    for (int s = 0; s < 2; ++s) b_of[(size_t)ci * 2 + s] = b.find(qsub(c.q[ci], W.qs[s], ly));
   for (int w = 0; w < dl; ++w)
     for (int bi = 0; bi < b.size(); ++bi) {
       const int64_t base = t2off[(size_t)w * b.size() + bi];
@@ -637,21 +700,22 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
         const int cpi = S.b[bpi][sp];
         MixTask tk{base + (int64_t)ro * b.dim[bi], b.dim[bi], c.dim[cpi], b.dim[bi],
                    (int32_t)ep.mix.srcs.size(), 0, 0};
-        for (int wp = 0; wp < dr; ++wp)
-          for (int s = 0; s < 2; ++s) {
-            const auto v = W.at(w, sp, s, wp);
-            if (v == std::complex<double>(0, 0)) continue;
-            const int ci = c.find(qsub(c.q[cpi], W.qr[wp], ly));
+        for (const MpoNz& e : nz[(size_t)w * 2 + sp]) {
+          const int wp = e.w, s = e.s;
+          const auto v = e.v;
+          {
+            const int ci = c_of[(size_t)cpi * dr + wp];
             if (ci < 0) continue;
             const int64_t o = t1off[ci * 2 + s];
             if (o < 0) continue;
             const int ro1 = t1roff[((size_t)ci * 2 + s) * dr + wp];
             if (ro1 < 0) throw DmError{DM_ERR_CHARGE, "inconsistent MPO charges"};
-            if (b.find(qsub(c.q[ci], W.qs[s], ly)) != bi)
+            if (b_of[(size_t)ci * 2 + s] != bi)
               throw DmError{DM_ERR_CHARGE, "inconsistent MPO charges"};
             ep.mix.srcs.push_back({o + (int64_t)ro1 * b.dim[bi], b.dim[bi], 0, v.real(), v.imag()});
             tk.nsrc++;
           }
+        }
         ep.mix.flops += 8.0 * tk.nsrc * tk.rows * tk.cols;
         ep.mix.tasks.push_back(tk);
       }

@@ -89,9 +89,10 @@ GemmStage merge_gemm(const std::vector<const GemmStage*>& in, const std::vector<
   return m;
 }
 
+// Mixing tasks are short and memory-bound: they keep each plan's own order (tasks that
+// share source blocks are adjacent, and the kernel hands each XCD a contiguous run).
 MixStage merge_mix(const std::vector<const MixStage*>& in, const std::vector<Shift>& sh) {
   MixStage m;
-  std::vector<std::pair<double, MixTask>> tasks;
   for (size_t i = 0; i < in.size(); ++i) {
     const int32_t src0 = (int32_t)m.srcs.size();
     for (MixSrc s : in[i]->srcs) {
@@ -101,13 +102,10 @@ MixStage merge_mix(const std::vector<const MixStage*>& in, const std::vector<Shi
     for (MixTask t : in[i]->tasks) {
       t.dst += sh[i].c;
       t.src0 += src0;
-      tasks.emplace_back((double)t.rows * t.cols * t.nsrc, t);
+      m.tasks.push_back(t);
     }
     m.flops += in[i]->flops;
   }
-  std::stable_sort(tasks.begin(), tasks.end(),
-                   [](const auto& x, const auto& y) { return x.first > y.first; });
-  for (auto& t : tasks) m.tasks.push_back(t.second);
   return m;
 }
 

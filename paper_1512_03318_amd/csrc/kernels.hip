@@ -349,10 +349,15 @@ __global__ void __launch_bounds__(256) mix_kernel(const MixTask* __restrict__ ta
                                                   const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   const MixTask tk = tasks[blockIdx.x];
-  const int n = tk.rows * tk.cols;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int r = e / tk.cols;
-    const int c = e - r * tk.cols;
+  // element e = r * cols + c; (r, c) advance by blockDim.x elements without dividing
+  const int step_r = blockDim.x / tk.cols, step_c = blockDim.x - step_r * tk.cols;
+  int r = threadIdx.x / tk.cols, c = threadIdx.x - r * tk.cols;
+  for (; r < tk.rows; r += step_r, c += step_c) {
+    if (c >= tk.cols) {
+      c -= tk.cols;
+      ++r;
+      if (r >= tk.rows) break;
+    }
     T re = 0, im = 0;
     for (int q = 0; q < tk.nsrc; ++q) {
       const MixSrc sr = srcs[tk.src0 + q];
