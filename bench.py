@@ -15,9 +15,14 @@ Inputs are resident in HBM before the timed region: the library's own Hofstadter
 environments contracted on the GPU from seeded isometries (workloads), and a seeded
 random start vector.  value = algorithmic GFLOP of the step / step time, where the
 flops are counted from the library's task tables (8 real flops per complex
-multiply-add, no padding).
+multiply-add, no padding).  Matrix products run in --prec (default bf16x3: bf16 hi/lo
+split products with FP32 accumulation); Lanczos is FP64 in every mode.  Afterwards the
+three precisions are compared on the same window (matvec time, cold start, and the
+warm-start gate against the converged FP64 ground state).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32|fp64]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec bf16x3|fp32|fp64]
+  python bench.py --workload ly10_chi6000 --compare-real   (real-space basis ratios)
+  python bench.py --batched                                  (64 independent windows)
 """
 import argparse
 import json
@@ -110,8 +115,9 @@ def step_flops(plan, k, prec, env_flops, pk):
     return n_mv * mv + sum(env_flops)
 
 
-def matvec_time(pk, torch, inp, prec, stream, reps=20):
-    plan = pk.HeffPlan(inp["ly"], inp["a"], inp["c"], inp["w1"], inp["w2"], inp["L"], inp["R"], prec, stream)
+def matvec_time(pk, torch, inp, prec, stream, reps=20, plan=None):
+    if plan is None:
+        plan = pk.HeffPlan(inp["ly"], inp["a"], inp["c"], inp["w1"], inp["w2"], inp["L"], inp["R"], prec, stream)
     x = inp["theta"]
     y = torch.empty_like(x)
     for _ in range(3):
@@ -124,6 +130,109 @@ def matvec_time(pk, torch, inp, prec, stream, reps=20):
     ev[1].record(s)
     torch.cuda.synchronize()
     return ev[0].elapsed_time(ev[1]) / reps, sum(plan.flops), plan.flops
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain streaming kernel of known traffic (read nbytes, write nbytes per launch):
+    the reference against which the HBM byte counters of the other kernels are scaled."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_kernel": "elementwise neg (float32)", "read_bytes": nbytes,
+                      "write_bytes": nbytes, "launches": reps}), flush=True)
+
+
+def stage_rooflines(pk, plan, prec, pname, prof, nmv):
+    """Roofline of each matvec stage from its in-run device time (HIP events on the
+    launch stream, averaged over the timed matvecs) and its algorithmic work: block GEMMs
+    against the matrix-core peak of their arithmetic, the mixing against HBM bandwidth
+    with algorithmic bytes = read X once + write Z once.  The dominant (longest) stage is
+    the reported one."""
+    eb = 16 if prec == pk.DM_FP64 else 8
+    avg = [p / max(nmv, 1) for p in prof]
+    gemm = {pk.DM_FP64: ("gemm_kernel<double, 0, false>", "gemm_kernel<double, 20, true>"),
+            pk.DM_FP32: ("gemm_kernel<float, 0, false>", "gemm_kernel<float, 20, true>"),
+            pk.DM_BF16X3: ("gemm_bf3_kernel<0, false>", "gemm_bf3_kernel<20, true>")}[prec]
+    mixk = "mix_kernel<double>" if prec == pk.DM_FP64 else "mix_kernel<float>"
+    peak = PEAK_TFLOPS[pname]
+    stages = []
+    for i, (kern, what) in enumerate([(gemm[0], "L.theta block GEMM"), (mixk, "MPO mixing"),
+                                      (gemm[1], "(.).R block GEMM")]):
+        t = avg[i] * 1e-3
+        if i == 1:
+            nbytes = (plan.sizes["X"] + plan.sizes["Z"]) * eb
+            ach = nbytes / t / 1e9
+            r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_GBS, "unit": "GB/s",
+                 "frac": round(ach / HBM_GBS, 4), "algorithmic_bytes": nbytes}
+        else:
+            ach = plan.flops[i] / t / 1e12
+            r = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                 "frac": round(ach / peak, 4), "algorithmic_flops": plan.flops[i]}
+            if prec == pk.DM_BF16X3:
+                r["hw_products_per_algorithmic"] = 3   # hi*hi + hi*lo + lo*hi per real product
+        r.update({"kernel": f"{kern} ({what}, {pname})", "avg_launch_ms": round(avg[i], 4),
+                  "traffic": None})
+        stages.append(r)
+    dom = max(range(3), key=lambda i: avg[i])
+    out = dict(stages[dom])
+    out["stages"] = stages
+    out["k_split_reduction_ms"] = round(avg[3], 4)
+    return out
+
+
+def precision_report(pk, torch, inp, iters, stream, noise=1e-3, reps=3):
+    """Per precision: matvec time, cold-start Lanczos energy (same seeded start vector as
+    the timed steps), and the warm-start gate: the start vector is the FP64 ground state
+    (restarted FP64 Lanczos until the energy is stationary to 1e-15) plus seeded noise of
+    relative size `noise`; reported are |E - E_gs| / |E_gs|, 1 - |<theta_gs|theta>| and
+    the median wall time of the solve (max `iters` steps)."""
+    precs = {"fp64": pk.DM_FP64, "fp32": pk.DM_FP32, "bf16x3": pk.DM_BF16X3}
+    mk = lambda q: pk.HeffPlan(inp["ly"], inp["a"], inp["c"], inp["w1"], inp["w2"], inp["L"], inp["R"],
+                               q, stream)
+    plan64 = mk(pk.DM_FP64)
+    gs = inp["theta"].clone()
+    e_gs, e_prev, restarts = 0.0, None, 0
+    for restarts in range(1, 41):
+        e_gs, _ = pk.lanczos_ground(plan64, gs, iters, 1e-14, stream)
+        if e_prev is not None and abs(e_gs - e_prev) <= 1e-15 * abs(e_gs):
+            break
+        e_prev = e_gs
+    gs = gs / torch.linalg.vector_norm(gs)
+    hv = torch.empty_like(gs)
+    pk.heff_apply(plan64, gs, hv, stream)
+    resid = float(torch.linalg.vector_norm(hv - e_gs * gs))
+    g = torch.Generator().manual_seed(2024)
+    nz = torch.complex(torch.randn(gs.numel(), generator=g, dtype=torch.float64),
+                       torch.randn(gs.numel(), generator=g, dtype=torch.float64)).to(gs.device)
+    warm = gs + noise * nz / torch.linalg.vector_norm(nz)
+    warm = warm / torch.linalg.vector_norm(warm)
+    out = {"ground_state": {"energy": e_gs, "restarts": restarts, "residual": resid, "noise": noise}}
+    for name, q in precs.items():
+        plan = mk(q)
+        ms, _, _ = matvec_time(pk, torch, inp, q, stream, plan=plan)
+        cold = inp["theta"].clone()
+        e_cold, _ = pk.lanczos_ground(plan, cold, iters, 1e-14, stream)
+        ts, e, k, x = [], 0.0, 0, None
+        for _ in range(reps):
+            x = warm.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, k = pk.lanczos_ground(plan, x, iters, 1e-14, stream)
+            ts.append(time.perf_counter() - t0)
+        x = x / torch.linalg.vector_norm(x)
+        ov = 1.0 - float(torch.abs(torch.vdot(gs, x)))
+        out[name] = {"matvec_ms": round(ms, 4), "matvec_gflops": round(sum(plan.flops) / ms / 1e6, 2),
+                     "lanczos_warm_ms": round(1e3 * statistics.median(ts), 3), "warm_steps": k,
+                     "warm_rel_energy_err": abs(e - e_gs) / abs(e_gs), "warm_1_minus_overlap": ov,
+                     "gate_passed": abs(e - e_gs) / abs(e_gs) <= 1e-9 and ov <= 1e-6,
+                     "cold_energy": e_cold}
+    for name in precs:
+        out[name]["cold_rel_energy_diff_vs_fp64"] = abs(out[name]["cold_energy"] - out["fp64"]["cold_energy"]) / \
+            abs(out["fp64"]["cold_energy"])
+    return out
 
 
 def cpu_baseline(wl, iters=30):
@@ -378,7 +487,7 @@ def batched_main(args):
            "value": round(len(plans) / wall, 2), "unit": "solves/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {pk.DM_FP64: "c128", pk.DM_FP32: "c64", pk.DM_BF16X3: "c64 (bf16x3 products)"}[prec],
+           "dtype": {pk.DM_FP64: "fp64", pk.DM_FP32: "fp32", pk.DM_BF16X3: "bf16x3"}[prec],
            "data": "synthetic",
            "config": {"workload": "batch64_ly4-8_chi200-2000", "instances": len(plans),
                       "lanczos_iters": iters, "precision": args.prec},
@@ -399,12 +508,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="ly8_chi3200")
-    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--compare-real", action="store_true",
                     help="also time the same window in the real-space basis (cost ratios)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain elementwise copy of 1 GiB (HBM counter calibration)")
     ap.add_argument("--batched", action="store_true",
                     help="64 independent windows in one batched Lanczos instead of one bond update")
     args = ap.parse_args()
@@ -414,6 +525,9 @@ def main():
         sys.exit(2)
     if args.batched:
         batched_main(args)
+        return
+    if args.copy_calibration:
+        copy_calibration()
         return
 
     import torch
@@ -449,7 +563,6 @@ def main():
         nmv += nm
         flops += step_flops(plan, k, prec, inp["env_flops"], pk)
         host.append(ts)
-        stage_flops = plan.flops
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = 1e3 * elapsed / args.steps
@@ -457,23 +570,12 @@ def main():
     lanczos_ms = 1e3 * statistics.median(t[1] for t in host)
     log(f"timed {args.steps} steps: {ms_step:.2f} ms/step, {value:.1f} GFLOP/s, lanczos {lanczos_ms:.2f} ms, E={e:.12f}")
 
-    # dominant kernel: the one with the most device time
-    names = ["L.theta block GEMM", "MPO mixing", "(.).R block GEMM", "K-split reduction"]
-    dom = max(range(3), key=lambda s: prof[s])
-    avg_ms = prof[dom] / max(nmv, 1)
-    achieved = stage_flops[dom] / (avg_ms * 1e-3) / 1e12
-    kern = {0: "gemm_kernel<T, 0, false>", 1: "mix_kernel<T>", 2: "gemm_kernel<T, 20, true>"}[dom]
-    roofline = {"bound": "mfma", "kernel": f"{kern} ({names[dom]}, {args.prec})",
-                "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS[args.prec], 4), "traffic": None,
-                "avg_launch_ms": round(avg_ms, 4),
-                "stage_ms_per_matvec": [round(p / max(nmv, 1), 4) for p in prof]}
-
+    roofline = stage_rooflines(pk, plan, prec, args.prec, prof, nmv)
     mv_ms, mv_flops, _ = matvec_time(pk, torch, inp, prec, stream)
     out = {"metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {pk.DM_FP64: "c128", pk.DM_FP32: "c64", pk.DM_BF16X3: "c64 (bf16x3 products)"}[prec], "data": "synthetic",
+           "dtype": {pk.DM_FP64: "fp64", pk.DM_FP32: "fp32", pk.DM_BF16X3: "bf16x3"}[prec], "data": "synthetic",
            "config": {"workload": args.workload, "Ly": wl.Ly, "Lx": wl.Lx, "flux": f"{wl.flux[0]}/{wl.flux[1]}",
                       "chi": int(sum(wl.bonds[wl.j].values())), "sectors": len(wl.bonds[wl.j]),
                       "mpo_D": list(inp["D"]), "lanczos_iters": args.iters, "precision": args.prec,
@@ -483,20 +585,14 @@ def main():
            "matvec_ms": round(mv_ms, 4), "matvec_gflops": round(mv_flops / mv_ms / 1e6, 2),
            "matvec_gflop": round(mv_flops / 1e9, 4),
            "roofline": roofline}
-    if not args.no_fp64_compare and prec != pk.DM_FP64:
-        f_ms, _, _ = matvec_time(pk, torch, inp, pk.DM_FP64, stream)
-        e64, k64, _, ts64 = run_step(pk, inp, pk.DM_FP64, args.iters, stream)
-        torch.cuda.synchronize()
-        hs = []
-        for _ in range(2):
-            e64, k64, _, ts64 = run_step(pk, inp, pk.DM_FP64, args.iters, stream)
-            hs.append(ts64)
-        out["fp64"] = {"matvec_ms": round(f_ms, 4), "matvec_gflops": round(mv_flops / f_ms / 1e6, 2),
-                       "lanczos_ms": round(1e3 * statistics.median(t[1] for t in hs), 3),
-                       "step_ms": round(1e3 * statistics.median(sum(t) for t in hs), 3),
-                       "energy": e64, "rel_energy_diff_cold_start": abs(e - e64) / abs(e64)}
-        out["speedup_vs_fp64"] = {"matvec": round(f_ms / mv_ms, 3),
-                                  "lanczos": round(out["fp64"]["lanczos_ms"] / lanczos_ms, 3)}
+    if not args.no_fp64_compare:
+        log("precision comparison (cold and warm start) ...")
+        out["precisions"] = precision_report(pk, torch, inp, args.iters, stream)
+        p = out["precisions"]
+        out["speedup_vs_fp64"] = {
+            q: {"matvec": round(p["fp64"]["matvec_ms"] / p[q]["matvec_ms"], 3),
+                "lanczos": round(p["fp64"]["lanczos_warm_ms"] / p[q]["lanczos_warm_ms"], 3)}
+            for q in ("fp32", "bf16x3")}
     if args.compare_real:
         log("real-space basis comparison ...")
         out["real_space"] = compare_real(pk, torch, wl, inp, prec, stream)

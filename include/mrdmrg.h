@@ -154,6 +154,11 @@ void dm_heff_plan_destroy(dm_heff_plan* p);
  * flops[1] = MPO mixing, flops[2] = (.).R block GEMMs. */
 int dm_heff_info(const dm_heff_plan* p, int64_t* theta_elems, double flops[3]);
 
+/* Complex elements of the plan's operands and intermediates: sizes[0] = L, sizes[1] = R,
+ * sizes[2] = theta, sizes[3] = X (L.theta panels), sizes[4] = Z (mixed panels).  The
+ * algorithmic bytes of a stage follow from these (each element read or written once). */
+int dm_heff_sizes(const dm_heff_plan* p, int64_t sizes[5]);
+
 /* Device-time profile of the matvec stages.  While enabled, every matvec of the plan
  * (heff_apply and the ones inside lanczos_ground) records HIP events on its stream
  * around each kernel; dm_heff_profile_read synchronises and returns the accumulated

@@ -56,6 +56,7 @@ _sigs = {
                                    C.POINTER(DmMpoSite), _vp, _vp, _i32, _vp, C.POINTER(_vp)]),
     "dm_heff_plan_destroy": (None, [_vp]),
     "dm_heff_info": (_i32, [_vp, C.POINTER(_i64), C.POINTER(_f64)]),
+    "dm_heff_sizes": (_i32, [_vp, C.POINTER(_i64)]),
     "heff_apply": (_i32, [_vp, _vp, _vp, _vp]),
     "lanczos_ground": (_i32, [_vp, _vp, _i32, _f64, C.POINTER(_f64), C.POINTER(_i32), _vp]),
     "env_update_left": (_i32, [_i32, C.POINTER(DmBond), C.POINTER(DmBond), C.POINTER(DmMpoSite),
@@ -215,6 +216,9 @@ class HeffPlan:
         _check(lib.dm_heff_info(h, C.byref(n), fl))
         self.n = n.value
         self.flops = tuple(fl)
+        sz = (_i64 * 5)()
+        _check(lib.dm_heff_sizes(h, sz))
+        self.sizes = dict(zip(("L", "R", "theta", "X", "Z"), (int(v) for v in sz)))
 
     def profile(self, enable=True):
         _check(lib.dm_heff_profile(self.h, 1 if enable else 0))

@@ -108,17 +108,21 @@ static void build_heff_tables(dm_heff_plan& p) {
       if (ai >= 0 && p.th.c[ai][s12] == ci) zap[ci][s12] = ai;
     }
   // S1: X_a = Lpanel_a (M_a x m_a) . Theta_a (m_a x N_a)
-  GemmStage& s1 = p.s1;
-  s1.flags = 0;
-  for (int ai = 0; ai < a.size(); ++ai) {
-    const int M = p.L.P.rows[ai], N = p.th.P.cols[ai], K = a.dim[ai];
-    if (M == 0 || N == 0) continue;
-    GemmProb pr{p.xoff[ai], M, N, (int32_t)s1.segs.size(), 1, N, -1};
-    s1.segs.push_back({p.L.P.off[ai], p.th.P.off[ai], K, N, K, 0});
-    s1.probs.push_back(pr);
-    add_tiles(s1, (int32_t)s1.probs.size() - 1, M, N);
-    s1.flops += 8.0 * M * N * K;
-  }
+  auto build_s1 = [&](GemmStage& s1, bool bf3) {
+    s1.flags = 0;
+    if (bf3) s1.tile_m = 128;  // 128 x 64 tiles for the bf16 matrix cores
+    for (int ai = 0; ai < a.size(); ++ai) {
+      const int M = p.L.P.rows[ai], N = p.th.P.cols[ai], K = a.dim[ai];
+      if (M == 0 || N == 0) continue;
+      GemmProb pr{p.xoff[ai], M, N, (int32_t)s1.segs.size(), 1, N, -1};
+      s1.segs.push_back({p.L.P.off[ai], p.th.P.off[ai], K, N, K, 0});
+      s1.probs.push_back(pr);
+      add_tiles(s1, (int32_t)s1.probs.size() - 1, M, N);
+      s1.flops += 8.0 * M * N * K;
+    }
+  };
+  build_s1(p.s1, p.prec == DM_BF16X3);
+  if (p.prec == DM_BF16X3) build_s1(p.s1f, false);
   // two-site MPO W12[w, s12', s12, w''] = sum_w' W1[w, s1', s1, w'] W2[w', s2', s2, w'']
   std::vector<std::complex<double>> w12((size_t)dl * 16 * dr);
   auto W12 = [&](int w, int sp, int s, int wpp) -> std::complex<double>& {
@@ -221,24 +225,38 @@ static void build_heff_tables(dm_heff_plan& p) {
   // (.)R stage, one problem per output sector c':
   //   theta'[(s12', a'), c'] = Z_{c'} (M x K) . Rpanel_{c'}^T (K x m_c'), K = R panel width,
   // rows scattered to the theta blocks through the row table.  K-split over workgroups.
-  GemmStage& s4 = p.s4;
-  s4.flags = G_B_T | G_C_ROWMAP;
-  s4.deep = true;
-  for (int ci2 = 0; ci2 < c.size(); ++ci2) {
-    const int M = p.zrows[ci2], N = c.dim[ci2], K = p.R.P.cols[ci2];
-    if (M == 0) continue;
-    GemmProb pr{0, M, N, (int32_t)s4.segs.size(), K > 0 ? 1 : 0, 0, (int32_t)s4.rows.size()};
-    for (int s12p = 0; s12p < 4; ++s12p) {
-      const int aip = zap[ci2][s12p];
-      if (aip < 0) continue;
-      const int64_t base = p.th.P.off[aip] + p.th.coff[aip][s12p];
-      for (int r = 0; r < a.dim[aip]; ++r) s4.rows.push_back(base + (int64_t)r * p.th.P.cols[aip]);
+  auto build_s4 = [&](GemmStage& s4, bool bf3) {
+    s4.flags = G_B_T | G_C_ROWMAP;
+    s4.split = true;
+    if (bf3) {  // 128 x 32 tiles, K split over workgroups in runs of >= 6 chunks of 32
+      s4.tile_m = 128;
+      s4.tile_n = 32;
+      s4.kc = 32;
+      s4.split_min = 6;
+    } else {    // 32 x 32 tiles shared by four waves, >= 4 chunks of 64 per split
+      s4.deep = true;
+      s4.tile_m = s4.tile_n = 32;
+      s4.kc = 64;
+      s4.split_min = 4;
     }
-    if (K > 0) s4.segs.push_back({p.zoff[ci2], p.R.P.off[ci2], K, K, K, 0});
-    s4.probs.push_back(pr);
-    add_tiles(s4, (int32_t)s4.probs.size() - 1, M, N);
-    s4.flops += 8.0 * M * N * K;
-  }
+    for (int ci2 = 0; ci2 < c.size(); ++ci2) {
+      const int M = p.zrows[ci2], N = c.dim[ci2], K = p.R.P.cols[ci2];
+      if (M == 0) continue;
+      GemmProb pr{0, M, N, (int32_t)s4.segs.size(), K > 0 ? 1 : 0, 0, (int32_t)s4.rows.size()};
+      for (int s12p = 0; s12p < 4; ++s12p) {
+        const int aip = zap[ci2][s12p];
+        if (aip < 0) continue;
+        const int64_t base = p.th.P.off[aip] + p.th.coff[aip][s12p];
+        for (int r = 0; r < a.dim[aip]; ++r) s4.rows.push_back(base + (int64_t)r * p.th.P.cols[aip]);
+      }
+      if (K > 0) s4.segs.push_back({p.zoff[ci2], p.R.P.off[ci2], K, K, K, 0});
+      s4.probs.push_back(pr);
+      add_tiles(s4, (int32_t)s4.probs.size() - 1, M, N);
+      s4.flops += 8.0 * M * N * K;
+    }
+  };
+  build_s4(p.s4, p.prec == DM_BF16X3);
+  if (p.prec == DM_BF16X3) build_s4(p.s4f, false);
 }
 
 extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* c,
@@ -270,10 +288,14 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     validate(p->s1, p->L.P.total, p->n(), p->xtotal);
     validate(p->mix, p->xtotal, p->ztotal);
     validate(p->s4, p->ztotal, p->R.P.total, p->n());
+    validate(p->s1f, p->L.P.total, p->n(), p->xtotal);
+    validate(p->s4f, p->ztotal, p->R.P.total, p->n());
     {
       TableUpload up;
       up.add(p->s1);
       up.add(p->s4);
+      up.add(p->s1f);
+      up.add(p->s4f);
       up.add(p->mix);
       p->dTables = up.commit();
     }
@@ -283,7 +305,7 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     p->dR = dev_alloc(p->R.P.total * eb);
     p->dX = dev_alloc(p->xtotal * eb);
     p->dZ = dev_alloc(p->ztotal * eb);
-    p->dSplit = dev_alloc(p->s4.nslots * 1024 * eb);
+    p->dSplit = dev_alloc(p->s4.nslots * p->s4.slot_elems() * eb);
     hipStream_t s = (hipStream_t)stream;
     stage_in(L, p->dL, p->L.P.total, prec, s);
     stage_in(R, p->dR, p->R.P.total, prec, s);
@@ -321,6 +343,16 @@ extern "C" int dm_heff_info(const dm_heff_plan* p, int64_t* theta_elems, double 
   return DM_OK;
 }
 
+extern "C" int dm_heff_sizes(const dm_heff_plan* p, int64_t sizes[5]) {
+  if (!p || !sizes) return fail(DM_ERR_ARG, "null argument");
+  sizes[0] = p->L.P.total;
+  sizes[1] = p->R.P.total;
+  sizes[2] = p->n();
+  sizes[3] = p->xtotal;
+  sizes[4] = p->ztotal;
+  return DM_OK;
+}
+
 static hipEvent_t* prof_slot(dm_heff_plan* p) {
   if (!p->profiling) return nullptr;
   if (p->ev_used == p->ev.size()) {
@@ -347,17 +379,18 @@ void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStrea
     if (p->prec != DM_FP64) {
       if (!p->dX64) p->dX64 = dev_alloc(p->xtotal * 16);
       if (!p->dZ64) p->dZ64 = dev_alloc(p->ztotal * 16);
-      if (!p->dSplit64) p->dSplit64 = dev_alloc(p->s4.nslots * 1024 * 16);
+      if (!p->dSplit64) p->dSplit64 = dev_alloc(p->rq_s4().nslots * p->rq_s4().slot_elems() * 16);
       dX = p->dX64;
       dZ = p->dZ64;
       dP = p->dSplit64;
     }
     mark(0);
-    HIPCHK(launch_gemm<double>(p->s1, (const double*)dL, (const double*)theta, (double*)dX, nullptr, s, skip));
+    HIPCHK(launch_gemm<double>(p->rq_s1(), (const double*)dL, (const double*)theta, (double*)dX, nullptr,
+                               s, skip));
     mark(1);
     HIPCHK(launch_mix<double>(p->mix, (const double*)dX, (double*)dZ, s, skip));
     mark(2);
-    HIPCHK(launch_gemm<double>(p->s4, (const double*)dZ, (const double*)dR, (double*)theta_out,
+    HIPCHK(launch_gemm<double>(p->rq_s4(), (const double*)dZ, (const double*)dR, (double*)theta_out,
                                (double*)dP, s, skip, [&] { mark(3); }));
     mark(4);
     return;
@@ -441,7 +474,7 @@ void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
   if (p->prec != DM_FP64) {
     if (!p->dX64) p->dX64 = dev_alloc(p->xtotal * 16);
     if (!p->dZ64) p->dZ64 = dev_alloc(p->ztotal * 16);
-    if (!p->dSplit64) p->dSplit64 = dev_alloc(p->s4.nslots * 1024 * 16);
+    if (!p->dSplit64) p->dSplit64 = dev_alloc(p->rq_s4().nslots * p->rq_s4().slot_elems() * 16);
   }
 }
 

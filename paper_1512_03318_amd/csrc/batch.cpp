@@ -35,20 +35,25 @@ struct Shift {
 // Work of one tile in staged K chunks (the kernel's run time is set by its K loop).
 double tile_cost(const GemmStage& st, const GemmTile& t) {
   const GemmProb& p = st.probs[t.prob];
-  const int kc = st.deep ? 64 : 32;
   double chunks = 0;
-  for (int g = 0; g < p.nseg; ++g) chunks += (st.segs[p.seg0 + g].k + kc - 1) / kc;
-  return st.deep ? chunks / std::max(1, p.nks) : chunks;
+  for (int g = 0; g < p.nseg; ++g) chunks += (st.segs[p.seg0 + g].k + st.kc - 1) / st.kc;
+  return chunks / std::max(1, p.nks);
 }
 
 GemmStage merge_gemm(const std::vector<const GemmStage*>& in, const std::vector<Shift>& sh) {
   GemmStage m;
   m.flags = in[0]->flags;
   m.deep = in[0]->deep;
+  m.tile_m = in[0]->tile_m;
+  m.tile_n = in[0]->tile_n;
+  m.split = in[0]->split;
+  m.kc = in[0]->kc;
+  m.split_min = in[0]->split_min;
   std::vector<std::pair<double, GemmTile>> tiles;
   for (size_t i = 0; i < in.size(); ++i) {
     const GemmStage& st = *in[i];
-    if (st.flags != m.flags || st.deep != m.deep)
+    if (st.flags != m.flags || st.deep != m.deep || st.tile_m != m.tile_m || st.tile_n != m.tile_n ||
+        st.split != m.split)
       throw DmError{DM_ERR_ARG, "batched plans have different stage kinds"};
     if (st.flags & G_A_MIX) throw DmError{DM_ERR_ARG, "mixed operands cannot be batched"};
     const int32_t seg0 = (int32_t)m.segs.size(), prob0 = (int32_t)m.probs.size();
@@ -203,8 +208,8 @@ MergedMatvec build_merged(dm_batch& b, bool f64) {
   std::vector<Shift> sh1, sh4, shm;
   for (size_t i = 0; i < b.plans.size(); ++i) {
     const Bufs& q = bufs[i];
-    s1.push_back(&b.plans[i]->s1);
-    s4.push_back(&b.plans[i]->s4);
+    s1.push_back(f64 ? &b.plans[i]->rq_s1() : &b.plans[i]->s1);
+    s4.push_back(f64 ? &b.plans[i]->rq_s4() : &b.plans[i]->s4);
     mx.push_back(&b.plans[i]->mix);
     sh1.push_back({rb.shift(q.L), rb.shift(q.in), rb.shift(q.X)});
     shm.push_back({rb.shift(q.X), 0, rb.shift(q.Z)});
@@ -214,7 +219,7 @@ MergedMatvec build_merged(dm_batch& b, bool f64) {
   m.mix = merge_mix(mx, shm);
   m.s4 = merge_gemm(s4, sh4);
   m.base = rb.base;
-  m.split = dev_alloc((size_t)m.s4.nslots * 1024 * rb.eb);
+  m.split = dev_alloc((size_t)m.s4.nslots * m.s4.slot_elems() * rb.eb);
   return m;
 }
 

@@ -35,26 +35,31 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * q + min(x, r) + (b >> 3);
 }
 
-// Sums the K-split partial tiles of one output tile in split order and stores it.
+// Sums the K-split partial tiles (tm x tn each) of one output tile in split order and
+// stores it.  Block (x, y): output tile x, elements [1024 y, 1024 y + 1024) of the tile.
 template <typename T, int FLAGS>
 __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const GemmProb* __restrict__ probs,
                                                                 const GemmTile* __restrict__ tiles,
                                                                 const int64_t* __restrict__ rows,
                                                                 const T* __restrict__ part,
-                                                                T* __restrict__ C,
+                                                                T* __restrict__ C, int tm, int tn,
                                                                 const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   const GemmTile tile = tiles[blockIdx.x];
   const GemmProb P = probs[tile.prob];
-  const int tiles_n = (P.N + 31) / 32;
+  const int tiles_n = (P.N + tn - 1) / tn;
+  const int64_t slot = (int64_t)tm * tn;
   const int64_t base = (int64_t)P.slot0 + ((int64_t)tile.tm * tiles_n + tile.tn) * P.nks;
-  for (int e = threadIdx.x; e < 1024; e += 256) {
-    const int r = e >> 5, c = e & 31;
-    const int i = tile.tm * 32 + r, j = tile.tn * 32 + c;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = blockIdx.y * 1024 + q * 256 + threadIdx.x;
+    if (e >= tm * tn) break;
+    const int r = e / tn, c = e - r * tn;
+    const int i = tile.tm * tm + r, j = tile.tn * tn + c;
     if (i >= P.M || j >= P.N) continue;
     T re = 0, im = 0;
     for (int ks = 0; ks < P.nks; ++ks) {
-      const Cplx<T> v = ldc(part, (base + ks) * 1024 + e);
+      const Cplx<T> v = ldc(part, (base + ks) * slot + e);
       re += v.re;
       im += v.im;
     }

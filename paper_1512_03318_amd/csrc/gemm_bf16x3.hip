@@ -8,8 +8,14 @@
 // dropping xl yl (relative <= 2^-18) -- about 16 significant bits per product instead of
 // FP32's 24, at the rate of the bf16 matrix cores.  The complex product takes four real
 // products (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br), so twelve MFMAs per 16x16x32
-// complex sub-block.  The task tables, tiles and K-split are those of the FP32/FP64
-// kernels, so the host planner is shared.
+// complex sub-block.
+//
+// Because the bf16 matrix cores are fast, these tiles are larger than those of the
+// FP32/FP64 kernels (more reuse of every staged element): BM x BN per workgroup of four
+// waves arranged WM x WN, each wave (BM/WM) x (BN/WN) in 16 x 16 MFMA blocks, K staged
+// in chunks of 32.  With SPLIT the K range of a problem is divided over nks workgroups
+// (chunks ks, ks + nks, ...) that write partial tiles, summed in split order by
+// gemm_split_reduce_kernel.
 //
 // MFMA 16x16x32 bf16 operands (8 bf16 per lane): A(i, k) with i = lane % 16 and
 // k = 8 (lane / 16) + t, B(k, j) with j = lane % 16 and the same k; result row
@@ -35,20 +41,18 @@ __device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
-template <int FLAGS, bool DEEP>
+template <int FLAGS, int BM, int BN, int WM, int WN>
 struct Bf3Cfg {
-  static constexpr int KC = DEEP ? 128 : 32;  // K chunk; DEEP: 32 per wave
-  static constexpr int BM = DEEP ? 32 : 64;
-  static constexpr int BN = BM;
+  static constexpr int KC = 32;                // K chunk = one bf16 MFMA step
   static constexpr int LD = KC + 8;            // LDS row stride (bf16), 16-byte pad
   static constexpr int QA = BM * KC / 4 / 256;  // k-quads of A staged per thread
   static constexpr int QB = BN * KC / 4 / 256;
+  static constexpr int XB = BM / WM / 16, YB = BN / WN / 16;  // MFMA blocks per wave
   static constexpr bool A_KC = !(FLAGS & G_A_T);
   static constexpr bool B_KC = (FLAGS & G_B_T) != 0;
   static constexpr int PLANE_A = BM * LD, PLANE_B = BN * LD;  // bf16 per plane
-  static constexpr int STAGE_BYTES = 2 * 4 * (PLANE_A + PLANE_B);
-  static constexpr int RED_BYTES = DEEP ? 3 * 32 * 64 * 4 : 0;
-  static constexpr int SMEM = STAGE_BYTES > RED_BYTES ? STAGE_BYTES : RED_BYTES;
+  static constexpr int SMEM = 2 * 4 * (PLANE_A + PLANE_B);  // bytes: 4 parts of bf16
+  static_assert(WM * WN == 4 && QA >= 1 && QB >= 1 && XB >= 1 && YB >= 1, "tile shape");
 };
 
 // quad q of this thread -> (row, first k of the quad) of an R x KC chunk
@@ -77,7 +81,7 @@ __device__ __forceinline__ void split_store(const Cplx<float> (&v)[4], __bf16* p
   *reinterpret_cast<bf16x4*>(plane + 3 * plane_sz + off) = il;
 }
 
-template <int FLAGS, bool DEEP>
+template <int FLAGS, int BM, int BN, int WM, int WN, bool SPLIT>
 __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict__ segs,
                                                        const GemmProb* __restrict__ probs,
                                                        const GemmTile* __restrict__ tiles,
@@ -88,8 +92,8 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
                                                        float* __restrict__ part,
                                                        const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  typedef Bf3Cfg<FLAGS, DEEP> G;
-  constexpr int BM = G::BM, BN = G::BN, KC = G::KC, LD = G::LD, QA = G::QA, QB = G::QB;
+  typedef Bf3Cfg<FLAGS, BM, BN, WM, WN> G;
+  constexpr int KC = G::KC, LD = G::LD, QA = G::QA, QB = G::QB, XB = G::XB, YB = G::YB;
   __shared__ __attribute__((aligned(16))) char smem[G::SMEM];
   __bf16* sA = reinterpret_cast<__bf16*>(smem);          // [4 parts][BM][LD]
   __bf16* sB = sA + 4 * G::PLANE_A;                      // [4 parts][BN][LD]
@@ -100,8 +104,8 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
   const GemmTile tile = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const GemmProb P = probs[tile.prob];
   const int i0 = tile.tm * BM, j0 = tile.tn * BN;
-  const int kfirst = DEEP ? tile.ks * KC : 0;
-  const int kstep = DEEP ? P.nks * KC : KC;
+  const int kfirst = SPLIT ? tile.ks * KC : 0;
+  const int kstep = SPLIT ? P.nks * KC : KC;
 
   int64_t arow[QA];
 #pragma unroll
@@ -151,16 +155,16 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
     }
   };
 
-  f32x4 cre[2][2], cim[2][2];
+  f32x4 cre[XB][YB], cim[XB][YB];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < XB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
+    for (int y = 0; y < YB; ++y) {
       cre[x][y] = f32x4{0, 0, 0, 0};
       cim[x][y] = f32x4{0, 0, 0, 0};
     }
-  const int wr = DEEP ? 0 : (wave & 1) * 32;
-  const int wc = DEEP ? 0 : (wave >> 1) * 32;
+  const int wr = (wave % WM) * (BM / WM);
+  const int wc = (wave / WM) * (BN / WN);
 
   int sg = 0, k0 = kfirst;
   GemmSeg S;
@@ -172,7 +176,6 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
   }
   if (sg < P.nseg) load_chunk(S, k0);
   while (sg < P.nseg) {
-    const int kc = min(KC, S.k - k0);
     __syncthreads();  // previous chunk fully consumed
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
@@ -194,92 +197,61 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
       k0 = kfirst;
     }
     if (sg < P.nseg) load_chunk(S, k0);
-    // k positions >= kc were staged as zeros, so whole 32-wide steps are exact
-    const int kbeg = DEEP ? wave * 32 : 0;
-    const int kend = DEEP ? min(kbeg + 32, kc) : kc;
-    for (int kb = kbeg; kb < kend; kb += 32) {
-      bf16x8 a[2][4], b[2][4];
+    // k positions beyond the chunk's valid range were staged as zeros
+    bf16x8 b[YB][4];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < YB; ++y)
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
-          a[x][p] = *reinterpret_cast<const bf16x8*>(sA + p * G::PLANE_A + (wr + x * 16 + li) * LD + kb + 8 * lk);
+      for (int p = 0; p < 4; ++p)
+        b[y][p] = *reinterpret_cast<const bf16x8*>(sB + p * G::PLANE_B + (wc + y * 16 + li) * LD + 8 * lk);
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+    for (int x = 0; x < XB; ++x) {
+      bf16x8 a[4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p)
-          b[y][p] = *reinterpret_cast<const bf16x8*>(sB + p * G::PLANE_B + (wc + y * 16 + li) * LD + kb + 8 * lk);
+      for (int p = 0; p < 4; ++p)
+        a[p] = *reinterpret_cast<const bf16x8*>(sA + p * G::PLANE_A + (wr + x * 16 + li) * LD + 8 * lk);
       // parts: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
+      const bf16x8 nih = neg8(a[2]), nil = neg8(a[3]);
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        const bf16x8 nih = neg8(a[x][2]), nil = neg8(a[x][3]);
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          cre[x][y] = mfma_bf16(a[x][1], b[y][0], cre[x][y]);
-          cim[x][y] = mfma_bf16(a[x][1], b[y][2], cim[x][y]);
-          cre[x][y] = mfma_bf16(a[x][0], b[y][1], cre[x][y]);
-          cim[x][y] = mfma_bf16(a[x][0], b[y][3], cim[x][y]);
-          cre[x][y] = mfma_bf16(nil, b[y][2], cre[x][y]);
-          cim[x][y] = mfma_bf16(a[x][3], b[y][0], cim[x][y]);
-          cre[x][y] = mfma_bf16(nih, b[y][3], cre[x][y]);
-          cim[x][y] = mfma_bf16(a[x][2], b[y][1], cim[x][y]);
-          cre[x][y] = mfma_bf16(a[x][0], b[y][0], cre[x][y]);
-          cim[x][y] = mfma_bf16(a[x][0], b[y][2], cim[x][y]);
-          cre[x][y] = mfma_bf16(nih, b[y][2], cre[x][y]);
-          cim[x][y] = mfma_bf16(a[x][2], b[y][0], cim[x][y]);
-        }
+      for (int y = 0; y < YB; ++y) {
+        cre[x][y] = mfma_bf16(a[1], b[y][0], cre[x][y]);
+        cim[x][y] = mfma_bf16(a[1], b[y][2], cim[x][y]);
+        cre[x][y] = mfma_bf16(a[0], b[y][1], cre[x][y]);
+        cim[x][y] = mfma_bf16(a[0], b[y][3], cim[x][y]);
+        cre[x][y] = mfma_bf16(nil, b[y][2], cre[x][y]);
+        cim[x][y] = mfma_bf16(a[3], b[y][0], cim[x][y]);
+        cre[x][y] = mfma_bf16(nih, b[y][3], cre[x][y]);
+        cim[x][y] = mfma_bf16(a[2], b[y][1], cim[x][y]);
+        cre[x][y] = mfma_bf16(a[0], b[y][0], cre[x][y]);
+        cim[x][y] = mfma_bf16(a[0], b[y][2], cim[x][y]);
+        cre[x][y] = mfma_bf16(nih, b[y][2], cre[x][y]);
+        cim[x][y] = mfma_bf16(a[2], b[y][0], cim[x][y]);
       }
     }
   }
 
-  if constexpr (DEEP) {
-    float (*red)[32][64] = reinterpret_cast<float (*)[32][64]>(smem);
-    __syncthreads();  // staging planes are no longer read
-    if (wave > 0) {
+  if (SPLIT && P.nks > 1) {
+    // partial tile of this K split, summed later by gemm_split_reduce_kernel
+    const int tiles_n = (P.N + BN - 1) / BN;
+    float* dst = part + 2 * ((int64_t)P.slot0 + ((int64_t)tile.tm * tiles_n + tile.tn) * P.nks + tile.ks) * (BM * BN);
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < XB; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            red[wave - 1][((x * 2 + y) * 4 + r) * 2][lane] = cre[x][y][r];
-            red[wave - 1][((x * 2 + y) * 4 + r) * 2 + 1][lane] = cim[x][y][r];
-          }
-    }
-    __syncthreads();
-    if (wave != 0) return;
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int e = ((x * 2 + y) * 4 + r) * 2;
-          cre[x][y][r] = ((cre[x][y][r] + red[0][e][lane]) + red[1][e][lane]) + red[2][e][lane];
-          cim[x][y][r] = ((cim[x][y][r] + red[0][e + 1][lane]) + red[1][e + 1][lane]) + red[2][e + 1][lane];
-        }
-    if (P.nks > 1) {
-      const int tiles_n = (P.N + BN - 1) / BN;
-      float* dst = part + 2 * ((int64_t)P.slot0 + ((int64_t)tile.tm * tiles_n + tile.tn) * P.nks + tile.ks) * 1024;
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-            stc(dst, (x * 16 + 4 * lk + r) * 32 + y * 16 + li, cre[x][y][r], cim[x][y][r]);
-      return;
-    }
+        for (int y = 0; y < YB; ++y)
+          stc(dst, (wr + x * 16 + 4 * lk + r) * BN + wc + y * 16 + li, cre[x][y][r], cim[x][y][r]);
+    return;
   }
 #pragma unroll
-  for (int x = 0; x < 2; ++x) {
+  for (int x = 0; x < XB; ++x) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = i0 + wr + x * 16 + 4 * lk + r;
       if (i >= P.M) continue;
       const int64_t rbase = (FLAGS & G_C_ROWMAP) ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
+      for (int y = 0; y < YB; ++y) {
         const int j = j0 + wc + y * 16 + li;
         if (j < P.N) stc(C, rbase + j, cre[x][y][r], cim[x][y][r]);
       }
@@ -295,21 +267,26 @@ hipError_t launch_gemm_bf16x3(const GemmStage& st, const float* A, const float* 
   if (st.nslots > 0 && !part) return hipErrorInvalidValue;
   if (st.flags & G_A_MIX) return hipErrorInvalidValue;
   dim3 grid(nt), block(256);
-#define MRD_BF3_CASE(F, D)                                                                  \
-  if (st.flags == (F) && st.deep == (D)) {                                                  \
-    hipLaunchKernelGGL((gemm_bf3_kernel<F, D>), grid, block, 0, s, st.d_segs, st.d_probs,   \
-                       st.d_tiles, st.d_rows, A, B, C, part, skip);                         \
-    if (between) between();                                                                 \
-    if (D && !st.red_tiles.empty())                                                         \
-      hipLaunchKernelGGL((gemm_split_reduce_kernel<float, F>), dim3(st.red_tiles.size()),   \
-                         block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C, skip);\
-    return hipGetLastError();                                                               \
+#define MRD_BF3_CASE(F, TM, TN, WM, WN, SP)                                                     \
+  if (st.flags == (F) && st.tile_m == (TM) && st.tile_n == (TN) && st.split == (SP)) {          \
+    hipLaunchKernelGGL((gemm_bf3_kernel<F, TM, TN, WM, WN, SP>), grid, block, 0, s, st.d_segs,  \
+                       st.d_probs, st.d_tiles, st.d_rows, A, B, C, part, skip);                 \
+    if (between) between();                                                                     \
+    if (SP && !st.red_tiles.empty())                                                            \
+      hipLaunchKernelGGL((gemm_split_reduce_kernel<float, F>),                                  \
+                         dim3(st.red_tiles.size(), (TM * TN + 1023) / 1024),                    \
+                         block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C, TM, TN,   \
+                         skip);                                                                 \
+    return hipGetLastError();                                                                   \
   }
-  MRD_BF3_CASE(0, false)
-  MRD_BF3_CASE(G_A_T | G_A_CONJ, false)
-  MRD_BF3_CASE(G_A_ROWMAP | G_B_T, false)
-  MRD_BF3_CASE(G_A_CONJ, false)
-  MRD_BF3_CASE(G_B_T | G_C_ROWMAP, true)
+  // short-K stages: 128 x 64 (L.theta) or 64 x 64 tiles; long-K stages: 128 x 32 with
+  // the K range split over workgroups
+  MRD_BF3_CASE(0, 128, 64, 2, 2, false)
+  MRD_BF3_CASE(0, 64, 64, 2, 2, false)
+  MRD_BF3_CASE(G_A_T | G_A_CONJ, 64, 64, 2, 2, false)
+  MRD_BF3_CASE(G_A_ROWMAP | G_B_T, 64, 64, 2, 2, false)
+  MRD_BF3_CASE(G_A_CONJ, 64, 64, 2, 2, false)
+  MRD_BF3_CASE(G_B_T | G_C_ROWMAP, 128, 32, 4, 1, true)
 #undef MRD_BF3_CASE
   return hipErrorInvalidValue;
 }

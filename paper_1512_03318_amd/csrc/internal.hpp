@@ -83,8 +83,16 @@ struct GemmStage {
   std::vector<GemmTile> tiles;
   std::vector<int64_t> rows;  // row table
   std::vector<MixSrc> asrc;   // A_MIX sources
-  std::vector<GemmTile> red_tiles;  // DEEP: tiles whose K-split partials are summed
-  int64_t nslots = 0;               // DEEP: partial tiles (32 x 32 each, per split)
+  // Output tile of one workgroup and the K split.  FP32/FP64 kernels: 64 x 64 tiles,
+  // or DEEP 32 x 32 tiles whose four waves share the K range; BF16x3 kernel: 64 x 64,
+  // 128 x 64, or 128 x 32 with split.  With split, a problem's K range is divided over
+  // up to 8 workgroups, at least split_min chunks of kc each.
+  int32_t tile_m = 64, tile_n = 64;
+  bool split = false;
+  int32_t kc = 32, split_min = 4;
+  std::vector<GemmTile> red_tiles;  // split: tiles whose K-split partials are summed
+  int64_t nslots = 0;               // split: partial tiles (tile_m x tile_n each)
+  int64_t slot_elems() const { return (int64_t)tile_m * tile_n; }
   double flops = 0.0;         // algorithmic: 8 * M * N * K per problem (+ mixing MACs)
   // device
   GemmSeg* d_segs = nullptr;
@@ -96,19 +104,15 @@ struct GemmStage {
 };
 
 struct MixStage {
-  std::vector<MixTask> tasks;
+  std::vector<MixTask> tasks;   // in launch order
   std::vector<MixSrc> srcs;
   double flops = 0.0;  // 8 flops per complex multiply-add
   MixTask* d_tasks = nullptr;
   MixSrc* d_srcs = nullptr;
 };
 
-// Output tile of one workgroup: 64 x 64 for short-K stages, 32 x 32 for DEEP stages.
-int gemm_tile_m(bool deep);
-int gemm_tile_n(bool deep);
-
 // Kernel launchers (kernels.hip).  T = double or float (complex interleaved).
-// part: scratch of st.nslots * 1024 complex elements (DEEP stages with K-splits).
+// part: scratch of st.nslots * st.slot_elems() complex elements (stages with K splits).
 // skip (may be null): the kernels return at once when *skip != 0 (a stopped Lanczos).
 // between (may be empty) runs on the host after the main kernel is enqueued and before
 // the K-split reduction (used to record a profiling event).

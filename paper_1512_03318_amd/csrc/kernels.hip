@@ -310,13 +310,15 @@ hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* par
   if (st.nslots > 0 && !part) return hipErrorInvalidValue;
   dim3 grid(nt), block(256);
 #define MRD_GEMM_CASE(F, D)                                                                \
-  if (st.flags == (F) && st.deep == (D)) {                                                 \
+  if (st.flags == (F) && st.deep == (D) && st.tile_m == (D ? 32 : 64) &&                  \
+      st.tile_n == (D ? 32 : 64) && st.split == (D)) {                                     \
     hipLaunchKernelGGL((gemm_kernel<T, F, D>), grid, block, 0, s, st.d_segs, st.d_probs,   \
                        st.d_tiles, st.d_rows, st.d_asrc, A, B, C, part, skip);             \
     if (between) between();                                                                \
     if (D && !st.red_tiles.empty())                                                        \
-      hipLaunchKernelGGL((gemm_split_reduce_kernel<T, F>), dim3(st.red_tiles.size()),      \
-                         block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C, skip);\
+      hipLaunchKernelGGL((gemm_split_reduce_kernel<T, F>), dim3(st.red_tiles.size(), 1),   \
+                         block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C, 32, 32,\
+                         skip);                                                            \
     return hipGetLastError();                                                              \
   }
   MRD_GEMM_CASE(0, false)
@@ -327,9 +329,6 @@ hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* par
 #undef MRD_GEMM_CASE
   return hipErrorInvalidValue;
 }
-
-int gemm_tile_m(bool deep) { return deep ? 32 : 64; }
-int gemm_tile_n(bool deep) { return deep ? 32 : 64; }
 
 template hipError_t launch_gemm<double>(const GemmStage&, const double*, const double*, double*,
                                         double*, hipStream_t, const int32_t*,
@@ -349,24 +348,34 @@ __global__ void __launch_bounds__(256) mix_kernel(const MixTask* __restrict__ ta
                                                   const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   const MixTask tk = tasks[blockIdx.x];
-  // element e = r * cols + c; (r, c) advance by blockDim.x elements without dividing
-  const int step_r = blockDim.x / tk.cols, step_c = blockDim.x - step_r * tk.cols;
-  int r = threadIdx.x / tk.cols, c = threadIdx.x - r * tk.cols;
-  for (; r < tk.rows; r += step_r, c += step_c) {
-    if (c >= tk.cols) {
-      c -= tk.cols;
-      ++r;
-      if (r >= tk.rows) break;
+  const int n = tk.rows * tk.cols;
+  // 1024 elements per pass, four per thread (e = base + 256 t + thread); the source
+  // descriptors are read once per pass and the four loads of a source are independent
+  for (int base = 0; base < n; base += 1024) {
+    int r[4], c[4];
+    T re[4], im[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = base + 256 * t + threadIdx.x;
+      r[t] = e / tk.cols;
+      c[t] = e - r[t] * tk.cols;
+      re[t] = 0;
+      im[t] = 0;
     }
-    T re = 0, im = 0;
     for (int q = 0; q < tk.nsrc; ++q) {
       const MixSrc sr = srcs[tk.src0 + q];
-      const Cplx<T> x = ldc(src, sr.off + (int64_t)r * sr.ld + c);
       const T cr = (T)sr.re, ci = (T)sr.im;
-      re += cr * x.re - ci * x.im;
-      im += cr * x.im + ci * x.re;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (r[t] >= tk.rows) continue;
+        const Cplx<T> x = ldc(src, sr.off + (int64_t)r[t] * sr.ld + c[t]);
+        re[t] += cr * x.re - ci * x.im;
+        im[t] += cr * x.im + ci * x.re;
+      }
     }
-    stc(dst, tk.dst + (int64_t)r * tk.ld_dst + c, re, im);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (r[t] < tk.rows) stc(dst, tk.dst + (int64_t)r[t] * tk.ld_dst + c[t], re[t], im[t]);
   }
 }
 

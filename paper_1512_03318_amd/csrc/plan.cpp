@@ -144,17 +144,17 @@ EnvRLayout envr_layout(const Bond& c, const std::vector<dm_charge>& qw, int ly) 
 }
 
 void add_tiles(GemmStage& st, int32_t prob, int M, int N) {
-  const int TM = gemm_tile_m(st.deep), TN = gemm_tile_n(st.deep);
+  const int TM = st.tile_m, TN = st.tile_n;
   const int tm = (M + TM - 1) / TM, tn = (N + TN - 1) / TN;
   if (M > 0 && N == 0) return;
   GemmProb& P = st.probs[prob];
   P.nks = 1;
   P.slot0 = -1;
-  if (st.deep) {
-    // split long K over several workgroups: at least 4 chunks of 64 per split, at most 8
+  if (st.split) {
+    // split long K over several workgroups: at least split_min chunks per split, at most 8
     int chunks = 0;
-    for (int q = 0; q < P.nseg; ++q) chunks += (st.segs[P.seg0 + q].k + 63) / 64;
-    P.nks = std::max(1, std::min(8, chunks / 4));
+    for (int q = 0; q < P.nseg; ++q) chunks += (st.segs[P.seg0 + q].k + st.kc - 1) / st.kc;
+    P.nks = std::max(1, std::min(8, chunks / std::max(1, st.split_min)));
     if (P.nks > 1) {  // partial tile of (tm, tn, ks): slot0 + (tm * tiles_n + tn) * nks + ks
       P.slot0 = (int32_t)st.nslots;
       st.nslots += (int64_t)tm * tn * P.nks;
@@ -182,14 +182,14 @@ void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_siz
       const GemmProb& p = st.probs[t.prob];
       if (t.ks < 0 || t.ks >= std::max(1, p.nks)) throw err(DM_ERR_LAYOUT, "bad K-split");
       if (p.nks > 1) {
-        const int tn = (p.N + 31) / 32;
+        const int tn = (p.N + st.tile_n - 1) / st.tile_n;
         const int64_t slot = (int64_t)p.slot0 + ((int64_t)t.tm * tn + t.tn) * p.nks + t.ks;
-        if (!st.deep || p.slot0 < 0 || slot >= st.nslots) throw err(DM_ERR_LAYOUT, "bad partial slot");
+        if (!st.split || p.slot0 < 0 || slot >= st.nslots) throw err(DM_ERR_LAYOUT, "bad partial slot");
       }
     }
   for (const GemmTile& t : st.tiles) {
     const GemmProb& p = st.probs[t.prob];
-    if (t.tm * gemm_tile_m(st.deep) >= p.M || t.tn * gemm_tile_n(st.deep) >= p.N)
+    if (t.tm * st.tile_m >= p.M || t.tn * st.tile_n >= p.N)
       throw err(DM_ERR_LAYOUT, "empty tile");
   }
   for (const GemmProb& p : st.probs) {

@@ -103,6 +103,9 @@ struct dm_heff_plan {
   std::vector<int64_t> xoff;  // per a: X panel offset (rows = L.P.rows[a], cols = th.P.cols[a])
   int64_t xtotal = 0;
   mrd::GemmStage s1, s4;
+  mrd::GemmStage s1f, s4f;  // DM_BF16X3: the stages in FP kernel shapes (FP64 Rayleigh quotient)
+  const mrd::GemmStage& rq_s1() const { return prec == DM_BF16X3 ? s1f : s1; }
+  const mrd::GemmStage& rq_s4() const { return prec == DM_BF16X3 ? s4f : s4; }
   mrd::MixStage mix;
   void* dTables = nullptr;      // all task tables (one pool block)
   hipEvent_t done = nullptr;    // recorded after every use; waited on before release

@@ -19,7 +19,7 @@ if not torch.cuda.is_available():
 import paper_1512_03318_amd as pk  # noqa: E402
 from gpu_helpers import WindowGPU, max_rel, mpo_site, problem, to_dev  # noqa: E402
 
-CASES = ["ly3_chi16", "ly4_chi64", "ly6_chi200"]
+CASES = ["ly3_chi16", "ly4_chi64", "ly6_chi200", "ly6_chi800"]
 # FP32: 2^-24 per product; BF16x3: three bf16 products per real product, about 2^-17
 PRECS = [(pk.DM_FP64, 1e-12), (pk.DM_FP32, 2e-5), (pk.DM_BF16X3, 1e-4)]
 
