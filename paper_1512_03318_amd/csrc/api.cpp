@@ -220,7 +220,14 @@ static void build_heff_tables(dm_heff_plan& p) {
     sorted.reserve(ord.size());
     for (int i : ord) sorted.push_back(mx.tasks[i]);
     mx.tasks.swap(sorted);
+    std::vector<int64_t> key;
+    key.reserve(ord.size());
+    for (int i : ord) key.push_back(task_key[i]);
+    task_key.swap(key);
   }
+  // slab form with about 20 KB of LDS per workgroup (several workgroups per CU keep
+  // enough loads in flight; measured best between 12 and 32 KB at Ly=8, chi=3200)
+  mix_to_slabs(mx, task_key, (int)elem_bytes(p.prec), 20480);
   p.mix_flops = mx.flops;
   // (.)R stage, one problem per output sector c':
   //   theta'[(s12', a'), c'] = Z_{c'} (M x K) . Rpanel_{c'}^T (K x m_c'), K = R panel width,

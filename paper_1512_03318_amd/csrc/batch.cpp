@@ -111,6 +111,31 @@ MixStage merge_mix(const std::vector<const MixStage*>& in, const std::vector<Shi
     }
     m.flops += in[i]->flops;
   }
+  // slab forms, if every plan has one of the same element size
+  bool slabs = true;
+  for (const MixStage* x : in) slabs = slabs && !x->wgs.empty() && x->slab_eb == in[0]->slab_eb;
+  if (slabs) {
+    m.slab_eb = in[0]->slab_eb;
+    for (size_t i = 0; i < in.size(); ++i) {
+      const int32_t b0 = (int32_t)m.blks.size(), t0 = (int32_t)m.stasks.size(), c0 = (int32_t)m.coefs.size();
+      for (SlabBlk b : in[i]->blks) {
+        b.off += sh[i].a;
+        m.blks.push_back(b);
+      }
+      for (SlabTask t : in[i]->stasks) {
+        t.dst += sh[i].c;
+        t.c0 += c0;
+        m.stasks.push_back(t);
+      }
+      m.coefs.insert(m.coefs.end(), in[i]->coefs.begin(), in[i]->coefs.end());
+      for (SlabWG g : in[i]->wgs) {
+        g.blk0 += b0;
+        g.task0 += t0;
+        m.wgs.push_back(g);
+      }
+      m.lds_bytes = std::max(m.lds_bytes, in[i]->lds_bytes);
+    }
+  }
   return m;
 }
 

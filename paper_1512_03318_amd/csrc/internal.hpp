@@ -103,12 +103,48 @@ struct GemmStage {
   GemmTile* d_red_tiles = nullptr;
 };
 
+// Slab form of a mixing stage.  All sources of a task lie in one slab: a set of
+// equally shaped source blocks (rows x cols).  A workgroup stages rows [r0, r0 + nr)
+// and columns [col0, col0 + ncol) of every block of its slab in LDS once, then writes
+// that part of every task of the slab, so each source element is read from memory once.
+struct SlabWG {
+  int32_t blk0, nblk;    // the slab's blocks
+  int32_t task0, ntask;  // the slab's tasks
+  int32_t r0, nr, col0, ncol;
+};
+struct SlabBlk {
+  int64_t off;  // source element (0, 0) of the block
+  int32_t ld, pad;
+};
+struct SlabTask {
+  int64_t dst;  // destination element (0, 0) of the task
+  int32_t ld_dst;
+  int32_t c0, nc;  // coefficients [c0, c0 + nc)
+  int32_t pad;
+};
+struct SlabCoef {
+  int32_t blk, pad;  // block index within the slab
+  double re, im;
+};
+
 struct MixStage {
   std::vector<MixTask> tasks;   // in launch order
   std::vector<MixSrc> srcs;
   double flops = 0.0;  // 8 flops per complex multiply-add
   MixTask* d_tasks = nullptr;
   MixSrc* d_srcs = nullptr;
+  // slab form (used by launch_mix when present)
+  std::vector<SlabWG> wgs;
+  std::vector<SlabBlk> blks;
+  std::vector<SlabTask> stasks;
+  std::vector<SlabCoef> coefs;
+  int32_t lds_bytes = 0;  // largest LDS footprint of one workgroup
+  int32_t slab_eb = 0;    // bytes per complex element the slab form was sized for; a
+                          // launch in another precision uses the task form
+  SlabWG* d_wgs = nullptr;
+  SlabBlk* d_blks = nullptr;
+  SlabTask* d_stasks = nullptr;
+  SlabCoef* d_coefs = nullptr;
 };
 
 // Kernel launchers (kernels.hip).  T = double or float (complex interleaved).

@@ -379,9 +379,76 @@ __global__ void __launch_bounds__(256) mix_kernel(const MixTask* __restrict__ ta
   }
 }
 
+// Slab form: stage the workgroup's part (rows r0.., columns col0..) of every source block
+// of its slab in LDS (planes [block][row][col], interleaved complex), then produce that
+// part of each task of the slab from LDS.  Elements e of the part map to (row, col) with
+// a running (row, col) pair instead of a division per element.
+template <typename T>
+__global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict__ wgs,
+                                                       const SlabBlk* __restrict__ blks,
+                                                       const SlabTask* __restrict__ tasks,
+                                                       const SlabCoef* __restrict__ coefs,
+                                                       const T* __restrict__ src,
+                                                       T* __restrict__ dst,
+                                                       const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ __attribute__((aligned(16))) char mix_lds[];
+  T* lds = reinterpret_cast<T*>(mix_lds);
+  const SlabWG g = wgs[blockIdx.x];
+  const int per = g.nr * g.ncol;
+  const int step_r = 256 / g.ncol, step_c = 256 - step_r * g.ncol;
+  const int r_init = threadIdx.x / g.ncol, c_init = threadIdx.x - r_init * g.ncol;
+  for (int b = 0; b < g.nblk; ++b) {
+    const SlabBlk k = blks[g.blk0 + b];
+    const T* base = src + 2 * (k.off + (int64_t)g.r0 * k.ld + g.col0);
+    T* out = lds + 2 * (int64_t)b * per;
+    int r = r_init, c = c_init;
+    for (int e = threadIdx.x; e < per; e += 256) {
+      const Cplx<T> v = ldc(base, (int64_t)r * k.ld + c);
+      out[2 * e] = v.re;
+      out[2 * e + 1] = v.im;
+      r += step_r;
+      c += step_c;
+      if (c >= g.ncol) {
+        c -= g.ncol;
+        ++r;
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = 0; t < g.ntask; ++t) {
+    const SlabTask k = tasks[g.task0 + t];
+    T* obase = dst + 2 * (k.dst + (int64_t)g.r0 * k.ld_dst + g.col0);
+    int r = r_init, c = c_init;
+    for (int e = threadIdx.x; e < per; e += 256) {
+      T re = 0, im = 0;
+      for (int q = 0; q < k.nc; ++q) {
+        const SlabCoef w = coefs[k.c0 + q];
+        const T* x = lds + 2 * ((int64_t)w.blk * per + e);
+        const T cr = (T)w.re, ci = (T)w.im;
+        re += cr * x[0] - ci * x[1];
+        im += cr * x[1] + ci * x[0];
+      }
+      stc(obase, (int64_t)r * k.ld_dst + c, re, im);
+      r += step_r;
+      c += step_c;
+      if (c >= g.ncol) {
+        c -= g.ncol;
+        ++r;
+      }
+    }
+  }
+}
+
 template <typename T>
 hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s, const int32_t* skip) {
   if (st.tasks.empty()) return hipSuccess;
+  if (!st.wgs.empty() && st.slab_eb == (int)(2 * sizeof(T))) {
+    hipLaunchKernelGGL((mix_slab_kernel<T>), dim3((uint32_t)st.wgs.size()), dim3(256),
+                       (uint32_t)st.lds_bytes, s, st.d_wgs, st.d_blks, st.d_stasks, st.d_coefs, src,
+                       dst, skip);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((mix_kernel<T>), dim3((uint32_t)st.tasks.size()), dim3(256), 0, s,
                      st.d_tasks, st.d_srcs, src, dst, skip);
   return hipGetLastError();

@@ -2,6 +2,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <unordered_map>
 #include <cmath>
 #include <sstream>
 
@@ -236,6 +237,60 @@ void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_siz
   }
 }
 
+void mix_to_slabs(MixStage& st, const std::vector<int64_t>& key, int eb, int lds_budget) {
+  st.wgs.clear();
+  st.blks.clear();
+  st.stasks.clear();
+  st.coefs.clear();
+  st.lds_bytes = 0;
+  st.slab_eb = eb;
+  if (key.size() != st.tasks.size()) throw err(DM_ERR_LAYOUT, "mixing slab keys");
+  std::vector<int> ord(st.tasks.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key[x] < key[y]; });
+  for (size_t i = 0; i < ord.size();) {
+    size_t j = i;
+    while (j < ord.size() && key[ord[j]] == key[ord[i]]) ++j;
+    const MixTask& t0 = st.tasks[ord[i]];
+    const int rows = t0.rows, cols = t0.cols;
+    const int32_t blk0 = (int32_t)st.blks.size(), task0 = (int32_t)st.stasks.size();
+    std::unordered_map<int64_t, int32_t> bix;  // source offset -> block index in the slab
+    for (size_t q = i; q < j; ++q) {
+      const MixTask& t = st.tasks[ord[q]];
+      if (t.rows != rows || t.cols != cols) throw err(DM_ERR_LAYOUT, "mixing slab shapes differ");
+      SlabTask out{t.dst, t.ld_dst, (int32_t)st.coefs.size(), t.nsrc, 0};
+      for (int k = 0; k < t.nsrc; ++k) {
+        const MixSrc& m = st.srcs[t.src0 + k];
+        auto it = bix.find(m.off);
+        int32_t b;
+        if (it == bix.end()) {
+          b = (int32_t)(st.blks.size() - blk0);
+          bix.emplace(m.off, b);
+          st.blks.push_back({m.off, m.ld, 0});
+        } else {
+          b = it->second;
+          if (st.blks[blk0 + b].ld != m.ld) throw err(DM_ERR_LAYOUT, "mixing slab ld differs");
+        }
+        st.coefs.push_back({b, 0, m.re, m.im});
+      }
+      st.stasks.push_back(out);
+    }
+    const int nblk = (int)(st.blks.size() - blk0);
+    // largest column chunk, then row chunk, that fit the LDS budget
+    const int64_t per_elem = (int64_t)std::max(1, nblk) * eb;
+    int ncol = (int)std::min<int64_t>(cols, std::max<int64_t>(1, lds_budget / per_elem));
+    int nr = (int)std::min<int64_t>(rows, std::max<int64_t>(1, lds_budget / (per_elem * ncol)));
+    nr = std::min(nr, 16);
+    for (int r0 = 0; r0 < rows; r0 += nr)
+      for (int c0 = 0; c0 < cols; c0 += ncol) {
+        const int wr = std::min(nr, rows - r0), wc = std::min(ncol, cols - c0);
+        st.wgs.push_back({blk0, nblk, task0, (int32_t)(j - i), r0, wr, c0, wc});
+        st.lds_bytes = std::max<int32_t>(st.lds_bytes, (int32_t)(per_elem * wr * wc));
+      }
+    i = j;
+  }
+}
+
 void validate(const MixStage& st, int64_t src_size, int64_t dst_size) {
   for (const MixTask& t : st.tasks) {
     if (t.rows <= 0 || t.cols <= 0) throw err(DM_ERR_LAYOUT, "empty mixing task");
@@ -246,6 +301,28 @@ void validate(const MixStage& st, int64_t src_size, int64_t dst_size) {
       const MixSrc& s = st.srcs[t.src0 + q];
       range_check(s.off, s.off + (int64_t)(t.rows - 1) * s.ld + t.cols - 1, src_size, "mix src");
       if (s.ld < t.cols) throw err(DM_ERR_LAYOUT, "mix src ld");
+    }
+  }
+  // slab form: every workgroup's chunk inside its blocks and tasks, coefficients in range
+  for (const SlabWG& g : st.wgs) {
+    if (g.blk0 < 0 || g.nblk < 0 || g.blk0 + g.nblk > (int64_t)st.blks.size() || g.task0 < 0 ||
+        g.ntask < 0 || g.task0 + g.ntask > (int64_t)st.stasks.size() || g.r0 < 0 || g.nr <= 0 ||
+        g.col0 < 0 || g.ncol <= 0)
+      throw err(DM_ERR_LAYOUT, "bad mixing slab");
+    if ((int64_t)g.nblk * g.nr * g.ncol * st.slab_eb > st.lds_bytes) throw err(DM_ERR_LAYOUT, "mixing slab LDS");
+    const int r1 = g.r0 + g.nr - 1, c1 = g.col0 + g.ncol - 1;
+    for (int b = 0; b < g.nblk; ++b) {
+      const SlabBlk& k = st.blks[g.blk0 + b];
+      if (k.ld <= c1) throw err(DM_ERR_LAYOUT, "mixing slab block ld");
+      range_check(k.off + (int64_t)g.r0 * k.ld + g.col0, k.off + (int64_t)r1 * k.ld + c1, src_size, "slab src");
+    }
+    for (int t = 0; t < g.ntask; ++t) {
+      const SlabTask& k = st.stasks[g.task0 + t];
+      if (k.ld_dst <= c1) throw err(DM_ERR_LAYOUT, "mixing slab task ld");
+      range_check(k.dst + (int64_t)g.r0 * k.ld_dst + g.col0, k.dst + (int64_t)r1 * k.ld_dst + c1, dst_size, "slab dst");
+      if (k.c0 < 0 || k.nc < 0 || k.c0 + k.nc > (int64_t)st.coefs.size()) throw err(DM_ERR_LAYOUT, "slab coefficients");
+      for (int q = 0; q < k.nc; ++q)
+        if (st.coefs[k.c0 + q].blk < 0 || st.coefs[k.c0 + q].blk >= g.nblk) throw err(DM_ERR_LAYOUT, "slab block index");
     }
   }
 }

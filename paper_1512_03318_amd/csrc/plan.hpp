@@ -108,6 +108,10 @@ void add_tiles(GemmStage& st, int32_t prob, int M, int N);
 // Host check that every access of a stage stays inside its buffers (sizes in complex
 // elements); throws DmError(DM_ERR_LAYOUT) otherwise.  Run on every table before upload.
 void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_size);
+// Builds the slab form of a mixing stage from its task list.  key[t] names the slab of
+// task t (tasks of one slab share rows, cols and source blocks); eb = bytes per complex
+// element; each workgroup stages at most lds_budget bytes.
+void mix_to_slabs(MixStage& st, const std::vector<int64_t>& key, int eb, int lds_budget);
 void validate(const MixStage& st, int64_t src_size, int64_t dst_size);
 
 }  // namespace mrd

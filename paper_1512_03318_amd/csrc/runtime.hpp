@@ -66,6 +66,10 @@ struct TableUpload {
   void add(MixStage& st) {
     add(st.tasks, &st.d_tasks);
     add(st.srcs, &st.d_srcs);
+    add(st.wgs, &st.d_wgs);
+    add(st.blks, &st.d_blks);
+    add(st.stasks, &st.d_stasks);
+    add(st.coefs, &st.d_coefs);
   }
   // Synchronous copy into a pool block; returns the block (free it with dev_free).
   void* commit() {
