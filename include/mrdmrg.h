@@ -53,9 +53,9 @@
  *
  * Errors.  Every int-returning call returns DM_OK (0) or a negative DM_ERR_* code and
  *   sets a thread-local message readable with dm_last_error().  No C++ exception
- *   crosses this boundary.  GPU work is enqueued on the given stream; only
- *   lanczos_ground and the env_update calls synchronise (they return host scalars or
- *   free stream-ordered scratch).
+ *   crosses this boundary.  GPU work is enqueued on the given stream; only the Lanczos
+ *   calls synchronise (they return host scalars).  Library scratch is released in
+ *   stream order (reused once the stream has passed the work that used it).
  * ---------------------------------------------------------------------------------
  */
 #ifndef MRDMRG_H
@@ -138,9 +138,12 @@ int dm_layout(const dm_layout_desc* d, int64_t* nblocks, int64_t* nelem, dm_bloc
  * precomputes the charge-matched block task table (which L block meets which theta
  * block, which MPO entries mix which intermediate blocks) and copies L and R into
  * plan-owned device buffers in the plan's precision (plus FP64 copies for the final
- * Rayleigh quotient in DM_FP32 / DM_BF16X3).  L and R may be freed after creation.
- * The plan owns its device scratch.  Several plans may run concurrently on different
- * streams; one plan must not be used by two streams at the same time. */
+ * Rayleigh quotient in DM_FP32 / DM_BF16X3).  The copies are stream-ordered on
+ * `stream` (the call does not wait for them): L and R may be freed or overwritten by
+ * later work on the same stream (e.g. a stream-ordered allocator), or after that stream
+ * has been synchronised.  The plan owns its device scratch.  Several plans may run
+ * concurrently on different streams; one plan must not be used by two streams at the
+ * same time. */
 typedef struct dm_heff_plan dm_heff_plan;
 
 int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* c,
@@ -187,7 +190,10 @@ int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double 
  * L_out (bond b, MPO states w.qr) from L (bond a, states w.ql) and the left-canonical
  * site tensor A (SITE layout of a, b, w.qs).  R_out (bond b, states w.ql) from R
  * (bond c, states w.qr) and the right-canonical B (SITE layout of b, c, w.qs).
- * Outputs are overwritten.  Synchronises before returning (its scratch is freed). */
+ * Outputs are overwritten.  Asynchronous on `stream`: the inputs must stay valid and
+ * the output is complete only once the work queued there has run (same rule as for
+ * dm_heff_plan_create).  Scratch comes from the library's caching pool and is reused
+ * only after the stream has passed this update. */
 int env_update_left(int32_t ly, const dm_bond* a, const dm_bond* b, const dm_mpo_site* w,
                     const void* L, const void* A, void* L_out, int32_t prec, dm_stream stream);
 int env_update_right(int32_t ly, const dm_bond* b, const dm_bond* c, const dm_mpo_site* w,

@@ -297,6 +297,7 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     validate(p->s4, p->ztotal, p->R.P.total, p->n());
     validate(p->s1f, p->L.P.total, p->n(), p->xtotal);
     validate(p->s4f, p->ztotal, p->R.P.total, p->n());
+    hipStream_t s = (hipStream_t)stream;
     {
       TableUpload up;
       up.add(p->s1);
@@ -304,7 +305,7 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       up.add(p->s1f);
       up.add(p->s4f);
       up.add(p->mix);
-      p->dTables = up.commit();
+      p->dTables = up.commit(s);
     }
     HIPCHK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
     const size_t eb = elem_bytes(prec);
@@ -313,7 +314,6 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     p->dX = dev_alloc(p->xtotal * eb);
     p->dZ = dev_alloc(p->ztotal * eb);
     p->dSplit = dev_alloc(p->s4.nslots * p->s4.slot_elems() * eb);
-    hipStream_t s = (hipStream_t)stream;
     stage_in(L, p->dL, p->L.P.total, prec, s);
     stage_in(R, p->dR, p->R.P.total, prec, s);
     if (prec != DM_FP64) {
@@ -332,7 +332,6 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       p->use_graph = g && g[0] == '1';
     }
     HIPCHK(hipEventRecord(p->done, s));
-    HIPCHK(hipStreamSynchronize(s));
     *out = p.release();
   });
 }
@@ -788,39 +787,33 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
 }
 
 // Runs T1 -> mix -> T3 with stream-ordered scratch, FP64 or FP32 arithmetic.
+// Runs T1 -> mix -> T3, stream-ordered (no host wait): tables and scratch come from
+// the caching pools and are handed back for reuse once the stream has passed them.
 void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64_t nsite,
              void* out, int64_t nout, int prec, hipStream_t s) {
   const size_t eb = elem_bytes(prec);
-  void *t1 = nullptr, *t2 = nullptr, *e32 = nullptr, *s32 = nullptr, *o32 = nullptr, *tab = nullptr;
-  auto amalloc = [&](void** q, size_t bytes) {
-    if (bytes == 0) return;
-    if (hipMallocAsync(q, bytes, s) != hipSuccess) {
-      (void)hipGetLastError();
-      throw DmError{DM_ERR_ALLOC, "hipMallocAsync failed"};
-    }
+  std::vector<void*> scratch;
+  auto alloc = [&](size_t bytes) {
+    void* q = dev_alloc(bytes);
+    scratch.push_back(q);
+    return q;
   };
-  std::string failure;
-  int code = DM_OK;
-  TableUpload up;  // host copy lives until the stream is synchronised below
   try {
+    TableUpload up;
     up.add(ep.t1);
     up.add(ep.t3);
     up.add(ep.mix);
-    if (!up.host.empty()) {
-      amalloc(&tab, up.host.size());
-      HIPCHK(hipMemcpyAsync(tab, up.host.data(), up.host.size(), hipMemcpyHostToDevice, s));
-      for (auto& f : up.fix) *f.second = (char*)tab + f.first;
-    }
-    amalloc(&t1, ep.t1total * eb);
-    amalloc(&t2, ep.t2total * eb);
+    scratch.push_back(up.commit(s));
+    void* t1 = alloc(ep.t1total * eb);
+    void* t2 = alloc(ep.t2total * eb);
     if (prec == DM_FP64) {
       HIPCHK(launch_gemm<double>(ep.t1, (const double*)env, (const double*)site, (double*)t1, nullptr, s));
       HIPCHK(launch_mix<double>(ep.mix, (const double*)t1, (double*)t2, s));
       HIPCHK(launch_gemm<double>(ep.t3, (const double*)site, (const double*)t2, (double*)out, nullptr, s));
     } else {
-      amalloc(&e32, nenv * eb);
-      amalloc(&s32, nsite * eb);
-      amalloc(&o32, nout * eb);
+      void* e32 = alloc(nenv * eb);
+      void* s32 = alloc(nsite * eb);
+      void* o32 = alloc(nout * eb);
       stage_in(env, e32, nenv, DM_FP32, s);
       stage_in(site, s32, nsite, DM_FP32, s);
       HIPCHK(gemm_lp(prec, ep.t1, (const float*)e32, (const float*)s32, (float*)t1, nullptr, s));
@@ -828,15 +821,11 @@ void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64
       HIPCHK(gemm_lp(prec, ep.t3, (const float*)s32, (const float*)t2, (float*)o32, nullptr, s));
       stage_out(o32, out, nout, DM_FP32, s);
     }
-  } catch (const DmError& e) {
-    failure = e.msg;
-    code = e.code;
+  } catch (...) {
+    for (void* q : scratch) dev_free_after(q, s);
+    throw;
   }
-  for (void* q : {t1, t2, e32, s32, o32, tab})
-    if (q) (void)hipFreeAsync(q, s);
-  const hipError_t se = hipStreamSynchronize(s);
-  if (code != DM_OK) throw DmError{code, failure};
-  if (se != hipSuccess) throw DmError{DM_ERR_HIP, std::string("stream sync: ") + hipGetErrorString(se)};
+  for (void* q : scratch) dev_free_after(q, s);
 }
 
 }  // namespace

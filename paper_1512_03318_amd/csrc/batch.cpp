@@ -262,7 +262,7 @@ void run_merged(const MergedMatvec& m, hipStream_t s) {
   }
 }
 
-void build_batch(dm_batch& b) {
+void build_batch(dm_batch& b, hipStream_t s) {
   b.mv = build_merged(b, false);
   if (b.prec != DM_FP64) {
     b.mv64 = build_merged(b, true);
@@ -281,7 +281,7 @@ void build_batch(dm_batch& b) {
   }
   up.add(b.cin, &b.d_cin);
   up.add(b.cout, &b.d_cout);
-  b.dTables = up.commit();
+  b.dTables = up.commit(s);
   b.built = true;
 }
 
@@ -334,7 +334,7 @@ extern "C" int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t 
       if (!thetas[i]) throw DmError{DM_ERR_ARG, "null theta"};
     hipStream_t s = (hipStream_t)stream;
     for (dm_heff_plan* p : b->plans) ensure_lanczos(p, max_iter);
-    if (!b->built) build_batch(*b);
+    if (!b->built) build_batch(*b, s);
     if (b->lz_cap != max_iter) {
       if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
       if (b->graph) (void)hipGraphDestroy(b->graph);

@@ -2,6 +2,7 @@
 #include <map>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "runtime.hpp"
 
@@ -20,20 +21,24 @@ void set_last_error(const std::string& msg) { g_err = msg; }
 
 namespace {
 
-// Caching device allocator for plan buffers.  A DMRG sweep creates and destroys one
-// plan per bond with similar sizes; reusing freed blocks avoids hipMalloc / hipFree
-// (each of which can cost milliseconds) on every bond.  Blocks are rounded up to 1/8 of
-// their power of two, kept per device, and released with hipFree beyond 24 GiB cached.
-// Callers guarantee that no kernel still uses a block when it is returned.
-class DevicePool {
+// Caching allocator for plan buffers (device) and upload staging (pinned host).  A DMRG
+// sweep creates and destroys one plan per bond with similar sizes; reusing freed blocks
+// avoids hipMalloc / hipFree (each of which can cost milliseconds) on every bond.
+// Blocks are rounded up to 1/8 of their power of two, kept per device, and released
+// beyond 24 GiB cached.  A block is returned either when no kernel uses it any more
+// (put) or at a point of a stream (put_after): it is then reused only once an event
+// recorded there has completed, so stream-ordered work never needs a host wait.
+class BlockPool {
  public:
+  explicit BlockPool(bool pinned) : pinned_(pinned) {}
   void* get(size_t bytes) {
     if (bytes == 0) return nullptr;
     const size_t r = round(bytes);
     int dev = 0;
-    (void)hipGetDevice(&dev);
+    if (!pinned_) (void)hipGetDevice(&dev);
     {
       std::lock_guard<std::mutex> g(m_);
+      reap_locked();
       auto& fl = free_[dev];
       auto it = fl.lower_bound(r);
       if (it != fl.end() && it->first <= r + r / 4) {
@@ -43,14 +48,13 @@ class DevicePool {
         return p;
       }
     }
-    void* p = nullptr;
-    if (hipMalloc(&p, r) != hipSuccess) {
-      (void)hipGetLastError();
+    void* p = raw_alloc(r);
+    if (!p) {
       trim(0);
-      if (hipMalloc(&p, r) != hipSuccess) {
-        (void)hipGetLastError();
-        throw DmError{DM_ERR_ALLOC, "hipMalloc of " + std::to_string(r) + " bytes failed"};
-      }
+      p = raw_alloc(r);
+      if (!p)
+        throw DmError{DM_ERR_ALLOC, std::string(pinned_ ? "hipHostMalloc" : "hipMalloc") + " of " +
+                                        std::to_string(r) + " bytes failed"};
     }
     std::lock_guard<std::mutex> g(m_);
     size_[p] = {r, dev};
@@ -59,11 +63,30 @@ class DevicePool {
   void put(void* p) {
     if (!p) return;
     std::lock_guard<std::mutex> g(m_);
-    auto it = size_.find(p);
-    if (it == size_.end()) return;
-    free_[it->second.second].emplace(it->second.first, p);
-    cached_ += it->second.first;
-    if (cached_ > kMaxCached) trim_locked(kMaxCached);
+    put_locked(p);
+    reap_locked();
+  }
+  void put_after(void* p, hipStream_t s) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(m_);
+    hipEvent_t e = nullptr;
+    if (!events_.empty()) {
+      e = events_.back();
+      events_.pop_back();
+    } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(s);  // no event: wait here instead
+      put_locked(p);
+      return;
+    }
+    if (hipEventRecord(e, s) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(s);
+      events_.push_back(e);
+      put_locked(p);
+      return;
+    }
+    pending_.push_back({e, p});
   }
 
  private:
@@ -74,6 +97,41 @@ class DevicePool {
     const size_t step = top / 8;
     return (b + step - 1) / step * step;
   }
+  void* raw_alloc(size_t r) {
+    void* p = nullptr;
+    const hipError_t e = pinned_ ? hipHostMalloc(&p, r, hipHostMallocDefault) : hipMalloc(&p, r);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  void raw_free(void* p) {
+    if (pinned_) (void)hipHostFree(p);
+    else (void)hipFree(p);
+  }
+  void put_locked(void* p) {
+    auto it = size_.find(p);
+    if (it == size_.end()) return;
+    free_[it->second.second].emplace(it->second.first, p);
+    cached_ += it->second.first;
+    if (cached_ > kMaxCached) trim_locked(kMaxCached);
+  }
+  // blocks whose release point has been reached become free
+  void reap_locked() {
+    for (size_t i = 0; i < pending_.size();) {
+      const hipError_t q = hipEventQuery(pending_[i].first);
+      if (q == hipErrorNotReady) {
+        ++i;
+        continue;
+      }
+      if (q != hipSuccess) (void)hipGetLastError();
+      events_.push_back(pending_[i].first);
+      put_locked(pending_[i].second);
+      pending_[i] = pending_.back();
+      pending_.pop_back();
+    }
+  }
   void trim(size_t limit) {
     std::lock_guard<std::mutex> g(m_);
     trim_locked(limit);
@@ -83,21 +141,28 @@ class DevicePool {
       auto& fl = kv.second;
       while (cached_ > limit && !fl.empty()) {
         auto last = std::prev(fl.end());
-        (void)hipFree(last->second);
+        raw_free(last->second);
         size_.erase(last->second);
         cached_ -= last->first;
         fl.erase(last);
       }
     }
   }
+  const bool pinned_;
   std::mutex m_;
   std::map<int, std::multimap<size_t, void*>> free_;
   std::unordered_map<void*, std::pair<size_t, int>> size_;
+  std::vector<std::pair<hipEvent_t, void*>> pending_;
+  std::vector<hipEvent_t> events_;
   size_t cached_ = 0;
 };
 
-DevicePool& pool() {
-  static DevicePool* p = new DevicePool();  // never destroyed: outlives static teardown
+BlockPool& pool() {
+  static BlockPool* p = new BlockPool(false);  // never destroyed: outlives static teardown
+  return *p;
+}
+BlockPool& pinned_pool() {
+  static BlockPool* p = new BlockPool(true);
   return *p;
 }
 
@@ -105,6 +170,9 @@ DevicePool& pool() {
 
 void* dev_alloc(size_t bytes) { return pool().get(bytes); }
 void dev_free(void* p) { pool().put(p); }
+void dev_free_after(void* p, hipStream_t s) { pool().put_after(p, s); }
+void* pinned_alloc(size_t bytes) { return pinned_pool().get(bytes); }
+void pinned_free_after(void* p, hipStream_t s) { pinned_pool().put_after(p, s); }
 
 size_t elem_bytes(int prec) { return prec == DM_FP64 ? 16 : 8; }
 

@@ -38,9 +38,14 @@ int guarded(F&& f) {
   }
 }
 
-// Caching device allocator (runtime.cpp): blocks are reused across plans.
+// Caching allocators (runtime.cpp): blocks are reused across plans.  dev_free: no
+// kernel uses the block any more; dev_free_after: reusable once stream s has passed
+// this point (no host wait).  Pinned host blocks stage uploads.
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
+void dev_free_after(void* p, hipStream_t s);
+void* pinned_alloc(size_t bytes);
+void pinned_free_after(void* p, hipStream_t s);
 
 // All task tables of one or more stages in one device block, uploaded with one copy.
 struct TableUpload {
@@ -71,11 +76,19 @@ struct TableUpload {
     add(st.stasks, &st.d_stasks);
     add(st.coefs, &st.d_coefs);
   }
-  // Synchronous copy into a pool block; returns the block (free it with dev_free).
-  void* commit() {
+  // Stream-ordered upload into a pool block through pinned staging (released after the
+  // copy on s); returns the block (free it with dev_free / dev_free_after).
+  void* commit(hipStream_t s) {
     if (host.empty()) return nullptr;
+    char* h = (char*)pinned_alloc(host.size());
+    std::memcpy(h, host.data(), host.size());
     char* d = (char*)dev_alloc(host.size());
-    HIPCHK(hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice));
+    const hipError_t e = hipMemcpyAsync(d, h, host.size(), hipMemcpyHostToDevice, s);
+    pinned_free_after(h, s);
+    if (e != hipSuccess) {
+      dev_free_after(d, s);
+      HIPCHK(e);
+    }
     for (auto& f : fix) *f.second = d + f.first;
     return d;
   }
