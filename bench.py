@@ -525,6 +525,7 @@ def batched_main(args):
            "sequential_ms": round(1e3 * seq, 3),
            "speedup_vs_sequential": round(seq / wall, 3),
            "max_rel_energy_diff_vs_sequential": max(abs(a - b) / abs(b) for a, b in zip(e_b, e_s)),
+           "tile_tuning": batch.info().strip().splitlines(),
            "chi_range": [min(s["chi"] for s in shapes), max(s["chi"] for s in shapes)],
            "theta_elems_range": [min(s["n"] for s in shapes), max(s["n"] for s in shapes)]}
     print(json.dumps(out), flush=True)

@@ -207,15 +207,24 @@ int dm_env_flops(int32_t left, int32_t ly, const dm_bond* x, const dm_bond* y,
 
 /* ---- Many independent problems -------------------------------------------------
  * A batch merges the task tables of n plans (same precision) so that every phase of
- * one matvec runs as one launch over all instances; each Lanczos iteration of the
- * whole batch is one HIP graph replay.  Plans must outlive the batch. */
+ * one Lanczos step runs as one launch over all instances (one per problem bucket for
+ * the block GEMMs).  At the first solve the GEMM problems of all instances are grouped
+ * into buckets by output shape (rows <= 64 / > 64, columns <= 32 / <= 64 / > 64) and each
+ * bucket is timed with every tile shape the kernels provide; the fastest is kept (set
+ * MRDMRG_TUNE=0 to keep the plans' own shapes).  Tiles are issued longest first.  With
+ * MRDMRG_GRAPH=1 each Lanczos iteration of the whole batch is one HIP graph replay.
+ * Plans must outlive the batch. */
 typedef struct dm_batch dm_batch;
 int dm_batch_create(int32_t n, dm_heff_plan* const* plans, dm_stream stream, dm_batch** out);
 void dm_batch_destroy(dm_batch* b);
+/* The tile shape chosen per bucket, as text (empty before the first solve).  Writes at
+ * most len bytes including the terminating zero; returns the full length. */
+int64_t dm_batch_info(const dm_batch* b, char* buf, int64_t len);
 /* thetas[i]: device start vector / Ritz vector of instance i.  energies, iters: host
- * arrays of n.  Same algorithm and stopping rule as lanczos_ground per instance.
+ * arrays of n.  Same algorithm and stopping rule as lanczos_ground per instance (the
+ * tuned tile shapes may sum in another order: results agree to rounding).
  * done_us (may be NULL): host array of n, microseconds from launch until instance i
- * converged, measured on the device.  Synchronises. */
+ * stopped, read from the device clock.  Synchronises. */
 int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t max_iter, double tol,
                            double* energies, int32_t* iters, double* done_us, dm_stream stream);
 

@@ -65,6 +65,7 @@ _sigs = {
                                 _vp, _vp, _vp, _i32, _vp]),
     "dm_batch_create": (_i32, [_i32, C.POINTER(_vp), _vp, C.POINTER(_vp)]),
     "dm_batch_destroy": (None, [_vp]),
+    "dm_batch_info": (_i64, [_vp, C.c_char_p, _i64]),
     "lanczos_ground_batched": (_i32, [_vp, C.POINTER(_vp), _i32, _f64, C.POINTER(_f64),
                                       C.POINTER(_i32), C.POINTER(_f64), _vp]),
     "dm_mpo_hofstadter": (_i32, [_i32, _i32, _i32, _i32, _f64, _f64, _i32, C.POINTER(_vp)]),
@@ -273,6 +274,13 @@ class Batch:
         h = _vp()
         _check(lib.dm_batch_create(len(self.plans), arr, _stream(stream), C.byref(h)))
         self.h = h
+
+    def info(self) -> str:
+        """Tile shape chosen per problem bucket (after the first solve)."""
+        n = lib.dm_batch_info(self.h, None, 0)
+        buf = C.create_string_buffer(max(1, n))
+        lib.dm_batch_info(self.h, buf, len(buf))
+        return buf.value.decode()
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -13,8 +13,10 @@
 // wall clock.
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
 #include <memory>
 #include <numeric>
+#include <string>
 
 #include "runtime.hpp"
 
@@ -40,25 +42,16 @@ double tile_cost(const GemmStage& st, const GemmTile& t) {
   return chunks / std::max(1, p.nks);
 }
 
-GemmStage merge_gemm(const std::vector<const GemmStage*>& in, const std::vector<Shift>& sh) {
+// Concatenates the problems of all plans (offsets rebased); tiles are built per bucket.
+GemmStage merge_problems(const std::vector<const GemmStage*>& in, const std::vector<Shift>& sh) {
   GemmStage m;
   m.flags = in[0]->flags;
-  m.deep = in[0]->deep;
-  m.tile_m = in[0]->tile_m;
-  m.tile_n = in[0]->tile_n;
-  m.split = in[0]->split;
-  m.kc = in[0]->kc;
-  m.split_min = in[0]->split_min;
-  std::vector<std::pair<double, GemmTile>> tiles;
   for (size_t i = 0; i < in.size(); ++i) {
     const GemmStage& st = *in[i];
-    if (st.flags != m.flags || st.deep != m.deep || st.tile_m != m.tile_m || st.tile_n != m.tile_n ||
-        st.split != m.split)
-      throw DmError{DM_ERR_ARG, "batched plans have different stage kinds"};
+    if (st.flags != m.flags) throw DmError{DM_ERR_ARG, "batched plans have different stage kinds"};
     if (st.flags & G_A_MIX) throw DmError{DM_ERR_ARG, "mixed operands cannot be batched"};
-    const int32_t seg0 = (int32_t)m.segs.size(), prob0 = (int32_t)m.probs.size();
+    const int32_t seg0 = (int32_t)m.segs.size();
     const int32_t row0 = (int32_t)m.rows.size();
-    const int64_t slot0 = m.nslots;
     for (GemmSeg g : st.segs) {
       g.a_off += sh[i].a;
       g.b_off += sh[i].b;
@@ -69,29 +62,69 @@ GemmStage merge_gemm(const std::vector<const GemmStage*>& in, const std::vector<
       if (!(m.flags & G_C_ROWMAP)) p.c_off += sh[i].c;
       p.seg0 += seg0;
       if (p.rowmap >= 0) p.rowmap += row0;
-      p.slot0 += (int32_t)slot0;
       m.probs.push_back(p);
     }
-    for (GemmTile t : st.tiles) {
-      const double c = tile_cost(st, t);
-      t.prob += prob0;
-      tiles.emplace_back(c, t);
-    }
-    for (GemmTile t : st.red_tiles) {
-      t.prob += prob0;
-      m.red_tiles.push_back(t);
-    }
-    m.nslots += st.nslots;
     m.flops += st.flops;
   }
-  if (m.segs.size() > INT32_MAX || m.rows.size() > INT32_MAX || m.nslots > INT32_MAX)
+  if (m.segs.size() > INT32_MAX || m.rows.size() > INT32_MAX)
     throw DmError{DM_ERR_ARG, "batched task table too large"};
-  std::stable_sort(tiles.begin(), tiles.end(),
-                   [](const auto& x, const auto& y) { return x.first > y.first; });
-  const int n = (int)tiles.size();
-  m.tiles.resize(n);
-  for (int b = 0; b < n; ++b) m.tiles[xcd_tile_host(b, n)] = tiles[b].second;
   return m;
+}
+
+// Workgroup tile shape of a GEMM stage (the fields add_tiles and the launchers read).
+struct Shape {
+  int tm, tn;
+  bool deep, split;
+  int kc, split_min;
+};
+
+void set_shape(GemmStage& st, const Shape& sh) {
+  st.tile_m = sh.tm;
+  st.tile_n = sh.tn;
+  st.deep = sh.deep;
+  st.split = sh.split;
+  st.kc = sh.kc;
+  st.split_min = sh.split_min;
+}
+
+// Shapes the kernels provide for a stage (see launch_gemm / launch_gemm_bf16x3).
+std::vector<Shape> candidates(int prec, int32_t flags) {
+  const bool long_k = flags == (G_B_T | G_C_ROWMAP);
+  if (prec == DM_BF16X3) {
+    if (long_k) return {{128, 32, false, true, 32, 6}, {64, 32, false, true, 32, 6}, {64, 64, false, true, 32, 6}};
+    return {{128, 64, false, false, 32, 4}, {64, 64, false, false, 32, 4}};
+  }
+  if (long_k) return {{32, 32, true, true, 64, 4}, {64, 64, false, false, 32, 4}};
+  return {{64, 64, false, false, 32, 4}, {32, 32, true, false, 64, 4}};
+}
+
+// Problem buckets by output shape: rows (<= 64, > 64) x columns (<= 32, <= 64, > 64).
+int bucket_of(const GemmProb& p) { return (p.M > 64 ? 3 : 0) + (p.N > 64 ? 2 : p.N > 32 ? 1 : 0); }
+constexpr int kBuckets = 6;
+
+// Tiles of the problems in `which` with shape sh, longest first (LPT), interleaved so
+// that block b -- dispatched to XCD b % 8 -- starts the b-th longest tile.
+void tile_bucket(GemmStage& st, const std::vector<int>& which, const Shape& sh) {
+  set_shape(st, sh);
+  st.tiles.clear();
+  st.red_tiles.clear();
+  st.nslots = 0;
+  for (GemmProb& p : st.probs) {
+    p.nks = 1;
+    p.slot0 = -1;
+  }
+  for (int i : which) add_tiles(st, i, st.probs[i].M, st.probs[i].N);
+  std::vector<std::pair<double, GemmTile>> tl;
+  for (const GemmTile& t : st.tiles) tl.emplace_back(tile_cost(st, t), t);
+  std::stable_sort(tl.begin(), tl.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  const int n = (int)tl.size();
+  for (int b = 0; b < n; ++b) st.tiles[xcd_tile_host(b, n)] = tl[b].second;
+  double f = 0;
+  for (int i : which) {
+    const GemmProb& p = st.probs[i];
+    for (int q = 0; q < p.nseg; ++q) f += 8.0 * p.M * p.N * st.segs[p.seg0 + q].k;
+  }
+  st.flops = f;
 }
 
 // Mixing tasks are short and memory-bound: they keep each plan's own order (tasks that
@@ -141,11 +174,12 @@ MixStage merge_mix(const std::vector<const MixStage*>& in, const std::vector<Shi
 
 // One merged matvec: theta (per instance) -> w, all instances in one launch per phase.
 struct MergedMatvec {
-  GemmStage s1, s4;
+  std::vector<GemmStage> s1, s4;  // one stage per problem bucket, each with its tuned shape
   MixStage mix;
   char* base = nullptr;  // every offset counts elements from here
-  void* split = nullptr; // K-split partial tiles of the merged (.).R stage
+  void* split = nullptr; // K-split partial tiles (buckets run in stream order and share it)
   int prec = DM_FP64;
+  std::vector<std::string> tuning;  // chosen shape per bucket, for reports
 };
 
 // Rebasing: offsets of instance i move by (buffer_i - base) / element size.
@@ -186,6 +220,7 @@ struct dm_batch {
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;
   bool use_graph = false;
+  bool tune = true;             // tile shape per problem bucket timed at the first solve
   ~dm_batch() {
     if (done) {
       (void)hipEventSynchronize(done);
@@ -207,7 +242,82 @@ struct dm_batch {
 namespace {
 
 // Merged tables of the step matvec (f64 = false) or of the FP64 Rayleigh quotient.
-MergedMatvec build_merged(dm_batch& b, bool f64) {
+// Device time (ms, best of 3 after one warm-up) of one bucket stage on the batch's buffers.
+double time_stage(GemmStage& t, int prec, char* base, size_t eb, hipStream_t s) {
+  TableUpload up;
+  up.add(t);
+  void* tab = up.commit(s);
+  void* part = dev_alloc((size_t)t.nslots * t.slot_elems() * eb);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double best = 1e30;
+  try {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int r = 0; r < 4; ++r) {
+      HIPCHK(hipEventRecord(e0, s));
+      if (prec == DM_FP64)
+        HIPCHK(launch_gemm<double>(t, (double*)base, (double*)base, (double*)base, (double*)part, s));
+      else
+        HIPCHK(gemm_lp(prec, t, (float*)base, (float*)base, (float*)base, (float*)part, s));
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (r > 0) best = std::min(best, (double)ms);
+    }
+  } catch (...) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dev_free_after(tab, s);
+    dev_free_after(part, s);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  dev_free(tab);   // the stream was synchronised above
+  dev_free(part);
+  return best;
+}
+
+// One stage per problem bucket; with tune, each bucket takes the fastest candidate shape
+// (timed on the batch's own buffers), otherwise the plans' default shape.
+std::vector<GemmStage> tune_stage(const GemmStage& base, int prec, const Shape& dflt, bool tune,
+                                  char* ptr, size_t eb, hipStream_t s, std::vector<std::string>& log) {
+  std::vector<std::vector<int>> which(kBuckets);
+  for (int i = 0; i < (int)base.probs.size(); ++i) which[bucket_of(base.probs[i])].push_back(i);
+  const std::vector<Shape> cand = candidates(prec, base.flags);
+  std::vector<GemmStage> out;
+  for (int bk = 0; bk < kBuckets; ++bk) {
+    if (which[bk].empty()) continue;
+    Shape best = dflt;
+    if (tune && cand.size() > 1) {
+      double tbest = 1e30;
+      for (const Shape& c : cand) {
+        GemmStage t = base;
+        tile_bucket(t, which[bk], c);
+        const double ms = time_stage(t, prec, ptr, eb, s);
+        if (ms < tbest) {
+          tbest = ms;
+          best = c;
+        }
+      }
+    }
+    GemmStage t = base;
+    tile_bucket(t, which[bk], best);
+    log.push_back("flags " + std::to_string(base.flags) + " bucket " + std::to_string(bk) + ": " +
+                  std::to_string(which[bk].size()) + " problems, " + std::to_string(best.tm) + "x" +
+                  std::to_string(best.tn) + (best.deep ? " deep" : "") + (best.split ? " split" : ""));
+    out.push_back(std::move(t));
+  }
+  return out;
+}
+
+Shape shape_of(const GemmStage& st) {
+  return {st.tile_m, st.tile_n, st.deep, st.split, st.kc, st.split_min};
+}
+
+// Merged tables of the step matvec (f64 = false) or of the FP64 Rayleigh quotient.
+MergedMatvec build_merged(dm_batch& b, bool f64, hipStream_t s) {
   MergedMatvec m;
   m.prec = f64 ? DM_FP64 : b.prec;
   const bool low = m.prec != DM_FP64;
@@ -240,32 +350,36 @@ MergedMatvec build_merged(dm_batch& b, bool f64) {
     shm.push_back({rb.shift(q.X), 0, rb.shift(q.Z)});
     sh4.push_back({rb.shift(q.Z), rb.shift(q.R), rb.shift(q.out)});
   }
-  m.s1 = merge_gemm(s1, sh1);
-  m.mix = merge_mix(mx, shm);
-  m.s4 = merge_gemm(s4, sh4);
   m.base = rb.base;
-  m.split = dev_alloc((size_t)m.s4.nslots * m.s4.slot_elems() * rb.eb);
+  // the once-per-solve FP64 Rayleigh-quotient matvec keeps the plans' shapes untuned
+  const bool tune = b.tune && !f64;
+  m.s1 = tune_stage(merge_problems(s1, sh1), m.prec, shape_of(*s1[0]), tune, m.base, rb.eb, s, m.tuning);
+  m.mix = merge_mix(mx, shm);
+  m.s4 = tune_stage(merge_problems(s4, sh4), m.prec, shape_of(*s4[0]), tune, m.base, rb.eb, s, m.tuning);
+  size_t split = 0;
+  for (const GemmStage& t : m.s4) split = std::max(split, (size_t)t.nslots * t.slot_elems() * rb.eb);
+  m.split = dev_alloc(split);
   return m;
 }
 
 void run_merged(const MergedMatvec& m, hipStream_t s) {
   if (m.prec == DM_FP64) {
     double* base = (double*)m.base;
-    HIPCHK(launch_gemm<double>(m.s1, base, base, base, nullptr, s));
+    for (const GemmStage& t : m.s1) HIPCHK(launch_gemm<double>(t, base, base, base, nullptr, s));
     HIPCHK(launch_mix<double>(m.mix, base, base, s));
-    HIPCHK(launch_gemm<double>(m.s4, base, base, base, (double*)m.split, s));
+    for (const GemmStage& t : m.s4) HIPCHK(launch_gemm<double>(t, base, base, base, (double*)m.split, s));
   } else {
     float* base = (float*)m.base;
-    HIPCHK(gemm_lp(m.prec, m.s1, base, base, base, nullptr, s));
+    for (const GemmStage& t : m.s1) HIPCHK(gemm_lp(m.prec, t, base, base, base, nullptr, s));
     HIPCHK(launch_mix<float>(m.mix, base, base, s));
-    HIPCHK(gemm_lp(m.prec, m.s4, base, base, base, (float*)m.split, s));
+    for (const GemmStage& t : m.s4) HIPCHK(gemm_lp(m.prec, t, base, base, base, (float*)m.split, s));
   }
 }
 
 void build_batch(dm_batch& b, hipStream_t s) {
-  b.mv = build_merged(b, false);
+  b.mv = build_merged(b, false, s);
   if (b.prec != DM_FP64) {
-    b.mv64 = build_merged(b, true);
+    b.mv64 = build_merged(b, true, s);
     for (dm_heff_plan* p : b.plans) {
       b.cin.push_back({p->dVcur, p->dTin, 2 * p->n(), 0, 0});
       b.cout.push_back({p->dTout, p->dW, 2 * p->n(), 0, 0});
@@ -275,8 +389,8 @@ void build_batch(dm_batch& b, hipStream_t s) {
   }
   TableUpload up;
   for (MergedMatvec* m : {&b.mv, &b.mv64}) {
-    up.add(m->s1);
-    up.add(m->s4);
+    for (GemmStage& t : m->s1) up.add(t);
+    for (GemmStage& t : m->s4) up.add(t);
     up.add(m->mix);
   }
   up.add(b.cin, &b.d_cin);
@@ -317,11 +431,25 @@ extern "C" int dm_batch_create(int32_t n, dm_heff_plan* const* plans, dm_stream 
     HIPCHK(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
     const char* g = getenv("MRDMRG_GRAPH");
     b->use_graph = g && g[0] == '1';
+    const char* t = getenv("MRDMRG_TUNE");  // "0": keep the plans' tile shapes
+    b->tune = !(t && t[0] == '0');
     *out = b.release();
   });
 }
 
 extern "C" void dm_batch_destroy(dm_batch* b) { delete b; }
+
+extern "C" int64_t dm_batch_info(const dm_batch* b, char* buf, int64_t len) {
+  if (!b) return 0;
+  std::string t;
+  for (const std::string& l : b->mv.tuning) t += l + "\n";
+  if (buf && len > 0) {
+    const int64_t n = std::min<int64_t>(len - 1, (int64_t)t.size());
+    std::memcpy(buf, t.data(), (size_t)n);
+    buf[n] = 0;
+  }
+  return (int64_t)t.size() + 1;
+}
 
 extern "C" int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t max_iter,
                                       double tol, double* energies, int32_t* iters,

@@ -311,7 +311,7 @@ hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* par
   dim3 grid(nt), block(256);
 #define MRD_GEMM_CASE(F, D)                                                                \
   if (st.flags == (F) && st.deep == (D) && st.tile_m == (D ? 32 : 64) &&                  \
-      st.tile_n == (D ? 32 : 64) && st.split == (D)) {                                     \
+      st.tile_n == (D ? 32 : 64) && (D || !st.split)) {                                    \
     hipLaunchKernelGGL((gemm_kernel<T, F, D>), grid, block, 0, s, st.d_segs, st.d_probs,   \
                        st.d_tiles, st.d_rows, st.d_asrc, A, B, C, part, skip);             \
     if (between) between();                                                                \
@@ -326,6 +326,9 @@ hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* par
   MRD_GEMM_CASE(G_A_ROWMAP | G_B_T, false)
   MRD_GEMM_CASE(G_A_CONJ, false)
   MRD_GEMM_CASE(G_B_T | G_C_ROWMAP, true)
+  // further shapes for the batched tile tuning
+  MRD_GEMM_CASE(0, true)
+  MRD_GEMM_CASE(G_B_T | G_C_ROWMAP, false)
 #undef MRD_GEMM_CASE
   return hipErrorInvalidValue;
 }

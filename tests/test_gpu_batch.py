@@ -1,9 +1,10 @@
 """Batched Lanczos: many windows of different shape in one set of launches.
 
-Each instance of a batch runs exactly the arithmetic of its single-plan solve (same
-kernels per tile, same fixed-order reductions), so energies, step counts and Ritz
-vectors must equal the single-plan results bit for bit, and those match the FP64
-oracle's Lanczos."""
+With the plans' own tile shapes (tuning off) each instance of a batch runs exactly the
+arithmetic of its single-plan solve (same kernels per tile, same fixed-order
+reductions): energies, step counts and Ritz vectors equal the single-plan results bit
+for bit.  With the tuned shapes (default) the block GEMMs may sum in another order:
+results agree to the precision's rounding.  Both match the FP64 oracle's Lanczos."""
 import sys
 import time
 
@@ -37,9 +38,15 @@ def starts(name, seed):
     return v + 0.3 * (rng.standard_normal(v.size) + 1j * rng.standard_normal(v.size))
 
 
+# matvec tolerance of each precision (relative to the largest element)
+TOL = {pk.DM_FP64: 1e-12, pk.DM_FP32: 2e-5, pk.DM_BF16X3: 1e-4}
+
+
+@pytest.mark.parametrize("tuned", [False, True])
 @pytest.mark.parametrize("prec", [pk.DM_FP64, pk.DM_FP32, pk.DM_BF16X3])
-def test_batched_equals_single(prec):
-    say(f"batched vs single prec={prec}")
+def test_batched_equals_single(prec, tuned, monkeypatch):
+    say(f"batched vs single prec={prec} tuned={tuned}")
+    monkeypatch.setenv("MRDMRG_TUNE", "1" if tuned else "0")
     gs, plans, x0 = [], [], []
     for i, name in enumerate(NAMES):
         wl, L, W1, W2, R, th, keys, mpo = problem(name)
@@ -56,9 +63,17 @@ def test_batched_equals_single(prec):
         for i, p in enumerate(plans):
             xs = x0[i].clone()
             es, ks = pk.lanczos_ground(p, xs, 30, 1e-14)
-            assert kb[i] == ks and eb[i] == es, (rep, i, eb[i], es)
-            assert torch.equal(xb[i], xs)
+            assert kb[i] == ks, (rep, i)
+            if tuned:
+                assert abs(eb[i] - es) <= 100 * TOL[prec] * abs(es), (rep, i, eb[i], es)
+                assert 1 - abs(complex(torch.vdot(xb[i], xs))) <= 100 * TOL[prec], (rep, i)
+            else:
+                assert eb[i] == es, (rep, i, eb[i], es)
+                assert torch.equal(xb[i], xs)
             assert 0 < us[i] <= wall_us
+    if tuned:
+        say(batch.info())
+        assert batch.info().count("bucket") >= 2
     if prec == pk.DM_FP64:
         for i, name in enumerate(NAMES):
             wl, L, W1, W2, R, th, keys, mpo = problem(name)
