@@ -185,7 +185,7 @@ __global__ void lz_start_scale_kernel(const LzInst* __restrict__ I, int nins) {
   in.vcur[2 * e + 1] = b;
 }
 
-constexpr int LZ_G = 4;  // Krylov vectors per dot-product block
+constexpr int LZ_G = 8;  // Krylov vectors per dot-product block
 
 // Block sums of NVAL per-thread values with one barrier (wave shuffles, then the four
 // wave partials in a fixed order); out[c] for c < nval.
@@ -206,10 +206,34 @@ __device__ __forceinline__ void block_sums(const double (&v)[NVAL], int nval, do
 }
 
 // part[y][2i + {0,1}] = sum of conj(V_i) w over the elements e = (y + nb1 q) * 256 +
-// thread, q = 0, 1, ..., for the LZ_G vectors i = LZ_G * blockIdx.x + g < nv (nv =
-// iter + 1), y = this block's dot-product block within its instance.  Each thread
+// thread, q = 0, 1, ..., for the (up to) LZ_G vectors i = LZ_G * blockIdx.x + g < nv
+// (nv = iter + 1), y = this block's dot-product block within its instance.  Each thread
 // accumulates many elements before the single block reduction; consecutive blocks
 // (same y, next group) read the same w elements, which stay in L2.
+// Dot products of NG Krylov vectors (NG = the number of this block's vectors that exist)
+// with w over the block's elements, then the block sums.
+template <int NG>
+__device__ __forceinline__ void lz_dots_body(const LzInst& in, int i0, int nv, int y, double* sh) {
+  const double2* xv = reinterpret_cast<const double2*>(in.w);
+  const double2* vv[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) vv[g] = reinterpret_cast<const double2*>(in.V) + (int64_t)(i0 + g) * in.ld;
+  double acc[2 * NG];
+#pragma unroll
+  for (int c = 0; c < 2 * NG; ++c) acc[c] = 0.0;
+  const int64_t stride = (int64_t)in.nb1 * 256, n = in.n;
+  for (int64_t e = (int64_t)y * 256 + threadIdx.x; e < n; e += stride) {
+    const double2 xe = xv[e];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      const double2 v = vv[g][e];
+      acc[2 * g] += v.x * xe.x + v.y * xe.y;
+      acc[2 * g + 1] += v.x * xe.y - v.y * xe.x;
+    }
+  }
+  block_sums(acc, 2 * NG, sh, in.part + y * (int64_t)(2 * nv) + 2 * i0);
+}
+
 __global__ void __launch_bounds__(256) lz_dots_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4 * 2 * LZ_G];
   const int q0 = lz_find<2>(I, nins, blockIdx.y);
@@ -219,25 +243,16 @@ __global__ void __launch_bounds__(256) lz_dots_kernel(const LzInst* __restrict__
   const int i0 = blockIdx.x * LZ_G;
   if (i0 >= nv) return;
   const int y = blockIdx.y - in.d0;
-  const double2* xv = reinterpret_cast<const double2*>(in.w);
-  const double2* vv[LZ_G];
-#pragma unroll
-  for (int g = 0; g < LZ_G; ++g)
-    vv[g] = reinterpret_cast<const double2*>(in.V) + (int64_t)min(i0 + g, nv - 1) * in.ld;
-  double acc[2 * LZ_G];
-#pragma unroll
-  for (int c = 0; c < 2 * LZ_G; ++c) acc[c] = 0.0;
-  const int64_t stride = (int64_t)in.nb1 * 256, n = in.n;
-  for (int64_t e = (int64_t)y * 256 + threadIdx.x; e < n; e += stride) {
-    const double2 xe = xv[e];
-#pragma unroll
-    for (int g = 0; g < LZ_G; ++g) {
-      const double2 v = vv[g][e];
-      acc[2 * g] += v.x * xe.x + v.y * xe.y;
-      acc[2 * g + 1] += v.x * xe.y - v.y * xe.x;
-    }
+  switch (min(LZ_G, nv - i0)) {  // uniform over the block
+    case 1: lz_dots_body<1>(in, i0, nv, y, sh); break;
+    case 2: lz_dots_body<2>(in, i0, nv, y, sh); break;
+    case 3: lz_dots_body<3>(in, i0, nv, y, sh); break;
+    case 4: lz_dots_body<4>(in, i0, nv, y, sh); break;
+    case 5: lz_dots_body<5>(in, i0, nv, y, sh); break;
+    case 6: lz_dots_body<6>(in, i0, nv, y, sh); break;
+    case 7: lz_dots_body<7>(in, i0, nv, y, sh); break;
+    default: lz_dots_body<LZ_G>(in, i0, nv, y, sh); break;
   }
-  block_sums(acc, 2 * min(LZ_G, nv - i0), sh, in.part + y * (int64_t)(2 * nv) + 2 * i0);
 }
 
 // w -= V h1 over the nv = iter + 1 Krylov vectors; pnorm[chunk] = |w_new|^2 over the chunk.
