@@ -6,7 +6,8 @@
 //   v_0 = theta / |theta|
 //   step j:  w = H v_j
 //            h1 = V^H w,  alpha_j = Re h1_j            (V = [v_0 .. v_j])
-//            w1 = w - V h1,  h2 = V^H w1        (four streaming passes over V)
+//            w1 = w - V h1,  h2 = V^H w1        (three streaming passes over V; four
+//                                                beyond LZ_FUSE vectors)
 //            beta_j = |w1 - V h2| = sqrt(|w1|^2 - |h2|^2)
 //            stop if beta_j <= tol * |T| (|T| = max_i |alpha_i| + beta_i + beta_{i-1})
 //            or j = max_iter - 1;  else v_{j+1} = (w1 - V h2) / beta_j
@@ -35,8 +36,12 @@ static int lz_nblk256(int64_t n) { return (int)((n + 255) / 256); }
 // dot-product blocks along the vector: about 16 elements per thread
 static int lz_dots_nblk(int64_t n) { return (int)std::max<int64_t>(1, (n + 4095) / 4096); }
 
+// rows of projection partials: dot-product blocks (first projection) or chunk blocks
+// (fused subtraction and second projection), whichever is more
+static int64_t lz_part_rows(int64_t n) { return std::max(lz_dots_nblk(n), lz_nblk(n)); }
+
 int64_t lz_part_doubles(int64_t n, int32_t max_iter) {
-  return (int64_t)lz_dots_nblk(n) * (2 * max_iter + 1) + 2 * (int64_t)lz_nblk(n);
+  return lz_part_rows(n) * (2 * max_iter + 1) + 2 * (int64_t)lz_nblk(n);
 }
 
 LzGrid lz_layout(std::vector<LzInst>& I, int32_t max_iter) {
@@ -46,7 +51,7 @@ LzGrid lz_layout(std::vector<LzInst>& I, int32_t max_iter) {
   for (auto& x : I) {
     x.nb = lz_nblk(x.n);
     x.nb1 = lz_dots_nblk(x.n);
-    x.pnorm = x.part + (int64_t)x.nb1 * (2 * max_iter + 1);
+    x.pnorm = x.part + lz_part_rows(x.n) * (2 * max_iter + 1);
     x.c0 = g.nchunk;
     x.g0 = g.n256;
     x.d0 = g.ndots;
@@ -129,6 +134,7 @@ enum LzReduce : int32_t {
   LZR_H2 = 2,     // dot partials -> h2
   LZR_NORM = 3,   // sum of pnorm -> h2[2 nv] (|w1|^2)
   LZR_RQ = 4,     // pnorm pairs -> rq[0..1]
+  LZR_H2N = 5,    // chunk partials -> h2 and |w1|^2 (2 nv + 1 components)
 };
 
 // Fixed-order reduction of one component (blockIdx.x) of instance blockIdx.y.
@@ -136,7 +142,7 @@ __global__ void __launch_bounds__(256) lz_reduce_kernel(const LzInst* __restrict
   __shared__ double sm[256];
   const LzInst& in = I[blockIdx.y];
   LzState* st = in.st;
-  const bool step = mode == LZR_H1 || mode == LZR_H2 || mode == LZR_NORM;
+  const bool step = mode == LZR_H1 || mode == LZR_H2 || mode == LZR_NORM || mode == LZR_H2N;
   if (step && st->stop) return;
   const int nv = st->iter + 1;
   const double* src;
@@ -147,6 +153,7 @@ __global__ void __launch_bounds__(256) lz_reduce_kernel(const LzInst* __restrict
     case LZR_H1: src = in.part; nblk = in.nb1; ncomp = 2 * nv; out = st->h1; break;
     case LZR_H2: src = in.part; nblk = in.nb1; ncomp = 2 * nv; out = st->h2; break;
     case LZR_NORM: src = in.pnorm; nblk = in.nb; ncomp = 1; out = st->h2 + 2 * nv; break;
+    case LZR_H2N: src = in.part; nblk = in.nb; ncomp = 2 * nv + 1; out = st->h2; break;
     default: src = in.pnorm; nblk = in.nb; ncomp = 2; out = st->rq; break;
   }
   const int c = blockIdx.x;
@@ -286,6 +293,81 @@ __global__ void __launch_bounds__(256) lz_sub_kernel(const LzInst* __restrict__ 
   }
   nn = block_sum(nn, sh);
   if (threadIdx.x == 0) in.pnorm[blk] = nn;
+}
+
+// The subtraction and the second projection in one pass over the basis (bases of at
+// most LZ_FUSE vectors): w1 = w - V h1 over the nv = iter + 1 Krylov vectors, then
+// part[blk][2i + {0,1}] = sum of conj(V_i) w1 and part[blk][2 nv] = sum of |w1|^2 over
+// the chunk blk (elements blk * LZ_CHUNK + q * 256 + thread, q < LZ_EPT).  Each thread
+// holds its element of every vector in registers between the subtraction and the
+// products (NVB >= nv of them, unrolled; vectors i >= nv are skipped by a branch that
+// is uniform over the block), so the basis is read once for both.
+constexpr int LZ_FUSE = 32;
+
+template <int NVB>
+__device__ __forceinline__ void lz_subdots_body(const LzInst& in, int nv, int blk, double* sh) {
+  const double* h1 = in.st->h1;
+  double2* w = reinterpret_cast<double2*>(in.w);
+  const double2* V = reinterpret_cast<const double2*>(in.V);
+  const int64_t ld = in.ld;
+  double acc[2 * NVB + 1];
+#pragma unroll
+  for (int c = 0; c < 2 * NVB + 1; ++c) acc[c] = 0.0;
+#pragma unroll 1
+  for (int q = 0; q < LZ_EPT; ++q) {
+    const int64_t e = (int64_t)blk * LZ_CHUNK + q * 256 + threadIdx.x;
+    if (e >= in.n) break;
+    double2 v[NVB];
+#pragma unroll
+    for (int i = 0; i < NVB; ++i)
+      if (i < nv) v[i] = V[i * ld + e];
+    double2 x = w[e];
+#pragma unroll
+    for (int i = 0; i < NVB; ++i)
+      if (i < nv) {
+        const double hr = h1[2 * i], hi = h1[2 * i + 1];
+        x.x -= hr * v[i].x - hi * v[i].y;
+        x.y -= hr * v[i].y + hi * v[i].x;
+      }
+    w[e] = x;
+#pragma unroll
+    for (int i = 0; i < NVB; ++i)
+      if (i < nv) {
+        acc[2 * i] += v[i].x * x.x + v[i].y * x.y;
+        acc[2 * i + 1] += v[i].x * x.y - v[i].y * x.x;
+      }
+    acc[2 * NVB] += x.x * x.x + x.y * x.y;
+  }
+  // block sums in a fixed order: wave shuffles, then the four wave partials
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < 2 * NVB + 1; ++c) {
+    if (c < 2 * nv || c == 2 * NVB) {
+      const double t = wave_sum(acc[c]);
+      if (lane == 0) sh[c * 4 + wv] = t;
+    }
+  }
+  __syncthreads();
+  double* out = in.part + (int64_t)blk * (2 * nv + 1);
+  const int c = threadIdx.x;
+  if (c <= 2 * nv) {
+    const int src = c < 2 * nv ? c : 2 * NVB;
+    out[c] = (sh[src * 4] + sh[src * 4 + 1]) + (sh[src * 4 + 2] + sh[src * 4 + 3]);
+  }
+}
+
+__global__ void __launch_bounds__(256) lz_subdots_kernel(const LzInst* __restrict__ I, int nins) {
+  __shared__ double sh[4 * (2 * LZ_FUSE + 1)];
+  const int q0 = lz_find<0>(I, nins, blockIdx.x);
+  const LzInst& in = I[q0];
+  if (in.st->stop) return;
+  const int nv = in.st->iter + 1;
+  const int blk = blockIdx.x - in.c0;
+  if (nv <= 8) lz_subdots_body<8>(in, nv, blk, sh);
+  else if (nv <= 16) lz_subdots_body<16>(in, nv, blk, sh);
+  else if (nv <= 24) lz_subdots_body<24>(in, nv, blk, sh);
+  else if (nv <= LZ_FUSE) lz_subdots_body<LZ_FUSE>(in, nv, blk, sh);
+  // larger bases are launched on the unfused path (the host checks the capacity)
 }
 
 // Scalar part of step j = st->iter of instance blockIdx.x: alpha_j, beta_j, |T|, stopping rule.
@@ -544,10 +626,16 @@ hipError_t lz_launch_step_tail(const LzInst* I, const LzGrid& g, hipStream_t s) 
   const dim3 gd((g.max_iter + LZ_G - 1) / LZ_G, g.ndots);
   hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, I, g.nins);
   hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H1);
-  hipLaunchKernelGGL(lz_sub_kernel, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
-  hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, I, g.nins);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H2);
-  hipLaunchKernelGGL(lz_reduce_kernel, dim3(1, g.nins), dim3(256), 0, s, I, (int32_t)LZR_NORM);
+  if (g.max_iter <= LZ_FUSE) {
+    // nv <= max_iter <= LZ_FUSE at every step: one pass for w1, h2 and |w1|^2
+    hipLaunchKernelGGL(lz_subdots_kernel, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+    hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H2N);
+  } else {
+    hipLaunchKernelGGL(lz_sub_kernel, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+    hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, I, g.nins);
+    hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H2);
+    hipLaunchKernelGGL(lz_reduce_kernel, dim3(1, g.nins), dim3(256), 0, s, I, (int32_t)LZR_NORM);
+  }
   hipLaunchKernelGGL(lz_scalar_kernel, dim3(g.nins), dim3(64), 0, s, I);
   hipLaunchKernelGGL(lz_next_kernel, dim3(g.n256), dim3(256), 0, s, I, g.nins);
   return hipGetLastError();

@@ -61,6 +61,24 @@ def test_lanczos_parity_fp64(name):
     assert 1 - abs(np.vdot(vo, v)) < 1e-8
 
 
+@pytest.mark.parametrize("max_iter", [8, 17, 25, 48])
+def test_lanczos_parity_basis_sizes(max_iter):
+    """Krylov bases of every register width of the fused subtraction-projection pass
+    (up to 8, 16, 24 and 32 vectors) and one beyond it (unfused passes)."""
+    wl, L, W1, W2, R, th, keys, mpo = problem("ly4_chi64")
+    say(f"lanczos ly4_chi64 max_iter={max_iter}")
+    g = WindowGPU(wl, L, R, mpo)
+    plan = g.plan(pk.DM_FP64)
+    x = to_dev(g.pack_theta(th))
+    e, k = pk.lanczos_ground(plan, x, max_iter, 1e-14)
+    mv = lambda v: bs.flatten(bs.heff_apply(L, W1, W2, R, bs.unflatten(v, keys)), keys)
+    eo, vo, ko, _, _ = olz.lanczos(mv, bs.flatten(th, keys), max_iter=max_iter)
+    assert k == ko
+    assert abs(e - eo) <= 1e-10 * abs(eo)
+    v = bs.flatten(g.unpack_theta(x.cpu().numpy()), keys)
+    assert 1 - abs(np.vdot(vo, v)) < 1e-8
+
+
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("prec,tol", PRECS)
 def test_env_updates_parity(name, prec, tol):
