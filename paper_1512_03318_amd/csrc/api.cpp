@@ -484,10 +484,12 @@ void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
   }
 }
 
-// One Lanczos step: w = H v_j, projections, scalars, v_{j+1}.  Fixed arguments.
-static void lanczos_step(dm_heff_plan* p, hipStream_t s, bool capturing) {
+// One Lanczos step: w = H v_j, projections, scalars, v_{j+1}.  The device state holds
+// the step index; j + 1 (or 0 for a step captured once for every replay) only bounds
+// the Krylov vector count so the projection kernels can be sized to it.
+static void lanczos_step(dm_heff_plan* p, hipStream_t s, bool capturing, int32_t j) {
   heff_run(p, p->dVcur, p->dW, s, false, &p->dState->stop, capturing);
-  HIPCHK(lz_launch_step_tail(p->dInst, p->lzg, s));
+  HIPCHK(lz_launch_step_tail(p->dInst, p->lzg, capturing ? 0 : j + 1, s));
 }
 
 extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double tol,
@@ -509,7 +511,7 @@ extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_it
       if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
       HIPCHK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
       try {
-        lanczos_step(p, p->cap_stream, true);
+        lanczos_step(p, p->cap_stream, true, 0);
       } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(p->cap_stream, &g);
@@ -523,7 +525,7 @@ extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_it
       if (graph)
         HIPCHK(hipGraphLaunch(p->graph_exec, s));
       else
-        lanczos_step(p, s, false);
+        lanczos_step(p, s, false, j);
     }
     HIPCHK(lz_launch_finish(p->dInst, p->lzg, s));
     if (p->prec != DM_FP64) {

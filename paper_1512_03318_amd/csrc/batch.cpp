@@ -399,13 +399,15 @@ void build_batch(dm_batch& b, hipStream_t s) {
   b.built = true;
 }
 
-void batch_step(dm_batch& b, hipStream_t s) {
+// One batched Lanczos step; nv_bound as for lz_launch_step_tail (step index + 1, or 0
+// for the captured step).
+void batch_step(dm_batch& b, hipStream_t s, int32_t nv_bound) {
   if (b.prec != DM_FP64)
     HIPCHK(launch_cast_batch(true, b.d_cin, (int32_t)b.cin.size(), b.cin_blocks, s));
   run_merged(b.mv, s);
   if (b.prec != DM_FP64)
     HIPCHK(launch_cast_batch(false, b.d_cout, (int32_t)b.cout.size(), b.cout_blocks, s));
-  HIPCHK(lz_launch_step_tail(b.dInst, b.lzg, s));
+  HIPCHK(lz_launch_step_tail(b.dInst, b.lzg, nv_bound, s));
 }
 
 }  // namespace
@@ -509,7 +511,7 @@ extern "C" int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t 
       if (!b->cap_stream) HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
       HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
       try {
-        batch_step(*b, b->cap_stream);
+        batch_step(*b, b->cap_stream, 0);
       } catch (...) {
         hipGraph_t gr = nullptr;
         (void)hipStreamEndCapture(b->cap_stream, &gr);
@@ -523,7 +525,7 @@ extern "C" int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t 
       if (b->use_graph)
         HIPCHK(hipGraphLaunch(b->graph_exec, s));
       else
-        batch_step(*b, s);
+        batch_step(*b, s, j + 1);
     }
     HIPCHK(lz_launch_finish(b->dInst, b->lzg, s));
     if (b->prec != DM_FP64) {

@@ -185,22 +185,22 @@ struct LzState {
 
 // One Lanczos instance of a (possibly batched) launch.  Every Lanczos kernel runs over
 // all instances of its table at once: a flat grid whose blocks are assigned to
-// instances by the first-block offsets c0 / g0 / d0 (found by binary search).
+// instances by the first-block offsets c0 / g0 (found by binary search).
 struct LzInst {
   double* V;       // Krylov basis, vector j at V + 2 j ld (doubles)
   double* w;       // H v_j
   double* vcur;    // v_j (matvec input of every step)
-  double* part;    // dot-product partials: nb1 x (2 max_iter + 1)
+  double* part;    // projection partials: nb x (2 max_iter + 1)
   double* pnorm;   // norm / Rayleigh-quotient partials: 2 nb
   double* x;       // caller's start vector in, Ritz vector out
   LzState* st;
   int64_t ld, n;   // n complex elements
-  int32_t nb, nb1; // chunk blocks (1024 elements), dot-product blocks
-  int32_t c0, g0, d0, pad;  // first chunk / 256-element / dot-product block of this instance
+  int32_t nb;      // chunk blocks (1024 elements)
+  int32_t c0, g0;  // first chunk / 256-element block of this instance
 };
 // Launch shape of an instance table (host side).
 struct LzGrid {
-  int32_t nins = 0, nchunk = 0, n256 = 0, ndots = 0;
+  int32_t nins = 0, nchunk = 0, n256 = 0;
   int32_t max_iter = 0;  // capacity: Krylov vectors - 1 of every instance
 };
 struct LzResult {
@@ -208,15 +208,17 @@ struct LzResult {
   int32_t k, bad;
   uint64_t t0, t1;
 };
-// Fills nb, nb1, pnorm and the block offsets of I (V, w, vcur, part, x, st, ld, n set by
-// the caller; part must hold nb1 (2 max_iter + 1) + 2 nb doubles, see lz_part_doubles).
+// Fills nb, pnorm and the block offsets of I (V, w, vcur, part, x, st, ld, n set by
+// the caller; part must hold nb (2 max_iter + 1) + 2 nb doubles, see lz_part_doubles).
 LzGrid lz_layout(std::vector<LzInst>& I, int32_t max_iter);
 int64_t lz_part_doubles(int64_t n, int32_t max_iter);
 // Resets the states for a solve of at most max_iter (<= g.max_iter) steps.
 hipError_t lz_launch_init(const LzInst* I, const LzGrid& g, int32_t max_iter, double tol,
                           hipStream_t s);
 hipError_t lz_launch_start(const LzInst* I, const LzGrid& g, hipStream_t s);
-hipError_t lz_launch_step_tail(const LzInst* I, const LzGrid& g, hipStream_t s);
+// nv_bound: an upper bound of the Krylov vector count at this step (step index + 1),
+// or 0 when unknown (a step captured once and replayed)
+hipError_t lz_launch_step_tail(const LzInst* I, const LzGrid& g, int32_t nv_bound, hipStream_t s);
 // Lowest Ritz pair; the Ritz vector goes to x and to vcur.
 hipError_t lz_launch_finish(const LzInst* I, const LzGrid& g, hipStream_t s);
 // energy = <vcur, w> / <vcur, vcur> (w = FP64 H vcur computed by the caller).

@@ -6,8 +6,8 @@
 //   v_0 = theta / |theta|
 //   step j:  w = H v_j
 //            h1 = V^H w,  alpha_j = Re h1_j            (V = [v_0 .. v_j])
-//            w1 = w - V h1,  h2 = V^H w1        (three streaming passes over V; four
-//                                                beyond LZ_FUSE vectors)
+//            w1 = w - V h1,  h2 = V^H w1        (three streaming passes over V up to
+//                                                LZ_FUSE vectors, four beyond)
 //            beta_j = |w1 - V h2| = sqrt(|w1|^2 - |h2|^2)
 //            stop if beta_j <= tol * |T| (|T| = max_i |alpha_i| + beta_i + beta_{i-1})
 //            or j = max_iter - 1;  else v_{j+1} = (w1 - V h2) / beta_j
@@ -33,15 +33,10 @@ constexpr int LZ_CHUNK = 256 * LZ_EPT;
 
 static int lz_nblk(int64_t n) { return (int)((n + LZ_CHUNK - 1) / LZ_CHUNK); }
 static int lz_nblk256(int64_t n) { return (int)((n + 255) / 256); }
-// dot-product blocks along the vector: about 16 elements per thread
-static int lz_dots_nblk(int64_t n) { return (int)std::max<int64_t>(1, (n + 4095) / 4096); }
-
-// rows of projection partials: dot-product blocks (first projection) or chunk blocks
-// (fused subtraction and second projection), whichever is more
-static int64_t lz_part_rows(int64_t n) { return std::max(lz_dots_nblk(n), lz_nblk(n)); }
-
+// projection partials: one row of at most 2 max_iter + 1 doubles per chunk, then the
+// norm partials
 int64_t lz_part_doubles(int64_t n, int32_t max_iter) {
-  return lz_part_rows(n) * (2 * max_iter + 1) + 2 * (int64_t)lz_nblk(n);
+  return (int64_t)lz_nblk(n) * (2 * max_iter + 1) + 2 * (int64_t)lz_nblk(n);
 }
 
 LzGrid lz_layout(std::vector<LzInst>& I, int32_t max_iter) {
@@ -50,25 +45,22 @@ LzGrid lz_layout(std::vector<LzInst>& I, int32_t max_iter) {
   g.max_iter = max_iter;
   for (auto& x : I) {
     x.nb = lz_nblk(x.n);
-    x.nb1 = lz_dots_nblk(x.n);
-    x.pnorm = x.part + lz_part_rows(x.n) * (2 * max_iter + 1);
+    x.pnorm = x.part + (int64_t)x.nb * (2 * max_iter + 1);
     x.c0 = g.nchunk;
     x.g0 = g.n256;
-    x.d0 = g.ndots;
     g.nchunk += x.nb;
     g.n256 += lz_nblk256(x.n);
-    g.ndots += x.nb1;
   }
   return g;
 }
 
-// Instance owning flat block b of a grid laid out by the offsets F (0: c0, 1: g0, 2: d0).
+// Instance owning flat block b of a grid laid out by the offsets F (0: c0, 1: g0).
 template <int F>
 __device__ __forceinline__ int lz_find(const LzInst* __restrict__ I, int nins, int b) {
   int lo = 0, hi = nins - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int v = F == 0 ? I[mid].c0 : (F == 1 ? I[mid].g0 : I[mid].d0);
+    const int v = F == 0 ? I[mid].c0 : I[mid].g0;
     if (v <= b) lo = mid;
     else hi = mid - 1;
   }
@@ -130,8 +122,8 @@ __global__ void __launch_bounds__(256) lz_norm_kernel(const LzInst* __restrict__
 
 enum LzReduce : int32_t {
   LZR_SCAL0 = 0,  // sum of pnorm -> scal0
-  LZR_H1 = 1,     // dot partials -> h1 (2 nv components)
-  LZR_H2 = 2,     // dot partials -> h2
+  LZR_H1 = 1,     // chunk partials -> h1 (2 nv components)
+  LZR_H2 = 2,     // chunk partials -> h2
   LZR_NORM = 3,   // sum of pnorm -> h2[2 nv] (|w1|^2)
   LZR_RQ = 4,     // pnorm pairs -> rq[0..1]
   LZR_H2N = 5,    // chunk partials -> h2 and |w1|^2 (2 nv + 1 components)
@@ -142,7 +134,7 @@ __global__ void __launch_bounds__(256) lz_reduce_kernel(const LzInst* __restrict
   __shared__ double sm[256];
   const LzInst& in = I[blockIdx.y];
   LzState* st = in.st;
-  const bool step = mode == LZR_H1 || mode == LZR_H2 || mode == LZR_NORM || mode == LZR_H2N;
+  const bool step = mode != LZR_SCAL0 && mode != LZR_RQ;
   if (step && st->stop) return;
   const int nv = st->iter + 1;
   const double* src;
@@ -150,8 +142,8 @@ __global__ void __launch_bounds__(256) lz_reduce_kernel(const LzInst* __restrict
   double* out;
   switch (mode) {
     case LZR_SCAL0: src = in.pnorm; nblk = in.nb; ncomp = 1; out = &st->scal0; break;
-    case LZR_H1: src = in.part; nblk = in.nb1; ncomp = 2 * nv; out = st->h1; break;
-    case LZR_H2: src = in.part; nblk = in.nb1; ncomp = 2 * nv; out = st->h2; break;
+    case LZR_H1: src = in.part; nblk = in.nb; ncomp = 2 * nv; out = st->h1; break;
+    case LZR_H2: src = in.part; nblk = in.nb; ncomp = 2 * nv; out = st->h2; break;
     case LZR_NORM: src = in.pnorm; nblk = in.nb; ncomp = 1; out = st->h2 + 2 * nv; break;
     case LZR_H2N: src = in.part; nblk = in.nb; ncomp = 2 * nv + 1; out = st->h2; break;
     default: src = in.pnorm; nblk = in.nb; ncomp = 2; out = st->rq; break;
@@ -212,15 +204,12 @@ __device__ __forceinline__ void block_sums(const double (&v)[NVAL], int nval, do
   }
 }
 
-// part[y][2i + {0,1}] = sum of conj(V_i) w over the elements e = (y + nb1 q) * 256 +
-// thread, q = 0, 1, ..., for the (up to) LZ_G vectors i = LZ_G * blockIdx.x + g < nv
-// (nv = iter + 1), y = this block's dot-product block within its instance.  Each thread
-// accumulates many elements before the single block reduction; consecutive blocks
-// (same y, next group) read the same w elements, which stay in L2.
-// Dot products of NG Krylov vectors (NG = the number of this block's vectors that exist)
-// with w over the block's elements, then the block sums.
+// part[blk][2i + {0,1}] = sum over chunk blk of conj(V_i) w for the (up to) LZ_G
+// vectors i = LZ_G * blockIdx.x + g < nv (nv = iter + 1).  Chunk blk holds the elements
+// blk * LZ_CHUNK + q * 256 + thread, q < LZ_EPT.  Blocks of the same chunk and other
+// groups read the same w elements (L2 hits).
 template <int NG>
-__device__ __forceinline__ void lz_dots_body(const LzInst& in, int i0, int nv, int y, double* sh) {
+__device__ __forceinline__ void lz_dots_body(const LzInst& in, int i0, int nv, int blk, double* sh) {
   const double2* xv = reinterpret_cast<const double2*>(in.w);
   const double2* vv[NG];
 #pragma unroll
@@ -228,37 +217,40 @@ __device__ __forceinline__ void lz_dots_body(const LzInst& in, int i0, int nv, i
   double acc[2 * NG];
 #pragma unroll
   for (int c = 0; c < 2 * NG; ++c) acc[c] = 0.0;
-  const int64_t stride = (int64_t)in.nb1 * 256, n = in.n;
-  for (int64_t e = (int64_t)y * 256 + threadIdx.x; e < n; e += stride) {
-    const double2 xe = xv[e];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      const double2 v = vv[g][e];
-      acc[2 * g] += v.x * xe.x + v.y * xe.y;
-      acc[2 * g + 1] += v.x * xe.y - v.y * xe.x;
+  for (int q = 0; q < LZ_EPT; ++q) {
+    const int64_t e = (int64_t)blk * LZ_CHUNK + q * 256 + threadIdx.x;
+    if (e < in.n) {
+      const double2 xe = xv[e];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const double2 v = vv[g][e];
+        acc[2 * g] += v.x * xe.x + v.y * xe.y;
+        acc[2 * g + 1] += v.x * xe.y - v.y * xe.x;
+      }
     }
   }
-  block_sums(acc, 2 * NG, sh, in.part + y * (int64_t)(2 * nv) + 2 * i0);
+  block_sums(acc, 2 * NG, sh, in.part + (int64_t)blk * (2 * nv) + 2 * i0);
 }
 
 __global__ void __launch_bounds__(256) lz_dots_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4 * 2 * LZ_G];
-  const int q0 = lz_find<2>(I, nins, blockIdx.y);
+  const int q0 = lz_find<0>(I, nins, blockIdx.y);
   const LzInst& in = I[q0];
   if (in.st->stop) return;
   const int nv = in.st->iter + 1;
   const int i0 = blockIdx.x * LZ_G;
   if (i0 >= nv) return;
-  const int y = blockIdx.y - in.d0;
+  const int blk = blockIdx.y - in.c0;
   switch (min(LZ_G, nv - i0)) {  // uniform over the block
-    case 1: lz_dots_body<1>(in, i0, nv, y, sh); break;
-    case 2: lz_dots_body<2>(in, i0, nv, y, sh); break;
-    case 3: lz_dots_body<3>(in, i0, nv, y, sh); break;
-    case 4: lz_dots_body<4>(in, i0, nv, y, sh); break;
-    case 5: lz_dots_body<5>(in, i0, nv, y, sh); break;
-    case 6: lz_dots_body<6>(in, i0, nv, y, sh); break;
-    case 7: lz_dots_body<7>(in, i0, nv, y, sh); break;
-    default: lz_dots_body<LZ_G>(in, i0, nv, y, sh); break;
+    case 1: lz_dots_body<1>(in, i0, nv, blk, sh); break;
+    case 2: lz_dots_body<2>(in, i0, nv, blk, sh); break;
+    case 3: lz_dots_body<3>(in, i0, nv, blk, sh); break;
+    case 4: lz_dots_body<4>(in, i0, nv, blk, sh); break;
+    case 5: lz_dots_body<5>(in, i0, nv, blk, sh); break;
+    case 6: lz_dots_body<6>(in, i0, nv, blk, sh); break;
+    case 7: lz_dots_body<7>(in, i0, nv, blk, sh); break;
+    default: lz_dots_body<LZ_G>(in, i0, nv, blk, sh); break;
   }
 }
 
@@ -295,18 +287,61 @@ __global__ void __launch_bounds__(256) lz_sub_kernel(const LzInst* __restrict__ 
   if (threadIdx.x == 0) in.pnorm[blk] = nn;
 }
 
-// The subtraction and the second projection in one pass over the basis (bases of at
-// most LZ_FUSE vectors): w1 = w - V h1 over the nv = iter + 1 Krylov vectors, then
-// part[blk][2i + {0,1}] = sum of conj(V_i) w1 and part[blk][2 nv] = sum of |w1|^2 over
-// the chunk blk (elements blk * LZ_CHUNK + q * 256 + thread, q < LZ_EPT).  Each thread
-// holds its element of every vector in registers between the subtraction and the
-// products (NVB >= nv of them, unrolled; vectors i >= nv are skipped by a branch that
-// is uniform over the block), so the basis is read once for both.
-constexpr int LZ_FUSE = 32;
+// Fused pass for bases of at most LZ_FUSE vectors, specialised on a bound NVB >= nv of
+// the vector count (nv = iter + 1; the host passes the step's bound rounded up to a
+// multiple of 8), so that the per-thread registers, and with them the occupancy, follow
+// the basis size.  Vectors i >= nv are skipped by branches uniform over the block.
+// Beyond 24 vectors the registers (about 280 per thread) leave one wave per SIMD, and
+// the separate subtraction and grouped projection passes stream faster.
+constexpr int LZ_FUSE = 24;
 
+// Fixed-order block sums of the first ncomp of NV per-thread values (wave shuffles, then
+// the four wave partials) into out[c]; value `last` goes to out[ncomp - 1] when given.
+template <int NV>
+__device__ __forceinline__ void block_sums_n(const double (&acc)[NV], int ncomp, int last,
+                                            double* sh, double* out) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    if (c < ncomp || c == last) {
+      const double t = wave_sum(acc[c]);
+      if (lane == 0) sh[c * 4 + wv] = t;
+    }
+  }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < ncomp) {
+    const int src = (last >= 0 && c == ncomp - 1) ? last : c;
+    out[c] = (sh[src * 4] + sh[src * 4 + 1]) + (sh[src * 4 + 2] + sh[src * 4 + 3]);
+  }
+}
+
+// A bound below the actual vector count cannot happen (the step index bounds iter); if
+// it did, the solve is flagged and stopped rather than computed on part of the basis.
+__device__ __forceinline__ bool lz_over_bound(LzState* st, int nv, int nvb) {
+  if (nv <= nvb) return false;
+  if (threadIdx.x == 0) {
+    st->bad = 1;
+    lz_mark_stop(st);
+  }
+  return true;
+}
+
+// The subtraction and the second projection in one pass over the basis: w1 = w - V h1,
+// then part[blk][2i + {0,1}] = sum of conj(V_i) w1 and part[blk][2 nv] = sum of |w1|^2
+// over the chunk.  Each thread holds its element of every vector in registers between
+// the subtraction and the products, so the basis is read once for both.
 template <int NVB>
-__device__ __forceinline__ void lz_subdots_body(const LzInst& in, int nv, int blk, double* sh) {
-  const double* h1 = in.st->h1;
+__global__ void __launch_bounds__(256) lz_subdots_kernel(const LzInst* __restrict__ I, int nins) {
+  __shared__ double sh[4 * (2 * NVB + 1)];
+  const int q0 = lz_find<0>(I, nins, blockIdx.x);
+  const LzInst& in = I[q0];
+  LzState* st = in.st;
+  if (st->stop) return;
+  const int nv = st->iter + 1;
+  if (lz_over_bound(st, nv, NVB)) return;
+  const int blk = blockIdx.x - in.c0;
+  const double* h1 = st->h1;
   double2* w = reinterpret_cast<double2*>(in.w);
   const double2* V = reinterpret_cast<const double2*>(in.V);
   const int64_t ld = in.ld;
@@ -338,36 +373,7 @@ __device__ __forceinline__ void lz_subdots_body(const LzInst& in, int nv, int bl
       }
     acc[2 * NVB] += x.x * x.x + x.y * x.y;
   }
-  // block sums in a fixed order: wave shuffles, then the four wave partials
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int c = 0; c < 2 * NVB + 1; ++c) {
-    if (c < 2 * nv || c == 2 * NVB) {
-      const double t = wave_sum(acc[c]);
-      if (lane == 0) sh[c * 4 + wv] = t;
-    }
-  }
-  __syncthreads();
-  double* out = in.part + (int64_t)blk * (2 * nv + 1);
-  const int c = threadIdx.x;
-  if (c <= 2 * nv) {
-    const int src = c < 2 * nv ? c : 2 * NVB;
-    out[c] = (sh[src * 4] + sh[src * 4 + 1]) + (sh[src * 4 + 2] + sh[src * 4 + 3]);
-  }
-}
-
-__global__ void __launch_bounds__(256) lz_subdots_kernel(const LzInst* __restrict__ I, int nins) {
-  __shared__ double sh[4 * (2 * LZ_FUSE + 1)];
-  const int q0 = lz_find<0>(I, nins, blockIdx.x);
-  const LzInst& in = I[q0];
-  if (in.st->stop) return;
-  const int nv = in.st->iter + 1;
-  const int blk = blockIdx.x - in.c0;
-  if (nv <= 8) lz_subdots_body<8>(in, nv, blk, sh);
-  else if (nv <= 16) lz_subdots_body<16>(in, nv, blk, sh);
-  else if (nv <= 24) lz_subdots_body<24>(in, nv, blk, sh);
-  else if (nv <= LZ_FUSE) lz_subdots_body<LZ_FUSE>(in, nv, blk, sh);
-  // larger bases are launched on the unfused path (the host checks the capacity)
+  block_sums_n(acc, 2 * nv + 1, 2 * NVB, sh, in.part + (int64_t)blk * (2 * nv + 1));
 }
 
 // Scalar part of step j = st->iter of instance blockIdx.x: alpha_j, beta_j, |T|, stopping rule.
@@ -621,14 +627,19 @@ hipError_t lz_launch_start(const LzInst* I, const LzGrid& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t lz_launch_step_tail(const LzInst* I, const LzGrid& g, hipStream_t s) {
+hipError_t lz_launch_step_tail(const LzInst* I, const LzGrid& g, int32_t nv_bound, hipStream_t s) {
   const int maxc = 2 * g.max_iter + 1;
-  const dim3 gd((g.max_iter + LZ_G - 1) / LZ_G, g.ndots);
+  // nv <= max_iter at every step; without a bound from the caller (a step captured once
+  // for every replay) the capacity bounds it
+  const int b = (nv_bound > 0 && nv_bound < g.max_iter) ? nv_bound : g.max_iter;
+  const dim3 gd((b + LZ_G - 1) / LZ_G, g.nchunk);
   hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, I, g.nins);
   hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H1);
-  if (g.max_iter <= LZ_FUSE) {
-    // nv <= max_iter <= LZ_FUSE at every step: one pass for w1, h2 and |w1|^2
-    hipLaunchKernelGGL(lz_subdots_kernel, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+  if (b <= LZ_FUSE) {
+    // one pass for w1, h2 and |w1|^2
+    if (b <= 8) hipLaunchKernelGGL(lz_subdots_kernel<8>, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+    else if (b <= 16) hipLaunchKernelGGL(lz_subdots_kernel<16>, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+    else hipLaunchKernelGGL(lz_subdots_kernel<LZ_FUSE>, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
     hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H2N);
   } else {
     hipLaunchKernelGGL(lz_sub_kernel, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
