@@ -21,6 +21,14 @@ class LibraryError(RuntimeError):
 
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is missing: build it with `python paper_1512_03318_amd/build.py`")
+# One HIP runtime per process.  PyTorch ships its own copies of the HIP and HSA runtimes;
+# loaded before PyTorch, the library would bind the system copies and PyTorch would then
+# load a second pair beside them (two runtimes share neither device memory nor pinned
+# allocations).  Importing PyTorch first makes the library bind the copies it loaded.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 lib = C.CDLL(_LIB_PATH)
 
 

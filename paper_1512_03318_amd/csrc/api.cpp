@@ -235,11 +235,13 @@ static void build_heff_tables(dm_heff_plan& p) {
   auto build_s4 = [&](GemmStage& s4, bool bf3) {
     s4.flags = G_B_T | G_C_ROWMAP;
     s4.split = true;
-    if (bf3) {  // 128 x 32 tiles, K split over workgroups in runs of >= 6 chunks of 32
+    if (bf3) {  // 128 x 32 tiles, K split over workgroups in runs of >= 12 chunks of 32
+      // (at Ly=8, chi=3200 the GEMM takes about the same time for runs of 6 to 12 chunks,
+      // while fewer partial tiles halve the split reduction)
       s4.tile_m = 128;
       s4.tile_n = 32;
       s4.kc = 32;
-      s4.split_min = 6;
+      s4.split_min = 12;
     } else {    // 32 x 32 tiles shared by four waves, >= 4 chunks of 64 per split
       s4.deep = true;
       s4.tile_m = s4.tile_n = 32;

@@ -91,7 +91,9 @@ void set_shape(GemmStage& st, const Shape& sh) {
 std::vector<Shape> candidates(int prec, int32_t flags) {
   const bool long_k = flags == (G_B_T | G_C_ROWMAP);
   if (prec == DM_BF16X3) {
-    if (long_k) return {{128, 32, false, true, 32, 6}, {64, 32, false, true, 32, 6}, {64, 64, false, true, 32, 6}};
+    if (long_k)
+      return {{128, 32, false, true, 32, 12}, {128, 32, false, true, 32, 6}, {64, 32, false, true, 32, 6},
+              {64, 64, false, true, 32, 6}};
     return {{128, 64, false, false, 32, 4}, {64, 64, false, false, 32, 4}};
   }
   if (long_k) return {{32, 32, true, true, 64, 4}, {64, 64, false, false, 32, 4}};
