@@ -213,16 +213,20 @@ static void build_heff_tables(dm_heff_plan& p) {
   // Tasks are ordered by slab, so the tasks that re-read one slab run at about the same
   // time (workgroups are dispatched in list order) and find it in cache.
   {
-    std::vector<int> ord(mx.tasks.size());
-    for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return task_key[x] < task_key[y]; });
-    std::vector<MixTask> sorted;
-    sorted.reserve(ord.size());
-    for (int i : ord) sorted.push_back(mx.tasks[i]);
+    // stable counting sort by the dense slab index a' * |c| + c
+    const size_t nc = (size_t)c.size(), nt = mx.tasks.size();
+    std::vector<int32_t> start(a.size() * nc + 1, 0);
+    auto slab = [&](int64_t key) { return (size_t)(key >> 32) * nc + (size_t)(uint32_t)key; };
+    for (int64_t k : task_key) ++start[slab(k) + 1];
+    for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
+    std::vector<MixTask> sorted(nt);
+    std::vector<int64_t> key(nt);
+    for (size_t i = 0; i < nt; ++i) {
+      const int32_t d = start[slab(task_key[i])]++;
+      sorted[d] = mx.tasks[i];
+      key[d] = task_key[i];
+    }
     mx.tasks.swap(sorted);
-    std::vector<int64_t> key;
-    key.reserve(ord.size());
-    for (int i : ord) key.push_back(task_key[i]);
     task_key.swap(key);
   }
   // slab form with about 20 KB of LDS per workgroup (several workgroups per CU keep
@@ -676,6 +680,20 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
   std::vector<int64_t> t1off((size_t)c.size() * 2, -1);
   std::vector<int> t1roff((size_t)c.size() * 2 * dr, -1);
   ep.t1.flags = G_A_ROWMAP | G_B_T;
+  {
+    // row table size: every (c, s) with a b sector stacks the R rows of every (w', c')
+    size_t nrows = 0;
+    for (int ci = 0; ci < c.size(); ++ci)
+      for (int s = 0; s < 2; ++s) {
+        const int bi = b.find(qsub(c.q[ci], W.qs[s], ly));
+        if (bi < 0 || S.b[bi][s] != ci) continue;
+        for (int wp = 0; wp < dr; ++wp) {
+          const int cpi = c.find(qadd(c.q[ci], W.qr[wp], ly));
+          if (cpi >= 0) nrows += c.dim[cpi];
+        }
+      }
+    ep.t1.rows.reserve(nrows);
+  }
   for (int ci = 0; ci < c.size(); ++ci)
     for (int s = 0; s < 2; ++s) {
       const int bi = b.find(qsub(c.q[ci], W.qs[s], ly));

@@ -1,6 +1,8 @@
 // Host planner: bond / MPO validation and the canonical layouts.
 #include "plan.hpp"
 
+#include <climits>
+
 #include <algorithm>
 #include <unordered_map>
 #include <cmath>
@@ -199,6 +201,16 @@ void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_siz
     const bool arow = st.flags & G_A_ROWMAP, crow = st.flags & G_C_ROWMAP;
     if ((arow || crow) && (p.rowmap < 0 || p.rowmap + p.M > (int64_t)st.rows.size()))
       throw err(DM_ERR_LAYOUT, "bad row table");
+    // lowest and highest row offset of a row table: every row's range lies between the
+    // range of the lowest and that of the highest
+    int64_t rlo = 0, rhi = 0;
+    if (arow || crow) {
+      rlo = rhi = st.rows[p.rowmap];
+      for (int i = 1; i < p.M; ++i) {
+        rlo = std::min(rlo, st.rows[p.rowmap + i]);
+        rhi = std::max(rhi, st.rows[p.rowmap + i]);
+      }
+    }
     for (int q = 0; q < p.nseg; ++q) {
       const GemmSeg& g = st.segs[p.seg0 + q];
       if (g.k < 0) throw err(DM_ERR_LAYOUT, "negative K");
@@ -212,7 +224,7 @@ void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_siz
           if (m.ld < g.k) throw err(DM_ERR_LAYOUT, "mix ld");
         }
       } else if (arow) {
-        for (int i = 0; i < p.M; ++i) range_check(st.rows[p.rowmap + i] + g.a_off, st.rows[p.rowmap + i] + g.a_off + g.k - 1, a_size, "A");
+        range_check(rlo + g.a_off, rhi + g.a_off + g.k - 1, a_size, "A");
       } else if (st.flags & G_A_T) {
         range_check(g.a_off, g.a_off + (int64_t)(g.k - 1) * g.lda + p.M - 1, a_size, "A");
         if (g.lda < p.M) throw err(DM_ERR_LAYOUT, "lda");
@@ -229,7 +241,7 @@ void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_siz
       }
     }
     if (crow) {
-      for (int i = 0; i < p.M; ++i) range_check(st.rows[p.rowmap + i], st.rows[p.rowmap + i] + p.N - 1, c_size, "C");
+      range_check(rlo, rhi + p.N - 1, c_size, "C");
     } else {
       range_check(p.c_off, p.c_off + (int64_t)(p.M - 1) * p.ldc + p.N - 1, c_size, "C");
       if (p.ldc < p.N) throw err(DM_ERR_LAYOUT, "ldc");
@@ -247,30 +259,30 @@ void mix_to_slabs(MixStage& st, const std::vector<int64_t>& key, int eb, int lds
   if (key.size() != st.tasks.size()) throw err(DM_ERR_LAYOUT, "mixing slab keys");
   std::vector<int> ord(st.tasks.size());
   for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
-  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key[x] < key[y]; });
+  if (!std::is_sorted(key.begin(), key.end()))
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key[x] < key[y]; });
+  st.blks.reserve(st.srcs.size());
+  st.coefs.reserve(st.srcs.size());
+  st.stasks.reserve(st.tasks.size());
+  st.wgs.reserve(2 * st.tasks.size());
   for (size_t i = 0; i < ord.size();) {
     size_t j = i;
     while (j < ord.size() && key[ord[j]] == key[ord[i]]) ++j;
     const MixTask& t0 = st.tasks[ord[i]];
     const int rows = t0.rows, cols = t0.cols;
     const int32_t blk0 = (int32_t)st.blks.size(), task0 = (int32_t)st.stasks.size();
-    std::unordered_map<int64_t, int32_t> bix;  // source offset -> block index in the slab
     for (size_t q = i; q < j; ++q) {
       const MixTask& t = st.tasks[ord[q]];
       if (t.rows != rows || t.cols != cols) throw err(DM_ERR_LAYOUT, "mixing slab shapes differ");
       SlabTask out{t.dst, t.ld_dst, (int32_t)st.coefs.size(), t.nsrc, 0};
       for (int k = 0; k < t.nsrc; ++k) {
         const MixSrc& m = st.srcs[t.src0 + k];
-        auto it = bix.find(m.off);
-        int32_t b;
-        if (it == bix.end()) {
-          b = (int32_t)(st.blks.size() - blk0);
-          bix.emplace(m.off, b);
-          st.blks.push_back({m.off, m.ld, 0});
-        } else {
-          b = it->second;
-          if (st.blks[blk0 + b].ld != m.ld) throw err(DM_ERR_LAYOUT, "mixing slab ld differs");
-        }
+        // block index of this source in the slab (a slab has few blocks: linear search)
+        int32_t b = 0;
+        const int32_t nb = (int32_t)(st.blks.size() - blk0);
+        while (b < nb && st.blks[blk0 + b].off != m.off) ++b;
+        if (b == nb) st.blks.push_back({m.off, m.ld, 0});
+        else if (st.blks[blk0 + b].ld != m.ld) throw err(DM_ERR_LAYOUT, "mixing slab ld differs");
         st.coefs.push_back({b, 0, m.re, m.im});
       }
       st.stasks.push_back(out);
@@ -303,27 +315,41 @@ void validate(const MixStage& st, int64_t src_size, int64_t dst_size) {
       if (s.ld < t.cols) throw err(DM_ERR_LAYOUT, "mix src ld");
     }
   }
-  // slab form: every workgroup's chunk inside its blocks and tasks, coefficients in range
-  for (const SlabWG& g : st.wgs) {
-    if (g.blk0 < 0 || g.nblk < 0 || g.blk0 + g.nblk > (int64_t)st.blks.size() || g.task0 < 0 ||
-        g.ntask < 0 || g.task0 + g.ntask > (int64_t)st.stasks.size() || g.r0 < 0 || g.nr <= 0 ||
-        g.col0 < 0 || g.ncol <= 0)
-      throw err(DM_ERR_LAYOUT, "bad mixing slab");
-    if ((int64_t)g.nblk * g.nr * g.ncol * st.slab_eb > st.lds_bytes) throw err(DM_ERR_LAYOUT, "mixing slab LDS");
-    const int r1 = g.r0 + g.nr - 1, c1 = g.col0 + g.ncol - 1;
-    for (int b = 0; b < g.nblk; ++b) {
-      const SlabBlk& k = st.blks[g.blk0 + b];
-      if (k.ld <= c1) throw err(DM_ERR_LAYOUT, "mixing slab block ld");
-      range_check(k.off + (int64_t)g.r0 * k.ld + g.col0, k.off + (int64_t)r1 * k.ld + c1, src_size, "slab src");
+  // slab form: every workgroup's chunk inside its blocks and tasks, coefficients in range.
+  // The workgroups of one slab (consecutive, same blocks and tasks) are checked together:
+  // the blocks and tasks once, over the union of the workgroups' row and column ranges
+  // (an element range that holds the union's first and last elements holds every part).
+  for (size_t i = 0; i < st.wgs.size();) {
+    const SlabWG& g0 = st.wgs[i];
+    int rmin = INT32_MAX, rmax = -1, cmin = INT32_MAX, cmax = -1;
+    size_t j = i;
+    for (; j < st.wgs.size() && st.wgs[j].blk0 == g0.blk0 && st.wgs[j].nblk == g0.nblk &&
+           st.wgs[j].task0 == g0.task0 && st.wgs[j].ntask == g0.ntask; ++j) {
+      const SlabWG& g = st.wgs[j];
+      if (g.r0 < 0 || g.nr <= 0 || g.col0 < 0 || g.ncol <= 0) throw err(DM_ERR_LAYOUT, "bad mixing slab");
+      if ((int64_t)g.nblk * g.nr * g.ncol * st.slab_eb > st.lds_bytes) throw err(DM_ERR_LAYOUT, "mixing slab LDS");
+      rmin = std::min(rmin, g.r0);
+      rmax = std::max(rmax, g.r0 + g.nr - 1);
+      cmin = std::min(cmin, g.col0);
+      cmax = std::max(cmax, g.col0 + g.ncol - 1);
     }
-    for (int t = 0; t < g.ntask; ++t) {
-      const SlabTask& k = st.stasks[g.task0 + t];
-      if (k.ld_dst <= c1) throw err(DM_ERR_LAYOUT, "mixing slab task ld");
-      range_check(k.dst + (int64_t)g.r0 * k.ld_dst + g.col0, k.dst + (int64_t)r1 * k.ld_dst + c1, dst_size, "slab dst");
+    if (g0.blk0 < 0 || g0.nblk < 0 || g0.blk0 + g0.nblk > (int64_t)st.blks.size() || g0.task0 < 0 ||
+        g0.ntask < 0 || g0.task0 + g0.ntask > (int64_t)st.stasks.size())
+      throw err(DM_ERR_LAYOUT, "bad mixing slab");
+    for (int b = 0; b < g0.nblk; ++b) {
+      const SlabBlk& k = st.blks[g0.blk0 + b];
+      if (k.ld <= cmax) throw err(DM_ERR_LAYOUT, "mixing slab block ld");
+      range_check(k.off + (int64_t)rmin * k.ld + cmin, k.off + (int64_t)rmax * k.ld + cmax, src_size, "slab src");
+    }
+    for (int t = 0; t < g0.ntask; ++t) {
+      const SlabTask& k = st.stasks[g0.task0 + t];
+      if (k.ld_dst <= cmax) throw err(DM_ERR_LAYOUT, "mixing slab task ld");
+      range_check(k.dst + (int64_t)rmin * k.ld_dst + cmin, k.dst + (int64_t)rmax * k.ld_dst + cmax, dst_size, "slab dst");
       if (k.c0 < 0 || k.nc < 0 || k.c0 + k.nc > (int64_t)st.coefs.size()) throw err(DM_ERR_LAYOUT, "slab coefficients");
       for (int q = 0; q < k.nc; ++q)
-        if (st.coefs[k.c0 + q].blk < 0 || st.coefs[k.c0 + q].blk >= g.nblk) throw err(DM_ERR_LAYOUT, "slab block index");
+        if (st.coefs[k.c0 + q].blk < 0 || st.coefs[k.c0 + q].blk >= g0.nblk) throw err(DM_ERR_LAYOUT, "slab block index");
     }
+    i = j;
   }
 }
 

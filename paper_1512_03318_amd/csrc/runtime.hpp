@@ -49,16 +49,20 @@ void pinned_free_after(void* p, hipStream_t s);
 
 // All task tables of one or more stages in one device block, uploaded with one copy.
 struct TableUpload {
-  std::vector<char> host;
-  std::vector<std::pair<size_t, void**>> fix;  // offset -> device pointer to patch
+  struct Part {
+    const void* src;
+    size_t bytes, off;
+    void** dst;
+  };
+  std::vector<Part> parts;
+  size_t total = 0;
   template <typename T>
   void add(const std::vector<T>& v, T** dst) {
     *dst = nullptr;
     if (v.empty()) return;
-    const size_t off = (host.size() + 255) & ~size_t(255);
-    host.resize(off + v.size() * sizeof(T));
-    std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
-    fix.emplace_back(off, (void**)dst);
+    const size_t off = (total + 255) & ~size_t(255);
+    parts.push_back({v.data(), v.size() * sizeof(T), off, (void**)dst});
+    total = off + v.size() * sizeof(T);
   }
   void add(GemmStage& st) {
     add(st.segs, &st.d_segs);
@@ -76,20 +80,21 @@ struct TableUpload {
     add(st.stasks, &st.d_stasks);
     add(st.coefs, &st.d_coefs);
   }
-  // Stream-ordered upload into a pool block through pinned staging (released after the
-  // copy on s); returns the block (free it with dev_free / dev_free_after).
+  // Stream-ordered upload into a pool block: the host tables (which must stay unchanged
+  // until commit) are copied straight into pinned staging, released after the copy on s;
+  // returns the block (free it with dev_free / dev_free_after).
   void* commit(hipStream_t s) {
-    if (host.empty()) return nullptr;
-    char* h = (char*)pinned_alloc(host.size());
-    std::memcpy(h, host.data(), host.size());
-    char* d = (char*)dev_alloc(host.size());
-    const hipError_t e = hipMemcpyAsync(d, h, host.size(), hipMemcpyHostToDevice, s);
+    if (parts.empty()) return nullptr;
+    char* h = (char*)pinned_alloc(total);
+    for (const Part& p : parts) std::memcpy(h + p.off, p.src, p.bytes);
+    char* d = (char*)dev_alloc(total);
+    const hipError_t e = hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, s);
     pinned_free_after(h, s);
     if (e != hipSuccess) {
       dev_free_after(d, s);
       HIPCHK(e);
     }
-    for (auto& f : fix) *f.second = d + f.first;
+    for (const Part& p : parts) *p.dst = d + p.off;
     return d;
   }
 };
