@@ -170,10 +170,14 @@ def measured_traffic(workload, pname):
 
 def stage_rooflines(pk, plan, prec, pname, prof, nmv, workload):
     """Roofline of each matvec stage from its in-run device time (HIP events on the
-    launch stream, averaged over the timed matvecs) and its algorithmic work: block GEMMs
-    against the matrix-core peak of their arithmetic, the mixing against HBM bandwidth
-    with algorithmic bytes = read X once + write Z once.  The dominant (longest) stage is
-    the reported one; `traffic` = counted HBM bytes per launch (profiles/) or null."""
+    launch stream, averaged over the timed matvecs) and its algorithmic work.  A block
+    GEMM has two floors: its algorithmic flops at the matrix-core peak of its arithmetic
+    (BF16x3: the bf16 dense peak over the three bf16 products per real product) and its
+    algorithmic bytes at the HBM peak (each operand read once, the output written once:
+    L + theta -> X and Z + R -> theta', in the plan's storage precision); the higher floor
+    is the binding roof, reported as `bound`.  The mixing is HBM-bound (read X once,
+    write Z once).  The dominant (longest) stage is the reported one; `traffic` = counted
+    HBM bytes per launch (profiles/) or null."""
     eb = 16 if prec == pk.DM_FP64 else 8
     avg = [p / max(nmv, 1) for p in prof]
     gemm = {pk.DM_FP64: ("mrd::gemm_kernel<double, 0, false>", "mrd::gemm_kernel<double, 20, true>"),
@@ -182,22 +186,40 @@ def stage_rooflines(pk, plan, prec, pname, prof, nmv, workload):
                            "mrd::gemm_bf3_kernel<20, 128, 32, 4, 1, true>")}[prec]
     mixk = "mrd::mix_slab_kernel<double>" if prec == pk.DM_FP64 else "mrd::mix_slab_kernel<float>"
     traffic = measured_traffic(workload, pname)
-    peak = PEAK_TFLOPS[pname]
+    # matrix-core peak in algorithmic flops (BF16x3: three bf16 products per real product)
+    hw = 3 if prec == pk.DM_BF16X3 else 1
+    peak_alg = PEAK_TFLOPS[pname] / hw
+    sz = plan.sizes
+    gemm_bytes = [(sz["L"] + sz["theta"] + sz["X"]) * eb, None, (sz["Z"] + sz["R"] + sz["theta"]) * eb]
     stages = []
     for i, (kern, what) in enumerate([(gemm[0], "L.theta block GEMM"), (mixk, "MPO mixing"),
                                       (gemm[1], "(.).R block GEMM")]):
         t = avg[i] * 1e-3
         if i == 1:
-            nbytes = (plan.sizes["X"] + plan.sizes["Z"]) * eb
+            nbytes = (sz["X"] + sz["Z"]) * eb
             ach = nbytes / t / 1e9
             r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_GBS, "unit": "GB/s",
                  "frac": round(ach / HBM_GBS, 4), "algorithmic_bytes": nbytes}
         else:
-            ach = plan.flops[i] / t / 1e12
-            r = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                 "frac": round(ach / peak, 4), "algorithmic_flops": plan.flops[i]}
-            if prec == pk.DM_BF16X3:
-                r["hw_products_per_algorithmic"] = 3   # hi*hi + hi*lo + lo*hi per real product
+            flops, nbytes = plan.flops[i], gemm_bytes[i]
+            t_mfma, t_hbm = flops / (peak_alg * 1e12), nbytes / (HBM_GBS * 1e9)
+            floors = {"mfma_floor_us": round(1e6 * t_mfma, 2), "hbm_floor_us": round(1e6 * t_hbm, 2),
+                      "flop_per_byte": round(flops / nbytes, 1),
+                      "ridge_flop_per_byte": round(peak_alg * 1e12 / (HBM_GBS * 1e9), 1),
+                      "algorithmic_flops": flops, "algorithmic_bytes": nbytes}
+            if t_mfma >= t_hbm:
+                ach = flops / t / 1e12
+                r = {"bound": "mfma", "achieved": round(ach, 3), "peak": round(peak_alg, 1),
+                     "unit": "TFLOP/s", "frac": round(ach / peak_alg, 4)}
+            else:
+                ach = nbytes / t / 1e9
+                r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_GBS, 4)}
+            r.update(floors)
+            r["mfma_frac"] = round(flops / t / 1e12 / peak_alg, 4)
+            if hw > 1:
+                r["matrix_peak_note"] = (f"{PEAK_TFLOPS[pname]} TFLOP/s bf16 dense / {hw} bf16 products "
+                                         "per algorithmic real product")
         tr = traffic.get(kern)
         r.update({"kernel": f"{kern} ({what}, {pname})", "avg_launch_ms": round(avg[i], 4),
                   "traffic": (tr["read_bytes"] + tr["write_bytes"]) if tr else None})
