@@ -11,6 +11,9 @@ _LIB_PATH = os.path.join(_HERE, "libmrdmrg.so")
 
 DM_FP64, DM_FP32, DM_BF16X3 = 0, 1, 2
 LAYOUT_SITE, LAYOUT_THETA, LAYOUT_ENV_L, LAYOUT_ENV_R = 0, 1, 2, 3
+# error codes of include/mrdmrg.h
+DM_OK, DM_ERR_ARG, DM_ERR_CHARGE, DM_ERR_DIM, DM_ERR_LAYOUT = 0, -1, -2, -3, -4
+DM_ERR_DTYPE, DM_ERR_ALLOC, DM_ERR_HIP, DM_ERR_NONFINITE = -5, -6, -7, -8
 
 
 class LibraryError(RuntimeError):

@@ -24,6 +24,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(pk.lib, n), n
 
 
+def test_binding_error_codes_match_header():
+    hdr = open(os.path.join(ROOT, "include", "mrdmrg.h")).read()
+    codes = dict(re.findall(r"#define (DM_(?:OK|ERR_\w+)) \(?(-?\d+)\)?", hdr))
+    assert len(codes) == 9
+    for name, v in codes.items():
+        assert getattr(pk, name) == int(v), name
+
+
 def _bonds():
     wl = workloads.preset("ly4_chi64")
     return wl, pk.Bond(wl.bonds[wl.j]), pk.Bond(wl.bonds[wl.j + 2])

@@ -139,6 +139,18 @@ def right_isometry(rng, bl: dict, br: dict, qs, ly: int) -> dict:
     return out
 
 
+def random_site(rng, bl: dict, br: dict, qs, ly: int) -> dict:
+    """Site tensor M[a, s, b] with Gaussian blocks (not an isometry), blocks keyed
+    (qa, s, qb) for every charge-allowed q(a) + q(s) = q(b)."""
+    out = {}
+    for qb, mb in br.items():
+        for s in (0, 1):
+            qa = _sub(qb, qs[s], ly)
+            if qa in bl:
+                out[(qa, s, qb)] = _gauss(rng, (bl[qa], mb))
+    return out
+
+
 def random_theta(rng, ba: dict, bc: dict, qs1, qs2, ly: int) -> dict:
     """Two-site wavefunction theta[a, s1, s2, c], blocks keyed (qa, s1, s2, qc), unnormalised."""
     out = {}
