@@ -567,9 +567,14 @@ struct EnvPlan {
   double flops() const { return t1.flops + mix.flops + t3.flops; }
 };
 
+// Output tile of the T3 stage: its problems are one m_b' x m_b block each (a few tens
+// of rows and columns), which 32 x 32 BF16x3 tiles cover with little padding; the FP
+// kernels keep their 64 x 64 shape.
+int env_t3_tile(int prec) { return prec == DM_BF16X3 ? 32 : 64; }
+
 // L'[b', w', b] = sum conj(A[a', s', b']) L[a', w, a] W[w, s', s, w'] A[a, s, b]
 EnvPlan plan_left(int ly, const Bond& a, const Bond& b, const MpoSite& W, const EnvLLayout& L,
-                  const SiteLayout& S, const EnvLLayout& Lo) {
+                  const SiteLayout& S, const EnvLLayout& Lo, int t3_tile) {
   EnvPlan ep;
   const int dl = W.dl, dr = W.dr;
   std::vector<int64_t> t1off(a.size());
@@ -647,6 +652,7 @@ EnvPlan plan_left(int ly, const Bond& a, const Bond& b, const MpoSite& W, const 
     }
   // T3: L'_{w'}[b', b] = sum_{s'} conj(A_{a',s',b'})^T (m_b' x m_a') . T2 (m_a' x m_b)
   ep.t3.flags = G_A_T | G_A_CONJ;
+  ep.t3.tile_m = ep.t3.tile_n = t3_tile;
   for (int bi = 0; bi < b.size(); ++bi)
     for (int wp = 0; wp < dr; ++wp) {
       const int bpi = Lo.ap[bi * dr + wp];
@@ -673,7 +679,7 @@ EnvPlan plan_left(int ly, const Bond& a, const Bond& b, const MpoSite& W, const 
 
 // R'[b', w, b] = sum conj(B[b', s', c']) W[w, s', s, w'] R[c', w', c] B[b, s, c]
 EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const EnvRLayout& R,
-                   const SiteLayout& S, const EnvRLayout& Ro) {
+                   const SiteLayout& S, const EnvRLayout& Ro, int t3_tile) {
   EnvPlan ep;
   const int dl = W.dl, dr = W.dr;
   // T1 per (c, s): rows (w', c') with c' = c + q(w'); cols m_b, b = c - q(s)
@@ -783,6 +789,7 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
     }
   // T3: R'_w[b', b] = sum_{s'} conj(B_{b', s', c'}) (m_b' x m_c') . T2 (m_c' x m_b)
   ep.t3.flags = G_A_CONJ;
+  ep.t3.tile_m = ep.t3.tile_n = t3_tile;
   for (int w = 0; w < dl; ++w)
     for (int bi = 0; bi < b.size(); ++bi) {
       const int64_t base = t2off[(size_t)w * b.size() + bi];
@@ -865,7 +872,7 @@ extern "C" int env_update_left(int32_t ly, const dm_bond* a, const dm_bond* b,
     SiteLayout S = site_layout(ba, bb, W.qs, ly);
     if ((Li.P.total && !L) || (S.P.total && !A) || (Lo.P.total && !L_out))
       throw DmError{DM_ERR_ARG, "null tensor"};
-    EnvPlan ep = plan_left(ly, ba, bb, W, Li, S, Lo);
+    EnvPlan ep = plan_left(ly, ba, bb, W, Li, S, Lo, env_t3_tile(prec));
     validate(ep.t1, Li.P.total, S.P.total, ep.t1total);
     validate(ep.mix, ep.t1total, ep.t2total);
     validate(ep.t3, S.P.total, ep.t2total, Lo.P.total);
@@ -886,7 +893,7 @@ extern "C" int env_update_right(int32_t ly, const dm_bond* b, const dm_bond* c,
     SiteLayout S = site_layout(bb, bc, W.qs, ly);
     if ((Ri.P.total && !R) || (S.P.total && !B) || (Ro.P.total && !R_out))
       throw DmError{DM_ERR_ARG, "null tensor"};
-    EnvPlan ep = plan_right(ly, bb, bc, W, Ri, S, Ro);
+    EnvPlan ep = plan_right(ly, bb, bc, W, Ri, S, Ro, env_t3_tile(prec));
     validate(ep.t1, Ri.P.total, S.P.total, ep.t1total);
     validate(ep.mix, ep.t1total, ep.t2total);
     validate(ep.t3, S.P.total, ep.t2total, Ro.P.total);
@@ -904,11 +911,11 @@ extern "C" int dm_env_flops(int32_t left, int32_t ly, const dm_bond* x, const dm
     if (left) {
       EnvLLayout Li = envl_layout(bx, W.ql, ly), Lo = envl_layout(by, W.qr, ly);
       SiteLayout S = site_layout(bx, by, W.qs, ly);
-      *flops = plan_left(ly, bx, by, W, Li, S, Lo).flops();
+      *flops = plan_left(ly, bx, by, W, Li, S, Lo, 64).flops();
     } else {
       EnvRLayout Ri = envr_layout(by, W.qr, ly), Ro = envr_layout(bx, W.ql, ly);
       SiteLayout S = site_layout(bx, by, W.qs, ly);
-      *flops = plan_right(ly, bx, by, W, Ri, S, Ro).flops();
+      *flops = plan_right(ly, bx, by, W, Ri, S, Ro, 64).flops();
     }
   });
 }

@@ -284,8 +284,10 @@ hipError_t launch_gemm_bf16x3(const GemmStage& st, const float* A, const float* 
   MRD_BF3_CASE(0, 128, 64, 2, 2, false)
   MRD_BF3_CASE(0, 64, 64, 2, 2, false)
   MRD_BF3_CASE(G_A_T | G_A_CONJ, 64, 64, 2, 2, false)
+  MRD_BF3_CASE(G_A_T | G_A_CONJ, 32, 32, 2, 2, false)
   MRD_BF3_CASE(G_A_ROWMAP | G_B_T, 64, 64, 2, 2, false)
   MRD_BF3_CASE(G_A_CONJ, 64, 64, 2, 2, false)
+  MRD_BF3_CASE(G_A_CONJ, 32, 32, 2, 2, false)
   MRD_BF3_CASE(G_B_T | G_C_ROWMAP, 128, 32, 4, 1, true)
   // further shapes for the batched tile tuning
   MRD_BF3_CASE(G_B_T | G_C_ROWMAP, 64, 32, 4, 1, true)
