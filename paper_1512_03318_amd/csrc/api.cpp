@@ -571,6 +571,8 @@ struct EnvPlan {
 // of rows and columns), which 32 x 32 BF16x3 tiles cover with little padding; the FP
 // kernels keep their 64 x 64 shape.
 int env_t3_tile(int prec) { return prec == DM_BF16X3 ? 32 : 64; }
+// Column tile of the right update's T1 stage (N = m_b, a few tens): 32 for BF16x3.
+int env_t1r_tile_n(int prec) { return prec == DM_BF16X3 ? 32 : 64; }
 
 // L'[b', w', b] = sum conj(A[a', s', b']) L[a', w, a] W[w, s', s, w'] A[a, s, b]
 EnvPlan plan_left(int ly, const Bond& a, const Bond& b, const MpoSite& W, const EnvLLayout& L,
@@ -679,13 +681,14 @@ EnvPlan plan_left(int ly, const Bond& a, const Bond& b, const MpoSite& W, const 
 
 // R'[b', w, b] = sum conj(B[b', s', c']) W[w, s', s, w'] R[c', w', c] B[b, s, c]
 EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const EnvRLayout& R,
-                   const SiteLayout& S, const EnvRLayout& Ro, int t3_tile) {
+                   const SiteLayout& S, const EnvRLayout& Ro, int t3_tile, int t1_tile_n) {
   EnvPlan ep;
   const int dl = W.dl, dr = W.dr;
   // T1 per (c, s): rows (w', c') with c' = c + q(w'); cols m_b, b = c - q(s)
   std::vector<int64_t> t1off((size_t)c.size() * 2, -1);
   std::vector<int> t1roff((size_t)c.size() * 2 * dr, -1);
   ep.t1.flags = G_A_ROWMAP | G_B_T;
+  ep.t1.tile_n = t1_tile_n;
   {
     // row table size: every (c, s) with a b sector stacks the R rows of every (w', c')
     size_t nrows = 0;
@@ -893,7 +896,7 @@ extern "C" int env_update_right(int32_t ly, const dm_bond* b, const dm_bond* c,
     SiteLayout S = site_layout(bb, bc, W.qs, ly);
     if ((Ri.P.total && !R) || (S.P.total && !B) || (Ro.P.total && !R_out))
       throw DmError{DM_ERR_ARG, "null tensor"};
-    EnvPlan ep = plan_right(ly, bb, bc, W, Ri, S, Ro, env_t3_tile(prec));
+    EnvPlan ep = plan_right(ly, bb, bc, W, Ri, S, Ro, env_t3_tile(prec), env_t1r_tile_n(prec));
     validate(ep.t1, Ri.P.total, S.P.total, ep.t1total);
     validate(ep.mix, ep.t1total, ep.t2total);
     validate(ep.t3, S.P.total, ep.t2total, Ro.P.total);
@@ -915,7 +918,7 @@ extern "C" int dm_env_flops(int32_t left, int32_t ly, const dm_bond* x, const dm
     } else {
       EnvRLayout Ri = envr_layout(by, W.qr, ly), Ro = envr_layout(bx, W.ql, ly);
       SiteLayout S = site_layout(bx, by, W.qs, ly);
-      *flops = plan_right(ly, bx, by, W, Ri, S, Ro, 64).flops();
+      *flops = plan_right(ly, bx, by, W, Ri, S, Ro, 64, 64).flops();
     }
   });
 }

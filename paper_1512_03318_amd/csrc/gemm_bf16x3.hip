@@ -286,6 +286,7 @@ hipError_t launch_gemm_bf16x3(const GemmStage& st, const float* A, const float* 
   MRD_BF3_CASE(G_A_T | G_A_CONJ, 64, 64, 2, 2, false)
   MRD_BF3_CASE(G_A_T | G_A_CONJ, 32, 32, 2, 2, false)
   MRD_BF3_CASE(G_A_ROWMAP | G_B_T, 64, 64, 2, 2, false)
+  MRD_BF3_CASE(G_A_ROWMAP | G_B_T, 64, 32, 4, 1, false)
   MRD_BF3_CASE(G_A_CONJ, 64, 64, 2, 2, false)
   MRD_BF3_CASE(G_A_CONJ, 32, 32, 2, 2, false)
   MRD_BF3_CASE(G_B_T | G_C_ROWMAP, 128, 32, 4, 1, true)
