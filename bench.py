@@ -174,7 +174,7 @@ def stage_rooflines(pk, plan, prec, pname, prof, nmv, workload):
     GEMM has two floors: its algorithmic flops at the matrix-core peak of its arithmetic
     (BF16x3: the bf16 dense peak over the three bf16 products per real product) and its
     algorithmic bytes at the HBM peak (each operand read once, the output written once:
-    L + theta -> X and Z + R -> theta', in the plan's storage precision); the higher floor
+    L + theta -> X and Z + R -> theta', in the storage precision of each operand); the higher floor
     is the binding roof, reported as `bound`.  The mixing is HBM-bound (read X once,
     write Z once).  The dominant (longest) stage is the reported one; `traffic` = counted
     HBM bytes per launch (profiles/) or null."""
@@ -183,14 +183,17 @@ def stage_rooflines(pk, plan, prec, pname, prof, nmv, workload):
     gemm = {pk.DM_FP64: ("mrd::gemm_kernel<double, 0, false>", "mrd::gemm_kernel<double, 20, true>"),
             pk.DM_FP32: ("mrd::gemm_kernel<float, 0, false>", "mrd::gemm_kernel<float, 20, true>"),
             pk.DM_BF16X3: ("mrd::gemm_bf3_kernel<0, 128, 64, 2, 2, false>",
-                           "mrd::gemm_bf3_kernel<20, 128, 32, 4, 1, true>")}[prec]
+                           "mrd::gemm_bf3_kernel<148, 128, 32, 4, 1, true>")}[prec]
     mixk = "mrd::mix_slab_kernel<double>" if prec == pk.DM_FP64 else "mrd::mix_slab_kernel<float>"
     traffic = measured_traffic(workload, pname)
     # matrix-core peak in algorithmic flops (BF16x3: three bf16 products per real product)
     hw = 3 if prec == pk.DM_BF16X3 else 1
     peak_alg = PEAK_TFLOPS[pname] / hw
     sz = plan.sizes
-    gemm_bytes = [(sz["L"] + sz["theta"] + sz["X"]) * eb, None, (sz["Z"] + sz["R"] + sz["theta"]) * eb]
+    # BF16x3 (.).R writes theta' in FP64 itself (16 B per element)
+    eb_out = 16 if prec == pk.DM_BF16X3 else eb
+    gemm_bytes = [(sz["L"] + sz["theta"] + sz["X"]) * eb, None,
+                  (sz["Z"] + sz["R"]) * eb + sz["theta"] * eb_out]
     stages = []
     for i, (kern, what) in enumerate([(gemm[0], "L.theta block GEMM"), (mixk, "MPO mixing"),
                                       (gemm[1], "(.).R block GEMM")]):

@@ -237,7 +237,7 @@ static void build_heff_tables(dm_heff_plan& p) {
   //   theta'[(s12', a'), c'] = Z_{c'} (M x K) . Rpanel_{c'}^T (K x m_c'), K = R panel width,
   // rows scattered to the theta blocks through the row table.  K-split over workgroups.
   auto build_s4 = [&](GemmStage& s4, bool bf3) {
-    s4.flags = G_B_T | G_C_ROWMAP;
+    s4.flags = G_B_T | G_C_ROWMAP | (bf3 ? G_C_F64 : 0);  // BF16x3 writes theta' in FP64
     s4.split = true;
     if (bf3) {  // 128 x 32 tiles, K split over workgroups in runs of >= 12 chunks of 32
       // (at Ly=8, chi=3200 the GEMM takes about the same time for runs of 6 to 12 chunks,
@@ -407,16 +407,20 @@ void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStrea
     mark(4);
     return;
   }
+  // theta in: an FP32 copy; theta' out: BF16x3 stages write FP64 themselves (the FP32
+  // results widened as they are stored), FP32 stages through an FP32 copy
+  const bool direct = p->prec == DM_BF16X3;
   HIPCHK(launch_cast_d2f((const double*)theta, (float*)p->dTin, 2 * p->n(), s, skip));
+  float* tout = direct ? (float*)theta_out : (float*)p->dTout;
   mark(0);
   HIPCHK(gemm_lp(p->prec, p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, nullptr, s, skip));
   mark(1);
   HIPCHK(launch_mix<float>(p->mix, (const float*)p->dX, (float*)p->dZ, s, skip));
   mark(2);
-  HIPCHK(gemm_lp(p->prec, p->s4, (const float*)p->dZ, (const float*)p->dR, (float*)p->dTout,
+  HIPCHK(gemm_lp(p->prec, p->s4, (const float*)p->dZ, (const float*)p->dR, tout,
                  (float*)p->dSplit, s, skip, [&] { mark(3); }));
   mark(4);
-  HIPCHK(launch_cast_f2d((const float*)p->dTout, (double*)theta_out, 2 * p->n(), s, skip));
+  if (!direct) HIPCHK(launch_cast_f2d((const float*)p->dTout, (double*)theta_out, 2 * p->n(), s, skip));
 }
 
 extern "C" int dm_heff_profile(dm_heff_plan* p, int32_t enable) {

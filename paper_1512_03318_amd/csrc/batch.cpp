@@ -44,11 +44,14 @@ double tile_cost(const GemmStage& st, const GemmTile& t) {
 
 // Concatenates the problems of all plans (offsets rebased); tiles are built per bucket.
 GemmStage merge_problems(const std::vector<const GemmStage*>& in, const std::vector<Shift>& sh) {
+  // merged stages work on the batch's FP32 staging copies of theta (cast for all
+  // instances in one launch), so the FP64 output flag of the plans' own stages is dropped
+  constexpr int32_t f64 = G_C_F64;
   GemmStage m;
-  m.flags = in[0]->flags;
+  m.flags = in[0]->flags & ~f64;
   for (size_t i = 0; i < in.size(); ++i) {
     const GemmStage& st = *in[i];
-    if (st.flags != m.flags) throw DmError{DM_ERR_ARG, "batched plans have different stage kinds"};
+    if ((st.flags & ~f64) != m.flags) throw DmError{DM_ERR_ARG, "batched plans have different stage kinds"};
     if (st.flags & G_A_MIX) throw DmError{DM_ERR_ARG, "mixed operands cannot be batched"};
     const int32_t seg0 = (int32_t)m.segs.size();
     const int32_t row0 = (int32_t)m.rows.size();

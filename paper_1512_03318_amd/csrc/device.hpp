@@ -64,7 +64,8 @@ __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const GemmProb* 
       im += v.im;
     }
     const int64_t rb = (FLAGS & G_C_ROWMAP) ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
-    stc(C, rb + j, re, im);
+    if (FLAGS & G_C_F64) stc(reinterpret_cast<double*>(C), rb + j, (double)re, (double)im);
+    else stc(C, rb + j, re, im);
   }
 }
 

@@ -253,7 +253,11 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
 #pragma unroll
       for (int y = 0; y < YB; ++y) {
         const int j = j0 + wc + y * 16 + li;
-        if (j < P.N) stc(C, rbase + j, cre[x][y][r], cim[x][y][r]);
+        if (j >= P.N) continue;
+        if (FLAGS & G_C_F64)
+          stc(reinterpret_cast<double*>(C), rbase + j, (double)cre[x][y][r], (double)cim[x][y][r]);
+        else
+          stc(C, rbase + j, cre[x][y][r], cim[x][y][r]);
       }
     }
   }
@@ -290,6 +294,7 @@ hipError_t launch_gemm_bf16x3(const GemmStage& st, const float* A, const float* 
   MRD_BF3_CASE(G_A_CONJ, 64, 64, 2, 2, false)
   MRD_BF3_CASE(G_A_CONJ, 32, 32, 2, 2, false)
   MRD_BF3_CASE(G_B_T | G_C_ROWMAP, 128, 32, 4, 1, true)
+  MRD_BF3_CASE(G_B_T | G_C_ROWMAP | G_C_F64, 128, 32, 4, 1, true)
   // further shapes for the batched tile tuning
   MRD_BF3_CASE(G_B_T | G_C_ROWMAP, 64, 32, 4, 1, true)
   MRD_BF3_CASE(G_B_T | G_C_ROWMAP, 64, 64, 2, 2, true)

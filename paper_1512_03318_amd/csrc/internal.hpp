@@ -32,6 +32,7 @@ enum GemmFlags : int32_t {
   G_A_ROWMAP = 8,
   G_C_ROWMAP = 16,
   G_A_MIX = 32,
+  G_C_F64 = 128,  // BF16x3: C is complex128, the FP32 results widened as they are stored
 };
 
 struct GemmSeg {
