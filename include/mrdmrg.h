@@ -173,16 +173,18 @@ int dm_heff_profile(dm_heff_plan* p, int32_t enable);
 int dm_heff_profile_read(dm_heff_plan* p, double ms[4], int64_t* matvecs);
 
 /* theta_out = H_eff theta.  Both are device complex128 in the THETA layout of (a, c,
- * w1.qs, w2.qs); they must not overlap.  Asynchronous on `stream`. */
+ * w1.qs, w2.qs), 16-byte aligned (DM_ERR_ARG otherwise); they must not overlap.
+ * Asynchronous on `stream`. */
 int heff_apply(dm_heff_plan* p, const void* theta, void* theta_out, dm_stream stream);
 
 /* Lanczos ground state of H_eff (textbook Lanczos, classical Gram-Schmidt against all
  * previous vectors applied twice, FP64 on the device; lowest eigenpair of the
  * tridiagonal matrix by bisection and inverse iteration on the device).
- * theta_inout: start vector in (need not be normalised), normalised Ritz vector out.
- * Stops after max_iter (1..64) matvecs or when beta_j <= tol * |T|.  In DM_FP32 /
- * DM_BF16X3 the energy is the FP64 Rayleigh quotient <theta|H_eff|theta> of the Ritz
- * vector (one extra FP64 matvec); in DM_FP64 it is the Ritz value.  Synchronises. */
+ * theta_inout: start vector in (need not be normalised), normalised Ritz vector out;
+ * device complex128, 16-byte aligned (DM_ERR_ARG otherwise).  Stops after max_iter
+ * (1..64) matvecs or when beta_j <= tol * |T|.  In DM_FP32 / DM_BF16X3 the energy is the
+ * FP64 Rayleigh quotient <theta|H_eff|theta> of the Ritz vector (one extra FP64
+ * matvec); in DM_FP64 it is the Ritz value.  Synchronises. */
 int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double tol,
                    double* energy, int32_t* iters, dm_stream stream);
 
@@ -220,7 +222,8 @@ void dm_batch_destroy(dm_batch* b);
 /* The tile shape chosen per bucket, as text (empty before the first solve).  Writes at
  * most len bytes including the terminating zero; returns the full length. */
 int64_t dm_batch_info(const dm_batch* b, char* buf, int64_t len);
-/* thetas[i]: device start vector / Ritz vector of instance i.  energies, iters: host
+/* thetas[i]: device start vector / Ritz vector of instance i (16-byte aligned, as for
+ * lanczos_ground).  energies, iters: host
  * arrays of n.  Same algorithm and stopping rule as lanczos_ground per instance (the
  * tuned tile shapes may sum in another order: results agree to rounding).
  * done_us (may be NULL): host array of n, microseconds from launch until instance i

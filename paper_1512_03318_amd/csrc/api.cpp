@@ -450,6 +450,8 @@ extern "C" int heff_apply(dm_heff_plan* p, const void* theta, void* theta_out, d
   return guarded([&] {
     if (!p) throw DmError{DM_ERR_ARG, "null plan"};
     if (p->n() > 0 && (!theta || !theta_out)) throw DmError{DM_ERR_ARG, "null theta"};
+    if (misaligned(theta) || misaligned(theta_out))
+      throw DmError{DM_ERR_ARG, "theta buffers must be 16-byte aligned"};
     if (theta == theta_out && p->n() > 0) throw DmError{DM_ERR_ARG, "theta and theta_out overlap"};
     heff_run(p, theta, theta_out, (hipStream_t)stream, false);
     HIPCHK(hipEventRecord(p->done, (hipStream_t)stream));
@@ -510,6 +512,7 @@ extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_it
     const int64_t n = p->n();
     if (n == 0) throw DmError{DM_ERR_LAYOUT, "empty theta"};
     if (!theta_inout) throw DmError{DM_ERR_ARG, "null theta"};
+    if (misaligned(theta_inout)) throw DmError{DM_ERR_ARG, "theta must be 16-byte aligned"};
     ensure_lanczos(p, max_iter);
     hipStream_t s = (hipStream_t)stream;
     p->hInst->x = (double*)theta_inout;  // the previous solve synchronised: buffer is free

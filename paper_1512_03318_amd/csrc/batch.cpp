@@ -467,6 +467,7 @@ extern "C" int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t 
     const int n = (int)b->plans.size();
     for (int i = 0; i < n; ++i)
       if (!thetas[i]) throw DmError{DM_ERR_ARG, "null theta"};
+      else if (misaligned(thetas[i])) throw DmError{DM_ERR_ARG, "theta must be 16-byte aligned"};
     hipStream_t s = (hipStream_t)stream;
     for (dm_heff_plan* p : b->plans) ensure_lanczos(p, max_iter);
     if (!b->built) build_batch(*b, s);

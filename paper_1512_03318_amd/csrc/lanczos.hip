@@ -28,6 +28,17 @@
 
 namespace mrd {
 
+// Device pointers read from an instance table are generic to the compiler, which then
+// emits flat loads; those share the LDS counter, so every wait on them waits for all
+// loads in flight.  Typed as global memory they become global loads with per-load waits.
+#define LZ_GLOBAL __attribute__((address_space(1)))
+// complex FP64 element (re, im) as a native vector: 16-byte loads through global pointers
+typedef double lzc __attribute__((ext_vector_type(2)));
+template <class T>
+__device__ __forceinline__ LZ_GLOBAL T* glb(T* p) {
+  return (LZ_GLOBAL T*)p;
+}
+
 constexpr int LZ_EPT = 4;                 // elements per thread in streaming kernels
 constexpr int LZ_CHUNK = 256 * LZ_EPT;
 
@@ -67,9 +78,30 @@ __device__ __forceinline__ int lz_find(const LzInst* __restrict__ I, int nins, i
   return lo;
 }
 
+// One DPP row operation on a double (two 32-bit moves); lanes of rows outside ROWS
+// receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, returned in every lane.  Register
+// moves between lanes (DPP) instead of LDS permutes: pairs, quads, half rows (mirror),
+// rows of 16 (mirror), then row 0 into row 1 and row 2 into row 3 (broadcast of lane
+// 15 of each row), then rows 0-1 into rows 2-3 (broadcast of lane 31); lane 63 holds
+// the total.  Every lane of the wave must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_d<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_d<0x140, 0xf>(v);  // row_mirror
+  v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Block-sum of one value per thread; result valid in thread 0.  `sh` holds 4 doubles.
@@ -109,7 +141,7 @@ __global__ void __launch_bounds__(256) lz_norm_kernel(const LzInst* __restrict__
   const int q0 = lz_find<0>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
   const int blk = blockIdx.x - in.c0;
-  const double* x = in.x;
+  const auto x = glb(in.x);
   double s = 0;
 #pragma unroll
   for (int q = 0; q < LZ_EPT; ++q) {
@@ -117,7 +149,7 @@ __global__ void __launch_bounds__(256) lz_norm_kernel(const LzInst* __restrict__
     if (e < in.n) s += x[2 * e] * x[2 * e] + x[2 * e + 1] * x[2 * e + 1];
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) in.pnorm[blk] = s;
+  if (threadIdx.x == 0) glb(in.pnorm)[blk] = s;
 }
 
 enum LzReduce : int32_t {
@@ -151,7 +183,8 @@ __global__ void __launch_bounds__(256) lz_reduce_kernel(const LzInst* __restrict
   const int c = blockIdx.x;
   if (c >= ncomp) return;
   double s = 0;
-  for (int b = threadIdx.x; b < nblk; b += 256) s += src[(int64_t)b * ncomp + c];
+  const auto sp = glb(src);
+  for (int b = threadIdx.x; b < nblk; b += 256) s += sp[(int64_t)b * ncomp + c];
   sm[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -177,11 +210,10 @@ __global__ void lz_start_scale_kernel(const LzInst* __restrict__ I, int nins) {
   const double s = 1.0 / sqrt(nrm2);
   const int64_t e = (int64_t)(blockIdx.x - in.g0) * 256 + threadIdx.x;
   if (e >= in.n) return;
-  const double a = in.x[2 * e] * s, b = in.x[2 * e + 1] * s;
-  in.V[2 * e] = a;
-  in.V[2 * e + 1] = b;
-  in.vcur[2 * e] = a;
-  in.vcur[2 * e + 1] = b;
+  const lzc x = glb(reinterpret_cast<const lzc*>(in.x))[e];
+  const lzc v = lzc{x.x * s, x.y * s};
+  glb(reinterpret_cast<lzc*>(in.V))[e] = v;
+  glb(reinterpret_cast<lzc*>(in.vcur))[e] = v;
 }
 
 constexpr int LZ_G = 8;  // Krylov vectors per dot-product block
@@ -190,7 +222,7 @@ constexpr int LZ_G = 8;  // Krylov vectors per dot-product block
 // wave partials in a fixed order); out[c] for c < nval.
 template <int NVAL>
 __device__ __forceinline__ void block_sums(const double (&v)[NVAL], int nval, double* sh,
-                                           double* out) {
+                                           LZ_GLOBAL double* out) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int c = 0; c < NVAL; ++c) {
@@ -210,35 +242,56 @@ __device__ __forceinline__ void block_sums(const double (&v)[NVAL], int nval, do
 // groups read the same w elements (L2 hits).
 template <int NG>
 __device__ __forceinline__ void lz_dots_body(const LzInst& in, int i0, int nv, int blk, double* sh) {
-  const double2* xv = reinterpret_cast<const double2*>(in.w);
-  const double2* vv[NG];
+  const auto xv = glb(reinterpret_cast<const lzc*>(in.w));
+  const auto v0 = glb(reinterpret_cast<const lzc*>(in.V));
+  LZ_GLOBAL const lzc* vv[NG];
 #pragma unroll
-  for (int g = 0; g < NG; ++g) vv[g] = reinterpret_cast<const double2*>(in.V) + (int64_t)(i0 + g) * in.ld;
+  for (int g = 0; g < NG; ++g) vv[g] = v0 + (int64_t)(i0 + g) * in.ld;
   double acc[2 * NG];
 #pragma unroll
   for (int c = 0; c < 2 * NG; ++c) acc[c] = 0.0;
+  const int64_t e0 = (int64_t)blk * LZ_CHUNK + threadIdx.x;
+  if (e0 + (LZ_EPT - 1) * 256 < in.n) {
+    // every element of this thread in range: all loads are issued before the products
+    lzc xe[LZ_EPT], v[NG][LZ_EPT];
 #pragma unroll
-  for (int q = 0; q < LZ_EPT; ++q) {
-    const int64_t e = (int64_t)blk * LZ_CHUNK + q * 256 + threadIdx.x;
-    if (e < in.n) {
-      const double2 xe = xv[e];
+    for (int q = 0; q < LZ_EPT; ++q) xe[q] = xv[e0 + q * 256];
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int q = 0; q < LZ_EPT; ++q) v[g][q] = vv[g][e0 + q * 256];
+#pragma unroll
+    for (int q = 0; q < LZ_EPT; ++q)
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
-        const double2 v = vv[g][e];
-        acc[2 * g] += v.x * xe.x + v.y * xe.y;
-        acc[2 * g + 1] += v.x * xe.y - v.y * xe.x;
+        acc[2 * g] += v[g][q].x * xe[q].x + v[g][q].y * xe[q].y;
+        acc[2 * g + 1] += v[g][q].x * xe[q].y - v[g][q].y * xe[q].x;
+      }
+  } else {
+#pragma unroll
+    for (int q = 0; q < LZ_EPT; ++q) {
+      const int64_t e = e0 + q * 256;
+      if (e < in.n) {
+        const lzc xe = xv[e];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          const lzc v = vv[g][e];
+          acc[2 * g] += v.x * xe.x + v.y * xe.y;
+          acc[2 * g + 1] += v.x * xe.y - v.y * xe.x;
+        }
       }
     }
   }
-  block_sums(acc, 2 * NG, sh, in.part + (int64_t)blk * (2 * nv) + 2 * i0);
+  block_sums(acc, 2 * NG, sh, glb(in.part) + (int64_t)blk * (2 * nv) + 2 * i0);
 }
 
 __global__ void __launch_bounds__(256) lz_dots_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4 * 2 * LZ_G];
   const int q0 = lz_find<0>(I, nins, blockIdx.y);
   const LzInst& in = I[q0];
-  if (in.st->stop) return;
-  const int nv = in.st->iter + 1;
+  const auto sg = glb(in.st);
+  if (sg->stop) return;
+  const int nv = sg->iter + 1;
   const int i0 = blockIdx.x * LZ_G;
   if (i0 >= nv) return;
   const int blk = blockIdx.y - in.c0;
@@ -254,17 +307,43 @@ __global__ void __launch_bounds__(256) lz_dots_kernel(const LzInst* __restrict__
   }
 }
 
+constexpr int LZ_U = 4;  // basis vectors loaded together in the subtraction loops
+
+// x -= sum_{i < nv} h_i V_i[e] (h complex, interleaved), subtracted in index order;
+// the loads of LZ_U vectors are issued before their products.
+__device__ __forceinline__ void lz_sub_basis(lzc& x, LZ_GLOBAL const lzc* V, int64_t ld,
+                                             int64_t e, const LZ_GLOBAL double* h, int nv) {
+  int i = 0;
+  for (; i + LZ_U <= nv; i += LZ_U) {
+    lzc v[LZ_U];
+#pragma unroll
+    for (int u = 0; u < LZ_U; ++u) v[u] = V[(int64_t)(i + u) * ld + e];
+#pragma unroll
+    for (int u = 0; u < LZ_U; ++u) {
+      const double hr = h[2 * (i + u)], hi = h[2 * (i + u) + 1];
+      x.x -= hr * v[u].x - hi * v[u].y;
+      x.y -= hr * v[u].y + hi * v[u].x;
+    }
+  }
+  for (; i < nv; ++i) {
+    const double hr = h[2 * i], hi = h[2 * i + 1];
+    const lzc v = V[(int64_t)i * ld + e];
+    x.x -= hr * v.x - hi * v.y;
+    x.y -= hr * v.y + hi * v.x;
+  }
+}
+
 // w -= V h1 over the nv = iter + 1 Krylov vectors; pnorm[chunk] = |w_new|^2 over the chunk.
 __global__ void __launch_bounds__(256) lz_sub_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4];
   const int q0 = lz_find<0>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
-  const LzState* st = in.st;
+  const LZ_GLOBAL LzState* st = glb(in.st);
   if (st->stop) return;
   const int nv = st->iter + 1;
-  const double* h1 = st->h1;
-  const double* V = in.V;
-  double* w = in.w;
+  const LZ_GLOBAL double* h1 = st->h1;
+  const auto V = glb(reinterpret_cast<const lzc*>(in.V));
+  const auto w = glb(reinterpret_cast<lzc*>(in.w));
   const int64_t ld = in.ld;
   const int blk = blockIdx.x - in.c0;
   double nn = 0;
@@ -272,19 +351,13 @@ __global__ void __launch_bounds__(256) lz_sub_kernel(const LzInst* __restrict__ 
   for (int q = 0; q < LZ_EPT; ++q) {
     const int64_t e = (int64_t)blk * LZ_CHUNK + q * 256 + threadIdx.x;
     if (e >= in.n) continue;
-    double wr = w[2 * e], wi = w[2 * e + 1];
-    for (int i = 0; i < nv; ++i) {
-      const double hr = h1[2 * i], hi = h1[2 * i + 1];
-      const double vr = V[2 * ((int64_t)i * ld + e)], vi = V[2 * ((int64_t)i * ld + e) + 1];
-      wr -= hr * vr - hi * vi;
-      wi -= hr * vi + hi * vr;
-    }
-    w[2 * e] = wr;
-    w[2 * e + 1] = wi;
-    nn += wr * wr + wi * wi;
+    lzc x = w[e];
+    lz_sub_basis(x, V, ld, e, h1, nv);
+    w[e] = x;
+    nn += x.x * x.x + x.y * x.y;
   }
   nn = block_sum(nn, sh);
-  if (threadIdx.x == 0) in.pnorm[blk] = nn;
+  if (threadIdx.x == 0) glb(in.pnorm)[blk] = nn;
 }
 
 // Fused pass for bases of at most LZ_FUSE vectors, specialised on a bound NVB >= nv of
@@ -299,7 +372,7 @@ constexpr int LZ_FUSE = 24;
 // the four wave partials) into out[c]; value `last` goes to out[ncomp - 1] when given.
 template <int NV>
 __device__ __forceinline__ void block_sums_n(const double (&acc)[NV], int ncomp, int last,
-                                            double* sh, double* out) {
+                                            double* sh, LZ_GLOBAL double* out) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
@@ -337,13 +410,13 @@ __global__ void __launch_bounds__(256) lz_subdots_kernel(const LzInst* __restric
   const int q0 = lz_find<0>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
   LzState* st = in.st;
-  if (st->stop) return;
-  const int nv = st->iter + 1;
+  if (glb(st)->stop) return;
+  const int nv = glb(st)->iter + 1;
   if (lz_over_bound(st, nv, NVB)) return;
   const int blk = blockIdx.x - in.c0;
-  const double* h1 = st->h1;
-  double2* w = reinterpret_cast<double2*>(in.w);
-  const double2* V = reinterpret_cast<const double2*>(in.V);
+  const auto h1 = glb(st->h1);
+  const auto w = glb(reinterpret_cast<lzc*>(in.w));
+  const auto V = glb(reinterpret_cast<const lzc*>(in.V));
   const int64_t ld = in.ld;
   double acc[2 * NVB + 1];
 #pragma unroll
@@ -352,11 +425,11 @@ __global__ void __launch_bounds__(256) lz_subdots_kernel(const LzInst* __restric
   for (int q = 0; q < LZ_EPT; ++q) {
     const int64_t e = (int64_t)blk * LZ_CHUNK + q * 256 + threadIdx.x;
     if (e >= in.n) break;
-    double2 v[NVB];
+    lzc v[NVB];
 #pragma unroll
     for (int i = 0; i < NVB; ++i)
       if (i < nv) v[i] = V[i * ld + e];
-    double2 x = w[e];
+    lzc x = w[e];
 #pragma unroll
     for (int i = 0; i < NVB; ++i)
       if (i < nv) {
@@ -373,7 +446,7 @@ __global__ void __launch_bounds__(256) lz_subdots_kernel(const LzInst* __restric
       }
     acc[2 * NVB] += x.x * x.x + x.y * x.y;
   }
-  block_sums_n(acc, 2 * nv + 1, 2 * NVB, sh, in.part + (int64_t)blk * (2 * nv + 1));
+  block_sums_n(acc, 2 * nv + 1, 2 * NVB, sh, glb(in.part) + (int64_t)blk * (2 * nv + 1));
 }
 
 // Scalar part of step j = st->iter of instance blockIdx.x: alpha_j, beta_j, |T|, stopping rule.
@@ -408,29 +481,20 @@ __global__ void lz_scalar_kernel(const LzInst* __restrict__ I) {
 __global__ void __launch_bounds__(256) lz_next_kernel(const LzInst* __restrict__ I, int nins) {
   const int q0 = lz_find<1>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
-  const LzState* st = in.st;
+  const LZ_GLOBAL LzState* st = glb(in.st);
   if (st->stop) return;
   const int nv = st->iter;  // already advanced: vectors 0 .. j
   const int64_t e = (int64_t)(blockIdx.x - in.g0) * 256 + threadIdx.x;
   if (e >= in.n) return;
-  const double* V = in.V;
+  const auto V = glb(reinterpret_cast<lzc*>(in.V));
   const int64_t ld = in.ld;
-  double wr = in.w[2 * e], wi = in.w[2 * e + 1];
-  const double* h2 = st->h2;
-  for (int i = 0; i < nv; ++i) {
-    const double hr = h2[2 * i], hi = h2[2 * i + 1];
-    const double vr = V[2 * ((int64_t)i * ld + e)], vi = V[2 * ((int64_t)i * ld + e) + 1];
-    wr -= hr * vr - hi * vi;
-    wi -= hr * vi + hi * vr;
-  }
+  lzc x = glb(reinterpret_cast<const lzc*>(in.w))[e];
+  lz_sub_basis(x, V, ld, e, st->h2, nv);
   const double s = st->inv_beta;
-  wr *= s;
-  wi *= s;
-  double* out = in.V + 2 * (int64_t)nv * ld;
-  out[2 * e] = wr;
-  out[2 * e + 1] = wi;
-  in.vcur[2 * e] = wr;
-  in.vcur[2 * e + 1] = wi;
+  x.x *= s;
+  x.y *= s;
+  V[(int64_t)nv * ld + e] = x;
+  glb(reinterpret_cast<lzc*>(in.vcur))[e] = x;
 }
 
 // Sturm count: number of eigenvalues of T_k below x.
@@ -554,18 +618,29 @@ __global__ void lz_combine_kernel(const LzInst* __restrict__ I, int nins) {
   const LzInst& in = I[q0];
   const int64_t e = (int64_t)(blockIdx.x - in.g0) * 256 + threadIdx.x;
   if (e >= in.n) return;
-  const LzState* st = in.st;
+  const LZ_GLOBAL LzState* st = glb(in.st);
   const int k = st->k;
+  const auto V = glb(reinterpret_cast<const lzc*>(in.V));
+  const LZ_GLOBAL double* y = st->y;
   double r = 0, im = 0;
-  for (int i = 0; i < k; ++i) {
-    const double yi = st->y[i];
-    r += yi * in.V[2 * ((int64_t)i * in.ld + e)];
-    im += yi * in.V[2 * ((int64_t)i * in.ld + e) + 1];
+  int i = 0;
+  for (; i + LZ_U <= k; i += LZ_U) {  // loads first, then the sums in index order
+    lzc v[LZ_U];
+#pragma unroll
+    for (int u = 0; u < LZ_U; ++u) v[u] = V[(int64_t)(i + u) * in.ld + e];
+#pragma unroll
+    for (int u = 0; u < LZ_U; ++u) {
+      r += y[i + u] * v[u].x;
+      im += y[i + u] * v[u].y;
+    }
   }
-  in.x[2 * e] = r;
-  in.x[2 * e + 1] = im;
-  in.vcur[2 * e] = r;
-  in.vcur[2 * e + 1] = im;
+  for (; i < k; ++i) {
+    const lzc v = V[(int64_t)i * in.ld + e];
+    r += y[i] * v.x;
+    im += y[i] * v.y;
+  }
+  glb(reinterpret_cast<lzc*>(in.x))[e] = lzc{r, im};
+  glb(reinterpret_cast<lzc*>(in.vcur))[e] = lzc{r, im};
 }
 
 // pnorm[2 chunk + {0,1}] = (Re <vcur, w>, |vcur|^2) over the chunk (Rayleigh quotient).
@@ -574,21 +649,23 @@ __global__ void __launch_bounds__(256) lz_rq_kernel(const LzInst* __restrict__ I
   const int q0 = lz_find<0>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
   const int blk = blockIdx.x - in.c0;
-  const double *x = in.vcur, *w = in.w;
+  const auto x = glb(reinterpret_cast<const lzc*>(in.vcur));
+  const auto w = glb(reinterpret_cast<const lzc*>(in.w));
   double s = 0, q2 = 0;
 #pragma unroll
   for (int q = 0; q < LZ_EPT; ++q) {
     const int64_t e = (int64_t)blk * LZ_CHUNK + q * 256 + threadIdx.x;
     if (e < in.n) {
-      s += x[2 * e] * w[2 * e] + x[2 * e + 1] * w[2 * e + 1];
-      q2 += x[2 * e] * x[2 * e] + x[2 * e + 1] * x[2 * e + 1];
+      const lzc xe = x[e], we = w[e];
+      s += xe.x * we.x + xe.y * we.y;
+      q2 += xe.x * xe.x + xe.y * xe.y;
     }
   }
   s = block_sum(s, sh);
   q2 = block_sum(q2, sh);
   if (threadIdx.x == 0) {
-    in.pnorm[2 * blk] = s;
-    in.pnorm[2 * blk + 1] = q2;
+    glb(in.pnorm)[2 * blk] = s;
+    glb(in.pnorm)[2 * blk + 1] = q2;
   }
 }
 

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <array>
+#include <cstdint>
 #include <cstring>
 #include <functional>
 #include <string>
@@ -37,6 +38,9 @@ int guarded(F&& f) {
     return fail(DM_ERR_ARG, e.what());
   }
 }
+
+// Complex FP64 vectors are read and written as 16-byte elements.
+inline bool misaligned(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 != 0; }
 
 // Caching allocators (runtime.cpp): blocks are reused across plans.  dev_free: no
 // kernel uses the block any more; dev_free_after: reusable once stream s has passed

@@ -147,6 +147,29 @@ def test_ragged_lanczos_fp64():
     assert 1 - abs(np.vdot(vo, v)) < 1e-8
 
 
+def test_misaligned_theta_is_refused():
+    """Complex FP64 vectors are moved as 16-byte elements: a theta 8 bytes off is refused
+    before any work is queued, and the aligned call still works afterwards."""
+    c = ragged()
+    say("misaligned theta")
+    pack, _ = _theta_io(c)
+    plan = _plan(c, pk.DM_FP64)
+    x = to_dev(pack(c["th"]))
+    n = x.numel()
+    raw = torch.zeros(2 * n + 2, dtype=torch.float64, device="cuda")
+    off = raw[1:1 + 2 * n]  # starts 8 bytes into the allocation
+    assert off.data_ptr() % 16 == 8
+    off.copy_(torch.view_as_real(x).reshape(-1))
+    y = torch.empty_like(x)
+    for call in (lambda: pk.heff_apply(plan, off, y), lambda: pk.heff_apply(plan, x, off),
+                 lambda: pk.lanczos_ground(plan, off, 30, 1e-14)):
+        with pytest.raises(pk.LibraryError) as ei:
+            call()
+        assert ei.value.code == pk.DM_ERR_ARG
+    e, k = pk.lanczos_ground(plan, x, 30, 1e-14)
+    assert np.isfinite(e) and k > 0
+
+
 def test_window_without_theta_blocks():
     """Bond charges two particles apart cannot be joined by two sites: the theta layout,
     the matvec tables and the middle-bond environments are empty."""
