@@ -1,9 +1,19 @@
-// Device helpers shared by the GEMM kernels of every precision.
+// Device helpers shared by the kernels (GEMMs of every precision, casts, Lanczos).
 #pragma once
 
 #include "internal.hpp"
 
 namespace mrd {
+
+// Device pointers read from a table in device memory are generic to the compiler, which
+// then emits flat loads; those also count on the LDS counter, so every wait on them
+// waits for all loads in flight.  Typed as global memory they become global loads with
+// per-load waits.
+#define MRD_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ MRD_GLOBAL T* glb(T* p) {
+  return (MRD_GLOBAL T*)p;
+}
 
 template <typename T>
 struct Cplx {

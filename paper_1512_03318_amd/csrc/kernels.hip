@@ -382,6 +382,46 @@ __global__ void __launch_bounds__(256) mix_kernel(const MixTask* __restrict__ ta
   }
 }
 
+// The workgroup's part of a slab: per = rows x ncol elements, thread t starting at
+// (r0, c0) and advancing by (step_r, step_c) per 256 elements.
+struct MixPart {
+  int per, ncol, r0, c0, step_r, step_c;
+};
+
+// One output task of a slab with NC coefficients, all read once before the element
+// loop (the generic loop reads the coefficient of every term of every element and waits
+// for it); the terms are summed in the same order.
+template <typename T, int NC>
+__device__ __forceinline__ void mix_slab_task(const SlabTask& k, const SlabCoef* __restrict__ coefs,
+                                              const T* lds, T* obase, const MixPart& p) {
+  T cr[NC], ci[NC];
+  int bo[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const SlabCoef w = coefs[k.c0 + q];
+    cr[q] = (T)w.re;
+    ci[q] = (T)w.im;
+    bo[q] = w.blk * p.per;
+  }
+  int r = p.r0, c = p.c0;
+  for (int e = threadIdx.x; e < p.per; e += 256) {
+    T re = 0, im = 0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const T* x = lds + 2 * ((int64_t)bo[q] + e);
+      re += cr[q] * x[0] - ci[q] * x[1];
+      im += cr[q] * x[1] + ci[q] * x[0];
+    }
+    stc(obase, (int64_t)r * k.ld_dst + c, re, im);
+    r += p.step_r;
+    c += p.step_c;
+    if (c >= p.ncol) {
+      c -= p.ncol;
+      ++r;
+    }
+  }
+}
+
 // Slab form: stage the workgroup's part (rows r0.., columns col0..) of every source block
 // of its slab in LDS (planes [block][row][col], interleaved complex), then produce that
 // part of each task of the slab from LDS.  Elements e of the part map to (row, col) with
@@ -401,15 +441,33 @@ __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict_
   const int per = g.nr * g.ncol;
   const int step_r = 256 / g.ncol, step_c = 256 - step_r * g.ncol;
   const int r_init = threadIdx.x / g.ncol, c_init = threadIdx.x - r_init * g.ncol;
-  for (int b = 0; b < g.nblk; ++b) {
-    const SlabBlk k = blks[g.blk0 + b];
-    const T* base = src + 2 * (k.off + (int64_t)g.r0 * k.ld + g.col0);
-    T* out = lds + 2 * (int64_t)b * per;
+  // The blocks of a slab share the part's (row, col) walk: the same element of MIX_G
+  // blocks is loaded at once (a group's missing blocks re-read its last one, in range of
+  // the slab's block table, and are not stored), so every thread has MIX_G loads in
+  // flight instead of one.
+  constexpr int MIX_G = 8;
+  for (int b0 = 0; b0 < g.nblk; b0 += MIX_G) {
+    const int nb = min(MIX_G, g.nblk - b0);
+    const T* base[MIX_G];
+    int64_t ld[MIX_G];
+#pragma unroll
+    for (int u = 0; u < MIX_G; ++u) {
+      const SlabBlk k = blks[g.blk0 + b0 + min(u, nb - 1)];
+      base[u] = src + 2 * (k.off + (int64_t)g.r0 * k.ld + g.col0);
+      ld[u] = k.ld;
+    }
     int r = r_init, c = c_init;
     for (int e = threadIdx.x; e < per; e += 256) {
-      const Cplx<T> v = ldc(base, (int64_t)r * k.ld + c);
-      out[2 * e] = v.re;
-      out[2 * e + 1] = v.im;
+      Cplx<T> v[MIX_G];
+#pragma unroll
+      for (int u = 0; u < MIX_G; ++u) v[u] = ldc(base[u], (int64_t)r * ld[u] + c);
+#pragma unroll
+      for (int u = 0; u < MIX_G; ++u)
+        if (u < nb) {
+          T* out = lds + 2 * ((int64_t)(b0 + u) * per + e);
+          out[0] = v[u].re;
+          out[1] = v[u].im;
+        }
       r += step_r;
       c += step_c;
       if (c >= g.ncol) {
@@ -422,6 +480,18 @@ __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict_
   for (int t = 0; t < g.ntask; ++t) {
     const SlabTask k = tasks[g.task0 + t];
     T* obase = dst + 2 * (k.dst + (int64_t)g.r0 * k.ld_dst + g.col0);
+    const MixPart part{per, g.ncol, r_init, c_init, step_r, step_c};
+    switch (k.nc) {  // uniform over the workgroup
+      case 1: mix_slab_task<T, 1>(k, coefs, lds, obase, part); continue;
+      case 2: mix_slab_task<T, 2>(k, coefs, lds, obase, part); continue;
+      case 3: mix_slab_task<T, 3>(k, coefs, lds, obase, part); continue;
+      case 4: mix_slab_task<T, 4>(k, coefs, lds, obase, part); continue;
+      case 5: mix_slab_task<T, 5>(k, coefs, lds, obase, part); continue;
+      case 6: mix_slab_task<T, 6>(k, coefs, lds, obase, part); continue;
+      case 7: mix_slab_task<T, 7>(k, coefs, lds, obase, part); continue;
+      case 8: mix_slab_task<T, 8>(k, coefs, lds, obase, part); continue;
+      default: break;
+    }
     int r = r_init, c = c_init;
     for (int e = threadIdx.x; e < per; e += 256) {
       T re = 0, im = 0;
@@ -513,8 +583,8 @@ __global__ void __launch_bounds__(256) cast_batch_kernel(const CastJob* __restri
   for (int q = 0; q < 4; ++q) {
     const int64_t i = base + 256 * q;
     if (i >= j.n) break;
-    if (D2F) static_cast<float*>(j.dst)[i] = (float)static_cast<const double*>(j.src)[i];
-    else static_cast<double*>(j.dst)[i] = (double)static_cast<const float*>(j.src)[i];
+    if (D2F) glb(static_cast<float*>(j.dst))[i] = (float)glb(static_cast<const double*>(j.src))[i];
+    else glb(static_cast<double*>(j.dst))[i] = (double)glb(static_cast<const float*>(j.src))[i];
   }
 }
 

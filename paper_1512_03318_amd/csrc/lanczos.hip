@@ -24,20 +24,12 @@
 // phase serves a single plan or a whole batch of them.
 #include <algorithm>
 
-#include "internal.hpp"
+#include "device.hpp"
 
 namespace mrd {
 
-// Device pointers read from an instance table are generic to the compiler, which then
-// emits flat loads; those share the LDS counter, so every wait on them waits for all
-// loads in flight.  Typed as global memory they become global loads with per-load waits.
-#define LZ_GLOBAL __attribute__((address_space(1)))
 // complex FP64 element (re, im) as a native vector: 16-byte loads through global pointers
 typedef double lzc __attribute__((ext_vector_type(2)));
-template <class T>
-__device__ __forceinline__ LZ_GLOBAL T* glb(T* p) {
-  return (LZ_GLOBAL T*)p;
-}
 
 constexpr int LZ_EPT = 4;                 // elements per thread in streaming kernels
 constexpr int LZ_CHUNK = 256 * LZ_EPT;
@@ -222,7 +214,7 @@ constexpr int LZ_G = 8;  // Krylov vectors per dot-product block
 // wave partials in a fixed order); out[c] for c < nval.
 template <int NVAL>
 __device__ __forceinline__ void block_sums(const double (&v)[NVAL], int nval, double* sh,
-                                           LZ_GLOBAL double* out) {
+                                           MRD_GLOBAL double* out) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int c = 0; c < NVAL; ++c) {
@@ -244,7 +236,7 @@ template <int NG>
 __device__ __forceinline__ void lz_dots_body(const LzInst& in, int i0, int nv, int blk, double* sh) {
   const auto xv = glb(reinterpret_cast<const lzc*>(in.w));
   const auto v0 = glb(reinterpret_cast<const lzc*>(in.V));
-  LZ_GLOBAL const lzc* vv[NG];
+  MRD_GLOBAL const lzc* vv[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) vv[g] = v0 + (int64_t)(i0 + g) * in.ld;
   double acc[2 * NG];
@@ -311,8 +303,8 @@ constexpr int LZ_U = 4;  // basis vectors loaded together in the subtraction loo
 
 // x -= sum_{i < nv} h_i V_i[e] (h complex, interleaved), subtracted in index order;
 // the loads of LZ_U vectors are issued before their products.
-__device__ __forceinline__ void lz_sub_basis(lzc& x, LZ_GLOBAL const lzc* V, int64_t ld,
-                                             int64_t e, const LZ_GLOBAL double* h, int nv) {
+__device__ __forceinline__ void lz_sub_basis(lzc& x, MRD_GLOBAL const lzc* V, int64_t ld,
+                                             int64_t e, const MRD_GLOBAL double* h, int nv) {
   int i = 0;
   for (; i + LZ_U <= nv; i += LZ_U) {
     lzc v[LZ_U];
@@ -338,10 +330,10 @@ __global__ void __launch_bounds__(256) lz_sub_kernel(const LzInst* __restrict__ 
   __shared__ double sh[4];
   const int q0 = lz_find<0>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
-  const LZ_GLOBAL LzState* st = glb(in.st);
+  const MRD_GLOBAL LzState* st = glb(in.st);
   if (st->stop) return;
   const int nv = st->iter + 1;
-  const LZ_GLOBAL double* h1 = st->h1;
+  const MRD_GLOBAL double* h1 = st->h1;
   const auto V = glb(reinterpret_cast<const lzc*>(in.V));
   const auto w = glb(reinterpret_cast<lzc*>(in.w));
   const int64_t ld = in.ld;
@@ -372,7 +364,7 @@ constexpr int LZ_FUSE = 24;
 // the four wave partials) into out[c]; value `last` goes to out[ncomp - 1] when given.
 template <int NV>
 __device__ __forceinline__ void block_sums_n(const double (&acc)[NV], int ncomp, int last,
-                                            double* sh, LZ_GLOBAL double* out) {
+                                            double* sh, MRD_GLOBAL double* out) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
@@ -481,7 +473,7 @@ __global__ void lz_scalar_kernel(const LzInst* __restrict__ I) {
 __global__ void __launch_bounds__(256) lz_next_kernel(const LzInst* __restrict__ I, int nins) {
   const int q0 = lz_find<1>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
-  const LZ_GLOBAL LzState* st = glb(in.st);
+  const MRD_GLOBAL LzState* st = glb(in.st);
   if (st->stop) return;
   const int nv = st->iter;  // already advanced: vectors 0 .. j
   const int64_t e = (int64_t)(blockIdx.x - in.g0) * 256 + threadIdx.x;
@@ -618,10 +610,10 @@ __global__ void lz_combine_kernel(const LzInst* __restrict__ I, int nins) {
   const LzInst& in = I[q0];
   const int64_t e = (int64_t)(blockIdx.x - in.g0) * 256 + threadIdx.x;
   if (e >= in.n) return;
-  const LZ_GLOBAL LzState* st = glb(in.st);
+  const MRD_GLOBAL LzState* st = glb(in.st);
   const int k = st->k;
   const auto V = glb(reinterpret_cast<const lzc*>(in.V));
-  const LZ_GLOBAL double* y = st->y;
+  const MRD_GLOBAL double* y = st->y;
   double r = 0, im = 0;
   int i = 0;
   for (; i + LZ_U <= k; i += LZ_U) {  // loads first, then the sums in index order
