@@ -3,7 +3,6 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
-#include <unordered_map>
 #include <cmath>
 #include <cstring>
 #include <memory>

@@ -4,7 +4,6 @@
 #include <climits>
 
 #include <algorithm>
-#include <unordered_map>
 #include <cmath>
 #include <sstream>
 
@@ -32,7 +31,16 @@ Bond make_bond(const dm_bond* b, int ly) {
     }
     out.q.push_back(q);
     out.dim.push_back(b->dim[i]);
-    out.index[((int64_t)q.n << 32) ^ (int64_t)(uint32_t)q.k] = i;
+  }
+  if (b->nsec > 0) {
+    out.nlo = out.q.front().n;
+    const int64_t span = (int64_t)out.q.back().n - out.nlo + 1;
+    if (span * ly <= std::max<int64_t>(4096, 16 * (int64_t)b->nsec)) {
+      out.nspan = span;
+      out.lut.assign((size_t)(span * ly), -1);
+      for (int i = 0; i < b->nsec; ++i)
+        out.lut[(size_t)((int64_t)out.q[i].n - out.nlo) * ly + out.q[i].k] = i;
+    }
   }
   return out;
 }

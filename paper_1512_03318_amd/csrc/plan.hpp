@@ -5,7 +5,6 @@
 #include <complex>
 #include <cstdint>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/mrdmrg.h"
@@ -29,13 +28,28 @@ inline bool qeq(dm_charge a, dm_charge b) { return a.n == b.n && a.k == b.k; }
 // A validated virtual bond.
 struct Bond {
   int ly = 1;
-  std::vector<dm_charge> q;
+  std::vector<dm_charge> q;  // strictly increasing in (n, k)
   std::vector<int> dim;
-  std::unordered_map<int64_t, int> index;
+  // Sector lookup (the planners call it tens of thousands of times per bond update): a
+  // dense table over (n - nlo) * ly + k when the range of n is small, else a binary
+  // search of the sorted charges.
+  int nlo = 0;
+  int64_t nspan = 0;
+  std::vector<int32_t> lut;
   int size() const { return (int)q.size(); }
   int find(dm_charge c) const {
-    auto it = index.find(((int64_t)c.n << 32) ^ (int64_t)(uint32_t)c.k);
-    return it == index.end() ? -1 : it->second;
+    if (c.k < 0 || c.k >= ly) return -1;
+    if (!lut.empty()) {
+      const int64_t d = (int64_t)c.n - nlo;
+      return (d < 0 || d >= nspan) ? -1 : lut[(size_t)d * ly + c.k];
+    }
+    int lo = 0, hi = size();
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (q[mid].n < c.n || (q[mid].n == c.n && q[mid].k < c.k)) lo = mid + 1;
+      else hi = mid;
+    }
+    return (lo < size() && q[lo].n == c.n && q[lo].k == c.k) ? lo : -1;
   }
   int64_t total() const {
     int64_t s = 0;

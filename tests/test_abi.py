@@ -54,6 +54,32 @@ def test_theta_layout_covers_buffer_once():
     assert all(np.array_equal(back[k], th[k]) for k in th)
 
 
+def test_layouts_with_a_wide_charge_range():
+    """Sector lookup over a wide range of N (a sector 10^6 particles away: the library's
+    sorted-search path instead of its dense table) gives the same blocks for the original
+    sectors; the far sector only adds its own blocks after them."""
+    wl, a, c = _bonds()
+    qs1 = [tuple(q) for q in wl.qsite[wl.j]]
+    qs2 = [tuple(q) for q in wl.qsite[wl.j + 1]]
+    far = (max(q[0] for q in wl.bonds[wl.j + 2]) + 10**6, 0)
+    a_w = pk.Bond({**wl.bonds[wl.j], far: 2})
+    c_w = pk.Bond({**wl.bonds[wl.j + 2], far: 3})
+    m = mpo.build(model.Cylinder(wl.Ly, wl.Lx, Fraction(*wl.flux), 1.0, 1.0), "mixed")
+    for kind, args, kw in ((pk.LAYOUT_THETA, (a, c), dict(qs1=qs1, qs2=qs2)),
+                           (pk.LAYOUT_THETA, (a_w, c_w), dict(qs1=qs1, qs2=qs2)),
+                           (pk.LAYOUT_ENV_L, (a,), dict(qw=m.qbond[wl.j])),
+                           (pk.LAYOUT_ENV_L, (a_w,), dict(qw=m.qbond[wl.j]))):
+        if args[0] is a:
+            ref, nref = pk.layout(kind, wl.ly, *args, **kw)
+            continue
+        got, n = pk.layout(kind, wl.ly, *args, **kw)
+        assert got[:len(ref)] == ref
+        extra = got[len(ref):]
+        assert extra and n > nref
+        far_idx = len(wl.bonds[wl.j])  # the far sector sorts last in a_w (and in c_w)
+        assert all(b[0][0] == far_idx for b in extra)
+
+
 @pytest.mark.parametrize("kind", [pk.LAYOUT_ENV_L, pk.LAYOUT_ENV_R])
 def test_env_layout_covers_buffer_once(kind):
     wl, a, c = _bonds()
