@@ -52,7 +52,6 @@ GemmStage merge_problems(const std::vector<const GemmStage*>& in, const std::vec
   for (size_t i = 0; i < in.size(); ++i) {
     const GemmStage& st = *in[i];
     if ((st.flags & ~f64) != m.flags) throw DmError{DM_ERR_ARG, "batched plans have different stage kinds"};
-    if (st.flags & G_A_MIX) throw DmError{DM_ERR_ARG, "mixed operands cannot be batched"};
     const int32_t seg0 = (int32_t)m.segs.size();
     const int32_t row0 = (int32_t)m.rows.size();
     for (GemmSeg g : st.segs) {

@@ -269,7 +269,6 @@ hipError_t launch_gemm_bf16x3(const GemmStage& st, const float* A, const float* 
   const int32_t nt = (int32_t)st.tiles.size();
   if (nt == 0) return hipSuccess;
   if (st.nslots > 0 && !part) return hipErrorInvalidValue;
-  if (st.flags & G_A_MIX) return hipErrorInvalidValue;
   dim3 grid(nt), block(256);
 #define MRD_BF3_CASE(F, TM, TN, WM, WN, SP)                                                     \
   if (st.flags == (F) && st.tile_m == (TM) && st.tile_n == (TN) && st.split == (SP)) {          \

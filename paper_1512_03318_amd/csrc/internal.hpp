@@ -21,26 +21,21 @@ namespace mrd {
 //   C(i, j): affine      c_off + i * ldc + j,  row table crow[c_rowmap + i] + j
 // All offsets count complex elements.  A_CONJ conjugates A.  The K-segments of one
 // problem are summed in order into one accumulator; C is overwritten.
-// ---------------------------------------------------------------------------------
-//   A_MIX:   A(i, k) = sum_q coef_q X[src_q.off + i * src_q.ld + k] over the segment's
-//            sources (a_off = first source, nsrc = count) -- the sparse MPO mixing is
-//            folded into the operand load, so the mixed intermediate is never stored.
 enum GemmFlags : int32_t {
   G_A_T = 1,
   G_A_CONJ = 2,
   G_B_T = 4,
   G_A_ROWMAP = 8,
   G_C_ROWMAP = 16,
-  G_A_MIX = 32,
   G_C_F64 = 128,  // BF16x3: C is complex128, the FP32 results widened as they are stored
 };
 
 struct GemmSeg {
-  int64_t a_off;  // A_MIX: index of the first source in the stage's source list
+  int64_t a_off;
   int64_t b_off;
   int32_t lda, ldb;
   int32_t k;
-  int32_t nsrc;   // A_MIX: number of sources
+  int32_t pad;
 };
 
 struct GemmProb {
@@ -83,7 +78,6 @@ struct GemmStage {
   std::vector<GemmProb> probs;
   std::vector<GemmTile> tiles;
   std::vector<int64_t> rows;  // row table
-  std::vector<MixSrc> asrc;   // A_MIX sources
   // Output tile of one workgroup and the K split.  FP32/FP64 kernels: 64 x 64 tiles,
   // or DEEP 32 x 32 tiles whose four waves share the K range; BF16x3 kernel: 64 x 64,
   // 128 x 64, or 128 x 32 with split.  With split, a problem's K range is divided over
@@ -100,7 +94,6 @@ struct GemmStage {
   GemmProb* d_probs = nullptr;
   GemmTile* d_tiles = nullptr;
   int64_t* d_rows = nullptr;
-  MixSrc* d_asrc = nullptr;
   GemmTile* d_red_tiles = nullptr;
 };
 

@@ -71,7 +71,6 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
                                                    const GemmProb* __restrict__ probs,
                                                    const GemmTile* __restrict__ tiles,
                                                    const int64_t* __restrict__ rows,
-                                                   const MixSrc* __restrict__ asrc,
                                                    const T* __restrict__ A,
                                                    const T* __restrict__ B,
                                                    T* __restrict__ C,
@@ -128,15 +127,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
       Cplx<T> v{0, 0};
       if (i < P.M && k < kc) {
         const int kk = k0 + k;
-        if (FLAGS & G_A_MIX) {
-          for (int s = 0; s < S.nsrc; ++s) {
-            const MixSrc src = asrc[S.a_off + s];
-            const Cplx<T> x = ldc(A, src.off + (int64_t)i * src.ld + kk);
-            const T cr = (T)src.re, ci = (T)src.im;
-            v.re += cr * x.re - ci * x.im;
-            v.im += cr * x.im + ci * x.re;
-          }
-        } else if (FLAGS & G_A_ROWMAP) {
+        if (FLAGS & G_A_ROWMAP) {
           v = ldc(A, arow[q] + S.a_off + kk);
         } else if (FLAGS & G_A_T) {
           v = ldc(A, S.a_off + (int64_t)kk * S.lda + i);
@@ -313,7 +304,7 @@ hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* par
   if (st.flags == (F) && st.deep == (D) && st.tile_m == (D ? 32 : 64) &&                  \
       st.tile_n == (D ? 32 : 64) && (D || !st.split)) {                                    \
     hipLaunchKernelGGL((gemm_kernel<T, F, D>), grid, block, 0, s, st.d_segs, st.d_probs,   \
-                       st.d_tiles, st.d_rows, st.d_asrc, A, B, C, part, skip);             \
+                       st.d_tiles, st.d_rows, A, B, C, part, skip);                        \
     if (between) between();                                                                \
     if (D && !st.red_tiles.empty())                                                        \
       hipLaunchKernelGGL((gemm_split_reduce_kernel<T, F>), dim3(st.red_tiles.size(), 1),   \

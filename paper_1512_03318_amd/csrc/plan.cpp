@@ -223,15 +223,7 @@ void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_siz
       const GemmSeg& g = st.segs[p.seg0 + q];
       if (g.k < 0) throw err(DM_ERR_LAYOUT, "negative K");
       if (g.k == 0) continue;
-      if (st.flags & G_A_MIX) {
-        if (g.a_off < 0 || g.nsrc < 0 || g.a_off + g.nsrc > (int64_t)st.asrc.size())
-          throw err(DM_ERR_LAYOUT, "bad mixing sources");
-        for (int q = 0; q < g.nsrc; ++q) {
-          const MixSrc& m = st.asrc[g.a_off + q];
-          range_check(m.off, m.off + (int64_t)(p.M - 1) * m.ld + g.k - 1, a_size, "A mix");
-          if (m.ld < g.k) throw err(DM_ERR_LAYOUT, "mix ld");
-        }
-      } else if (arow) {
+      if (arow) {
         range_check(rlo + g.a_off, rhi + g.a_off + g.k - 1, a_size, "A");
       } else if (st.flags & G_A_T) {
         range_check(g.a_off, g.a_off + (int64_t)(g.k - 1) * g.lda + p.M - 1, a_size, "A");

@@ -73,7 +73,6 @@ struct TableUpload {
     add(st.probs, &st.d_probs);
     add(st.tiles, &st.d_tiles);
     add(st.rows, &st.d_rows);
-    add(st.asrc, &st.d_asrc);
     add(st.red_tiles, &st.d_red_tiles);
   }
   void add(MixStage& st) {
