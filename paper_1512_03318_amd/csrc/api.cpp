@@ -376,7 +376,7 @@ static hipEvent_t* prof_slot(dm_heff_plan* p) {
 
 // theta_out = H_eff theta in the plan's precision (FP64 in / out).
 void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStream_t s,
-                   bool force64, const int32_t* skip, bool capturing) {
+                   bool force64, const int32_t* skip, bool capturing, bool staged) {
   hipEvent_t* ev = (force64 || capturing) ? nullptr : prof_slot(p);
   auto mark = [&](int i) {
     if (ev) HIPCHK(hipEventRecord(ev[i], s));
@@ -409,7 +409,7 @@ void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStrea
   // theta in: an FP32 copy; theta' out: BF16x3 stages write FP64 themselves (the FP32
   // results widened as they are stored), FP32 stages through an FP32 copy
   const bool direct = p->prec == DM_BF16X3;
-  HIPCHK(launch_cast_d2f((const double*)theta, (float*)p->dTin, 2 * p->n(), s, skip));
+  if (!staged) HIPCHK(launch_cast_d2f((const double*)theta, (float*)p->dTin, 2 * p->n(), s, skip));
   float* tout = direct ? (float*)theta_out : (float*)p->dTout;
   mark(0);
   HIPCHK(gemm_lp(p->prec, p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, nullptr, s, skip));
@@ -485,6 +485,7 @@ void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
   if (relayout) {
     std::vector<LzInst> I(1);
     I[0] = LzInst{p->dV, p->dW, p->dVcur, p->dPart, nullptr, nullptr, p->dState, n, n};
+    I[0].tin = p->prec == DM_FP64 ? nullptr : (float*)p->dTin;  // v_j also written in FP32
     p->lzg = lz_layout(I, p->Vcap - 1);
     *p->hInst = I[0];
   }
@@ -499,7 +500,7 @@ void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
 // the step index; j + 1 (or 0 for a step captured once for every replay) only bounds
 // the Krylov vector count so the projection kernels can be sized to it.
 static void lanczos_step(dm_heff_plan* p, hipStream_t s, bool capturing, int32_t j) {
-  heff_run(p, p->dVcur, p->dW, s, false, &p->dState->stop, capturing);
+  heff_run(p, p->dVcur, p->dW, s, false, &p->dState->stop, capturing, p->prec != DM_FP64);
   HIPCHK(lz_launch_step_tail(p->dInst, p->lzg, capturing ? 0 : j + 1, s));
 }
 

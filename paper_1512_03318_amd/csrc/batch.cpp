@@ -208,9 +208,8 @@ struct dm_batch {
   int prec = DM_FP64;
   bool built = false;
   MergedMatvec mv, mv64;        // mv64: FP64 matvec of the final Rayleigh quotient
-  std::vector<CastJob> cin, cout;
-  int32_t cin_blocks = 0, cout_blocks = 0;
-  CastJob* d_cin = nullptr;
+  std::vector<CastJob> cout;    // FP32 results of each instance to its FP64 w
+  int32_t cout_blocks = 0;
   CastJob* d_cout = nullptr;
   void* dTables = nullptr;
   int lz_cap = 0;               // max_iter the instance table is laid out for
@@ -385,10 +384,8 @@ void build_batch(dm_batch& b, hipStream_t s) {
   if (b.prec != DM_FP64) {
     b.mv64 = build_merged(b, true, s);
     for (dm_heff_plan* p : b.plans) {
-      b.cin.push_back({p->dVcur, p->dTin, 2 * p->n(), 0, 0});
       b.cout.push_back({p->dTout, p->dW, 2 * p->n(), 0, 0});
     }
-    b.cin_blocks = cast_layout(b.cin);
     b.cout_blocks = cast_layout(b.cout);
   }
   TableUpload up;
@@ -397,17 +394,15 @@ void build_batch(dm_batch& b, hipStream_t s) {
     for (GemmStage& t : m->s4) up.add(t);
     up.add(m->mix);
   }
-  up.add(b.cin, &b.d_cin);
   up.add(b.cout, &b.d_cout);
   b.dTables = up.commit(s);
   b.built = true;
 }
 
 // One batched Lanczos step; nv_bound as for lz_launch_step_tail (step index + 1, or 0
-// for the captured step).
+// for the captured step).  The FP32 inputs of an FP32 / BF16x3 batch were written by
+// the Lanczos kernels that produced v_j.
 void batch_step(dm_batch& b, hipStream_t s, int32_t nv_bound) {
-  if (b.prec != DM_FP64)
-    HIPCHK(launch_cast_batch(true, b.d_cin, (int32_t)b.cin.size(), b.cin_blocks, s));
   run_merged(b.mv, s);
   if (b.prec != DM_FP64)
     HIPCHK(launch_cast_batch(false, b.d_cout, (int32_t)b.cout.size(), b.cout_blocks, s));
@@ -496,6 +491,7 @@ extern "C" int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t 
       dm_heff_plan* p = b->plans[i];
       I[i] = LzInst{p->dV, p->dW, p->dVcur, p->dPart, nullptr, (double*)thetas[i], p->dState,
                     p->n(), p->n()};
+      I[i].tin = b->prec == DM_FP64 ? nullptr : (float*)p->dTin;
     }
     const LzGrid g = lz_layout(I, max_iter);
     const bool same = b->graph_exec && std::equal(I.begin(), I.end(), b->hInst, [](const LzInst& x, const LzInst& y) {

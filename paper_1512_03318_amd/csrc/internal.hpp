@@ -191,6 +191,8 @@ struct LzInst {
   int64_t ld, n;   // n complex elements
   int32_t nb;      // chunk blocks (1024 elements)
   int32_t c0, g0;  // first chunk / 256-element block of this instance
+  float* tin;      // or null: FP32 copy of v_j written with it (input of an FP32 /
+                   // BF16x3 matvec, which then needs no cast of its own)
 };
 // Launch shape of an instance table (host side).
 struct LzGrid {

@@ -30,6 +30,7 @@ namespace mrd {
 
 // complex FP64 element (re, im) as a native vector: 16-byte loads through global pointers
 typedef double lzc __attribute__((ext_vector_type(2)));
+typedef float lzf __attribute__((ext_vector_type(2)));
 
 constexpr int LZ_EPT = 4;                 // elements per thread in streaming kernels
 constexpr int LZ_CHUNK = 256 * LZ_EPT;
@@ -206,6 +207,7 @@ __global__ void lz_start_scale_kernel(const LzInst* __restrict__ I, int nins) {
   const lzc v = lzc{x.x * s, x.y * s};
   glb(reinterpret_cast<lzc*>(in.V))[e] = v;
   glb(reinterpret_cast<lzc*>(in.vcur))[e] = v;
+  if (in.tin) glb(reinterpret_cast<lzf*>(in.tin))[e] = lzf{(float)v.x, (float)v.y};
 }
 
 constexpr int LZ_G = 8;  // Krylov vectors per dot-product block
@@ -487,6 +489,7 @@ __global__ void __launch_bounds__(256) lz_next_kernel(const LzInst* __restrict__
   x.y *= s;
   V[(int64_t)nv * ld + e] = x;
   glb(reinterpret_cast<lzc*>(in.vcur))[e] = x;
+  if (in.tin) glb(reinterpret_cast<lzf*>(in.tin))[e] = lzf{(float)x.x, (float)x.y};
 }
 
 // Sturm count: number of eigenvalues of T_k below x.

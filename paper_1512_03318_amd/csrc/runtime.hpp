@@ -198,9 +198,11 @@ struct dm_heff_plan {
 namespace mrd {
 // theta_out = H_eff theta in the plan's precision (FP64 in / out); force64 uses the
 // FP64 copies of L and R.  skip (may be null): device flag that turns the launches into
-// no-ops.  capturing: no profiling events (inside HIP graph capture).
+// no-ops.  capturing: no profiling events (inside HIP graph capture).  staged: an FP32 /
+// BF16x3 plan's FP32 copy of theta is already in its input buffer (written by the
+// Lanczos kernels that produced theta), so no cast is launched.
 void heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStream_t s, bool force64,
-              const int32_t* skip = nullptr, bool capturing = false);
+              const int32_t* skip = nullptr, bool capturing = false, bool staged = false);
 // Lanczos workspace of a plan for up to max_iter steps.
 void ensure_lanczos(dm_heff_plan* p, int max_iter);
 }  // namespace mrd
