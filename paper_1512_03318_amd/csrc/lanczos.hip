@@ -230,13 +230,16 @@ __device__ __forceinline__ void block_sums(const double (&v)[NVAL], int nval, do
   }
 }
 
-// part[blk][2i + {0,1}] = sum over chunk blk of conj(V_i) w for the (up to) LZ_G
-// vectors i = LZ_G * blockIdx.x + g < nv (nv = iter + 1).  Chunk blk holds the elements
-// blk * LZ_CHUNK + q * 256 + thread, q < LZ_EPT.  Blocks of the same chunk and other
-// groups read the same w elements (L2 hits).
+// part[blk][2i + {0,1}] = sum over chunk blk of conj(V_i) w for every i < nv (nv =
+// iter + 1).  Chunk blk holds the elements blk * LZ_CHUNK + q * 256 + thread, q < LZ_EPT.
+// One block per chunk keeps its w elements in registers and walks the basis in groups
+// of LZ_G vectors; a group's loads are all issued before its products (measured at 30
+// vectors of 660k elements: 56 us against 74 us with one block per chunk and group,
+// which re-read w and ended after one round of loads).
 template <int NG>
-__device__ __forceinline__ void lz_dots_body(const LzInst& in, int i0, int nv, int blk, double* sh) {
-  const auto xv = glb(reinterpret_cast<const lzc*>(in.w));
+__device__ __forceinline__ void lz_dots_group(const LzInst& in, const lzc (&xe)[LZ_EPT],
+                                              int64_t e0, bool full, int i0, int nv, int blk,
+                                              double* sh) {
   const auto v0 = glb(reinterpret_cast<const lzc*>(in.V));
   MRD_GLOBAL const lzc* vv[NG];
 #pragma unroll
@@ -244,12 +247,8 @@ __device__ __forceinline__ void lz_dots_body(const LzInst& in, int i0, int nv, i
   double acc[2 * NG];
 #pragma unroll
   for (int c = 0; c < 2 * NG; ++c) acc[c] = 0.0;
-  const int64_t e0 = (int64_t)blk * LZ_CHUNK + threadIdx.x;
-  if (e0 + (LZ_EPT - 1) * 256 < in.n) {
-    // every element of this thread in range: all loads are issued before the products
-    lzc xe[LZ_EPT], v[NG][LZ_EPT];
-#pragma unroll
-    for (int q = 0; q < LZ_EPT; ++q) xe[q] = xv[e0 + q * 256];
+  if (full) {
+    lzc v[NG][LZ_EPT];
 #pragma unroll
     for (int g = 0; g < NG; ++g)
 #pragma unroll
@@ -266,12 +265,11 @@ __device__ __forceinline__ void lz_dots_body(const LzInst& in, int i0, int nv, i
     for (int q = 0; q < LZ_EPT; ++q) {
       const int64_t e = e0 + q * 256;
       if (e < in.n) {
-        const lzc xe = xv[e];
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
           const lzc v = vv[g][e];
-          acc[2 * g] += v.x * xe.x + v.y * xe.y;
-          acc[2 * g + 1] += v.x * xe.y - v.y * xe.x;
+          acc[2 * g] += v.x * xe[q].x + v.y * xe[q].y;
+          acc[2 * g + 1] += v.x * xe[q].y - v.y * xe[q].x;
         }
       }
     }
@@ -281,23 +279,30 @@ __device__ __forceinline__ void lz_dots_body(const LzInst& in, int i0, int nv, i
 
 __global__ void __launch_bounds__(256) lz_dots_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4 * 2 * LZ_G];
-  const int q0 = lz_find<0>(I, nins, blockIdx.y);
+  const int q0 = lz_find<0>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
   const auto sg = glb(in.st);
   if (sg->stop) return;
   const int nv = sg->iter + 1;
-  const int i0 = blockIdx.x * LZ_G;
-  if (i0 >= nv) return;
-  const int blk = blockIdx.y - in.c0;
-  switch (min(LZ_G, nv - i0)) {  // uniform over the block
-    case 1: lz_dots_body<1>(in, i0, nv, blk, sh); break;
-    case 2: lz_dots_body<2>(in, i0, nv, blk, sh); break;
-    case 3: lz_dots_body<3>(in, i0, nv, blk, sh); break;
-    case 4: lz_dots_body<4>(in, i0, nv, blk, sh); break;
-    case 5: lz_dots_body<5>(in, i0, nv, blk, sh); break;
-    case 6: lz_dots_body<6>(in, i0, nv, blk, sh); break;
-    case 7: lz_dots_body<7>(in, i0, nv, blk, sh); break;
-    default: lz_dots_body<LZ_G>(in, i0, nv, blk, sh); break;
+  const int blk = blockIdx.x - in.c0;
+  const int64_t e0 = (int64_t)blk * LZ_CHUNK + threadIdx.x;
+  const bool full = e0 + (LZ_EPT - 1) * 256 < in.n;  // every element of this thread in range
+  const auto xv = glb(reinterpret_cast<const lzc*>(in.w));
+  lzc xe[LZ_EPT];
+#pragma unroll
+  for (int q = 0; q < LZ_EPT; ++q) xe[q] = e0 + q * 256 < in.n ? xv[e0 + q * 256] : lzc{0.0, 0.0};
+  for (int i0 = 0; i0 < nv; i0 += LZ_G) {
+    if (i0 > 0) __syncthreads();  // the previous group's sums have been read from sh
+    switch (min(LZ_G, nv - i0)) {  // uniform over the block
+      case 1: lz_dots_group<1>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 2: lz_dots_group<2>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 3: lz_dots_group<3>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 4: lz_dots_group<4>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 5: lz_dots_group<5>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 6: lz_dots_group<6>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 7: lz_dots_group<7>(in, xe, e0, full, i0, nv, blk, sh); break;
+      default: lz_dots_group<LZ_G>(in, xe, e0, full, i0, nv, blk, sh); break;
+    }
   }
 }
 
@@ -704,7 +709,7 @@ hipError_t lz_launch_step_tail(const LzInst* I, const LzGrid& g, int32_t nv_boun
   // nv <= max_iter at every step; without a bound from the caller (a step captured once
   // for every replay) the capacity bounds it
   const int b = (nv_bound > 0 && nv_bound < g.max_iter) ? nv_bound : g.max_iter;
-  const dim3 gd((b + LZ_G - 1) / LZ_G, g.nchunk);
+  const dim3 gd(g.nchunk);  // projections: one block per chunk over the whole basis
   hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, I, g.nins);
   hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H1);
   if (b <= LZ_FUSE) {
