@@ -189,7 +189,8 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
       quad_rk<G::B_KC, BN, KC>(tid, q, c, k);
       split_store(rb[q], sB, G::PLANE_B, c * LD + k);
     }
-    __syncthreads();
+    // the staging registers are free again: the next chunk's loads go out before the
+    // barrier and stay in flight during it and the products of this chunk
     k0 += kstep;
     while (k0 >= S.k) {
       if (++sg >= P.nseg) break;
@@ -197,6 +198,7 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
       k0 = kfirst;
     }
     if (sg < P.nseg) load_chunk(S, k0);
+    __syncthreads();
     // k positions beyond the chunk's valid range were staged as zeros
     bf16x8 b[YB][4];
 #pragma unroll
