@@ -192,8 +192,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
       sB[0][k][c] = rb[q].re;
       sB[1][k][c] = rb[q].im;
     }
-    __syncthreads();
-    // advance and prefetch the next chunk while this one is multiplied
+    // advance and prefetch the next chunk (the staging registers are free again): the
+    // loads stay in flight during the barrier and the products of this chunk
     k0 += kstep;
     while (k0 >= S.k) {
       if (++sg >= P.nseg) break;
@@ -201,6 +201,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
       k0 = kfirst;
     }
     if (sg < P.nseg) load_chunk(S, k0);
+    __syncthreads();
     const int kbeg = DEEP ? wave * KW : 0;
     const int kend = DEEP ? min(kbeg + KW, kc) : kc;
     for (int kb = kbeg; kb < kend; kb += 4) {
