@@ -1,6 +1,6 @@
 """The library from a plain C program (tests/c_abi/heff_driver.c): no Python and no
 PyTorch in the process that runs the kernels, only include/mrdmrg.h, libmrdmrg.so and
-the HIP runtime.  The test packs an oracle window problem, runs the driver as a child
+the HIP runtime.  The test packs an oracle window problem, runs heff_driver as a child
 process and compares its matvec and Lanczos energy with the FP64 oracle."""
 import os
 import struct
@@ -45,7 +45,7 @@ def _arr(x):
 
 @pytest.mark.parametrize("prec,tol", [(pk.DM_FP64, 1e-12), (pk.DM_BF16X3, 1e-4)])
 def test_c_program_matvec_and_lanczos(prec, tol, tmp_path):
-    assert os.path.exists(DRIVER), "build the driver with __graft_entry__.build()"
+    assert os.path.exists(DRIVER), "build heff_driver with __graft_entry__.build()"
     wl, L, W1, W2, R, th, keys, mpo = problem("ly4_chi64")
     j, ly = wl.j, wl.ly
     g = WindowGPU(wl, L, R, mpo)
