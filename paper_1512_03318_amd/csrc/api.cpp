@@ -5,6 +5,7 @@
 #include <mutex>
 #include <cmath>
 #include <cstring>
+#include <future>
 #include <memory>
 #include <sstream>
 
@@ -120,8 +121,73 @@ static void build_heff_tables(dm_heff_plan& p) {
       s1.flops += 8.0 * M * N * K;
     }
   };
-  build_s1(p.s1, p.prec == DM_BF16X3);
-  if (p.prec == DM_BF16X3) build_s1(p.s1f, false);
+  // Mixing: Z_{c'}[(s12', a'), (w'', c)] = sum_{w, s12} W12[w, s12', s12, w''] X_a[(w, a'), (s12, c)]
+  // Z panel per output sector c': rows (s12', a') stacked, columns the R panel's (w'', c).
+  p.zoff.assign(c.size(), 0);
+  p.zrows.assign(c.size(), 0);
+  p.ztotal = 0;
+  std::vector<std::array<int, 4>> zroff(c.size(), {-1, -1, -1, -1});
+  for (int ci2 = 0; ci2 < c.size(); ++ci2) {
+    int rows = 0;
+    for (int s12p = 0; s12p < 4; ++s12p) {
+      const int aip = zap[ci2][s12p];
+      if (aip < 0) continue;
+      zroff[ci2][s12p] = rows;
+      rows += a.dim[aip];
+    }
+    p.zrows[ci2] = rows;
+    p.zoff[ci2] = p.ztotal;
+    p.ztotal += (int64_t)rows * p.R.P.cols[ci2];
+  }
+  // (.)R stage, one problem per output sector c':
+  //   theta'[(s12', a'), c'] = Z_{c'} (M x K) . Rpanel_{c'}^T (K x m_c'), K = R panel width,
+  // rows scattered to the theta blocks through the row table.  K-split over workgroups.
+  auto build_s4 = [&](GemmStage& s4, bool bf3) {
+    s4.flags = G_B_T | G_C_ROWMAP | (bf3 ? G_C_F64 : 0);  // BF16x3 writes theta' in FP64
+    s4.split = true;
+    if (bf3) {  // 128 x 32 tiles, K split over workgroups in runs of >= 12 chunks of 32
+      // (at Ly=8, chi=3200 the GEMM takes about the same time for runs of 6 to 12 chunks,
+      // while fewer partial tiles halve the split reduction)
+      s4.tile_m = 128;
+      s4.tile_n = 32;
+      s4.kc = 32;
+      s4.split_min = 12;
+    } else {    // 32 x 32 tiles shared by four waves, >= 4 chunks of 64 per split
+      s4.deep = true;
+      s4.tile_m = s4.tile_n = 32;
+      s4.kc = 64;
+      s4.split_min = 4;
+    }
+    for (int ci2 = 0; ci2 < c.size(); ++ci2) {
+      const int M = p.zrows[ci2], N = c.dim[ci2], K = p.R.P.cols[ci2];
+      if (M == 0) continue;
+      GemmProb pr{0, M, N, (int32_t)s4.segs.size(), K > 0 ? 1 : 0, 0, (int32_t)s4.rows.size()};
+      for (int s12p = 0; s12p < 4; ++s12p) {
+        const int aip = zap[ci2][s12p];
+        if (aip < 0) continue;
+        const int64_t base = p.th.P.off[aip] + p.th.coff[aip][s12p];
+        for (int r = 0; r < a.dim[aip]; ++r) s4.rows.push_back(base + (int64_t)r * p.th.P.cols[aip]);
+      }
+      if (K > 0) s4.segs.push_back({p.zoff[ci2], p.R.P.off[ci2], K, K, K, 0});
+      s4.probs.push_back(pr);
+      add_tiles(s4, (int32_t)s4.probs.size() - 1, M, N);
+      s4.flops += 8.0 * M * N * K;
+    }
+  };
+  // The GEMM stage tables are built and bounds-checked on a second thread while this one
+  // builds the mixing tables (disjoint members of the plan; an exception there is
+  // rethrown by get()).
+  const bool bf3 = p.prec == DM_BF16X3;
+  auto gemm_tables = std::async(std::launch::async, [&] {
+    build_s1(p.s1, bf3);
+    if (bf3) build_s1(p.s1f, false);
+    build_s4(p.s4, bf3);
+    if (bf3) build_s4(p.s4f, false);
+    validate(p.s1, p.L.P.total, p.n(), p.xtotal);
+    validate(p.s4, p.ztotal, p.R.P.total, p.n());
+    validate(p.s1f, p.L.P.total, p.n(), p.xtotal);
+    validate(p.s4f, p.ztotal, p.R.P.total, p.n());
+  });
   // two-site MPO W12[w, s12', s12, w''] = sum_w' W1[w, s1', s1, w'] W2[w', s2', s2, w'']
   std::vector<std::complex<double>> w12((size_t)dl * 16 * dr);
   auto W12 = [&](int w, int sp, int s, int wpp) -> std::complex<double>& {
@@ -141,24 +207,6 @@ static void build_heff_tables(dm_heff_plan& p) {
                 W12(w, s1p * 2 + s2p, s1 * 2 + s2, wpp) += x * y;
               }
         }
-  // Mixing: Z_{c'}[(s12', a'), (w'', c)] = sum_{w, s12} W12[w, s12', s12, w''] X_a[(w, a'), (s12, c)]
-  // Z panel per output sector c': rows (s12', a') stacked, columns the R panel's (w'', c).
-  p.zoff.assign(c.size(), 0);
-  p.zrows.assign(c.size(), 0);
-  p.ztotal = 0;
-  std::vector<std::array<int, 4>> zroff(c.size(), {-1, -1, -1, -1});
-  for (int ci2 = 0; ci2 < c.size(); ++ci2) {
-    int rows = 0;
-    for (int s12p = 0; s12p < 4; ++s12p) {
-      const int aip = zap[ci2][s12p];
-      if (aip < 0) continue;
-      zroff[ci2][s12p] = rows;
-      rows += a.dim[aip];
-    }
-    p.zrows[ci2] = rows;
-    p.zoff[ci2] = p.ztotal;
-    p.ztotal += (int64_t)rows * p.R.P.cols[ci2];
-  }
   // nonzeros of W12 per (s12', w''): (w, s12, value)
   struct Nz {
     int w, s12;
@@ -232,43 +280,7 @@ static void build_heff_tables(dm_heff_plan& p) {
   // enough loads in flight; measured best between 12 and 32 KB at Ly=8, chi=3200)
   mix_to_slabs(mx, task_key, (int)elem_bytes(p.prec), 20480);
   p.mix_flops = mx.flops;
-  // (.)R stage, one problem per output sector c':
-  //   theta'[(s12', a'), c'] = Z_{c'} (M x K) . Rpanel_{c'}^T (K x m_c'), K = R panel width,
-  // rows scattered to the theta blocks through the row table.  K-split over workgroups.
-  auto build_s4 = [&](GemmStage& s4, bool bf3) {
-    s4.flags = G_B_T | G_C_ROWMAP | (bf3 ? G_C_F64 : 0);  // BF16x3 writes theta' in FP64
-    s4.split = true;
-    if (bf3) {  // 128 x 32 tiles, K split over workgroups in runs of >= 12 chunks of 32
-      // (at Ly=8, chi=3200 the GEMM takes about the same time for runs of 6 to 12 chunks,
-      // while fewer partial tiles halve the split reduction)
-      s4.tile_m = 128;
-      s4.tile_n = 32;
-      s4.kc = 32;
-      s4.split_min = 12;
-    } else {    // 32 x 32 tiles shared by four waves, >= 4 chunks of 64 per split
-      s4.deep = true;
-      s4.tile_m = s4.tile_n = 32;
-      s4.kc = 64;
-      s4.split_min = 4;
-    }
-    for (int ci2 = 0; ci2 < c.size(); ++ci2) {
-      const int M = p.zrows[ci2], N = c.dim[ci2], K = p.R.P.cols[ci2];
-      if (M == 0) continue;
-      GemmProb pr{0, M, N, (int32_t)s4.segs.size(), K > 0 ? 1 : 0, 0, (int32_t)s4.rows.size()};
-      for (int s12p = 0; s12p < 4; ++s12p) {
-        const int aip = zap[ci2][s12p];
-        if (aip < 0) continue;
-        const int64_t base = p.th.P.off[aip] + p.th.coff[aip][s12p];
-        for (int r = 0; r < a.dim[aip]; ++r) s4.rows.push_back(base + (int64_t)r * p.th.P.cols[aip]);
-      }
-      if (K > 0) s4.segs.push_back({p.zoff[ci2], p.R.P.off[ci2], K, K, K, 0});
-      s4.probs.push_back(pr);
-      add_tiles(s4, (int32_t)s4.probs.size() - 1, M, N);
-      s4.flops += 8.0 * M * N * K;
-    }
-  };
-  build_s4(p.s4, p.prec == DM_BF16X3);
-  if (p.prec == DM_BF16X3) build_s4(p.s4f, false);
+  gemm_tables.get();
 }
 
 extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* c,
@@ -296,12 +308,8 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     p->R = envr_layout(p->c, p->w2.qr, ly);
     if ((p->L.P.total > 0 && !L) || (p->R.P.total > 0 && !R))
       throw DmError{DM_ERR_ARG, "null environment"};
-    build_heff_tables(*p);
-    validate(p->s1, p->L.P.total, p->n(), p->xtotal);
+    build_heff_tables(*p);  // also validates the GEMM stages
     validate(p->mix, p->xtotal, p->ztotal);
-    validate(p->s4, p->ztotal, p->R.P.total, p->n());
-    validate(p->s1f, p->L.P.total, p->n(), p->xtotal);
-    validate(p->s4f, p->ztotal, p->R.P.total, p->n());
     hipStream_t s = (hipStream_t)stream;
     {
       TableUpload up;
@@ -696,45 +704,52 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
   std::vector<int> t1roff((size_t)c.size() * 2 * dr, -1);
   ep.t1.flags = G_A_ROWMAP | G_B_T;
   ep.t1.tile_n = t1_tile_n;
-  {
-    // row table size: every (c, s) with a b sector stacks the R rows of every (w', c')
-    size_t nrows = 0;
-    for (int ci = 0; ci < c.size(); ++ci)
-      for (int s = 0; s < 2; ++s) {
-        const int bi = b.find(qsub(c.q[ci], W.qs[s], ly));
-        if (bi < 0 || S.b[bi][s] != ci) continue;
-        for (int wp = 0; wp < dr; ++wp) {
-          const int cpi = c.find(qadd(c.q[ci], W.qr[wp], ly));
-          if (cpi >= 0) nrows += c.dim[cpi];
-        }
-      }
-    ep.t1.rows.reserve(nrows);
-  }
+  // Offsets first (the mixing tables need them): every (c, s) with a b sector stacks the
+  // R rows of every (w', c'); its rows start at t1rm in the row table.
+  std::vector<int32_t> t1m((size_t)c.size() * 2, 0), t1rm((size_t)c.size() * 2, 0);
+  size_t nrows = 0;
   for (int ci = 0; ci < c.size(); ++ci)
     for (int s = 0; s < 2; ++s) {
       const int bi = b.find(qsub(c.q[ci], W.qs[s], ly));
       if (bi < 0 || S.b[bi][s] != ci) continue;
       int M = 0;
-      const int32_t rm = (int32_t)ep.t1.rows.size();
       for (int wp = 0; wp < dr; ++wp) {
         const int cpi = c.find(qadd(c.q[ci], W.qr[wp], ly));
         if (cpi < 0) continue;
         t1roff[((size_t)ci * 2 + s) * dr + wp] = M;
-        const int64_t col = R.coff[cpi * dr + wp];
-        for (int r = 0; r < c.dim[cpi]; ++r)
-          ep.t1.rows.push_back(R.P.off[cpi] + (int64_t)r * R.P.cols[cpi] + col);
         M += c.dim[cpi];
       }
-      const int N = b.dim[bi], K = c.dim[ci];
+      t1m[ci * 2 + s] = M;
+      t1rm[ci * 2 + s] = (int32_t)nrows;
+      nrows += M;
       t1off[ci * 2 + s] = ep.t1total;
-      ep.t1total += (int64_t)M * N;
-      if (M == 0) continue;
-      GemmProb pr{t1off[ci * 2 + s], M, N, (int32_t)ep.t1.segs.size(), 1, N, rm};
-      ep.t1.segs.push_back({0, S.P.off[bi] + S.coff[bi][s], 0, S.P.cols[bi], K, 0});
-      ep.t1.probs.push_back(pr);
-      add_tiles(ep.t1, (int32_t)ep.t1.probs.size() - 1, M, N);
-      ep.t1.flops += 8.0 * M * N * K;
+      ep.t1total += (int64_t)M * b.dim[bi];
     }
+  // The T1 row table and problems on a second thread while this one builds the mixing and
+  // T3 tables (disjoint members of ep)
+  auto t1_tables = std::async(std::launch::async, [&] {
+    ep.t1.rows.resize(nrows);
+    for (int ci = 0; ci < c.size(); ++ci)
+      for (int s = 0; s < 2; ++s) {
+        const int64_t o = t1off[ci * 2 + s];
+        if (o < 0) continue;
+        const int bi = b.find(qsub(c.q[ci], W.qs[s], ly));
+        int64_t* out = ep.t1.rows.data() + t1rm[ci * 2 + s];
+        for (int wp = 0; wp < dr; ++wp) {
+          const int cpi = c.find(qadd(c.q[ci], W.qr[wp], ly));
+          if (cpi < 0) continue;
+          const int64_t base = R.P.off[cpi] + R.coff[cpi * dr + wp];
+          for (int r = 0; r < c.dim[cpi]; ++r) *out++ = base + (int64_t)r * R.P.cols[cpi];
+        }
+        const int M = t1m[ci * 2 + s], N = b.dim[bi], K = c.dim[ci];
+        if (M == 0) continue;
+        GemmProb pr{o, M, N, (int32_t)ep.t1.segs.size(), 1, N, t1rm[ci * 2 + s]};
+        ep.t1.segs.push_back({0, S.P.off[bi] + S.coff[bi][s], 0, S.P.cols[bi], K, 0});
+        ep.t1.probs.push_back(pr);
+        add_tiles(ep.t1, (int32_t)ep.t1.probs.size() - 1, M, N);
+        ep.t1.flops += 8.0 * M * N * K;
+      }
+  });
   // T2 per (w, b): rows (s', c') with b' = b + q(w), c' = b' + q(s'); cols m_b
   std::vector<int64_t> t2off((size_t)dl * b.size(), -1);
   std::vector<int> t2roff((size_t)dl * b.size() * 2, -1);
@@ -822,6 +837,7 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
       add_tiles(ep.t3, (int32_t)ep.t3.probs.size() - 1, M, N);
       ep.t3.flops += 8.0 * M * N * K;
     }
+  t1_tables.get();
   return ep;
 }
 
