@@ -6,12 +6,24 @@
 #include <cmath>
 #include <cstring>
 #include <future>
+#include <system_error>
 #include <memory>
 #include <sstream>
 
 #include "runtime.hpp"
 
 using namespace mrd;
+
+// Runs f on a second thread, or later on the caller (at get()) when no thread can be
+// started; the result and any exception come back through get().
+template <class F>
+static std::future<void> run_beside(const F& f) {
+  try {
+    return std::async(std::launch::async, f);
+  } catch (const std::system_error&) {
+    return std::async(std::launch::deferred, f);
+  }
+}
 
 // =====================================================================================
 // Layout query
@@ -178,7 +190,7 @@ static void build_heff_tables(dm_heff_plan& p) {
   // builds the mixing tables (disjoint members of the plan; an exception there is
   // rethrown by get()).
   const bool bf3 = p.prec == DM_BF16X3;
-  auto gemm_tables = std::async(std::launch::async, [&] {
+  auto gemm_tables = run_beside([&] {
     build_s1(p.s1, bf3);
     if (bf3) build_s1(p.s1f, false);
     build_s4(p.s4, bf3);
@@ -727,7 +739,7 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
     }
   // The T1 row table and problems on a second thread while this one builds the mixing and
   // T3 tables (disjoint members of ep)
-  auto t1_tables = std::async(std::launch::async, [&] {
+  auto t1_tables = run_beside([&] {
     ep.t1.rows.resize(nrows);
     for (int ci = 0; ci < c.size(); ++ci)
       for (int s = 0; s < 2; ++s) {
