@@ -56,6 +56,12 @@
  *   crosses this boundary.  GPU work is enqueued on the given stream; only the Lanczos
  *   calls synchronise (they return host scalars).  Library scratch is released in
  *   stream order (reused once the stream has passed the work that used it).
+ *
+ * Threads.  The library's device and pinned-host pools are locked: distinct plans and
+ *   batches may be created and used from different host threads at once (each on its
+ *   own stream).  Calls on one plan, or on a batch and the plans it holds, must not
+ *   overlap.  Plan creation and the right environment update run part of their host
+ *   planning on a helper thread that they join before returning.
  * ---------------------------------------------------------------------------------
  */
 #ifndef MRDMRG_H
