@@ -92,13 +92,18 @@ def build_inputs(pk, torch, wl, stream):
     return out
 
 
+PROFILE_EVERY = 4
+
+
 def run_step(pk, inp, prec, iters, stream, profile=False):
     """One bond update; returns (energy, iterations, plan, host times)."""
     t0 = time.perf_counter()
     plan = pk.HeffPlan(inp["ly"], inp["a"], inp["c"], inp["w1"], inp["w2"], inp["L"], inp["R"],
                        prec, stream)
     if profile:
-        plan.profile(True)
+        # stage times from every PROFILE_EVERY-th matvec: each recorded HIP event costs
+        # the stream a few microseconds, five per recorded matvec
+        plan.profile(True, every=PROFILE_EVERY)
     th = inp["theta"].clone()
     t1 = time.perf_counter()
     e, k = pk.lanczos_ground(plan, th, iters, 1e-14, stream)
@@ -233,6 +238,7 @@ def stage_rooflines(pk, plan, prec, pname, prof, nmv, workload):
     out = dict(stages[dom])
     out["stages"] = stages
     out["k_split_reduction_ms"] = round(avg[3], 4)
+    out["profiled_matvecs"] = nmv  # HIP-event samples (every PROFILE_EVERY-th matvec)
     return out
 
 

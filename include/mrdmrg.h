@@ -168,13 +168,16 @@ int dm_heff_info(const dm_heff_plan* p, int64_t* theta_elems, double flops[3]);
  * algorithmic bytes of a stage follow from these (each element read or written once). */
 int dm_heff_sizes(const dm_heff_plan* p, int64_t sizes[5]);
 
-/* Device-time profile of the matvec stages.  While enabled, every matvec of the plan
- * (heff_apply and the ones inside lanczos_ground) records HIP events on its stream
- * around each kernel; dm_heff_profile_read synchronises and returns the accumulated
+/* Device-time profile of the matvec stages.  With enable = k > 0, every k-th matvec of
+ * the plan (heff_apply and the ones inside lanczos_ground, counted from this call)
+ * records HIP events on its stream around each kernel (each recorded event costs the
+ * stream a few microseconds, so k > 1 keeps the instrumented run close to an
+ * uninstrumented one); dm_heff_profile_read synchronises and returns the accumulated
  * milliseconds of 0: the L.theta GEMM kernel, 1: the MPO mixing kernel, 2: the (.).R
  * GEMM kernel, 3: the reduction of its K-split partial tiles, and the number of
- * matvecs recorded.  enable = 0 stops recording and clears the totals.  Profiling
- * keeps lanczos_ground on plain stream launches (no graph replay). */
+ * matvecs recorded.  enable = 0 stops recording and clears the totals; enable < 0 is
+ * DM_ERR_ARG.  Profiling keeps lanczos_ground on plain stream launches (no graph
+ * replay). */
 int dm_heff_profile(dm_heff_plan* p, int32_t enable);
 int dm_heff_profile_read(dm_heff_plan* p, double ms[4], int64_t* matvecs);
 

@@ -232,8 +232,9 @@ class HeffPlan:
         _check(lib.dm_heff_sizes(h, sz))
         self.sizes = dict(zip(("L", "R", "theta", "X", "Z"), (int(v) for v in sz)))
 
-    def profile(self, enable=True):
-        _check(lib.dm_heff_profile(self.h, 1 if enable else 0))
+    def profile(self, enable=True, every=1):
+        """Record the stage times of every `every`-th matvec (enable=False: stop)."""
+        _check(lib.dm_heff_profile(self.h, int(every) if enable else 0))
 
     def profile_read(self):
         """(ms per kernel [L.theta GEMM, mixing, (.).R GEMM, K-split reduction] accumulated,

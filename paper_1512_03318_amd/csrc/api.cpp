@@ -386,6 +386,7 @@ extern "C" int dm_heff_sizes(const dm_heff_plan* p, int64_t sizes[5]) {
 
 static hipEvent_t* prof_slot(dm_heff_plan* p) {
   if (!p->profiling) return nullptr;
+  if (p->prof_seen++ % p->prof_stride != 0) return nullptr;
   if (p->ev_used == p->ev.size()) {
     std::array<hipEvent_t, 5> e;
     for (auto& x : e) HIPCHK(hipEventCreate(&x));
@@ -444,7 +445,10 @@ void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStrea
 
 extern "C" int dm_heff_profile(dm_heff_plan* p, int32_t enable) {
   if (!p) return fail(DM_ERR_ARG, "null plan");
+  if (enable < 0) return fail(DM_ERR_ARG, "negative profiling stride");
   p->profiling = enable != 0;
+  p->prof_stride = enable > 0 ? enable : 1;
+  p->prof_seen = 0;
   p->ev_used = 0;
   return DM_OK;
 }

@@ -169,6 +169,8 @@ struct dm_heff_plan {
   bool use_graph = true;
   // profiling: events around the three stages of each recorded matvec
   bool profiling = false;
+  int32_t prof_stride = 1;  // record every prof_stride-th matvec
+  int64_t prof_seen = 0;    // matvecs since profiling was enabled
   std::vector<std::array<hipEvent_t, 5>> ev;
   size_t ev_used = 0;
   ~dm_heff_plan() {

@@ -170,6 +170,28 @@ def test_misaligned_theta_is_refused():
     assert np.isfinite(e) and k > 0
 
 
+def test_profile_stride():
+    """dm_heff_profile(k) records every k-th matvec; a negative stride is refused."""
+    c = ragged()
+    say("profile stride")
+    pack, _ = _theta_io(c)
+    plan = _plan(c, pk.DM_BF16X3)
+    x = to_dev(pack(c["th"]))
+    y = torch.empty_like(x)
+    plan.profile(True, every=4)
+    for _ in range(8):
+        pk.heff_apply(plan, x, y)
+    ms, n = plan.profile_read()
+    assert n == 2 and all(t > 0 for t in ms[:3]), (n, ms)
+    plan.profile(True, every=1)
+    pk.heff_apply(plan, x, y)
+    assert plan.profile_read()[1] == 1
+    with pytest.raises(pk.LibraryError) as ei:
+        plan.profile(True, every=-1)
+    assert ei.value.code == pk.DM_ERR_ARG
+    plan.profile(False)
+
+
 def test_window_without_theta_blocks():
     """Bond charges two particles apart cannot be joined by two sites: the theta layout,
     the matvec tables and the middle-bond environments are empty."""
