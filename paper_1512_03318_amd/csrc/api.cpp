@@ -504,8 +504,10 @@ void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
   if (!p->dState) p->dState = (LzState*)dev_alloc(sizeof(LzState));
   if (!p->dInst) p->dInst = (LzInst*)dev_alloc(sizeof(LzInst));
   if (!p->dRes) p->dRes = (LzResult*)dev_alloc(sizeof(LzResult));
-  if (!p->hInst) HIPCHK(hipHostMalloc((void**)&p->hInst, sizeof(LzInst), hipHostMallocDefault));
-  if (!p->hRes) HIPCHK(hipHostMalloc((void**)&p->hRes, sizeof(LzResult), hipHostMallocDefault));
+  // pinned from the library's pool: a plan per bond update would otherwise pay a pinned
+  // allocation and free (which can wait for the device) on every bond
+  if (!p->hInst) p->hInst = (LzInst*)pinned_alloc(sizeof(LzInst));
+  if (!p->hRes) p->hRes = (LzResult*)pinned_alloc(sizeof(LzResult));
   if (relayout) {
     std::vector<LzInst> I(1);
     I[0] = LzInst{p->dV, p->dW, p->dVcur, p->dPart, nullptr, nullptr, p->dState, n, n};

@@ -173,6 +173,7 @@ void dev_free(void* p) { pool().put(p); }
 void dev_free_after(void* p, hipStream_t s) { pool().put_after(p, s); }
 void* pinned_alloc(size_t bytes) { return pinned_pool().get(bytes); }
 void pinned_free_after(void* p, hipStream_t s) { pinned_pool().put_after(p, s); }
+void pinned_free(void* p) { pinned_pool().put(p); }
 
 size_t elem_bytes(int prec) { return prec == DM_FP64 ? 16 : 8; }
 

@@ -50,6 +50,7 @@ void dev_free(void* p);
 void dev_free_after(void* p, hipStream_t s);
 void* pinned_alloc(size_t bytes);
 void pinned_free_after(void* p, hipStream_t s);
+void pinned_free(void* p);  // no copy uses the block any more
 
 // All task tables of one or more stages in one device block, uploaded with one copy.
 struct TableUpload {
@@ -190,8 +191,8 @@ struct dm_heff_plan {
     mrd::dev_free(dState);
     mrd::dev_free(dInst);
     mrd::dev_free(dRes);
-    if (hInst) (void)hipHostFree(hInst);
-    if (hRes) (void)hipHostFree(hRes);
+    mrd::pinned_free(hInst);  // the solves that copied them have synchronised
+    mrd::pinned_free(hRes);
   }
   int64_t n() const { return th.P.total; }
 };
