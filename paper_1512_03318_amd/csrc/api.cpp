@@ -14,17 +14,6 @@
 
 using namespace mrd;
 
-// Runs f on a second thread, or later on the caller (at get()) when no thread can be
-// started; the result and any exception come back through get().
-template <class F>
-static std::future<void> run_beside(const F& f) {
-  try {
-    return std::async(std::launch::async, f);
-  } catch (const std::system_error&) {
-    return std::async(std::launch::deferred, f);
-  }
-}
-
 // =====================================================================================
 // Layout query
 // =====================================================================================

@@ -7,7 +7,9 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <future>
 #include <string>
+#include <system_error>
 #include <vector>
 
 #include "plan.hpp"
@@ -36,6 +38,17 @@ int guarded(F&& f) {
     return fail(DM_ERR_ALLOC, "host allocation failed");
   } catch (const std::exception& e) {
     return fail(DM_ERR_ARG, e.what());
+  }
+}
+
+// Runs f on a second thread, or later on the caller (at get()) when no thread can be
+// started; the result and any exception come back through get().
+template <class F>
+std::future<void> run_beside(const F& f) {
+  try {
+    return std::async(std::launch::async, f);
+  } catch (const std::system_error&) {
+    return std::async(std::launch::deferred, f);
   }
 }
 
