@@ -642,6 +642,11 @@ def main():
                       "lanczos_fp64": True},
            "energy": e, "lanczos_steps": k,
            "lanczos_ms": round(lanczos_ms, 3),
+           # host wall time per phase of a timed step (medians): plan creation, Lanczos
+           # (synchronising), both environment updates (enqueued, not waited for)
+           "phase_ms": {"plan": round(1e3 * statistics.median(t[0] for t in host), 3),
+                        "lanczos": round(lanczos_ms, 3),
+                        "env_updates": round(1e3 * statistics.median(t[2] for t in host), 3)},
            "matvec_ms": round(mv_ms, 4), "matvec_gflops": round(mv_flops / mv_ms / 1e6, 2),
            "matvec_gflop": round(mv_flops / 1e9, 4),
            "roofline": roofline}
