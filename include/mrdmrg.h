@@ -156,6 +156,9 @@ int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* c,
                         const dm_mpo_site* w1, const dm_mpo_site* w2,
                         const void* L, const void* R, int32_t prec,
                         dm_stream stream, dm_heff_plan** out);
+/* Waits for the plan's creation work, then hands its device buffers back to the
+ * library's pool for reuse: work of the plan queued by heff_apply must have completed
+ * (synchronise its stream first; lanczos_ground returns synchronised). */
 void dm_heff_plan_destroy(dm_heff_plan* p);
 
 /* Number of complex elements of theta for this plan, and algorithmic flop counts of
