@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H_eff matvec GFLOP/s & Lanczos time at Ly=8 χ=3200: FP32/BF16x3 vs FP64"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA, MI355X
+VECTOR_TFLOPS = {"fp64": 78.6, "fp32": 157.3}                    # vector ALU, MI355X
 HBM_GBS = 8000.0
 
 
@@ -151,7 +152,7 @@ def copy_calibration(nbytes=1 << 30, reps=5):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ly8_chi3200_bf16x3_hbm_traffic.md")
-KERNEL_SOURCES = ["gemm_bf16x3.hip", "kernels.hip", "device.hpp", "internal.hpp"]
+KERNEL_SOURCES = ["gemm_bf16x3.hip", "gemm_presplit.hip", "kernels.hip", "device.hpp", "internal.hpp"]
 
 
 def measured_traffic(workload, pname):
@@ -174,72 +175,104 @@ def measured_traffic(workload, pname):
 
 
 def stage_rooflines(pk, plan, prec, pname, prof, nmv, workload):
-    """Roofline of each matvec stage from its in-run device time (HIP events on the
-    launch stream, averaged over the timed matvecs) and its algorithmic work.  A block
-    GEMM has two floors: its algorithmic flops at the matrix-core peak of its arithmetic
-    (BF16x3: the bf16 dense peak over the three bf16 products per real product) and its
-    algorithmic bytes at the HBM peak (each operand read once, the output written once:
-    L + theta -> X and Z + R -> theta', in the storage precision of each operand); the higher floor
-    is the binding roof, reported as `bound`.  The mixing is HBM-bound (read X once,
-    write Z once).  The dominant (longest) stage is the reported one; `traffic` = counted
-    HBM bytes per launch (profiles/) or null."""
+    """Roofline of each matvec kernel from its in-run device time (HIP events on the
+    launch stream, averaged over the sampled matvecs) and its algorithmic work.
+
+    Algorithmic bytes are those of the matvec's own operands only: L, R and the MPO
+    tensors W1, W2 read, theta read and theta' written, each once, in the precision it
+    is stored in (the L.theta GEMM reads the FP32 copy of theta in the low-precision
+    modes; BF16x3 writes theta' in FP64).  The intermediates X (L.theta) and Z (mixed)
+    are not algorithmic bytes: their traffic is overhead, visible as the ratio of the
+    counted HBM bytes (profiles/, when they match the kernel sources) to the algorithmic
+    ones.  Per kernel: L.theta GEMM = 8 flop per complex MAC of its task table over
+    L + theta bytes; (.).R GEMM over R + theta' bytes; MPO mixing over the W bytes (it
+    runs on the vector ALUs).  A kernel's bound is the roof its algorithmic work reaches
+    first (matrix cores for BF16x3: the bf16 dense peak over three bf16 products per real
+    product; HBM at 8 TB/s); `frac` is its achieved fraction of that roof."""
     eb = 16 if prec == pk.DM_FP64 else 8
     avg = [p / max(nmv, 1) for p in prof]
     gemm = {pk.DM_FP64: ("mrd::gemm_kernel<double, 0, false>", "mrd::gemm_kernel<double, 20, true>"),
             pk.DM_FP32: ("mrd::gemm_kernel<float, 0, false>", "mrd::gemm_kernel<float, 20, true>"),
-            pk.DM_BF16X3: ("mrd::gemm_bf3_kernel<0, 128, 64, 2, 2, false>",
-                           "mrd::gemm_bf3_kernel<148, 128, 32, 4, 1, true>")}[prec]
-    mixk = "mrd::mix_slab_kernel<double>" if prec == pk.DM_FP64 else "mrd::mix_slab_kernel<float>"
+            pk.DM_BF16X3: ("mrd::gemm_ps_kernel<128, 64, 2, 2, false, 0>",
+                           "mrd::gemm_ps_kernel<128, 32, 4, 1, true, 1>")}[prec]
+    mixk = {pk.DM_FP64: "mrd::mix_slab_kernel<double, double>",
+            pk.DM_FP32: "mrd::mix_slab_kernel<float, float>",
+            pk.DM_BF16X3: "mrd::mix_slab_kernel<float, __bf16>"}[prec]
+    redk = {pk.DM_FP64: "mrd::gemm_split_reduce_kernel<double, 20, mrd::GemmProb>",
+            pk.DM_FP32: "mrd::gemm_split_reduce_kernel<float, 20, mrd::GemmProb>",
+            pk.DM_BF16X3: "mrd::gemm_split_reduce_kernel<float, 144, mrd::PsProb>"}[prec]
     traffic = measured_traffic(workload, pname)
-    # matrix-core peak in algorithmic flops (BF16x3: three bf16 products per real product)
     hw = 3 if prec == pk.DM_BF16X3 else 1
     peak_alg = PEAK_TFLOPS[pname] / hw
     sz = plan.sizes
-    # BF16x3 (.).R writes theta' in FP64 itself (16 B per element)
-    eb_out = 16 if prec == pk.DM_BF16X3 else eb
-    gemm_bytes = [(sz["L"] + sz["theta"] + sz["X"]) * eb, None,
-                  (sz["Z"] + sz["R"]) * eb + sz["theta"] * eb_out]
+    w_bytes = 16 * (plan.w1.W.size + plan.w2.W.size)
+    th_in = sz["theta"] * eb
+    th_out = sz["theta"] * (16 if prec in (pk.DM_FP64, pk.DM_BF16X3) else 8)
+    rows = [(gemm[0], "L.theta block GEMM", plan.flops[0], sz["L"] * eb + th_in, "matrix"),
+            (mixk, "MPO mixing", plan.flops[1], w_bytes, "alu"),
+            (gemm[1], "(.).R block GEMM", plan.flops[2], sz["R"] * eb + th_out, "matrix"),
+            (redk, "(.).R K-split reduction", 0.0, 0, None)]
     stages = []
-    for i, (kern, what) in enumerate([(gemm[0], "L.theta block GEMM"), (mixk, "MPO mixing"),
-                                      (gemm[1], "(.).R block GEMM")]):
+    for i, (kern, what, flops, nbytes, unit) in enumerate(rows):
         t = avg[i] * 1e-3
-        if i == 1:
-            nbytes = (sz["X"] + sz["Z"]) * eb
-            ach = nbytes / t / 1e9
-            r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_GBS, "unit": "GB/s",
-                 "frac": round(ach / HBM_GBS, 4), "algorithmic_bytes": nbytes}
-        else:
-            flops, nbytes = plan.flops[i], gemm_bytes[i]
+        tr = traffic.get(kern)
+        counted = (tr["read_bytes"] + tr["write_bytes"]) if tr else None
+        r = {"kernel": f"{kern} ({what}, {pname})", "avg_launch_ms": round(avg[i], 4),
+             "algorithmic_flops": flops, "algorithmic_bytes": nbytes, "traffic": counted,
+             "traffic_ratio": round(counted / nbytes, 2) if (counted and nbytes) else None}
+        if tr:
+            r["traffic_read_write"] = [tr["read_bytes"], tr["write_bytes"]]
+        if unit == "matrix" and t > 0:
             t_mfma, t_hbm = flops / (peak_alg * 1e12), nbytes / (HBM_GBS * 1e9)
-            floors = {"mfma_floor_us": round(1e6 * t_mfma, 2), "hbm_floor_us": round(1e6 * t_hbm, 2),
+            tf = flops / t / 1e12
+            r.update({"bound": "mfma" if t_mfma >= t_hbm else "hbm",
+                      "mfma_floor_us": round(1e6 * t_mfma, 2), "hbm_floor_us": round(1e6 * t_hbm, 2),
                       "flop_per_byte": round(flops / nbytes, 1),
-                      "ridge_flop_per_byte": round(peak_alg * 1e12 / (HBM_GBS * 1e9), 1),
-                      "algorithmic_flops": flops, "algorithmic_bytes": nbytes}
+                      "ridge_flop_per_byte": round(peak_alg * 1e12 / (HBM_GBS * 1e9), 1)})
             if t_mfma >= t_hbm:
-                ach = flops / t / 1e12
-                r = {"bound": "mfma", "achieved": round(ach, 3), "peak": round(peak_alg, 1),
-                     "unit": "TFLOP/s", "frac": round(ach / peak_alg, 4)}
+                r.update({"achieved": round(tf, 3), "peak": round(peak_alg, 1), "unit": "TFLOP/s",
+                          "frac": round(tf / peak_alg, 4)})
             else:
                 ach = nbytes / t / 1e9
-                r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_GBS, 4)}
-            r.update(floors)
-            r["mfma_frac"] = round(flops / t / 1e12 / peak_alg, 4)
+                r.update({"achieved": round(ach, 1), "peak": HBM_GBS, "unit": "GB/s",
+                          "frac": round(ach / HBM_GBS, 4)})
+            r["mfma_frac"] = round(tf / peak_alg, 4)
             if hw > 1:
                 r["matrix_peak_note"] = (f"{PEAK_TFLOPS[pname]} TFLOP/s bf16 dense / {hw} bf16 products "
                                          "per algorithmic real product")
-        tr = traffic.get(kern)
-        r.update({"kernel": f"{kern} ({what}, {pname})", "avg_launch_ms": round(avg[i], 4),
-                  "traffic": (tr["read_bytes"] + tr["write_bytes"]) if tr else None})
-        if tr:
-            r["traffic_read_write"] = [tr["read_bytes"], tr["write_bytes"]]
+        elif unit == "alu" and t > 0:
+            peak_v = VECTOR_TFLOPS["fp64" if prec == pk.DM_FP64 else "fp32"]
+            tf = flops / t / 1e12
+            r.update({"bound": "alu", "achieved": round(tf, 3), "peak": peak_v, "unit": "TFLOP/s",
+                      "frac": round(tf / peak_v, 4)})
         stages.append(r)
     dom = max(range(3), key=lambda i: avg[i])
     out = dict(stages[dom])
     out["stages"] = stages
-    out["k_split_reduction_ms"] = round(avg[3], 4)
     out["profiled_matvecs"] = nmv  # HIP-event samples (every PROFILE_EVERY-th matvec)
     return out
+
+
+def matvec_roofline(pk, plan, prec, pname, mv_ms, stages):
+    """The whole matvec against the matrix-core roof: all its algorithmic flops over
+    L + R + W + theta + theta' bytes, and the counted HBM bytes of its kernels (when the
+    counters match the sources) over those algorithmic bytes."""
+    eb = 16 if prec == pk.DM_FP64 else 8
+    sz = plan.sizes
+    hw = 3 if prec == pk.DM_BF16X3 else 1
+    peak_alg = PEAK_TFLOPS[pname] / hw
+    nbytes = (sz["L"] + sz["R"] + sz["theta"]) * eb + 16 * (plan.w1.W.size + plan.w2.W.size) + \
+        sz["theta"] * (16 if prec in (pk.DM_FP64, pk.DM_BF16X3) else 8)
+    flops = sum(plan.flops)
+    tf = flops / (mv_ms * 1e-3) / 1e12
+    counted = [st["traffic"] for st in stages]
+    total = sum(counted) if all(c is not None for c in counted) else None
+    return {"algorithmic_flops": flops, "algorithmic_bytes": nbytes, "ms": round(mv_ms, 4),
+            "achieved": round(tf, 3), "peak": round(peak_alg, 1), "unit": "TFLOP/s",
+            "frac": round(tf / peak_alg, 4),
+            "mfma_floor_us": round(1e6 * flops / (peak_alg * 1e12), 2),
+            "hbm_floor_us": round(1e6 * nbytes / (HBM_GBS * 1e9), 2),
+            "traffic": total, "traffic_ratio": round(total / nbytes, 2) if total else None}
 
 
 def precision_report(pk, torch, inp, iters, stream, noise=1e-3, reps=3):
@@ -268,7 +301,10 @@ def precision_report(pk, torch, inp, iters, stream, noise=1e-3, reps=3):
                        torch.randn(gs.numel(), generator=g, dtype=torch.float64)).to(gs.device)
     warm = gs + noise * nz / torch.linalg.vector_norm(nz)
     warm = warm / torch.linalg.vector_norm(warm)
-    out = {"ground_state": {"energy": e_gs, "restarts": restarts, "residual": resid, "noise": noise}}
+    out = {"ground_state": {"energy": e_gs, "restarts": restarts, "residual": resid, "noise": noise,
+                            "reference": "the library's FP64 path (restarted Lanczos on the GPU); the "
+                                         "same gate against the FP64 CPU oracle's ground state of this "
+                                         "window runs in tests/test_gpu_gate_fullsize.py"}}
     for name, q in precs.items():
         plan = mk(q)
         ms, _, _ = matvec_time(pk, torch, inp, q, stream, plan=plan)
@@ -292,6 +328,17 @@ def precision_report(pk, torch, inp, iters, stream, noise=1e-3, reps=3):
         out[name]["cold_rel_energy_diff_vs_fp64"] = abs(out[name]["cold_energy"] - out["fp64"]["cold_energy"]) / \
             abs(out["fp64"]["cold_energy"])
     return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(wl, iters=30):
@@ -337,7 +384,7 @@ def cpu_baseline(wl, iters=30):
             flops += 8.0 * rb.shape[0] * rb.shape[1] * na
     cores = len(os.sched_getaffinity(0))
     return {"value": round(nmv[0] * flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"{iters}-step FP64 oracle Lanczos (numpy, per-block matmuls) of the same "
                       f"window, random environments of the exact block structure, {dt:.1f} s; "
                       f"block-GEMM flops only"}
@@ -633,6 +680,9 @@ def main():
     roofline = stage_rooflines(pk, plan, prec, args.prec, prof, nmv, args.workload)
     mv_ms, mv_flops, _ = matvec_time(pk, torch, inp, prec, stream)
     out = {"metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
+           "value_is": "algorithmic GFLOP of one bond update (host plan, 30-step Lanczos with one "
+                       "matvec per step plus the FP64 Rayleigh-quotient matvec, both environment "
+                       "updates) divided by its wall time; matvec_gflops is one heff_apply alone",
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": {pk.DM_FP64: "fp64", pk.DM_FP32: "fp32", pk.DM_BF16X3: "bf16x3"}[prec], "data": "synthetic",
@@ -649,7 +699,8 @@ def main():
                         "env_updates": round(1e3 * statistics.median(t[2] for t in host), 3)},
            "matvec_ms": round(mv_ms, 4), "matvec_gflops": round(mv_flops / mv_ms / 1e6, 2),
            "matvec_gflop": round(mv_flops / 1e9, 4),
-           "roofline": roofline}
+           "roofline": roofline,
+           "matvec_roofline": matvec_roofline(pk, plan, prec, args.prec, mv_ms, roofline["stages"])}
     if not args.no_fp64_compare:
         log("precision comparison (cold and warm start) ...")
         out["precisions"] = precision_report(pk, torch, inp, args.iters, stream)

@@ -225,7 +225,12 @@ int dm_env_flops(int32_t left, int32_t ly, const dm_bond* x, const dm_bond* y,
  * the block GEMMs).  At the first solve the GEMM problems of all instances are grouped
  * into buckets by output shape (rows <= 64 / > 64, columns <= 32 / <= 64 / > 64) and each
  * bucket is timed with every tile shape the kernels provide; the fastest is kept (set
- * MRDMRG_TUNE=0 to keep the plans' own shapes).  Tiles are issued longest first.  With
+ * MRDMRG_TUNE=0 to keep the plans' own shapes).  Chosen shapes are remembered in a text
+ * file keyed by (GPU architecture, precision, stage, bucket, log2 of the bucket's
+ * GFLOP): later batches of the same kind read them instead of timing.  The file is
+ * $MRDMRG_TUNE_CACHE, else $XDG_CACHE_HOME/mrdmrg/tile_shapes.txt, else
+ * ~/.cache/mrdmrg/tile_shapes.txt; MRDMRG_TUNE_CACHE=0 disables it.  Tiles are issued
+ * longest first.  With
  * MRDMRG_GRAPH=1 each Lanczos iteration of the whole batch is one HIP graph replay.
  * Plans must outlive the batch. */
 typedef struct dm_batch dm_batch;
@@ -242,6 +247,73 @@ int64_t dm_batch_info(const dm_batch* b, char* buf, int64_t len);
  * stopped, read from the device clock.  Synchronises. */
 int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t max_iter, double tol,
                            double* energies, int32_t* iters, double* done_us, dm_stream stream);
+
+/* ---- Two-site split (block SVD truncation) ------------------------------------------
+ * theta (device complex128, THETA layout of a, c, qs1, qs2) is a block-diagonal matrix
+ * over the charge of the middle bond, q(b) = q(a) + q(s1) (the Schmidt states carry
+ * (N, k), Sec. III C): M_b[(a, s1), (s2, c)].  Each M_b is factorised U S V^H in FP64 on
+ * the device (one-sided Jacobi, one workgroup per sector).  Kept: the chi largest
+ * singular values over all sectors (ties broken by sector charge, then rank within the
+ * sector), none <= cutoff, renormalised to a unit sum of squares.  The new bond b lists
+ * the sectors that keep at least one value, with that count as their dimension.
+ * move_right != 0: left = U (left-canonical A, SITE layout of a, b, qs1) and right =
+ * S V^H (SITE layout of b, c, qs2); move_right = 0: left = U S, right = V^H
+ * (right-canonical B).  Synchronises (the kept values are chosen on the host).  The
+ * split owns the new bond and both device tensors until dm_split_destroy, which
+ * requires the work that reads them to have completed.  DM_ERR_NONFINITE when no value
+ * exceeds the cutoff or a value is not finite. */
+typedef struct dm_split dm_split;
+int dm_theta_split(int32_t ly, const dm_bond* a, const dm_bond* c, const dm_charge qs1[2],
+                   const dm_charge qs2[2], const void* theta, int32_t chi, double cutoff,
+                   int32_t move_right, dm_stream stream, dm_split** out);
+/* The new bond: *nsec, then (when q and dim are not NULL, room for *nsec each) its
+ * charges and dimensions. */
+int dm_split_bond(const dm_split* sp, int32_t* nsec, dm_charge* q, int32_t* dim);
+/* Device pointers and element counts of the two site tensors (valid until destroyed). */
+int dm_split_tensors(const dm_split* sp, const void** left, int64_t* nleft, const void** right,
+                     int64_t* nright);
+/* Kept Schmidt values (normalised), sector by sector in bond order, descending within a
+ * sector (sum of the bond's dimensions values), and the discarded weight
+ * 1 - sum(kept^2) / sum(all^2).  Either pointer may be NULL. */
+int dm_split_schmidt(const dm_split* sp, double* values, double* discarded);
+/* Copies the two site tensors into caller buffers (nleft / nright complex128 elements),
+ * stream-ordered. */
+int dm_split_copy(const dm_split* sp, void* left, void* right, dm_stream stream);
+void dm_split_destroy(dm_split* sp);
+
+/* ---- Finite two-site DMRG on the device ------------------------------------------------
+ * An MPS of n >= 2 orbitals held by the library: bonds[0..n] (bond 0 the vacuum charge,
+ * bond n the total charge), local charges qs[2 i], qs[2 i + 1] of orbital i, and site
+ * tensors (device complex128, SITE layout of bonds[i], bonds[i+1], qs of i), copied.
+ * Synchronises. */
+typedef struct dm_mps dm_mps;
+int dm_mps_create(int32_t ly, int32_t n, const dm_bond* bonds, const dm_charge* qs,
+                  const void* const* tensors, dm_stream stream, dm_mps** out);
+void dm_mps_destroy(dm_mps* m);
+/* Bond i (0..n): *nsec, then charges and dimensions as dm_split_bond. */
+int dm_mps_bond(const dm_mps* m, int32_t i, int32_t* nsec, dm_charge* q, int32_t* dim);
+/* Device pointer and element count of site tensor i (valid until the next sweep). */
+int dm_mps_tensor(const dm_mps* m, int32_t i, const void** data, int64_t* nelem);
+/* Copies site tensor i into a caller buffer of nelem complex128 elements, stream-ordered. */
+int dm_mps_copy(const dm_mps* m, int32_t i, void* dst, dm_stream stream);
+/* Schmidt values of bond i from its last split (layout as dm_split_schmidt): *count,
+ * then the values when `values` is not NULL. */
+int dm_mps_schmidt(const dm_mps* m, int32_t i, double* values, int64_t* count);
+/* Two-site DMRG sweeps (the paper's (i)DMRG relies on them, Sec. I, III A): the MPS must
+ * be right-canonical from orbital 1 on.  One sweep moves right over bonds (0,1) ..
+ * (n-2, n-1) and back left; at every bond the two-site tensor is the start vector of
+ * lanczos_ground (max_iter steps, the plan in precision prec), its Ritz vector is split by
+ * dm_theta_split (chi, cutoff; left-canonical behind a right move, right-canonical behind
+ * a left move) and the environment behind the move is updated (FP64).  w: the n MPO
+ * site tensors (w[0] with one left state, w[n-1] with one right state, the boundary
+ * states of eq. MPO).  energies[s]: the energy of the last bond update of sweep s.
+ * Synchronises. */
+int dm_dmrg_sweeps(dm_mps* psi, const dm_mpo_site* w, int32_t nsweeps, int32_t chi,
+                   int32_t max_iter, double cutoff, int32_t prec, double* energies,
+                   dm_stream stream);
+/* Entanglement spectrum of one cut (Sec. III C): energies[i] = -2 ln lambda_i (may be
+ * NULL) and the entropy -sum lambda^2 ln lambda^2 of count positive Schmidt values. */
+int dm_entanglement(const double* values, int64_t count, double* entropy, double* energies);
 
 /* ---- Hofstadter MPO ----------------------------------------------------------------
  * Builds the exact MPO of eq. H (Sec. III A) on an Ly x Lx cylinder, open in x and

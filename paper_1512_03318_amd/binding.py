@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -79,6 +80,22 @@ _sigs = {
     "dm_batch_info": (_i64, [_vp, C.c_char_p, _i64]),
     "lanczos_ground_batched": (_i32, [_vp, C.POINTER(_vp), _i32, _f64, C.POINTER(_f64),
                                       C.POINTER(_i32), C.POINTER(_f64), _vp]),
+    "dm_theta_split": (_i32, [_i32, C.POINTER(DmBond), C.POINTER(DmBond), C.POINTER(DmCharge),
+                              C.POINTER(DmCharge), _vp, _i32, _f64, _i32, _vp, C.POINTER(_vp)]),
+    "dm_split_bond": (_i32, [_vp, C.POINTER(_i32), C.POINTER(DmCharge), C.POINTER(_i32)]),
+    "dm_split_tensors": (_i32, [_vp, C.POINTER(_vp), C.POINTER(_i64), C.POINTER(_vp), C.POINTER(_i64)]),
+    "dm_split_schmidt": (_i32, [_vp, C.POINTER(_f64), C.POINTER(_f64)]),
+    "dm_split_copy": (_i32, [_vp, _vp, _vp, _vp]),
+    "dm_split_destroy": (None, [_vp]),
+    "dm_mps_create": (_i32, [_i32, _i32, C.POINTER(DmBond), C.POINTER(DmCharge), C.POINTER(_vp), _vp,
+                             C.POINTER(_vp)]),
+    "dm_mps_destroy": (None, [_vp]),
+    "dm_mps_bond": (_i32, [_vp, _i32, C.POINTER(_i32), C.POINTER(DmCharge), C.POINTER(_i32)]),
+    "dm_mps_tensor": (_i32, [_vp, _i32, C.POINTER(_vp), C.POINTER(_i64)]),
+    "dm_mps_copy": (_i32, [_vp, _i32, _vp, _vp]),
+    "dm_mps_schmidt": (_i32, [_vp, _i32, C.POINTER(_f64), C.POINTER(_i64)]),
+    "dm_dmrg_sweeps": (_i32, [_vp, C.POINTER(DmMpoSite), _i32, _i32, _i32, _f64, _i32, C.POINTER(_f64), _vp]),
+    "dm_entanglement": (_i32, [C.POINTER(_f64), _i64, C.POINTER(_f64), C.POINTER(_f64)]),
     "dm_mpo_hofstadter": (_i32, [_i32, _i32, _i32, _i32, _f64, _f64, _i32, C.POINTER(_vp)]),
     "dm_mpo_n_sites": (_i32, [_vp]),
     "dm_mpo_site_get": (_i32, [_vp, _i32, C.POINTER(DmMpoSite)]),
@@ -223,6 +240,9 @@ class HeffPlan:
                                        C.byref(w2.c), _ptr(L), _ptr(R), prec, _stream(stream),
                                        C.byref(h)))
         self.h = h
+        # the destructor keeps its own reference: at interpreter exit the module's
+        # globals (``lib``) may already be cleared when this object is collected
+        self._destroy = lib.dm_heff_plan_destroy
         n = _i64()
         fl = (_f64 * 3)()
         _check(lib.dm_heff_info(h, C.byref(n), fl))
@@ -245,8 +265,9 @@ class HeffPlan:
         return list(ms), n.value
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib.dm_heff_plan_destroy(self.h)
+        # at interpreter exit the process's device memory goes with it: no library call
+        if getattr(self, "h", None) and not sys.is_finalizing():
+            self._destroy(self.h)
             self.h = None
 
 
@@ -286,6 +307,7 @@ class Batch:
         h = _vp()
         _check(lib.dm_batch_create(len(self.plans), arr, _stream(stream), C.byref(h)))
         self.h = h
+        self._destroy = lib.dm_batch_destroy
 
     def info(self) -> str:
         """Tile shape chosen per problem bucket (after the first solve)."""
@@ -295,8 +317,9 @@ class Batch:
         return buf.value.decode()
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib.dm_batch_destroy(self.h)
+        # at interpreter exit the process's device memory goes with it: no library call
+        if getattr(self, "h", None) and not sys.is_finalizing():
+            self._destroy(self.h)
             self.h = None
 
 
@@ -317,6 +340,7 @@ class HofstadterMPO:
         h = _vp()
         _check(lib.dm_mpo_hofstadter(Ly, Lx, p, q, t, V, 0 if basis == "mixed" else 1, C.byref(h)))
         self.h = h
+        self._destroy = lib.dm_mpo_destroy
         self.ly = Ly if basis == "mixed" else 1
         self.n_sites = lib.dm_mpo_n_sites(h)
 
@@ -331,6 +355,105 @@ class HofstadterMPO:
         return MpoSite(W, ql, qr, qs)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib.dm_mpo_destroy(self.h)
+        # at interpreter exit the process's device memory goes with it: no library call
+        if getattr(self, "h", None) and not sys.is_finalizing():
+            self._destroy(self.h)
             self.h = None
+
+
+def _bond_of(getter, *args) -> dict:
+    n = _i32()
+    _check(getter(*args, C.byref(n), None, None))
+    q = (DmCharge * max(n.value, 1))()
+    d = (_i32 * max(n.value, 1))()
+    _check(getter(*args, C.byref(n), q, d))
+    return {(q[i].n, q[i].k): d[i] for i in range(n.value)}
+
+
+class Split:
+    """dm_split: theta split at its middle bond by the block SVD truncation.
+    .bond: {(N, k): dim} of the new bond; .left / .right: device complex128 tensors in
+    the SITE layouts (copies); .schmidt: kept values; .discarded: discarded weight."""
+
+    def __init__(self, ly, a: Bond, c: Bond, qs1, qs2, theta, chi, cutoff=1e-14, move_right=True,
+                 stream=None):
+        import torch
+        h = _vp()
+        q1 = (DmCharge * 2)(DmCharge(*qs1[0]), DmCharge(*qs1[1]))
+        q2 = (DmCharge * 2)(DmCharge(*qs2[0]), DmCharge(*qs2[1]))
+        _check(lib.dm_theta_split(ly, C.byref(a.c), C.byref(c.c), q1, q2, _ptr(theta), int(chi), float(cutoff),
+                                  1 if move_right else 0, _stream(stream), C.byref(h)))
+        try:
+            self.bond = _bond_of(lib.dm_split_bond, h)
+            nl, nr = _i64(), _i64()
+            _check(lib.dm_split_tensors(h, None, C.byref(nl), None, C.byref(nr)))
+            dev = theta.device
+            self.left = torch.empty(nl.value, dtype=torch.complex128, device=dev)
+            self.right = torch.empty(nr.value, dtype=torch.complex128, device=dev)
+            _check(lib.dm_split_copy(h, _ptr(self.left), _ptr(self.right), _stream(stream)))
+            torch.cuda.synchronize(dev)
+            vals = (_f64 * max(1, sum(self.bond.values())))()
+            disc = _f64()
+            _check(lib.dm_split_schmidt(h, vals, C.byref(disc)))
+            self.schmidt = np.array(vals[:sum(self.bond.values())])
+            self.discarded = disc.value
+        finally:
+            lib.dm_split_destroy(h)
+
+
+class MPS:
+    """dm_mps: an MPS held by the library (site tensors on the device)."""
+
+    def __init__(self, ly, bonds, qs, tensors, stream=None):
+        self.ly, self.n = ly, len(tensors)
+        self._bonds = [Bond(b) for b in bonds]
+        arr = (DmBond * len(self._bonds))(*[b.c for b in self._bonds])
+        q = _charges([x for pair in qs for x in pair])
+        ptrs = (_vp * self.n)(*[t.data_ptr() for t in tensors])
+        h = _vp()
+        _check(lib.dm_mps_create(ly, self.n, arr, q, ptrs, _stream(stream), C.byref(h)))
+        self.h = h
+        self._destroy = lib.dm_mps_destroy
+
+    def bond(self, i) -> dict:
+        return _bond_of(lib.dm_mps_bond, self.h, i)
+
+    def tensor(self, i, device="cuda"):
+        import torch
+        n = _i64()
+        _check(lib.dm_mps_tensor(self.h, i, None, C.byref(n)))
+        out = torch.empty(n.value, dtype=torch.complex128, device=device)
+        _check(lib.dm_mps_copy(self.h, i, _ptr(out), _stream(None)))
+        torch.cuda.synchronize()
+        return out
+
+    def schmidt(self, i) -> np.ndarray:
+        n = _i64()
+        _check(lib.dm_mps_schmidt(self.h, i, None, C.byref(n)))
+        vals = (_f64 * max(1, n.value))()
+        _check(lib.dm_mps_schmidt(self.h, i, vals, C.byref(n)))
+        return np.array(vals[:n.value])
+
+    def __del__(self):
+        # at interpreter exit the process's device memory goes with it: no library call
+        if getattr(self, "h", None) and not sys.is_finalizing():
+            self._destroy(self.h)
+            self.h = None
+
+
+def dmrg_sweeps(psi: MPS, sites, nsweeps, chi, max_iter=30, cutoff=1e-14, prec=DM_FP64, stream=None):
+    """Energies after each of nsweeps two-site sweeps (dm_dmrg_sweeps)."""
+    arr = (DmMpoSite * len(sites))(*[s.c for s in sites])
+    e = (_f64 * nsweeps)()
+    _check(lib.dm_dmrg_sweeps(psi.h, arr, nsweeps, chi, max_iter, cutoff, prec, e, _stream(stream)))
+    return list(e)
+
+
+def entanglement(values):
+    """(entropy, entanglement energies -2 ln lambda) of one cut's Schmidt values."""
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    ent = _f64()
+    out = np.zeros(max(1, v.size))
+    _check(lib.dm_entanglement(v.ctypes.data_as(C.POINTER(C.c_double)), v.size, C.byref(ent),
+                               out.ctypes.data_as(C.POINTER(C.c_double))))
+    return ent.value, out[:v.size]

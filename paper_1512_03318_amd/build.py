@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrdmrg.so")
-SOURCES = ["kernels.hip", "gemm_bf16x3.hip", "lanczos.hip", "api.cpp", "runtime.cpp", "plan.cpp", "mpo.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "gemm_bf16x3.hip", "gemm_presplit.hip", "lanczos.hip", "api.cpp", "runtime.cpp", "plan.cpp", "mpo.cpp", "batch.cpp",
+           "svd.hip", "split.cpp", "sweep.cpp"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

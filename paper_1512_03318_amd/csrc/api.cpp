@@ -14,6 +14,9 @@
 
 using namespace mrd;
 
+static int lanczos_ground_impl(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double tol,
+                               double* energy, int32_t* iters, dm_stream stream);
+
 // =====================================================================================
 // Layout query
 // =====================================================================================
@@ -140,6 +143,46 @@ static void build_heff_tables(dm_heff_plan& p) {
     p.zoff[ci2] = p.ztotal;
     p.ztotal += (int64_t)rows * p.R.P.cols[ci2];
   }
+  // BF16x3 pre-split operands (bf16 planes, k padded to a multiple of 8): L per ket
+  // sector a (M_a x m_a), theta^T per a (N_a x m_a), Z and R per output sector c'
+  // (rows x K with K the R panel width).
+  if (p.prec == DM_BF16X3) {
+    auto r8 = [](int64_t k) { return (k + 7) / 8 * 8; };
+    p.lsoff.assign(a.size(), 0);
+    p.thsoff.assign(a.size(), 0);
+    p.zsoff.assign(c.size(), 0);
+    p.rsoff.assign(c.size(), 0);
+    p.zkp.assign(c.size(), 0);
+    p.ls_total = p.ths_total = p.zs_total = p.rs_total = 0;
+    for (int ai = 0; ai < a.size(); ++ai) {
+      const int64_t kp = r8(a.dim[ai]);
+      p.lsoff[ai] = p.ls_total;
+      p.ls_total += 4 * (int64_t)p.L.P.rows[ai] * kp;
+      p.thsoff[ai] = p.ths_total;
+      p.ths_total += 4 * (int64_t)p.th.P.cols[ai] * kp;
+      if (p.L.P.rows[ai] > 0)
+        p.lsplit.push_back({p.L.P.off[ai], p.lsoff[ai], a.dim[ai], p.L.P.rows[ai], a.dim[ai], (int32_t)kp, 0,
+                            (int32_t)((int64_t)p.L.P.rows[ai] * kp), 0});
+      if (p.th.P.cols[ai] > 0)
+        p.thsplit.push_back({p.th.P.off[ai], p.thsoff[ai], p.th.P.cols[ai], a.dim[ai], p.th.P.cols[ai],
+                             (int32_t)kp, 1, (int32_t)((int64_t)p.th.P.cols[ai] * kp), 0});
+    }
+    for (int ci2 = 0; ci2 < c.size(); ++ci2) {
+      const int K = p.R.P.cols[ci2];
+      const int64_t kp = std::max<int64_t>(8, r8(K));  // an empty R panel keeps zero planes
+      p.zkp[ci2] = (int32_t)kp;
+      p.zsoff[ci2] = p.zs_total;
+      p.zs_total += 4 * (int64_t)p.zrows[ci2] * kp;
+      p.rsoff[ci2] = p.rs_total;
+      p.rs_total += 4 * (int64_t)c.dim[ci2] * kp;
+      if (K > 0)
+        p.rsplit.push_back({p.R.P.off[ci2], p.rsoff[ci2], K, c.dim[ci2], K, (int32_t)kp, 0,
+                            (int32_t)((int64_t)c.dim[ci2] * kp), 0});
+    }
+    p.lsplit_items = split_layout(p.lsplit);
+    p.rsplit_items = split_layout(p.rsplit);
+    p.thsplit_items = split_layout(p.thsplit);
+  }
   // (.)R stage, one problem per output sector c':
   //   theta'[(s12', a'), c'] = Z_{c'} (M x K) . Rpanel_{c'}^T (K x m_c'), K = R panel width,
   // rows scattered to the theta blocks through the row table.  K-split over workgroups.
@@ -178,6 +221,50 @@ static void build_heff_tables(dm_heff_plan& p) {
   // The GEMM stage tables are built and bounds-checked on a second thread while this one
   // builds the mixing tables (disjoint members of the plan; an exception there is
   // rethrown by get()).
+  // The matvec stages on pre-split operands (BF16x3): same problems, tiles and K splits
+  // as the FP32-operand BF16x3 stages above.
+  auto build_ps = [&] {
+    PsStage& q1 = p.s1p;
+    q1.cout = 0;
+    q1.tile_m = 128;
+    q1.tile_n = 64;
+    q1.split = false;
+    for (int ai = 0; ai < a.size(); ++ai) {
+      const int M = p.L.P.rows[ai], N = p.th.P.cols[ai], K = a.dim[ai];
+      if (M == 0 || N == 0) continue;
+      const int kp = (K + 7) / 8 * 8;
+      q1.probs.push_back({p.lsoff[ai], p.thsoff[ai], (int64_t)M * kp, (int64_t)N * kp, p.xoff[ai], M, N, kp,
+                          N, -1, 1, -1, 0});
+      add_ps_tiles(q1, (int32_t)q1.probs.size() - 1);
+      q1.flops += 8.0 * M * N * K;
+    }
+    PsStage& q4 = p.s4p;
+    q4.cout = 1;
+    q4.tile_m = 128;
+    q4.tile_n = 32;
+    q4.split = true;
+    q4.split_min = 12;
+    for (int ci2 = 0; ci2 < c.size(); ++ci2) {
+      const int M = p.zrows[ci2], N = c.dim[ci2], K = p.R.P.cols[ci2], kp = p.zkp[ci2];
+      if (M == 0) continue;
+      const int32_t rm = (int32_t)q4.rows.size();
+      for (int s12p = 0; s12p < 4; ++s12p) {
+        const int aip = zap[ci2][s12p];
+        if (aip < 0) continue;
+        const int64_t base = p.th.P.off[aip] + p.th.coff[aip][s12p];
+        for (int r = 0; r < a.dim[aip]; ++r) q4.rows.push_back(base + (int64_t)r * p.th.P.cols[aip]);
+      }
+      q4.probs.push_back({p.zsoff[ci2], p.rsoff[ci2], (int64_t)M * kp, (int64_t)N * kp, 0, M, N, kp, 0, rm,
+                          1, -1, 0});
+      add_ps_tiles(q4, (int32_t)q4.probs.size() - 1);
+      q4.flops += 8.0 * M * N * K;
+    }
+    validate(q1, p.ls_total, p.ths_total, p.xtotal);
+    validate(q4, p.zs_total, p.rs_total, p.n());
+    validate(p.lsplit, p.L.P.total, p.ls_total);
+    validate(p.rsplit, p.R.P.total, p.rs_total);
+    validate(p.thsplit, p.n(), p.ths_total);
+  };
   const bool bf3 = p.prec == DM_BF16X3;
   auto gemm_tables = run_beside([&] {
     build_s1(p.s1, bf3);
@@ -188,6 +275,7 @@ static void build_heff_tables(dm_heff_plan& p) {
     validate(p.s4, p.ztotal, p.R.P.total, p.n());
     validate(p.s1f, p.L.P.total, p.n(), p.xtotal);
     validate(p.s4f, p.ztotal, p.R.P.total, p.n());
+    if (bf3) build_ps();
   });
   // two-site MPO W12[w, s12', s12, w''] = sum_w' W1[w, s1', s1, w'] W2[w', s2', s2, w'']
   std::vector<std::complex<double>> w12((size_t)dl * 16 * dr);
@@ -227,6 +315,9 @@ static void build_heff_tables(dm_heff_plan& p) {
     for (int w = 0; w < dl; ++w) a_of[(size_t)aip * dl + w] = a.find(qsub(a.q[aip], p.w1.ql[w], ly));
   MixStage& mx = p.mix;
   std::vector<int64_t> task_key;  // (a', c) slab of each task
+  // BF16x3: the same tasks writing Z split into bf16 planes (pre-split (.).R operand)
+  const bool presplit = p.prec == DM_BF16X3;
+  std::vector<MixTask> ptasks;
   for (int ci2 = 0; ci2 < c.size(); ++ci2) {
     const int Kc = p.R.P.cols[ci2];
     for (int s12p = 0; s12p < 4; ++s12p) {
@@ -254,6 +345,14 @@ static void build_heff_tables(dm_heff_plan& p) {
         mx.flops += 8.0 * tk.nsrc * tk.rows * tk.cols;
         mx.tasks.push_back(tk);
         task_key.push_back(((int64_t)aip << 32) | (uint32_t)ci);
+        if (presplit) {
+          MixTask pt = tk;
+          const int kpz = p.zkp[ci2];
+          pt.dst = p.zsoff[ci2] + (int64_t)zroff[ci2][s12p] * kpz + p.R.coff[ci2 * dr + wpp];
+          pt.ld_dst = kpz;
+          pt.pstride = (int32_t)((int64_t)p.zrows[ci2] * kpz);
+          ptasks.push_back(pt);
+        }
       }
     }
   }
@@ -267,15 +366,23 @@ static void build_heff_tables(dm_heff_plan& p) {
     auto slab = [&](int64_t key) { return (size_t)(key >> 32) * nc + (size_t)(uint32_t)key; };
     for (int64_t k : task_key) ++start[slab(k) + 1];
     for (size_t i = 1; i < start.size(); ++i) start[i] += start[i - 1];
-    std::vector<MixTask> sorted(nt);
+    std::vector<MixTask> sorted(nt), psorted(presplit ? nt : 0);
     std::vector<int64_t> key(nt);
     for (size_t i = 0; i < nt; ++i) {
       const int32_t d = start[slab(task_key[i])]++;
       sorted[d] = mx.tasks[i];
+      if (presplit) psorted[d] = ptasks[i];
       key[d] = task_key[i];
     }
     mx.tasks.swap(sorted);
+    ptasks.swap(psorted);
     task_key.swap(key);
+  }
+  if (presplit) {
+    p.mixp.tasks = ptasks;
+    p.mixp.srcs = mx.srcs;
+    p.mixp.flops = mx.flops;
+    mix_to_slabs(p.mixp, task_key, 8, 20480);
   }
   // slab form with about 20 KB of LDS per workgroup (several workgroups per CU keep
   // enough loads in flight; measured best between 12 and 32 KB at Ly=8, chi=3200)
@@ -311,6 +418,7 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       throw DmError{DM_ERR_ARG, "null environment"};
     build_heff_tables(*p);  // also validates the GEMM stages
     validate(p->mix, p->xtotal, p->ztotal);
+    if (prec == DM_BF16X3) validate(p->mixp, p->xtotal, p->zs_total);
     hipStream_t s = (hipStream_t)stream;
     {
       TableUpload up;
@@ -319,6 +427,12 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       up.add(p->s1f);
       up.add(p->s4f);
       up.add(p->mix);
+      up.add(p->s1p);
+      up.add(p->s4p);
+      up.add(p->mixp);
+      up.add(p->lsplit, &p->d_lsplit);
+      up.add(p->rsplit, &p->d_rsplit);
+      up.add(p->thsplit, &p->d_thsplit);
       p->dTables = up.commit(s);
     }
     HIPCHK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
@@ -337,6 +451,28 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       stage_in(R, p->dR64, p->R.P.total, DM_FP64, s);
       p->dTin = dev_alloc(p->n() * eb);
       p->dTout = dev_alloc(p->n() * eb);
+    }
+    {
+      // BF16x3 matvec on pre-split operands with MRDMRG_PRESPLIT=1 (otherwise the
+      // kernels split FP32 operands while staging them)
+      const char* e = getenv("MRDMRG_PRESPLIT");
+      p->presplit = prec == DM_BF16X3 && e && e[0] == '1';
+    }
+    if (p->presplit) {
+      // pre-split L and R (once per plan), theta^T (per matvec) and the split Z; pad
+      // columns stay zero: the L and R splits write them, Z's are cleared here and never
+      // written by the mixing
+      p->dLs = dev_alloc(p->ls_total * 2);
+      p->dRs = dev_alloc(p->rs_total * 2);
+      p->dThs = dev_alloc(p->ths_total * 2);
+      p->dZs = dev_alloc(p->zs_total * 2);
+      p->dSplitP = dev_alloc(p->s4p.nslots * p->s4p.slot_elems() * 8);
+      if (p->zs_total) HIPCHK(hipMemsetAsync(p->dZs, 0, p->zs_total * 2, s));
+      if (p->rs_total) HIPCHK(hipMemsetAsync(p->dRs, 0, p->rs_total * 2, s));
+      HIPCHK(launch_split(p->d_lsplit, (int32_t)p->lsplit.size(), p->lsplit_items, (const double*)L,
+                          (__bf16*)p->dLs, s));
+      HIPCHK(launch_split(p->d_rsplit, (int32_t)p->rsplit.size(), p->rsplit_items, (const double*)R,
+                          (__bf16*)p->dRs, s));
     }
     {
       // One Lanczos step per HIP graph replay is available but off by default: on
@@ -416,6 +552,21 @@ void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStrea
     mark(4);
     return;
   }
+  if (p->prec == DM_BF16X3 && p->presplit) {
+    // theta split into bf16 planes (transposed per panel: the L.theta GEMM's B operand),
+    // both block GEMMs on pre-split operands, theta' written in FP64 by the (.).R stage
+    HIPCHK(launch_split(p->d_thsplit, (int32_t)p->thsplit.size(), p->thsplit_items, (const double*)theta,
+                        (__bf16*)p->dThs, s, skip));
+    mark(0);
+    HIPCHK(launch_gemm_ps(p->s1p, (const __bf16*)p->dLs, (const __bf16*)p->dThs, p->dX, nullptr, s, skip));
+    mark(1);
+    HIPCHK(launch_mix_split(p->mixp, (const float*)p->dX, (__bf16*)p->dZs, s, skip));
+    mark(2);
+    HIPCHK(launch_gemm_ps(p->s4p, (const __bf16*)p->dZs, (const __bf16*)p->dRs, theta_out, (float*)p->dSplitP,
+                          s, skip, [&] { mark(3); }));
+    mark(4);
+    return;
+  }
   // theta in: an FP32 copy; theta' out: BF16x3 stages write FP64 themselves (the FP32
   // results widened as they are stored), FP32 stages through an FP32 copy
   const bool direct = p->prec == DM_BF16X3;
@@ -458,7 +609,15 @@ extern "C" int dm_heff_profile_read(dm_heff_plan* p, double ms[4], int64_t* matv
   });
 }
 
+static int heff_apply_impl(dm_heff_plan* p, const void* theta, void* theta_out, dm_stream stream);
+
 extern "C" int heff_apply(dm_heff_plan* p, const void* theta, void* theta_out, dm_stream stream) {
+  const int rc = heff_apply_impl(p, theta, theta_out, stream);
+  if (rc != DM_OK) drain(stream);  // no queued work outlives the error
+  return rc;
+}
+
+static int heff_apply_impl(dm_heff_plan* p, const void* theta, void* theta_out, dm_stream stream) {
   return guarded([&] {
     if (!p) throw DmError{DM_ERR_ARG, "null plan"};
     if (p->n() > 0 && (!theta || !theta_out)) throw DmError{DM_ERR_ARG, "null theta"};
@@ -500,7 +659,9 @@ void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
   if (relayout) {
     std::vector<LzInst> I(1);
     I[0] = LzInst{p->dV, p->dW, p->dVcur, p->dPart, nullptr, nullptr, p->dState, n, n};
-    I[0].tin = p->prec == DM_FP64 ? nullptr : (float*)p->dTin;  // v_j also written in FP32
+    // v_j also written in FP32 when the matvec reads an FP32 copy (a BF16x3 plan on
+    // pre-split operands splits v_j itself)
+    I[0].tin = p->staged_in() ? (float*)p->dTin : nullptr;
     p->lzg = lz_layout(I, p->Vcap - 1);
     *p->hInst = I[0];
   }
@@ -515,12 +676,21 @@ void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
 // the step index; j + 1 (or 0 for a step captured once for every replay) only bounds
 // the Krylov vector count so the projection kernels can be sized to it.
 static void lanczos_step(dm_heff_plan* p, hipStream_t s, bool capturing, int32_t j) {
-  heff_run(p, p->dVcur, p->dW, s, false, &p->dState->stop, capturing, p->prec != DM_FP64);
+  heff_run(p, p->dVcur, p->dW, s, false, &p->dState->stop, capturing, p->staged_in());
   HIPCHK(lz_launch_step_tail(p->dInst, p->lzg, capturing ? 0 : j + 1, s));
 }
 
 extern "C" int lanczos_ground(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double tol,
                               double* energy, int32_t* iters, dm_stream stream) {
+  // an error after work was queued returns only once that work has drained, so that no
+  // kernel of the solve can still run when the caller reacts (frees buffers, exits)
+  const int rc = lanczos_ground_impl(p, theta_inout, max_iter, tol, energy, iters, stream);
+  if (rc != DM_OK && p) drain(stream);
+  return rc;
+}
+
+static int lanczos_ground_impl(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double tol,
+                               double* energy, int32_t* iters, dm_stream stream) {
   return guarded([&] {
     if (!p || !energy || !iters) throw DmError{DM_ERR_ARG, "null argument"};
     if (max_iter < 1 || max_iter > LZ_MAX) throw DmError{DM_ERR_ARG, "max_iter must be in 1..64"};
@@ -848,34 +1018,67 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
   return ep;
 }
 
-// Runs T1 -> mix -> T3 with stream-ordered scratch, FP64 or FP32 arithmetic.
-// Runs T1 -> mix -> T3, stream-ordered (no host wait): tables and scratch come from
-// the caching pools and are handed back for reuse once the stream has passed them.
-void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64_t nsite,
-             void* out, int64_t nout, int prec, hipStream_t s) {
+// Device scratch of one environment update: blocks from the caching pool, handed back
+// in stream order (run_env), or consecutive pieces of one fixed region that the caller
+// owns.
+struct EnvScratch {
+  char* base = nullptr;  // fixed region, or null for the pool
+  size_t cap = 0, used = 0;
+  std::vector<void*> pooled;
+  static size_t align(size_t b) { return (b + 255) & ~size_t(255); }
+  void* get(size_t bytes) {
+    if (!base) {
+      void* q = dev_alloc(bytes);
+      pooled.push_back(q);
+      return q;
+    }
+    if (bytes == 0) return nullptr;
+    const size_t off = align(used);
+    if (off + bytes > cap) throw DmError{DM_ERR_ALLOC, "environment update scratch exceeds its region"};
+    used = off + bytes;
+    return base + off;
+  }
+  void release(hipStream_t s) {
+    for (void* q : pooled) dev_free_after(q, s);
+    pooled.clear();
+  }
+};
+
+// Bytes of fixed-region scratch run_env takes (every piece 256-byte aligned).
+size_t env_scratch_bytes(const EnvPlan& ep, size_t table_bytes, int64_t nenv, int64_t nsite,
+                         int64_t nout, int prec) {
   const size_t eb = elem_bytes(prec);
-  std::vector<void*> scratch;
-  auto alloc = [&](size_t bytes) {
-    void* q = dev_alloc(bytes);
-    scratch.push_back(q);
-    return q;
-  };
+  size_t b = EnvScratch::align(table_bytes) + EnvScratch::align(ep.t1total * eb) +
+             EnvScratch::align(ep.t2total * eb);
+  if (prec != DM_FP64)
+    b += EnvScratch::align(nenv * eb) + EnvScratch::align(nsite * eb) + EnvScratch::align(nout * eb);
+  return b;
+}
+
+// Runs T1 -> mix -> T3, stream-ordered (no host wait), FP64 or FP32 storage.  Tables
+// and intermediates come from `sc`: from the caching pools (handed back for reuse once
+// the stream has passed them), or from a fixed region (tables copied from pageable host
+// memory, which the copy has consumed when it returns).
+void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64_t nsite,
+             void* out, int64_t nout, int prec, hipStream_t s, EnvScratch& sc) {
+  const size_t eb = elem_bytes(prec);
   try {
     TableUpload up;
     up.add(ep.t1);
     up.add(ep.t3);
     up.add(ep.mix);
-    scratch.push_back(up.commit(s));
-    void* t1 = alloc(ep.t1total * eb);
-    void* t2 = alloc(ep.t2total * eb);
+    if (sc.base) up.commit_pageable(sc.get(up.total), s);
+    else sc.pooled.push_back(up.commit(s));
+    void* t1 = sc.get(ep.t1total * eb);
+    void* t2 = sc.get(ep.t2total * eb);
     if (prec == DM_FP64) {
       HIPCHK(launch_gemm<double>(ep.t1, (const double*)env, (const double*)site, (double*)t1, nullptr, s));
       HIPCHK(launch_mix<double>(ep.mix, (const double*)t1, (double*)t2, s));
       HIPCHK(launch_gemm<double>(ep.t3, (const double*)site, (const double*)t2, (double*)out, nullptr, s));
     } else {
-      void* e32 = alloc(nenv * eb);
-      void* s32 = alloc(nsite * eb);
-      void* o32 = alloc(nout * eb);
+      void* e32 = sc.get(nenv * eb);
+      void* s32 = sc.get(nsite * eb);
+      void* o32 = sc.get(nout * eb);
       stage_in(env, e32, nenv, DM_FP32, s);
       stage_in(site, s32, nsite, DM_FP32, s);
       HIPCHK(gemm_lp(prec, ep.t1, (const float*)e32, (const float*)s32, (float*)t1, nullptr, s));
@@ -884,15 +1087,27 @@ void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64
       stage_out(o32, out, nout, DM_FP32, s);
     }
   } catch (...) {
-    for (void* q : scratch) dev_free_after(q, s);
+    sc.release(s);
     throw;
   }
-  for (void* q : scratch) dev_free_after(q, s);
+  sc.release(s);
 }
 
 }  // namespace
 
+static int env_update_left_impl(int32_t ly, const dm_bond* a, const dm_bond* b,
+                               const dm_mpo_site* w, const void* L, const void* A, void* L_out,
+                               int32_t prec, dm_stream stream);
+
 extern "C" int env_update_left(int32_t ly, const dm_bond* a, const dm_bond* b,
+                               const dm_mpo_site* w, const void* L, const void* A, void* L_out,
+                               int32_t prec, dm_stream stream) {
+  const int rc = env_update_left_impl(ly, a, b, w, L, A, L_out, prec, stream);
+  if (rc != DM_OK) drain(stream);  // no queued work outlives the error
+  return rc;
+}
+
+static int env_update_left_impl(int32_t ly, const dm_bond* a, const dm_bond* b,
                                const dm_mpo_site* w, const void* L, const void* A, void* L_out,
                                int32_t prec, dm_stream stream) {
   return guarded([&] {
@@ -909,11 +1124,24 @@ extern "C" int env_update_left(int32_t ly, const dm_bond* a, const dm_bond* b,
     validate(ep.t1, Li.P.total, S.P.total, ep.t1total);
     validate(ep.mix, ep.t1total, ep.t2total);
     validate(ep.t3, S.P.total, ep.t2total, Lo.P.total);
-    run_env(ep, L, Li.P.total, A, S.P.total, L_out, Lo.P.total, prec, (hipStream_t)stream);
+    EnvScratch pool;
+    run_env(ep, L, Li.P.total, A, S.P.total, L_out, Lo.P.total, prec, (hipStream_t)stream, pool);
   });
 }
 
+static int env_update_right_impl(int32_t ly, const dm_bond* b, const dm_bond* c,
+                                const dm_mpo_site* w, const void* R, const void* B, void* R_out,
+                                int32_t prec, dm_stream stream);
+
 extern "C" int env_update_right(int32_t ly, const dm_bond* b, const dm_bond* c,
+                                const dm_mpo_site* w, const void* R, const void* B, void* R_out,
+                                int32_t prec, dm_stream stream) {
+  const int rc = env_update_right_impl(ly, b, c, w, R, B, R_out, prec, stream);
+  if (rc != DM_OK) drain(stream);  // no queued work outlives the error
+  return rc;
+}
+
+static int env_update_right_impl(int32_t ly, const dm_bond* b, const dm_bond* c,
                                 const dm_mpo_site* w, const void* R, const void* B, void* R_out,
                                 int32_t prec, dm_stream stream) {
   return guarded([&] {
@@ -930,7 +1158,8 @@ extern "C" int env_update_right(int32_t ly, const dm_bond* b, const dm_bond* c,
     validate(ep.t1, Ri.P.total, S.P.total, ep.t1total);
     validate(ep.mix, ep.t1total, ep.t2total);
     validate(ep.t3, S.P.total, ep.t2total, Ro.P.total);
-    run_env(ep, R, Ri.P.total, B, S.P.total, R_out, Ro.P.total, prec, (hipStream_t)stream);
+    EnvScratch pool;
+    run_env(ep, R, Ri.P.total, B, S.P.total, R_out, Ro.P.total, prec, (hipStream_t)stream, pool);
   });
 }
 
@@ -952,5 +1181,3 @@ extern "C" int dm_env_flops(int32_t left, int32_t ly, const dm_bond* x, const dm
     }
   });
 }
-
-

@@ -11,9 +11,16 @@
 // list.  The instances run in lock step; each instance stops on its own rule (its
 // remaining vector launches become no-ops) and its stop time is read from the device
 // wall clock.
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
 #include <numeric>
 #include <string>
@@ -282,36 +289,125 @@ double time_stage(GemmStage& t, int prec, char* base, size_t eb, hipStream_t s) 
   return best;
 }
 
+// ---------------------------------------------------------------------------------
+// Tile shapes chosen by timing are kept in a small text file, one line per key
+//   <gfx arch> <precision> <stage flags> <bucket> <work class>  <candidate index>
+// (work class: log2 of the bucket's algorithmic GFLOP, rounded), so later batches of the
+// same kind skip the timing.  File: $MRDMRG_TUNE_CACHE, else $XDG_CACHE_HOME/mrdmrg/
+// tile_shapes.txt, else ~/.cache/mrdmrg/tile_shapes.txt; MRDMRG_TUNE_CACHE=0 turns it
+// off.  Written whole to a temporary file and renamed over the old one.
+// ---------------------------------------------------------------------------------
+std::string cache_path() {
+  const char* e = getenv("MRDMRG_TUNE_CACHE");
+  if (e && e[0] == '0' && e[1] == 0) return "";
+  if (e && e[0]) return e;
+  const char* x = getenv("XDG_CACHE_HOME");
+  if (x && x[0]) return std::string(x) + "/mrdmrg/tile_shapes.txt";
+  const char* h = getenv("HOME");
+  if (h && h[0]) return std::string(h) + "/.cache/mrdmrg/tile_shapes.txt";
+  return "";
+}
+
+std::map<std::string, int> cache_read(const std::string& path) {
+  std::map<std::string, int> out;
+  if (path.empty()) return out;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t cut = line.rfind(' ');
+    if (cut == std::string::npos || cut == 0) continue;
+    try {
+      out[line.substr(0, cut)] = std::stoi(line.substr(cut + 1));
+    } catch (const std::exception&) {  // a damaged line is ignored
+    }
+  }
+  return out;
+}
+
+void cache_write(const std::string& path, const std::map<std::string, int>& add) {
+  if (path.empty() || add.empty()) return;
+  std::map<std::string, int> all = cache_read(path);
+  for (const auto& kv : add) all[kv.first] = kv.second;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    std::string dir = path.substr(0, slash);
+    for (size_t i = 1; i <= dir.size(); ++i)
+      if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+  }
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  {
+    std::ofstream f(tmp);
+    if (!f) return;  // an unwritable cache only costs the timing next time
+    for (const auto& kv : all) f << kv.first << ' ' << kv.second << '\n';
+    if (!f) return;
+  }
+  (void)std::rename(tmp.c_str(), path.c_str());
+}
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
 // One stage per problem bucket; with tune, each bucket takes the fastest candidate shape
-// (timed on the batch's own buffers), otherwise the plans' default shape.
+// (timed on the batch's own buffers, or read from the cache of earlier timings),
+// otherwise the plans' default shape.
 std::vector<GemmStage> tune_stage(const GemmStage& base, int prec, const Shape& dflt, bool tune,
                                   char* ptr, size_t eb, hipStream_t s, std::vector<std::string>& log) {
   std::vector<std::vector<int>> which(kBuckets);
   for (int i = 0; i < (int)base.probs.size(); ++i) which[bucket_of(base.probs[i])].push_back(i);
   const std::vector<Shape> cand = candidates(prec, base.flags);
+  const std::string path = tune ? cache_path() : std::string();
+  const std::map<std::string, int> cached = cache_read(path);
+  std::map<std::string, int> learned;
+  const std::string arch = tune ? arch_name() : std::string();
   std::vector<GemmStage> out;
   for (int bk = 0; bk < kBuckets; ++bk) {
     if (which[bk].empty()) continue;
     Shape best = dflt;
+    bool from_cache = false;
     if (tune && cand.size() > 1) {
-      double tbest = 1e30;
-      for (const Shape& c : cand) {
-        GemmStage t = base;
-        tile_bucket(t, which[bk], c);
-        const double ms = time_stage(t, prec, ptr, eb, s);
-        if (ms < tbest) {
-          tbest = ms;
-          best = c;
+      double gf = 0;
+      for (int i : which[bk]) {
+        const GemmProb& p = base.probs[i];
+        for (int q = 0; q < p.nseg; ++q) gf += 8.0 * p.M * p.N * base.segs[p.seg0 + q].k;
+      }
+      const int wclass = (int)std::lround(std::log2(std::max(gf * 1e-9, 1e-6)));
+      const std::string key = arch + " " + std::to_string(prec) + " " + std::to_string(base.flags) + " " +
+                              std::to_string(bk) + " " + std::to_string(wclass);
+      auto it = cached.find(key);
+      if (it != cached.end() && it->second >= 0 && it->second < (int)cand.size()) {
+        best = cand[it->second];
+        from_cache = true;
+      } else {
+        double tbest = 1e30;
+        int ibest = 0;
+        for (size_t ci = 0; ci < cand.size(); ++ci) {
+          GemmStage t = base;
+          tile_bucket(t, which[bk], cand[ci]);
+          const double ms = time_stage(t, prec, ptr, eb, s);
+          if (ms < tbest) {
+            tbest = ms;
+            best = cand[ci];
+            ibest = (int)ci;
+          }
         }
+        learned[key] = ibest;
       }
     }
     GemmStage t = base;
     tile_bucket(t, which[bk], best);
     log.push_back("flags " + std::to_string(base.flags) + " bucket " + std::to_string(bk) + ": " +
                   std::to_string(which[bk].size()) + " problems, " + std::to_string(best.tm) + "x" +
-                  std::to_string(best.tn) + (best.deep ? " deep" : "") + (best.split ? " split" : ""));
+                  std::to_string(best.tn) + (best.deep ? " deep" : "") + (best.split ? " split" : "") +
+                  (from_cache ? " (cached)" : ""));
     out.push_back(std::move(t));
   }
+  cache_write(path, learned);
   return out;
 }
 
@@ -452,9 +548,22 @@ extern "C" int64_t dm_batch_info(const dm_batch* b, char* buf, int64_t len) {
   return (int64_t)t.size() + 1;
 }
 
+static int lanczos_ground_batched_impl(dm_batch* b, void* const* thetas, int32_t max_iter,
+                                       double tol, double* energies, int32_t* iters,
+                                       double* done_us, dm_stream stream);
+
 extern "C" int lanczos_ground_batched(dm_batch* b, void* const* thetas, int32_t max_iter,
                                       double tol, double* energies, int32_t* iters,
                                       double* done_us, dm_stream stream) {
+  // as lanczos_ground: an error returns only once the queued work has drained
+  const int rc = lanczos_ground_batched_impl(b, thetas, max_iter, tol, energies, iters, done_us, stream);
+  if (rc != DM_OK && b) drain(stream);
+  return rc;
+}
+
+static int lanczos_ground_batched_impl(dm_batch* b, void* const* thetas, int32_t max_iter,
+                                       double tol, double* energies, int32_t* iters,
+                                       double* done_us, dm_stream stream) {
   return guarded([&] {
     if (!b || !thetas || !energies || !iters) throw DmError{DM_ERR_ARG, "null argument"};
     if (max_iter < 1 || max_iter > LZ_MAX) throw DmError{DM_ERR_ARG, "max_iter must be in 1..64"};

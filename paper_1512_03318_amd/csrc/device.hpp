@@ -47,8 +47,8 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 
 // Sums the K-split partial tiles (tm x tn each) of one output tile in split order and
 // stores it.  Block (x, y): output tile x, elements [1024 y, 1024 y + 1024) of the tile.
-template <typename T, int FLAGS>
-__global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const GemmProb* __restrict__ probs,
+template <typename T, int FLAGS, typename Prob = GemmProb>
+__global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const Prob* __restrict__ probs,
                                                                 const GemmTile* __restrict__ tiles,
                                                                 const int64_t* __restrict__ rows,
                                                                 const T* __restrict__ part,
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const GemmProb* 
                                                                 const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   const GemmTile tile = tiles[blockIdx.x];
-  const GemmProb P = probs[tile.prob];
+  const Prob P = probs[tile.prob];
   const int tiles_n = (P.N + tn - 1) / tn;
   const int64_t slot = (int64_t)tm * tn;
   const int64_t base = (int64_t)P.slot0 + ((int64_t)tile.tm * tiles_n + tile.tn) * P.nks;

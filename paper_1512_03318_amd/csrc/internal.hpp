@@ -57,11 +57,13 @@ struct GemmTile {
 };
 
 // Sparse mixing: dst[r, c] = sum_s coef_s * src_s[r, c] over a rows x cols sub-block.
+// pstride > 0: the destination is split into four bf16 planes (re_hi, re_lo, im_hi,
+// im_lo) pstride elements apart, dst and ld_dst counting bf16 elements of one plane.
 struct MixTask {
   int64_t dst;
   int32_t ld_dst, rows, cols;
   int32_t src0, nsrc;
-  int32_t pad;
+  int32_t pstride;
 };
 struct MixSrc {
   int64_t off;
@@ -114,7 +116,7 @@ struct SlabTask {
   int64_t dst;  // destination element (0, 0) of the task
   int32_t ld_dst;
   int32_t c0, nc;  // coefficients [c0, c0 + nc)
-  int32_t pad;
+  int32_t pstride;  // as MixTask::pstride
 };
 struct SlabCoef {
   int32_t blk, pad;  // block index within the slab
@@ -157,6 +159,64 @@ hipError_t launch_gemm_bf16x3(const GemmStage& st, const float* A, const float* 
 template <typename T>
 hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s,
                       const int32_t* skip = nullptr);
+// Mixing whose output is split into bf16 planes (tasks with pstride > 0, slab form).
+hipError_t launch_mix_split(const MixStage& st, const float* src, __bf16* dst, hipStream_t s,
+                            const int32_t* skip = nullptr);
+
+// ---------------------------------------------------------------------------------
+// Pre-split operands (BF16x3).  A complex matrix of R rows and K columns is stored as
+// four bf16 planes re_hi, re_lo, im_hi, im_lo (x = hi + lo, hi = bf16(x), lo =
+// bf16(x - hi), both round to nearest even, x the FP32 value), each R x kp with k
+// contiguous, kp = K rounded up to a multiple of 8, the padding zero.
+// One problem: C[M x N] = A (M x kp planes) . B^T (B: N x kp planes), in chunks of 32
+// along k (K-split: split ks takes chunks ks, ks + nks, ...).  C is complex FP32 at
+// c_off + i * ldc + j (COUT 0) or complex FP64 at row-table offsets (COUT 1).
+struct PsProb {
+  int64_t a_off, b_off;  // bf16 elements: plane 0, row 0 of A and of B
+  int64_t a_ps, b_ps;    // plane strides (bf16 elements)
+  int64_t c_off;
+  int32_t M, N, kp;
+  int32_t ldc;
+  int32_t rowmap;  // start in the row table (COUT 1), -1 if none
+  int32_t nks, slot0;
+  int32_t pad;
+};
+struct PsStage {
+  int32_t cout = 0;  // 0: FP32 affine C; 1: FP64 C through the row table
+  int32_t tile_m = 128, tile_n = 64;
+  bool split = false;
+  int32_t split_min = 12;  // chunks of 32 per K split at least (at most 8 splits)
+  std::vector<PsProb> probs;
+  std::vector<GemmTile> tiles;
+  std::vector<int64_t> rows;
+  std::vector<GemmTile> red_tiles;
+  int64_t nslots = 0;
+  double flops = 0.0;
+  int64_t slot_elems() const { return (int64_t)tile_m * tile_n; }
+  PsProb* d_probs = nullptr;
+  GemmTile* d_tiles = nullptr;
+  int64_t* d_rows = nullptr;
+  GemmTile* d_red_tiles = nullptr;
+};
+hipError_t launch_gemm_ps(const PsStage& st, const __bf16* A, const __bf16* B, void* C, float* part,
+                          hipStream_t s, const int32_t* skip = nullptr,
+                          const std::function<void()>& between = std::function<void()>());
+
+// Conversion of complex FP64 matrices into split planes.  Job: the source block is rows
+// x cols at src + r * ld + c (complex elements); the destination rows are the source
+// rows (trans 0) or the source columns (trans 1), each kp bf16 long (k = the other
+// index, zero beyond it), planes pstride apart.  i0: first flat item (one item = eight
+// k values of one destination row) of this job.
+struct SplitJob {
+  int64_t src, dst;
+  int32_t ld, rows, cols, kp;
+  int32_t trans, pstride;
+  int64_t i0;
+};
+int64_t split_layout(std::vector<SplitJob>& jobs);  // fills i0, returns the total items
+hipError_t launch_split(const SplitJob* jobs, int32_t njobs, int64_t nitems, const double* src,
+                        __bf16* dst, hipStream_t s, const int32_t* skip = nullptr);
+
 hipError_t launch_cast_d2f(const double* in, float* out, int64_t n_real, hipStream_t s,
                            const int32_t* skip = nullptr);
 hipError_t launch_cast_f2d(const float* in, double* out, int64_t n_real, hipStream_t s,

@@ -380,12 +380,28 @@ struct MixPart {
   int per, ncol, r0, c0, step_r, step_c;
 };
 
+// Output element store of the mixing: complex in the element type (OT = T), or split
+// into four bf16 planes pstride apart (OT = __bf16; see internal.hpp, PsProb).
+template <typename T, typename OT>
+__device__ __forceinline__ void mix_store(OT* obase, int64_t off, int32_t pstride, T re, T im) {
+  if constexpr (sizeof(OT) == 2) {
+    const float fr = (float)re, fi = (float)im;
+    const __bf16 hr = (__bf16)fr, hi = (__bf16)fi;
+    obase[off] = hr;
+    obase[off + pstride] = (__bf16)(fr - (float)hr);
+    obase[off + 2 * (int64_t)pstride] = hi;
+    obase[off + 3 * (int64_t)pstride] = (__bf16)(fi - (float)hi);
+  } else {
+    stc(obase, off, re, im);
+  }
+}
+
 // One output task of a slab with NC coefficients, all read once before the element
 // loop (the generic loop reads the coefficient of every term of every element and waits
 // for it); the terms are summed in the same order.
-template <typename T, int NC>
+template <typename T, typename OT, int NC>
 __device__ __forceinline__ void mix_slab_task(const SlabTask& k, const SlabCoef* __restrict__ coefs,
-                                              const T* lds, T* obase, const MixPart& p) {
+                                              const T* lds, OT* obase, const MixPart& p) {
   T cr[NC], ci[NC];
   int bo[NC];
 #pragma unroll
@@ -404,7 +420,7 @@ __device__ __forceinline__ void mix_slab_task(const SlabTask& k, const SlabCoef*
       re += cr[q] * x[0] - ci[q] * x[1];
       im += cr[q] * x[1] + ci[q] * x[0];
     }
-    stc(obase, (int64_t)r * k.ld_dst + c, re, im);
+    mix_store<T, OT>(obase, (int64_t)r * k.ld_dst + c, k.pstride, re, im);
     r += p.step_r;
     c += p.step_c;
     if (c >= p.ncol) {
@@ -417,14 +433,15 @@ __device__ __forceinline__ void mix_slab_task(const SlabTask& k, const SlabCoef*
 // Slab form: stage the workgroup's part (rows r0.., columns col0..) of every source block
 // of its slab in LDS (planes [block][row][col], interleaved complex), then produce that
 // part of each task of the slab from LDS.  Elements e of the part map to (row, col) with
-// a running (row, col) pair instead of a division per element.
-template <typename T>
+// a running (row, col) pair instead of a division per element.  OT: output element type
+// (T, or __bf16 for an output split into planes).
+template <typename T, typename OT>
 __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict__ wgs,
                                                        const SlabBlk* __restrict__ blks,
                                                        const SlabTask* __restrict__ tasks,
                                                        const SlabCoef* __restrict__ coefs,
                                                        const T* __restrict__ src,
-                                                       T* __restrict__ dst,
+                                                       OT* __restrict__ dst,
                                                        const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   extern __shared__ __attribute__((aligned(16))) char mix_lds[];
@@ -471,17 +488,18 @@ __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict_
   __syncthreads();
   for (int t = 0; t < g.ntask; ++t) {
     const SlabTask k = tasks[g.task0 + t];
-    T* obase = dst + 2 * (k.dst + (int64_t)g.r0 * k.ld_dst + g.col0);
+    // complex elements of T (two per element) or bf16 elements of one plane
+    OT* obase = dst + (sizeof(OT) == 2 ? 1 : 2) * (k.dst + (int64_t)g.r0 * k.ld_dst + g.col0);
     const MixPart part{per, g.ncol, r_init, c_init, step_r, step_c};
     switch (k.nc) {  // uniform over the workgroup
-      case 1: mix_slab_task<T, 1>(k, coefs, lds, obase, part); continue;
-      case 2: mix_slab_task<T, 2>(k, coefs, lds, obase, part); continue;
-      case 3: mix_slab_task<T, 3>(k, coefs, lds, obase, part); continue;
-      case 4: mix_slab_task<T, 4>(k, coefs, lds, obase, part); continue;
-      case 5: mix_slab_task<T, 5>(k, coefs, lds, obase, part); continue;
-      case 6: mix_slab_task<T, 6>(k, coefs, lds, obase, part); continue;
-      case 7: mix_slab_task<T, 7>(k, coefs, lds, obase, part); continue;
-      case 8: mix_slab_task<T, 8>(k, coefs, lds, obase, part); continue;
+      case 1: mix_slab_task<T, OT, 1>(k, coefs, lds, obase, part); continue;
+      case 2: mix_slab_task<T, OT, 2>(k, coefs, lds, obase, part); continue;
+      case 3: mix_slab_task<T, OT, 3>(k, coefs, lds, obase, part); continue;
+      case 4: mix_slab_task<T, OT, 4>(k, coefs, lds, obase, part); continue;
+      case 5: mix_slab_task<T, OT, 5>(k, coefs, lds, obase, part); continue;
+      case 6: mix_slab_task<T, OT, 6>(k, coefs, lds, obase, part); continue;
+      case 7: mix_slab_task<T, OT, 7>(k, coefs, lds, obase, part); continue;
+      case 8: mix_slab_task<T, OT, 8>(k, coefs, lds, obase, part); continue;
       default: break;
     }
     int r = r_init, c = c_init;
@@ -494,7 +512,7 @@ __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict_
         re += cr * x[0] - ci * x[1];
         im += cr * x[1] + ci * x[0];
       }
-      stc(obase, (int64_t)r * k.ld_dst + c, re, im);
+      mix_store<T, OT>(obase, (int64_t)r * k.ld_dst + c, k.pstride, re, im);
       r += step_r;
       c += step_c;
       if (c >= g.ncol) {
@@ -509,7 +527,7 @@ template <typename T>
 hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s, const int32_t* skip) {
   if (st.tasks.empty()) return hipSuccess;
   if (!st.wgs.empty() && st.slab_eb == (int)(2 * sizeof(T))) {
-    hipLaunchKernelGGL((mix_slab_kernel<T>), dim3((uint32_t)st.wgs.size()), dim3(256),
+    hipLaunchKernelGGL((mix_slab_kernel<T, T>), dim3((uint32_t)st.wgs.size()), dim3(256),
                        (uint32_t)st.lds_bytes, s, st.d_wgs, st.d_blks, st.d_stasks, st.d_coefs, src,
                        dst, skip);
     return hipGetLastError();
@@ -518,6 +536,16 @@ hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s, c
                      st.d_tasks, st.d_srcs, src, dst, skip);
   return hipGetLastError();
 }
+hipError_t launch_mix_split(const MixStage& st, const float* src, __bf16* dst, hipStream_t s,
+                            const int32_t* skip) {
+  if (st.tasks.empty()) return hipSuccess;
+  if (st.wgs.empty() || st.slab_eb != 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((mix_slab_kernel<float, __bf16>), dim3((uint32_t)st.wgs.size()), dim3(256),
+                     (uint32_t)st.lds_bytes, s, st.d_wgs, st.d_blks, st.d_stasks, st.d_coefs, src,
+                     dst, skip);
+  return hipGetLastError();
+}
+
 template hipError_t launch_mix<double>(const MixStage&, const double*, double*, hipStream_t,
                                        const int32_t*);
 template hipError_t launch_mix<float>(const MixStage&, const float*, float*, hipStream_t,

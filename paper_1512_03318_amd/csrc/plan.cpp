@@ -274,7 +274,7 @@ void mix_to_slabs(MixStage& st, const std::vector<int64_t>& key, int eb, int lds
     for (size_t q = i; q < j; ++q) {
       const MixTask& t = st.tasks[ord[q]];
       if (t.rows != rows || t.cols != cols) throw err(DM_ERR_LAYOUT, "mixing slab shapes differ");
-      SlabTask out{t.dst, t.ld_dst, (int32_t)st.coefs.size(), t.nsrc, 0};
+      SlabTask out{t.dst, t.ld_dst, (int32_t)st.coefs.size(), t.nsrc, t.pstride};
       for (int k = 0; k < t.nsrc; ++k) {
         const MixSrc& m = st.srcs[t.src0 + k];
         // block index of this source in the slab (a slab has few blocks: linear search)
@@ -303,10 +303,89 @@ void mix_to_slabs(MixStage& st, const std::vector<int64_t>& key, int eb, int lds
   }
 }
 
+void add_ps_tiles(PsStage& st, int32_t prob) {
+  PsProb& P = st.probs[prob];
+  const int tm = (P.M + st.tile_m - 1) / st.tile_m, tn = (P.N + st.tile_n - 1) / st.tile_n;
+  P.nks = 1;
+  P.slot0 = -1;
+  if (P.M <= 0 || P.N <= 0) return;
+  if (st.split) {
+    const int chunks = (P.kp + 31) / 32;
+    P.nks = std::max(1, std::min(8, chunks / std::max(1, st.split_min)));
+    if (P.nks > 1) {
+      P.slot0 = (int32_t)st.nslots;
+      st.nslots += (int64_t)tm * tn * P.nks;
+    }
+  }
+  for (int a = 0; a < tm; ++a)
+    for (int b = 0; b < tn; ++b) {
+      for (int ks = 0; ks < P.nks; ++ks) st.tiles.push_back({prob, a, b, ks});
+      if (P.nks > 1) st.red_tiles.push_back({prob, a, b, 0});
+    }
+}
+
+void validate(const PsStage& st, int64_t a_size, int64_t b_size, int64_t c_size) {
+  for (const std::vector<GemmTile>* tl : {&st.tiles, &st.red_tiles})
+    for (const GemmTile& t : *tl) {
+      if (t.prob < 0 || t.prob >= (int)st.probs.size()) throw err(DM_ERR_LAYOUT, "bad tile");
+      const PsProb& p = st.probs[t.prob];
+      if (t.ks < 0 || t.ks >= std::max(1, p.nks)) throw err(DM_ERR_LAYOUT, "bad K-split");
+      if (t.tm < 0 || t.tn < 0 || t.tm * st.tile_m >= p.M || t.tn * st.tile_n >= p.N)
+        throw err(DM_ERR_LAYOUT, "empty tile");
+      if (p.nks > 1) {
+        const int tn = (p.N + st.tile_n - 1) / st.tile_n;
+        const int64_t slot = (int64_t)p.slot0 + ((int64_t)t.tm * tn + t.tn) * p.nks + t.ks;
+        if (!st.split || p.slot0 < 0 || slot >= st.nslots) throw err(DM_ERR_LAYOUT, "bad partial slot");
+      }
+    }
+  for (const PsProb& p : st.probs) {
+    if (p.M <= 0 || p.N <= 0 || p.kp <= 0 || p.kp % 8) throw err(DM_ERR_LAYOUT, "bad pre-split problem");
+    // 16-byte loads: every offset and stride a multiple of 8 bf16
+    if (p.a_off % 8 || p.b_off % 8 || p.a_ps % 8 || p.b_ps % 8) throw err(DM_ERR_LAYOUT, "pre-split alignment");
+    if (p.a_ps < (int64_t)p.M * p.kp || p.b_ps < (int64_t)p.N * p.kp) throw err(DM_ERR_LAYOUT, "pre-split planes overlap");
+    range_check(p.a_off, p.a_off + 3 * p.a_ps + (int64_t)p.M * p.kp - 1, a_size, "pre-split A");
+    range_check(p.b_off, p.b_off + 3 * p.b_ps + (int64_t)p.N * p.kp - 1, b_size, "pre-split B");
+    if (st.cout == 1) {
+      if (p.rowmap < 0 || p.rowmap + p.M > (int64_t)st.rows.size()) throw err(DM_ERR_LAYOUT, "bad row table");
+      for (int i = 0; i < p.M; ++i) {
+        const int64_t r = st.rows[p.rowmap + i];
+        range_check(r, r + p.N - 1, c_size, "pre-split C row");
+      }
+    } else {
+      if (p.ldc < p.N) throw err(DM_ERR_LAYOUT, "pre-split ldc");
+      range_check(p.c_off, p.c_off + (int64_t)(p.M - 1) * p.ldc + p.N - 1, c_size, "pre-split C");
+    }
+  }
+}
+
+int64_t split_layout(std::vector<SplitJob>& jobs) {
+  int64_t n = 0;
+  for (SplitJob& j : jobs) {
+    j.i0 = n;
+    const int drows = j.trans ? j.cols : j.rows;
+    n += (int64_t)drows * (j.kp / 8);
+  }
+  return n;
+}
+
+void validate(const std::vector<SplitJob>& jobs, int64_t src_size, int64_t dst_size) {
+  for (const SplitJob& j : jobs) {
+    if (j.rows <= 0 || j.cols <= 0 || j.ld < j.cols || j.kp % 8 || j.pstride < 0)
+      throw err(DM_ERR_LAYOUT, "bad split job");
+    const int drows = j.trans ? j.cols : j.rows, k = j.trans ? j.rows : j.cols;
+    if (j.kp < k || (int64_t)j.pstride < (int64_t)drows * j.kp || j.dst % 8 || j.pstride % 8)
+      throw err(DM_ERR_LAYOUT, "bad split job");
+    range_check(j.src, j.src + (int64_t)(j.rows - 1) * j.ld + j.cols - 1, src_size, "split src");
+    range_check(j.dst, j.dst + 3 * (int64_t)j.pstride + (int64_t)drows * j.kp - 1, dst_size, "split dst");
+  }
+}
+
 void validate(const MixStage& st, int64_t src_size, int64_t dst_size) {
   for (const MixTask& t : st.tasks) {
     if (t.rows <= 0 || t.cols <= 0) throw err(DM_ERR_LAYOUT, "empty mixing task");
-    range_check(t.dst, t.dst + (int64_t)(t.rows - 1) * t.ld_dst + t.cols - 1, dst_size, "mix dst");
+    if (t.pstride < 0) throw err(DM_ERR_LAYOUT, "mix plane stride");
+    range_check(t.dst, t.dst + 3 * (int64_t)t.pstride + (int64_t)(t.rows - 1) * t.ld_dst + t.cols - 1,
+                dst_size, "mix dst");
     if (t.ld_dst < t.cols) throw err(DM_ERR_LAYOUT, "mix ld");
     if (t.src0 < 0 || t.nsrc < 0 || t.src0 + t.nsrc > (int)st.srcs.size()) throw err(DM_ERR_LAYOUT, "mix sources");
     for (int q = 0; q < t.nsrc; ++q) {
@@ -344,7 +423,9 @@ void validate(const MixStage& st, int64_t src_size, int64_t dst_size) {
     for (int t = 0; t < g0.ntask; ++t) {
       const SlabTask& k = st.stasks[g0.task0 + t];
       if (k.ld_dst <= cmax) throw err(DM_ERR_LAYOUT, "mixing slab task ld");
-      range_check(k.dst + (int64_t)rmin * k.ld_dst + cmin, k.dst + (int64_t)rmax * k.ld_dst + cmax, dst_size, "slab dst");
+      if (k.pstride < 0) throw err(DM_ERR_LAYOUT, "slab plane stride");
+      range_check(k.dst + (int64_t)rmin * k.ld_dst + cmin,
+                  k.dst + 3 * (int64_t)k.pstride + (int64_t)rmax * k.ld_dst + cmax, dst_size, "slab dst");
       if (k.c0 < 0 || k.nc < 0 || k.c0 + k.nc > (int64_t)st.coefs.size()) throw err(DM_ERR_LAYOUT, "slab coefficients");
       for (int q = 0; q < k.nc; ++q)
         if (st.coefs[k.c0 + q].blk < 0 || st.coefs[k.c0 + q].blk >= g0.nblk) throw err(DM_ERR_LAYOUT, "slab block index");

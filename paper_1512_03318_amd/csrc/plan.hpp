@@ -127,5 +127,10 @@ void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_siz
 // element; each workgroup stages at most lds_budget bytes.
 void mix_to_slabs(MixStage& st, const std::vector<int64_t>& key, int eb, int lds_budget);
 void validate(const MixStage& st, int64_t src_size, int64_t dst_size);
+// Pre-split stages: tiles (and K splits) of problem `prob`; bounds of every access
+// (A and B sizes in bf16 elements, C in complex elements).
+void add_ps_tiles(PsStage& st, int32_t prob);
+void validate(const PsStage& st, int64_t a_size, int64_t b_size, int64_t c_size);
+void validate(const std::vector<SplitJob>& jobs, int64_t src_size, int64_t dst_size);
 
 }  // namespace mrd

@@ -52,6 +52,13 @@ std::future<void> run_beside(const F& f) {
   }
 }
 
+// Waits for the work queued on a stream (errors ignored): called before an error
+// leaves an entry point that had queued work, so none of it is still running when the
+// caller reacts to the error.
+inline void drain(dm_stream s) {
+  if (hipStreamSynchronize((hipStream_t)s) != hipSuccess) (void)hipGetLastError();
+}
+
 // Complex FP64 vectors are read and written as 16-byte elements.
 inline bool misaligned(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 != 0; }
 
@@ -89,6 +96,12 @@ struct TableUpload {
     add(st.rows, &st.d_rows);
     add(st.red_tiles, &st.d_red_tiles);
   }
+  void add(PsStage& st) {
+    add(st.probs, &st.d_probs);
+    add(st.tiles, &st.d_tiles);
+    add(st.rows, &st.d_rows);
+    add(st.red_tiles, &st.d_red_tiles);
+  }
   void add(MixStage& st) {
     add(st.tasks, &st.d_tasks);
     add(st.srcs, &st.d_srcs);
@@ -113,6 +126,17 @@ struct TableUpload {
     }
     for (const Part& p : parts) *p.dst = d + p.off;
     return d;
+  }
+  // Upload into a device block d of at least `total` bytes that the caller provides, from
+  // pageable host memory (no pinned staging block): the copy has consumed the host
+  // bytes when hipMemcpyAsync returns, and is ordered on s.
+  void commit_pageable(void* dv, hipStream_t s) {
+    if (parts.empty()) return;
+    char* d = static_cast<char*>(dv);
+    std::vector<char> h(total);
+    for (const Part& p : parts) std::memcpy(h.data() + p.off, p.src, p.bytes);
+    HIPCHK(hipMemcpyAsync(d, h.data(), total, hipMemcpyHostToDevice, s));
+    for (const Part& p : parts) *p.dst = d + p.off;
   }
 };
 
@@ -146,6 +170,27 @@ struct dm_heff_plan {
   const mrd::GemmStage& rq_s1() const { return prec == DM_BF16X3 ? s1f : s1; }
   const mrd::GemmStage& rq_s4() const { return prec == DM_BF16X3 ? s4f : s4; }
   mrd::MixStage mix;
+  // DM_BF16X3 matvec on pre-split operands (bf16 planes): stages, the mixing that writes
+  // Z split, the split jobs of L, R (plan creation) and theta (every matvec), and the
+  // plane offsets (bf16 elements) per ket sector a (L, theta^T) and output sector c' (Z, R)
+  mrd::PsStage s1p, s4p;
+  mrd::MixStage mixp;
+  std::vector<mrd::SplitJob> lsplit, rsplit, thsplit;
+  mrd::SplitJob* d_lsplit = nullptr;
+  mrd::SplitJob* d_rsplit = nullptr;
+  mrd::SplitJob* d_thsplit = nullptr;
+  int64_t lsplit_items = 0, rsplit_items = 0, thsplit_items = 0;
+  std::vector<int64_t> lsoff, thsoff, zsoff, rsoff;
+  std::vector<int32_t> zkp;  // padded K of each Z / R panel
+  int64_t ls_total = 0, ths_total = 0, zs_total = 0, rs_total = 0;
+  void* dLs = nullptr;
+  void* dRs = nullptr;
+  void* dThs = nullptr;
+  void* dZs = nullptr;
+  void* dSplitP = nullptr;  // K-split partial tiles of the pre-split (.).R stage
+  bool presplit = false;    // BF16x3 matvec on the pre-split operands
+  // the Lanczos kernels write an FP32 copy of v_j that the matvec reads
+  bool staged_in() const { return prec == DM_FP32 || (prec == DM_BF16X3 && !presplit); }
   void* dTables = nullptr;      // all task tables (one pool block)
   hipEvent_t done = nullptr;    // recorded after every use; waited on before release
   double mix_flops = 0;
@@ -195,7 +240,8 @@ struct dm_heff_plan {
     for (auto& e : ev)
       for (hipEvent_t x : e) (void)hipEventDestroy(x);
     mrd::dev_free(dTables);
-    for (void* p : {dL, dR, dL64, dR64, dX, dX64, dSplit, dSplit64, dTin, dTout, dZ, dZ64})
+    for (void* p : {dL, dR, dL64, dR64, dX, dX64, dSplit, dSplit64, dTin, dTout, dZ, dZ64, dLs, dRs, dThs, dZs,
+                    dSplitP})
       mrd::dev_free(p);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);

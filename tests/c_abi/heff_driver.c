@@ -5,11 +5,16 @@
  *
  * input (little-endian): int32 ly, prec, max_iter; bond a; bond c; MPO site w1; MPO
  * site w2; then L, R and theta as int64 n followed by n complex128 (interleaved) in the
- * canonical layouts.  bond = int32 nsec, nsec x (int32 n, int32 k), nsec x int32 dim;
+ * canonical layouts; then bond b (between the two orbitals) and the site tensors A
+ * (SITE layout of a, b) and B (SITE layout of b, c), each as int64 n + n complex128.
+ * bond = int32 nsec, nsec x (int32 n, int32 k), nsec x int32 dim;
  * site = int32 dl, dr, dl x charge, dr x charge, 2 x charge (qs), dl*2*2*dr complex128.
  * output: int64 n, n complex128 (H_eff theta), float64 energy, int32 iterations of
- * lanczos_ground started from theta.  Exit status 0 on success; on a library error the
- * message of dm_last_error() goes to stderr and the status is 2. */
+ * lanczos_ground started from theta; int64 n + n complex128 of env_update_left(L, A)
+ * and of env_update_right(R, B) (sizes from dm_layout); float64 energy and int32
+ * iterations of each of the two instances of a two-plan lanczos_ground_batched started
+ * from theta.  Exit status 0 on success; on a library error the message of
+ * dm_last_error() goes to stderr and the status is 2. */
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -99,7 +104,20 @@ int main(int argc, char** argv) {
   void* L = read_device(&nl);
   void* R = read_device(&nr);
   void* th = read_device(&nt);
+  dm_bond b;
+  read_bond(&b);
+  int64_t na, nb;
+  void* A = read_device(&na);
+  void* B = read_device(&nb);
   fclose(in);
+  /* a second copy of theta: the Lanczos calls overwrite their start vector */
+  void* th2 = NULL;
+  void* th3 = NULL;
+  if (hipMalloc(&th2, (size_t)(nt > 0 ? nt : 1) * 16) != hipSuccess ||
+      hipMalloc(&th3, (size_t)(nt > 0 ? nt : 1) * 16) != hipSuccess ||
+      hipMemcpy(th2, th, (size_t)nt * 16, hipMemcpyDeviceToDevice) != hipSuccess ||
+      hipMemcpy(th3, th, (size_t)nt * 16, hipMemcpyDeviceToDevice) != hipSuccess)
+    return 3;
 
   dm_heff_plan* plan = NULL;
   CHECK(dm_heff_plan_create(ly, &a, &c, &w1, &w2, L, R, prec, NULL, &plan));
@@ -118,6 +136,49 @@ int main(int argc, char** argv) {
   double energy = 0.0;
   int32_t iters = 0;
   CHECK(lanczos_ground(plan, th, max_iter, 1e-14, &energy, &iters, NULL));
+
+  /* environment updates through the window: output sizes from the layout query */
+  dm_layout_desc dl_desc;
+  memset(&dl_desc, 0, sizeof(dl_desc));
+  dl_desc.kind = DM_LAYOUT_ENV_L;
+  dl_desc.ly = ly;
+  dl_desc.x = &b;
+  dl_desc.nw = w1.dr;
+  dl_desc.qw = w1.qr;
+  int64_t nblk = 0, nlo = 0, nro = 0;
+  CHECK(dm_layout(&dl_desc, &nblk, &nlo, NULL));
+  dl_desc.kind = DM_LAYOUT_ENV_R;
+  dl_desc.nw = w2.dl;
+  dl_desc.qw = w2.ql;
+  CHECK(dm_layout(&dl_desc, &nblk, &nro, NULL));
+  void *Lo = NULL, *Ro = NULL;
+  if (hipMalloc(&Lo, (size_t)(nlo > 0 ? nlo : 1) * 16) != hipSuccess ||
+      hipMalloc(&Ro, (size_t)(nro > 0 ? nro : 1) * 16) != hipSuccess)
+    return 3;
+  CHECK(env_update_left(ly, &a, &b, &w1, L, A, Lo, prec, NULL));
+  CHECK(env_update_right(ly, &b, &c, &w2, R, B, Ro, prec, NULL));
+  double* hl = (double*)malloc((size_t)(nlo > 0 ? nlo : 1) * 16);
+  double* hr = (double*)malloc((size_t)(nro > 0 ? nro : 1) * 16);
+  if (hipMemcpy(hl, Lo, (size_t)nlo * 16, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(hr, Ro, (size_t)nro * 16, hipMemcpyDeviceToHost) != hipSuccess)
+    return 3;
+
+  /* two plans of the same window in one batch */
+  dm_heff_plan* plan2 = NULL;
+  CHECK(dm_heff_plan_create(ly, &a, &c, &w1, &w2, L, R, prec, NULL, &plan2));
+  dm_heff_plan* pair[2];
+  pair[0] = plan;
+  pair[1] = plan2;
+  dm_batch* batch = NULL;
+  CHECK(dm_batch_create(2, pair, NULL, &batch));
+  void* thetas[2];
+  thetas[0] = th2;
+  thetas[1] = th3;
+  double eb[2];
+  int32_t kb[2];
+  CHECK(lanczos_ground_batched(batch, thetas, max_iter, 1e-14, eb, kb, NULL, NULL));
+  dm_batch_destroy(batch);
+  dm_heff_plan_destroy(plan2);
   dm_heff_plan_destroy(plan);
 
   FILE* out = fopen(argv[2], "wb");
@@ -126,11 +187,17 @@ int main(int argc, char** argv) {
   fwrite(hy, 16, (size_t)n, out);
   fwrite(&energy, 8, 1, out);
   fwrite(&iters, 4, 1, out);
+  fwrite(&nlo, 8, 1, out);
+  fwrite(hl, 16, (size_t)nlo, out);
+  fwrite(&nro, 8, 1, out);
+  fwrite(hr, 16, (size_t)nro, out);
+  fwrite(eb, 8, 2, out);
+  fwrite(kb, 4, 2, out);
   fclose(out);
-  (void)hipFree(L);
-  (void)hipFree(R);
-  (void)hipFree(th);
-  (void)hipFree(y);
+  void* bufs[] = {L, R, th, th2, th3, y, A, B, Lo, Ro};
+  for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i) (void)hipFree(bufs[i]);
   free(hy);
+  free(hl);
+  free(hr);
   return 0;
 }

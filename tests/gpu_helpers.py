@@ -63,3 +63,18 @@ def problem(name):
         L, W1, W2, R, th, keys, mpo = synth.window_problem(wl)
         _problems[name] = (wl, L, W1, W2, R, th, keys, mpo)
     return _problems[name]
+
+
+def block_rel(got: dict, ref: dict, keys):
+    """Largest relative error of one block, |got_b - ref_b|_F / |ref_b|_F, over the blocks
+    whose reference is not zero (the per-block companion of max_rel)."""
+    worst = 0.0
+    for k, _ in keys:
+        r = ref.get(k)
+        if r is None or r.size == 0:
+            continue
+        nr = np.linalg.norm(r)
+        if nr == 0.0:
+            continue
+        worst = max(worst, float(np.linalg.norm(got[k] - r) / nr))
+    return worst

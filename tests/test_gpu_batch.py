@@ -90,3 +90,51 @@ def test_batch_rejects_mixed_precision_and_repeats():
         pk.Batch([p64, p32])
     with pytest.raises(pk.LibraryError):
         pk.Batch([p64, p64])
+
+
+# The many-window workload spans Ly in {4, 6, 8} and chi in [200, 2000]: one batch with
+# its largest window (Ly=8, chi=2000) beside small and mid-size ones, in the batched
+# workload's precision (FP32) and in FP64, tuned tiles, against the oracle's 30-step
+# Lanczos from the same start vectors.
+SCALE_NAMES = ["ly8_chi2000", "ly4_chi200", "ly6_chi800", "ly3_chi16", "ly6_chi200"]
+SCALE_TOL = {pk.DM_FP64: 1e-10, pk.DM_FP32: 1e-6}
+_oracle_runs = {}
+
+
+def oracle_run(name, seed):
+    if (name, seed) not in _oracle_runs:
+        wl, L, W1, W2, R, th, keys, mpo = problem(name)
+        mv = lambda v: bs.flatten(bs.heff_apply(L, W1, W2, R, bs.unflatten(v, keys)), keys)
+        t0 = time.perf_counter()
+        eo, vo, ko, _, _ = olz.lanczos(mv, starts(name, seed), max_iter=30)
+        say(f"  oracle Lanczos {name}: {ko} steps, {time.perf_counter() - t0:.1f} s")
+        _oracle_runs[(name, seed)] = (eo, vo, ko)
+    return _oracle_runs[(name, seed)]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [pk.DM_FP32, pk.DM_FP64])
+def test_batched_at_many_window_scale(prec, monkeypatch):
+    monkeypatch.setenv("MRDMRG_TUNE", "1")
+    say(f"batched at scale prec={prec}: building the windows with the oracle ...")
+    gs, plans, x0 = [], [], []
+    for i, name in enumerate(SCALE_NAMES):
+        wl, L, W1, W2, R, th, keys, mpo = problem(name)
+        say(f"  {name}: chi={sum(wl.bonds[wl.j].values())} n={sum(m * n for _, (m, n) in keys)}")
+        g = WindowGPU(wl, L, R, mpo)
+        gs.append((g, keys))
+        plans.append(g.plan(prec))
+        x0.append(to_dev(g.pack_theta(bs.unflatten(starts(name, 40 + i), keys))))
+    batch = pk.Batch(plans)
+    xb = [x.clone() for x in x0]
+    eb, kb, us = pk.lanczos_ground_batched(batch, xb, 30, 1e-14)
+    say(batch.info())
+    for i, name in enumerate(SCALE_NAMES):
+        eo, vo, ko = oracle_run(name, 40 + i)
+        g, keys = gs[i]
+        v = bs.flatten(g.unpack_theta(xb[i].cpu().numpy()), keys)
+        de = abs(eb[i] - eo) / abs(eo)
+        ov = 1 - abs(np.vdot(vo, v / np.linalg.norm(v)))
+        say(f"  {name}: steps {kb[i]} (oracle {ko}) dE/E={de:.3e} 1-overlap={ov:.3e} done at {us[i]:.0f} us")
+        assert kb[i] == ko
+        assert de <= SCALE_TOL[prec]

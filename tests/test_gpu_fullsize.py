@@ -1,7 +1,8 @@
-"""Parity at the benchmark's full size: the Ly=8, chi=3200 centre window (104 sectors,
-MPO bond dimensions 28/26/28), in the tile shapes and K splits the benchmark runs.
+"""Parity at full size: the benchmark's Ly=8, chi=3200 centre window (104 sectors, MPO
+bond dimensions 28/26/28), in the tile shapes and K splits the benchmark runs, and the
+Ly=10, chi=6000 centre window (150 sectors, flux 1/10) whose stated precision is FP32.
 
-One matvec and both environment updates in every precision against the FP64 oracle.
+One matvec and both environment updates per precision against the FP64 oracle.
 The environments have seeded Gaussian entries with the exact block structure of the
 window (a contraction's result does not depend on the environments being physical), so
 the oracle needs no sweep through the 256 sites; the MPO is the oracle's own."""
@@ -22,17 +23,20 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import paper_1512_03318_amd as pk  # noqa: E402
-from gpu_helpers import max_rel, mpo_site, to_dev  # noqa: E402
+from gpu_helpers import block_rel, max_rel, mpo_site, to_dev  # noqa: E402
 
-PRECS = [(pk.DM_FP64, 1e-12), (pk.DM_FP32, 2e-5), (pk.DM_BF16X3, 1e-4)]
-_case = {}
+TOL = {pk.DM_FP64: 1e-12, pk.DM_FP32: 2e-5, pk.DM_BF16X3: 1e-4}
+CASES = [("ly8_chi3200", pk.DM_FP64), ("ly8_chi3200", pk.DM_FP32), ("ly8_chi3200", pk.DM_BF16X3),
+         ("ly10_chi6000", pk.DM_FP64), ("ly10_chi6000", pk.DM_FP32)]
+_cases = {}
 
 
-def case():
-    if not _case:
-        print("building the Ly=8 chi=3200 window with the oracle ...", flush=True)
+def case(name):
+    if name not in _cases:
+        _case = _cases[name] = {}
+        print(f"building the {name} window with the oracle ...", flush=True)
         sys.stdout.flush()
-        wl = workloads.preset("ly8_chi3200")
+        wl = workloads.preset(name)
         m = omp.build(synth.cylinder_of(wl), wl.basis)
         j, ly = wl.j, wl.ly
         rng = np.random.default_rng(31)
@@ -46,15 +50,16 @@ def case():
                      heff=bs.heff_apply(L, m.W[j], m.W[j + 1], R, th),
                      envl=bs.env_left_update(L, A, m.W[j]),
                      envr=bs.env_right_update(R, B, m.W[j + 1]))
-    return _case
+    return _cases[name]
 
 
-@pytest.mark.parametrize("prec,tol", PRECS)
-def test_fullsize_matvec(prec, tol):
-    c = case()
+@pytest.mark.parametrize("name,prec", CASES)
+def test_fullsize_matvec(name, prec):
+    c = case(name)
+    tol = TOL[prec]
     wl, m = c["wl"], c["m"]
     j, ly = wl.j, wl.ly
-    print(f"full-size matvec prec={prec}", flush=True)
+    print(f"full-size matvec {name} prec={prec}", flush=True)
     a, cb = pk.Bond(wl.bonds[j]), pk.Bond(wl.bonds[j + 2])
     w1, w2 = mpo_site(m, j), mpo_site(m, j + 1)
     qs1 = [tuple(q) for q in m.qsite[j]]
@@ -68,16 +73,18 @@ def test_fullsize_matvec(prec, tol):
     torch.cuda.synchronize()
     got = pk.unpack(y.cpu().numpy(), pk.LAYOUT_THETA, ly, a, cb, qs1=qs1, qs2=qs2)
     err = max_rel(got, c["heff"], c["keys"])
-    print(f"  max relative error {err:.3e}", flush=True)
+    berr = block_rel(got, c["heff"], c["keys"])
+    print(f"  max relative error {err:.3e}, worst block {berr:.3e}", flush=True)
     assert err < tol
 
 
-@pytest.mark.parametrize("prec,tol", PRECS)
-def test_fullsize_env_updates(prec, tol):
-    c = case()
+@pytest.mark.parametrize("name,prec", CASES)
+def test_fullsize_env_updates(name, prec):
+    c = case(name)
+    tol = TOL[prec]
     wl, m = c["wl"], c["m"]
     j, ly = wl.j, wl.ly
-    print(f"full-size environment updates prec={prec}", flush=True)
+    print(f"full-size environment updates {name} prec={prec}", flush=True)
     a, b, cb = (pk.Bond(wl.bonds[k]) for k in (j, j + 1, j + 2))
     for left in (True, False):
         if left:

@@ -17,11 +17,15 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import paper_1512_03318_amd as pk  # noqa: E402
-from gpu_helpers import WindowGPU, max_rel, mpo_site, problem, to_dev  # noqa: E402
+from gpu_helpers import WindowGPU, block_rel, max_rel, mpo_site, problem, to_dev  # noqa: E402
+from helpers import heff_flops  # noqa: E402
 
 CASES = ["ly3_chi16", "ly4_chi64", "ly6_chi200", "ly6_chi800"]
 # FP32: 2^-24 per product; BF16x3: three bf16 products per real product, about 2^-17
 PRECS = [(pk.DM_FP64, 1e-12), (pk.DM_FP32, 2e-5), (pk.DM_BF16X3, 1e-4)]
+# per-block relative error (Frobenius norm of each theta' block): the same rounding,
+# measured against each block's own size instead of the largest element
+BLOCK_TOL = {pk.DM_FP64: 1e-11, pk.DM_FP32: 2e-4, pk.DM_BF16X3: 1e-3}
 
 
 def say(*a):
@@ -42,7 +46,36 @@ def test_heff_apply_parity(name, prec, tol):
     torch.cuda.synchronize()
     got = g.unpack_theta(y.cpu().numpy())
     ref = bs.heff_apply(L, W1, W2, R, th)
-    assert max_rel(got, ref, keys) < tol
+    err, berr = max_rel(got, ref, keys), block_rel(got, ref, keys)
+    say(f"  max relative error {err:.3e}, worst block {berr:.3e}")
+    assert err < tol
+    assert berr < BLOCK_TOL[prec]
+
+
+@pytest.mark.parametrize("name", CASES + ["ly8_chi3200"])
+def test_plan_flops_equal_the_charge_count(name):
+    """The flop counts a plan reports (the numerator of every GFLOP/s figure) equal a
+    count written from charges and bond dimensions alone."""
+    import workloads
+    from oracle import mpo as omp
+    from oracle import synth
+    wl = workloads.preset(name)
+    m = omp.build(synth.cylinder_of(wl), wl.basis)
+    j, ly = wl.j, wl.ly
+    a, c = pk.Bond(wl.bonds[j]), pk.Bond(wl.bonds[j + 2])
+    w1, w2 = mpo_site(m, j), mpo_site(m, j + 1)
+    _, nl = pk.layout(pk.LAYOUT_ENV_L, ly, a, qw=m.qbond[j])
+    _, nr = pk.layout(pk.LAYOUT_ENV_R, ly, c, qw=m.qbond[j + 2])
+    L = torch.zeros(nl, dtype=torch.complex128, device="cuda")
+    R = torch.zeros(nr, dtype=torch.complex128, device="cuda")
+    qs1 = [tuple(map(int, q)) for q in m.qsite[j]]
+    qs2 = [tuple(map(int, q)) for q in m.qsite[j + 1]]
+    ref = heff_flops(wl.bonds[j], wl.bonds[j + 2], m.W[j], m.W[j + 1], m.qbond[j], m.qbond[j + 2],
+                     qs1, qs2, ly)
+    for prec in (pk.DM_FP64, pk.DM_BF16X3):
+        plan = pk.HeffPlan(ly, a, c, w1, w2, L, R, prec)
+        say(f"plan flops {name} prec={prec}: {plan.flops} vs {ref}")
+        assert tuple(plan.flops) == ref
 
 
 @pytest.mark.parametrize("name", CASES)

@@ -1,0 +1,79 @@
+"""Host-side pins of the library that need no GPU.
+
+* The library's own Hofstadter MPO (the one the benchmark's environments are built
+  from) against the oracle's: the two finite-state machines may choose different
+  gauges on the MPO bonds (the scale of a merged state, how far proportional states are
+  merged), so the entries need not agree; what must agree is the operator.  The test
+  contracts the environments of the benchmark's own cylinder (Ly=8, Lx=32, flux 1/8,
+  window at orbitals 127 and 128, so every one of the 256 site tensors enters) from the
+  same seeded isometries with each MPO, by the oracle's block-sparse updates, and
+  compares the two effective Hamiltonians applied to one seeded theta.  The projected
+  Hamiltonian P^H H P of the window does not depend on the MPO gauge.
+* The algorithmic flop counts of the environment updates (dm_env_flops, counted on the
+  task tables the updates run) against a count written in the test from charges and
+  bond dimensions alone.
+"""
+import numpy as np
+import pytest
+
+import paper_1512_03318_amd as pk
+import workloads
+from helpers import env_left_flops, env_right_flops
+from oracle import blocksparse as bs
+from oracle import mpo as omp
+from oracle import synth
+
+_mpo = {}
+
+
+def oracle_mpo(wl):
+    key = (wl.Ly, wl.Lx)
+    if key not in _mpo:
+        _mpo[key] = omp.build(synth.cylinder_of(wl), wl.basis)
+    return _mpo[key]
+
+
+class _Sites:
+    def __init__(self, W):
+        self.W = W
+
+
+def test_library_mpo_gives_the_oracle_heff_on_the_benchmark_cylinder():
+    # the benchmark's cylinder and window, at a small bond dimension
+    wl = workloads.make_workload("ly8_lx32_chi48", 8, 32, (1, 8), 48, 21)
+    assert (wl.Ly, wl.Lx, wl.j) == (8, 32, 127)
+    m = oracle_mpo(wl)
+    lib = pk.HofstadterMPO(wl.Ly, wl.Lx, wl.flux[0], wl.flux[1], wl.t, wl.V, wl.basis)
+    assert lib.n_sites == m.n_sites == 256
+    Wl = [lib.site(i).W for i in range(lib.n_sites)]
+    Lo, W1o, W2o, Ro, _, keys, _ = synth.window_problem(wl, m)
+    Ll, W1l, W2l, Rl, _, _, _ = synth.window_problem(wl, _Sites(Wl))
+    rng = np.random.default_rng(5)
+    j = wl.j
+    th = workloads.random_theta(rng, wl.bonds[j], wl.bonds[j + 2], wl.qsite[j], wl.qsite[j + 1], wl.ly)
+    ref = bs.flatten(bs.heff_apply(Lo, W1o, W2o, Ro, th), keys)
+    got = bs.flatten(bs.heff_apply(Ll, W1l, W2l, Rl, th), keys)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    # same charges on every MPO bond state at the window
+    for i in (j, j + 1):
+        s = lib.site(i)
+        assert s.ql == [tuple(map(int, q)) for q in m.qbond[i]]
+        assert s.qr == [tuple(map(int, q)) for q in m.qbond[i + 1]]
+
+
+@pytest.mark.parametrize("name", ["ly4_chi64", "ly6_chi800", "ly8_chi3200"])
+def test_env_flops_equal_the_charge_count(name):
+    wl = workloads.preset(name)
+    m = oracle_mpo(wl)
+    j, ly = wl.j, wl.ly
+    a, b, c = (pk.Bond(wl.bonds[k]) for k in (j, j + 1, j + 2))
+    w1 = pk.MpoSite(m.W[j], m.qbond[j], m.qbond[j + 1], m.qsite[j])
+    w2 = pk.MpoSite(m.W[j + 1], m.qbond[j + 1], m.qbond[j + 2], m.qsite[j + 1])
+    qs1 = [tuple(map(int, q)) for q in m.qsite[j]]
+    qs2 = [tuple(map(int, q)) for q in m.qsite[j + 1]]
+    fl = pk.env_flops(True, ly, a, b, w1)
+    fr = pk.env_flops(False, ly, b, c, w2)
+    el = env_left_flops(wl.bonds[j], wl.bonds[j + 1], m.W[j], m.qbond[j], m.qbond[j + 1], qs1, ly)
+    er = env_right_flops(wl.bonds[j + 1], wl.bonds[j + 2], m.W[j + 1], m.qbond[j + 1], m.qbond[j + 2], qs2, ly)
+    assert fl == el and fr == er, (fl, el, fr, er)
+    assert fl > 0 and fr > 0

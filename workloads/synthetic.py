@@ -267,6 +267,7 @@ PRESETS = {
     "ly8_chi400": (8, 400, 14),
     "ly4_chi64": (4, 64, 11),
     "ly3_chi16": (3, 16, 15),
+    "ly8_chi2000": (8, 2000, 16),  # the largest window of the many-window batch
 }
 
 
