@@ -213,6 +213,21 @@ int env_update_left(int32_t ly, const dm_bond* a, const dm_bond* b, const dm_mpo
 int env_update_right(int32_t ly, const dm_bond* b, const dm_bond* c, const dm_mpo_site* w,
                      const void* R, const void* B, void* R_out, int32_t prec, dm_stream stream);
 
+/* env_update_left for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): same arguments, kernels
+ * and results as env_update_left, but the task tables and intermediates live in one fixed
+ * device region of 64 MiB that the library holds per device from load until the process
+ * ends, instead of the caching pool.  The call makes no device or pinned allocation
+ * (tables go up from pageable host memory).  An update whose scratch does not fit
+ * (tables + the L.A and mixed intermediates, plus FP32 copies of L, A and L_out in
+ * DM_FP32 / DM_BF16X3) returns DM_ERR_ALLOC before queueing any work.  All calls on one
+ * device share the region: two calls whose queued work overlaps in time (different
+ * streams, or different host threads) race, so callers serialise them, e.g. on one
+ * stream.  Asynchronous on `stream` like env_update_left. */
+int env_update_left_noalloc(int32_t ly, const dm_bond* a, const dm_bond* b, const dm_mpo_site* w,
+                            const void* L, const void* A, void* L_out, int32_t prec,
+                            dm_stream stream);
+
 /* Algorithmic flops of one environment update, 8 per complex multiply-add, counted on
  * the same task tables the update runs.  left = 1: env_update_left from bond x (= a) to
  * bond y (= b); left = 0: env_update_right from bond y (= c) to bond x (= b). */

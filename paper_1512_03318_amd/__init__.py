@@ -8,7 +8,7 @@ library's canonical layouts (offsets come from ``dm_layout``).  Every arithmetic
 runs in the library.  Importing this package fails if the library is missing.
 """
 from .binding import (Split, MPS, dmrg_sweeps, entanglement, DM_BF16X3, DM_FP32, DM_FP64, Bond, HeffPlan, Batch, HofstadterMPO,
-                      LibraryError, MpoSite, env_flops, env_update_left,
+                      LibraryError, MpoSite, env_flops, env_update_left, env_update_left_noalloc,
                       env_update_right, heff_apply,
                       lanczos_ground, lanczos_ground_batched, layout, lib, pack, unpack,
                       LAYOUT_SITE, LAYOUT_THETA, LAYOUT_ENV_L, LAYOUT_ENV_R, DM_OK, DM_ERR_ARG,
@@ -16,7 +16,7 @@ from .binding import (Split, MPS, dmrg_sweeps, entanglement, DM_BF16X3, DM_FP32,
                       DM_ERR_HIP, DM_ERR_NONFINITE)
 
 __all__ = ["Split", "MPS", "dmrg_sweeps", "entanglement", "DM_BF16X3", "DM_FP32", "DM_FP64", "Bond", "HeffPlan", "Batch", "HofstadterMPO",
-           "LibraryError", "MpoSite", "env_flops", "env_update_left",
+           "LibraryError", "MpoSite", "env_flops", "env_update_left", "env_update_left_noalloc",
            "env_update_right", "heff_apply",
            "lanczos_ground", "lanczos_ground_batched", "layout", "lib", "pack", "unpack",
            "LAYOUT_SITE", "LAYOUT_THETA", "LAYOUT_ENV_L", "LAYOUT_ENV_R", "DM_OK", "DM_ERR_ARG",

@@ -75,6 +75,8 @@ _sigs = {
                                _vp, _vp, _vp, _i32, _vp]),
     "env_update_right": (_i32, [_i32, C.POINTER(DmBond), C.POINTER(DmBond), C.POINTER(DmMpoSite),
                                 _vp, _vp, _vp, _i32, _vp]),
+    "env_update_left_noalloc": (_i32, [_i32, C.POINTER(DmBond), C.POINTER(DmBond), C.POINTER(DmMpoSite),
+                                       _vp, _vp, _vp, _i32, _vp]),
     "dm_batch_create": (_i32, [_i32, C.POINTER(_vp), _vp, C.POINTER(_vp)]),
     "dm_batch_destroy": (None, [_vp]),
     "dm_batch_info": (_i64, [_vp, C.c_char_p, _i64]),
@@ -291,6 +293,11 @@ def lanczos_ground(plan: HeffPlan, theta, max_iter=30, tol=1e-14, stream=None):
 def env_update_left(ly, a: Bond, b: Bond, w: MpoSite, L, A, L_out, prec=DM_FP64, stream=None):
     _check(lib.env_update_left(ly, C.byref(a.c), C.byref(b.c), C.byref(w.c), _ptr(L), _ptr(A),
                                _ptr(L_out), prec, _stream(stream)))
+
+
+def env_update_left_noalloc(ly, a: Bond, b: Bond, w: MpoSite, L, A, L_out, prec=DM_FP64, stream=None):
+    _check(lib.env_update_left_noalloc(ly, C.byref(a.c), C.byref(b.c), C.byref(w.c), _ptr(L), _ptr(A),
+                                       _ptr(L_out), prec, _stream(stream)))
 
 
 def env_update_right(ly, b: Bond, c: Bond, w: MpoSite, R, B, R_out, prec=DM_FP64, stream=None):

@@ -1020,7 +1020,7 @@ EnvPlan plan_right(int ly, const Bond& b, const Bond& c, const MpoSite& W, const
 
 // Device scratch of one environment update: blocks from the caching pool, handed back
 // in stream order (run_env), or consecutive pieces of one fixed region that the caller
-// owns.
+// owns (env_update_left_noalloc).
 struct EnvScratch {
   char* base = nullptr;  // fixed region, or null for the pool
   size_t cap = 0, used = 0;
@@ -1179,5 +1179,82 @@ extern "C" int dm_env_flops(int32_t left, int32_t ly, const dm_bond* x, const dm
       SiteLayout S = site_layout(bx, by, W.qs, ly);
       *flops = plan_right(ly, bx, by, W, Ri, S, Ro, 64, 64).flops();
     }
+  });
+}
+
+
+
+// =====================================================================================
+// Left environment update that allocates nothing
+// =====================================================================================
+// The task tables and intermediates of env_update_left_noalloc live in one fixed device
+// array of this size; every device the library runs on holds its own copy of it until
+// the process ends.  Host code never passes the array's name to a kernel or a copy: it
+// uses the device address hipGetSymbolAddress returns for the current device.
+static constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;  // device -> address of its copy of `scratch`
+
+// Address of the current device's copy of `scratch`, looked up once per device.
+char* scratch_on_current_device() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) return it->second;
+  char* ptr = nullptr;
+  HIPCHK(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) throw DmError{DM_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array"};
+  g_scratch_ptr[dev] = ptr;
+  return ptr;
+}
+}  // namespace
+
+static int env_update_left_noalloc_impl(int32_t ly, const dm_bond* a, const dm_bond* b,
+                                       const dm_mpo_site* w, const void* L, const void* A,
+                                       void* L_out, int32_t prec, dm_stream stream);
+
+extern "C" int env_update_left_noalloc(int32_t ly, const dm_bond* a, const dm_bond* b,
+                                       const dm_mpo_site* w, const void* L, const void* A,
+                                       void* L_out, int32_t prec, dm_stream stream) {
+  const int rc = env_update_left_noalloc_impl(ly, a, b, w, L, A, L_out, prec, stream);
+  if (rc != DM_OK) drain(stream);  // no queued work outlives the error
+  return rc;
+}
+
+static int env_update_left_noalloc_impl(int32_t ly, const dm_bond* a, const dm_bond* b,
+                                       const dm_mpo_site* w, const void* L, const void* A,
+                                       void* L_out, int32_t prec, dm_stream stream) {
+  return guarded([&] {
+    check_ly(ly);
+    check_prec(prec);
+    Bond ba = make_bond(a, ly), bb = make_bond(b, ly);
+    MpoSite W = make_mpo(w, ly);
+    EnvLLayout Li = envl_layout(ba, W.ql, ly);
+    EnvLLayout Lo = envl_layout(bb, W.qr, ly);
+    SiteLayout S = site_layout(ba, bb, W.qs, ly);
+    if ((Li.P.total && !L) || (S.P.total && !A) || (Lo.P.total && !L_out))
+      throw DmError{DM_ERR_ARG, "null tensor"};
+    EnvPlan ep = plan_left(ly, ba, bb, W, Li, S, Lo, env_t3_tile(prec));
+    validate(ep.t1, Li.P.total, S.P.total, ep.t1total);
+    validate(ep.mix, ep.t1total, ep.t2total);
+    validate(ep.t3, S.P.total, ep.t2total, Lo.P.total);
+    // the whole footprint is checked before any work is queued
+    TableUpload probe;
+    probe.add(ep.t1);
+    probe.add(ep.t3);
+    probe.add(ep.mix);
+    const size_t need = env_scratch_bytes(ep, probe.total, Li.P.total, S.P.total, Lo.P.total, prec);
+    if (need > kNoallocScratchBytes)
+      throw DmError{DM_ERR_ALLOC, "env_update_left_noalloc needs " + std::to_string(need) +
+                                      " bytes of scratch; its fixed region holds " +
+                                      std::to_string(kNoallocScratchBytes)};
+    EnvScratch fixed;
+    fixed.base = scratch_on_current_device();
+    fixed.cap = kNoallocScratchBytes;
+    run_env(ep, L, Li.P.total, A, S.P.total, L_out, Lo.P.total, prec, (hipStream_t)stream, fixed);
   });
 }
