@@ -191,16 +191,23 @@ def stage_rooflines(pk, plan, prec, pname, prof, nmv, workload):
     product; HBM at 8 TB/s); `frac` is its achieved fraction of that roof."""
     eb = 16 if prec == pk.DM_FP64 else 8
     avg = [p / max(nmv, 1) for p in prof]
+    # BF16x3: the kernels that split FP32 operands while staging them, or with
+    # MRDMRG_PRESPLIT=1 the kernels on pre-split operands
+    presplit = os.environ.get("MRDMRG_PRESPLIT", "0") == "1"
+    bf3 = (("mrd::gemm_ps_kernel<128, 64, 2, 2, false, 0>", "mrd::gemm_ps_kernel<128, 32, 4, 1, true, 1>",
+            "mrd::mix_slab_kernel<float, __bf16>", "mrd::gemm_split_reduce_kernel<float, 144, mrd::PsProb>")
+           if presplit else
+           ("mrd::gemm_bf3_kernel<0, 128, 64, 2, 2, false>", "mrd::gemm_bf3_kernel<148, 128, 32, 4, 1, true>",
+            "mrd::mix_slab_kernel<float, float>", "mrd::gemm_split_reduce_kernel<float, 148, mrd::GemmProb>"))
     gemm = {pk.DM_FP64: ("mrd::gemm_kernel<double, 0, false>", "mrd::gemm_kernel<double, 20, true>"),
             pk.DM_FP32: ("mrd::gemm_kernel<float, 0, false>", "mrd::gemm_kernel<float, 20, true>"),
-            pk.DM_BF16X3: ("mrd::gemm_ps_kernel<128, 64, 2, 2, false, 0>",
-                           "mrd::gemm_ps_kernel<128, 32, 4, 1, true, 1>")}[prec]
+            pk.DM_BF16X3: bf3[:2]}[prec]
     mixk = {pk.DM_FP64: "mrd::mix_slab_kernel<double, double>",
             pk.DM_FP32: "mrd::mix_slab_kernel<float, float>",
-            pk.DM_BF16X3: "mrd::mix_slab_kernel<float, __bf16>"}[prec]
+            pk.DM_BF16X3: bf3[2]}[prec]
     redk = {pk.DM_FP64: "mrd::gemm_split_reduce_kernel<double, 20, mrd::GemmProb>",
             pk.DM_FP32: "mrd::gemm_split_reduce_kernel<float, 20, mrd::GemmProb>",
-            pk.DM_BF16X3: "mrd::gemm_split_reduce_kernel<float, 144, mrd::PsProb>"}[prec]
+            pk.DM_BF16X3: bf3[3]}[prec]
     traffic = measured_traffic(workload, pname)
     hw = 3 if prec == pk.DM_BF16X3 else 1
     peak_alg = PEAK_TFLOPS[pname] / hw

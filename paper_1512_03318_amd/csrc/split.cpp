@@ -32,6 +32,48 @@ struct Sector {
   int wn() const { return trans ? m : n; }  // workspace columns (<= rows)
 };
 
+// Host check that every element a copy job touches lies inside its buffers (sizes in
+// complex elements; perm / scale tables of the given lengths, permuted indices in range).
+void validate_copies(const std::vector<CopyJob>& jobs, int64_t src_size, int64_t dst_size,
+                     const std::vector<int32_t>& perm, size_t nscale, int64_t src_rows, int64_t src_cols) {
+  for (const CopyJob& j : jobs) {
+    if (j.rows < 0 || j.cols < 0) throw DmError{DM_ERR_LAYOUT, "bad copy job"};
+    if (j.rows == 0 || j.cols == 0) continue;
+    auto span = [](int64_t off, int64_t a, int64_t b, int64_t na, int64_t nb) {
+      // first and last offsets of off + i a + j b over i < na, j < nb (a, b >= 0)
+      return std::make_pair(off, off + (na - 1) * a + (nb - 1) * b);
+    };
+    if (j.s_r < 0 || j.s_c < 0 || j.d_r < 0 || j.d_c < 0) throw DmError{DM_ERR_LAYOUT, "bad copy strides"};
+    int64_t nr = j.rows, nc = j.cols;
+    if (j.rperm >= 0) {
+      if ((size_t)j.rperm + j.rows > perm.size()) throw DmError{DM_ERR_LAYOUT, "copy row table"};
+      int64_t mx = 0;
+      for (int i = 0; i < j.rows; ++i) {
+        const int32_t v = perm[j.rperm + i];
+        if (v < 0 || v >= src_cols) throw DmError{DM_ERR_LAYOUT, "copy row index"};
+        mx = std::max<int64_t>(mx, v);
+      }
+      nr = mx + 1;
+    }
+    if (j.cperm >= 0) {
+      if ((size_t)j.cperm + j.cols > perm.size()) throw DmError{DM_ERR_LAYOUT, "copy column table"};
+      int64_t mx = 0;
+      for (int i = 0; i < j.cols; ++i) {
+        const int32_t v = perm[j.cperm + i];
+        if (v < 0 || v >= src_cols) throw DmError{DM_ERR_LAYOUT, "copy column index"};
+        mx = std::max<int64_t>(mx, v);
+      }
+      nc = mx + 1;
+    }
+    (void)src_rows;
+    const auto s = span(j.src, j.s_r, j.s_c, nr, nc), d = span(j.dst, j.d_r, j.d_c, j.rows, j.cols);
+    if (s.first < 0 || s.second >= src_size) throw DmError{DM_ERR_LAYOUT, "copy source out of bounds"};
+    if (d.first < 0 || d.second >= dst_size) throw DmError{DM_ERR_LAYOUT, "copy target out of bounds"};
+    if ((j.rscale >= 0 && (size_t)j.rscale + j.rows > nscale) || (j.cscale >= 0 && (size_t)j.cscale + j.cols > nscale))
+      throw DmError{DM_ERR_LAYOUT, "copy scale table"};
+  }
+}
+
 }  // namespace
 
 extern "C" int dm_theta_split(int32_t ly, const dm_bond* a_, const dm_bond* c_, const dm_charge qs1[2],
@@ -134,6 +176,11 @@ extern "C" int dm_theta_split(int32_t ly, const dm_bond* a_, const dm_bond* c_, 
         }
         svd.push_back({S->w_off, S->v_off, S->sig_off, S->wm(), S->wn()});
       }
+      for (const SvdJob& J : svd)
+        if (J.n > J.m || J.m <= 0 || J.n <= 0 || J.w_off + (int64_t)J.m * J.n > wtot || J.v_off + (int64_t)J.n * J.n > wtot ||
+            J.sig_off + J.n > stot)
+          throw DmError{DM_ERR_LAYOUT, "split: SVD workspace out of bounds"};
+      validate_copies(gather, th.P.total, wtot, {}, 0, 0, 0);
       const int64_t ng = copy_layout(gather);
       TableUpload up;
       CopyJob* d_gather = nullptr;
@@ -252,6 +299,11 @@ extern "C" int dm_theta_split(int32_t ly, const dm_bond* a_, const dm_bond* c_, 
         }
         ++bi;
       }
+      // permuted indices are workspace columns: below the largest column count
+      int32_t maxw = 0;
+      for (const Sector* S : order) maxw = std::max(maxw, S->wn());
+      validate_copies(lj, wtot, Lt.P.total, perm, scl.size(), 0, maxw);
+      validate_copies(rj, wtot, Rt.P.total, perm, scl.size(), 0, maxw);
       const int64_t nl = copy_layout(lj), nr = copy_layout(rj);
       TableUpload up2;
       CopyJob* d_lj = nullptr;
