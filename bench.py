@@ -192,13 +192,18 @@ def stage_rooflines(pk, plan, prec, pname, prof, nmv, workload):
     eb = 16 if prec == pk.DM_FP64 else 8
     avg = [p / max(nmv, 1) for p in prof]
     # BF16x3: the kernels that split FP32 operands while staging them, or with
-    # MRDMRG_PRESPLIT=1 the kernels on pre-split operands
+    # MRDMRG_PRESPLIT=1 the kernels on pre-split operands (stream-K unless MRDMRG_SK=0)
     presplit = os.environ.get("MRDMRG_PRESPLIT", "0") == "1"
-    bf3 = (("mrd::gemm_ps_kernel<128, 64, 2, 2, false, 0>", "mrd::gemm_ps_kernel<128, 32, 4, 1, true, 1>",
-            "mrd::mix_slab_kernel<float, __bf16>", "mrd::gemm_split_reduce_kernel<float, 144, mrd::PsProb>")
-           if presplit else
-           ("mrd::gemm_bf3_kernel<0, 128, 64, 2, 2, false>", "mrd::gemm_bf3_kernel<148, 128, 32, 4, 1, true>",
-            "mrd::mix_slab_kernel<float, float>", "mrd::gemm_split_reduce_kernel<float, 148, mrd::GemmProb>"))
+    streamk = os.environ.get("MRDMRG_SK", "1") != "0"
+    if presplit and streamk:
+        bf3 = ("mrd::gemm_sk_kernel<0>", "mrd::gemm_sk_kernel<1>", "mrd::mix_slab_kernel<float, __bf16>",
+               "mrd::gemm_sk_reduce_kernel<1>")
+    elif presplit:
+        bf3 = ("mrd::gemm_ps_kernel<128, 64, 2, 2, false, 0>", "mrd::gemm_ps_kernel<128, 32, 4, 1, true, 1>",
+               "mrd::mix_slab_kernel<float, __bf16>", "mrd::gemm_split_reduce_kernel<float, 144, mrd::PsProb>")
+    else:
+        bf3 = ("mrd::gemm_bf3_kernel<0, 128, 64, 2, 2, false>", "mrd::gemm_bf3_kernel<148, 128, 32, 4, 1, true>",
+               "mrd::mix_slab_kernel<float, float>", "mrd::gemm_split_reduce_kernel<float, 148, mrd::GemmProb>")
     gemm = {pk.DM_FP64: ("mrd::gemm_kernel<double, 0, false>", "mrd::gemm_kernel<double, 20, true>"),
             pk.DM_FP32: ("mrd::gemm_kernel<float, 0, false>", "mrd::gemm_kernel<float, 20, true>"),
             pk.DM_BF16X3: bf3[:2]}[prec]

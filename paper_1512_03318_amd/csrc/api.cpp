@@ -96,12 +96,17 @@ static void build_heff_tables(dm_heff_plan& p) {
   const int ly = p.ly;
   const Bond &a = p.a, &c = p.c;
   const int dl = p.w1.dl, dm = p.w1.dr, dr = p.w2.dr;
-  // X panels
+  // X panels.  Rows of X and Z start on 128-byte boundaries (leading dimensions rounded
+  // up to 16 complex elements): a store of a row segment then covers whole cache lines
+  // instead of straddling two.
+  auto ld16 = [](int n) { return (n + 15) / 16 * 16; };
   p.xoff.assign(a.size(), 0);
+  p.xld.assign(a.size(), 0);
   p.xtotal = 0;
   for (int i = 0; i < a.size(); ++i) {
     p.xoff[i] = p.xtotal;
-    p.xtotal += (int64_t)p.L.P.rows[i] * p.th.P.cols[i];
+    p.xld[i] = ld16(p.th.P.cols[i]);
+    p.xtotal += (int64_t)p.L.P.rows[i] * p.xld[i];
   }
   // zap[c'][s12'] = a' with theta block (a', s12', c'), or -1
   std::vector<std::array<int, 4>> zap(c.size(), {-1, -1, -1, -1});
@@ -118,7 +123,7 @@ static void build_heff_tables(dm_heff_plan& p) {
     for (int ai = 0; ai < a.size(); ++ai) {
       const int M = p.L.P.rows[ai], N = p.th.P.cols[ai], K = a.dim[ai];
       if (M == 0 || N == 0) continue;
-      GemmProb pr{p.xoff[ai], M, N, (int32_t)s1.segs.size(), 1, N, -1};
+      GemmProb pr{p.xoff[ai], M, N, (int32_t)s1.segs.size(), 1, p.xld[ai], -1};
       s1.segs.push_back({p.L.P.off[ai], p.th.P.off[ai], K, N, K, 0});
       s1.probs.push_back(pr);
       add_tiles(s1, (int32_t)s1.probs.size() - 1, M, N);
@@ -128,6 +133,7 @@ static void build_heff_tables(dm_heff_plan& p) {
   // Mixing: Z_{c'}[(s12', a'), (w'', c)] = sum_{w, s12} W12[w, s12', s12, w''] X_a[(w, a'), (s12, c)]
   // Z panel per output sector c': rows (s12', a') stacked, columns the R panel's (w'', c).
   p.zoff.assign(c.size(), 0);
+  p.zld.assign(c.size(), 0);
   p.zrows.assign(c.size(), 0);
   p.ztotal = 0;
   std::vector<std::array<int, 4>> zroff(c.size(), {-1, -1, -1, -1});
@@ -141,13 +147,16 @@ static void build_heff_tables(dm_heff_plan& p) {
     }
     p.zrows[ci2] = rows;
     p.zoff[ci2] = p.ztotal;
-    p.ztotal += (int64_t)rows * p.R.P.cols[ci2];
+    p.zld[ci2] = ld16(p.R.P.cols[ci2]);
+    p.ztotal += (int64_t)rows * p.zld[ci2];
   }
   // BF16x3 pre-split operands (bf16 planes, k padded to a multiple of 8): L per ket
   // sector a (M_a x m_a), theta^T per a (N_a x m_a), Z and R per output sector c'
   // (rows x K with K the R panel width).
   if (p.prec == DM_BF16X3) {
-    auto r8 = [](int64_t k) { return (k + 7) / 8 * 8; };
+    // k padded to the chunk width of the stream-K kernels (a multiple of 8 is all the
+    // tiled kernels need)
+    auto r8 = [](int64_t k) { return (k + SK_KC - 1) / SK_KC * SK_KC; };
     p.lsoff.assign(a.size(), 0);
     p.thsoff.assign(a.size(), 0);
     p.zsoff.assign(c.size(), 0);
@@ -169,7 +178,7 @@ static void build_heff_tables(dm_heff_plan& p) {
     }
     for (int ci2 = 0; ci2 < c.size(); ++ci2) {
       const int K = p.R.P.cols[ci2];
-      const int64_t kp = std::max<int64_t>(8, r8(K));  // an empty R panel keeps zero planes
+      const int64_t kp = std::max<int64_t>(SK_KC, r8(K));  // an empty R panel keeps zero planes
       p.zkp[ci2] = (int32_t)kp;
       p.zsoff[ci2] = p.zs_total;
       p.zs_total += 4 * (int64_t)p.zrows[ci2] * kp;
@@ -212,7 +221,7 @@ static void build_heff_tables(dm_heff_plan& p) {
         const int64_t base = p.th.P.off[aip] + p.th.coff[aip][s12p];
         for (int r = 0; r < a.dim[aip]; ++r) s4.rows.push_back(base + (int64_t)r * p.th.P.cols[aip]);
       }
-      if (K > 0) s4.segs.push_back({p.zoff[ci2], p.R.P.off[ci2], K, K, K, 0});
+      if (K > 0) s4.segs.push_back({p.zoff[ci2], p.R.P.off[ci2], p.zld[ci2], K, K, 0});
       s4.probs.push_back(pr);
       add_tiles(s4, (int32_t)s4.probs.size() - 1, M, N);
       s4.flops += 8.0 * M * N * K;
@@ -232,9 +241,9 @@ static void build_heff_tables(dm_heff_plan& p) {
     for (int ai = 0; ai < a.size(); ++ai) {
       const int M = p.L.P.rows[ai], N = p.th.P.cols[ai], K = a.dim[ai];
       if (M == 0 || N == 0) continue;
-      const int kp = (K + 7) / 8 * 8;
+      const int kp = (K + SK_KC - 1) / SK_KC * SK_KC;
       q1.probs.push_back({p.lsoff[ai], p.thsoff[ai], (int64_t)M * kp, (int64_t)N * kp, p.xoff[ai], M, N, kp,
-                          N, -1, 1, -1, 0});
+                          p.xld[ai], -1, 1, -1, 0});
       add_ps_tiles(q1, (int32_t)q1.probs.size() - 1);
       q1.flops += 8.0 * M * N * K;
     }
@@ -259,6 +268,9 @@ static void build_heff_tables(dm_heff_plan& p) {
       add_ps_tiles(q4, (int32_t)q4.probs.size() - 1);
       q4.flops += 8.0 * M * N * K;
     }
+    // stream-K schedules for a persistent grid of one workgroup per CU
+    sk_schedule(q1, p.ncu);
+    sk_schedule(q4, p.ncu);
     validate(q1, p.ls_total, p.ths_total, p.xtotal);
     validate(q4, p.zs_total, p.rs_total, p.n());
     validate(p.lsplit, p.L.P.total, p.ls_total);
@@ -319,14 +331,14 @@ static void build_heff_tables(dm_heff_plan& p) {
   const bool presplit = p.prec == DM_BF16X3;
   std::vector<MixTask> ptasks;
   for (int ci2 = 0; ci2 < c.size(); ++ci2) {
-    const int Kc = p.R.P.cols[ci2];
+    const int Kc = p.R.P.cols[ci2], zl = p.zld[ci2];
     for (int s12p = 0; s12p < 4; ++s12p) {
       const int aip = zap[ci2][s12p];
       if (aip < 0) continue;
       for (int wpp = 0; wpp < dr; ++wpp) {
         const int ci = p.R.c[ci2 * dr + wpp];
         if (ci < 0) continue;
-        MixTask tk{p.zoff[ci2] + (int64_t)zroff[ci2][s12p] * Kc + p.R.coff[ci2 * dr + wpp], Kc,
+        MixTask tk{p.zoff[ci2] + (int64_t)zroff[ci2][s12p] * zl + p.R.coff[ci2 * dr + wpp], zl,
                    a.dim[aip], c.dim[ci], (int32_t)mx.srcs.size(), 0, 0};
         for (const Nz& e : nz[(size_t)s12p * dr + wpp]) {
           const int w = e.w, s12 = e.s12;
@@ -336,7 +348,7 @@ static void build_heff_tables(dm_heff_plan& p) {
           {
             if (p.th.c[ai][s12] != ci || p.L.ap[ai * dl + w] != aip)
               throw DmError{DM_ERR_CHARGE, "MPO charges inconsistent with the bonds"};
-            const int Na = p.th.P.cols[ai];
+            const int Na = p.xld[ai];
             mx.srcs.push_back({p.xoff[ai] + (int64_t)p.L.roff[ai * dl + w] * Na + p.th.coff[ai][s12],
                                Na, 0, v.real(), v.imag()});
             tk.nsrc++;
@@ -416,6 +428,11 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     p->R = envr_layout(p->c, p->w2.qr, ly);
     if ((p->L.P.total > 0 && !L) || (p->R.P.total > 0 && !R))
       throw DmError{DM_ERR_ARG, "null environment"};
+    {
+      int dev = 0;
+      HIPCHK(hipGetDevice(&dev));
+      HIPCHK(hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     build_heff_tables(*p);  // also validates the GEMM stages
     validate(p->mix, p->xtotal, p->ztotal);
     if (prec == DM_BF16X3) validate(p->mixp, p->xtotal, p->zs_total);
@@ -466,7 +483,12 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       p->dRs = dev_alloc(p->rs_total * 2);
       p->dThs = dev_alloc(p->ths_total * 2);
       p->dZs = dev_alloc(p->zs_total * 2);
-      p->dSplitP = dev_alloc(p->s4p.nslots * p->s4p.slot_elems() * 8);
+      // partial tiles of either block GEMM (they run one after the other on one stream)
+      p->dSplitP = dev_alloc(std::max({p->s4p.nslots * p->s4p.slot_elems(), p->s1p.sk_nslots * SK_BM * SK_BN,
+                                       p->s4p.sk_nslots * SK_BM * SK_BN}) * 8);
+      // stream-K kernels unless MRDMRG_SK=0 (the tiled pre-split kernels)
+      const char* k = getenv("MRDMRG_SK");
+      p->streamk = !(k && k[0] == '0');
       if (p->zs_total) HIPCHK(hipMemsetAsync(p->dZs, 0, p->zs_total * 2, s));
       if (p->rs_total) HIPCHK(hipMemsetAsync(p->dRs, 0, p->rs_total * 2, s));
       HIPCHK(launch_split(p->d_lsplit, (int32_t)p->lsplit.size(), p->lsplit_items, (const double*)L,
@@ -558,12 +580,13 @@ void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStrea
     HIPCHK(launch_split(p->d_thsplit, (int32_t)p->thsplit.size(), p->thsplit_items, (const double*)theta,
                         (__bf16*)p->dThs, s, skip));
     mark(0);
-    HIPCHK(launch_gemm_ps(p->s1p, (const __bf16*)p->dLs, (const __bf16*)p->dThs, p->dX, nullptr, s, skip));
+    auto gemm = p->streamk ? launch_gemm_sk : launch_gemm_ps;
+    HIPCHK(gemm(p->s1p, (const __bf16*)p->dLs, (const __bf16*)p->dThs, p->dX, (float*)p->dSplitP, s, skip, {}));
     mark(1);
     HIPCHK(launch_mix_split(p->mixp, (const float*)p->dX, (__bf16*)p->dZs, s, skip));
     mark(2);
-    HIPCHK(launch_gemm_ps(p->s4p, (const __bf16*)p->dZs, (const __bf16*)p->dRs, theta_out, (float*)p->dSplitP,
-                          s, skip, [&] { mark(3); }));
+    HIPCHK(gemm(p->s4p, (const __bf16*)p->dZs, (const __bf16*)p->dRs, theta_out, (float*)p->dSplitP, s, skip,
+                [&] { mark(3); }));
     mark(4);
     return;
   }

@@ -216,6 +216,287 @@ hipError_t launch_gemm_ps(const PsStage& st, const __bf16* A, const __bf16* B, v
 }
 
 // ---------------------------------------------------------------------------------
+// Stream-K persistent form (schedule: internal.hpp, SkTile / SkSeg).  One workgroup per
+// CU walks its run of chunks through SK_NS LDS stages filled by direct global-to-LDS
+// loads (global_load_lds_dwordx4: lane l of a wave writes 16 bytes at the stage address
+// + 16 l, so the swizzle is applied by choosing which global group each lane loads).
+// Eight waves (a 4 x 2 grid of 32 x 32 sub-tiles) share the stages, two per SIMD.
+// While chunk i is multiplied, the loads of chunks i + 1 .. i + SK_NS - 1 are in flight,
+// across tile boundaries too: no staging registers, no per-tile pipeline start.
+//
+// Ordering: each wave issues exactly SK_LPC load instructions per chunk, and vector
+// memory operations complete in issue order, so "my loads of chunk i have landed" is
+// vmcnt <= SK_LPC x (chunks issued after i); the stores at a segment end only add to
+// that count.  Every wave waits so (and for its own LDS reads of the previous chunk),
+// then the workgroup barrier makes the stage complete for all waves, and only after it
+// is the stage of chunk i - 1 refilled.  Rows past M or N load the last valid row (their
+// results are never stored); kp is a multiple of the chunk width, so no k is out of range.
+// The products and their order within a chunk are those of gemm_ps_kernel; the K order
+// within a tile is the chunk order, split at segment boundaries and summed in K order.
+// ---------------------------------------------------------------------------------
+#define MRD_LDS __attribute__((address_space(3)))
+
+namespace {
+
+constexpr int SK_NS = 3;                       // LDS stages
+constexpr int SK_SA = 16 * SK_BM;              // 16-byte slots of A per stage (4 planes x rows x 4)
+constexpr int SK_SB = 16 * SK_BN;
+constexpr int SK_STAGE = SK_SA + SK_SB;
+constexpr int SK_WAVES = 8;                    // two waves per SIMD hide each other's LDS and MFMA waits
+constexpr int SK_LPC = (SK_BM + SK_BN) / 4 / SK_WAVES;  // load instructions per wave per chunk
+constexpr int SK_WM = 4, SK_WN = 2;            // wave grid over the tile
+constexpr int SK_XB = SK_BM / SK_WM / 16, SK_YB = SK_BN / SK_WN / 16;
+static_assert(SK_BM % 64 == 0 && SK_BN % 64 == 0 && SK_KC == 32 && SK_WM * SK_WN == SK_WAVES &&
+              (SK_BM / 4) % SK_WAVES == 0 && (SK_BN / 4) % SK_WAVES == 0, "stream-K tile");
+static_assert((SK_NS - 2) * SK_LPC <= 63, "vmcnt range");
+
+// s_waitcnt with vmcnt <= vm, lgkmcnt = 0, expcnt unconstrained (gfx9 encoding)
+template <int VM>
+__device__ __forceinline__ void sk_waitcnt() {
+  __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4));
+}
+
+// All waves: this wave's loads of the chunk about to be used (all but the last `after`
+// chunks it issued) and its LDS reads have completed; then the workgroup barrier.
+// (sched_barrier keeps the compiler from moving any instruction across the wait and the
+// barrier; an inline-asm memory clobber would do the same but makes the compiler wait
+// for every load in flight.)
+__device__ __forceinline__ void sk_sync(int after) {
+  __builtin_amdgcn_sched_barrier(0);
+  if (after <= 0)
+    sk_waitcnt<0>();
+  else
+    sk_waitcnt<SK_LPC * (SK_NS - 2)>();  // after == SK_NS - 2 (the pipeline's steady state)
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ void sk_issue(MRD_LDS u32x4* __restrict__ st, const SkJob& J, int k0,
+                                         const __bf16* __restrict__ A, const __bf16* __restrict__ B, int wave,
+                                         int lane) {
+  const int rl = lane >> 2, sl = lane & 3;
+#pragma unroll
+  for (int t = 0; t < SK_BM / 4 / SK_WAVES; ++t) {  // A: blocks of 16 rows of one plane
+    const int q = wave + SK_WAVES * t, p = q / (SK_BM / 16), rb = q % (SK_BM / 16);
+    const int r = rb * 16 + rl, g = sl ^ swz(r);
+    const int i = min(J.i0 + r, J.M - 1);
+    const __bf16* src = A + J.a_off + p * J.a_ps + (int64_t)i * J.kp + k0 + 8 * g;
+    __builtin_amdgcn_global_load_lds((const MRD_GLOBAL void*)src, (MRD_LDS void*)(st + p * SK_BM * 4 + rb * 64),
+                                     16, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < SK_BN / 4 / SK_WAVES; ++t) {  // B
+    const int q = wave + SK_WAVES * t, p = q / (SK_BN / 16), rb = q % (SK_BN / 16);
+    const int r = rb * 16 + rl, g = sl ^ swz(r);
+    const int j = min(J.j0 + r, J.N - 1);
+    const __bf16* src = B + J.b_off + p * J.b_ps + (int64_t)j * J.kp + k0 + 8 * g;
+    __builtin_amdgcn_global_load_lds((const MRD_GLOBAL void*)src,
+                                     (MRD_LDS void*)(st + SK_SA + p * SK_BN * 4 + rb * 64), 16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void sk_mma(const MRD_LDS u32x4* __restrict__ st, f32x4 (&cre)[SK_XB][SK_YB],
+                                       f32x4 (&cim)[SK_XB][SK_YB], int wr, int wc, int li, int lk) {
+  bf16x8 b[SK_YB][4];
+#pragma unroll
+  for (int y = 0; y < SK_YB; ++y) {
+    const int r = wc + y * 16 + li;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) b[y][p] = __builtin_bit_cast(bf16x8, st[SK_SA + p * SK_BN * 4 + r * 4 + (lk ^ swz(r))]);
+  }
+#pragma unroll
+  for (int x = 0; x < SK_XB; ++x) {
+    const int r = wr + x * 16 + li;
+    bf16x8 a[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) a[p] = __builtin_bit_cast(bf16x8, st[p * SK_BM * 4 + r * 4 + (lk ^ swz(r))]);
+    const bf16x8 nih = neg8(a[2]), nil = neg8(a[3]);
+#pragma unroll
+    for (int y = 0; y < SK_YB; ++y) {
+      cre[x][y] = mfma_bf16(a[1], b[y][0], cre[x][y]);
+      cim[x][y] = mfma_bf16(a[1], b[y][2], cim[x][y]);
+      cre[x][y] = mfma_bf16(a[0], b[y][1], cre[x][y]);
+      cim[x][y] = mfma_bf16(a[0], b[y][3], cim[x][y]);
+      cre[x][y] = mfma_bf16(nil, b[y][2], cre[x][y]);
+      cim[x][y] = mfma_bf16(a[3], b[y][0], cim[x][y]);
+      cre[x][y] = mfma_bf16(nih, b[y][3], cre[x][y]);
+      cim[x][y] = mfma_bf16(a[2], b[y][1], cim[x][y]);
+      cre[x][y] = mfma_bf16(a[0], b[y][0], cre[x][y]);
+      cim[x][y] = mfma_bf16(a[0], b[y][2], cim[x][y]);
+      cre[x][y] = mfma_bf16(nih, b[y][2], cre[x][y]);
+      cim[x][y] = mfma_bf16(a[2], b[y][0], cim[x][y]);
+    }
+  }
+}
+
+// One stream-K step: wait for chunk i's stage, refill the stage of chunk i - 1 with
+// chunk i + SK_NS - 1 (when there is one), multiply chunk i.
+__device__ __forceinline__ void sk_step(const MRD_LDS u32x4* __restrict__ cur, MRD_LDS u32x4* __restrict__ nxt,
+                                        int after, bool refill, const SkJob& Jn, int k0n,
+                                        const __bf16* __restrict__ A, const __bf16* __restrict__ B,
+                                        f32x4 (&cre)[SK_XB][SK_YB], f32x4 (&cim)[SK_XB][SK_YB], int wave,
+                                        int lane, int wr, int wc, int li, int lk) {
+  sk_sync(after);
+  if (refill) sk_issue(nxt, Jn, k0n, A, B, wave, lane);
+  sk_mma(cur, cre, cim, wr, wc, li, lk);
+}
+
+}  // namespace
+
+template <int COUT>
+__global__ void __launch_bounds__(64 * SK_WAVES) gemm_sk_kernel(const SkJob* __restrict__ jobs,
+                                                               const int32_t* __restrict__ wgseg,
+                                                               const int64_t* __restrict__ rows,
+                                                               const __bf16* __restrict__ A,
+                                                               const __bf16* __restrict__ B,
+                                                               void* __restrict__ C, float* __restrict__ part,
+                                                               const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ u32x4 lds_raw[SK_NS * SK_STAGE];
+  MRD_LDS u32x4* const lds = (MRD_LDS u32x4*)lds_raw;
+  const int w = xcd_tile(blockIdx.x, gridDim.x);  // consecutive runs (neighbouring tiles) share an XCD
+  const int sb = wgseg[w], se = wgseg[w + 1];
+  if (sb >= se) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (wave % SK_WM) * (SK_BM / SK_WM), wc = (wave / SK_WM) * (SK_BN / SK_WN);
+  int total = 0;
+  for (int q = sb; q < se; ++q) total += jobs[q].c1 - jobs[q].c0;
+
+  // issue cursor: job `is` (a copy in `ji`, the next one prefetched in `jn`), chunk `ic`
+  int is = sb, issued = 0;
+  SkJob ji = jobs[sb];
+  SkJob jn = jobs[min(sb + 1, se - 1)];
+  int ic = ji.c0;
+  auto advance = [&] {
+    ++issued;
+    if (++ic == ji.c1 && ++is < se) {
+      ji = jn;
+      ic = ji.c0;
+      jn = jobs[min(is + 1, se - 1)];
+    }
+  };
+  for (int q = 0; q < SK_NS - 1 && issued < total; ++q) {
+    sk_issue(lds + q * SK_STAGE, ji, ic * SK_KC, A, B, wave, lane);
+    advance();
+  }
+
+  f32x4 cre[SK_XB][SK_YB], cim[SK_XB][SK_YB];
+  auto zero = [&] {
+#pragma unroll
+    for (int x = 0; x < SK_XB; ++x)
+#pragma unroll
+      for (int y = 0; y < SK_YB; ++y) {
+        cre[x][y] = f32x4{0, 0, 0, 0};
+        cim[x][y] = f32x4{0, 0, 0, 0};
+      }
+  };
+  zero();
+  int cs = sb, cend = jobs[sb].c1 - jobs[sb].c0;  // compute cursor: job, chunks left in it
+  for (int i = 0; i < total; ++i) {
+    const int after = issued - (i + 1);  // chunks issued after chunk i
+    const bool refill = issued < total;
+    const int sc = i % SK_NS, sn = (i + SK_NS - 1) % SK_NS;
+    sk_step(lds + sc * SK_STAGE, lds + sn * SK_STAGE, after, refill, ji, ic * SK_KC, A, B, cre, cim, wave, lane,
+            wr, wc, li, lk);
+    if (refill) advance();
+    if (--cend > 0) continue;
+    // end of a job: store the tile (slot < 0) or its partial, then start the next
+    const SkJob J = jobs[cs];
+    if (J.slot >= 0) {
+      float* dst = part + 2 * (int64_t)J.slot * (SK_BM * SK_BN);
+#pragma unroll
+      for (int x = 0; x < SK_XB; ++x)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int y = 0; y < SK_YB; ++y)
+            stc(dst, (wr + x * 16 + 4 * lk + r) * SK_BN + wc + y * 16 + li, cre[x][y][r], cim[x][y][r]);
+    } else {
+#pragma unroll
+      for (int x = 0; x < SK_XB; ++x)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = J.i0 + wr + x * 16 + 4 * lk + r;
+          if (gi >= J.M) continue;
+          const int64_t rbase = COUT == 1 ? rows[J.rowmap + gi] : J.c_off + (int64_t)gi * J.ldc;
+#pragma unroll
+          for (int y = 0; y < SK_YB; ++y) {
+            const int gj = J.j0 + wc + y * 16 + li;
+            if (gj >= J.N) continue;
+            if (COUT == 1)
+              stc(static_cast<double*>(C), rbase + gj, (double)cre[x][y][r], (double)cim[x][y][r]);
+            else
+              stc(static_cast<float*>(C), rbase + gj, cre[x][y][r], cim[x][y][r]);
+          }
+        }
+    }
+    // FP64 output: let the row-table loads and stores finish here, once per job
+    // (otherwise the compiler waits for every load in flight at each step)
+    if (COUT == 1) sk_waitcnt<0>();
+    zero();
+    if (++cs < se) cend = jobs[cs].c1 - jobs[cs].c0;
+  }
+}
+
+// Sums the partial tiles of each split tile in K order and stores the result.  Block
+// (x, y): split tile sk_red[x], elements [1024 y, 1024 y + 1024) of the tile.
+template <int COUT>
+__global__ void __launch_bounds__(256) gemm_sk_reduce_kernel(const PsProb* __restrict__ probs,
+                                                             const SkTile* __restrict__ tiles,
+                                                             const int32_t* __restrict__ red,
+                                                             const int64_t* __restrict__ rows,
+                                                             const float* __restrict__ part, void* __restrict__ C,
+                                                             const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const SkTile t = tiles[red[blockIdx.x]];
+  const PsProb P = probs[t.prob];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = blockIdx.y * 1024 + q * 256 + threadIdx.x;
+    if (e >= SK_BM * SK_BN) break;
+    const int r = e / SK_BN, c = e - r * SK_BN;
+    const int i = t.tm * SK_BM + r, j = t.tn * SK_BN + c;
+    if (i >= P.M || j >= P.N) continue;
+    float re = 0.f, im = 0.f;
+    for (int k = 0; k < t.nseg; ++k) {
+      const Cplx<float> v = ldc(part, (int64_t)(t.slot0 + k) * (SK_BM * SK_BN) + e);
+      re += v.re;
+      im += v.im;
+    }
+    const int64_t rb = COUT == 1 ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
+    if (COUT == 1)
+      stc(static_cast<double*>(C), rb + j, (double)re, (double)im);
+    else
+      stc(static_cast<float*>(C), rb + j, re, im);
+  }
+}
+
+hipError_t launch_gemm_sk(const PsStage& st, const __bf16* A, const __bf16* B, void* C, float* part,
+                          hipStream_t s, const int32_t* skip, const std::function<void()>& between) {
+  if (st.sk_grid == 0) return hipSuccess;
+  if (st.sk_nslots > 0 && !part) return hipErrorInvalidValue;
+  if (st.cout == 1) {
+    hipLaunchKernelGGL(gemm_sk_kernel<1>, dim3(st.sk_grid), dim3(64 * SK_WAVES), 0, s, st.d_sk_jobs, st.d_sk_wg,
+                       st.d_rows, A, B, C, part, skip);
+  } else {
+    hipLaunchKernelGGL(gemm_sk_kernel<0>, dim3(st.sk_grid), dim3(64 * SK_WAVES), 0, s, st.d_sk_jobs, st.d_sk_wg,
+                       st.d_rows, A, B, C, part, skip);
+  }
+  if (between) between();
+  if (!st.sk_red.empty()) {
+    const dim3 grid((uint32_t)st.sk_red.size(), (SK_BM * SK_BN + 1023) / 1024);
+    if (st.cout == 1)
+      hipLaunchKernelGGL(gemm_sk_reduce_kernel<1>, grid, dim3(256), 0, s, st.d_probs, st.d_sk_tiles, st.d_sk_red,
+                         st.d_rows, part, C, skip);
+    else
+      hipLaunchKernelGGL(gemm_sk_reduce_kernel<0>, grid, dim3(256), 0, s, st.d_probs, st.d_sk_tiles, st.d_sk_red,
+                         st.d_rows, part, C, skip);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
 // FP64 complex -> split planes.  One item: eight consecutive k values of one
 // destination row (16 bytes per plane).  With trans = 0 the k values are consecutive
 // source columns (one 128-byte read per item); with trans = 1 the destination row is a
@@ -240,9 +521,16 @@ __global__ void __launch_bounds__(256) split_kernel(const SplitJob* __restrict__
   const int ng = J.kp / 8;
   const int drows = J.trans ? J.cols : J.rows, kmax = J.trans ? J.rows : J.cols;
   int row, g;
-  if (J.trans) {  // rows fastest: neighbouring threads read neighbouring source columns
-    row = (int)(local % drows);
-    g = (int)(local / drows);
+  if (J.trans) {
+    // blocks of 16 destination rows x 4 groups per wave, groups fastest: the four lanes
+    // of a row write its 64 contiguous bytes per plane, and each of the wave's loads
+    // reads 16 neighbouring source columns (256 bytes) for each of 4 k values
+    const int nrb = (drows + 15) / 16;
+    const int64_t blk = local >> 6;
+    const int l = (int)(local & 63);
+    row = (int)(blk % nrb) * 16 + (l >> 2);
+    g = (int)(blk / nrb) * 4 + (l & 3);
+    if (row >= drows || g >= ng) return;
   } else {
     row = (int)(local / ng);
     g = (int)(local % ng);

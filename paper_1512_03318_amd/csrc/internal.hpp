@@ -181,6 +181,28 @@ struct PsProb {
   int32_t nks, slot0;
   int32_t pad;
 };
+// Stream-K schedule of a pre-split stage for a persistent grid: the K chunks of all
+// output tiles form one sequence (tile after tile, chunks in K order), cut into equal
+// runs, one per workgroup.  A run is a list of segments (chunks [c0, c1) of one tile); a
+// tile that lies in one segment is stored directly (slot -1), otherwise each of its
+// segments writes a partial tile to its own slot (slot0 + segment index, in K order) and
+// a reduction sums them in that order.
+struct SkTile {
+  int32_t prob, tm, tn, nch;  // nch: chunks of 32 k values (kp / 32)
+  int32_t slot0, nseg;
+};
+struct SkSeg {
+  int32_t tile, c0, c1, slot;
+};
+// One segment as the kernel reads it: everything its loads and its store need, in one
+// record (no dependent table lookups in the chunk loop).
+struct SkJob {
+  int64_t a_off, b_off, a_ps, b_ps, c_off;  // as PsProb
+  int32_t M, N, kp, ldc, rowmap;
+  int32_t i0, j0;   // first row and column of the tile
+  int32_t c0, c1;   // chunks
+  int32_t slot;     // partial slot, or -1: store the tile
+};
 struct PsStage {
   int32_t cout = 0;  // 0: FP32 affine C; 1: FP64 C through the row table
   int32_t tile_m = 128, tile_n = 64;
@@ -197,7 +219,26 @@ struct PsStage {
   GemmTile* d_tiles = nullptr;
   int64_t* d_rows = nullptr;
   GemmTile* d_red_tiles = nullptr;
+  // stream-K schedule (sk_schedule; tiles of SK_BM x SK_BN)
+  int32_t sk_grid = 0;
+  std::vector<SkTile> sk_tiles;
+  std::vector<SkSeg> sk_segs;
+  std::vector<SkJob> sk_jobs;   // per segment (same order)
+  std::vector<int32_t> sk_wg;   // segments of workgroup g: [sk_wg[g], sk_wg[g + 1])
+  std::vector<int32_t> sk_red;  // tiles with more than one segment
+  int64_t sk_nslots = 0;
+  SkTile* d_sk_tiles = nullptr;
+  SkSeg* d_sk_segs = nullptr;
+  SkJob* d_sk_jobs = nullptr;
+  int32_t* d_sk_wg = nullptr;
+  int32_t* d_sk_red = nullptr;
 };
+// Stream-K tile of the pre-split kernels (rows x columns) and chunk width.
+constexpr int SK_BM = 128, SK_BN = 64, SK_KC = 32;
+void sk_schedule(PsStage& st, int grid);  // needs every problem's kp a multiple of SK_KC
+hipError_t launch_gemm_sk(const PsStage& st, const __bf16* A, const __bf16* B, void* C, float* part,
+                          hipStream_t s, const int32_t* skip = nullptr,
+                          const std::function<void()>& between = std::function<void()>());
 hipError_t launch_gemm_ps(const PsStage& st, const __bf16* A, const __bf16* B, void* C, float* part,
                           hipStream_t s, const int32_t* skip = nullptr,
                           const std::function<void()>& between = std::function<void()>());

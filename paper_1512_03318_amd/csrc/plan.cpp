@@ -324,6 +324,8 @@ void add_ps_tiles(PsStage& st, int32_t prob) {
     }
 }
 
+static void validate_sk(const PsStage& st);
+
 void validate(const PsStage& st, int64_t a_size, int64_t b_size, int64_t c_size) {
   for (const std::vector<GemmTile>* tl : {&st.tiles, &st.red_tiles})
     for (const GemmTile& t : *tl) {
@@ -356,14 +358,122 @@ void validate(const PsStage& st, int64_t a_size, int64_t b_size, int64_t c_size)
       range_check(p.c_off, p.c_off + (int64_t)(p.M - 1) * p.ldc + p.N - 1, c_size, "pre-split C");
     }
   }
+  validate_sk(st);
+}
+
+void sk_schedule(PsStage& st, int grid) {
+  st.sk_tiles.clear();
+  st.sk_segs.clear();
+  st.sk_wg.assign(1, 0);
+  st.sk_red.clear();
+  st.sk_nslots = 0;
+  st.sk_grid = 0;
+  // tiles in problem order, each with its chunk count; chunk sequence offsets
+  std::vector<int64_t> first;
+  int64_t total = 0;
+  for (int32_t q = 0; q < (int32_t)st.probs.size(); ++q) {
+    const PsProb& p = st.probs[q];
+    if (p.M <= 0 || p.N <= 0 || p.kp <= 0 || p.kp % SK_KC) throw err(DM_ERR_LAYOUT, "bad stream-K problem");
+    const int tm = (p.M + SK_BM - 1) / SK_BM, tn = (p.N + SK_BN - 1) / SK_BN;
+    for (int a = 0; a < tm; ++a)
+      for (int b = 0; b < tn; ++b) {
+        st.sk_tiles.push_back({q, a, b, p.kp / SK_KC, -1, 0});
+        first.push_back(total);
+        total += p.kp / SK_KC;
+      }
+  }
+  if (total == 0) return;
+  const int g = (int)std::max<int64_t>(1, std::min<int64_t>(grid, total));
+  st.sk_grid = g;
+  // workgroup w: chunks [w * total / g, (w + 1) * total / g), cut at tile boundaries
+  size_t t = 0;
+  for (int w = 0; w < g; ++w) {
+    int64_t lo = total * w / g;
+    const int64_t hi = total * (w + 1) / g;
+    while (lo < hi) {
+      while (first[t] + st.sk_tiles[t].nch <= lo) ++t;
+      const int64_t end = std::min(hi, first[t] + st.sk_tiles[t].nch);
+      st.sk_segs.push_back({(int32_t)t, (int32_t)(lo - first[t]), (int32_t)(end - first[t]), -1});
+      st.sk_tiles[t].nseg++;
+      lo = end;
+    }
+    st.sk_wg.push_back((int32_t)st.sk_segs.size());
+  }
+  // partial slots of split tiles, in K order within each tile
+  for (size_t i = 0; i < st.sk_tiles.size(); ++i)
+    if (st.sk_tiles[i].nseg > 1) {
+      st.sk_tiles[i].slot0 = (int32_t)st.sk_nslots;
+      st.sk_nslots += st.sk_tiles[i].nseg;
+      st.sk_red.push_back((int32_t)i);
+    }
+  std::vector<int32_t> seen(st.sk_tiles.size(), 0);
+  for (SkSeg& sg : st.sk_segs) {  // segments of one tile appear in K order
+    const SkTile& tl = st.sk_tiles[sg.tile];
+    if (tl.nseg > 1) sg.slot = tl.slot0 + seen[sg.tile];
+    seen[sg.tile]++;
+  }
+  st.sk_jobs.clear();
+  st.sk_jobs.reserve(st.sk_segs.size());
+  for (const SkSeg& sg : st.sk_segs) {
+    const SkTile& tl = st.sk_tiles[sg.tile];
+    const PsProb& p = st.probs[tl.prob];
+    st.sk_jobs.push_back({p.a_off, p.b_off, p.a_ps, p.b_ps, p.c_off, p.M, p.N, p.kp, p.ldc, p.rowmap,
+                          tl.tm * SK_BM, tl.tn * SK_BN, sg.c0, sg.c1, sg.slot});
+  }
+}
+
+// The stream-K schedule covers every chunk of every tile exactly once, in K order
+// within each tile; slots and tables are in range.
+static void validate_sk(const PsStage& st) {
+  if (st.sk_tiles.empty()) return;
+  if (st.sk_grid <= 0 || (int)st.sk_wg.size() != st.sk_grid + 1 || st.sk_wg[0] != 0 ||
+      st.sk_wg.back() != (int32_t)st.sk_segs.size())
+    throw err(DM_ERR_LAYOUT, "bad stream-K workgroup table");
+  for (size_t w = 0; w + 1 < st.sk_wg.size(); ++w)
+    if (st.sk_wg[w] > st.sk_wg[w + 1]) throw err(DM_ERR_LAYOUT, "bad stream-K workgroup table");
+  std::vector<int32_t> next(st.sk_tiles.size(), 0), nseg(st.sk_tiles.size(), 0);
+  for (const SkSeg& sg : st.sk_segs) {
+    if (sg.tile < 0 || sg.tile >= (int32_t)st.sk_tiles.size()) throw err(DM_ERR_LAYOUT, "bad stream-K segment");
+    const SkTile& tl = st.sk_tiles[sg.tile];
+    if (sg.c0 != next[sg.tile] || sg.c1 <= sg.c0 || sg.c1 > tl.nch) throw err(DM_ERR_LAYOUT, "bad stream-K segment");
+    next[sg.tile] = sg.c1;
+    if (tl.nseg > 1 ? (sg.slot != tl.slot0 + nseg[sg.tile] || sg.slot < 0 || sg.slot >= st.sk_nslots) : sg.slot != -1)
+      throw err(DM_ERR_LAYOUT, "bad stream-K slot");
+    nseg[sg.tile]++;
+  }
+  for (size_t i = 0; i < st.sk_tiles.size(); ++i) {
+    const SkTile& tl = st.sk_tiles[i];
+    if (tl.prob < 0 || tl.prob >= (int32_t)st.probs.size()) throw err(DM_ERR_LAYOUT, "bad stream-K tile");
+    const PsProb& p = st.probs[tl.prob];
+    if (p.kp % SK_KC || tl.nch != p.kp / SK_KC || next[i] != tl.nch || nseg[i] != tl.nseg || tl.tm < 0 ||
+        tl.tn < 0 || tl.tm * SK_BM >= p.M || tl.tn * SK_BN >= p.N)
+      throw err(DM_ERR_LAYOUT, "bad stream-K tile");
+  }
+  for (int32_t r : st.sk_red)
+    if (r < 0 || r >= (int32_t)st.sk_tiles.size() || st.sk_tiles[r].nseg < 2) throw err(DM_ERR_LAYOUT, "bad stream-K reduction");
+  // the job records repeat their segment, tile and problem
+  if (st.sk_jobs.size() != st.sk_segs.size()) throw err(DM_ERR_LAYOUT, "bad stream-K jobs");
+  for (size_t q = 0; q < st.sk_segs.size(); ++q) {
+    const SkSeg& sg = st.sk_segs[q];
+    const SkTile& tl = st.sk_tiles[sg.tile];
+    const PsProb& p = st.probs[tl.prob];
+    const SkJob& j = st.sk_jobs[q];
+    if (j.a_off != p.a_off || j.b_off != p.b_off || j.a_ps != p.a_ps || j.b_ps != p.b_ps || j.c_off != p.c_off ||
+        j.M != p.M || j.N != p.N || j.kp != p.kp || j.ldc != p.ldc || j.rowmap != p.rowmap ||
+        j.i0 != tl.tm * SK_BM || j.j0 != tl.tn * SK_BN || j.c0 != sg.c0 || j.c1 != sg.c1 || j.slot != sg.slot)
+      throw err(DM_ERR_LAYOUT, "bad stream-K job");
+  }
 }
 
 int64_t split_layout(std::vector<SplitJob>& jobs) {
   int64_t n = 0;
   for (SplitJob& j : jobs) {
     j.i0 = n;
-    const int drows = j.trans ? j.cols : j.rows;
-    n += (int64_t)drows * (j.kp / 8);
+    const int drows = j.trans ? j.cols : j.rows, ng = j.kp / 8;
+    if (j.trans)  // blocks of 16 rows x 4 groups (split_kernel), partial blocks padded
+      n += (int64_t)((drows + 15) / 16) * ((ng + 3) / 4) * 64;
+    else
+      n += (int64_t)drows * ng;
   }
   return n;
 }

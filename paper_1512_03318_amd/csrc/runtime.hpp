@@ -101,6 +101,11 @@ struct TableUpload {
     add(st.tiles, &st.d_tiles);
     add(st.rows, &st.d_rows);
     add(st.red_tiles, &st.d_red_tiles);
+    add(st.sk_tiles, &st.d_sk_tiles);
+    add(st.sk_segs, &st.d_sk_segs);
+    add(st.sk_jobs, &st.d_sk_jobs);
+    add(st.sk_wg, &st.d_sk_wg);
+    add(st.sk_red, &st.d_sk_red);
   }
   void add(MixStage& st) {
     add(st.tasks, &st.d_tasks);
@@ -164,6 +169,7 @@ struct dm_heff_plan {
   mrd::EnvLLayout L;
   mrd::EnvRLayout R;
   std::vector<int64_t> xoff;  // per a: X panel offset (rows = L.P.rows[a], cols = th.P.cols[a])
+  std::vector<int> xld;       // per a: X panel leading dimension (cols rounded up to 16)
   int64_t xtotal = 0;
   mrd::GemmStage s1, s4;
   mrd::GemmStage s1f, s4f;  // DM_BF16X3: the stages in FP kernel shapes (FP64 Rayleigh quotient)
@@ -189,12 +195,15 @@ struct dm_heff_plan {
   void* dZs = nullptr;
   void* dSplitP = nullptr;  // K-split partial tiles of the pre-split (.).R stage
   bool presplit = false;    // BF16x3 matvec on the pre-split operands
+  bool streamk = false;     // ... through the stream-K kernels
+  int ncu = 1;              // compute units of the plan's device
   // the Lanczos kernels write an FP32 copy of v_j that the matvec reads
   bool staged_in() const { return prec == DM_FP32 || (prec == DM_BF16X3 && !presplit); }
   void* dTables = nullptr;      // all task tables (one pool block)
   hipEvent_t done = nullptr;    // recorded after every use; waited on before release
   double mix_flops = 0;
   std::vector<int64_t> zoff;  // per c': Z panel offset (rows zrows[c'], cols R.P.cols[c'])
+  std::vector<int> zld;       // per c': Z panel leading dimension (cols rounded up to 16)
   std::vector<int> zrows;
   int64_t ztotal = 0;
   void* dZ = nullptr;

@@ -64,7 +64,10 @@ def test_batched_equals_single(prec, tuned, monkeypatch):
             xs = x0[i].clone()
             es, ks = pk.lanczos_ground(p, xs, 30, 1e-14)
             assert kb[i] == ks, (rep, i)
-            if tuned:
+            # untuned batches run the single plans' kernels and tiles, so FP64 and FP32
+            # results are the same bit for bit; a BF16x3 plan's own matvec runs on
+            # pre-split operands (stream-K order), the batch on FP32 operands
+            if tuned or prec == pk.DM_BF16X3:
                 assert abs(eb[i] - es) <= 100 * TOL[prec] * abs(es), (rep, i, eb[i], es)
                 assert 1 - abs(complex(torch.vdot(xb[i], xs))) <= 100 * TOL[prec], (rep, i)
             else:
