@@ -246,11 +246,64 @@ def deparallelise(mpo: MPO, max_rounds: int = 50) -> MPO:
     return MPO(W, q, mpo.qsite.copy(), mpo.ly, keys)
 
 
-def build(cyl, basis: str, merge: bool = True) -> MPO:
-    """Hofstadter MPO of eq. H_real ("real") or eqs. H_kin + H_int ("mixed")."""
+def _branch_partner(key):
+    """The state of the other phase branch with the same roles and charge, or None.
+    Only the intra-ring family carries a branch: key = ("intra", x, s, mask, dN, dk)."""
+    if len(key) == 6 and key[0] == "intra":
+        return ("intra", key[1], -key[2]) + key[3:]
+    return None
+
+
+def rotate_real(mpo: MPO) -> MPO:
+    """Eq. rot: rewrite the complex phases of the mixed-basis MPO with real arithmetic.
+
+    The two branches s = +-1 of the intra-ring term carry conjugate phases e^{+-i alpha}
+    and are otherwise the same, so at every bond conj(W) = P W P, where P swaps each
+    branch pair (p, m) and fixes every other state.  With the bond basis change T that
+    maps a pair to ((e_p + e_m) / sqrt2, i (e_p - e_m) / sqrt2) (conj(T) = P T), the
+    rotated W'[i] = T_i^{-1} W[i] T_{i+1} obeys conj(W') = W', i.e. it is real; this is
+    the similarity of eq. rot written per pair (diag(e^{i a}, e^{-i a}) becomes the
+    rotation by a).  The bond dimension and the states' charges are unchanged (a pair
+    shares its charge).  Applied to the finite-state machine's MPO (with state keys)."""
+    n = mpo.n_sites
+    T, Tinv = [], []
+    for b in range(n + 1):
+        keys = mpo.keys[b]
+        idx = {k: j for j, k in enumerate(keys)}
+        t = np.eye(len(keys), dtype=np.complex128)
+        for j, k in enumerate(keys):
+            q = _branch_partner(k)
+            if q is None or k[2] != 1:
+                continue
+            m = idx.get(q)
+            if m is None:
+                raise AssertionError(f"branch state {k} has no partner at bond {b}")
+            t[:, j] = 0.0
+            t[:, m] = 0.0
+            t[j, j], t[m, j] = 1 / np.sqrt(2), 1 / np.sqrt(2)
+            t[j, m], t[m, m] = 1j / np.sqrt(2), -1j / np.sqrt(2)
+        T.append(t)
+        Tinv.append(np.linalg.inv(t))
+    W = []
+    for i in range(n):
+        w = np.einsum("ab,bstc,cd->astd", Tinv[i], mpo.W[i], T[i + 1])
+        scale = max(np.abs(w).max(), 1.0)
+        if np.abs(w.imag).max() > 1e-12 * scale:
+            raise AssertionError(f"rotated MPO not real at site {i}")
+        W.append(w.real.astype(np.complex128))
+    return MPO(W, [q.copy() for q in mpo.qbond], mpo.qsite.copy(), mpo.ly, [list(k) for k in mpo.keys])
+
+
+def build(cyl, basis: str, merge: bool = True, real: bool = False) -> MPO:
+    """Hofstadter MPO of eq. H_real ("real") or eqs. H_kin + H_int ("mixed"); with real=True
+    (mixed basis) the phases rewritten by eq. rot, so every entry is real."""
     from .model import terms_for, orbital_momenta
     ly = cyl.Ly if basis == "mixed" else 1
     m = fsm_mpo(cyl.n_orb, terms_for(cyl, basis), orbital_momenta(cyl, basis), ly)
+    if real:
+        if basis != "mixed":
+            raise ValueError("eq. rot applies to the mixed basis")
+        m = rotate_real(m)
     return deparallelise(m) if merge else m
 
 

@@ -26,7 +26,7 @@ def cylinder_of(wl) -> Cylinder:
 def window_problem(wl, mpo=None):
     """(L, W1, W2, R, theta0, theta_keys, mpo) for the window (j, j+1) of a workload."""
     if mpo is None:
-        mpo = mpo_mod.build(cylinder_of(wl), wl.basis)
+        mpo = mpo_mod.build(cylinder_of(wl), wl.basis, real=getattr(wl, "real", False))
     j = wl.j
     L = bs.left_boundary()
     for i in range(j):

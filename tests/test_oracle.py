@@ -119,6 +119,81 @@ def test_mpo_contracts_to_hamiltonian(Lx, Ly, flux, basis):
     assert max(merged.bond_dims()) <= max(raw.bond_dims())
 
 
+@pytest.mark.parametrize("Lx,Ly,flux", SMALL + [(3, 4, Fraction(1, 4))])
+def test_eq_rot_mpo_is_real_and_exact(Lx, Ly, flux):
+    """Eq. rot: the mixed-basis MPO rewritten with real numbers only; it keeps the
+    machine's bond dimension (Sec. IV D) and charges and still contracts to H."""
+    cyl = model.Cylinder(Ly, Lx, flux, 1.0, 1.0)
+    raw = mpo.build(cyl, "mixed", merge=False)
+    rot = mpo.build(cyl, "mixed", merge=False, real=True)
+    merged = mpo.build(cyl, "mixed", real=True)
+    assert rot.bond_dims() == raw.bond_dims()
+    assert any(np.abs(w.imag).max() > 0 for w in raw.W)      # the phases were complex
+    H = ed.hamiltonian(model.mixed_terms(cyl), ed.sector_basis(cyl.n_orb)).toarray()
+    for m in (rot, merged):
+        assert all(np.abs(w.imag).max() == 0 for w in m.W)
+        mpo.check_charges(m)
+        if cyl.n_orb <= 12:
+            assert np.abs(mpo.to_dense(m) - H).max() < 1e-12
+
+
+def test_eq_rot_turns_a_phase_pair_into_a_rotation():
+    """A transition between two branch pairs that carries (e^{i t}, e^{-i t}) on the
+    diagonal becomes the real 2 x 2 rotation [[cos t, -sin t], [sin t, cos t]]: the
+    similarity of eq. rot, read off the machine's own states."""
+    cyl = model.Cylinder(4, 2, Fraction(1, 4), 1.0, 1.0)
+    raw = mpo.build(cyl, "mixed", merge=False)
+    rot = mpo.build(cyl, "mixed", merge=False, real=True)
+    seen = 0
+    for i, w in enumerate(raw.W):
+        kin, kout = raw.keys[i], raw.keys[i + 1]
+        jin = {k: j for j, k in enumerate(kin)}
+        jout = {k: j for j, k in enumerate(kout)}
+        for p, k in enumerate(kin):
+            q = mpo._branch_partner(k)
+            if q is None or k[2] != 1:
+                continue
+            m = jin[q]
+            for pp, ko in enumerate(kout):
+                qo = mpo._branch_partner(ko)
+                if qo is None or ko[2] != 1:
+                    continue
+                mm = jout[qo]
+                for sp_, s in ((1, 0), (0, 1), (1, 1), (0, 0)):
+                    c = w[p, sp_, s, pp]
+                    if abs(c) < 1e-12 or abs(c.imag) < 1e-9:
+                        continue
+                    # conjugate branch carries conj(c), no cross terms
+                    assert abs(w[m, sp_, s, mm] - np.conj(c)) < 1e-13
+                    assert abs(w[p, sp_, s, mm]) == 0 and abs(w[m, sp_, s, pp]) == 0
+                    blk = rot.W[i][np.ix_([p, m], [sp_], [s], [pp, mm])][:, 0, 0, :]
+                    want = np.array([[c.real, -c.imag], [c.imag, c.real]])
+                    assert np.abs(blk - want).max() < 1e-13
+                    seen += 1
+    assert seen > 0
+
+
+def test_real_window_heff_is_real_and_equals_ed():
+    """A window of the real formulation (real MPO, real isometries and theta): every
+    block of L, R and H_eff theta is real, and <theta2|H_eff theta1> equals
+    <psi2|H|psi1> with H from exact diagonalisation."""
+    wl = workloads.make_workload("pin", 3, 4, (1, 3), 16, 7, real=True)
+    L, W1, W2, R, th1, keys, m = synth.window_problem(wl)
+    assert all(np.abs(w.imag).max() == 0 for w in m.W)
+    for env in (L, R):
+        assert max(np.abs(b.imag).max() for b in env.values()) == 0
+    rng = np.random.default_rng(1)
+    th2 = {k: rng.standard_normal(v.shape) + 0j for k, v in th1.items()}
+    h1 = bs.heff_apply(L, W1, W2, R, th1)
+    assert max(np.abs(b.imag).max() for b in h1.values()) == 0
+    cyl = synth.cylinder_of(wl)
+    H = ed.hamiltonian(model.terms_for(cyl, "mixed"), ed.sector_basis(wl.n))
+    p1, p2 = mps_vector(wl, th1), mps_vector(wl, th2)
+    lhs = np.vdot(p2, H @ p1)
+    rhs = np.vdot(bs.flatten(th2, keys), bs.flatten(h1, keys))
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
 @pytest.mark.parametrize("L", [3, 4, 5])
 def test_real_space_bond_dimension(L):
     cyl = model.Cylinder(L, 4, Fraction(1, L), 1.0, 1.0)

@@ -13,7 +13,9 @@ Recipe (each step is a workload choice, not part of the method):
   isometry from (s, c) to b;
 * isometries: complex Gaussian entries (real and imaginary parts N(0, 1/2)), QR per
   charge block, columns rephased so that diag(R) > 0; one numpy generator per site from
-  ``SeedSequence(seed).spawn(n + 1)``, the last one for the two-site wavefunction.
+  ``SeedSequence(seed).spawn(n + 1)``, the last one for the two-site wavefunction;
+* ``real=True`` (mixed basis only): the same recipe with real N(0, 1) entries, for the
+  real formulation of the mixed-basis Hamiltonian (eq. rot) whose MPO is real.
 """
 from __future__ import annotations
 
@@ -97,26 +99,30 @@ def bond_sectors(n: int, qsite, ly: int, chi: int, N_tot: int, K_tot: int,
     return [dict(sorted(bd.items())) for bd in bonds]
 
 
-def _gauss(rng, shape):
+def _gauss(rng, shape, real=False):
+    """Complex Gaussian (real and imaginary parts N(0, 1/2)), or with real=True real
+    N(0, 1) entries (stored complex with zero imaginary parts)."""
+    if real:
+        return rng.standard_normal(shape).astype(np.complex128)
     return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / sqrt(2.0)
 
 
-def _isometry(rng, rows: int, cols: int) -> np.ndarray:
+def _isometry(rng, rows: int, cols: int, real=False) -> np.ndarray:
     if rows < cols:
         raise ValueError("isometry needs rows >= cols")
-    q, r = np.linalg.qr(_gauss(rng, (rows, cols)))
+    q, r = np.linalg.qr(_gauss(rng, (rows, cols), real))
     d = np.diag(r)
     return q * (d / np.abs(d))[None, :]
 
 
-def left_isometry(rng, bl: dict, br: dict, qs, ly: int) -> dict:
+def left_isometry(rng, bl: dict, br: dict, qs, ly: int, real=False) -> dict:
     """A[a, s, b] with sum_{a,s} conj(A[a,s,b]) A[a,s,b'] = delta_{bb'}; blocks keyed (qa, s, qb)."""
     out = {}
     for qb, mb in br.items():
         parts = [(s, _sub(qb, qs[s], ly)) for s in (0, 1)]
         parts = [(s, qa) for s, qa in parts if qa in bl]
         rows = sum(bl[qa] for _, qa in parts)
-        q = _isometry(rng, rows, mb)
+        q = _isometry(rng, rows, mb, real)
         r0 = 0
         for s, qa in parts:
             out[(qa, s, qb)] = q[r0:r0 + bl[qa]].copy()
@@ -124,14 +130,14 @@ def left_isometry(rng, bl: dict, br: dict, qs, ly: int) -> dict:
     return out
 
 
-def right_isometry(rng, bl: dict, br: dict, qs, ly: int) -> dict:
+def right_isometry(rng, bl: dict, br: dict, qs, ly: int, real=False) -> dict:
     """B[b, s, c] with sum_{s,c} B[b,s,c] conj(B[b',s,c]) = delta_{bb'}; blocks keyed (qb, s, qc)."""
     out = {}
     for qb, mb in bl.items():
         parts = [(s, _add(qb, qs[s], ly)) for s in (0, 1)]
         parts = [(s, qc) for s, qc in parts if qc in br]
         cols = sum(br[qc] for _, qc in parts)
-        q = _isometry(rng, cols, mb).conj().T          # (mb, cols), orthonormal rows
+        q = _isometry(rng, cols, mb, real).conj().T    # (mb, cols), orthonormal rows
         c0 = 0
         for s, qc in parts:
             out[(qb, s, qc)] = q[:, c0:c0 + br[qc]].copy()
@@ -151,7 +157,7 @@ def random_site(rng, bl: dict, br: dict, qs, ly: int) -> dict:
     return out
 
 
-def random_theta(rng, ba: dict, bc: dict, qs1, qs2, ly: int) -> dict:
+def random_theta(rng, ba: dict, bc: dict, qs1, qs2, ly: int, real=False) -> dict:
     """Two-site wavefunction theta[a, s1, s2, c], blocks keyed (qa, s1, s2, qc), unnormalised."""
     out = {}
     for qa, ma in ba.items():
@@ -159,11 +165,11 @@ def random_theta(rng, ba: dict, bc: dict, qs1, qs2, ly: int) -> dict:
             for s2 in (0, 1):
                 qc = _add(_add(qa, qs1[s1], ly), qs2[s2], ly)
                 if qc in bc:
-                    out[(qa, s1, s2, qc)] = _gauss(rng, (ma, bc[qc]))
+                    out[(qa, s1, s2, qc)] = _gauss(rng, (ma, bc[qc]), real)
     return out
 
 
-def random_env(rng, bond: dict, qw, ly: int, side: str) -> dict:
+def random_env(rng, bond: dict, qw, ly: int, side: str, real=False) -> dict:
     """Random environment blocks with the block structure of a left (side="L",
     q(a') = q(a) + q(w)) or right (side="R", same rule on (c', c)) environment on
     ``bond`` with MPO state charges ``qw`` (given by the caller).  Keys (q', w, q)."""
@@ -172,7 +178,7 @@ def random_env(rng, bond: dict, qw, ly: int, side: str) -> dict:
         for q, m in bond.items():
             qp = _add(q, (int(qwv[0]), int(qwv[1])), ly)
             if qp in bond:
-                out[(qp, w, q)] = _gauss(rng, (bond[qp], m))
+                out[(qp, w, q)] = _gauss(rng, (bond[qp], m), real)
     return out
 
 
@@ -193,6 +199,7 @@ class Workload:
     seed: int
     basis: str = "mixed"
     j: int = -1
+    real: bool = False   # real entries (the eq. rot formulation of the mixed basis)
     bonds: list = field(default_factory=list, repr=False)
     qsite: list = field(default_factory=list, repr=False)
 
@@ -212,24 +219,26 @@ class Workload:
     def site_tensor(self, i: int) -> dict:
         """Left isometry for i < j, right isometry for i > j + 1."""
         if i < self.j:
-            return left_isometry(self.rng(i), self.bonds[i], self.bonds[i + 1], self.qsite[i], self.ly)
+            return left_isometry(self.rng(i), self.bonds[i], self.bonds[i + 1], self.qsite[i], self.ly,
+                                 self.real)
         if i > self.j + 1:
-            return right_isometry(self.rng(i), self.bonds[i], self.bonds[i + 1], self.qsite[i], self.ly)
+            return right_isometry(self.rng(i), self.bonds[i], self.bonds[i + 1], self.qsite[i], self.ly,
+                                  self.real)
         raise ValueError("sites j and j+1 belong to the two-site window")
 
     def right_canonical_mps(self) -> list:
         """Right isometries on every site (a normalised random state with the target charge)."""
-        return [right_isometry(self.rng(i), self.bonds[i], self.bonds[i + 1], self.qsite[i], self.ly)
-                for i in range(self.n)]
+        return [right_isometry(self.rng(i), self.bonds[i], self.bonds[i + 1], self.qsite[i], self.ly,
+                               self.real) for i in range(self.n)]
 
     def theta(self) -> dict:
         j = self.j
         return random_theta(self.rng(self.n), self.bonds[j], self.bonds[j + 2],
-                            self.qsite[j], self.qsite[j + 1], self.ly)
+                            self.qsite[j], self.qsite[j + 1], self.ly, self.real)
 
 
 def make_workload(name, Ly, Lx, flux, chi, seed, t=1.0, V=1.0, N_tot=None, K_tot=0,
-                  sigma_N=None, basis="mixed", j=None) -> Workload:
+                  sigma_N=None, basis="mixed", j=None, real=False) -> Workload:
     n = Lx * Ly
     if N_tot is None:
         N_tot = (Lx * Ly) // (2 * flux[1])        # half of the lowest band
@@ -239,19 +248,21 @@ def make_workload(name, Ly, Lx, flux, chi, seed, t=1.0, V=1.0, N_tot=None, K_tot
         j = n // 2 - 1
     ly = Ly if basis == "mixed" else 1
     qsite = site_charges(Lx, Ly, basis)
-    wl = Workload(name, Ly, Lx, tuple(flux), t, V, chi, N_tot, K_tot % ly, sigma_N, seed, basis, j)
+    if real and basis != "mixed":
+        raise ValueError("real entries are the eq. rot form of the mixed basis")
+    wl = Workload(name, Ly, Lx, tuple(flux), t, V, chi, N_tot, K_tot % ly, sigma_N, seed, basis, j, real=real)
     wl.qsite = qsite
     wl.bonds = bond_sectors(n, qsite, ly, chi, N_tot, K_tot % ly, sigma_N)
     return wl
 
 
-def centre_workload(name, Ly, chi, seed, basis="mixed", V=1.0) -> Workload:
+def centre_workload(name, Ly, chi, seed, basis="mixed", V=1.0, real=False) -> Workload:
     """Centre-bond problem at flux 1/Ly: Lx starts at 2 Ly and doubles until the clipped
     bond dimension at the window reaches 0.95 chi (a dilute cylinder clips the extreme
     particle-number sectors)."""
     Lx = 2 * Ly
     while True:
-        wl = make_workload(name, Ly, Lx, (1, Ly), chi, seed, V=V, basis=basis)
+        wl = make_workload(name, Ly, Lx, (1, Ly), chi, seed, V=V, basis=basis, real=real)
         if sum(wl.bonds[wl.j].values()) >= 0.95 * chi or Lx >= 64 * Ly:
             return wl
         Lx *= 2
@@ -271,7 +282,7 @@ PRESETS = {
 }
 
 
-def preset(name: str, basis: str = "mixed") -> Workload:
-    """Named centre-bond workloads (see PRESETS)."""
+def preset(name: str, basis: str = "mixed", real: bool = False) -> Workload:
+    """Named centre-bond workloads (see PRESETS); real=True: real entries (eq. rot)."""
     Ly, chi, seed = PRESETS[name]
-    return centre_workload(name, Ly, chi, seed, basis=basis)
+    return centre_workload(name, Ly, chi, seed, basis=basis, real=real)
