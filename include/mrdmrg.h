@@ -90,6 +90,16 @@ typedef struct ihipStream_t* dm_stream; /* hipStream_t; NULL is the default stre
 #define DM_FP64 0
 #define DM_FP32 1
 #define DM_BF16X3 2 /* hi/lo bfloat16 split of FP32 operands, FP32 accumulation */
+/* OR'ed into DM_FP64 or DM_FP32 (dm_heff_plan_create, env_update_left / _right and the
+ * allocation-free variant): real operands, the formulation of eq. rot (Sec. IV D) in
+ * which the mixed-basis MPO (dm_mpo_hofstadter basis 2), theta and the environments are
+ * real.  Every tensor argument is then an array of float64 values in the same block
+ * layout as its complex128 form (dm_layout: element counts and offsets are unchanged,
+ * each element is one double); the MPO site tensors are still passed as complex128 and
+ * must have zero imaginary parts (DM_ERR_ARG otherwise).  A real plan's flop counts
+ * (dm_heff_info) are 2 per real multiply-add.  Real plans are not batched and not used
+ * by the sweep. */
+#define DM_REAL 16
 
 typedef struct {
   int32_t n;
@@ -335,7 +345,10 @@ int dm_entanglement(const double* values, int64_t count, double* entropy, double
  * periodic in y, flux 2 pi p/q per plaquette, in the mixed basis of eqs. H_kin and
  * H_int (basis = 0; orbital x*Ly + m, charges (1, m) mod Ly) or the real-space basis of
  * eq. H_real (basis = 1; orbital x*Ly + y, charges (1, 0), ly = 1), by the finite-state
- * machine of Sec. IV with exact merging of proportional states.  The MPO lives in the
+ * machine of Sec. IV with exact merging of proportional states.  basis = 2: the mixed
+ * basis in the real form of eq. rot (Sec. IV D): the two phase branches of the
+ * intra-ring interaction are rotated into cos / sin combinations at every bond, so every
+ * entry is real (returned with zero imaginary parts); same charges and bond dimensions.  The MPO lives in the
  * library; query site tensors with dm_mpo_site_get (pointers stay valid until
  * dm_mpo_destroy). */
 typedef struct dm_mpo dm_mpo;

@@ -266,11 +266,11 @@ def rotate_real(mpo: MPO) -> MPO:
     rotation by a).  The bond dimension and the states' charges are unchanged (a pair
     shares its charge).  Applied to the finite-state machine's MPO (with state keys)."""
     n = mpo.n_sites
-    T, Tinv = [], []
+    pairs = []  # per bond: (p, m) index pairs
     for b in range(n + 1):
         keys = mpo.keys[b]
         idx = {k: j for j, k in enumerate(keys)}
-        t = np.eye(len(keys), dtype=np.complex128)
+        pb = []
         for j, k in enumerate(keys):
             q = _branch_partner(k)
             if q is None or k[2] != 1:
@@ -278,15 +278,22 @@ def rotate_real(mpo: MPO) -> MPO:
             m = idx.get(q)
             if m is None:
                 raise AssertionError(f"branch state {k} has no partner at bond {b}")
-            t[:, j] = 0.0
-            t[:, m] = 0.0
-            t[j, j], t[m, j] = 1 / np.sqrt(2), 1 / np.sqrt(2)
-            t[j, m], t[m, m] = 1j / np.sqrt(2), -1j / np.sqrt(2)
-        T.append(t)
-        Tinv.append(np.linalg.inv(t))
+            pb.append((j, m))
+        pairs.append(np.array(pb, dtype=np.int64).reshape(-1, 2))
+    # T is the identity outside the pair blocks [[1, i], [1, -i]] / sqrt2 (columns: the
+    # new states p', m' in the old basis); T^{-1} on a pair is [[1, 1], [-i, i]] / sqrt2
+    r2 = 1 / np.sqrt(2)
     W = []
     for i in range(n):
-        w = np.einsum("ab,bstc,cd->astd", Tinv[i], mpo.W[i], T[i + 1])
+        w = mpo.W[i].copy()
+        p, m = pairs[i + 1][:, 0], pairs[i + 1][:, 1]   # columns: W T_{i+1}
+        cp, cm = w[..., p].copy(), w[..., m].copy()
+        w[..., p] = (cp + cm) * r2
+        w[..., m] = 1j * (cp - cm) * r2
+        p, m = pairs[i][:, 0], pairs[i][:, 1]           # rows: T_i^{-1} W
+        rp, rm = w[p].copy(), w[m].copy()
+        w[p] = (rp + rm) * r2
+        w[m] = 1j * (rm - rp) * r2
         scale = max(np.abs(w).max(), 1.0)
         if np.abs(w.imag).max() > 1e-12 * scale:
             raise AssertionError(f"rotated MPO not real at site {i}")

@@ -11,6 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmrdmrg.so")
 
 DM_FP64, DM_FP32, DM_BF16X3 = 0, 1, 2
+DM_REAL = 16  # OR'ed into DM_FP64 / DM_FP32: real (float64) operands, the eq. rot form
 LAYOUT_SITE, LAYOUT_THETA, LAYOUT_ENV_L, LAYOUT_ENV_R = 0, 1, 2, 3
 # error codes of include/mrdmrg.h
 DM_OK, DM_ERR_ARG, DM_ERR_CHARGE, DM_ERR_DIM, DM_ERR_LAYOUT = 0, -1, -2, -3, -4
@@ -341,11 +342,15 @@ def lanczos_ground_batched(batch: Batch, thetas, max_iter=30, tol=1e-14, stream=
 
 
 class HofstadterMPO:
-    """dm_mpo_hofstadter: the library's own MPO of eq. H (basis 'mixed' or 'real')."""
+    """dm_mpo_hofstadter: the library's own MPO of eq. H (basis 'mixed' or 'real'; with
+    rot=True the mixed-basis MPO in the real form of eq. rot)."""
 
-    def __init__(self, Ly, Lx, p, q, t=1.0, V=1.0, basis="mixed"):
+    def __init__(self, Ly, Lx, p, q, t=1.0, V=1.0, basis="mixed", rot=False):
+        if rot and basis != "mixed":
+            raise ValueError("eq. rot applies to the mixed basis")
+        code = 2 if rot else (0 if basis == "mixed" else 1)
         h = _vp()
-        _check(lib.dm_mpo_hofstadter(Ly, Lx, p, q, t, V, 0 if basis == "mixed" else 1, C.byref(h)))
+        _check(lib.dm_mpo_hofstadter(Ly, Lx, p, q, t, V, code, C.byref(h)))
         self.h = h
         self._destroy = lib.dm_mpo_destroy
         self.ly = Ly if basis == "mixed" else 1

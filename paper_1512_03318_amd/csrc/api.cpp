@@ -16,6 +16,9 @@ using namespace mrd;
 
 static int lanczos_ground_impl(dm_heff_plan* p, void* theta_inout, int32_t max_iter, double tol,
                                double* energy, int32_t* iters, dm_stream stream);
+namespace {
+void check_real_mix(const MixStage& m);
+}
 
 // =====================================================================================
 // Layout query
@@ -401,6 +404,15 @@ static void build_heff_tables(dm_heff_plan& p) {
   mix_to_slabs(mx, task_key, (int)elem_bytes(p.prec), 20480);
   p.mix_flops = mx.flops;
   gemm_tables.get();
+  if (p.real) {
+    // real kernels; flops at 2 per real multiply-add (the tables counted 8 per complex)
+    check_real_mix(mx);
+    p.s1.real = p.s4.real = mx.real = true;
+    p.s1.flops /= 4;
+    p.s4.flops /= 4;
+    mx.flops /= 4;
+    p.mix_flops = mx.flops;
+  }
 }
 
 extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* c,
@@ -411,10 +423,12 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     if (!out) throw DmError{DM_ERR_ARG, "null output"};
     *out = nullptr;
     check_ly(ly);
+    const bool real = take_real(prec);
     check_prec(prec);
     auto p = std::make_unique<dm_heff_plan>();
     p->ly = ly;
     p->prec = prec;
+    p->real = real;
     p->a = make_bond(a, ly);
     p->c = make_bond(c, ly);
     p->w1 = make_mpo(w1, ly);
@@ -453,21 +467,24 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       p->dTables = up.commit(s);
     }
     HIPCHK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
-    const size_t eb = elem_bytes(prec);
+    const size_t eb = elem_bytes(prec, real);
     p->dL = dev_alloc(p->L.P.total * eb);
     p->dR = dev_alloc(p->R.P.total * eb);
     p->dX = dev_alloc(p->xtotal * eb);
     p->dZ = dev_alloc(p->ztotal * eb);
-    p->dSplit = dev_alloc(p->s4.nslots * p->s4.slot_elems() * eb);
-    stage_in(L, p->dL, p->L.P.total, prec, s);
-    stage_in(R, p->dR, p->R.P.total, prec, s);
+    // partial-tile slots keep the complex size (a real partial tile fills the first half)
+    p->dSplit = dev_alloc(p->s4.nslots * p->s4.slot_elems() * elem_bytes(prec));
+    stage_in(L, p->dL, p->L.P.total, prec, s, real);
+    stage_in(R, p->dR, p->R.P.total, prec, s, real);
     if (prec != DM_FP64) {
-      p->dL64 = dev_alloc(p->L.P.total * 16);
-      p->dR64 = dev_alloc(p->R.P.total * 16);
-      stage_in(L, p->dL64, p->L.P.total, DM_FP64, s);
-      stage_in(R, p->dR64, p->R.P.total, DM_FP64, s);
-      p->dTin = dev_alloc(p->n() * eb);
-      p->dTout = dev_alloc(p->n() * eb);
+      p->dL64 = dev_alloc(p->L.P.total * elem_bytes(DM_FP64, real));
+      p->dR64 = dev_alloc(p->R.P.total * elem_bytes(DM_FP64, real));
+      stage_in(L, p->dL64, p->L.P.total, DM_FP64, s, real);
+      stage_in(R, p->dR64, p->R.P.total, DM_FP64, s, real);
+      // FP32 copies of theta: the Lanczos kernels write whole complex-pair elements
+      // (a real theta of odd length gets a zero pad value)
+      p->dTin = dev_alloc(std::max<int64_t>(p->n() * eb, p->nlz() * 8));
+      p->dTout = dev_alloc(std::max<int64_t>(p->n() * eb, p->nlz() * 8));
     }
     {
       // BF16x3 matvec on pre-split operands with MRDMRG_PRESPLIT=1 (otherwise the
@@ -593,7 +610,7 @@ void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStrea
   // theta in: an FP32 copy; theta' out: BF16x3 stages write FP64 themselves (the FP32
   // results widened as they are stored), FP32 stages through an FP32 copy
   const bool direct = p->prec == DM_BF16X3;
-  if (!staged) HIPCHK(launch_cast_d2f((const double*)theta, (float*)p->dTin, 2 * p->n(), s, skip));
+  if (!staged) HIPCHK(launch_cast_d2f((const double*)theta, (float*)p->dTin, p->nreal(), s, skip));
   float* tout = direct ? (float*)theta_out : (float*)p->dTout;
   mark(0);
   HIPCHK(gemm_lp(p->prec, p->s1, (const float*)p->dL, (const float*)p->dTin, (float*)p->dX, nullptr, s, skip));
@@ -603,7 +620,7 @@ void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStrea
   HIPCHK(gemm_lp(p->prec, p->s4, (const float*)p->dZ, (const float*)p->dR, tout,
                  (float*)p->dSplit, s, skip, [&] { mark(3); }));
   mark(4);
-  if (!direct) HIPCHK(launch_cast_f2d((const float*)p->dTout, (double*)theta_out, 2 * p->n(), s, skip));
+  if (!direct) HIPCHK(launch_cast_f2d((const float*)p->dTout, (double*)theta_out, p->nreal(), s, skip));
 }
 
 extern "C" int dm_heff_profile(dm_heff_plan* p, int32_t enable) {
@@ -653,7 +670,7 @@ static int heff_apply_impl(dm_heff_plan* p, const void* theta, void* theta_out, 
 }
 
 void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
-  const int64_t n = p->n();
+  const int64_t n = p->nlz();  // complex elements of the Lanczos vectors
   bool relayout = !p->dInst;
   if (p->Vcap < max_iter + 1) {
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
@@ -670,8 +687,16 @@ void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
     p->dPart = (double*)dev_alloc((size_t)lz_part_doubles(n, cap - 1) * 8);
     relayout = true;
   }
-  if (!p->dW) p->dW = (double*)dev_alloc((size_t)n * 16);
-  if (!p->dVcur) p->dVcur = (double*)dev_alloc((size_t)n * 16);
+  if (!p->dW || !p->dVcur) {
+    if (!p->dW) p->dW = (double*)dev_alloc((size_t)n * 16);
+    if (!p->dVcur) p->dVcur = (double*)dev_alloc((size_t)n * 16);
+    // a real theta of odd length: the pad value of w (never written by the matvec) and
+    // of v_j must be zero from the start
+    if (p->real && (p->n() & 1)) {
+      HIPCHK(hipMemset(p->dW, 0, (size_t)n * 16));
+      HIPCHK(hipMemset(p->dVcur, 0, (size_t)n * 16));
+    }
+  }
   if (!p->dState) p->dState = (LzState*)dev_alloc(sizeof(LzState));
   if (!p->dInst) p->dInst = (LzInst*)dev_alloc(sizeof(LzInst));
   if (!p->dRes) p->dRes = (LzResult*)dev_alloc(sizeof(LzResult));
@@ -682,6 +707,8 @@ void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
   if (relayout) {
     std::vector<LzInst> I(1);
     I[0] = LzInst{p->dV, p->dW, p->dVcur, p->dPart, nullptr, nullptr, p->dState, n, n};
+    I[0].xn = p->nreal();
+    I[0].real = p->real ? 1 : 0;
     // v_j also written in FP32 when the matvec reads an FP32 copy (a BF16x3 plan on
     // pre-split operands splits v_j itself)
     I[0].tin = p->staged_in() ? (float*)p->dTin : nullptr;
@@ -1067,10 +1094,21 @@ struct EnvScratch {
   }
 };
 
+// Real operands (eq. rot): every stage runs its real kernels; the MPO coefficients the
+// mixing applies must be real.
+void check_real_mix(const MixStage& m) {
+  for (const MixSrc& x : m.srcs)
+    if (x.im != 0.0) throw DmError{DM_ERR_ARG, "real operands (DM_REAL) need an MPO with real entries"};
+}
+void make_real(EnvPlan& ep) {
+  check_real_mix(ep.mix);
+  ep.t1.real = ep.t3.real = ep.mix.real = true;
+}
+
 // Bytes of fixed-region scratch run_env takes (every piece 256-byte aligned).
 size_t env_scratch_bytes(const EnvPlan& ep, size_t table_bytes, int64_t nenv, int64_t nsite,
-                         int64_t nout, int prec) {
-  const size_t eb = elem_bytes(prec);
+                         int64_t nout, int prec, bool real) {
+  const size_t eb = elem_bytes(prec, real);
   size_t b = EnvScratch::align(table_bytes) + EnvScratch::align(ep.t1total * eb) +
              EnvScratch::align(ep.t2total * eb);
   if (prec != DM_FP64)
@@ -1083,8 +1121,8 @@ size_t env_scratch_bytes(const EnvPlan& ep, size_t table_bytes, int64_t nenv, in
 // the stream has passed them), or from a fixed region (tables copied from pageable host
 // memory, which the copy has consumed when it returns).
 void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64_t nsite,
-             void* out, int64_t nout, int prec, hipStream_t s, EnvScratch& sc) {
-  const size_t eb = elem_bytes(prec);
+             void* out, int64_t nout, int prec, bool real, hipStream_t s, EnvScratch& sc) {
+  const size_t eb = elem_bytes(prec, real);
   try {
     TableUpload up;
     up.add(ep.t1);
@@ -1102,12 +1140,12 @@ void run_env(EnvPlan& ep, const void* env, int64_t nenv, const void* site, int64
       void* e32 = sc.get(nenv * eb);
       void* s32 = sc.get(nsite * eb);
       void* o32 = sc.get(nout * eb);
-      stage_in(env, e32, nenv, DM_FP32, s);
-      stage_in(site, s32, nsite, DM_FP32, s);
+      stage_in(env, e32, nenv, DM_FP32, s, real);
+      stage_in(site, s32, nsite, DM_FP32, s, real);
       HIPCHK(gemm_lp(prec, ep.t1, (const float*)e32, (const float*)s32, (float*)t1, nullptr, s));
       HIPCHK(launch_mix<float>(ep.mix, (const float*)t1, (float*)t2, s));
       HIPCHK(gemm_lp(prec, ep.t3, (const float*)s32, (const float*)t2, (float*)o32, nullptr, s));
-      stage_out(o32, out, nout, DM_FP32, s);
+      stage_out(o32, out, nout, DM_FP32, s, real);
     }
   } catch (...) {
     sc.release(s);
@@ -1135,6 +1173,7 @@ static int env_update_left_impl(int32_t ly, const dm_bond* a, const dm_bond* b,
                                int32_t prec, dm_stream stream) {
   return guarded([&] {
     check_ly(ly);
+    const bool real = take_real(prec);
     check_prec(prec);
     Bond ba = make_bond(a, ly), bb = make_bond(b, ly);
     MpoSite W = make_mpo(w, ly);
@@ -1147,8 +1186,9 @@ static int env_update_left_impl(int32_t ly, const dm_bond* a, const dm_bond* b,
     validate(ep.t1, Li.P.total, S.P.total, ep.t1total);
     validate(ep.mix, ep.t1total, ep.t2total);
     validate(ep.t3, S.P.total, ep.t2total, Lo.P.total);
+    if (real) make_real(ep);
     EnvScratch pool;
-    run_env(ep, L, Li.P.total, A, S.P.total, L_out, Lo.P.total, prec, (hipStream_t)stream, pool);
+    run_env(ep, L, Li.P.total, A, S.P.total, L_out, Lo.P.total, prec, real, (hipStream_t)stream, pool);
   });
 }
 
@@ -1169,6 +1209,7 @@ static int env_update_right_impl(int32_t ly, const dm_bond* b, const dm_bond* c,
                                 int32_t prec, dm_stream stream) {
   return guarded([&] {
     check_ly(ly);
+    const bool real = take_real(prec);
     check_prec(prec);
     Bond bb = make_bond(b, ly), bc = make_bond(c, ly);
     MpoSite W = make_mpo(w, ly);
@@ -1181,8 +1222,9 @@ static int env_update_right_impl(int32_t ly, const dm_bond* b, const dm_bond* c,
     validate(ep.t1, Ri.P.total, S.P.total, ep.t1total);
     validate(ep.mix, ep.t1total, ep.t2total);
     validate(ep.t3, S.P.total, ep.t2total, Ro.P.total);
+    if (real) make_real(ep);
     EnvScratch pool;
-    run_env(ep, R, Ri.P.total, B, S.P.total, R_out, Ro.P.total, prec, (hipStream_t)stream, pool);
+    run_env(ep, R, Ri.P.total, B, S.P.total, R_out, Ro.P.total, prec, real, (hipStream_t)stream, pool);
   });
 }
 
@@ -1253,6 +1295,7 @@ static int env_update_left_noalloc_impl(int32_t ly, const dm_bond* a, const dm_b
                                        void* L_out, int32_t prec, dm_stream stream) {
   return guarded([&] {
     check_ly(ly);
+    const bool real = take_real(prec);
     check_prec(prec);
     Bond ba = make_bond(a, ly), bb = make_bond(b, ly);
     MpoSite W = make_mpo(w, ly);
@@ -1265,12 +1308,13 @@ static int env_update_left_noalloc_impl(int32_t ly, const dm_bond* a, const dm_b
     validate(ep.t1, Li.P.total, S.P.total, ep.t1total);
     validate(ep.mix, ep.t1total, ep.t2total);
     validate(ep.t3, S.P.total, ep.t2total, Lo.P.total);
+    if (real) make_real(ep);
     // the whole footprint is checked before any work is queued
     TableUpload probe;
     probe.add(ep.t1);
     probe.add(ep.t3);
     probe.add(ep.mix);
-    const size_t need = env_scratch_bytes(ep, probe.total, Li.P.total, S.P.total, Lo.P.total, prec);
+    const size_t need = env_scratch_bytes(ep, probe.total, Li.P.total, S.P.total, Lo.P.total, prec, real);
     if (need > kNoallocScratchBytes)
       throw DmError{DM_ERR_ALLOC, "env_update_left_noalloc needs " + std::to_string(need) +
                                       " bytes of scratch; its fixed region holds " +
@@ -1278,6 +1322,6 @@ static int env_update_left_noalloc_impl(int32_t ly, const dm_bond* a, const dm_b
     EnvScratch fixed;
     fixed.base = scratch_on_current_device();
     fixed.cap = kNoallocScratchBytes;
-    run_env(ep, L, Li.P.total, A, S.P.total, L_out, Lo.P.total, prec, (hipStream_t)stream, fixed);
+    run_env(ep, L, Li.P.total, A, S.P.total, L_out, Lo.P.total, prec, real, (hipStream_t)stream, fixed);
   });
 }

@@ -518,6 +518,7 @@ extern "C" int dm_batch_create(int32_t n, dm_heff_plan* const* plans, dm_stream 
     for (dm_heff_plan* p : b->plans) {
       if (!p) throw DmError{DM_ERR_ARG, "dm_batch_create: null plan"};
       if (p->n() == 0) throw DmError{DM_ERR_LAYOUT, "dm_batch_create: empty theta"};
+      if (p->real) throw DmError{DM_ERR_ARG, "dm_batch_create: real (DM_REAL) plans are solved one by one"};
     }
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < i; ++j)
@@ -601,6 +602,8 @@ static int lanczos_ground_batched_impl(dm_batch* b, void* const* thetas, int32_t
       I[i] = LzInst{p->dV, p->dW, p->dVcur, p->dPart, nullptr, (double*)thetas[i], p->dState,
                     p->n(), p->n()};
       I[i].tin = b->prec == DM_FP64 ? nullptr : (float*)p->dTin;
+      I[i].xn = 2 * p->n();  // complex instances (real plans are not batched)
+      I[i].real = 0;
     }
     const LzGrid g = lz_layout(I, max_iter);
     const bool same = b->graph_exec && std::equal(I.begin(), I.end(), b->hInst, [](const LzInst& x, const LzInst& y) {

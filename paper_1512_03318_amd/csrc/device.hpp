@@ -47,7 +47,8 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 
 // Sums the K-split partial tiles (tm x tn each) of one output tile in split order and
 // stores it.  Block (x, y): output tile x, elements [1024 y, 1024 y + 1024) of the tile.
-template <typename T, int FLAGS, typename Prob = GemmProb>
+// REAL: real partial tiles and result (tm x tn values at the start of each slot).
+template <typename T, int FLAGS, typename Prob = GemmProb, bool REAL = false>
 __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const Prob* __restrict__ probs,
                                                                 const GemmTile* __restrict__ tiles,
                                                                 const int64_t* __restrict__ rows,
@@ -69,12 +70,17 @@ __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const Prob* __re
     if (i >= P.M || j >= P.N) continue;
     T re = 0, im = 0;
     for (int ks = 0; ks < P.nks; ++ks) {
-      const Cplx<T> v = ldc(part, (base + ks) * slot + e);
-      re += v.re;
-      im += v.im;
+      if constexpr (REAL) {
+        re += part[2 * (base + ks) * slot + e];
+      } else {
+        const Cplx<T> v = ldc(part, (base + ks) * slot + e);
+        re += v.re;
+        im += v.im;
+      }
     }
     const int64_t rb = (FLAGS & G_C_ROWMAP) ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
-    if (FLAGS & G_C_F64) stc(reinterpret_cast<double*>(C), rb + j, (double)re, (double)im);
+    if constexpr (REAL) C[rb + j] = re;
+    else if (FLAGS & G_C_F64) stc(reinterpret_cast<double*>(C), rb + j, (double)re, (double)im);
     else stc(C, rb + j, re, im);
   }
 }

@@ -75,6 +75,7 @@ struct MixSrc {
 // Host-side task table of one contraction stage, with its device copy.
 struct GemmStage {
   int32_t flags = 0;
+  bool real = false;  // real operands and result (eq. rot formulation)
   bool deep = false;  // one workgroup per tile, K-segments split over its 4 waves
   std::vector<GemmSeg> segs;
   std::vector<GemmProb> probs;
@@ -124,6 +125,7 @@ struct SlabCoef {
 };
 
 struct MixStage {
+  bool real = false;            // real data and coefficients (task form)
   std::vector<MixTask> tasks;   // in launch order
   std::vector<MixSrc> srcs;
   double flops = 0.0;  // 8 flops per complex multiply-add
@@ -294,6 +296,12 @@ struct LzInst {
   int32_t c0, g0;  // first chunk / 256-element block of this instance
   float* tin;      // or null: FP32 copy of v_j written with it (input of an FP32 /
                    // BF16x3 matvec, which then needs no cast of its own)
+  // Real instances (eq. rot): the vectors hold 2 n - 1 or 2 n real values read as n
+  // complex elements; xn is the number of doubles in the caller's x (2 n for a complex
+  // instance), and the projection coefficients are kept real (their imaginary parts,
+  // which pair unrelated components, are set to zero), so every update is the real one.
+  int64_t xn;
+  int32_t real;
 };
 // Launch shape of an instance table (host side).
 struct LzGrid {

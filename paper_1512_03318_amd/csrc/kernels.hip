@@ -66,7 +66,9 @@ struct GemmCfg {
   static constexpr bool B_KC = (FLAGS & G_B_T) != 0;
 };
 
-template <typename T, int FLAGS, bool DEEP>
+// REAL: real operands and result (the eq. rot formulation): one value per element, one
+// product per MFMA step, only the first LDS plane used.
+template <typename T, int FLAGS, bool DEEP, bool REAL = false>
 __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ segs,
                                                    const GemmProb* __restrict__ probs,
                                                    const GemmTile* __restrict__ tiles,
@@ -127,14 +129,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
       Cplx<T> v{0, 0};
       if (i < P.M && k < kc) {
         const int kk = k0 + k;
-        if (FLAGS & G_A_ROWMAP) {
-          v = ldc(A, arow[q] + S.a_off + kk);
-        } else if (FLAGS & G_A_T) {
-          v = ldc(A, S.a_off + (int64_t)kk * S.lda + i);
+        const int64_t off = (FLAGS & G_A_ROWMAP) ? arow[q] + S.a_off + kk
+                            : (FLAGS & G_A_T)    ? S.a_off + (int64_t)kk * S.lda + i
+                                                 : S.a_off + (int64_t)i * S.lda + kk;
+        if constexpr (REAL) {
+          v.re = A[off];
         } else {
-          v = ldc(A, S.a_off + (int64_t)i * S.lda + kk);
+          v = ldc(A, off);
+          if (FLAGS & G_A_CONJ) v.im = -v.im;
         }
-        if (FLAGS & G_A_CONJ) v.im = -v.im;
       }
       ra[q] = v;
     }
@@ -146,8 +149,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
       Cplx<T> v{0, 0};
       if (j < P.N && k < kc) {
         const int kk = k0 + k;
-        v = (FLAGS & G_B_T) ? ldc(B, S.b_off + (int64_t)j * S.ldb + kk)
-                            : ldc(B, S.b_off + (int64_t)kk * S.ldb + j);
+        const int64_t off = (FLAGS & G_B_T) ? S.b_off + (int64_t)j * S.ldb + kk : S.b_off + (int64_t)kk * S.ldb + j;
+        if constexpr (REAL)
+          v.re = B[off];
+        else
+          v = ldc(B, off);
       }
       rb[q] = v;
     }
@@ -183,14 +189,14 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
       int r, k;
       a_rk(q, r, k);
       sA[0][k][r] = ra[q].re;
-      sA[1][k][r] = ra[q].im;
+      if constexpr (!REAL) sA[1][k][r] = ra[q].im;
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       int k, c;
       b_kc(q, k, c);
       sB[0][k][c] = rb[q].re;
-      sB[1][k][c] = rb[q].im;
+      if constexpr (!REAL) sB[1][k][c] = rb[q].im;
     }
     // advance and prefetch the next chunk (the staging registers are free again): the
     // loads stay in flight during the barrier and the products of this chunk
@@ -206,6 +212,18 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
     const int kend = DEEP ? min(kbeg + KW, kc) : kc;
     for (int kb = kbeg; kb < kend; kb += 4) {
       const int k = kb + lk;
+      if constexpr (REAL) {
+        T a[2], b[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) a[x] = sA[0][k][wr + x * 16 + li];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) b[y] = sB[0][k][wc + y * 16 + li];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) cre[x][y] = Mfma<T>::mac(a[x], b[y], cre[x][y]);
+        continue;
+      }
       T are[2], aim[2], bre[2], bim[2];
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
@@ -246,7 +264,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             red[wave - 1][((x * 2 + y) * 4 + r) * 2][lane] = cre[x][y][r];
-            red[wave - 1][((x * 2 + y) * 4 + r) * 2 + 1][lane] = cim[x][y][r];
+            if constexpr (!REAL) red[wave - 1][((x * 2 + y) * 4 + r) * 2 + 1][lane] = cim[x][y][r];
           }
     }
     __syncthreads();
@@ -259,7 +277,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
         for (int r = 0; r < 4; ++r) {
           const int e = ((x * 2 + y) * 4 + r) * 2;
           cre[x][y][r] = ((cre[x][y][r] + red[0][e][lane]) + red[1][e][lane]) + red[2][e][lane];
-          cim[x][y][r] = ((cim[x][y][r] + red[0][e + 1][lane]) + red[1][e + 1][lane]) + red[2][e + 1][lane];
+          if constexpr (!REAL)
+            cim[x][y][r] = ((cim[x][y][r] + red[0][e + 1][lane]) + red[1][e + 1][lane]) + red[2][e + 1][lane];
         }
     if (P.nks > 1) {
       // partial tile of this K-split, summed later by gemm_split_reduce_kernel
@@ -272,7 +291,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
 #pragma unroll
           for (int y = 0; y < 2; ++y) {
             const int rr = x * 16 + Mfma<T>::row(lk, r), cc = y * 16 + li;
-            stc(dst, rr * 32 + cc, cre[x][y][r], cim[x][y][r]);
+            if constexpr (REAL)
+              dst[rr * 32 + cc] = cre[x][y][r];  // first half of the slot
+            else
+              stc(dst, rr * 32 + cc, cre[x][y][r], cim[x][y][r]);
           }
       return;
     }
@@ -288,7 +310,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmSeg* __restrict__ s
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
         const int j = j0 + wc + y * 16 + li;
-        if (j < P.N) stc(C, rbase + j, cre[x][y][r], cim[x][y][r]);
+        if (j >= P.N) continue;
+        if constexpr (REAL)
+          C[rbase + j] = cre[x][y][r];
+        else
+          stc(C, rbase + j, cre[x][y][r], cim[x][y][r]);
       }
     }
   }
@@ -301,17 +327,27 @@ hipError_t launch_gemm(const GemmStage& st, const T* A, const T* B, T* C, T* par
   if (nt == 0) return hipSuccess;
   if (st.nslots > 0 && !part) return hipErrorInvalidValue;
   dim3 grid(nt), block(256);
-#define MRD_GEMM_CASE(F, D)                                                                \
-  if (st.flags == (F) && st.deep == (D) && st.tile_m == (D ? 32 : 64) &&                  \
-      st.tile_n == (D ? 32 : 64) && (D || !st.split)) {                                    \
-    hipLaunchKernelGGL((gemm_kernel<T, F, D>), grid, block, 0, s, st.d_segs, st.d_probs,   \
-                       st.d_tiles, st.d_rows, A, B, C, part, skip);                        \
-    if (between) between();                                                                \
-    if (D && !st.red_tiles.empty())                                                        \
-      hipLaunchKernelGGL((gemm_split_reduce_kernel<T, F>), dim3(st.red_tiles.size(), 1),   \
-                         block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C, 32, 32,\
-                         skip);                                                            \
-    return hipGetLastError();                                                              \
+#define MRD_GEMM_CASE(F, D)                                                                   \
+  if (st.flags == (F) && st.deep == (D) && st.tile_m == (D ? 32 : 64) &&                     \
+      st.tile_n == (D ? 32 : 64) && (D || !st.split)) {                                       \
+    if (st.real)                                                                              \
+      hipLaunchKernelGGL((gemm_kernel<T, F, D, true>), grid, block, 0, s, st.d_segs,          \
+                         st.d_probs, st.d_tiles, st.d_rows, A, B, C, part, skip);             \
+    else                                                                                      \
+      hipLaunchKernelGGL((gemm_kernel<T, F, D, false>), grid, block, 0, s, st.d_segs,         \
+                         st.d_probs, st.d_tiles, st.d_rows, A, B, C, part, skip);             \
+    if (between) between();                                                                   \
+    if (D && !st.red_tiles.empty()) {                                                         \
+      if (st.real)                                                                            \
+        hipLaunchKernelGGL((gemm_split_reduce_kernel<T, F, GemmProb, true>),                  \
+                           dim3(st.red_tiles.size(), 1), block, 0, s, st.d_probs,             \
+                           st.d_red_tiles, st.d_rows, part, C, 32, 32, skip);                 \
+      else                                                                                    \
+        hipLaunchKernelGGL((gemm_split_reduce_kernel<T, F>), dim3(st.red_tiles.size(), 1),    \
+                           block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C, 32,   \
+                           32, skip);                                                         \
+    }                                                                                         \
+    return hipGetLastError();                                                                 \
   }
   MRD_GEMM_CASE(0, false)
   MRD_GEMM_CASE(G_A_T | G_A_CONJ, false)
@@ -335,7 +371,7 @@ template hipError_t launch_gemm<float>(const GemmStage&, const float*, const flo
 // Sparse MPO mixing: each workgroup owns one destination sub-block and sums its few
 // scaled source sub-blocks.  Consecutive threads walk consecutive columns.
 // ---------------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool REAL = false>
 __global__ void __launch_bounds__(256) mix_kernel(const MixTask* __restrict__ tasks,
                                                   const MixSrc* __restrict__ srcs,
                                                   const T* __restrict__ src,
@@ -363,14 +399,23 @@ __global__ void __launch_bounds__(256) mix_kernel(const MixTask* __restrict__ ta
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         if (r[t] >= tk.rows) continue;
-        const Cplx<T> x = ldc(src, sr.off + (int64_t)r[t] * sr.ld + c[t]);
-        re[t] += cr * x.re - ci * x.im;
-        im[t] += cr * x.im + ci * x.re;
+        if constexpr (REAL) {  // real coefficients (checked on the host)
+          re[t] += cr * src[sr.off + (int64_t)r[t] * sr.ld + c[t]];
+        } else {
+          const Cplx<T> x = ldc(src, sr.off + (int64_t)r[t] * sr.ld + c[t]);
+          re[t] += cr * x.re - ci * x.im;
+          im[t] += cr * x.im + ci * x.re;
+        }
       }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (r[t] < tk.rows) stc(dst, tk.dst + (int64_t)r[t] * tk.ld_dst + c[t], re[t], im[t]);
+    for (int t = 0; t < 4; ++t) {
+      if (r[t] >= tk.rows) continue;
+      if constexpr (REAL)
+        dst[tk.dst + (int64_t)r[t] * tk.ld_dst + c[t]] = re[t];
+      else
+        stc(dst, tk.dst + (int64_t)r[t] * tk.ld_dst + c[t], re[t], im[t]);
+    }
   }
 }
 
@@ -526,6 +571,11 @@ __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict_
 template <typename T>
 hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s, const int32_t* skip) {
   if (st.tasks.empty()) return hipSuccess;
+  if (st.real) {  // task form
+    hipLaunchKernelGGL((mix_kernel<T, true>), dim3((uint32_t)st.tasks.size()), dim3(256), 0, s, st.d_tasks,
+                       st.d_srcs, src, dst, skip);
+    return hipGetLastError();
+  }
   if (!st.wgs.empty() && st.slab_eb == (int)(2 * sizeof(T))) {
     hipLaunchKernelGGL((mix_slab_kernel<T, T>), dim3((uint32_t)st.wgs.size()), dim3(256),
                        (uint32_t)st.lds_bytes, s, st.d_wgs, st.d_blks, st.d_stasks, st.d_coefs, src,

@@ -139,7 +139,9 @@ __global__ void __launch_bounds__(256) lz_norm_kernel(const LzInst* __restrict__
 #pragma unroll
   for (int q = 0; q < LZ_EPT; ++q) {
     const int64_t e = (int64_t)blk * LZ_CHUNK + q * 256 + threadIdx.x;
-    if (e < in.n) s += x[2 * e] * x[2 * e] + x[2 * e + 1] * x[2 * e + 1];
+    if (e >= in.n) continue;
+    s += x[2 * e] * x[2 * e];
+    if (2 * e + 1 < in.xn) s += x[2 * e + 1] * x[2 * e + 1];  // a real x of odd length ends here
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) glb(in.pnorm)[blk] = s;
@@ -175,6 +177,10 @@ __global__ void __launch_bounds__(256) lz_reduce_kernel(const LzInst* __restrict
   }
   const int c = blockIdx.x;
   if (c >= ncomp) return;
+  if (in.real && (mode == LZR_H1 || mode == LZR_H2 || mode == LZR_H2N) && (c & 1) && c < 2 * nv) {
+    if (threadIdx.x == 0) out[c] = 0.0;  // real instance: real projection coefficients
+    return;
+  }
   double s = 0;
   const auto sp = glb(src);
   for (int b = threadIdx.x; b < nblk; b += 256) s += sp[(int64_t)b * ncomp + c];
@@ -203,8 +209,9 @@ __global__ void lz_start_scale_kernel(const LzInst* __restrict__ I, int nins) {
   const double s = 1.0 / sqrt(nrm2);
   const int64_t e = (int64_t)(blockIdx.x - in.g0) * 256 + threadIdx.x;
   if (e >= in.n) return;
-  const lzc x = glb(reinterpret_cast<const lzc*>(in.x))[e];
-  const lzc v = lzc{x.x * s, x.y * s};
+  const auto xr = glb(in.x);
+  const double x0 = xr[2 * e], x1 = 2 * e + 1 < in.xn ? xr[2 * e + 1] : 0.0;
+  const lzc v = lzc{x0 * s, x1 * s};
   glb(reinterpret_cast<lzc*>(in.V))[e] = v;
   glb(reinterpret_cast<lzc*>(in.vcur))[e] = v;
   if (in.tin) glb(reinterpret_cast<lzf*>(in.tin))[e] = lzf{(float)v.x, (float)v.y};
@@ -639,7 +646,8 @@ __global__ void lz_combine_kernel(const LzInst* __restrict__ I, int nins) {
     r += y[i] * v.x;
     im += y[i] * v.y;
   }
-  glb(reinterpret_cast<lzc*>(in.x))[e] = lzc{r, im};
+  glb(in.x)[2 * e] = r;
+  if (2 * e + 1 < in.xn) glb(in.x)[2 * e + 1] = im;
   glb(reinterpret_cast<lzc*>(in.vcur))[e] = lzc{r, im};
 }
 

@@ -135,7 +135,7 @@ class Builder {
     }
   }
 
-  dm_mpo* finish(const std::vector<int>& mom);
+  dm_mpo* finish(const std::vector<int>& mom, int pair_family);
 
  private:
   void reg(int site, const Key& in, const Key& kid, const Key& out, const Mat2& m) {
@@ -191,17 +191,36 @@ struct Dense {
   cplx& at(int i, int a, int x, int b) { return W[i][((size_t)a * 4 + x) * D[i + 1] + b]; }
 };
 
-// returns j's partner k < j and lambda with v_j = lambda v_k, or k = -1
-bool parallel(const std::vector<cplx>& vj, const std::vector<cplx>& vk, cplx* lam) {
-  size_t p = 0;
+// Rounding in the phase products leaves about 1e-17 where an entry is zero (a cosine of
+// a right angle, the imaginary part of e^{ia} e^{-ia}); such components are set to
+// exact zeros, so that proportionality is decided on the true nonzero pattern.
+void snap(std::vector<cplx>& w) {
   double mx = 0;
-  for (size_t i = 0; i < vj.size(); ++i) mx = std::max(mx, std::abs(vj[i]));
-  if (mx == 0) return false;
-  while (p < vj.size() && std::abs(vj[p]) <= 1e-14 * mx) ++p;
-  if (std::abs(vk[p]) == 0) return false;
+  for (auto& v : w) mx = std::max(mx, std::abs(v));
+  const double tol = 1e-14 * mx;
+  for (auto& v : w) v = cplx(std::abs(v.real()) <= tol ? 0.0 : v.real(), std::abs(v.imag()) <= tol ? 0.0 : v.imag());
+}
+
+// true with lambda when v_j = lambda v_k: the same nonzero pattern (components above
+// 1e-14 of each vector's largest), lambda taken at v_j's largest component, and the
+// difference within 1e-13 of v_j's largest.  Patterns are compared with thresholds so
+// that rounding residue (left by merges and phase products) never defines lambda.
+bool parallel(const std::vector<cplx>& vj, const std::vector<cplx>& vk, cplx* lam) {
+  double mj = 0, mk = 0;
+  size_t p = 0;
+  for (size_t i = 0; i < vj.size(); ++i) {
+    if (std::abs(vj[i]) > mj) {
+      mj = std::abs(vj[i]);
+      p = i;
+    }
+    mk = std::max(mk, std::abs(vk[i]));
+  }
+  if (mj == 0 || mk == 0) return false;
+  for (size_t i = 0; i < vj.size(); ++i)
+    if ((std::abs(vj[i]) > 1e-14 * mj) != (std::abs(vk[i]) > 1e-14 * mk)) return false;
   const cplx l = vj[p] / vk[p];
   for (size_t i = 0; i < vj.size(); ++i)
-    if (std::abs(vj[i] - l * vk[i]) > 1e-13 * mx) return false;
+    if (std::abs(vj[i] - l * vk[i]) > 1e-13 * mj) return false;
   *lam = l;
   return true;
 }
@@ -258,6 +277,8 @@ void deparallelise(Dense& d) {
         nq.push_back(d.q[i + 1][k]);
         nf.push_back(d.keep_fixed[i + 1][k]);
       }
+      snap(A);
+      snap(B);
       d.W[i] = A;
       d.W[i + 1] = B;
       d.D[i + 1] = nm;
@@ -311,6 +332,8 @@ void deparallelise(Dense& d) {
         nq.push_back(d.q[i][k]);
         nf.push_back(d.keep_fixed[i][k]);
       }
+      snap(A);
+      snap(B);
       d.W[i - 1] = A;
       d.W[i] = B;
       d.D[i] = nm;
@@ -323,7 +346,7 @@ void deparallelise(Dense& d) {
 
 }  // namespace
 
-dm_mpo* Builder::finish(const std::vector<int>& mom) {
+dm_mpo* Builder::finish(const std::vector<int>& mom, int pair_family) {
   for (int i = 0; i < n_; ++i) {
     reg(i, kR, kR, kR, kI);
     reg(i, kF, kF, kF, kI);
@@ -377,6 +400,50 @@ dm_mpo* Builder::finish(const std::vector<int>& mom) {
         if (ib == idx[i + 1].end()) continue;
         for (int x = 0; x < 4; ++x) d.at(i, ia->second, x, ib->second) += t.second.m[x];
       }
+    }
+  }
+  for (auto& w : d.W) snap(w);
+  if (pair_family > 0) {
+    // Eq. rot: the two phase branches s = +1, -1 of family `pair_family` (key[2] = s)
+    // carry conjugate phases, so with the bond basis change that maps each pair (p, m)
+    // to ((e_p + e_m) / sqrt 2, i (e_p - e_m) / sqrt 2) every W[i] = T_i^-1 W[i] T_{i+1}
+    // becomes real; a pair shares its charge, so the block structure is unchanged.
+    std::vector<std::vector<std::pair<int, int>>> pairs(n_ + 1);
+    for (int b = 0; b <= n_; ++b)
+      for (auto& kv : idx[b]) {
+        const Key& k = kv.first;
+        if (k[0] != pair_family || k[2] != 1) continue;
+        Key q = k;
+        q[2] = -1;
+        auto it = idx[b].find(q);
+        if (it == idx[b].end()) throw std::runtime_error("eq. rot: a phase branch state has no partner");
+        pairs[b].push_back({kv.second, it->second});
+      }
+    const double r2 = 1.0 / std::sqrt(2.0);
+    const cplx I(0.0, 1.0);
+    for (int i = 0; i < n_; ++i) {
+      for (auto& pm : pairs[i + 1])  // columns: times T_{i+1}
+        for (int a = 0; a < d.D[i]; ++a)
+          for (int x = 0; x < 4; ++x) {
+            const cplx cp = d.at(i, a, x, pm.first), cm = d.at(i, a, x, pm.second);
+            d.at(i, a, x, pm.first) = (cp + cm) * r2;
+            d.at(i, a, x, pm.second) = I * (cp - cm) * r2;
+          }
+      for (auto& pm : pairs[i])  // rows: T_i^-1 from the left
+        for (int x = 0; x < 4; ++x)
+          for (int b = 0; b < d.D[i + 1]; ++b) {
+            const cplx rp = d.at(i, pm.first, x, b), rm = d.at(i, pm.second, x, b);
+            d.at(i, pm.first, x, b) = (rp + rm) * r2;
+            d.at(i, pm.second, x, b) = I * (rm - rp) * r2;
+          }
+      double mx = 0, mi = 0;
+      for (auto& v : d.W[i]) {
+        mx = std::max(mx, std::abs(v));
+        mi = std::max(mi, std::abs(v.imag()));
+      }
+      if (mi > 1e-12 * std::max(1.0, mx)) throw std::runtime_error("eq. rot: rotated MPO is not real");
+      for (auto& v : d.W[i]) v = cplx(v.real(), 0.0);
+      snap(d.W[i]);
     }
   }
   deparallelise(d);
@@ -468,22 +535,23 @@ extern "C" int dm_mpo_hofstadter(int32_t Ly, int32_t Lx, int32_t p, int32_t q, d
     return DM_ERR_ARG;
   }
   *out = nullptr;
-  if (Ly < 3 || Lx < 1 || q == 0 || (basis != 0 && basis != 1)) {
-    mpo_error("need Ly >= 3, Lx >= 1, q != 0, basis 0 or 1");
+  if (Ly < 3 || Lx < 1 || q == 0 || basis < 0 || basis > 2) {
+    mpo_error("need Ly >= 3, Lx >= 1, q != 0, basis 0, 1 or 2");
     return DM_ERR_ARG;
   }
   try {
     const int n = Ly * Lx;
-    const int ly = basis == 0 ? Ly : 1;
+    const bool mixed = basis != 1;
+    const int ly = mixed ? Ly : 1;
     const double phi = 2.0 * M_PI * (double)p / (double)q;
     Builder B(n, ly);
-    if (basis == 0)
+    if (mixed)
       add_mixed(B, Ly, Lx, phi, t, V);
     else
       add_real(B, Ly, Lx, phi, t, V);
     std::vector<int> mom(n);
-    for (int i = 0; i < n; ++i) mom[i] = basis == 0 ? i % Ly : 0;
-    *out = B.finish(mom);
+    for (int i = 0; i < n; ++i) mom[i] = mixed ? i % Ly : 0;
+    *out = B.finish(mom, basis == 2 ? INTRA : 0);
     return DM_OK;
   } catch (const std::exception& e) {
     mpo_error(e.what());

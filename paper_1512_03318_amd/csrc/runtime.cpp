@@ -175,7 +175,14 @@ void* pinned_alloc(size_t bytes) { return pinned_pool().get(bytes); }
 void pinned_free_after(void* p, hipStream_t s) { pinned_pool().put_after(p, s); }
 void pinned_free(void* p) { pinned_pool().put(p); }
 
-size_t elem_bytes(int prec) { return prec == DM_FP64 ? 16 : 8; }
+size_t elem_bytes(int prec, bool real) { return (prec == DM_FP64 ? 16 : 8) / (real ? 2 : 1); }
+
+bool take_real(int32_t& prec) {
+  const bool real = (prec & DM_REAL) != 0;
+  prec &= ~DM_REAL;
+  if (real && prec == DM_BF16X3) throw DmError{DM_ERR_ARG, "real operands (DM_REAL) take FP64 or FP32"};
+  return real;
+}
 
 void check_prec(int prec) {
   if (prec != DM_FP64 && prec != DM_FP32 && prec != DM_BF16X3)
@@ -186,19 +193,21 @@ void check_ly(int ly) {
   if (ly < 1) throw DmError{DM_ERR_ARG, "ly must be >= 1"};
 }
 
-void stage_in(const void* src, void* dst, int64_t n, int prec, hipStream_t s) {
+void stage_in(const void* src, void* dst, int64_t n, int prec, hipStream_t s, bool real) {
   if (n == 0) return;
+  const int64_t nr = real ? n : 2 * n;  // real values
   if (prec == DM_FP64)
-    HIPCHK(hipMemcpyAsync(dst, src, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(dst, src, (size_t)nr * 8, hipMemcpyDeviceToDevice, s));
   else
-    HIPCHK(launch_cast_d2f((const double*)src, (float*)dst, 2 * n, s));
+    HIPCHK(launch_cast_d2f((const double*)src, (float*)dst, nr, s));
 }
-void stage_out(const void* src, void* dst, int64_t n, int prec, hipStream_t s) {
+void stage_out(const void* src, void* dst, int64_t n, int prec, hipStream_t s, bool real) {
   if (n == 0) return;
+  const int64_t nr = real ? n : 2 * n;
   if (prec == DM_FP64)
-    HIPCHK(hipMemcpyAsync(dst, src, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(dst, src, (size_t)nr * 8, hipMemcpyDeviceToDevice, s));
   else
-    HIPCHK(launch_cast_f2d((const float*)src, (double*)dst, 2 * n, s));
+    HIPCHK(launch_cast_f2d((const float*)src, (double*)dst, nr, s));
 }
 
 hipError_t gemm_lp(int prec, const GemmStage& st, const float* A, const float* B, float* C,

@@ -145,12 +145,17 @@ struct TableUpload {
   }
 };
 
-size_t elem_bytes(int prec);
+size_t elem_bytes(int prec, bool real = false);
 void check_prec(int prec);
+// Splits the DM_REAL bit off a precision argument (real: the eq. rot formulation, FP64
+// or FP32 only).
+bool take_real(int32_t& prec);
 void check_ly(int ly);
 // Copy (FP64) or cast (FP32 storage) n complex elements from a complex128 buffer, and back.
-void stage_in(const void* src, void* dst, int64_t n, int prec, hipStream_t s);
-void stage_out(const void* src, void* dst, int64_t n, int prec, hipStream_t s);
+// n elements (complex, or real values when real is set) from FP64 into the precision's
+// storage, and back
+void stage_in(const void* src, void* dst, int64_t n, int prec, hipStream_t s, bool real = false);
+void stage_out(const void* src, void* dst, int64_t n, int prec, hipStream_t s, bool real = false);
 // FP32-storage GEMM stage: FP32 MFMA (DM_FP32) or bf16 hi/lo split MFMA (DM_BF16X3).
 hipError_t gemm_lp(int prec, const GemmStage& st, const float* A, const float* B, float* C,
                    float* part, hipStream_t s, const int32_t* skip = nullptr,
@@ -194,6 +199,7 @@ struct dm_heff_plan {
   void* dThs = nullptr;
   void* dZs = nullptr;
   void* dSplitP = nullptr;  // K-split partial tiles of the pre-split (.).R stage
+  bool real = false;        // real operands (eq. rot): FP64 or FP32
   bool presplit = false;    // BF16x3 matvec on the pre-split operands
   bool streamk = false;     // ... through the stream-K kernels
   int ncu = 1;              // compute units of the plan's device
@@ -263,6 +269,11 @@ struct dm_heff_plan {
     mrd::pinned_free(hRes);
   }
   int64_t n() const { return th.P.total; }
+  // complex elements of the Lanczos vectors (a real vector of n values is read as
+  // ceil(n / 2) complex elements, the last one padded with a zero)
+  int64_t nlz() const { return real ? (th.P.total + 1) / 2 : th.P.total; }
+  // real values in theta (FP64 / FP32 casts)
+  int64_t nreal() const { return real ? th.P.total : 2 * th.P.total; }
 };
 
 

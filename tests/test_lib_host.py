@@ -61,6 +61,46 @@ def test_library_mpo_gives_the_oracle_heff_on_the_benchmark_cylinder():
         assert s.qr == [tuple(map(int, q)) for q in m.qbond[i + 1]]
 
 
+@pytest.mark.parametrize("Ly,Lx", [(6, 1), (7, 1), (8, 1), (6, 2), (4, 3)])
+@pytest.mark.parametrize("rot", [False, True])
+def test_library_mpo_contracts_to_the_ed_hamiltonian(Ly, Lx, rot):
+    """The library's MPO (complex, and the eq. rot form) contracted to a dense matrix
+    equals the Hamiltonian assembled from the term lists.  Regression: merging
+    proportional states must not take the ratio from rounding residue (single rings of
+    Ly = 6 and 8 went wrong that way)."""
+    from fractions import Fraction
+    from oracle import ed, model
+    cyl = model.Cylinder(Ly, Lx, Fraction(1, Ly), 1.0, 1.0)
+    H = ed.hamiltonian(model.mixed_terms(cyl), ed.sector_basis(cyl.n_orb)).toarray()
+    lib = pk.HofstadterMPO(Ly, Lx, 1, Ly, 1.0, 1.0, "mixed", rot=rot)
+    W = [lib.site(i).W for i in range(lib.n_sites)]
+    if rot:
+        assert all(np.abs(w.imag).max() == 0 for w in W)
+    assert np.abs(omp.to_dense(omp.MPO(W, None, None, Ly, None)) - H).max() < 1e-12
+
+
+def test_library_eq_rot_mpo_is_real_and_gives_the_oracle_heff():
+    """The library's eq. rot MPO (basis 2): every entry real, and on a real window of a
+    Ly=6 cylinder (every site tensor entering the environments) the same effective
+    Hamiltonian as the oracle's eq. rot MPO; also the same as the complex MPO's, since
+    the projected operator does not depend on the MPO gauge."""
+    wl = workloads.make_workload("ly6_lx12_chi40", 6, 12, (1, 6), 40, 23, real=True)
+    m = omp.build(synth.cylinder_of(wl), "mixed", real=True)
+    mc = omp.build(synth.cylinder_of(wl), "mixed")
+    lib = pk.HofstadterMPO(wl.Ly, wl.Lx, wl.flux[0], wl.flux[1], wl.t, wl.V, "mixed", rot=True)
+    Wl = [lib.site(i).W for i in range(lib.n_sites)]
+    assert all(np.abs(w.imag).max() == 0 for w in Wl)
+    assert [w.shape[0] for w in Wl] == [w.shape[0] for w in m.W]
+    Lo, W1o, W2o, Ro, th, keys, _ = synth.window_problem(wl, m)
+    Ll, W1l, W2l, Rl, _, _, _ = synth.window_problem(wl, _Sites(Wl))
+    Lc, W1c, W2c, Rc, _, _, _ = synth.window_problem(wl, mc)
+    ref = bs.flatten(bs.heff_apply(Lo, W1o, W2o, Ro, th), keys)
+    for L_, W1_, W2_, R_ in ((Ll, W1l, W2l, Rl), (Lc, W1c, W2c, Rc)):
+        got = bs.flatten(bs.heff_apply(L_, W1_, W2_, R_, th), keys)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(ref.imag).max() == 0
+
+
 @pytest.mark.parametrize("name", ["ly4_chi64", "ly6_chi800", "ly8_chi3200"])
 def test_env_flops_equal_the_charge_count(name):
     wl = workloads.preset(name)
