@@ -45,32 +45,37 @@ def log(*a):
 
 
 def build_inputs(pk, torch, wl, stream):
-    """Environments at the window from seeded isometries, contracted on the GPU."""
+    """Environments at the window from seeded isometries, contracted on the GPU.  A
+    workload with real entries (wl.real) is built in the real formulation of eq. rot:
+    the library's real MPO, float64 tensors, DM_REAL updates."""
     import workloads
-    mpo = pk.HofstadterMPO(wl.Ly, wl.Lx, wl.flux[0], wl.flux[1], wl.t, wl.V, wl.basis)
+    real = getattr(wl, "real", False)
+    mpo = pk.HofstadterMPO(wl.Ly, wl.Lx, wl.flux[0], wl.flux[1], wl.t, wl.V, wl.basis, rot=real)
     ly, j, n = wl.ly, wl.j, wl.n
     dev = torch.device("cuda:0")
     bonds = [pk.Bond(b) for b in wl.bonds]
     sites = [mpo.site(i) for i in range(n)]
+    dt = torch.float64 if real else torch.complex128
+    flag = pk.DM_REAL if real else 0
 
     def dev_of(flat):
-        return torch.from_numpy(flat).to(dev)
+        return torch.from_numpy(flat.real.copy() if real else flat).to(dev)
 
-    L = torch.ones(1, dtype=torch.complex128, device=dev)
+    L = torch.ones(1, dtype=dt, device=dev)
     for i in range(j):
         A = dev_of(pk.pack(wl.site_tensor(i), pk.LAYOUT_SITE, ly, bonds[i], bonds[i + 1], qs1=sites[i].qs))
         _, nout = pk.layout(pk.LAYOUT_ENV_L, ly, bonds[i + 1], qw=sites[i].qr)
-        Lo = torch.empty(nout, dtype=torch.complex128, device=dev)
-        pk.env_update_left(ly, bonds[i], bonds[i + 1], sites[i], L, A, Lo, pk.DM_FP64, stream)
+        Lo = torch.empty(nout, dtype=dt, device=dev)
+        pk.env_update_left(ly, bonds[i], bonds[i + 1], sites[i], L, A, Lo, pk.DM_FP64 | flag, stream)
         L = Lo
         if i % 32 == 31:
             log(f"  left environment: {i + 1}/{j} sites")
-    R = torch.ones(1, dtype=torch.complex128, device=dev)
+    R = torch.ones(1, dtype=dt, device=dev)
     for i in range(n - 1, j + 1, -1):
         B = dev_of(pk.pack(wl.site_tensor(i), pk.LAYOUT_SITE, ly, bonds[i], bonds[i + 1], qs1=sites[i].qs))
         _, nout = pk.layout(pk.LAYOUT_ENV_R, ly, bonds[i], qw=sites[i].ql)
-        Ro = torch.empty(nout, dtype=torch.complex128, device=dev)
-        pk.env_update_right(ly, bonds[i], bonds[i + 1], sites[i], R, B, Ro, pk.DM_FP64, stream)
+        Ro = torch.empty(nout, dtype=dt, device=dev)
+        pk.env_update_right(ly, bonds[i], bonds[i + 1], sites[i], R, B, Ro, pk.DM_FP64 | flag, stream)
         R = Ro
         if i % 32 == 0:
             log(f"  right environment: {n - i}/{n - j - 2} sites")
@@ -79,16 +84,16 @@ def build_inputs(pk, torch, wl, stream):
     theta = dev_of(pk.pack(wl.theta(), pk.LAYOUT_THETA, ly, a, c, qs1=w1.qs, qs2=w2.qs))
     import numpy as np
     rng = np.random.default_rng(1234)
-    Aj = dev_of(pk.pack(workloads.left_isometry(rng, wl.bonds[j], wl.bonds[j + 1], wl.qsite[j], ly),
+    Aj = dev_of(pk.pack(workloads.left_isometry(rng, wl.bonds[j], wl.bonds[j + 1], wl.qsite[j], ly, real),
                         pk.LAYOUT_SITE, ly, a, b, qs1=w1.qs))
-    Bj = dev_of(pk.pack(workloads.right_isometry(rng, wl.bonds[j + 1], wl.bonds[j + 2], wl.qsite[j + 1], ly),
+    Bj = dev_of(pk.pack(workloads.right_isometry(rng, wl.bonds[j + 1], wl.bonds[j + 2], wl.qsite[j + 1], ly, real),
                         pk.LAYOUT_SITE, ly, b, c, qs1=w2.qs))
     _, nl = pk.layout(pk.LAYOUT_ENV_L, ly, b, qw=w1.qr)
     _, nr = pk.layout(pk.LAYOUT_ENV_R, ly, b, qw=w2.ql)
     out = dict(ly=ly, a=a, b=b, c=c, w1=w1, w2=w2, L=L, R=R, theta=theta, Aj=Aj, Bj=Bj,
-               Lnext=torch.empty(nl, dtype=torch.complex128, device=dev),
-               Rnext=torch.empty(nr, dtype=torch.complex128, device=dev),
-               D=(w1.W.shape[0], w1.W.shape[3], w2.W.shape[3]))
+               Lnext=torch.empty(nl, dtype=dt, device=dev),
+               Rnext=torch.empty(nr, dtype=dt, device=dev),
+               D=(w1.W.shape[0], w1.W.shape[3], w2.W.shape[3]), flag=flag)
     out["env_flops"] = (pk.env_flops(True, ly, a, b, w1), pk.env_flops(False, ly, b, c, w2))
     return out
 
@@ -474,6 +479,151 @@ def compare_real(pk, torch, wl, inp, prec, stream):
             "chi_real": int(sum(wr.bonds[j].values())), "chi_mixed": int(sum(wl.bonds[wl.j].values()))}
 
 
+def eq_rot_report(pk, torch, wl, inp, iters, stream, reps=3):
+    """The real formulation of eq. rot at the same window: the library's real MPO, real
+    isometries and theta (float64), DM_REAL plans.  Matvec and cold-start Lanczos times
+    in FP64 and FP32 next to the complex plans' (same sectors, same chi; the windows'
+    random entries differ, so their energies are not compared here -- the GPU tests
+    check one window both ways)."""
+    import statistics
+
+    import workloads
+    wr = workloads.preset(wl.name, real=True)
+    log("eq. rot (real formulation): building the window ...")
+    rin = build_inputs(pk, torch, wr, stream)
+
+    def solve_ms(plan, x0):
+        ts = []
+        e = k = None
+        for _ in range(reps):
+            x = x0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, k = pk.lanczos_ground(plan, x, iters, 1e-14, stream)
+            ts.append(1e3 * (time.perf_counter() - t0))
+        return statistics.median(ts), e, k
+
+    out = {"mpo_D": list(rin["D"]), "workload": wr.name, "entries": "real (float64)"}
+    for name, prec in (("fp64", pk.DM_FP64), ("fp32", pk.DM_FP32)):
+        cplan = pk.HeffPlan(inp["ly"], inp["a"], inp["c"], inp["w1"], inp["w2"], inp["L"], inp["R"], prec, stream)
+        rplan = pk.HeffPlan(rin["ly"], rin["a"], rin["c"], rin["w1"], rin["w2"], rin["L"], rin["R"],
+                            prec | pk.DM_REAL, stream)
+        cms, cfl, _ = matvec_time(pk, torch, inp, prec, stream, plan=cplan)
+        rms, rfl, _ = matvec_time(pk, torch, rin, prec, stream, plan=rplan)
+        clz, _, _ = solve_ms(cplan, inp["theta"])
+        rlz, re_, rk = solve_ms(rplan, rin["theta"])
+        out[name] = {"matvec_ms": round(rms, 4), "matvec_gflop": round(rfl / 1e9, 3),
+                     "matvec_gflops": round(rfl / rms / 1e6, 1), "lanczos_ms": round(rlz, 3),
+                     "lanczos_steps": rk, "energy": re_,
+                     "complex_matvec_ms": round(cms, 4), "complex_lanczos_ms": round(clz, 3),
+                     "matvec_speedup_over_complex": round(cms / rms, 2),
+                     "lanczos_speedup_over_complex": round(clz / rlz, 2),
+                     "flops_over_complex": round(rfl / cfl, 4)}
+        log(f"  {name}: real matvec {rms:.4f} ms (complex {cms:.4f}), Lanczos {rlz:.2f} ms (complex {clz:.2f})")
+        del cplan, rplan
+    out["bytes_over_complex"] = round((rin["L"].numel() * 8 + rin["R"].numel() * 8 + rin["theta"].numel() * 8) /
+                                      (inp["L"].numel() * 16 + inp["R"].numel() * 16 + inp["theta"].numel() * 16), 4)
+    return out
+
+
+# ---------------------------------------------------------------------------------
+# The Fig. 3 workload's cost curves (Sec. III B): Ly=10, flux 1/3, V/t=0.1, lowest band
+# filled (N = n/3), chi from 100 to 12800, in the mixed basis (complex, and the real form
+# of eq. rot) and in the real-space basis.  Centre windows of a finite cylinder (Lx=6,
+# two magnetic cells) with the sector rule of the synthetic workloads; the values of
+# L, R, theta and the site tensors are seeded Gaussians drawn on the device at the
+# layouts' sizes (costs do not depend on them).  The paper's curves come from converged
+# iDMRG on an infinite cylinder; this re-measures time and memory per chi only.
+# ---------------------------------------------------------------------------------
+FIG3_CHI = (100, 200, 400, 800, 1600, 3200, 6400, 12800)
+
+
+def fig3_window(pk, torch, basis, rot, chi, prec, stream, reps=3):
+    import workloads
+    Ly, Lx, flux, V = 10, 6, (1, 3), 0.1
+    n = Ly * Lx
+    wl = workloads.make_workload(f"fig3_{basis}{'_rot' if rot else ''}_chi{chi}", Ly, Lx, flux, chi, 3,
+                                 V=V, N_tot=n // 3, basis=basis, real=rot)
+    mpo = pk.HofstadterMPO(Ly, Lx, flux[0], flux[1], 1.0, V, basis, rot=rot)
+    j, ly = wl.j, wl.ly
+    a, b, c = (pk.Bond(wl.bonds[k]) for k in (j, j + 1, j + 2))
+    w1, w2 = mpo.site(j), mpo.site(j + 1)
+    dt = torch.float64 if rot else torch.complex128
+    flag = pk.DM_REAL if rot else 0
+    gen = torch.Generator(device="cuda").manual_seed(chi)
+
+    def rnd(kind, *args, **kw):
+        _, ne = pk.layout(kind, ly, *args, **kw)
+        return torch.randn(max(ne, 1), dtype=dt, device="cuda", generator=gen)[:ne]
+
+    L = rnd(pk.LAYOUT_ENV_L, a, qw=w1.ql)
+    R = rnd(pk.LAYOUT_ENV_R, c, qw=w2.qr)
+    th = rnd(pk.LAYOUT_THETA, a, c, qs1=w1.qs, qs2=w2.qs)
+    A = rnd(pk.LAYOUT_SITE, a, b, qs1=w1.qs)
+    B = rnd(pk.LAYOUT_SITE, b, c, qs1=w2.qs)
+    _, nl = pk.layout(pk.LAYOUT_ENV_L, ly, b, qw=w1.qr)
+    _, nr = pk.layout(pk.LAYOUT_ENV_R, ly, b, qw=w2.ql)
+    Lo = torch.empty(nl, dtype=dt, device="cuda")
+    Ro = torch.empty(nr, dtype=dt, device="cuda")
+    plan = pk.HeffPlan(ly, a, c, w1, w2, L, R, prec | flag, stream)
+    y = torch.empty_like(th)
+    s = torch.cuda.current_stream()
+
+    def med(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[reps // 2]
+
+    t_mv = med(lambda: pk.heff_apply(plan, th, y, stream))
+    t_l = med(lambda: pk.env_update_left(ly, a, b, w1, L, A, Lo, prec | flag, stream))
+    t_r = med(lambda: pk.env_update_right(ly, b, c, w2, R, B, Ro, prec | flag, stream))
+    sz = plan.sizes
+    eb = (8 if rot else 16) // (2 if prec != pk.DM_FP64 else 1)
+    res = {"chi": int(sum(wl.bonds[j].values())), "sectors": len(wl.bonds[j]),
+           "mpo_D": [w1.W.shape[0], w1.W.shape[3], w2.W.shape[3]],
+           "matvec_ms": round(t_mv, 4), "env_ms": round(t_l + t_r, 4),
+           # one bond update of the benchmark's kind: 30 matvecs and both updates
+           "bond_update_model_ms": round(30 * t_mv + t_l + t_r, 3),
+           "matvec_gflop": round(sum(plan.flops) / 1e9, 4),
+           "state_bytes": int((sz["L"] + sz["R"] + sz["theta"]) * eb),
+           "matvec_bytes": int((sz["L"] + sz["R"] + sz["theta"] + sz["X"] + sz["Z"]) * eb)}
+    del plan, L, R, th, A, B, Lo, Ro, y
+    torch.cuda.empty_cache()
+    return res
+
+
+def fig3_main(args):
+    import torch
+
+    import paper_1512_03318_amd as pk
+    stream = torch.cuda.current_stream()
+    prec = {"fp64": pk.DM_FP64, "fp32": pk.DM_FP32}.get(args.prec, pk.DM_FP64)
+    rows = []
+    for chi in FIG3_CHI:
+        row = {"chi_target": chi}
+        for key, basis, rot in (("mixed", "mixed", False), ("mixed_eq_rot", "mixed", True), ("real_space", "real", False)):
+            row[key] = fig3_window(pk, torch, basis, rot, chi, prec, stream)
+            log(f"fig3 chi={chi} {key}: matvec {row[key]['matvec_ms']} ms, state {row[key]['state_bytes'] / 1e6:.1f} MB")
+        m, r, q = row["mixed"], row["real_space"], row["mixed_eq_rot"]
+        row["real_space_over_mixed"] = {"bond_update_time": round(r["bond_update_model_ms"] / m["bond_update_model_ms"], 2),
+                                        "state_memory": round(r["state_bytes"] / m["state_bytes"], 2),
+                                        "matvec_gflop": round(r["matvec_gflop"] / m["matvec_gflop"], 2)}
+        row["real_space_over_eq_rot"] = {"bond_update_time": round(r["bond_update_model_ms"] / q["bond_update_model_ms"], 2),
+                                         "state_memory": round(r["state_bytes"] / q["state_bytes"], 2)}
+        rows.append(row)
+    print(json.dumps({"workload": "fig3: Ly=10, flux 1/3, V/t=0.1, N = n/3, chi 100..12800",
+                      "precision": args.prec if args.prec in ("fp64", "fp32") else "fp64",
+                      "data": "synthetic (seeded Gaussian tensors of the exact block structure)",
+                      "rows": rows}), flush=True)
+
+
 # ---------------------------------------------------------------------------------
 # Many independent windows in one batched Lanczos (64 windows, Ly in {4, 6, 8},
 # chi in [200, 2000], seeds from SeedSequence(4).spawn(64)).
@@ -633,6 +783,10 @@ def main():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--compare-real", action="store_true",
                     help="also time the same window in the real-space basis (cost ratios)")
+    ap.add_argument("--no-eq-rot", action="store_true",
+                    help="skip the real formulation (eq. rot) of the same window")
+    ap.add_argument("--fig3", action="store_true",
+                    help="only the Fig. 3 workload's cost curves (chi 100..12800, mixed / eq. rot / real space)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain elementwise copy of 1 GiB (HBM counter calibration)")
     ap.add_argument("--batched", action="store_true",
@@ -642,6 +796,8 @@ def main():
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no "
               f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.fig3:
+        return fig3_main(args)
     if args.batched:
         batched_main(args)
         return
@@ -727,6 +883,8 @@ def main():
     if args.compare_real:
         log("real-space basis comparison ...")
         out["real_space"] = compare_real(pk, torch, wl, inp, prec, stream)
+    if not args.no_eq_rot:
+        out["eq_rot"] = eq_rot_report(pk, torch, wl, inp, args.iters, stream)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl)
