@@ -400,8 +400,9 @@ static void build_heff_tables(dm_heff_plan& p) {
     mix_to_slabs(p.mixp, task_key, 8, 20480);
   }
   // slab form with about 20 KB of LDS per workgroup (several workgroups per CU keep
-  // enough loads in flight; measured best between 12 and 32 KB at Ly=8, chi=3200)
-  mix_to_slabs(mx, task_key, (int)elem_bytes(p.prec), 20480);
+  // enough loads in flight; measured best between 12 and 32 KB at Ly=8, chi=3200),
+  // sized for the plan's element (a real plan stages one value per element)
+  mix_to_slabs(mx, task_key, (int)elem_bytes(p.prec, p.real), 20480);
   p.mix_flops = mx.flops;
   gemm_tables.get();
   if (p.real) {

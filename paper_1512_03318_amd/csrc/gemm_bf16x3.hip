@@ -22,6 +22,15 @@
 // 4 (lane / 16) + r, column lane % 16 (measured on gfx950).  LDS therefore holds each
 // operand as [row][k] planes (k contiguous), one plane per part: re_hi, re_lo, im_hi,
 // im_lo; a lane reads its 8 k values with one 16-byte load.
+//
+// LDS rows: an operand staged along k (its quads are four consecutive k of one row, eight
+// lanes per row) has 64-byte rows with 16-byte group g of row r stored at slot
+// g ^ f(r), f(r) = ((r >> 1) ^ (r >> 3)) & 3.  A pass of 32 lanes storing 8 bytes each
+// then covers four whole rows = all 64 banks once, and a fragment read (16 consecutive
+// rows, one group) puts rows r, r + 4, r + 8, r + 12 (same banks without the XOR) in four
+// different slots: no bank conflicts either way.  An operand staged across rows (quads
+// along k of one column of consecutive lanes' rows) keeps rows of 40 bf16 (80 bytes), which
+// keeps its fragment reads conflict-free.
 #include "device.hpp"
 
 namespace mrd {
@@ -41,16 +50,23 @@ __device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
+// bf16 offset of element (row r, k) in an LDS plane of K-chunk rows (see above)
+template <bool KCONTIG>
+__device__ __forceinline__ int lds_rk(int r, int k) {
+  if (KCONTIG) return r * 32 + ((((k >> 3) ^ (((r >> 1) ^ (r >> 3)) & 3)) << 3) | (k & 7));
+  return r * 40 + k;
+}
+
 template <int FLAGS, int BM, int BN, int WM, int WN>
 struct Bf3Cfg {
   static constexpr int KC = 32;                // K chunk = one bf16 MFMA step
-  static constexpr int LD = KC + 8;            // LDS row stride (bf16), 16-byte pad
   static constexpr int QA = BM * KC / 4 / 256;  // k-quads of A staged per thread
   static constexpr int QB = BN * KC / 4 / 256;
   static constexpr int XB = BM / WM / 16, YB = BN / WN / 16;  // MFMA blocks per wave
   static constexpr bool A_KC = !(FLAGS & G_A_T);
   static constexpr bool B_KC = (FLAGS & G_B_T) != 0;
-  static constexpr int PLANE_A = BM * LD, PLANE_B = BN * LD;  // bf16 per plane
+  // bf16 per plane: rows of 32 (swizzled) or 40 (padded) bf16
+  static constexpr int PLANE_A = BM * (A_KC ? 32 : 40), PLANE_B = BN * (B_KC ? 32 : 40);
   static constexpr int SMEM = 2 * 4 * (PLANE_A + PLANE_B);  // bytes: 4 parts of bf16
   static_assert(WM * WN == 4 && QA >= 1 && QB >= 1 && XB >= 1 && YB >= 1, "tile shape");
 };
@@ -93,10 +109,10 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
                                                        const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   typedef Bf3Cfg<FLAGS, BM, BN, WM, WN> G;
-  constexpr int KC = G::KC, LD = G::LD, QA = G::QA, QB = G::QB, XB = G::XB, YB = G::YB;
+  constexpr int KC = G::KC, QA = G::QA, QB = G::QB, XB = G::XB, YB = G::YB;
   __shared__ __attribute__((aligned(16))) char smem[G::SMEM];
-  __bf16* sA = reinterpret_cast<__bf16*>(smem);          // [4 parts][BM][LD]
-  __bf16* sB = sA + 4 * G::PLANE_A;                      // [4 parts][BN][LD]
+  __bf16* sA = reinterpret_cast<__bf16*>(smem);          // [4 parts][BM rows]
+  __bf16* sB = sA + 4 * G::PLANE_A;                      // [4 parts][BN rows]
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -181,13 +197,13 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
     for (int q = 0; q < QA; ++q) {
       int r, k;
       quad_rk<G::A_KC, BM, KC>(tid, q, r, k);
-      split_store(ra[q], sA, G::PLANE_A, r * LD + k);
+      split_store(ra[q], sA, G::PLANE_A, lds_rk<G::A_KC>(r, k));
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       int c, k;
       quad_rk<G::B_KC, BN, KC>(tid, q, c, k);
-      split_store(rb[q], sB, G::PLANE_B, c * LD + k);
+      split_store(rb[q], sB, G::PLANE_B, lds_rk<G::B_KC>(c, k));
     }
     // the staging registers are free again: the next chunk's loads go out before the
     // barrier and stay in flight during it and the products of this chunk
@@ -205,13 +221,13 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
     for (int y = 0; y < YB; ++y)
 #pragma unroll
       for (int p = 0; p < 4; ++p)
-        b[y][p] = *reinterpret_cast<const bf16x8*>(sB + p * G::PLANE_B + (wc + y * 16 + li) * LD + 8 * lk);
+        b[y][p] = *reinterpret_cast<const bf16x8*>(sB + p * G::PLANE_B + lds_rk<G::B_KC>(wc + y * 16 + li, 8 * lk));
 #pragma unroll
     for (int x = 0; x < XB; ++x) {
       bf16x8 a[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p)
-        a[p] = *reinterpret_cast<const bf16x8*>(sA + p * G::PLANE_A + (wr + x * 16 + li) * LD + 8 * lk);
+        a[p] = *reinterpret_cast<const bf16x8*>(sA + p * G::PLANE_A + lds_rk<G::A_KC>(wr + x * 16 + li, 8 * lk));
       // parts: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
       const bf16x8 nih = neg8(a[2]), nil = neg8(a[3]);
 #pragma unroll

@@ -125,7 +125,7 @@ struct SlabCoef {
 };
 
 struct MixStage {
-  bool real = false;            // real data and coefficients (task form)
+  bool real = false;            // real data and coefficients (eq. rot form)
   std::vector<MixTask> tasks;   // in launch order
   std::vector<MixSrc> srcs;
   double flops = 0.0;  // 8 flops per complex multiply-add
@@ -137,8 +137,9 @@ struct MixStage {
   std::vector<SlabTask> stasks;
   std::vector<SlabCoef> coefs;
   int32_t lds_bytes = 0;  // largest LDS footprint of one workgroup
-  int32_t slab_eb = 0;    // bytes per complex element the slab form was sized for; a
-                          // launch in another precision uses the task form
+  int32_t slab_eb = 0;    // bytes per element the slab form was sized for (one real value
+                          // per element for a real plan); a launch in another precision
+                          // uses the task form
   SlabWG* d_wgs = nullptr;
   SlabBlk* d_blks = nullptr;
   SlabTask* d_stasks = nullptr;

@@ -443,8 +443,9 @@ __device__ __forceinline__ void mix_store(OT* obase, int64_t off, int32_t pstrid
 
 // One output task of a slab with NC coefficients, all read once before the element
 // loop (the generic loop reads the coefficient of every term of every element and waits
-// for it); the terms are summed in the same order.
-template <typename T, typename OT, int NC>
+// for it); the terms are summed in the same order.  REAL: one T per element and real
+// coefficients (the eq. rot form).
+template <typename T, typename OT, int NC, bool REAL>
 __device__ __forceinline__ void mix_slab_task(const SlabTask& k, const SlabCoef* __restrict__ coefs,
                                               const T* lds, OT* obase, const MixPart& p) {
   T cr[NC], ci[NC];
@@ -461,11 +462,16 @@ __device__ __forceinline__ void mix_slab_task(const SlabTask& k, const SlabCoef*
     T re = 0, im = 0;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      const T* x = lds + 2 * ((int64_t)bo[q] + e);
-      re += cr[q] * x[0] - ci[q] * x[1];
-      im += cr[q] * x[1] + ci[q] * x[0];
+      if constexpr (REAL) {
+        re += cr[q] * lds[(int64_t)bo[q] + e];
+      } else {
+        const T* x = lds + 2 * ((int64_t)bo[q] + e);
+        re += cr[q] * x[0] - ci[q] * x[1];
+        im += cr[q] * x[1] + ci[q] * x[0];
+      }
     }
-    mix_store<T, OT>(obase, (int64_t)r * k.ld_dst + c, k.pstride, re, im);
+    if constexpr (REAL) obase[(int64_t)r * k.ld_dst + c] = re;
+    else mix_store<T, OT>(obase, (int64_t)r * k.ld_dst + c, k.pstride, re, im);
     r += p.step_r;
     c += p.step_c;
     if (c >= p.ncol) {
@@ -476,11 +482,11 @@ __device__ __forceinline__ void mix_slab_task(const SlabTask& k, const SlabCoef*
 }
 
 // Slab form: stage the workgroup's part (rows r0.., columns col0..) of every source block
-// of its slab in LDS (planes [block][row][col], interleaved complex), then produce that
-// part of each task of the slab from LDS.  Elements e of the part map to (row, col) with
-// a running (row, col) pair instead of a division per element.  OT: output element type
-// (T, or __bf16 for an output split into planes).
-template <typename T, typename OT>
+// of its slab in LDS (planes [block][row][col], interleaved complex, or one T per element
+// when REAL), then produce that part of each task of the slab from LDS.  Elements e of
+// the part map to (row, col) with a running (row, col) pair instead of a division per
+// element.  OT: output element type (T, or __bf16 for an output split into planes).
+template <typename T, typename OT, bool REAL = false>
 __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict__ wgs,
                                                        const SlabBlk* __restrict__ blks,
                                                        const SlabTask* __restrict__ tasks,
@@ -488,6 +494,8 @@ __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict_
                                                        const T* __restrict__ src,
                                                        OT* __restrict__ dst,
                                                        const int32_t* __restrict__ skip) {
+  static_assert(!REAL || sizeof(OT) == sizeof(T), "real mixing writes its own element type");
+  constexpr int EW = REAL ? 1 : 2;  // T values per element
   if (skip && *skip) return;
   extern __shared__ __attribute__((aligned(16))) char mix_lds[];
   T* lds = reinterpret_cast<T*>(mix_lds);
@@ -507,21 +515,30 @@ __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict_
 #pragma unroll
     for (int u = 0; u < MIX_G; ++u) {
       const SlabBlk k = blks[g.blk0 + b0 + min(u, nb - 1)];
-      base[u] = src + 2 * (k.off + (int64_t)g.r0 * k.ld + g.col0);
+      base[u] = src + EW * (k.off + (int64_t)g.r0 * k.ld + g.col0);
       ld[u] = k.ld;
     }
     int r = r_init, c = c_init;
     for (int e = threadIdx.x; e < per; e += 256) {
-      Cplx<T> v[MIX_G];
+      if constexpr (REAL) {
+        T v[MIX_G];
 #pragma unroll
-      for (int u = 0; u < MIX_G; ++u) v[u] = ldc(base[u], (int64_t)r * ld[u] + c);
+        for (int u = 0; u < MIX_G; ++u) v[u] = base[u][(int64_t)r * ld[u] + c];
 #pragma unroll
-      for (int u = 0; u < MIX_G; ++u)
-        if (u < nb) {
-          T* out = lds + 2 * ((int64_t)(b0 + u) * per + e);
-          out[0] = v[u].re;
-          out[1] = v[u].im;
-        }
+        for (int u = 0; u < MIX_G; ++u)
+          if (u < nb) lds[(int64_t)(b0 + u) * per + e] = v[u];
+      } else {
+        Cplx<T> v[MIX_G];
+#pragma unroll
+        for (int u = 0; u < MIX_G; ++u) v[u] = ldc(base[u], (int64_t)r * ld[u] + c);
+#pragma unroll
+        for (int u = 0; u < MIX_G; ++u)
+          if (u < nb) {
+            T* out = lds + 2 * ((int64_t)(b0 + u) * per + e);
+            out[0] = v[u].re;
+            out[1] = v[u].im;
+          }
+      }
       r += step_r;
       c += step_c;
       if (c >= g.ncol) {
@@ -533,18 +550,18 @@ __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict_
   __syncthreads();
   for (int t = 0; t < g.ntask; ++t) {
     const SlabTask k = tasks[g.task0 + t];
-    // complex elements of T (two per element) or bf16 elements of one plane
-    OT* obase = dst + (sizeof(OT) == 2 ? 1 : 2) * (k.dst + (int64_t)g.r0 * k.ld_dst + g.col0);
+    // elements of T (complex: two T each) or bf16 elements of one plane
+    OT* obase = dst + (sizeof(OT) == 2 ? 1 : EW) * (k.dst + (int64_t)g.r0 * k.ld_dst + g.col0);
     const MixPart part{per, g.ncol, r_init, c_init, step_r, step_c};
     switch (k.nc) {  // uniform over the workgroup
-      case 1: mix_slab_task<T, OT, 1>(k, coefs, lds, obase, part); continue;
-      case 2: mix_slab_task<T, OT, 2>(k, coefs, lds, obase, part); continue;
-      case 3: mix_slab_task<T, OT, 3>(k, coefs, lds, obase, part); continue;
-      case 4: mix_slab_task<T, OT, 4>(k, coefs, lds, obase, part); continue;
-      case 5: mix_slab_task<T, OT, 5>(k, coefs, lds, obase, part); continue;
-      case 6: mix_slab_task<T, OT, 6>(k, coefs, lds, obase, part); continue;
-      case 7: mix_slab_task<T, OT, 7>(k, coefs, lds, obase, part); continue;
-      case 8: mix_slab_task<T, OT, 8>(k, coefs, lds, obase, part); continue;
+      case 1: mix_slab_task<T, OT, 1, REAL>(k, coefs, lds, obase, part); continue;
+      case 2: mix_slab_task<T, OT, 2, REAL>(k, coefs, lds, obase, part); continue;
+      case 3: mix_slab_task<T, OT, 3, REAL>(k, coefs, lds, obase, part); continue;
+      case 4: mix_slab_task<T, OT, 4, REAL>(k, coefs, lds, obase, part); continue;
+      case 5: mix_slab_task<T, OT, 5, REAL>(k, coefs, lds, obase, part); continue;
+      case 6: mix_slab_task<T, OT, 6, REAL>(k, coefs, lds, obase, part); continue;
+      case 7: mix_slab_task<T, OT, 7, REAL>(k, coefs, lds, obase, part); continue;
+      case 8: mix_slab_task<T, OT, 8, REAL>(k, coefs, lds, obase, part); continue;
       default: break;
     }
     int r = r_init, c = c_init;
@@ -552,12 +569,17 @@ __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict_
       T re = 0, im = 0;
       for (int q = 0; q < k.nc; ++q) {
         const SlabCoef w = coefs[k.c0 + q];
-        const T* x = lds + 2 * ((int64_t)w.blk * per + e);
         const T cr = (T)w.re, ci = (T)w.im;
-        re += cr * x[0] - ci * x[1];
-        im += cr * x[1] + ci * x[0];
+        if constexpr (REAL) {
+          re += cr * lds[(int64_t)w.blk * per + e];
+        } else {
+          const T* x = lds + 2 * ((int64_t)w.blk * per + e);
+          re += cr * x[0] - ci * x[1];
+          im += cr * x[1] + ci * x[0];
+        }
       }
-      mix_store<T, OT>(obase, (int64_t)r * k.ld_dst + c, k.pstride, re, im);
+      if constexpr (REAL) obase[(int64_t)r * k.ld_dst + c] = re;
+      else mix_store<T, OT>(obase, (int64_t)r * k.ld_dst + c, k.pstride, re, im);
       r += step_r;
       c += step_c;
       if (c >= g.ncol) {
@@ -571,9 +593,14 @@ __global__ void __launch_bounds__(256) mix_slab_kernel(const SlabWG* __restrict_
 template <typename T>
 hipError_t launch_mix(const MixStage& st, const T* src, T* dst, hipStream_t s, const int32_t* skip) {
   if (st.tasks.empty()) return hipSuccess;
-  if (st.real) {  // task form
-    hipLaunchKernelGGL((mix_kernel<T, true>), dim3((uint32_t)st.tasks.size()), dim3(256), 0, s, st.d_tasks,
-                       st.d_srcs, src, dst, skip);
+  if (st.real) {  // slab form if its tables were sized for real elements, else task form
+    if (!st.wgs.empty() && st.slab_eb == (int)sizeof(T))
+      hipLaunchKernelGGL((mix_slab_kernel<T, T, true>), dim3((uint32_t)st.wgs.size()), dim3(256),
+                         (uint32_t)st.lds_bytes, s, st.d_wgs, st.d_blks, st.d_stasks, st.d_coefs, src,
+                         dst, skip);
+    else
+      hipLaunchKernelGGL((mix_kernel<T, true>), dim3((uint32_t)st.tasks.size()), dim3(256), 0, s,
+                         st.d_tasks, st.d_srcs, src, dst, skip);
     return hipGetLastError();
   }
   if (!st.wgs.empty() && st.slab_eb == (int)(2 * sizeof(T))) {
