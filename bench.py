@@ -201,22 +201,22 @@ def stage_rooflines(pk, plan, prec, pname, prof, nmv, workload):
     presplit = os.environ.get("MRDMRG_PRESPLIT", "0") == "1"
     streamk = os.environ.get("MRDMRG_SK", "1") != "0"
     if presplit and streamk:
-        bf3 = ("mrd::gemm_sk_kernel<0>", "mrd::gemm_sk_kernel<1>", "mrd::mix_slab_kernel<float, __bf16>",
+        bf3 = ("mrd::gemm_sk_kernel<0>", "mrd::gemm_sk_kernel<1>", "mrd::mix_slab_kernel<float, __bf16, false>",
                "mrd::gemm_sk_reduce_kernel<1>")
     elif presplit:
         bf3 = ("mrd::gemm_ps_kernel<128, 64, 2, 2, false, 0>", "mrd::gemm_ps_kernel<128, 32, 4, 1, true, 1>",
-               "mrd::mix_slab_kernel<float, __bf16>", "mrd::gemm_split_reduce_kernel<float, 144, mrd::PsProb>")
+               "mrd::mix_slab_kernel<float, __bf16, false>", "mrd::gemm_split_reduce_kernel<float, 144, mrd::PsProb, false>")
     else:
         bf3 = ("mrd::gemm_bf3_kernel<0, 128, 64, 2, 2, false>", "mrd::gemm_bf3_kernel<148, 128, 32, 4, 1, true>",
-               "mrd::mix_slab_kernel<float, float>", "mrd::gemm_split_reduce_kernel<float, 148, mrd::GemmProb>")
-    gemm = {pk.DM_FP64: ("mrd::gemm_kernel<double, 0, false>", "mrd::gemm_kernel<double, 20, true>"),
-            pk.DM_FP32: ("mrd::gemm_kernel<float, 0, false>", "mrd::gemm_kernel<float, 20, true>"),
+               "mrd::mix_slab_kernel<float, float, false>", "mrd::gemm_split_reduce_kernel<float, 148, mrd::GemmProb, false>")
+    gemm = {pk.DM_FP64: ("mrd::gemm_kernel<double, 0, false, false>", "mrd::gemm_kernel<double, 20, true, false>"),
+            pk.DM_FP32: ("mrd::gemm_kernel<float, 0, false, false>", "mrd::gemm_kernel<float, 20, true, false>"),
             pk.DM_BF16X3: bf3[:2]}[prec]
-    mixk = {pk.DM_FP64: "mrd::mix_slab_kernel<double, double>",
-            pk.DM_FP32: "mrd::mix_slab_kernel<float, float>",
+    mixk = {pk.DM_FP64: "mrd::mix_slab_kernel<double, double, false>",
+            pk.DM_FP32: "mrd::mix_slab_kernel<float, float, false>",
             pk.DM_BF16X3: bf3[2]}[prec]
-    redk = {pk.DM_FP64: "mrd::gemm_split_reduce_kernel<double, 20, mrd::GemmProb>",
-            pk.DM_FP32: "mrd::gemm_split_reduce_kernel<float, 20, mrd::GemmProb>",
+    redk = {pk.DM_FP64: "mrd::gemm_split_reduce_kernel<double, 20, mrd::GemmProb, false>",
+            pk.DM_FP32: "mrd::gemm_split_reduce_kernel<float, 20, mrd::GemmProb, false>",
             pk.DM_BF16X3: bf3[3]}[prec]
     traffic = measured_traffic(workload, pname)
     hw = 3 if prec == pk.DM_BF16X3 else 1
