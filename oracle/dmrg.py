@@ -110,10 +110,12 @@ class DMRGResult:
 
 def run(mpo, init: list, chis: list[int], ly: int, sweeps_per_chi: int = 4,
         tol_e: float = 1e-10, max_iter: int = 30, tol_res: float = 1e-10,
-        cutoff: float = 1e-14, noise: float = 1e-3, rng=None) -> DMRGResult:
+        cutoff: float = 1e-14, noise: float = 1e-3, rng=None, capture=None) -> DMRGResult:
     """Two-site DMRG from a right-canonical initial MPS ``init`` (list of block dicts).
     ``chis`` is the bond-dimension schedule, one entry per stage; the last stage sweeps
-    until convergence (at most 4 * sweeps_per_chi sweeps)."""
+    until convergence (at most 4 * sweeps_per_chi sweeps).  ``capture``, if given, is
+    called before each two-site eigensolve with the bond problem
+    (i, L, R, theta, keys, left bond dims, right bond dims); it does not change the run."""
     n = mpo.n_sites
     qsite = [tuple(map(tuple, q)) for q in mpo.qsite]
     M = [dict(t) for t in init]
@@ -143,6 +145,9 @@ def run(mpo, init: list, chis: list[int], ly: int, sweeps_per_chi: int = 4,
 
                     def mv(v, L=L, R=R, W1=W1, W2=W2, keys=keys):
                         return bs.flatten(bs.heff_apply(L, W1, W2, R, bs.unflatten(v, keys)), keys)
+
+                    if capture is not None:
+                        capture(i, L, R, theta, keys, _left_dims(M[i]), _right_dims(M[i + 1]))
 
                     e, vec, _, _, _ = lanczos(mv, bs.flatten(theta, keys), max_iter=max_iter,
                                               tol_res=tol_res)

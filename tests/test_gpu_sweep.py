@@ -10,6 +10,10 @@ against the oracle and exact diagonalisation.
   exact diagonalisation (-10.812773825927, K=2) and the momentum-resolved entanglement
   spectrum at the centre equals the Schmidt values of the exact ground state, sector by
   sector; at chi=64 the sweep energies equal the oracle's sweep from the same start.
+* The same cylinder's bond problems as the oracle's DMRG meets them: after the oracle
+  converges at chi=64, one more right sweep hands out every two-site problem (L, R, theta
+  and bonds of dimension 1 to 64); heff_apply matches the oracle's matvec on each of them
+  in FP64, FP32 and BF16x3, and FP64 Lanczos matches the oracle's Lanczos on several.
 """
 import json
 import os
@@ -33,7 +37,8 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import paper_1512_03318_amd as pk  # noqa: E402
-from gpu_helpers import problem, to_dev  # noqa: E402
+from gpu_helpers import WindowGPU, block_rel, max_rel, problem, to_dev  # noqa: E402
+from oracle import lanczos as olz  # noqa: E402
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -182,3 +187,84 @@ def test_gpu_sweeps_equal_the_oracle_sweeps_at_chi64():
     say(f"  oracle {['%.12f' % x for x in r.energies[:3]]}")
     for s in range(3):
         assert abs(e[s] - r.energies[s]) <= 1e-9 * abs(r.energies[s]), s
+
+
+class _Captured(Exception):
+    pass
+
+
+_cfg1_bonds = []
+
+
+def cfg1_bond_problems():
+    """Every two-site problem of one right sweep of the oracle's DMRG on the cfg1 cylinder,
+    taken after the oracle has converged at chi=64: (i, L, R, theta, keys, left bond,
+    right bond) per bond."""
+    if not _cfg1_bonds:
+        c = cfg1()
+        wl, m = c["wl"], c["m"]
+        say("oracle DMRG on Ly=4 Lx=8 at chi=64 (to convergence), then one captured right sweep ...")
+        r = odmrg.run(m, wl.right_canonical_mps(), [64], wl.ly, sweeps_per_chi=1)
+
+        def grab(i, L, R, th, keys, da, dc):
+            _cfg1_bonds.append((i, L, R, th, keys, da, dc))
+            if len(_cfg1_bonds) == wl.n - 1:
+                raise _Captured
+
+        try:
+            odmrg.run(m, r.tensors, [64], wl.ly, sweeps_per_chi=1, capture=grab)
+        except _Captured:
+            pass
+        say(f"  {len(_cfg1_bonds)} bond problems, left bond dimensions "
+            f"{[sum(b[5].values()) for b in _cfg1_bonds]}")
+    return _cfg1_bonds
+
+
+def _window(i, da, dc):
+    c = cfg1()
+
+    class W:  # the fields WindowGPU reads
+        ly = c["wl"].ly
+        j = i
+        bonds = {i: da, i + 2: dc}
+    return W
+
+
+@pytest.mark.timeout(900)
+def test_heff_apply_on_captured_cfg1_bond_problems():
+    probs = cfg1_bond_problems()
+    m = cfg1()["m"]
+    tol = {pk.DM_FP64: 1e-12, pk.DM_FP32: 2e-5, pk.DM_BF16X3: 1e-4}
+    worst = {p: 0.0 for p in tol}
+    for i, L, R, th, keys, da, dc in probs:
+        g = WindowGPU(_window(i, da, dc), L, R, m)
+        x = to_dev(g.pack_theta(th))
+        ref = bs.heff_apply(L, m.W[i], m.W[i + 1], R, th)
+        for prec in tol:
+            plan = g.plan(prec)
+            y = torch.empty_like(x)
+            pk.heff_apply(plan, x, y)
+            got = g.unpack_theta(y.cpu().numpy())
+            err, berr = max_rel(got, ref, keys), block_rel(got, ref, keys)
+            worst[prec] = max(worst[prec], err)
+            assert err <= tol[prec] and (prec != pk.DM_FP64 or berr <= 1e-12), (i, prec, err, berr)
+    say(f"  worst relative error over {len(probs)} bonds: FP64 {worst[pk.DM_FP64]:.2e}, "
+        f"FP32 {worst[pk.DM_FP32]:.2e}, BF16x3 {worst[pk.DM_BF16X3]:.2e}")
+
+
+@pytest.mark.timeout(900)
+def test_lanczos_on_captured_cfg1_bond_problems():
+    probs = cfg1_bond_problems()
+    m = cfg1()["m"]
+    for i, L, R, th, keys, da, dc in [probs[k] for k in (0, 2, 6, len(probs) // 2, len(probs) - 3)]:
+        g = WindowGPU(_window(i, da, dc), L, R, m)
+        x = to_dev(g.pack_theta(th))
+        e, k = pk.lanczos_ground(g.plan(pk.DM_FP64), x, 30, 1e-14)
+        mv = lambda v, L=L, R=R, i=i, keys=keys: bs.flatten(
+            bs.heff_apply(L, m.W[i], m.W[i + 1], R, bs.unflatten(v, keys)), keys)
+        eo, vo, ko, _, _ = olz.lanczos(mv, bs.flatten(th, keys), max_iter=30)
+        say(f"  bond {i} (n={x.numel()}): steps {k} (oracle {ko}), energy {e:.12f} (oracle {eo:.12f})")
+        assert k == ko
+        assert abs(e - eo) <= 1e-10 * abs(eo)
+        v = bs.flatten(g.unpack_theta(x.cpu().numpy()), keys)
+        assert 1 - abs(np.vdot(vo, v)) / np.linalg.norm(v) < 1e-8
