@@ -37,7 +37,7 @@ struct Mfma<float> {
 // Grouped complex GEMM on MFMA 16x16x4 with LDS staging.
 //
 // A workgroup (4 waves) owns one BM x BN output tile of one problem and walks the
-// problem's K-segments in chunks of KC (32 WIDE, 64 DEEP).  Each chunk of A (BM x KC) and B (KC x BN)
+// problem's K-segments in chunks of KC (32 WIDE, 64 DEEP; half that in FP64).  Each chunk of A (BM x KC) and B (KC x BN)
 // is loaded cooperatively with coalesced accesses -- consecutive threads read
 // consecutive elements along the operand's contiguous dimension -- then stored to LDS
 // as separate real / imaginary planes indexed [k][row], so that MFMA operands are
@@ -56,7 +56,9 @@ struct Mfma<float> {
 // ---------------------------------------------------------------------------------
 template <typename T, int FLAGS, bool DEEP>
 struct GemmCfg {
-  static constexpr int KC = DEEP ? 64 : 32;  // K chunk staged per step
+  // K chunk staged per step (FP64: half, so that the staging planes leave room for
+  // four workgroups per CU)
+  static constexpr int KC = (DEEP ? 64 : 32) / (sizeof(T) == 8 ? 2 : 1);
   static constexpr int BM = DEEP ? 32 : 64;
   static constexpr int BN = DEEP ? 32 : 64;
   static constexpr int NA = BM * KC / 256;  // A elements staged per thread per chunk
