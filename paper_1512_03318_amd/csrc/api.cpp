@@ -208,7 +208,8 @@ static void build_heff_tables(dm_heff_plan& p) {
       s4.tile_n = 32;
       s4.kc = 32;
       s4.split_min = 12;
-    } else {    // 32 x 32 tiles shared by four waves, >= 4 chunks of 64 per split
+    } else {    // 32 x 32 tiles shared by four waves, >= 256 K values per split (the
+                // kernels stage them in chunks of 32)
       s4.deep = true;
       s4.tile_m = s4.tile_n = 32;
       s4.kc = 64;

@@ -37,7 +37,7 @@ struct Mfma<float> {
 // Grouped complex GEMM on MFMA 16x16x4 with LDS staging.
 //
 // A workgroup (4 waves) owns one BM x BN output tile of one problem and walks the
-// problem's K-segments in chunks of KC (32 WIDE, 64 DEEP; half that in FP64).  Each chunk of A (BM x KC) and B (KC x BN)
+// problem's K-segments in chunks of KC (16 WIDE, 32 DEEP).  Each chunk of A (BM x KC) and B (KC x BN)
 // is loaded cooperatively with coalesced accesses -- consecutive threads read
 // consecutive elements along the operand's contiguous dimension -- then stored to LDS
 // as separate real / imaginary planes indexed [k][row], so that MFMA operands are
@@ -56,9 +56,10 @@ struct Mfma<float> {
 // ---------------------------------------------------------------------------------
 template <typename T, int FLAGS, bool DEEP>
 struct GemmCfg {
-  // K chunk staged per step (FP64: half, so that the staging planes leave room for
-  // four workgroups per CU)
-  static constexpr int KC = (DEEP ? 64 : 32) / (sizeof(T) == 8 ? 2 : 1);
+  // K chunk staged per step: short chunks keep the staging planes and registers small
+  // (FP64: three waves per SIMD instead of two with chunks of 32 / 64; FP32: five
+  // instead of four)
+  static constexpr int KC = DEEP ? 32 : 16;
   static constexpr int BM = DEEP ? 32 : 64;
   static constexpr int BN = DEEP ? 32 : 64;
   static constexpr int NA = BM * KC / 256;  // A elements staged per thread per chunk
