@@ -793,7 +793,7 @@ def main():
                     help="64 independent windows in one batched Lanczos instead of one bond update")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the library has no "
               f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.fig3:

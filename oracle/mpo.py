@@ -27,7 +27,7 @@ mixed-basis Hofstadter MPOs):
   checks this anyway.
 * ``deparallelise`` then merges states whose MPO columns (or rows) are proportional.
   This is an exact rewriting, not a truncation.  (The paper trims unreachable states
-  only; merging parallel states is an addition of this build and only lowers D.)
+  only; merging parallel states is an addition here and only lowers D.)
 
 Local basis of every orbital: |0> empty, |1> occupied.  W[w, s', s, w'] = <s'|op|s>.
 """

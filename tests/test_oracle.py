@@ -87,7 +87,7 @@ def test_fig7a_worked_example():
     paper = (V / 8) * 2 * (np.cos(2 * alpha) - np.cos(4 * alpha))
     assert abs(abs(coef) - g["abs_coefficient_over_V"] * V) < 1e-14
     assert abs(abs(coef) - abs(paper)) < 1e-14
-    # sign under this build's conventions (chain-ordered product, Fourier sign of eq. H_kin)
+    # sign under these conventions (chain-ordered product, Fourier sign of eq. H_kin)
     assert abs(coef + paper) < 1e-14
 
 
