@@ -122,7 +122,16 @@ static void build_heff_tables(dm_heff_plan& p) {
   // S1: X_a = Lpanel_a (M_a x m_a) . Theta_a (m_a x N_a)
   auto build_s1 = [&](GemmStage& s1, bool bf3) {
     s1.flags = 0;
-    if (bf3) s1.tile_m = 128;  // 128 x 64 tiles for the bf16 matrix cores
+    if (bf3) {
+      // 128 x 64 tiles for the bf16 matrix cores, or 64 x 64 when that leaves fewer than
+      // two tiles per CU (small windows: more workgroups; at Ly=6, chi=800 L.theta takes
+      // 12.7 against 14.5 us, at Ly=8, chi=3200 the 128-row tiles are the faster)
+      int64_t t128 = 0;
+      for (int ai = 0; ai < a.size(); ++ai)
+        if (p.L.P.rows[ai] > 0 && p.th.P.cols[ai] > 0)
+          t128 += (int64_t)((p.L.P.rows[ai] + 127) / 128) * ((p.th.P.cols[ai] + 63) / 64);
+      s1.tile_m = t128 < 2 * (int64_t)p.ncu ? 64 : 128;
+    }
     for (int ai = 0; ai < a.size(); ++ai) {
       const int M = p.L.P.rows[ai], N = p.th.P.cols[ai], K = a.dim[ai];
       if (M == 0 || N == 0) continue;
@@ -201,13 +210,28 @@ static void build_heff_tables(dm_heff_plan& p) {
   auto build_s4 = [&](GemmStage& s4, bool bf3) {
     s4.flags = G_B_T | G_C_ROWMAP | (bf3 ? G_C_F64 : 0);  // BF16x3 writes theta' in FP64
     s4.split = true;
-    if (bf3) {  // 128 x 32 tiles, K split over workgroups in runs of >= 12 chunks of 32
-      // (at Ly=8, chi=3200 the GEMM takes about the same time for runs of 6 to 12 chunks,
-      // while fewer partial tiles halve the split reduction)
-      s4.tile_m = 128;
+    if (bf3) {
+      // 128 x 32 tiles, K split over workgroups in runs of >= 12 chunks of 32 (at Ly=8,
+      // chi=3200 the GEMM takes about the same time for runs of 6 to 12 chunks, while
+      // fewer partial tiles halve the split reduction).  Small windows: 64-row tiles when
+      // the flop-weighted problem height is below 128 (half of a 128-row tile would be
+      // padding), and runs short enough for about 2.5 workgroups per CU (at least 4
+      // chunks): the matvec at Ly=6, chi=800 takes 50 against 70 us.
+      double fl = 0.0, flm = 0.0;
+      for (int ci2 = 0; ci2 < c.size(); ++ci2) {
+        const double f = (double)p.zrows[ci2] * c.dim[ci2] * p.R.P.cols[ci2];
+        fl += f;
+        flm += f * p.zrows[ci2];
+      }
+      s4.tile_m = (fl > 0.0 && flm / fl < 128.0) ? 64 : 128;
       s4.tile_n = 32;
       s4.kc = 32;
-      s4.split_min = 12;
+      int64_t chunks = 0;
+      for (int ci2 = 0; ci2 < c.size(); ++ci2)
+        if (p.zrows[ci2] > 0)
+          chunks += (int64_t)((p.zrows[ci2] + s4.tile_m - 1) / s4.tile_m) * ((c.dim[ci2] + 31) / 32) *
+                    ((p.R.P.cols[ci2] + 31) / 32);
+      s4.split_min = (int32_t)std::min<int64_t>(12, std::max<int64_t>(4, (chunks * 2) / (5 * (int64_t)p.ncu)));
     } else {    // 32 x 32 tiles shared by four waves, >= 256 K values per split (the
                 // kernels stage them in chunks of 32)
       s4.deep = true;

@@ -312,6 +312,7 @@ hipError_t launch_gemm_bf16x3(const GemmStage& st, const float* A, const float* 
   MRD_BF3_CASE(G_A_CONJ, 32, 32, 2, 2, false)
   MRD_BF3_CASE(G_B_T | G_C_ROWMAP, 128, 32, 4, 1, true)
   MRD_BF3_CASE(G_B_T | G_C_ROWMAP | G_C_F64, 128, 32, 4, 1, true)
+  MRD_BF3_CASE(G_B_T | G_C_ROWMAP | G_C_F64, 64, 32, 4, 1, true)
   // further shapes for the batched tile tuning
   MRD_BF3_CASE(G_B_T | G_C_ROWMAP, 64, 32, 4, 1, true)
   MRD_BF3_CASE(G_B_T | G_C_ROWMAP, 64, 64, 2, 2, true)
