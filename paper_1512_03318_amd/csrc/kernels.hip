@@ -37,7 +37,7 @@ struct Mfma<float> {
 // Grouped complex GEMM on MFMA 16x16x4 with LDS staging.
 //
 // A workgroup (4 waves) owns one BM x BN output tile of one problem and walks the
-// problem's K-segments in chunks of KC (16 WIDE, 32 DEEP).  Each chunk of A (BM x KC) and B (KC x BN)
+// problem's K-segments in chunks of KC (8 WIDE, 32 DEEP).  Each chunk of A (BM x KC) and B (KC x BN)
 // is loaded cooperatively with coalesced accesses -- consecutive threads read
 // consecutive elements along the operand's contiguous dimension -- then stored to LDS
 // as separate real / imaginary planes indexed [k][row], so that MFMA operands are
@@ -57,9 +57,9 @@ struct Mfma<float> {
 template <typename T, int FLAGS, bool DEEP>
 struct GemmCfg {
   // K chunk staged per step: short chunks keep the staging planes and registers small
-  // (FP64: three waves per SIMD instead of two with chunks of 32 / 64; FP32: five
-  // instead of four)
-  static constexpr int KC = DEEP ? 32 : 16;
+  // (WIDE with chunks of 8: FP64 four waves per SIMD, FP32 seven; DEEP with 32: FP64
+  // three, FP32 five -- against two and four with the chunks of 32 / 64 of before)
+  static constexpr int KC = DEEP ? 32 : 8;
   static constexpr int BM = DEEP ? 32 : 64;
   static constexpr int BN = DEEP ? 32 : 64;
   static constexpr int NA = BM * KC / 256;  // A elements staged per thread per chunk
