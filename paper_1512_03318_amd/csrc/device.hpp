@@ -68,16 +68,30 @@ __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const Prob* __re
     const int r = e / tn, c = e - r * tn;
     const int i = tile.tm * tm + r, j = tile.tn * tn + c;
     if (i >= P.M || j >= P.N) continue;
-    T re = 0, im = 0;
-    for (int ks = 0; ks < P.nks; ++ks) {
-      if constexpr (REAL) {
-        re += part[2 * (base + ks) * slot + e];
-      } else {
-        const Cplx<T> v = ldc(part, (base + ks) * slot + e);
-        re += v.re;
-        im += v.im;
+    // the partials of this element (at most 8 splits) are all loaded before they are
+    // summed, in split order
+    T pr[8], pi[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      pr[ks] = 0;
+      pi[ks] = 0;
+      if (ks < P.nks) {
+        if constexpr (REAL) {
+          pr[ks] = part[2 * (base + ks) * slot + e];
+        } else {
+          const Cplx<T> v = ldc(part, (base + ks) * slot + e);
+          pr[ks] = v.re;
+          pi[ks] = v.im;
+        }
       }
     }
+    T re = 0, im = 0;
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks)
+      if (ks < P.nks) {
+        re += pr[ks];
+        im += pi[ks];
+      }
     const int64_t rb = (FLAGS & G_C_ROWMAP) ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
     if constexpr (REAL) C[rb + j] = re;
     else if (FLAGS & G_C_F64) stc(reinterpret_cast<double*>(C), rb + j, (double)re, (double)im);

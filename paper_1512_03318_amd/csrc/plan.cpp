@@ -191,7 +191,8 @@ void validate(const GemmStage& st, int64_t a_size, int64_t b_size, int64_t c_siz
     for (const GemmTile& t : *tl) {
       if (t.prob < 0 || t.prob >= (int)st.probs.size()) throw err(DM_ERR_LAYOUT, "bad tile");
       const GemmProb& p = st.probs[t.prob];
-      if (t.ks < 0 || t.ks >= std::max(1, p.nks)) throw err(DM_ERR_LAYOUT, "bad K-split");
+      // the split reduction sums at most 8 partial tiles per output tile
+      if (t.ks < 0 || t.ks >= std::max(1, p.nks) || p.nks > 8) throw err(DM_ERR_LAYOUT, "bad K-split");
       if (p.nks > 1) {
         const int tn = (p.N + st.tile_n - 1) / st.tile_n;
         const int64_t slot = (int64_t)p.slot0 + ((int64_t)t.tm * tn + t.tn) * p.nks + t.ks;
@@ -331,7 +332,8 @@ void validate(const PsStage& st, int64_t a_size, int64_t b_size, int64_t c_size)
     for (const GemmTile& t : *tl) {
       if (t.prob < 0 || t.prob >= (int)st.probs.size()) throw err(DM_ERR_LAYOUT, "bad tile");
       const PsProb& p = st.probs[t.prob];
-      if (t.ks < 0 || t.ks >= std::max(1, p.nks)) throw err(DM_ERR_LAYOUT, "bad K-split");
+      // the split reduction sums at most 8 partial tiles per output tile
+      if (t.ks < 0 || t.ks >= std::max(1, p.nks) || p.nks > 8) throw err(DM_ERR_LAYOUT, "bad K-split");
       if (t.tm < 0 || t.tn < 0 || t.tm * st.tile_m >= p.M || t.tn * st.tile_n >= p.N)
         throw err(DM_ERR_LAYOUT, "empty tile");
       if (p.nks > 1) {
