@@ -12,7 +12,8 @@ follows):
 * ``model``       Hofstadter cylinder term lists, real-space basis (eq. H_real) and
                   mixed basis (eqs. H_kin, H_int).
 * ``ed``          bitstring exact diagonalisation with Jordan-Wigner signs (eq. JW).
-* ``free``        free-fermion closed form from eq. H_kin.
+* ``free``        free-fermion closed form from eq. H_kin (finite cylinders and the
+                  Bloch bands of the infinite cylinder).
 * ``mpo``         finite-state-machine MPO construction (Sec. IV A-D, eq. MPO),
                   trimming and exact deparallelisation, dense contraction.
 * ``blocksparse`` U(1) x Z_Ly block-sparse tensors, environment updates and the
@@ -21,5 +22,6 @@ follows):
 * ``lanczos``     host Lanczos with full reorthogonalisation and an FP64
                   tridiagonal eigensolve.
 * ``dmrg``        finite two-site DMRG with block-wise SVD truncation.
+* ``idmrg``       infinite-cylinder DMRG by unit-cell growth on the bulk MPO cell.
 * ``synth``       environments contracted from seeded isometries.
 """

@@ -39,3 +39,37 @@ def fock_ground_energy(cyl: Cylinder) -> float:
     """Ground energy over all particle numbers: the sum of all negative levels."""
     e = levels(cyl)[0]
     return float(np.sum(e[e < 0]))
+
+
+def bulk_energy_per_orbital(Ly: int, flux_p: int, flux_q: int, t: float = 1.0,
+                            bands: int = 1, nk: int = 4096) -> float:
+    """Ground energy per orbital of the infinite cylinder at V = 0 with the lowest
+    ``bands`` magnetic bands of every ring momentum filled (density bands / flux_q).
+
+    For ring momentum k = 2 pi m / Ly, eq. H_kin is a chain in x with on-site energy
+    -2 t cos(k + x phi), phi = 2 pi p / q, which repeats every q rings; its Bloch matrix
+    at quasi-momentum kappa is q x q with that diagonal, -t between neighbouring rings
+    and -t e^{+-i q kappa} across the magnetic cell.  The filled bands contribute their
+    average over the magnetic Brillouin zone; the average of a smooth periodic function
+    over a uniform grid of ``nk`` points converges exponentially."""
+    q = flux_q
+    phi = 2.0 * np.pi * flux_p / flux_q
+    kap = (np.arange(nk) + 0.5) * (2.0 * np.pi / q) / nk
+    total = 0.0
+    for m in range(Ly):
+        k = 2.0 * np.pi * m / Ly
+        diag = -2.0 * t * np.cos(k + np.arange(q) * phi)
+        acc = 0.0
+        for kp in kap:
+            h = np.diag(diag).astype(np.complex128)
+            if q == 1:
+                h[0, 0] += -2.0 * t * np.cos(kp)
+            else:
+                for x in range(q - 1):
+                    h[x, x + 1] += -t
+                    h[x + 1, x] += -t
+                h[q - 1, 0] += -t * np.exp(1j * q * kp)
+                h[0, q - 1] += -t * np.exp(-1j * q * kp)
+            acc += float(np.sum(np.linalg.eigvalsh(h)[:bands]))
+        total += acc / nk
+    return total / (q * Ly)

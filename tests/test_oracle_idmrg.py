@@ -1,0 +1,59 @@
+"""Pins of the oracle's infinite-cylinder pieces (no GPU).
+
+* The bulk MPO cell read off the finite-state machine (Sec. IV): copies of it between the
+  boundary vectors picking R and F contract to the Hamiltonian of the finite cylinder
+  built from the term lists (eqs. H_kin, H_int) by exact diagonalisation's operator
+  algebra, which shares nothing with the machine.
+* The free-fermion energy per orbital of the infinite cylinder (Bloch bands of eq. H_kin
+  with the magnetic cell) against finite cylinders: the energy added by 2 x more rings of a
+  gapped band insulator is the bulk energy up to exponentially small end effects.
+* iDMRG by unit-cell growth at V = 0 (flux 1/3, lowest band filled) converges to that
+  closed form.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import ed, free, idmrg, model
+
+
+@pytest.mark.parametrize("Ly,flux,rings,copies", [(3, Fraction(1, 1), 1, 3), (3, Fraction(1, 3), 3, 1),
+                                                  (4, Fraction(1, 2), 2, 1)])
+def test_bulk_cell_chain_contracts_to_hamiltonian(Ly, flux, rings, copies):
+    cell = idmrg.bulk_cell(Ly, flux, 1.0, 1.0, rings)
+    n = rings * Ly
+    assert cell.n_sites == n and cell.W[0].shape[0] == cell.W[-1].shape[3]
+    assert np.array_equal(cell.qbond[0], cell.qbond[-1])
+    cyl = model.Cylinder(Ly, rings * copies, flux, 1.0, 1.0)
+    H = ed.hamiltonian(model.mixed_terms(cyl), ed.sector_basis(cyl.n_orb)).toarray()
+    got = idmrg.cell_chain_dense(cell, copies)
+    assert np.abs(got - H).max() < 1e-12
+
+
+@pytest.mark.parametrize("Ly,q", [(3, 3), (4, 4)])
+def test_bulk_free_fermion_energy_against_finite_cylinders(Ly, q):
+    e_bulk = free.bulk_energy_per_orbital(Ly, 1, q)
+    e = {Lx: free.ground_energy(model.Cylinder(Ly, Lx, Fraction(1, q), 1.0, 0.0), Lx * Ly // q)
+         for Lx in (16 * q, 32 * q)}
+    assert abs((e[32 * q] - e[16 * q]) / (16 * q * Ly) - e_bulk) < 1e-12
+
+
+def test_idmrg_free_fermions_reach_the_bulk_energy():
+    """Ly=3, flux 1/3, V=0, three particles per three-ring cell (the lowest band), chi=64:
+    the energy added per iteration, per orbital, reaches the Bloch-band value."""
+    cell = idmrg.bulk_cell(3, Fraction(1, 3), 1.0, 0.0, 3)
+    gs = workloads.growth_start(3, 3, 3, 0, 64, 7)
+    L0, R0 = idmrg.block_envs(cell, gs.left, gs.right, next(iter(gs.bonds[-1])))
+    r = idmrg.run(cell, gs.cells, 6, 64, L0, R0, gs.d)
+    e = idmrg.energy_per_orbital(r.energies, cell.n_sites)
+    exact = free.bulk_energy_per_orbital(3, 1, 3)
+    print("energy per orbital", e, "exact", exact)
+    assert abs(e[-1] - exact) < 5e-5
+    # the Schmidt values at the centre are normalised and every (N, k) sector is a charge
+    # of the bond between two cells (N near the filling of the cells to its left)
+    lam = np.concatenate(list(r.schmidt[-1].values()))
+    assert abs(np.sum(lam ** 2) - 1) < 1e-12
+    cells_left = len(r.energies) + 1          # the initial block, the absorbed cells, one cell
+    assert all(abs(q[0] - 3 * cells_left) <= 4 for q in r.schmidt[-1])

@@ -15,8 +15,9 @@ with 0 <= k < ly.  A site tensor A[a, s, b] is {(qa, s, qb): array (m_a, m_b)}.
 """
 from .synthetic import (Workload, bond_sectors, left_isometry, right_isometry,
                         random_theta, site_charges, make_workload, preset,
-                        centre_workload, PRESETS, random_env, random_site)
+                        centre_workload, PRESETS, random_env, random_site,
+                        GrowthStart, growth_start)
 
-__all__ = ["Workload", "bond_sectors", "left_isometry", "right_isometry", "random_theta",
+__all__ = ["GrowthStart", "growth_start", "Workload", "bond_sectors", "left_isometry", "right_isometry", "random_theta",
            "site_charges", "make_workload", "preset",
            "centre_workload", "PRESETS", "random_env", "random_site"]

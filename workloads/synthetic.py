@@ -73,6 +73,14 @@ def bond_sectors(n: int, qsite, ly: int, chi: int, N_tot: int, K_tot: int,
         weights = {(N, k): float(np.exp(-(N - nbar) ** 2 / (2.0 * sigma_N ** 2)))
                    for N in range(lo, hi + 1) for k in range(ly)}
         bonds.append(_apportion(chi, weights))
+    _clip(bonds, qsite, ly)
+    return [dict(sorted(bd.items())) for bd in bonds]
+
+
+def _clip(bonds: list, qsite, ly: int) -> None:
+    """Shrink sector dimensions in place until every left site tensor can be an isometry
+    from (a, s) to b and every right site tensor one from (s, c) to b."""
+    n = len(bonds) - 1
     changed = True
     while changed:
         changed = False
@@ -96,7 +104,6 @@ def bond_sectors(n: int, qsite, ly: int, chi: int, N_tot: int, K_tot: int,
                         bonds[b][q] = cap
                     else:
                         del bonds[b][q]
-    return [dict(sorted(bd.items())) for bd in bonds]
 
 
 def _gauss(rng, shape, real=False):
@@ -286,3 +293,57 @@ def preset(name: str, basis: str = "mixed", real: bool = False) -> Workload:
     """Named centre-bond workloads (see PRESETS); real=True: real entries (eq. rot)."""
     Ly, chi, seed = PRESETS[name]
     return centre_workload(name, Ly, chi, seed, basis=basis, real=real)
+
+
+@dataclass
+class GrowthStart:
+    """Seeded start of the infinite-cylinder growth: a left block of one cell (left
+    isometries from the vacuum), two cells (right isometries) and a right block of one
+    cell (right isometries to the single last sector); the two cells' last bond is their
+    first bond with every charge moved by the two cells' charge ``d``."""
+
+    ly: int
+    n: int                  # orbitals per cell
+    qsite: list             # local charges of the 4 n orbitals
+    bonds: list             # 4 n + 1 bonds
+    left: list              # n tensors
+    cells: list             # 2 n tensors
+    right: list             # n tensors
+    d: tuple
+
+
+def growth_start(Ly: int, rings: int, N_cell: int, K_cell: int, chi: int, seed: int,
+                 sigma_N: float | None = None) -> GrowthStart:
+    """Sizes from the bond recipe on a chain of four cells (Ly x 4 rings, charge
+    4 (N_cell, K_cell)); bond n and bond 3 n are cut to the sectors they share under the
+    move by two cells (the smaller dimension) and the chain is clipped again until both
+    agree.  Tensors: one generator per orbital from ``SeedSequence(seed).spawn(4 n)``."""
+    n, ly = rings * Ly, Ly
+    if sigma_N is None:
+        sigma_N = sqrt(Ly / 2.0)
+    qsite = site_charges(4 * rings, Ly)
+    d = (2 * N_cell, (2 * K_cell) % ly)
+    bonds = bond_sectors(4 * n, qsite, ly, chi, 4 * N_cell, (4 * K_cell) % ly, sigma_N)
+    bonds = [dict(b) for b in bonds]
+    while True:
+        a, b = bonds[n], bonds[3 * n]
+        common = {q: min(m, b.get(_add(q, d, ly), 0)) for q, m in a.items()}
+        common = {q: m for q, m in common.items() if m > 0}
+        moved = {_add(q, d, ly): m for q, m in common.items()}
+        moved = {(q[0], q[1]): m for q, m in moved.items()}
+        bonds[n], bonds[3 * n] = dict(common), moved
+        _clip(bonds, qsite, ly)
+        if bonds[n] == common and bonds[3 * n] == moved:
+            break
+    if not bonds[n]:
+        raise ValueError("no sector survives on the cell boundary")
+    bonds = [dict(sorted(bd.items())) for bd in bonds]
+    kids = np.random.SeedSequence(seed).spawn(4 * n)
+
+    def g(i):
+        return np.random.default_rng(kids[i])
+
+    left = [left_isometry(g(i), bonds[i], bonds[i + 1], qsite[i], ly) for i in range(n)]
+    cells = [right_isometry(g(i), bonds[i], bonds[i + 1], qsite[i], ly) for i in range(n, 3 * n)]
+    right = [right_isometry(g(i), bonds[i], bonds[i + 1], qsite[i], ly) for i in range(3 * n, 4 * n)]
+    return GrowthStart(ly, n, qsite, bonds, left, cells, right, d)
