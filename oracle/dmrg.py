@@ -120,6 +120,11 @@ def run(mpo, init: list, chis: list[int], ly: int, sweeps_per_chi: int = 4,
     qsite = [tuple(map(tuple, q)) for q in mpo.qsite]
     M = [dict(t) for t in init]
     qtot = next(iter(M[-1]))[2]
+    # bond lists: the two-site space at a bond is every charge-allowed block of its outer
+    # bonds' sectors, kept through the splits (a sector a truncation has emptied in one
+    # site tensor still spans the space)
+    B = [_left_dims(M[0])] + [{**_right_dims(M[i]), **(_left_dims(M[i + 1]) if i + 1 < n else {})}
+                              for i in range(n)]
     Ls = [None] * (n + 1)
     Rs = [None] * (n + 1)
     Ls[0] = bs.left_boundary()
@@ -138,8 +143,7 @@ def run(mpo, init: list, chis: list[int], ly: int, sweeps_per_chi: int = 4,
                 bonds = range(n - 1) if direction == "right" else range(n - 2, -1, -1)
                 for i in bonds:
                     theta = bs.contract_two_site(M[i], M[i + 1], ly)
-                    keys = bs.theta_keys(_left_dims(M[i]), _right_dims(M[i + 1]),
-                                         qsite[i], qsite[i + 1], ly)
+                    keys = bs.theta_keys(B[i], B[i + 2], qsite[i], qsite[i + 1], ly)
                     L, R = Ls[i], Rs[i + 2]
                     W1, W2 = mpo.W[i], mpo.W[i + 1]
 
@@ -147,7 +151,7 @@ def run(mpo, init: list, chis: list[int], ly: int, sweeps_per_chi: int = 4,
                         return bs.flatten(bs.heff_apply(L, W1, W2, R, bs.unflatten(v, keys)), keys)
 
                     if capture is not None:
-                        capture(i, L, R, theta, keys, _left_dims(M[i]), _right_dims(M[i + 1]))
+                        capture(i, L, R, theta, keys, dict(B[i]), dict(B[i + 2]))
 
                     e, vec, _, _, _ = lanczos(mv, bs.flatten(theta, keys), max_iter=max_iter,
                                               tol_res=tol_res)
@@ -157,6 +161,7 @@ def run(mpo, init: list, chis: list[int], ly: int, sweeps_per_chi: int = 4,
                     theta = bs.unflatten(vec, keys)
                     move = "right" if direction == "right" else "left"
                     left, right, sch, disc = split_theta(theta, chi, ly, qsite[i], move, cutoff)
+                    B[i + 1] = {q: len(v) for q, v in sorted(sch.items())}
                     res.max_discarded = max(res.max_discarded, disc)
                     M[i], M[i + 1] = left, right
                     if direction == "right":

@@ -39,7 +39,7 @@ from fractions import Fraction
 import numpy as np
 
 from . import blocksparse as bs
-from .dmrg import split_theta, _left_dims, _right_dims
+from .dmrg import split_theta
 from .lanczos import lanczos
 from .model import Cylinder
 from .mpo import F_KEY, R_KEY, build
@@ -132,6 +132,7 @@ class IDMRGResult:
     energies: list = field(default_factory=list)      # E_j, total energy of 2 (j + 1) cells
     schmidt: list = field(default_factory=list)       # per iteration: {q(centre): values}
     tensors: list = field(default_factory=list)       # last iteration's two cells
+    bonds: list = field(default_factory=list)         # and their 2n + 1 bonds
 
 
 def block_envs(cell: MPOCell, left: list, right: list, q_end) -> tuple:
@@ -148,19 +149,21 @@ def block_envs(cell: MPOCell, left: list, right: list, q_end) -> tuple:
     return L, R
 
 
-def run(cell: MPOCell, init: list, n_iter: int, chi: int, L0: dict, R0: dict, d,
+def run(cell: MPOCell, init: list, bonds: list, n_iter: int, chi: int, L0: dict, R0: dict, d,
         sweeps: int = 1, max_iter: int = 30, tol_res: float | None = 1e-300,
         cutoff: float = 1e-14) -> IDMRGResult:
-    """iDMRG by unit-cell growth from ``init``: 2n site tensors on the bonds between the
-    left block's environment L0 and the right block's R0 (right-canonical form is not
-    required); the last bond must be the first moved by the two cells' charge d."""
+    """iDMRG by unit-cell growth from ``init``: 2n site tensors on ``bonds`` (2n + 1 dicts
+    {(N, k): dim}) between the left block's environment L0 and the right block's R0
+    (right-canonical form is not required); the last bond must be the first moved by
+    the two cells' charge d.  The two-site space at a bond is every charge-allowed block
+    of its two outer bonds' sectors (the bond lists, kept through every split; a sector
+    whose blocks a truncation has emptied in one site tensor still spans the space)."""
     n, ly = cell.n_sites, cell.ly
     W = cell.W + cell.W
     qsite = [tuple(map(tuple, q)) for q in cell.qsite] * 2
     T = [dict(t) for t in init]
-    first = sorted({k[0] for k in T[0]})
-    last = sorted({k[2] for k in T[-1]})
-    if sorted(shift_charge(q, d, ly) for q in first) != last:
+    B = [dict(b) for b in bonds]
+    if len(B) != 2 * n + 1 or {shift_charge(q, d, ly): m for q, m in B[0].items()} != B[-1]:
         raise ValueError("the last bond of the two cells must be the first moved by d")
     L, R = L0, R0
     res = IDMRGResult()
@@ -169,15 +172,20 @@ def run(cell: MPOCell, init: list, n_iter: int, chi: int, L0: dict, R0: dict, d,
         Ls = [None] * (N2 + 1)
         Rs = [None] * (N2 + 1)
         Ls[0], Rs[N2] = L, R
+        def split(i, th, move):
+            left, right, sch, disc = split_theta(th, chi, ly, qsite[i], move, cutoff)
+            B[i + 1] = {q: len(v) for q, v in sorted(sch.items())}
+            return left, right, sch, disc
+
         # right-canonical form: splits moving left, no eigensolve
         for i in range(N2 - 2, -1, -1):
             th = bs.contract_two_site(T[i], T[i + 1], ly)
-            T[i], T[i + 1], _, _ = split_theta(th, chi, ly, qsite[i], "left", cutoff)
+            T[i], T[i + 1], _, _ = split(i, th, "left")
             Rs[i + 1] = bs.env_right_update(Rs[i + 2], T[i + 1], W[i + 1])
 
         def solve(i):
             th = bs.contract_two_site(T[i], T[i + 1], ly)
-            keys = bs.theta_keys(_left_dims(T[i]), _right_dims(T[i + 1]), qsite[i], qsite[i + 1], ly)
+            keys = bs.theta_keys(B[i], B[i + 2], qsite[i], qsite[i + 1], ly)
             Li, Ri, W1, W2 = Ls[i], Rs[i + 2], W[i], W[i + 1]
 
             def mv(v):
@@ -190,26 +198,28 @@ def run(cell: MPOCell, init: list, n_iter: int, chi: int, L0: dict, R0: dict, d,
         for sweep in range(sweeps):
             for i in range(N2 - 1):
                 e, th = solve(i)
-                T[i], T[i + 1], _, _ = split_theta(th, chi, ly, qsite[i], "right", cutoff)
+                T[i], T[i + 1], _, _ = split(i, th, "right")
                 Ls[i + 1] = bs.env_left_update(Ls[i], T[i], W[i])
             stop = n if sweep == sweeps - 1 else 0
             for i in range(N2 - 2, stop - 1, -1):
                 e, th = solve(i)
-                T[i], T[i + 1], _, _ = split_theta(th, chi, ly, qsite[i], "left", cutoff)
+                T[i], T[i + 1], _, _ = split(i, th, "left")
                 Rs[i + 1] = bs.env_right_update(Rs[i + 2], T[i + 1], W[i + 1])
         # the bond between the two cells
         e, th = solve(n - 1)
-        A, SV, sch, _ = split_theta(th, chi, ly, qsite[n - 1], "right", cutoff)
-        _, B, _, _ = split_theta(th, chi, ly, qsite[n - 1], "left", cutoff)
+        A, SV, sch, _ = split(n - 1, th, "right")
+        _, Bn, _, _ = split_theta(th, chi, ly, qsite[n - 1], "left", cutoff)
         T[n - 1], T[n] = A, SV
         res.energies.append(float(e))
         res.schmidt.append(sch)
         if it + 1 == n_iter:
             break
         L = bs.env_left_update(Ls[n - 1], A, W[n - 1])
-        R = shift_blocks(bs.env_right_update(Rs[n + 1], B, W[n]), d, ly)
+        R = shift_blocks(bs.env_right_update(Rs[n + 1], Bn, W[n]), d, ly)
         T = [SV] + T[n + 1:] + [shift_blocks(t, d, ly) for t in T[:n]]
+        B = B[n:] + [{shift_charge(q, d, ly): m for q, m in b.items()} for b in B[1:n + 1]]
     res.tensors = T
+    res.bonds = B
     return res
 
 

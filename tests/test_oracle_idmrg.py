@@ -46,7 +46,7 @@ def test_idmrg_free_fermions_reach_the_bulk_energy():
     cell = idmrg.bulk_cell(3, Fraction(1, 3), 1.0, 0.0, 3)
     gs = workloads.growth_start(3, 3, 3, 0, 64, 7)
     L0, R0 = idmrg.block_envs(cell, gs.left, gs.right, next(iter(gs.bonds[-1])))
-    r = idmrg.run(cell, gs.cells, 6, 64, L0, R0, gs.d)
+    r = idmrg.run(cell, gs.cells, gs.bonds[gs.n:3 * gs.n + 1], 6, 64, L0, R0, gs.d)
     e = idmrg.energy_per_orbital(r.energies, cell.n_sites)
     exact = free.bulk_energy_per_orbital(3, 1, 3)
     print("energy per orbital", e, "exact", exact)
