@@ -336,6 +336,31 @@ int dm_mps_schmidt(const dm_mps* m, int32_t i, double* values, int64_t* count);
 int dm_dmrg_sweeps(dm_mps* psi, const dm_mpo_site* w, int32_t nsweeps, int32_t chi,
                    int32_t max_iter, double cutoff, int32_t prec, double* energies,
                    dm_stream stream);
+/* Infinite-cylinder DMRG by unit-cell growth (the paper's iDMRG, Sec. I, III A, Fig. 3).
+ * cell: the n MPO site tensors of one bulk cell (the MPO repeats every n orbitals:
+ * cell[n-1]'s right states are cell[0]'s left states, same order and charges).  psi: the
+ * 2n orbitals of two cells (local charges of cell i on orbitals i and n + i) whose last
+ * bond is its first bond with every charge moved by d, the charge of the two cells
+ * (N exactly, k modulo ly).  L0 (ENV_L on psi's bond 0, states cell[0].ql) and R0
+ * (ENV_R on bond 2n, states cell[0].ql): device environments of the blocks left and
+ * right of the two cells (read on `stream`; for instance contracted from the boundary
+ * states R and F through one cell of random isometries each: a one-sector boundary
+ * here would freeze the charge of the bond between the next two cells).
+ * Iteration j: the two cells are brought to right-canonical form (dm_theta_split moving
+ * left, no eigensolve), then `sweeps` two-site sweeps as dm_dmrg_sweeps (the last one
+ * stops at bond n); at bond n theta's Lanczos ground state is split once with both
+ * gauges, energies[j] = its energy (the total energy of the 2 (j + 1) cells between the
+ * initial blocks), the left cell (left-canonical) joins the left block and the right
+ * cell (right-canonical) the right block; the next two cells start from the right cell
+ * (with the Schmidt values at its left) followed by the left cell, its charges moved by
+ * d (the right block's environment moves with it).  (E_j - E_{j-1}) / 2n is the energy
+ * per orbital.  On return psi holds the last iteration's two cells, A..A (S V^H) B..B,
+ * and dm_mps_schmidt(psi, n) the Schmidt values between them.  Environments in FP64;
+ * the plans in precision prec.  Synchronises.  After an error psi is unspecified
+ * (destroy it). */
+int dm_idmrg(dm_mps* psi, const dm_mpo_site* cell, dm_charge d, const void* L0, const void* R0,
+             int32_t n_iter, int32_t sweeps, int32_t chi, int32_t max_iter, double cutoff,
+             int32_t prec, double* energies, dm_stream stream);
 /* Entanglement spectrum of one cut (Sec. III C): energies[i] = -2 ln lambda_i (may be
  * NULL) and the entropy -sum lambda^2 ln lambda^2 of count positive Schmidt values. */
 int dm_entanglement(const double* values, int64_t count, double* entropy, double* energies);

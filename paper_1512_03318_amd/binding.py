@@ -98,6 +98,8 @@ _sigs = {
     "dm_mps_copy": (_i32, [_vp, _i32, _vp, _vp]),
     "dm_mps_schmidt": (_i32, [_vp, _i32, C.POINTER(_f64), C.POINTER(_i64)]),
     "dm_dmrg_sweeps": (_i32, [_vp, C.POINTER(DmMpoSite), _i32, _i32, _i32, _f64, _i32, C.POINTER(_f64), _vp]),
+    "dm_idmrg": (_i32, [_vp, C.POINTER(DmMpoSite), DmCharge, _vp, _vp, _i32, _i32, _i32, _i32, _f64, _i32,
+                        C.POINTER(_f64), _vp]),
     "dm_entanglement": (_i32, [C.POINTER(_f64), _i64, C.POINTER(_f64), C.POINTER(_f64)]),
     "dm_mpo_hofstadter": (_i32, [_i32, _i32, _i32, _i32, _f64, _f64, _i32, C.POINTER(_vp)]),
     "dm_mpo_n_sites": (_i32, [_vp]),
@@ -458,6 +460,17 @@ def dmrg_sweeps(psi: MPS, sites, nsweeps, chi, max_iter=30, cutoff=1e-14, prec=D
     arr = (DmMpoSite * len(sites))(*[s.c for s in sites])
     e = (_f64 * nsweeps)()
     _check(lib.dm_dmrg_sweeps(psi.h, arr, nsweeps, chi, max_iter, cutoff, prec, e, _stream(stream)))
+    return list(e)
+
+
+def idmrg(psi: MPS, cell, d, L0, R0, n_iter, chi, sweeps=1, max_iter=30, cutoff=1e-14, prec=DM_FP64,
+          stream=None):
+    """Energies E_j of n_iter growth iterations (dm_idmrg); psi holds 2 len(cell) orbitals,
+    d = charge of the two cells, L0 / R0 device environments of the initial blocks."""
+    arr = (DmMpoSite * len(cell))(*[s.c for s in cell])
+    e = (_f64 * n_iter)()
+    _check(lib.dm_idmrg(psi.h, arr, DmCharge(int(d[0]), int(d[1])), _ptr(L0), _ptr(R0), n_iter, sweeps, chi,
+                        max_iter, cutoff, prec, e, _stream(stream)))
     return list(e)
 
 
