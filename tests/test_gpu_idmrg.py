@@ -4,9 +4,18 @@
   same seeded start (one-cell random blocks, two random right-canonical cells) the GPU's
   total energies E_j equal the oracle's iDMRG iteration by iteration, and the Schmidt
   values between the last two cells agree sector by sector.
+  With one particle of momentum 1 added per cell (two cells carry k = 2), the growth
+  moves every charge by (6, 2), which reorders sectors: the same comparison then checks
+  the panel permutation of the moved site tensors and environment.
 * The same cylinder at V=0: the energy added per iteration, per orbital, reaches the
   free-fermion Bloch-band value (closed form).
+* The model of Fig. 3 (Ly=10, flux 1/3, V/t=0.1, the lowest band filled: ten particles
+  per three-ring cell of 30 orbitals) in the mixed basis and in the real-space basis at
+  the same chi: time per growth iteration, energy per orbital and centre entropy (printed;
+  asserted: both bases agree on the energy per orbital, which lies above the V=0 Bloch
+  value).
 """
+import time
 import sys
 from fractions import Fraction
 
@@ -48,11 +57,13 @@ def gpu_start(cell, gs):
 
 
 @pytest.mark.timeout(900)
-def test_gpu_idmrg_equals_the_oracle():
+@pytest.mark.parametrize("K_cell", [0, 1])
+def test_gpu_idmrg_equals_the_oracle(K_cell):
     cell = idmrg.bulk_cell(3, Fraction(1, 3), 1.0, 1.0, 3)
-    gs = workloads.growth_start(3, 3, 3, 0, 32, 17)
+    gs = workloads.growth_start(3, 3, 3, K_cell, 32, 17)
     n, chi, iters = gs.n, 32, 4
-    say(f"iDMRG Ly=3 flux 1/3 V=1, {n}-orbital cell (D {cell.W[0].shape[0]}), chi={chi}, {iters} iterations")
+    say(f"iDMRG Ly=3 flux 1/3 V=1, {n}-orbital cell (D {cell.W[0].shape[0]}), two cells' charge {gs.d}, "
+        f"chi={chi}, {iters} iterations")
     psi, sites, (L0, R0), (l0, r0) = gpu_start(cell, gs)
     e = pk.idmrg(psi, sites, gs.d, l0, r0, iters, chi)
     r = idmrg.run(cell, gs.cells, gs.bonds[n:3 * n + 1], iters, chi, L0, R0, gs.d)
@@ -82,3 +93,71 @@ def test_gpu_idmrg_free_fermions_reach_the_bulk_energy():
     exact = free.bulk_energy_per_orbital(3, 1, 3)
     say(f"iDMRG V=0: energy per orbital {['%.9f' % x for x in per]}, Bloch bands {exact:.9f}")
     assert abs(per[-1] - exact) < 5e-5
+
+
+def gpu_block_envs(cell, gs, sites):
+    """L0 and R0 contracted on the device (env_update_left / _right) from the boundary
+    states R and F through the growth start's random one-cell blocks."""
+    ly, n = gs.ly, gs.n
+    B = [pk.Bond(b) for b in gs.bonds]
+    qs = [[tuple(map(int, q)) for q in cell.qsite[i]] for i in range(n)]
+    one = np.ones((1, 1), dtype=np.complex128)
+    L = to_dev(pk.pack({((0, 0), cell.r, (0, 0)): one}, pk.LAYOUT_ENV_L, ly, B[0], qw=cell.qbond[0]))
+    for i in range(n):
+        A = to_dev(pk.pack(gs.left[i], pk.LAYOUT_SITE, ly, B[i], B[i + 1], qs1=qs[i]))
+        out = torch.zeros(pk.layout(pk.LAYOUT_ENV_L, ly, B[i + 1], qw=cell.qbond[i + 1])[1],
+                          dtype=torch.complex128, device="cuda")
+        pk.env_update_left(ly, B[i], B[i + 1], sites[i], L, A, out)
+        L = out
+    q = next(iter(gs.bonds[-1]))
+    R = to_dev(pk.pack({(q, cell.f, q): one}, pk.LAYOUT_ENV_R, ly, B[4 * n], qw=cell.qbond[0]))
+    for i in range(n - 1, -1, -1):
+        j = 3 * n + i
+        Bt = to_dev(pk.pack(gs.right[i], pk.LAYOUT_SITE, ly, B[j], B[j + 1], qs1=qs[i]))
+        out = torch.zeros(pk.layout(pk.LAYOUT_ENV_R, ly, B[j], qw=cell.qbond[i])[1],
+                          dtype=torch.complex128, device="cuda")
+        pk.env_update_right(ly, B[j], B[j + 1], sites[i], R, Bt, out)
+        R = out
+    return L, R
+
+
+@pytest.mark.timeout(900)
+def test_gpu_idmrg_fig3_model():
+    """Fig. 3's cylinder: Ly=10, flux 1/3, V/t=0.1, 1/3 filling, three-ring cells."""
+    Ly = 10
+    runs = {"mixed": [(100, 8), (200, 8), (400, 8)], "real": [(100, 3), (200, 3)]}
+    e0 = free.bulk_energy_per_orbital(Ly, 1, 3)
+    res = {}
+    for basis, plan in runs.items():
+        t0 = time.perf_counter()
+        cell = idmrg.bulk_cell(Ly, Fraction(1, 3), 1.0, 0.1, 3, basis=basis)
+        say(f"{basis} basis: bulk cell of {cell.n_sites} orbitals, D {min(w.shape[0] for w in cell.W)}.."
+            f"{max(w.shape[0] for w in cell.W)} ({time.perf_counter() - t0:.1f} s on the host)")
+        for chi, iters in plan:
+            gs = workloads.growth_start(Ly, 3, Ly, (Ly * (Ly - 1) // 2) % Ly, chi, 30 + chi, basis=basis)
+            n = gs.n
+            qs = [[tuple(map(int, q)) for q in cell.qsite[i % n]] for i in range(2 * n)]
+            bonds = gs.bonds[n:3 * n + 1]
+            Bd = [pk.Bond(b) for b in bonds]
+            tens = [to_dev(pk.pack(gs.cells[i], pk.LAYOUT_SITE, gs.ly, Bd[i], Bd[i + 1], qs1=qs[i]))
+                    for i in range(2 * n)]
+            psi = pk.MPS(gs.ly, bonds, qs, tens)
+            sites = [pk.MpoSite(cell.W[i], cell.qbond[i], cell.qbond[i + 1], cell.qsite[i]) for i in range(n)]
+            l0, r0 = gpu_block_envs(cell, gs, sites)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            e = pk.idmrg(psi, sites, gs.d, l0, r0, iters, chi)
+            dt = (time.perf_counter() - t1) / iters
+            per = idmrg.energy_per_orbital(e, n)
+            lam = psi.schmidt(n)
+            ent, _ = pk.entanglement(lam[lam > 0])
+            res[(basis, chi)] = (per, dt)
+            say(f"  chi={chi}: {dt:.2f} s per growth iteration ({iters}), energy per orbital "
+                f"{['%.6f' % x for x in per]}, centre entropy {ent:.6f}, {len(psi.bond(n))} sectors")
+            assert all(x > e0 for x in per)  # V n n >= 0: above the V=0 Bloch-band energy
+    for chi in (100, 200):
+        say(f"chi={chi}: real-space / mixed time per growth iteration "
+            f"{res[('real', chi)][1] / res[('mixed', chi)][1]:.1f}x")
+    per = res[("mixed", 400)][0]
+    say(f"mixed chi=400: last two estimates {per[-2]:.6f}, {per[-1]:.6f} (V=0 Bloch value {e0:.6f})")
+    assert abs(per[-1] - per[-2]) < 2e-3

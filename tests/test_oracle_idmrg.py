@@ -1,9 +1,10 @@
 """Pins of the oracle's infinite-cylinder pieces (no GPU).
 
-* The bulk MPO cell read off the finite-state machine (Sec. IV): copies of it between the
-  boundary vectors picking R and F contract to the Hamiltonian of the finite cylinder
-  built from the term lists (eqs. H_kin, H_int) by exact diagonalisation's operator
-  algebra, which shares nothing with the machine.
+* The bulk MPO cell read off the finite-state machine (Sec. IV), mixed and real-space
+  basis: copies of it between the boundary vectors picking R and F contract to the
+  Hamiltonian of the finite cylinder built from the term lists (eqs. H_kin, H_int;
+  eq. H_real) by exact diagonalisation's operator algebra, which shares nothing with the
+  machine.
 * The free-fermion energy per orbital of the infinite cylinder (Bloch bands of eq. H_kin
   with the magnetic cell) against finite cylinders: the energy added by 2 x more rings of a
   gapped band insulator is the bulk energy up to exponentially small end effects.
@@ -19,15 +20,16 @@ import workloads
 from oracle import ed, free, idmrg, model
 
 
+@pytest.mark.parametrize("basis", ["mixed", "real"])
 @pytest.mark.parametrize("Ly,flux,rings,copies", [(3, Fraction(1, 1), 1, 3), (3, Fraction(1, 3), 3, 1),
                                                   (4, Fraction(1, 2), 2, 1)])
-def test_bulk_cell_chain_contracts_to_hamiltonian(Ly, flux, rings, copies):
-    cell = idmrg.bulk_cell(Ly, flux, 1.0, 1.0, rings)
+def test_bulk_cell_chain_contracts_to_hamiltonian(Ly, flux, rings, copies, basis):
+    cell = idmrg.bulk_cell(Ly, flux, 1.0, 1.0, rings, basis=basis)
     n = rings * Ly
     assert cell.n_sites == n and cell.W[0].shape[0] == cell.W[-1].shape[3]
     assert np.array_equal(cell.qbond[0], cell.qbond[-1])
     cyl = model.Cylinder(Ly, rings * copies, flux, 1.0, 1.0)
-    H = ed.hamiltonian(model.mixed_terms(cyl), ed.sector_basis(cyl.n_orb)).toarray()
+    H = ed.hamiltonian(model.terms_for(cyl, basis), ed.sector_basis(cyl.n_orb)).toarray()
     got = idmrg.cell_chain_dense(cell, copies)
     assert np.abs(got - H).max() < 1e-12
 

@@ -313,15 +313,16 @@ class GrowthStart:
 
 
 def growth_start(Ly: int, rings: int, N_cell: int, K_cell: int, chi: int, seed: int,
-                 sigma_N: float | None = None) -> GrowthStart:
+                 sigma_N: float | None = None, basis: str = "mixed") -> GrowthStart:
     """Sizes from the bond recipe on a chain of four cells (Ly x 4 rings, charge
     4 (N_cell, K_cell)); bond n and bond 3 n are cut to the sectors they share under the
     move by two cells (the smaller dimension) and the chain is clipped again until both
-    agree.  Tensors: one generator per orbital from ``SeedSequence(seed).spawn(4 n)``."""
-    n, ly = rings * Ly, Ly
+    agree.  Tensors: one generator per orbital from ``SeedSequence(seed).spawn(4 n)``.
+    basis="real": the real-space basis (charges (1, 0), modulus 1; K_cell ignored)."""
+    n, ly = rings * Ly, (Ly if basis == "mixed" else 1)
     if sigma_N is None:
         sigma_N = sqrt(Ly / 2.0)
-    qsite = site_charges(4 * rings, Ly)
+    qsite = site_charges(4 * rings, Ly, basis)
     d = (2 * N_cell, (2 * K_cell) % ly)
     bonds = bond_sectors(4 * n, qsite, ly, chi, 4 * N_cell, (4 * K_cell) % ly, sigma_N)
     bonds = [dict(b) for b in bonds]
