@@ -86,7 +86,10 @@ typedef struct ihipStream_t* dm_stream; /* hipStream_t; NULL is the default stre
 #define DM_ERR_NONFINITE (-8) /* Lanczos produced a NaN or Inf                   */
 
 /* Arithmetic of the block GEMMs.  Inputs and outputs stay complex128; Lanczos
- * scalars, reorthogonalisation and the tridiagonal solve are FP64 in every mode. */
+ * scalars, reorthogonalisation and the tridiagonal solve are FP64 in every mode.  In
+ * DM_FP32 and DM_BF16X3 the Krylov basis is stored in complex FP32: each Lanczos vector
+ * is rounded once as it is formed (the FP32 value is what the matvec reads) and every
+ * product and sum over the basis is FP64. */
 #define DM_FP64 0
 #define DM_FP32 1
 #define DM_BF16X3 2 /* hi/lo bfloat16 split of FP32 operands, FP32 accumulation */

@@ -739,6 +739,7 @@ void mrd::ensure_lanczos(dm_heff_plan* p, int max_iter) {
     // pre-split operands splits v_j itself)
     I[0].tin = p->staged_in() ? (float*)p->dTin : nullptr;
     p->lzg = lz_layout(I, p->Vcap - 1);
+    p->lzg.vf32 = p->prec != DM_FP64;  // FP32 / BF16x3: the basis in FP32, as the matvec reads it
     *p->hInst = I[0];
   }
   if (p->prec != DM_FP64) {

@@ -605,7 +605,8 @@ static int lanczos_ground_batched_impl(dm_batch* b, void* const* thetas, int32_t
       I[i].xn = 2 * p->n();  // complex instances (real plans are not batched)
       I[i].real = 0;
     }
-    const LzGrid g = lz_layout(I, max_iter);
+    LzGrid g = lz_layout(I, max_iter);
+    g.vf32 = b->prec != DM_FP64;
     const bool same = b->graph_exec && std::equal(I.begin(), I.end(), b->hInst, [](const LzInst& x, const LzInst& y) {
       return x.V == y.V && x.w == y.w && x.vcur == y.vcur && x.part == y.part && x.st == y.st;
     });

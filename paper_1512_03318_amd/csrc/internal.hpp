@@ -285,7 +285,8 @@ struct LzState {
 // all instances of its table at once: a flat grid whose blocks are assigned to
 // instances by the first-block offsets c0 / g0 (found by binary search).
 struct LzInst {
-  double* V;       // Krylov basis, vector j at V + 2 j ld (doubles)
+  double* V;       // Krylov basis, vector j at element j ld (complex FP64, or FP32 pairs
+                   // when the launch grid says vf32)
   double* w;       // H v_j
   double* vcur;    // v_j (matvec input of every step)
   double* part;    // projection partials: nb x (2 max_iter + 1)
@@ -308,6 +309,9 @@ struct LzInst {
 struct LzGrid {
   int32_t nins = 0, nchunk = 0, n256 = 0;
   int32_t max_iter = 0;  // capacity: Krylov vectors - 1 of every instance
+  // every instance keeps its Krylov basis in complex FP32 (V holds float pairs, same
+  // element stride ld): plans whose matvec reads an FP32 copy of v_j
+  bool vf32 = false;
 };
 struct LzResult {
   double energy;

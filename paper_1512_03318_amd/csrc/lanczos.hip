@@ -32,6 +32,31 @@ namespace mrd {
 typedef double lzc __attribute__((ext_vector_type(2)));
 typedef float lzf __attribute__((ext_vector_type(2)));
 
+// Krylov basis storage: complex FP64, or (F32) complex FP32 for plans whose matvec reads
+// an FP32 copy of v_j anyway.  Every vector is rounded once as it is formed, v_j in the
+// basis is then exactly the matvec's input, and all arithmetic on it stays FP64.
+template <bool F32>
+struct LzV {
+  typedef lzc T;
+};
+template <>
+struct LzV<true> {
+  typedef lzf T;
+};
+__device__ __forceinline__ lzc lz_wide(lzc v) { return v; }
+__device__ __forceinline__ lzc lz_wide(lzf v) { return lzc{(double)v.x, (double)v.y}; }
+// x rounded to the storage (in place) and returned in storage form
+template <bool F32>
+__device__ __forceinline__ typename LzV<F32>::T lz_round(lzc& x) {
+  if constexpr (F32) {
+    const lzf r = lzf{(float)x.x, (float)x.y};
+    x = lz_wide(r);
+    return r;
+  } else {
+    return x;
+  }
+}
+
 constexpr int LZ_EPT = 4;                 // elements per thread in streaming kernels
 constexpr int LZ_CHUNK = 256 * LZ_EPT;
 
@@ -194,6 +219,7 @@ __global__ void __launch_bounds__(256) lz_reduce_kernel(const LzInst* __restrict
 }
 
 // v_0 = x / |x| into V[0] and vcur.
+template <bool F32>
 __global__ void lz_start_scale_kernel(const LzInst* __restrict__ I, int nins) {
   const int q0 = lz_find<1>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
@@ -211,8 +237,8 @@ __global__ void lz_start_scale_kernel(const LzInst* __restrict__ I, int nins) {
   if (e >= in.n) return;
   const auto xr = glb(in.x);
   const double x0 = xr[2 * e], x1 = 2 * e + 1 < in.xn ? xr[2 * e + 1] : 0.0;
-  const lzc v = lzc{x0 * s, x1 * s};
-  glb(reinterpret_cast<lzc*>(in.V))[e] = v;
+  lzc v = lzc{x0 * s, x1 * s};
+  glb(reinterpret_cast<typename LzV<F32>::T*>(in.V))[e] = lz_round<F32>(v);
   glb(reinterpret_cast<lzc*>(in.vcur))[e] = v;
   if (in.tin) glb(reinterpret_cast<lzf*>(in.tin))[e] = lzf{(float)v.x, (float)v.y};
 }
@@ -243,19 +269,20 @@ __device__ __forceinline__ void block_sums(const double (&v)[NVAL], int nval, do
 // of LZ_G vectors; a group's loads are all issued before its products (measured at 30
 // vectors of 660k elements: 56 us against 74 us with one block per chunk and group,
 // which re-read w and ended after one round of loads).
-template <int NG>
+template <int NG, bool F32>
 __device__ __forceinline__ void lz_dots_group(const LzInst& in, const lzc (&xe)[LZ_EPT],
                                               int64_t e0, bool full, int i0, int nv, int blk,
                                               double* sh) {
-  const auto v0 = glb(reinterpret_cast<const lzc*>(in.V));
-  MRD_GLOBAL const lzc* vv[NG];
+  typedef typename LzV<F32>::T VT;
+  const auto v0 = glb(reinterpret_cast<const VT*>(in.V));
+  MRD_GLOBAL const VT* vv[NG];
 #pragma unroll
   for (int g = 0; g < NG; ++g) vv[g] = v0 + (int64_t)(i0 + g) * in.ld;
   double acc[2 * NG];
 #pragma unroll
   for (int c = 0; c < 2 * NG; ++c) acc[c] = 0.0;
   if (full) {
-    lzc v[NG][LZ_EPT];
+    VT v[NG][LZ_EPT];
 #pragma unroll
     for (int g = 0; g < NG; ++g)
 #pragma unroll
@@ -274,7 +301,7 @@ __device__ __forceinline__ void lz_dots_group(const LzInst& in, const lzc (&xe)[
       if (e < in.n) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-          const lzc v = vv[g][e];
+          const lzc v = lz_wide(vv[g][e]);
           acc[2 * g] += v.x * xe[q].x + v.y * xe[q].y;
           acc[2 * g + 1] += v.x * xe[q].y - v.y * xe[q].x;
         }
@@ -284,6 +311,7 @@ __device__ __forceinline__ void lz_dots_group(const LzInst& in, const lzc (&xe)[
   block_sums(acc, 2 * NG, sh, glb(in.part) + (int64_t)blk * (2 * nv) + 2 * i0);
 }
 
+template <bool F32>
 __global__ void __launch_bounds__(256) lz_dots_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4 * 2 * LZ_G];
   const int q0 = lz_find<0>(I, nins, blockIdx.x);
@@ -301,14 +329,14 @@ __global__ void __launch_bounds__(256) lz_dots_kernel(const LzInst* __restrict__
   for (int i0 = 0; i0 < nv; i0 += LZ_G) {
     if (i0 > 0) __syncthreads();  // the previous group's sums have been read from sh
     switch (min(LZ_G, nv - i0)) {  // uniform over the block
-      case 1: lz_dots_group<1>(in, xe, e0, full, i0, nv, blk, sh); break;
-      case 2: lz_dots_group<2>(in, xe, e0, full, i0, nv, blk, sh); break;
-      case 3: lz_dots_group<3>(in, xe, e0, full, i0, nv, blk, sh); break;
-      case 4: lz_dots_group<4>(in, xe, e0, full, i0, nv, blk, sh); break;
-      case 5: lz_dots_group<5>(in, xe, e0, full, i0, nv, blk, sh); break;
-      case 6: lz_dots_group<6>(in, xe, e0, full, i0, nv, blk, sh); break;
-      case 7: lz_dots_group<7>(in, xe, e0, full, i0, nv, blk, sh); break;
-      default: lz_dots_group<LZ_G>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 1: lz_dots_group<1, F32>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 2: lz_dots_group<2, F32>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 3: lz_dots_group<3, F32>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 4: lz_dots_group<4, F32>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 5: lz_dots_group<5, F32>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 6: lz_dots_group<6, F32>(in, xe, e0, full, i0, nv, blk, sh); break;
+      case 7: lz_dots_group<7, F32>(in, xe, e0, full, i0, nv, blk, sh); break;
+      default: lz_dots_group<LZ_G, F32>(in, xe, e0, full, i0, nv, blk, sh); break;
     }
   }
 }
@@ -317,29 +345,32 @@ constexpr int LZ_U = 4;  // basis vectors loaded together in the subtraction loo
 
 // x -= sum_{i < nv} h_i V_i[e] (h complex, interleaved), subtracted in index order;
 // the loads of LZ_U vectors are issued before their products.
-__device__ __forceinline__ void lz_sub_basis(lzc& x, MRD_GLOBAL const lzc* V, int64_t ld,
+template <typename VT>
+__device__ __forceinline__ void lz_sub_basis(lzc& x, MRD_GLOBAL const VT* V, int64_t ld,
                                              int64_t e, const MRD_GLOBAL double* h, int nv) {
   int i = 0;
   for (; i + LZ_U <= nv; i += LZ_U) {
-    lzc v[LZ_U];
+    VT vs[LZ_U];
 #pragma unroll
-    for (int u = 0; u < LZ_U; ++u) v[u] = V[(int64_t)(i + u) * ld + e];
+    for (int u = 0; u < LZ_U; ++u) vs[u] = V[(int64_t)(i + u) * ld + e];
 #pragma unroll
     for (int u = 0; u < LZ_U; ++u) {
+      const lzc v = lz_wide(vs[u]);
       const double hr = h[2 * (i + u)], hi = h[2 * (i + u) + 1];
-      x.x -= hr * v[u].x - hi * v[u].y;
-      x.y -= hr * v[u].y + hi * v[u].x;
+      x.x -= hr * v.x - hi * v.y;
+      x.y -= hr * v.y + hi * v.x;
     }
   }
   for (; i < nv; ++i) {
     const double hr = h[2 * i], hi = h[2 * i + 1];
-    const lzc v = V[(int64_t)i * ld + e];
+    const lzc v = lz_wide(V[(int64_t)i * ld + e]);
     x.x -= hr * v.x - hi * v.y;
     x.y -= hr * v.y + hi * v.x;
   }
 }
 
 // w -= V h1 over the nv = iter + 1 Krylov vectors; pnorm[chunk] = |w_new|^2 over the chunk.
+template <bool F32>
 __global__ void __launch_bounds__(256) lz_sub_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4];
   const int q0 = lz_find<0>(I, nins, blockIdx.x);
@@ -348,7 +379,7 @@ __global__ void __launch_bounds__(256) lz_sub_kernel(const LzInst* __restrict__ 
   if (st->stop) return;
   const int nv = st->iter + 1;
   const MRD_GLOBAL double* h1 = st->h1;
-  const auto V = glb(reinterpret_cast<const lzc*>(in.V));
+  const auto V = glb(reinterpret_cast<const typename LzV<F32>::T*>(in.V));
   const auto w = glb(reinterpret_cast<lzc*>(in.w));
   const int64_t ld = in.ld;
   const int blk = blockIdx.x - in.c0;
@@ -410,7 +441,7 @@ __device__ __forceinline__ bool lz_over_bound(LzState* st, int nv, int nvb) {
 // then part[blk][2i + {0,1}] = sum of conj(V_i) w1 and part[blk][2 nv] = sum of |w1|^2
 // over the chunk.  Each thread holds its element of every vector in registers between
 // the subtraction and the products, so the basis is read once for both.
-template <int NVB>
+template <int NVB, bool F32>
 __global__ void __launch_bounds__(256) lz_subdots_kernel(const LzInst* __restrict__ I, int nins) {
   __shared__ double sh[4 * (2 * NVB + 1)];
   const int q0 = lz_find<0>(I, nins, blockIdx.x);
@@ -422,7 +453,7 @@ __global__ void __launch_bounds__(256) lz_subdots_kernel(const LzInst* __restric
   const int blk = blockIdx.x - in.c0;
   const auto h1 = glb(st->h1);
   const auto w = glb(reinterpret_cast<lzc*>(in.w));
-  const auto V = glb(reinterpret_cast<const lzc*>(in.V));
+  const auto V = glb(reinterpret_cast<const typename LzV<F32>::T*>(in.V));
   const int64_t ld = in.ld;
   double acc[2 * NVB + 1];
 #pragma unroll
@@ -434,7 +465,7 @@ __global__ void __launch_bounds__(256) lz_subdots_kernel(const LzInst* __restric
     lzc v[NVB];
 #pragma unroll
     for (int i = 0; i < NVB; ++i)
-      if (i < nv) v[i] = V[i * ld + e];
+      if (i < nv) v[i] = lz_wide(V[i * ld + e]);
     lzc x = w[e];
 #pragma unroll
     for (int i = 0; i < NVB; ++i)
@@ -484,6 +515,7 @@ __global__ void lz_scalar_kernel(const LzInst* __restrict__ I) {
 }
 
 // v_{j+1} = (w - V h2) / beta_j into V[j+1] and vcur (runs only if the step continued).
+template <bool F32>
 __global__ void __launch_bounds__(256) lz_next_kernel(const LzInst* __restrict__ I, int nins) {
   const int q0 = lz_find<1>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
@@ -492,14 +524,14 @@ __global__ void __launch_bounds__(256) lz_next_kernel(const LzInst* __restrict__
   const int nv = st->iter;  // already advanced: vectors 0 .. j
   const int64_t e = (int64_t)(blockIdx.x - in.g0) * 256 + threadIdx.x;
   if (e >= in.n) return;
-  const auto V = glb(reinterpret_cast<lzc*>(in.V));
+  const auto V = glb(reinterpret_cast<typename LzV<F32>::T*>(in.V));
   const int64_t ld = in.ld;
   lzc x = glb(reinterpret_cast<const lzc*>(in.w))[e];
-  lz_sub_basis(x, V, ld, e, st->h2, nv);
+  lz_sub_basis(x, (MRD_GLOBAL const typename LzV<F32>::T*)V, ld, e, st->h2, nv);
   const double s = st->inv_beta;
   x.x *= s;
   x.y *= s;
-  V[(int64_t)nv * ld + e] = x;
+  V[(int64_t)nv * ld + e] = lz_round<F32>(x);
   glb(reinterpret_cast<lzc*>(in.vcur))[e] = x;
   if (in.tin) glb(reinterpret_cast<lzf*>(in.tin))[e] = lzf{(float)x.x, (float)x.y};
 }
@@ -620,6 +652,7 @@ __global__ void __launch_bounds__(64) lz_tridiag_kernel(const LzInst* __restrict
 }
 
 // Ritz vector sum_{i < k} y_i V_i into x and vcur.
+template <bool F32>
 __global__ void lz_combine_kernel(const LzInst* __restrict__ I, int nins) {
   const int q0 = lz_find<1>(I, nins, blockIdx.x);
   const LzInst& in = I[q0];
@@ -627,22 +660,24 @@ __global__ void lz_combine_kernel(const LzInst* __restrict__ I, int nins) {
   if (e >= in.n) return;
   const MRD_GLOBAL LzState* st = glb(in.st);
   const int k = st->k;
-  const auto V = glb(reinterpret_cast<const lzc*>(in.V));
+  typedef typename LzV<F32>::T VT;
+  const auto V = glb(reinterpret_cast<const VT*>(in.V));
   const MRD_GLOBAL double* y = st->y;
   double r = 0, im = 0;
   int i = 0;
   for (; i + LZ_U <= k; i += LZ_U) {  // loads first, then the sums in index order
-    lzc v[LZ_U];
+    VT vs[LZ_U];
 #pragma unroll
-    for (int u = 0; u < LZ_U; ++u) v[u] = V[(int64_t)(i + u) * in.ld + e];
+    for (int u = 0; u < LZ_U; ++u) vs[u] = V[(int64_t)(i + u) * in.ld + e];
 #pragma unroll
     for (int u = 0; u < LZ_U; ++u) {
-      r += y[i + u] * v[u].x;
-      im += y[i + u] * v[u].y;
+      const lzc v = lz_wide(vs[u]);
+      r += y[i + u] * v.x;
+      im += y[i + u] * v.y;
     }
   }
   for (; i < k; ++i) {
-    const lzc v = V[(int64_t)i * in.ld + e];
+    const lzc v = lz_wide(V[(int64_t)i * in.ld + e]);
     r += y[i] * v.x;
     im += y[i] * v.y;
   }
@@ -708,38 +743,46 @@ hipError_t lz_launch_init(const LzInst* I, const LzGrid& g, int32_t max_iter, do
 hipError_t lz_launch_start(const LzInst* I, const LzGrid& g, hipStream_t s) {
   hipLaunchKernelGGL(lz_norm_kernel, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
   hipLaunchKernelGGL(lz_reduce_kernel, dim3(1, g.nins), dim3(256), 0, s, I, (int32_t)LZR_SCAL0);
-  hipLaunchKernelGGL(lz_start_scale_kernel, dim3(g.n256), dim3(256), 0, s, I, g.nins);
+  if (g.vf32) hipLaunchKernelGGL(lz_start_scale_kernel<true>, dim3(g.n256), dim3(256), 0, s, I, g.nins);
+  else hipLaunchKernelGGL(lz_start_scale_kernel<false>, dim3(g.n256), dim3(256), 0, s, I, g.nins);
   return hipGetLastError();
 }
 
-hipError_t lz_launch_step_tail(const LzInst* I, const LzGrid& g, int32_t nv_bound, hipStream_t s) {
+template <bool F32>
+static void lz_step_tail(const LzInst* I, const LzGrid& g, int32_t nv_bound, hipStream_t s) {
   const int maxc = 2 * g.max_iter + 1;
   // nv <= max_iter at every step; without a bound from the caller (a step captured once
   // for every replay) the capacity bounds it
   const int b = (nv_bound > 0 && nv_bound < g.max_iter) ? nv_bound : g.max_iter;
   const dim3 gd(g.nchunk);  // projections: one block per chunk over the whole basis
-  hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, I, g.nins);
+  hipLaunchKernelGGL(lz_dots_kernel<F32>, gd, dim3(256), 0, s, I, g.nins);
   hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H1);
   if (b <= LZ_FUSE) {
     // one pass for w1, h2 and |w1|^2
-    if (b <= 8) hipLaunchKernelGGL(lz_subdots_kernel<8>, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
-    else if (b <= 16) hipLaunchKernelGGL(lz_subdots_kernel<16>, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
-    else hipLaunchKernelGGL(lz_subdots_kernel<LZ_FUSE>, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+    if (b <= 8) hipLaunchKernelGGL((lz_subdots_kernel<8, F32>), dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+    else if (b <= 16) hipLaunchKernelGGL((lz_subdots_kernel<16, F32>), dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+    else hipLaunchKernelGGL((lz_subdots_kernel<LZ_FUSE, F32>), dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
     hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H2N);
   } else {
-    hipLaunchKernelGGL(lz_sub_kernel, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
-    hipLaunchKernelGGL(lz_dots_kernel, gd, dim3(256), 0, s, I, g.nins);
+    hipLaunchKernelGGL(lz_sub_kernel<F32>, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+    hipLaunchKernelGGL(lz_dots_kernel<F32>, gd, dim3(256), 0, s, I, g.nins);
     hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H2);
     hipLaunchKernelGGL(lz_reduce_kernel, dim3(1, g.nins), dim3(256), 0, s, I, (int32_t)LZR_NORM);
   }
   hipLaunchKernelGGL(lz_scalar_kernel, dim3(g.nins), dim3(64), 0, s, I);
-  hipLaunchKernelGGL(lz_next_kernel, dim3(g.n256), dim3(256), 0, s, I, g.nins);
+  hipLaunchKernelGGL(lz_next_kernel<F32>, dim3(g.n256), dim3(256), 0, s, I, g.nins);
+}
+
+hipError_t lz_launch_step_tail(const LzInst* I, const LzGrid& g, int32_t nv_bound, hipStream_t s) {
+  if (g.vf32) lz_step_tail<true>(I, g, nv_bound, s);
+  else lz_step_tail<false>(I, g, nv_bound, s);
   return hipGetLastError();
 }
 
 hipError_t lz_launch_finish(const LzInst* I, const LzGrid& g, hipStream_t s) {
   hipLaunchKernelGGL(lz_tridiag_kernel, dim3(g.nins), dim3(64), 0, s, I);
-  hipLaunchKernelGGL(lz_combine_kernel, dim3(g.n256), dim3(256), 0, s, I, g.nins);
+  if (g.vf32) hipLaunchKernelGGL(lz_combine_kernel<true>, dim3(g.n256), dim3(256), 0, s, I, g.nins);
+  else hipLaunchKernelGGL(lz_combine_kernel<false>, dim3(g.n256), dim3(256), 0, s, I, g.nins);
   return hipGetLastError();
 }
 
