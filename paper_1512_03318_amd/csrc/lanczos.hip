@@ -757,11 +757,15 @@ static void lz_step_tail(const LzInst* I, const LzGrid& g, int32_t nv_bound, hip
   const dim3 gd(g.nchunk);  // projections: one block per chunk over the whole basis
   hipLaunchKernelGGL(lz_dots_kernel<F32>, gd, dim3(256), 0, s, I, g.nins);
   hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H1);
-  if (b <= LZ_FUSE) {
+  // the fused pass is bound by latency, not bytes: over an FP32 basis it runs no faster
+  // than over an FP64 one (15.5 / 36 us at 8 / 16 vectors) and at 24 vectors slower
+  // (86 against 62 us), while the separate passes stream half the bytes; so an FP32
+  // basis fuses up to 16 vectors only
+  if (b <= (F32 ? 16 : LZ_FUSE)) {
     // one pass for w1, h2 and |w1|^2
     if (b <= 8) hipLaunchKernelGGL((lz_subdots_kernel<8, F32>), dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
-    else if (b <= 16) hipLaunchKernelGGL((lz_subdots_kernel<16, F32>), dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
-    else hipLaunchKernelGGL((lz_subdots_kernel<LZ_FUSE, F32>), dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+    else if (F32 || b <= 16) hipLaunchKernelGGL((lz_subdots_kernel<16, F32>), dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
+    else hipLaunchKernelGGL((lz_subdots_kernel<LZ_FUSE, false>), dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
     hipLaunchKernelGGL(lz_reduce_kernel, dim3(maxc, g.nins), dim3(256), 0, s, I, (int32_t)LZR_H2N);
   } else {
     hipLaunchKernelGGL(lz_sub_kernel<F32>, dim3(g.nchunk), dim3(256), 0, s, I, g.nins);
