@@ -482,7 +482,7 @@ def compare_real(pk, torch, wl, inp, prec, stream):
 def eq_rot_report(pk, torch, wl, inp, iters, stream, reps=3):
     """The real formulation of eq. rot at the same window: the library's real MPO, real
     isometries and theta (float64), DM_REAL plans.  Matvec and cold-start Lanczos times
-    in FP64 and FP32 next to the complex plans' (same sectors, same chi; the windows'
+    in FP64, FP32 and BF16x3 next to the complex plans' (same sectors, same chi; the windows'
     random entries differ, so their energies are not compared here -- the GPU tests
     check one window both ways)."""
     import statistics
@@ -504,7 +504,7 @@ def eq_rot_report(pk, torch, wl, inp, iters, stream, reps=3):
         return statistics.median(ts), e, k
 
     out = {"mpo_D": list(rin["D"]), "workload": wr.name, "entries": "real (float64)"}
-    for name, prec in (("fp64", pk.DM_FP64), ("fp32", pk.DM_FP32)):
+    for name, prec in (("fp64", pk.DM_FP64), ("fp32", pk.DM_FP32), ("bf16x3", pk.DM_BF16X3)):
         cplan = pk.HeffPlan(inp["ly"], inp["a"], inp["c"], inp["w1"], inp["w2"], inp["L"], inp["R"], prec, stream)
         rplan = pk.HeffPlan(rin["ly"], rin["a"], rin["c"], rin["w1"], rin["w2"], rin["L"], rin["R"],
                             prec | pk.DM_REAL, stream)

@@ -93,7 +93,7 @@ typedef struct ihipStream_t* dm_stream; /* hipStream_t; NULL is the default stre
 #define DM_FP64 0
 #define DM_FP32 1
 #define DM_BF16X3 2 /* hi/lo bfloat16 split of FP32 operands, FP32 accumulation */
-/* OR'ed into DM_FP64 or DM_FP32 (dm_heff_plan_create, env_update_left / _right and the
+/* OR'ed into DM_FP64, DM_FP32 or DM_BF16X3 (dm_heff_plan_create, env_update_left / _right and the
  * allocation-free variant): real operands, the formulation of eq. rot (Sec. IV D) in
  * which the mixed-basis MPO (dm_mpo_hofstadter basis 2), theta and the environments are
  * real.  Every tensor argument is then an array of float64 values in the same block

@@ -11,7 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmrdmrg.so")
 
 DM_FP64, DM_FP32, DM_BF16X3 = 0, 1, 2
-DM_REAL = 16  # OR'ed into DM_FP64 / DM_FP32: real (float64) operands, the eq. rot form
+DM_REAL = 16  # OR'ed into DM_FP64 / DM_FP32 / DM_BF16X3: real (float64) operands, the eq. rot form
 LAYOUT_SITE, LAYOUT_THETA, LAYOUT_ENV_L, LAYOUT_ENV_R = 0, 1, 2, 3
 # error codes of include/mrdmrg.h
 DM_OK, DM_ERR_ARG, DM_ERR_CHARGE, DM_ERR_DIM, DM_ERR_LAYOUT = 0, -1, -2, -3, -4

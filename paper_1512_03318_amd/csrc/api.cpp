@@ -433,9 +433,13 @@ static void build_heff_tables(dm_heff_plan& p) {
   if (p.real) {
     // real kernels; flops at 2 per real multiply-add (the tables counted 8 per complex)
     check_real_mix(mx);
-    p.s1.real = p.s4.real = mx.real = true;
+    // (s1f / s4f: the FP64-shaped copies a BF16x3 plan keeps for its FP64 Rayleigh
+    // quotient run on the same real buffers)
+    p.s1.real = p.s4.real = p.s1f.real = p.s4f.real = mx.real = true;
     p.s1.flops /= 4;
     p.s4.flops /= 4;
+    p.s1f.flops /= 4;
+    p.s4f.flops /= 4;
     mx.flops /= 4;
     p.mix_flops = mx.flops;
   }
@@ -516,7 +520,7 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       // BF16x3 matvec on pre-split operands with MRDMRG_PRESPLIT=1 (otherwise the
       // kernels split FP32 operands while staging them)
       const char* e = getenv("MRDMRG_PRESPLIT");
-      p->presplit = prec == DM_BF16X3 && e && e[0] == '1';
+      p->presplit = prec == DM_BF16X3 && !real && e && e[0] == '1';
     }
     if (p->presplit) {
       // pre-split L and R (once per plan), theta^T (per matvec) and the split Z; pad
@@ -593,6 +597,10 @@ void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStrea
     if (ev) HIPCHK(hipEventRecord(ev[i], s));
   };
   if (p->prec == DM_FP64 || force64) {
+    // a stage's element form must be the plan's: a complex kernel on real buffers would
+    // index twice as far as they reach
+    if (p->rq_s1().real != p->real || p->rq_s4().real != p->real || p->mix.real != p->real)
+      throw DmError{DM_ERR_LAYOUT, "FP64 stages do not match the plan's real / complex form"};
     void* dL = p->prec == DM_FP64 ? p->dL : p->dL64;
     void* dR = p->prec == DM_FP64 ? p->dR : p->dR64;
     void* dX = p->dX;
@@ -636,6 +644,8 @@ void mrd::heff_run(dm_heff_plan* p, const void* theta, void* theta_out, hipStrea
   // theta in: an FP32 copy; theta' out: BF16x3 stages write FP64 themselves (the FP32
   // results widened as they are stored), FP32 stages through an FP32 copy
   const bool direct = p->prec == DM_BF16X3;
+  if (p->s1.real != p->real || p->s4.real != p->real || p->mix.real != p->real)
+    throw DmError{DM_ERR_LAYOUT, "stages do not match the plan's real / complex form"};
   if (!staged) HIPCHK(launch_cast_d2f((const double*)theta, (float*)p->dTin, p->nreal(), s, skip));
   float* tout = direct ? (float*)theta_out : (float*)p->dTout;
   mark(0);

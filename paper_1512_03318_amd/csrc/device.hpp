@@ -93,7 +93,10 @@ __global__ void __launch_bounds__(256) gemm_split_reduce_kernel(const Prob* __re
         im += pi[ks];
       }
     const int64_t rb = (FLAGS & G_C_ROWMAP) ? rows[P.rowmap + i] : P.c_off + (int64_t)i * P.ldc;
-    if constexpr (REAL) C[rb + j] = re;
+    if constexpr (REAL) {
+      if (FLAGS & G_C_F64) reinterpret_cast<double*>(C)[rb + j] = (double)re;
+      else C[rb + j] = re;
+    }
     else if (FLAGS & G_C_F64) stc(reinterpret_cast<double*>(C), rb + j, (double)re, (double)im);
     else stc(C, rb + j, re, im);
   }

@@ -23,6 +23,9 @@
 // operand as [row][k] planes (k contiguous), one plane per part: re_hi, re_lo, im_hi,
 // im_lo; a lane reads its 8 k values with one 16-byte load.
 //
+// REAL (the real formulation of eq. rot): operands and results are real FP32 (results FP64
+// with G_C_F64); two LDS planes per operand (hi, lo) and three MFMAs per 16x16x32 block.
+//
 // LDS rows: an operand staged along k (its quads are four consecutive k of one row, eight
 // lanes per row) has 64-byte rows with 16-byte group g of row r stored at slot
 // g ^ f(r), f(r) = ((r >> 1) ^ (r >> 3)) & 3.  A pass of 32 lanes storing 8 bytes each
@@ -57,8 +60,9 @@ __device__ __forceinline__ int lds_rk(int r, int k) {
   return r * 40 + k;
 }
 
-template <int FLAGS, int BM, int BN, int WM, int WN>
+template <int FLAGS, int BM, int BN, int WM, int WN, bool REAL = false>
 struct Bf3Cfg {
+  static constexpr int PARTS = REAL ? 2 : 4;    // bf16 planes per operand
   static constexpr int KC = 32;                // K chunk = one bf16 MFMA step
   static constexpr int QA = BM * KC / 4 / 256;  // k-quads of A staged per thread
   static constexpr int QB = BN * KC / 4 / 256;
@@ -67,7 +71,7 @@ struct Bf3Cfg {
   static constexpr bool B_KC = (FLAGS & G_B_T) != 0;
   // bf16 per plane: rows of 32 (swizzled) or 40 (padded) bf16
   static constexpr int PLANE_A = BM * (A_KC ? 32 : 40), PLANE_B = BN * (B_KC ? 32 : 40);
-  static constexpr int SMEM = 2 * 4 * (PLANE_A + PLANE_B);  // bytes: 4 parts of bf16
+  static constexpr int SMEM = 2 * PARTS * (PLANE_A + PLANE_B);  // bytes: PARTS planes of bf16
   static_assert(WM * WN == 4 && QA >= 1 && QB >= 1 && XB >= 1 && YB >= 1, "tile shape");
 };
 
@@ -97,7 +101,21 @@ __device__ __forceinline__ void split_store(const Cplx<float> (&v)[4], __bf16* p
   *reinterpret_cast<bf16x4*>(plane + 3 * plane_sz + off) = il;
 }
 
-template <int FLAGS, int BM, int BN, int WM, int WN, bool SPLIT>
+// the real form: four real values (in .re) into the two planes hi, lo
+__device__ __forceinline__ void split_store_real(const Cplx<float> (&v)[4], __bf16* plane, int plane_sz,
+                                                 int off) {
+  bf16x4 rh, rl;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const __bf16 a = (__bf16)v[t].re;
+    rh[t] = a;
+    rl[t] = (__bf16)(v[t].re - (float)a);
+  }
+  *reinterpret_cast<bf16x4*>(plane + off) = rh;
+  *reinterpret_cast<bf16x4*>(plane + plane_sz + off) = rl;
+}
+
+template <int FLAGS, int BM, int BN, int WM, int WN, bool SPLIT, bool REAL = false>
 __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict__ segs,
                                                        const GemmProb* __restrict__ probs,
                                                        const GemmTile* __restrict__ tiles,
@@ -108,11 +126,11 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
                                                        float* __restrict__ part,
                                                        const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  typedef Bf3Cfg<FLAGS, BM, BN, WM, WN> G;
-  constexpr int KC = G::KC, QA = G::QA, QB = G::QB, XB = G::XB, YB = G::YB;
+  typedef Bf3Cfg<FLAGS, BM, BN, WM, WN, REAL> G;
+  constexpr int KC = G::KC, QA = G::QA, QB = G::QB, XB = G::XB, YB = G::YB, NP = G::PARTS;
   __shared__ __attribute__((aligned(16))) char smem[G::SMEM];
-  __bf16* sA = reinterpret_cast<__bf16*>(smem);          // [4 parts][BM rows]
-  __bf16* sB = sA + 4 * G::PLANE_A;                      // [4 parts][BN rows]
+  __bf16* sA = reinterpret_cast<__bf16*>(smem);          // [NP parts][BM rows]
+  __bf16* sB = sA + NP * G::PLANE_A;                     // [NP parts][BN rows]
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -145,10 +163,15 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
         Cplx<float> v{0.f, 0.f};
         if (i < P.M && k + t < kc) {
           const int kk = k0 + k + t;
-          if (FLAGS & G_A_ROWMAP) v = ldc(A, arow[q] + S.a_off + kk);
-          else if (FLAGS & G_A_T) v = ldc(A, S.a_off + (int64_t)kk * S.lda + i);
-          else v = ldc(A, S.a_off + (int64_t)i * S.lda + kk);
-          if (FLAGS & G_A_CONJ) v.im = -v.im;
+          const int64_t ix = (FLAGS & G_A_ROWMAP) ? arow[q] + S.a_off + kk
+                             : (FLAGS & G_A_T)    ? S.a_off + (int64_t)kk * S.lda + i
+                                                  : S.a_off + (int64_t)i * S.lda + kk;
+          if constexpr (REAL) {
+            v.re = A[ix];
+          } else {
+            v = ldc(A, ix);
+            if (FLAGS & G_A_CONJ) v.im = -v.im;
+          }
         }
         ra[q][t] = v;
       }
@@ -163,8 +186,9 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
         Cplx<float> v{0.f, 0.f};
         if (j < P.N && k + t < kc) {
           const int kk = k0 + k + t;
-          v = (FLAGS & G_B_T) ? ldc(B, S.b_off + (int64_t)j * S.ldb + kk)
-                              : ldc(B, S.b_off + (int64_t)kk * S.ldb + j);
+          const int64_t ix = (FLAGS & G_B_T) ? S.b_off + (int64_t)j * S.ldb + kk : S.b_off + (int64_t)kk * S.ldb + j;
+          if constexpr (REAL) v.re = B[ix];
+          else v = ldc(B, ix);
         }
         rb[q][t] = v;
       }
@@ -197,13 +221,15 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
     for (int q = 0; q < QA; ++q) {
       int r, k;
       quad_rk<G::A_KC, BM, KC>(tid, q, r, k);
-      split_store(ra[q], sA, G::PLANE_A, lds_rk<G::A_KC>(r, k));
+      if constexpr (REAL) split_store_real(ra[q], sA, G::PLANE_A, lds_rk<G::A_KC>(r, k));
+      else split_store(ra[q], sA, G::PLANE_A, lds_rk<G::A_KC>(r, k));
     }
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       int c, k;
       quad_rk<G::B_KC, BN, KC>(tid, q, c, k);
-      split_store(rb[q], sB, G::PLANE_B, lds_rk<G::B_KC>(c, k));
+      if constexpr (REAL) split_store_real(rb[q], sB, G::PLANE_B, lds_rk<G::B_KC>(c, k));
+      else split_store(rb[q], sB, G::PLANE_B, lds_rk<G::B_KC>(c, k));
     }
     // the staging registers are free again: the next chunk's loads go out before the
     // barrier and stay in flight during it and the products of this chunk
@@ -216,18 +242,26 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
     if (sg < P.nseg) load_chunk(S, k0);
     __syncthreads();
     // k positions beyond the chunk's valid range were staged as zeros
-    bf16x8 b[YB][4];
+    bf16x8 b[YB][NP];
 #pragma unroll
     for (int y = 0; y < YB; ++y)
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
+      for (int p = 0; p < NP; ++p)
         b[y][p] = *reinterpret_cast<const bf16x8*>(sB + p * G::PLANE_B + lds_rk<G::B_KC>(wc + y * 16 + li, 8 * lk));
 #pragma unroll
     for (int x = 0; x < XB; ++x) {
-      bf16x8 a[4];
+      bf16x8 a[NP];
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
+      for (int p = 0; p < NP; ++p)
         a[p] = *reinterpret_cast<const bf16x8*>(sA + p * G::PLANE_A + lds_rk<G::A_KC>(wr + x * 16 + li, 8 * lk));
+      if constexpr (REAL) {  // parts: 0 hi, 1 lo; small products first
+#pragma unroll
+        for (int y = 0; y < YB; ++y) {
+          cre[x][y] = mfma_bf16(a[1], b[y][0], cre[x][y]);
+          cre[x][y] = mfma_bf16(a[0], b[y][1], cre[x][y]);
+          cre[x][y] = mfma_bf16(a[0], b[y][0], cre[x][y]);
+        }
+      } else {
       // parts: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
       const bf16x8 nih = neg8(a[2]), nil = neg8(a[3]);
 #pragma unroll
@@ -245,6 +279,7 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
         cre[x][y] = mfma_bf16(nih, b[y][2], cre[x][y]);
         cim[x][y] = mfma_bf16(a[2], b[y][0], cim[x][y]);
       }
+      }
     }
   }
 
@@ -257,8 +292,11 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int y = 0; y < YB; ++y)
-          stc(dst, (wr + x * 16 + 4 * lk + r) * BN + wc + y * 16 + li, cre[x][y][r], cim[x][y][r]);
+        for (int y = 0; y < YB; ++y) {
+          const int e = (wr + x * 16 + 4 * lk + r) * BN + wc + y * 16 + li;
+          if constexpr (REAL) dst[e] = cre[x][y][r];  // first half of the slot, as the reduction reads it
+          else stc(dst, e, cre[x][y][r], cim[x][y][r]);
+        }
     return;
   }
 #pragma unroll
@@ -272,10 +310,14 @@ __global__ void __launch_bounds__(256) gemm_bf3_kernel(const GemmSeg* __restrict
       for (int y = 0; y < YB; ++y) {
         const int j = j0 + wc + y * 16 + li;
         if (j >= P.N) continue;
-        if (FLAGS & G_C_F64)
+        if constexpr (REAL) {
+          if (FLAGS & G_C_F64) reinterpret_cast<double*>(C)[rbase + j] = (double)cre[x][y][r];
+          else C[rbase + j] = cre[x][y][r];
+        } else if (FLAGS & G_C_F64) {
           stc(reinterpret_cast<double*>(C), rbase + j, (double)cre[x][y][r], (double)cim[x][y][r]);
-        else
+        } else {
           stc(C, rbase + j, cre[x][y][r], cim[x][y][r]);
+        }
       }
     }
   }
@@ -290,14 +332,23 @@ hipError_t launch_gemm_bf16x3(const GemmStage& st, const float* A, const float* 
   dim3 grid(nt), block(256);
 #define MRD_BF3_CASE(F, TM, TN, WM, WN, SP)                                                     \
   if (st.flags == (F) && st.tile_m == (TM) && st.tile_n == (TN) && st.split == (SP)) {          \
-    hipLaunchKernelGGL((gemm_bf3_kernel<F, TM, TN, WM, WN, SP>), grid, block, 0, s, st.d_segs,  \
-                       st.d_probs, st.d_tiles, st.d_rows, A, B, C, part, skip);                 \
+    if (st.real)                                                                                \
+      hipLaunchKernelGGL((gemm_bf3_kernel<F, TM, TN, WM, WN, SP, true>), grid, block, 0, s,     \
+                         st.d_segs, st.d_probs, st.d_tiles, st.d_rows, A, B, C, part, skip);    \
+    else                                                                                        \
+      hipLaunchKernelGGL((gemm_bf3_kernel<F, TM, TN, WM, WN, SP>), grid, block, 0, s,           \
+                         st.d_segs, st.d_probs, st.d_tiles, st.d_rows, A, B, C, part, skip);    \
     if (between) between();                                                                     \
-    if (SP && !st.red_tiles.empty())                                                            \
-      hipLaunchKernelGGL((gemm_split_reduce_kernel<float, F>),                                  \
-                         dim3(st.red_tiles.size(), (TM * TN + 1023) / 1024),                    \
-                         block, 0, s, st.d_probs, st.d_red_tiles, st.d_rows, part, C, TM, TN,   \
-                         skip);                                                                 \
+    if (SP && !st.red_tiles.empty()) {                                                          \
+      if (st.real)                                                                              \
+        hipLaunchKernelGGL((gemm_split_reduce_kernel<float, F, GemmProb, true>),                \
+                           dim3(st.red_tiles.size(), (TM * TN + 1023) / 1024), block, 0, s,     \
+                           st.d_probs, st.d_red_tiles, st.d_rows, part, C, TM, TN, skip);       \
+      else                                                                                      \
+        hipLaunchKernelGGL((gemm_split_reduce_kernel<float, F>),                                \
+                           dim3(st.red_tiles.size(), (TM * TN + 1023) / 1024), block, 0, s,     \
+                           st.d_probs, st.d_red_tiles, st.d_rows, part, C, TM, TN, skip);       \
+    }                                                                                           \
     return hipGetLastError();                                                                   \
   }
   // short-K stages: 128 x 64 (L.theta) or 64 x 64 tiles; long-K stages: 128 x 32 with

@@ -180,7 +180,6 @@ size_t elem_bytes(int prec, bool real) { return (prec == DM_FP64 ? 16 : 8) / (re
 bool take_real(int32_t& prec) {
   const bool real = (prec & DM_REAL) != 0;
   prec &= ~DM_REAL;
-  if (real && prec == DM_BF16X3) throw DmError{DM_ERR_ARG, "real operands (DM_REAL) take FP64 or FP32"};
   return real;
 }
 
