@@ -404,68 +404,80 @@ extern "C" int dm_idmrg(dm_mps* psi, const dm_mpo_site* cell, dm_charge d, const
       }
       // the left cell joins the left block, the right cell (V^H) the right block
       sw.update_left(n - 1);  // L[n]
-      void* rn = dev_alloc(std::max<int64_t>(1, sw.env_elems(DM_LAYOUT_ENV_R, n, W[0].ql)) * 16);
-      {
-        dm_bond bb = psi->bond(n), bc = psi->bond(n + 1);
-        check(env_update_right(ly, &bb, &bc, &sw.w[n], sw.R[n + 1], spl->right, rn, DM_FP64, stream));
-      }
-      // next two cells: the right cell, then the left cell moved by d; the right block's
-      // environment moves with it
+      // device buffers of the next two cells and environments, released in stream order if
+      // anything below fails (psi itself is then left unspecified)
+      void* rn = nullptr;
+      void* rm = nullptr;
+      std::vector<void*> t(n2, nullptr);
       std::vector<std::vector<dm_charge>> bq(n2 + 1);
       std::vector<std::vector<int32_t>> bd(n2 + 1);
       std::vector<std::vector<double>> sch(n2 + 1);
-      std::vector<void*> t(n2, nullptr);
       std::vector<int64_t> nt(n2, 0);
-      for (int i = 0; i <= n; ++i) {
-        bq[i] = psi->bq[n + i];
-        bd[i] = psi->bd[n + i];
-        sch[i] = psi->schmidt[n + i];
-      }
-      std::vector<int> perm_c;  // the centre bond moved (the new right end)
-      for (int i = 1; i <= n; ++i) {
-        std::vector<int> perm;
-        moved_bond(*psi, i, d, bq[n + i], bd[n + i], perm);
-        if (i == n) perm_c = perm;
-        sch[n + i] = psi->schmidt[i];
-      }
-      for (int i = 0; i < n; ++i) {
-        t[i] = psi->t[n + i];
-        nt[i] = psi->nt[n + i];
-        psi->t[n + i] = nullptr;
-      }
-      for (int i = 0; i < n; ++i) {
-        dm_bond oa = psi->bond(i), ob = psi->bond(i + 1);
-        const Bond ba = make_bond(&oa, ly), bb = make_bond(&ob, ly);
-        std::vector<int> perm;
-        std::vector<dm_charge> qa;
-        std::vector<int32_t> da;
-        moved_bond(*psi, i, d, qa, da, perm);
-        dm_bond na{(int32_t)qa.size(), qa.data(), da.data()};
-        dm_bond nb{(int32_t)bq[n + i + 1].size(), bq[n + i + 1].data(), bd[n + i + 1].data()};
-        const SiteLayout from = site_layout(ba, bb, psi->qs[i].data(), ly);
-        const SiteLayout to = site_layout(make_bond(&na, ly), make_bond(&nb, ly), psi->qs[i].data(), ly);
-        if (from.P.total != psi->nt[i]) throw DmError{DM_ERR_LAYOUT, "dm_idmrg: site tensor size"};
-        t[n + i] = dev_alloc(std::max<int64_t>(1, to.P.total) * 16);
-        nt[n + i] = to.P.total;
-        permute_panels(from.P, to.P, perm, psi->t[i], t[n + i], s);
-        sw.release(psi->t[i]);
-      }
-      {
-        dm_bond oc = psi->bond(n);
-        dm_bond nc{(int32_t)bq[n2].size(), bq[n2].data(), bd[n2].data()};
-        const EnvRLayout from = envr_layout(make_bond(&oc, ly), W[0].ql, ly);
-        const EnvRLayout to = envr_layout(make_bond(&nc, ly), W[0].ql, ly);
-        if (from.P.total != sw.env_elems(DM_LAYOUT_ENV_R, n, W[0].ql))
-          throw DmError{DM_ERR_LAYOUT, "dm_idmrg: environment size"};
-        void* rm = dev_alloc(std::max<int64_t>(1, to.P.total) * 16);
-        permute_panels(from.P, to.P, perm_c, rn, rm, s);
+      try {
+        rn = dev_alloc(std::max<int64_t>(1, sw.env_elems(DM_LAYOUT_ENV_R, n, W[0].ql)) * 16);
+        {
+          dm_bond bb = psi->bond(n), bc = psi->bond(n + 1);
+          check(env_update_right(ly, &bb, &bc, &sw.w[n], sw.R[n + 1], spl->right, rn, DM_FP64, stream));
+        }
+        // next two cells: the right cell, then the left cell moved by d; the right block's
+        // environment moves with it
+        for (int i = 0; i <= n; ++i) {
+          bq[i] = psi->bq[n + i];
+          bd[i] = psi->bd[n + i];
+          sch[i] = psi->schmidt[n + i];
+        }
+        std::vector<int> perm_c;  // the centre bond moved (the new right end)
+        for (int i = 1; i <= n; ++i) {
+          std::vector<int> perm;
+          moved_bond(*psi, i, d, bq[n + i], bd[n + i], perm);
+          if (i == n) perm_c = perm;
+          sch[n + i] = psi->schmidt[i];
+        }
+        for (int i = 0; i < n; ++i) {
+          t[i] = psi->t[n + i];
+          nt[i] = psi->nt[n + i];
+          psi->t[n + i] = nullptr;
+        }
+        for (int i = 0; i < n; ++i) {
+          dm_bond oa = psi->bond(i), ob = psi->bond(i + 1);
+          const Bond ba = make_bond(&oa, ly), bb = make_bond(&ob, ly);
+          std::vector<int> perm;
+          std::vector<dm_charge> qa;
+          std::vector<int32_t> da;
+          moved_bond(*psi, i, d, qa, da, perm);
+          dm_bond na{(int32_t)qa.size(), qa.data(), da.data()};
+          dm_bond nb{(int32_t)bq[n + i + 1].size(), bq[n + i + 1].data(), bd[n + i + 1].data()};
+          const SiteLayout from = site_layout(ba, bb, psi->qs[i].data(), ly);
+          const SiteLayout to = site_layout(make_bond(&na, ly), make_bond(&nb, ly), psi->qs[i].data(), ly);
+          if (from.P.total != psi->nt[i]) throw DmError{DM_ERR_LAYOUT, "dm_idmrg: site tensor size"};
+          t[n + i] = dev_alloc(std::max<int64_t>(1, to.P.total) * 16);
+          nt[n + i] = to.P.total;
+          permute_panels(from.P, to.P, perm, psi->t[i], t[n + i], s);
+          sw.release(psi->t[i]);
+        }
+        {
+          dm_bond oc = psi->bond(n);
+          dm_bond nc{(int32_t)bq[n2].size(), bq[n2].data(), bd[n2].data()};
+          const EnvRLayout from = envr_layout(make_bond(&oc, ly), W[0].ql, ly);
+          const EnvRLayout to = envr_layout(make_bond(&nc, ly), W[0].ql, ly);
+          if (from.P.total != sw.env_elems(DM_LAYOUT_ENV_R, n, W[0].ql))
+            throw DmError{DM_ERR_LAYOUT, "dm_idmrg: environment size"};
+          rm = dev_alloc(std::max<int64_t>(1, to.P.total) * 16);
+          permute_panels(from.P, to.P, perm_c, rn, rm, s);
+          sw.release(rn);
+          void* ln = sw.L[n];
+          sw.L[n] = nullptr;
+          for (void*& p : sw.L) sw.release(p);
+          for (void*& p : sw.R) sw.release(p);
+          sw.L[0] = ln;
+          sw.R[n2] = rm;
+          rm = nullptr;
+        }
+      } catch (...) {
         sw.release(rn);
-        void* ln = sw.L[n];
-        sw.L[n] = nullptr;
-        for (void*& p : sw.L) sw.release(p);
-        for (void*& p : sw.R) sw.release(p);
-        sw.L[0] = ln;
-        sw.R[n2] = rm;
+        sw.release(rm);
+        for (void*& p : t) sw.release(p);
+        throw;
       }
       psi->bq = bq;
       psi->bd = bd;
