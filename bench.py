@@ -207,7 +207,7 @@ def stage_rooflines(pk, plan, prec, pname, prof, nmv, workload):
         bf3 = ("mrd::gemm_ps_kernel<128, 64, 2, 2, false, 0>", "mrd::gemm_ps_kernel<128, 32, 4, 1, true, 1>",
                "mrd::mix_slab_kernel<float, __bf16, false>", "mrd::gemm_split_reduce_kernel<float, 144, mrd::PsProb, false>")
     else:
-        bf3 = ("mrd::gemm_bf3_kernel<0, 128, 64, 2, 2, false>", "mrd::gemm_bf3_kernel<148, 128, 32, 4, 1, true>",
+        bf3 = ("mrd::gemm_bf3_kernel<0, 128, 64, 2, 2, false, false>", "mrd::gemm_bf3_kernel<148, 128, 32, 4, 1, true, false>",
                "mrd::mix_slab_kernel<float, float, false>", "mrd::gemm_split_reduce_kernel<float, 148, mrd::GemmProb, false>")
     gemm = {pk.DM_FP64: ("mrd::gemm_kernel<double, 0, false, false>", "mrd::gemm_kernel<double, 20, true, false>"),
             pk.DM_FP32: ("mrd::gemm_kernel<float, 0, false, false>", "mrd::gemm_kernel<float, 20, true, false>"),

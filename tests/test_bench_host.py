@@ -30,8 +30,8 @@ def test_measured_traffic_only_for_its_own_workload():
     # the committed counters either match the current kernel sources (then every matvec
     # kernel the bench names has an entry) or do not (then nothing is reported)
     if rec:
-        for k in ("mrd::gemm_bf3_kernel<0, 128, 64, 2, 2, false>",
-                  "mrd::gemm_bf3_kernel<148, 128, 32, 4, 1, true>",
+        for k in ("mrd::gemm_bf3_kernel<0, 128, 64, 2, 2, false, false>",
+                  "mrd::gemm_bf3_kernel<148, 128, 32, 4, 1, true, false>",
                   "mrd::mix_slab_kernel<float, float, false>",
                   "mrd::gemm_split_reduce_kernel<float, 148, mrd::GemmProb, false>"):
             assert rec[k]["read_bytes"] > 0 and rec[k]["write_bytes"] > 0
