@@ -14,6 +14,9 @@
 //   lowest eigenpair (E, y) of T_k by multisection on Sturm counts and inverse
 //   iteration, Ritz vector V y.
 //
+// Plans whose matvec reads FP32 (DM_FP32, DM_BF16X3) keep V in complex FP32 (LzGrid::vf32):
+// each v_j is rounded once when it is formed and widened to FP64 wherever it is used.
+//
 // All scalars live in LzState on the device.  Every kernel of one step reads the step
 // index and the stop flag from there, so the launches of a step have fixed arguments
 // (the step can be captured once as a HIP graph and replayed) and a breakdown turns
