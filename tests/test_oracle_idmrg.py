@@ -59,3 +59,25 @@ def test_idmrg_free_fermions_reach_the_bulk_energy():
     assert abs(np.sum(lam ** 2) - 1) < 1e-12
     cells_left = len(r.energies) + 1          # the initial block, the absorbed cells, one cell
     assert all(abs(q[0] - 3 * cells_left) <= 4 for q in r.schmidt[-1])
+
+
+@pytest.mark.parametrize("K_cell", [0, 1])
+def test_growth_start_shapes(K_cell):
+    """The seeded start of the growth: the left block's tensors are left isometries from
+    the vacuum, the two cells' and the right block's are right isometries, and the two
+    cells' last bond is their first with every charge moved by d."""
+    gs = workloads.growth_start(3, 3, 3, K_cell, 32, 17)
+    n, ly, d = gs.n, gs.ly, gs.d
+    assert d == (6, (2 * K_cell) % 3)
+    moved = {idmrg.shift_charge(q, d, ly): m for q, m in gs.bonds[n].items()}
+    assert moved == gs.bonds[3 * n] and len(gs.bonds[n]) > 1
+    assert gs.bonds[0] == {(0, 0): 1} and gs.bonds[4 * n] == {(12, (4 * K_cell) % 3): 1}
+    for i, A in enumerate(gs.left):  # sum_{a,s} A^H A = 1 per sector of the right bond
+        for qb, m in gs.bonds[i + 1].items():
+            g = sum(blk.conj().T @ blk for (qa, s, qb2), blk in A.items() if qb2 == qb)
+            assert np.abs(g - np.eye(m)).max() < 1e-12
+    for off, tens in ((n, gs.cells), (3 * n, gs.right)):
+        for i, B in enumerate(tens):  # sum_{s,c} B B^H = 1 per sector of the left bond
+            for qb, m in gs.bonds[off + i].items():
+                g = sum(blk @ blk.conj().T for (qb2, s, qc), blk in B.items() if qb2 == qb)
+                assert np.abs(g - np.eye(m)).max() < 1e-12
