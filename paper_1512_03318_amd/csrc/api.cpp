@@ -164,8 +164,9 @@ static void build_heff_tables(dm_heff_plan& p) {
   }
   // BF16x3 pre-split operands (bf16 planes, k padded to a multiple of 8): L per ket
   // sector a (M_a x m_a), theta^T per a (N_a x m_a), Z and R per output sector c'
-  // (rows x K with K the R panel width).
-  if (p.prec == DM_BF16X3) {
+  // (rows x K with K the R panel width).  Laid out, tabled and uploaded only for a plan
+  // that runs that path.
+  if (p.presplit) {
     // k padded to the chunk width of the stream-K kernels (a multiple of 8 is all the
     // tiled kernels need)
     auto r8 = [](int64_t k) { return (k + SK_KC - 1) / SK_KC * SK_KC; };
@@ -315,7 +316,7 @@ static void build_heff_tables(dm_heff_plan& p) {
     validate(p.s4, p.ztotal, p.R.P.total, p.n());
     validate(p.s1f, p.L.P.total, p.n(), p.xtotal);
     validate(p.s4f, p.ztotal, p.R.P.total, p.n());
-    if (bf3) build_ps();
+    if (p.presplit) build_ps();
   });
   // two-site MPO W12[w, s12', s12, w''] = sum_w' W1[w, s1', s1, w'] W2[w', s2', s2, w'']
   std::vector<std::complex<double>> w12((size_t)dl * 16 * dr);
@@ -356,7 +357,7 @@ static void build_heff_tables(dm_heff_plan& p) {
   MixStage& mx = p.mix;
   std::vector<int64_t> task_key;  // (a', c) slab of each task
   // BF16x3: the same tasks writing Z split into bf16 planes (pre-split (.).R operand)
-  const bool presplit = p.prec == DM_BF16X3;
+  const bool presplit = p.presplit;
   std::vector<MixTask> ptasks;
   for (int ci2 = 0; ci2 < c.size(); ++ci2) {
     const int Kc = p.R.P.cols[ci2], zl = p.zld[ci2];
@@ -459,6 +460,12 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     p->ly = ly;
     p->prec = prec;
     p->real = real;
+    {
+      // BF16x3 matvec on pre-split operands with MRDMRG_PRESPLIT=1 (otherwise the
+      // kernels split FP32 operands while staging them)
+      const char* e = getenv("MRDMRG_PRESPLIT");
+      p->presplit = prec == DM_BF16X3 && !real && e && e[0] == '1';
+    }
     p->a = make_bond(a, ly);
     p->c = make_bond(c, ly);
     p->w1 = make_mpo(w1, ly);
@@ -479,7 +486,7 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
     }
     build_heff_tables(*p);  // also validates the GEMM stages
     validate(p->mix, p->xtotal, p->ztotal);
-    if (prec == DM_BF16X3) validate(p->mixp, p->xtotal, p->zs_total);
+    if (p->presplit) validate(p->mixp, p->xtotal, p->zs_total);
     hipStream_t s = (hipStream_t)stream;
     {
       TableUpload up;
@@ -515,12 +522,6 @@ extern "C" int dm_heff_plan_create(int32_t ly, const dm_bond* a, const dm_bond* 
       // (a real theta of odd length gets a zero pad value)
       p->dTin = dev_alloc(std::max<int64_t>(p->n() * eb, p->nlz() * 8));
       p->dTout = dev_alloc(std::max<int64_t>(p->n() * eb, p->nlz() * 8));
-    }
-    {
-      // BF16x3 matvec on pre-split operands with MRDMRG_PRESPLIT=1 (otherwise the
-      // kernels split FP32 operands while staging them)
-      const char* e = getenv("MRDMRG_PRESPLIT");
-      p->presplit = prec == DM_BF16X3 && !real && e && e[0] == '1';
     }
     if (p->presplit) {
       // pre-split L and R (once per plan), theta^T (per matvec) and the split Z; pad
