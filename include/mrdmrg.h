@@ -100,8 +100,8 @@ typedef struct ihipStream_t* dm_stream; /* hipStream_t; NULL is the default stre
  * layout as its complex128 form (dm_layout: element counts and offsets are unchanged,
  * each element is one double); the MPO site tensors are still passed as complex128 and
  * must have zero imaginary parts (DM_ERR_ARG otherwise).  A real plan's flop counts
- * (dm_heff_info) are 2 per real multiply-add.  Real plans are not batched and not used
- * by the sweep. */
+ * (dm_heff_info) are 2 per real multiply-add.  Real plans are not batched; the sweeps
+ * and iDMRG use them when their precision carries DM_REAL. */
 #define DM_REAL 16
 
 typedef struct {
@@ -335,6 +335,9 @@ int dm_mps_schmidt(const dm_mps* m, int32_t i, double* values, int64_t* count);
  * a left move) and the environment behind the move is updated (FP64).  w: the n MPO
  * site tensors (w[0] with one left state, w[n-1] with one right state, the boundary
  * states of eq. MPO).  energies[s]: the energy of the last bond update of sweep s.
+ * prec may carry DM_REAL: the MPO (eq. rot form), the MPS and the environments are then
+ * real, still held as complex128 with zero imaginary parts, and every eigensolve runs a
+ * DM_REAL plan on their real parts (every other step keeps the imaginary parts zero).
  * Synchronises. */
 int dm_dmrg_sweeps(dm_mps* psi, const dm_mpo_site* w, int32_t nsweeps, int32_t chi,
                    int32_t max_iter, double cutoff, int32_t prec, double* energies,
@@ -359,8 +362,8 @@ int dm_dmrg_sweeps(dm_mps* psi, const dm_mpo_site* w, int32_t nsweeps, int32_t c
  * d (the right block's environment moves with it).  (E_j - E_{j-1}) / 2n is the energy
  * per orbital.  On return psi holds the last iteration's two cells, A..A (S V^H) B..B,
  * and dm_mps_schmidt(psi, n) the Schmidt values between them.  Environments in FP64;
- * the plans in precision prec.  Synchronises.  After an error psi is unspecified
- * (destroy it). */
+ * the plans in precision prec (DM_REAL as in dm_dmrg_sweeps).  Synchronises.  After an
+ * error psi is unspecified (destroy it). */
 int dm_idmrg(dm_mps* psi, const dm_mpo_site* cell, dm_charge d, const void* L0, const void* R0,
              int32_t n_iter, int32_t sweeps, int32_t chi, int32_t max_iter, double cutoff,
              int32_t prec, double* energies, dm_stream stream);

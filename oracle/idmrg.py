@@ -71,11 +71,13 @@ def _moved(key, c: int):
     return (key[0], key[1] + c) + tuple(key[2:])
 
 
-def bulk_cell(Ly: int, flux: Fraction, t: float, V: float, rings: int, basis: str = "mixed") -> MPOCell:
+def bulk_cell(Ly: int, flux: Fraction, t: float, V: float, rings: int, basis: str = "mixed",
+              real: bool = False) -> MPOCell:
     """The MPO of ``rings`` rings deep inside a long cylinder (Sec. IV), checked to
-    repeat: cell 2 and cell 3 of a 6-cell machine agree under the key shift."""
+    repeat: cell 2 and cell 3 of a 6-cell machine agree under the key shift; real=True:
+    the mixed basis in the real form of eq. rot (Sec. IV D)."""
     cyl = Cylinder(Ly, 6 * rings, Fraction(flux), t, V)
-    m = build(cyl, basis)
+    m = build(cyl, basis, real=real)
     n = rings * Ly
     k0 = 2 * n                      # first site of cell 2
 

@@ -261,6 +261,9 @@ int64_t split_layout(std::vector<SplitJob>& jobs);  // fills i0, returns the tot
 hipError_t launch_split(const SplitJob* jobs, int32_t njobs, int64_t nitems, const double* src,
                         __bf16* dst, hipStream_t s, const int32_t* skip = nullptr);
 
+// c: n complex128 (interleaved); r: n doubles.  take: r = Re c; put: c = r + 0i.
+hipError_t launch_re_take(const double* c, double* r, int64_t n, hipStream_t s);
+hipError_t launch_re_put(const double* r, double* c, int64_t n, hipStream_t s);
 hipError_t launch_cast_d2f(const double* in, float* out, int64_t n_real, hipStream_t s,
                            const int32_t* skip = nullptr);
 hipError_t launch_cast_f2d(const float* in, double* out, int64_t n_real, hipStream_t s,

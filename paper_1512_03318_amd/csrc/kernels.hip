@@ -654,6 +654,30 @@ static dim3 grid_for(int64_t n) {
   if (b < 1) b = 1;
   return dim3((uint32_t)b);
 }
+// Real parts of n complex128 values (interleaved) into n doubles, and back (imaginary
+// parts zero): a state held complex with zero imaginary parts handed to a real plan.
+__global__ void re_take_kernel(const double* __restrict__ c, double* __restrict__ r, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = c[2 * i];
+}
+__global__ void re_put_kernel(const double* __restrict__ r, double* __restrict__ c, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    c[2 * i] = r[i];
+    c[2 * i + 1] = 0.0;
+  }
+}
+hipError_t launch_re_take(const double* c, double* r, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(re_take_kernel, grid_for(n), dim3(256), 0, s, c, r, n);
+  return hipGetLastError();
+}
+hipError_t launch_re_put(const double* r, double* c, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(re_put_kernel, grid_for(n), dim3(256), 0, s, r, c, n);
+  return hipGetLastError();
+}
 hipError_t launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t s,
                            const int32_t* skip) {
   if (n == 0) return hipSuccess;

@@ -99,13 +99,15 @@ struct Sweeper {
   hipStream_t s;
   int32_t prec, chi, max_iter;
   double cutoff;
+  bool real;  // the eigensolves run DM_REAL plans on the real parts (eq. rot form)
   std::vector<void*> L, R, scratch;
   double e = 0.0;
+  int64_t theta_n = 0;  // elements of the last theta_of
 
   Sweeper(dm_mps& p, std::vector<dm_mpo_site> sites, int32_t prec_, int32_t chi_, int32_t max_iter_,
-          double cutoff_, hipStream_t st)
+          double cutoff_, hipStream_t st, bool real_ = false)
       : psi(p), w(std::move(sites)), ly(p.ly), n(p.n), s(st), prec(prec_), chi(chi_), max_iter(max_iter_),
-        cutoff(cutoff_), L(p.n + 1, nullptr), R(p.n + 1, nullptr) {}
+        cutoff(cutoff_), real(real_), L(p.n + 1, nullptr), R(p.n + 1, nullptr) {}
   ~Sweeper() {
     (void)hipStreamSynchronize(s);
     for (void* p : scratch) dev_free(p);
@@ -159,17 +161,40 @@ struct Sweeper {
     ThetaLayout th = theta_layout(a, c, q1, q2, ly);
     void* theta = dev_alloc(std::max<int64_t>(1, th.P.total) * 16);
     scratch.push_back(theta);
+    theta_n = th.P.total;
     contract_two_site(ly, a, b, c, q1, q2, psi.t[i], psi.t[i + 1], theta, s, scratch);
     return theta;
   }
-  // lowest eigenpair of H_eff(L[i], w[i], w[i+1], R[i+2]) from theta, in place
+  // lowest eigenpair of H_eff(L[i], w[i], w[i+1], R[i+2]) from theta (theta_of(i)), in
+  // place.  Real form: the state, the environments and the MPO are real (held complex with
+  // zero imaginary parts), so their real parts go to a DM_REAL plan and back.
   void solve(int i, void* theta) {
     dm_bond ba = psi.bond(i), bc = psi.bond(i + 2);
+    const void* Lp = L[i];
+    const void* Rp = R[i + 2];
+    void* th = theta;
+    if (real) {
+      const int64_t nl = env_elems(DM_LAYOUT_ENV_L, i, ql(i)), nr = env_elems(DM_LAYOUT_ENV_R, i + 2, qr(i + 1));
+      double* lr = (double*)dev_alloc(std::max<int64_t>(1, nl) * 8);
+      scratch.push_back(lr);
+      double* rr = (double*)dev_alloc(std::max<int64_t>(1, nr) * 8);
+      scratch.push_back(rr);
+      double* tr = (double*)dev_alloc(std::max<int64_t>(1, theta_n) * 8);
+      scratch.push_back(tr);
+      HIPCHK(launch_re_take((const double*)L[i], lr, nl, s));
+      HIPCHK(launch_re_take((const double*)R[i + 2], rr, nr, s));
+      HIPCHK(launch_re_take((const double*)theta, tr, theta_n, s));
+      Lp = lr;
+      Rp = rr;
+      th = tr;
+    }
     dm_heff_plan* plan = nullptr;
-    check(dm_heff_plan_create(ly, &ba, &bc, &w[i], &w[i + 1], L[i], R[i + 2], prec, (dm_stream)s, &plan));
+    check(dm_heff_plan_create(ly, &ba, &bc, &w[i], &w[i + 1], Lp, Rp, prec | (real ? DM_REAL : 0), (dm_stream)s,
+                              &plan));
     std::unique_ptr<dm_heff_plan, void (*)(dm_heff_plan*)> hold(plan, dm_heff_plan_destroy);
     int32_t k = 0;
-    check(lanczos_ground(plan, theta, max_iter, 1e-14, &e, &k, (dm_stream)s));
+    check(lanczos_ground(plan, th, max_iter, 1e-14, &e, &k, (dm_stream)s));
+    if (real) HIPCHK(launch_re_put((const double*)th, (double*)theta, theta_n, s));
   }
   std::unique_ptr<dm_split, void (*)(dm_split*)> split(int i, const void* theta, bool right) {
     dm_bond ba = psi.bond(i), bc = psi.bond(i + 2);
@@ -318,6 +343,7 @@ extern "C" int dm_dmrg_sweeps(dm_mps* psi, const dm_mpo_site* w, int32_t nsweeps
                               dm_stream stream) {
   return guarded([&] {
     if (!psi || !w || nsweeps < 1 || !energies) throw DmError{DM_ERR_ARG, "dm_dmrg_sweeps: bad arguments"};
+    const bool real = take_real(prec);
     check_prec(prec);
     const int n = psi->n, ly = psi->ly;
     hipStream_t s = (hipStream_t)stream;
@@ -329,7 +355,7 @@ extern "C" int dm_dmrg_sweeps(dm_mps* psi, const dm_mpo_site* w, int32_t nsweeps
       if (i > 0 && W[i].dl != W[i - 1].dr) throw DmError{DM_ERR_DIM, "MPO bond dimensions differ"};
     }
     if (W[0].dl != 1 || W[n - 1].dr != 1) throw DmError{DM_ERR_DIM, "MPO boundary dimensions must be 1"};
-    Sweeper sw(*psi, std::vector<dm_mpo_site>(w, w + n), prec, chi, max_iter, cutoff, s);
+    Sweeper sw(*psi, std::vector<dm_mpo_site>(w, w + n), prec, chi, max_iter, cutoff, s, real);
     if (sw.env_elems(DM_LAYOUT_ENV_L, 0, W[0].ql) != 1 || sw.env_elems(DM_LAYOUT_ENV_R, n, W[n - 1].qr) != 1)
       throw DmError{DM_ERR_CHARGE, "boundary bonds do not meet the MPO boundary states"};
     sw.L[0] = unit_env(s);
@@ -350,6 +376,7 @@ extern "C" int dm_idmrg(dm_mps* psi, const dm_mpo_site* cell, dm_charge d, const
   return guarded([&] {
     if (!psi || !cell || !L0 || !R0 || n_iter < 1 || sweeps < 1 || !energies || psi->n < 2 || psi->n % 2)
       throw DmError{DM_ERR_ARG, "dm_idmrg: bad arguments"};
+    const bool real = take_real(prec);
     check_prec(prec);
     const int n2 = psi->n, n = n2 / 2, ly = psi->ly;
     if (d.k < 0 || d.k >= ly) throw DmError{DM_ERR_CHARGE, "dm_idmrg: charge of two cells has k outside [0, ly)"};
@@ -377,7 +404,7 @@ extern "C" int dm_idmrg(dm_mps* psi, const dm_mpo_site* cell, dm_charge d, const
     }
     std::vector<dm_mpo_site> w2(cell, cell + n);
     w2.insert(w2.end(), cell, cell + n);
-    Sweeper sw(*psi, w2, prec, chi, max_iter, cutoff, s);
+    Sweeper sw(*psi, w2, prec, chi, max_iter, cutoff, s, real);
     const size_t nl = (size_t)sw.env_elems(DM_LAYOUT_ENV_L, 0, W[0].ql), nr = (size_t)sw.env_elems(DM_LAYOUT_ENV_R, n2, W[0].ql);
     sw.L[0] = dev_alloc(std::max<size_t>(1, nl) * 16);
     sw.R[n2] = dev_alloc(std::max<size_t>(1, nr) * 16);

@@ -7,13 +7,16 @@
   With one particle of momentum 1 added per cell (two cells carry k = 2), the growth
   moves every charge by (6, 2), which reorders sectors: the same comparison then checks
   the panel permutation of the moved site tensors and environment.
+* The same cylinder in the real form of eq. rot (the rotated bulk cell, real isometries):
+  the eigensolves run DM_REAL plans on the real parts, and the energies equal the oracle's
+  iDMRG on the same real cell.
 * The same cylinder at V=0: the energy added per iteration, per orbital, reaches the
   free-fermion Bloch-band value (closed form).
 * The model of Fig. 3 (Ly=10, flux 1/3, V/t=0.1, the lowest band filled: ten particles
-  per three-ring cell of 30 orbitals) in the mixed basis and in the real-space basis at
-  the same chi: time per growth iteration, energy per orbital and centre entropy (printed;
-  asserted: both bases agree on the energy per orbital, which lies above the V=0 Bloch
-  value).
+  per three-ring cell of 30 orbitals) in the mixed basis (complex and the real form of
+  eq. rot) and in the real-space basis: time per growth iteration, energy per orbital and
+  centre entropy (printed; asserted: every energy per orbital lies above the V=0 Bloch
+  value, and the mixed basis converges).
 """
 import time
 import sys
@@ -84,6 +87,26 @@ def test_gpu_idmrg_equals_the_oracle(K_cell):
 
 
 @pytest.mark.timeout(900)
+def test_gpu_idmrg_real_form_equals_the_oracle():
+    cell = idmrg.bulk_cell(3, Fraction(1, 3), 1.0, 1.0, 3, real=True)
+    gs = workloads.growth_start(3, 3, 3, 0, 32, 19, real=True)
+    n, chi, iters = gs.n, 32, 4
+    say(f"iDMRG, eq. rot form: Ly=3 flux 1/3 V=1, chi={chi}, {iters} iterations, DM_REAL eigensolves")
+    psi, sites, (L0, R0), (l0, r0) = gpu_start(cell, gs)
+    e = pk.idmrg(psi, sites, gs.d, l0, r0, iters, chi, prec=pk.DM_FP64 | pk.DM_REAL)
+    r = idmrg.run(cell, gs.cells, gs.bonds[n:3 * n + 1], iters, chi, L0, R0, gs.d)
+    say(f"  GPU    {['%.12f' % x for x in e]}")
+    say(f"  oracle {['%.12f' % x for x in r.energies]}")
+    for j in range(iters):
+        assert abs(e[j] - r.energies[j]) <= 1e-9 * abs(r.energies[j]), j
+    lam = psi.schmidt(n)
+    want = np.concatenate([r.schmidt[-1][q] for q in sorted(r.schmidt[-1])])
+    assert np.abs(lam - want).max() <= 1e-8
+    # the state stays real: the centre site tensor has zero imaginary parts
+    assert torch.abs(psi.tensor(n).imag).max().item() == 0.0
+
+
+@pytest.mark.timeout(900)
 def test_gpu_idmrg_free_fermions_reach_the_bulk_energy():
     cell = idmrg.bulk_cell(3, Fraction(1, 3), 1.0, 0.0, 3)
     gs = workloads.growth_start(3, 3, 3, 0, 64, 7)
@@ -125,16 +148,19 @@ def gpu_block_envs(cell, gs, sites):
 def test_gpu_idmrg_fig3_model():
     """Fig. 3's cylinder: Ly=10, flux 1/3, V/t=0.1, 1/3 filling, three-ring cells."""
     Ly = 10
-    runs = {"mixed": [(100, 8), (200, 8), (400, 8)], "real": [(100, 3), (200, 3)]}
+    runs = {"mixed": [(100, 8), (200, 8), (400, 8)], "mixed_eq_rot": [(100, 8), (200, 8), (400, 8)],
+            "real": [(100, 3), (200, 3)]}
     e0 = free.bulk_energy_per_orbital(Ly, 1, 3)
     res = {}
-    for basis, plan in runs.items():
+    for name, plan in runs.items():
+        basis, rot = ("mixed", True) if name == "mixed_eq_rot" else (name, False)
         t0 = time.perf_counter()
-        cell = idmrg.bulk_cell(Ly, Fraction(1, 3), 1.0, 0.1, 3, basis=basis)
-        say(f"{basis} basis: bulk cell of {cell.n_sites} orbitals, D {min(w.shape[0] for w in cell.W)}.."
+        cell = idmrg.bulk_cell(Ly, Fraction(1, 3), 1.0, 0.1, 3, basis=basis, real=rot)
+        say(f"{name}: bulk cell of {cell.n_sites} orbitals, D {min(w.shape[0] for w in cell.W)}.."
             f"{max(w.shape[0] for w in cell.W)} ({time.perf_counter() - t0:.1f} s on the host)")
         for chi, iters in plan:
-            gs = workloads.growth_start(Ly, 3, Ly, (Ly * (Ly - 1) // 2) % Ly, chi, 30 + chi, basis=basis)
+            gs = workloads.growth_start(Ly, 3, Ly, (Ly * (Ly - 1) // 2) % Ly, chi, 30 + chi, basis=basis,
+                                        real=rot)
             n = gs.n
             qs = [[tuple(map(int, q)) for q in cell.qsite[i % n]] for i in range(2 * n)]
             bonds = gs.bonds[n:3 * n + 1]
@@ -146,18 +172,21 @@ def test_gpu_idmrg_fig3_model():
             l0, r0 = gpu_block_envs(cell, gs, sites)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            e = pk.idmrg(psi, sites, gs.d, l0, r0, iters, chi)
+            e = pk.idmrg(psi, sites, gs.d, l0, r0, iters, chi, prec=pk.DM_FP64 | (pk.DM_REAL if rot else 0))
             dt = (time.perf_counter() - t1) / iters
             per = idmrg.energy_per_orbital(e, n)
             lam = psi.schmidt(n)
             ent, _ = pk.entanglement(lam[lam > 0])
-            res[(basis, chi)] = (per, dt)
+            res[(name, chi)] = (per, dt)
             say(f"  chi={chi}: {dt:.2f} s per growth iteration ({iters}), energy per orbital "
                 f"{['%.6f' % x for x in per]}, centre entropy {ent:.6f}, {len(psi.bond(n))} sectors")
             assert all(x > e0 for x in per)  # V n n >= 0: above the V=0 Bloch-band energy
     for chi in (100, 200):
         say(f"chi={chi}: real-space / mixed time per growth iteration "
             f"{res[('real', chi)][1] / res[('mixed', chi)][1]:.1f}x")
+    for chi in (100, 200, 400):
+        say(f"chi={chi}: mixed complex / eq. rot time per growth iteration "
+            f"{res[('mixed', chi)][1] / res[('mixed_eq_rot', chi)][1]:.2f}x")
     per = res[("mixed", 400)][0]
     say(f"mixed chi=400: last two estimates {per[-2]:.6f}, {per[-1]:.6f} (V=0 Bloch value {e0:.6f})")
     assert abs(per[-1] - per[-2]) < 2e-3

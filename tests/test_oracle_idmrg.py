@@ -1,7 +1,7 @@
 """Pins of the oracle's infinite-cylinder pieces (no GPU).
 
-* The bulk MPO cell read off the finite-state machine (Sec. IV), mixed and real-space
-  basis: copies of it between the boundary vectors picking R and F contract to the
+* The bulk MPO cell read off the finite-state machine (Sec. IV), mixed basis (complex and
+  in the real form of eq. rot) and real-space basis: copies of it between the boundary vectors picking R and F contract to the
   Hamiltonian of the finite cylinder built from the term lists (eqs. H_kin, H_int;
   eq. H_real) by exact diagonalisation's operator algebra, which shares nothing with the
   machine.
@@ -20,11 +20,13 @@ import workloads
 from oracle import ed, free, idmrg, model
 
 
-@pytest.mark.parametrize("basis", ["mixed", "real"])
+@pytest.mark.parametrize("basis,rot", [("mixed", False), ("mixed", True), ("real", False)])
 @pytest.mark.parametrize("Ly,flux,rings,copies", [(3, Fraction(1, 1), 1, 3), (3, Fraction(1, 3), 3, 1),
                                                   (4, Fraction(1, 2), 2, 1)])
-def test_bulk_cell_chain_contracts_to_hamiltonian(Ly, flux, rings, copies, basis):
-    cell = idmrg.bulk_cell(Ly, flux, 1.0, 1.0, rings, basis=basis)
+def test_bulk_cell_chain_contracts_to_hamiltonian(Ly, flux, rings, copies, basis, rot):
+    cell = idmrg.bulk_cell(Ly, flux, 1.0, 1.0, rings, basis=basis, real=rot)
+    if rot:  # eq. rot: every entry real
+        assert max(np.abs(w.imag).max() for w in cell.W) == 0
     n = rings * Ly
     assert cell.n_sites == n and cell.W[0].shape[0] == cell.W[-1].shape[3]
     assert np.array_equal(cell.qbond[0], cell.qbond[-1])

@@ -313,12 +313,13 @@ class GrowthStart:
 
 
 def growth_start(Ly: int, rings: int, N_cell: int, K_cell: int, chi: int, seed: int,
-                 sigma_N: float | None = None, basis: str = "mixed") -> GrowthStart:
+                 sigma_N: float | None = None, basis: str = "mixed", real: bool = False) -> GrowthStart:
     """Sizes from the bond recipe on a chain of four cells (Ly x 4 rings, charge
     4 (N_cell, K_cell)); bond n and bond 3 n are cut to the sectors they share under the
     move by two cells (the smaller dimension) and the chain is clipped again until both
     agree.  Tensors: one generator per orbital from ``SeedSequence(seed).spawn(4 n)``.
-    basis="real": the real-space basis (charges (1, 0), modulus 1; K_cell ignored)."""
+    basis="real": the real-space basis (charges (1, 0), modulus 1; K_cell ignored);
+    real=True: real isometries (the real form of eq. rot of the mixed basis)."""
     n, ly = rings * Ly, (Ly if basis == "mixed" else 1)
     if sigma_N is None:
         sigma_N = sqrt(Ly / 2.0)
@@ -344,7 +345,7 @@ def growth_start(Ly: int, rings: int, N_cell: int, K_cell: int, chi: int, seed: 
     def g(i):
         return np.random.default_rng(kids[i])
 
-    left = [left_isometry(g(i), bonds[i], bonds[i + 1], qsite[i], ly) for i in range(n)]
-    cells = [right_isometry(g(i), bonds[i], bonds[i + 1], qsite[i], ly) for i in range(n, 3 * n)]
-    right = [right_isometry(g(i), bonds[i], bonds[i + 1], qsite[i], ly) for i in range(3 * n, 4 * n)]
+    left = [left_isometry(g(i), bonds[i], bonds[i + 1], qsite[i], ly, real) for i in range(n)]
+    cells = [right_isometry(g(i), bonds[i], bonds[i + 1], qsite[i], ly, real) for i in range(n, 3 * n)]
+    right = [right_isometry(g(i), bonds[i], bonds[i + 1], qsite[i], ly, real) for i in range(3 * n, 4 * n)]
     return GrowthStart(ly, n, qsite, bonds, left, cells, right, d)
