@@ -582,11 +582,7 @@ extern "C" int dm_heff_sizes(const dm_heff_plan* p, int64_t sizes[5]) {
 static hipEvent_t* prof_slot(dm_heff_plan* p) {
   if (!p->profiling) return nullptr;
   if (p->prof_seen++ % p->prof_stride != 0) return nullptr;
-  if (p->ev_used == p->ev.size()) {
-    std::array<hipEvent_t, 5> e;
-    for (auto& x : e) HIPCHK(hipEventCreate(&x));
-    p->ev.push_back(e);
-  }
+  if (p->ev_used == p->ev.size()) p->ev.push_back(timing_events_get());
   return p->ev[p->ev_used++].data();
 }
 

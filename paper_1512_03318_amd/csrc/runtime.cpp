@@ -175,6 +175,38 @@ void* pinned_alloc(size_t bytes) { return pinned_pool().get(bytes); }
 void pinned_free_after(void* p, hipStream_t s) { pinned_pool().put_after(p, s); }
 void pinned_free(void* p) { pinned_pool().put(p); }
 
+namespace {
+std::mutex g_ev_mu;
+std::vector<std::pair<int, std::array<hipEvent_t, 5>>> g_ev_pool;  // (device, events)
+}  // namespace
+
+std::array<hipEvent_t, 5> timing_events_get() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> g(g_ev_mu);
+    for (size_t i = g_ev_pool.size(); i-- > 0;)
+      if (g_ev_pool[i].first == dev) {
+        const std::array<hipEvent_t, 5> e = g_ev_pool[i].second;
+        g_ev_pool.erase(g_ev_pool.begin() + (std::ptrdiff_t)i);
+        return e;
+      }
+  }
+  std::array<hipEvent_t, 5> e{};
+  for (auto& x : e) HIPCHK(hipEventCreate(&x));
+  return e;
+}
+
+void timing_events_put(const std::array<hipEvent_t, 5>& e) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {  // no device context: release them instead
+    for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    return;
+  }
+  std::lock_guard<std::mutex> g(g_ev_mu);
+  g_ev_pool.push_back({dev, e});
+}
+
 size_t elem_bytes(int prec, bool real) { return (prec == DM_FP64 ? 16 : 8) / (real ? 2 : 1); }
 
 bool take_real(int32_t& prec) {

@@ -71,6 +71,11 @@ void dev_free_after(void* p, hipStream_t s);
 void* pinned_alloc(size_t bytes);
 void pinned_free_after(void* p, hipStream_t s);
 void pinned_free(void* p);  // no copy uses the block any more
+// Timing events of the stage profiling (five per recorded matvec), reused across plans on
+// the current device: a plan per bond update would otherwise create and destroy them on
+// every bond.  put: every recorded event of the set has completed.
+std::array<hipEvent_t, 5> timing_events_get();
+void timing_events_put(const std::array<hipEvent_t, 5>& e);
 
 // All task tables of one or more stages in one device block, uploaded with one copy.
 struct TableUpload {
@@ -252,8 +257,7 @@ struct dm_heff_plan {
       (void)hipEventSynchronize(done);  // no kernel of this plan may still run
       (void)hipEventDestroy(done);
     }
-    for (auto& e : ev)
-      for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    for (auto& e : ev) mrd::timing_events_put(e);  // complete: `done` has been waited for
     mrd::dev_free(dTables);
     for (void* p : {dL, dR, dL64, dR64, dX, dX64, dSplit, dSplit64, dTin, dTout, dZ, dZ64, dLs, dRs, dThs, dZs,
                     dSplitP})
