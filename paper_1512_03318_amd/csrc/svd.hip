@@ -82,11 +82,24 @@ hipError_t launch_block_copy(const CopyJob* jobs, int32_t njobs, int64_t nitems,
 // One-sided Jacobi SVD of one m x n complex matrix per workgroup (column-major W at
 // w_off, n <= m), V (n x n, column-major) at v_off, singular values at sig_off (in
 // column order, unsorted).  On return W holds U (unit columns; a column with sigma = 0
-// is left as it is).  One thread per column pair of a round.
+// is left as it is).  One wave per column pair of a round: the lanes stride over the
+// rows (coalesced), the pair's norms and overlap are wave sums that every lane takes
+// from lane 0, so the rotation and the convergence decision are the same in all lanes.
+// (One thread per pair walked its two columns row by row, each step waiting on a
+// global-memory load: about 10 ms per split at chi = 800.)
 // ---------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) svd_jacobi_kernel(const SvdJob* __restrict__ jobs,
-                                                         double* __restrict__ work,
-                                                         double* __restrict__ sig, int32_t max_sweeps) {
+constexpr int SVD_THREADS = 1024;
+
+__device__ __forceinline__ double svd_wave_total(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return __shfl(x, 0, 64);
+}
+
+__global__ void __launch_bounds__(SVD_THREADS) svd_jacobi_kernel(const SvdJob* __restrict__ jobs,
+                                                                 double* __restrict__ work,
+                                                                 double* __restrict__ sig,
+                                                                 int32_t max_sweeps) {
   const SvdJob J = jobs[blockIdx.x];
   const int m = J.m, n = J.n;
   double* W = work + 2 * J.w_off;
@@ -97,13 +110,14 @@ __global__ void __launch_bounds__(256) svd_jacobi_kernel(const SvdJob* __restric
     V[2 * e] = r == c ? 1.0 : 0.0;
     V[2 * e + 1] = 0.0;
   }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int np = n + (n & 1);  // round-robin over an even count (one dummy when n is odd)
   constexpr double eps = 1e-15;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < np - 1; ++round) {
-      for (int k = threadIdx.x; k < np / 2; k += blockDim.x) {
+      for (int k = wv; k < np / 2; k += nwv) {  // uniform over the wave
         // position i of the round: 0 stays, the others rotate by `round`
         auto at = [&](int i) { return i == 0 ? 0 : (i - 1 + round) % (np - 1) + 1; };
         int p = at(k), q = at(np - 1 - k);
@@ -116,21 +130,25 @@ __global__ void __launch_bounds__(256) svd_jacobi_kernel(const SvdJob* __restric
         double* ap = W + 2 * (int64_t)p * m;
         double* aq = W + 2 * (int64_t)q * m;
         double a = 0, b = 0, gr = 0, gi = 0;
-        for (int r = 0; r < m; ++r) {
+        for (int r = lane; r < m; r += 64) {
           const double xr = ap[2 * r], xi = ap[2 * r + 1], yr = aq[2 * r], yi = aq[2 * r + 1];
           a += xr * xr + xi * xi;
           b += yr * yr + yi * yi;
           gr += xr * yr + xi * yi;  // conj(x) y
           gi += xr * yi - xi * yr;
         }
+        a = svd_wave_total(a);
+        b = svd_wave_total(b);
+        gr = svd_wave_total(gr);
+        gi = svd_wave_total(gi);
         const double g = sqrt(gr * gr + gi * gi);
         if (!(g > eps * sqrt(a) * sqrt(b))) continue;
-        rotated = 1;
+        if (lane == 0) rotated = 1;
         const double er = gr / g, ei = -gi / g;  // e^{-i phi}
         const double zeta = (b - a) / (2.0 * g);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int r = 0; r < m; ++r) {
+        for (int r = lane; r < m; r += 64) {
           const double xr = ap[2 * r], xi = ap[2 * r + 1];
           const double yr = aq[2 * r] * er - aq[2 * r + 1] * ei, yi = aq[2 * r] * ei + aq[2 * r + 1] * er;
           ap[2 * r] = c * xr - s * yr;
@@ -140,7 +158,7 @@ __global__ void __launch_bounds__(256) svd_jacobi_kernel(const SvdJob* __restric
         }
         double* vp = V + 2 * (int64_t)p * n;
         double* vq = V + 2 * (int64_t)q * n;
-        for (int r = 0; r < n; ++r) {
+        for (int r = lane; r < n; r += 64) {
           const double xr = vp[2 * r], xi = vp[2 * r + 1];
           const double yr = vq[2 * r] * er - vq[2 * r + 1] * ei, yi = vq[2 * r] * ei + vq[2 * r + 1] * er;
           vp[2 * r] = c * xr - s * yr;
@@ -155,15 +173,15 @@ __global__ void __launch_bounds__(256) svd_jacobi_kernel(const SvdJob* __restric
     __syncthreads();  // every thread has read the flag before it is cleared again
     if (!any) break;
   }
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+  for (int j = wv; j < n; j += nwv) {  // one wave per column
     double* aj = W + 2 * (int64_t)j * m;
     double nn = 0;
-    for (int r = 0; r < m; ++r) nn += aj[2 * r] * aj[2 * r] + aj[2 * r + 1] * aj[2 * r + 1];
-    const double sgm = sqrt(nn);
-    sig[J.sig_off + j] = sgm;
+    for (int r = lane; r < m; r += 64) nn += aj[2 * r] * aj[2 * r] + aj[2 * r + 1] * aj[2 * r + 1];
+    const double sgm = sqrt(svd_wave_total(nn));
+    if (lane == 0) sig[J.sig_off + j] = sgm;
     if (sgm > 0) {
       const double inv = 1.0 / sgm;
-      for (int r = 0; r < m; ++r) {
+      for (int r = lane; r < m; r += 64) {
         aj[2 * r] *= inv;
         aj[2 * r + 1] *= inv;
       }
@@ -174,7 +192,7 @@ __global__ void __launch_bounds__(256) svd_jacobi_kernel(const SvdJob* __restric
 hipError_t launch_svd_jacobi(const SvdJob* jobs, int32_t njobs, double* work, double* sig,
                              int32_t max_sweeps, hipStream_t s) {
   if (njobs == 0) return hipSuccess;
-  hipLaunchKernelGGL(svd_jacobi_kernel, dim3(njobs), dim3(256), 0, s, jobs, work, sig, max_sweeps);
+  hipLaunchKernelGGL(svd_jacobi_kernel, dim3(njobs), dim3(SVD_THREADS), 0, s, jobs, work, sig, max_sweeps);
   return hipGetLastError();
 }
 

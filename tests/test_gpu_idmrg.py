@@ -190,3 +190,41 @@ def test_gpu_idmrg_fig3_model():
     per = res[("mixed", 400)][0]
     say(f"mixed chi=400: last two estimates {per[-2]:.6f}, {per[-1]:.6f} (V=0 Bloch value {e0:.6f})")
     assert abs(per[-1] - per[-2]) < 2e-3
+
+
+_cells = {}
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name,chi,iters", [("mixed", 800, 4), ("mixed_eq_rot", 800, 4),
+                                            ("mixed", 1600, 3), ("mixed_eq_rot", 1600, 3)])
+def test_gpu_idmrg_fig3_large_chi(name, chi, iters):
+    """The Fig. 3 cylinder's growth at chi = 800 and 1600 in the mixed basis, complex and in
+    the real form of eq. rot: the centre bond reaches chi, its Schmidt values are
+    normalised, and every energy per orbital lies above the V = 0 Bloch-band value."""
+    Ly, rot = 10, name == "mixed_eq_rot"
+    if rot not in _cells:
+        _cells[rot] = idmrg.bulk_cell(Ly, Fraction(1, 3), 1.0, 0.1, 3, basis="mixed", real=rot)
+    cell = _cells[rot]
+    gs = workloads.growth_start(Ly, 3, Ly, (Ly * (Ly - 1) // 2) % Ly, chi, 30 + chi, real=rot)
+    n = gs.n
+    qs = [[tuple(map(int, q)) for q in cell.qsite[i % n]] for i in range(2 * n)]
+    bonds = gs.bonds[n:3 * n + 1]
+    Bd = [pk.Bond(b) for b in bonds]
+    tens = [to_dev(pk.pack(gs.cells[i], pk.LAYOUT_SITE, gs.ly, Bd[i], Bd[i + 1], qs1=qs[i]))
+            for i in range(2 * n)]
+    psi = pk.MPS(gs.ly, bonds, qs, tens)
+    sites = [pk.MpoSite(cell.W[i], cell.qbond[i], cell.qbond[i + 1], cell.qsite[i]) for i in range(n)]
+    l0, r0 = gpu_block_envs(cell, gs, sites)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    e = pk.idmrg(psi, sites, gs.d, l0, r0, iters, chi, prec=pk.DM_FP64 | (pk.DM_REAL if rot else 0))
+    dt = (time.perf_counter() - t1) / iters
+    per = idmrg.energy_per_orbital(e, n)
+    lam = psi.schmidt(n)
+    ent, _ = pk.entanglement(lam[lam > 0])
+    say(f"{name} chi={chi}: {dt:.2f} s per growth iteration ({iters}), energy per orbital "
+        f"{['%.6f' % x for x in per]}, centre entropy {ent:.6f}, {len(psi.bond(n))} sectors")
+    assert sum(psi.bond(n).values()) == chi
+    assert abs(np.sum(lam ** 2) - 1) < 1e-10
+    assert all(x > free.bulk_energy_per_orbital(Ly, 1, 3) for x in per)
